@@ -1,0 +1,157 @@
+// Gate matrices and gate-recipe evaluation, FP64, callable on host and device.
+//
+// A tensor of the network that stands for gates (a single gate, or a run of
+// gates pre-contracted into one two-qubit block, Sec. 3) is described by a
+// recipe: the list of elementary gates in circuit order.  The device
+// materialises every recipe at contraction time from the current angles
+// (FP64 trigonometry, rounded once to complex64); the host uses the same
+// functions to report FP64 tensor values for checks.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tn.h"
+
+namespace tnq {
+
+struct c128 {
+  double re, im;
+};
+
+__host__ __device__ inline c128 cm(double r, double i) { return c128{r, i}; }
+__host__ __device__ inline c128 cmul(c128 a, c128 b) { return cm(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re); }
+__host__ __device__ inline c128 cadd(c128 a, c128 b) { return cm(a.re + b.re, a.im + b.im); }
+__host__ __device__ inline c128 cconj(c128 a) { return cm(a.re, -a.im); }
+__host__ __device__ inline c128 cis(double t) { return cm(cos(t), sin(t)); }
+
+__host__ __device__ inline bool gate_is_two_qubit(int kind) {
+  return kind == TN_GATE_CZ || kind == TN_GATE_CNOT || kind == TN_GATE_SWAP || kind == TN_GATE_CPHASE ||
+         kind == TN_GATE_ZZPHASE || kind == TN_GATE_MATRIX2;
+}
+
+__host__ __device__ inline bool gate_is_diagonal(int kind) {
+  return kind == TN_GATE_Z || kind == TN_GATE_S || kind == TN_GATE_T || kind == TN_GATE_RZ || kind == TN_GATE_CZ ||
+         kind == TN_GATE_CPHASE || kind == TN_GATE_ZZPHASE;
+}
+
+__host__ __device__ inline int gate_n_angles(int kind) {
+  switch (kind) {
+    case TN_GATE_RX: case TN_GATE_RY: case TN_GATE_RZ: case TN_GATE_MIXER: case TN_GATE_CPHASE:
+    case TN_GATE_ZZPHASE: return 1;
+    case TN_GATE_U3: return 3;
+    default: return 0;
+  }
+}
+
+// Row-major matrix of a named gate (2x2 in m[0..3] or 4x4 in m[0..15]).
+// Returns false for an unknown kind.  Explicit matrices are handled by the caller.
+__host__ __device__ inline bool gate_matrix(int kind, const double* a, c128* m) {
+  for (int i = 0; i < 16; ++i) m[i] = cm(0, 0);
+  const double h = 0.70710678118654752440;
+  switch (kind) {
+    case TN_GATE_H: m[0] = cm(h, 0); m[1] = cm(h, 0); m[2] = cm(h, 0); m[3] = cm(-h, 0); return true;
+    case TN_GATE_X: m[1] = cm(1, 0); m[2] = cm(1, 0); return true;
+    case TN_GATE_Y: m[1] = cm(0, -1); m[2] = cm(0, 1); return true;
+    case TN_GATE_Z: m[0] = cm(1, 0); m[3] = cm(-1, 0); return true;
+    case TN_GATE_S: m[0] = cm(1, 0); m[3] = cm(0, 1); return true;
+    case TN_GATE_T: m[0] = cm(1, 0); m[3] = cm(h, h); return true;
+    case TN_GATE_SX: case TN_GATE_SY: case TN_GATE_SW: {
+      // ((1+i) I + (1-i) P) / 2 with P = X, Y or (X+Y)/sqrt2
+      c128 off01 = kind == TN_GATE_SX ? cm(1, 0) : kind == TN_GATE_SY ? cm(0, -1) : cm(h, -h);
+      c128 off10 = kind == TN_GATE_SX ? cm(1, 0) : kind == TN_GATE_SY ? cm(0, 1) : cm(h, h);
+      const c128 d = cm(0.5, 0.5), o = cm(0.5, -0.5);
+      m[0] = d; m[3] = d; m[1] = cmul(o, off01); m[2] = cmul(o, off10);
+      return true;
+    }
+    case TN_GATE_RX: { double c = cos(0.5 * a[0]), s = sin(0.5 * a[0]);
+      m[0] = cm(c, 0); m[3] = cm(c, 0); m[1] = cm(0, -s); m[2] = cm(0, -s); return true; }
+    case TN_GATE_RY: { double c = cos(0.5 * a[0]), s = sin(0.5 * a[0]);
+      m[0] = cm(c, 0); m[3] = cm(c, 0); m[1] = cm(-s, 0); m[2] = cm(s, 0); return true; }
+    case TN_GATE_RZ: m[0] = cis(-0.5 * a[0]); m[3] = cis(0.5 * a[0]); return true;
+    case TN_GATE_U3: { double c = cos(0.5 * a[0]), s = sin(0.5 * a[0]);
+      c128 el = cis(a[2]), ef = cis(a[1]), efl = cis(a[1] + a[2]);
+      m[0] = cm(c, 0); m[1] = cm(-s * el.re, -s * el.im); m[2] = cm(s * ef.re, s * ef.im);
+      m[3] = cm(c * efl.re, c * efl.im); return true; }
+    case TN_GATE_MIXER: { double c = cos(a[0]), s = sin(a[0]);
+      m[0] = cm(c, 0); m[3] = cm(c, 0); m[1] = cm(0, -s); m[2] = cm(0, -s); return true; }
+    case TN_GATE_CZ: m[0] = m[5] = m[10] = cm(1, 0); m[15] = cm(-1, 0); return true;
+    case TN_GATE_CNOT: m[0] = m[5] = cm(1, 0); m[11] = m[14] = cm(1, 0); return true;
+    case TN_GATE_SWAP: m[0] = m[15] = cm(1, 0); m[6] = m[9] = cm(1, 0); return true;
+    case TN_GATE_CPHASE: m[0] = m[5] = m[10] = cm(1, 0); m[15] = cis(a[0]); return true;
+    case TN_GATE_ZZPHASE: m[0] = m[15] = cm(1, 0); m[5] = m[10] = cis(-a[0]); return true;
+    default: return false;
+  }
+}
+
+// One elementary gate inside a recipe.
+struct RecipeOp {
+  int32_t kind;      // tn_gate_kind
+  int32_t pos;       // 1-qubit gate in a 2-qubit block: 0 = block's first (more significant) qubit, 1 = second.
+                     // 2-qubit gate: 0 = same qubit order as the block, 1 = reversed.
+  int32_t param[3];  // -1 = fixed angle
+  int32_t mat;       // index of an explicit matrix (32 doubles) for MATRIX kinds, else -1
+  double angle[3];
+};
+
+// A gate tensor: ops[op_begin, op_end) applied in order to a block of nq qubits.
+// Diagonal recipes store only the diagonal (tensor over the wires' hyper-indices).
+struct Recipe {
+  int32_t nq;
+  int32_t diag;
+  int32_t op_begin, op_end;
+  int64_t offset;  // element offset of the tensor in the per-batch input buffer
+};
+
+// d x d matrix (d = 2^nq) of a recipe, FP64.
+__host__ __device__ inline void recipe_matrix(const Recipe& r, const RecipeOp* ops, const double* mats,
+                                              const double* params, c128* M) {
+  const int d = r.nq == 2 ? 4 : 2;
+  for (int i = 0; i < d * d; ++i) M[i] = cm((i / d) == (i % d) ? 1.0 : 0.0, 0.0);
+  for (int o = r.op_begin; o < r.op_end; ++o) {
+    const RecipeOp& op = ops[o];
+    double ang[3];
+    for (int j = 0; j < 3; ++j) ang[j] = op.param[j] >= 0 ? params[op.param[j]] : op.angle[j];
+    c128 u[16];
+    if (op.kind == TN_GATE_MATRIX1 || op.kind == TN_GATE_MATRIX2) {
+      const int du = op.kind == TN_GATE_MATRIX2 ? 4 : 2;
+      for (int i = 0; i < du * du; ++i) u[i] = cm(mats[32 * op.mat + 2 * i], mats[32 * op.mat + 2 * i + 1]);
+    } else {
+      gate_matrix(op.kind, ang, u);
+    }
+    // embed into the block: G (d x d)
+    c128 G[16];
+    const bool two = gate_is_two_qubit(op.kind);
+    if (d == 2) {
+      for (int i = 0; i < 4; ++i) G[i] = u[i];
+    } else if (two) {
+      for (int x = 0; x < 4; ++x)
+        for (int y = 0; y < 4; ++y) {
+          int xs = op.pos ? ((x & 1) << 1) | (x >> 1) : x;
+          int ys = op.pos ? ((y & 1) << 1) | (y >> 1) : y;
+          G[4 * x + y] = u[4 * xs + ys];
+        }
+    } else {
+      for (int x = 0; x < 4; ++x)
+        for (int y = 0; y < 4; ++y) {
+          int xa = x >> 1, xb = x & 1, ya = y >> 1, yb = y & 1;
+          c128 v = cm(0, 0);
+          if (op.pos == 0) {
+            if (xb == yb) v = u[2 * xa + ya];
+          } else {
+            if (xa == ya) v = u[2 * xb + yb];
+          }
+          G[4 * x + y] = v;
+        }
+    }
+    c128 T[16];
+    for (int i = 0; i < d; ++i)
+      for (int j = 0; j < d; ++j) {
+        c128 acc = cm(0, 0);
+        for (int k = 0; k < d; ++k) acc = cadd(acc, cmul(G[d * i + k], M[d * k + j]));
+        T[d * i + j] = acc;
+      }
+    for (int i = 0; i < d * d; ++i) M[i] = T[i];
+  }
+}
+
+}  // namespace tnq

@@ -1,0 +1,76 @@
+// Launchers for the gfx950 kernels.  Every launcher enqueues on `stream` and
+// returns hipSuccess or the launch error.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "internal.h"
+
+namespace tnq {
+
+struct DevTensor {
+  int32_t kind, recipe, qubit, pad;
+  int64_t offset, size;
+};
+
+// Gate materialisation: every KET0 and GATE tensor of the network, for each
+// of `batch` parameter vectors (params: [batch][params_stride] or NULL).
+hipError_t launch_materialize(hipStream_t s, const DevTensor* ts, int nt, const Recipe* recipes, const RecipeOp* ops,
+                              const double* mats, const double* params, int64_t params_stride, int batch,
+                              float2* in, int64_t in_bs);
+// One-hot projectors P_q[s][w] = [w == bit_q(b_s)] for the last n tensors.
+hipError_t launch_projectors(hipStream_t s, const uint64_t* bits, int64_t count, int n_qubits, int blog2,
+                             int64_t first_offset, int batch, float2* in, int64_t in_bs);
+
+// Small-operand contraction streaming over the large operand (see SkinnyDesc).
+hipError_t launch_skinny(hipStream_t s, const SkinnyDesc& d, const float2* g, int64_t g_bs, const float2* t,
+                         int64_t t_bs, float2* c, int64_t c_bs, int batch, int precision);
+
+// Bit permutation of a 2^bits array: input bit p -> output bit dst[p].
+hipError_t launch_permute(hipStream_t s, const PermuteDesc& d, const float2* in, int64_t in_bs, float2* out,
+                          int64_t out_bs, int batch);
+
+// C[b] = A[b] B[b] on complex64 with FP32 MFMA accumulation.
+hipError_t launch_gemm(hipStream_t s, const GemmDesc& d, const float2* a, int64_t a_bs, const float2* b, int64_t b_bs,
+                       float2* c, int64_t c_bs, int batch, int precision);
+
+// Expectation of a diagonal Z-string observable: out[z] = sum_x |psi_z[x]|^2 D(x),
+// FP64 accumulation (block partials + a fixed-order second pass).
+constexpr int kMaxTerms = 128;
+struct ZTerms {
+  int32_t n;
+  uint64_t mask[kMaxTerms];  // address-bit masks
+  double coeff[kMaxTerms];
+};
+constexpr int kReduceBlocks = 512;
+hipError_t launch_expectation(hipStream_t s, const float2* psi, int64_t psi_bs, int64_t n_elems, const ZTerms& terms,
+                              int batch, double* partial, double* out, int64_t out_stride);
+
+// Contiguous copy of `n` complex64 per batch item.
+hipError_t launch_copy(hipStream_t s, const float2* in, int64_t in_bs, float2* out, int64_t out_bs, int64_t n,
+                       int batch);
+
+// ---- adjoint sweep
+struct SweepArgs {
+  int32_t nq;
+  int32_t pos[2];      // address-bit positions of the gate's qubits (q[0], q[1])
+  int32_t gen;         // GenKind of the gate (GEN_NONE: no gradient term)
+  int32_t slot;        // column of the gradient-partials table for this gate (or -1)
+};
+// lambda_z[x] = D(x) psi_z[x]
+hipError_t launch_apply_diag_obs(hipStream_t s, const float2* psi, int64_t psi_bs, float2* lam, int64_t lam_bs,
+                                 int64_t n_elems, const ZTerms& terms, int batch);
+// one reverse step: g = 2 Im<lam|G|psi> (partials), then psi <- U^dagger psi, lam <- U^dagger lam.
+// U: complex64 [batch][u_bs] matrix (2x2 or 4x4, row-major).
+hipError_t launch_adjoint_step(hipStream_t s, const SweepArgs& a, const float2* u, int64_t u_bs, float2* psi,
+                               int64_t psi_bs, float2* lam, int64_t lam_bs, int64_t n_elems, int batch,
+                               double* partials, int64_t partial_stride);
+// grad[z][p] = scale_z * sum over slots with param p and blocks of partials
+hipError_t launch_gradient_reduce(hipStream_t s, const double* partials, int64_t partial_stride, int n_slots,
+                                  const int32_t* slot_param, int n_params, const double* grad_out, int batch,
+                                  double* grad);
+// sweep gate matrices: recipe r of the sweep -> [batch][n_sweep][16] complex64
+hipError_t launch_sweep_matrices(hipStream_t s, const Recipe* recipes, int n, const RecipeOp* ops, const double* mats,
+                                 const double* params, int64_t params_stride, int batch, float2* out);
+
+}  // namespace tnq

@@ -1,0 +1,681 @@
+// gfx950 kernels of the contraction path.
+//
+//  * k_materialize / k_projectors: gate tensors from angles (FP64, rounded once
+//    to complex64), |0> vectors and one-hot bitstring projectors.
+//  * k_skinny: a pairwise contraction whose smaller operand is gate-sized.  It
+//    streams the large operand once from HBM (HBM-bound) through strided
+//    addresses, so no permute is needed before it.
+//  * k_permute: bit-permutation transpose staged through LDS so that both the
+//    reads and the writes are coalesced.
+//  * k_gemm: complex matrix product on the FP32 matrix cores (4M form through
+//    a real embedding, below), batched over the batch modes.
+//  * k_expect_* / k_adjoint_*: FP64-accumulated reductions for expectations
+//    and the adjoint gradient.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "kernels.h"
+
+namespace tnq {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ inline float2 f2(float x, float y) { return make_float2(x, y); }
+
+// round-to-nearest-even to bfloat16, returned as float
+__device__ inline float bf16_round(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return __uint_as_float(u & 0xffff0000u);
+}
+
+// a*b (real) in the requested precision: FP32, or the three-term bf16 split
+template <int PREC>
+__device__ inline float rmul(float a, float b) {
+  if constexpr (PREC == TN_PREC_C64) {
+    return a * b;
+  } else {
+    const float ah = bf16_round(a), al = bf16_round(a - ah);
+    const float bh = bf16_round(b), bl = bf16_round(b - bh);
+    return fmaf(ah, bh, fmaf(ah, bl, al * bh));
+  }
+}
+
+template <int PREC>
+__device__ inline float2 cmac(float2 acc, float2 a, float2 b) {
+  acc.x += rmul<PREC>(a.x, b.x) - rmul<PREC>(a.y, b.y);
+  acc.y += rmul<PREC>(a.x, b.y) + rmul<PREC>(a.y, b.x);
+  return acc;
+}
+
+__device__ inline double block_sum(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double t = 0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += red[i];
+  __syncthreads();
+  return t;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Materialisation of the network's input tensors
+// ---------------------------------------------------------------------------
+__global__ void k_materialize(const DevTensor* ts, int nt, const Recipe* rs, const RecipeOp* ops, const double* mats,
+                              const double* params, int64_t pstride, float2* in, int64_t in_bs) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int z = blockIdx.y;
+  if (t >= nt) return;
+  const DevTensor d = ts[t];
+  float2* o = in + (int64_t)z * in_bs + d.offset;
+  if (d.kind == TK_KET0) {
+    o[0] = f2(1.f, 0.f);
+    o[1] = f2(0.f, 0.f);
+  } else if (d.kind == TK_GATE) {
+    const Recipe r = rs[d.recipe];
+    c128 M[16];
+    recipe_matrix(r, ops, mats, params ? params + (int64_t)z * pstride : nullptr, M);
+    const int dd = r.nq == 2 ? 4 : 2;
+    if (r.diag) {
+      for (int i = 0; i < dd; ++i) o[i] = f2((float)M[dd * i + i].re, (float)M[dd * i + i].im);
+    } else {
+      for (int i = 0; i < dd * dd; ++i) o[i] = f2((float)M[i].re, (float)M[i].im);
+    }
+  }
+}
+
+__global__ void k_projectors(const uint64_t* bits, int64_t count, int n, int blog2, int64_t first, float2* in,
+                             int64_t in_bs) {
+  const int64_t per = (int64_t)1 << blog2;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int z = blockIdx.y;
+  if (i >= per * n) return;
+  const int q = (int)(i / per);
+  const int64_t s = i % per;
+  const int bit = s < count ? (int)((bits[s] >> (n - 1 - q)) & 1) : 0;
+  float2* o = in + (int64_t)z * in_bs + first + (int64_t)q * per * 2 + 2 * s;
+  o[0] = f2(bit == 0 ? 1.f : 0.f, 0.f);
+  o[1] = f2(bit == 1 ? 1.f : 0.f, 0.f);
+}
+
+hipError_t launch_materialize(hipStream_t s, const DevTensor* ts, int nt, const Recipe* recipes, const RecipeOp* ops,
+                              const double* mats, const double* params, int64_t params_stride, int batch,
+                              float2* in, int64_t in_bs) {
+  if (nt == 0) return hipSuccess;
+  dim3 grid((nt + 127) / 128, batch);
+  hipLaunchKernelGGL(k_materialize, grid, dim3(128), 0, s, ts, nt, recipes, ops, mats, params, params_stride, in,
+                     in_bs);
+  return hipGetLastError();
+}
+
+hipError_t launch_projectors(hipStream_t s, const uint64_t* bits, int64_t count, int n_qubits, int blog2,
+                             int64_t first_offset, int batch, float2* in, int64_t in_bs) {
+  const int64_t total = ((int64_t)1 << blog2) * n_qubits;
+  dim3 grid((unsigned)((total + kThreads - 1) / kThreads), batch);
+  hipLaunchKernelGGL(k_projectors, grid, dim3(kThreads), 0, s, bits, count, n_qubits, blog2, first_offset, in, in_bs);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Small-operand contraction
+// ---------------------------------------------------------------------------
+struct SkinnyArgs {
+  const float2* g;
+  const float2* t;
+  float2* c;
+  int64_t g_bs, t_bs, c_bs;
+  int64_t n_outer;
+  int32_t nb, c_mode, g_elems, pad;
+  int32_t k_pos[kSkinnyMaxK];
+  int32_t b_pos[kSkinnyMaxG];
+  int64_t kofs[1 << kSkinnyMaxK];
+  int64_t mofs[1 << kSkinnyMaxM];
+  int32_t gidx[1 << kSkinnyMaxG];
+};
+
+template <int NK, int NM, int PREC>
+__global__ __launch_bounds__(kThreads) void k_skinny(SkinnyArgs a) {
+  __shared__ float2 gs[1 << kSkinnyMaxG];
+  const int z = blockIdx.y;
+  const float2* G = a.g + (int64_t)z * a.g_bs;
+  const float2* Tp = a.t + (int64_t)z * a.t_bs;
+  float2* Cp = a.c + (int64_t)z * a.c_bs;
+  for (int i = threadIdx.x; i < a.g_elems; i += kThreads) gs[i] = G[a.gidx[i]];
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * kThreads;
+  for (int64_t o = (int64_t)blockIdx.x * kThreads + threadIdx.x; o < a.n_outer; o += stride) {
+    int64_t tb = o;
+#pragma unroll
+    for (int j = 0; j < NK; ++j) {
+      const int p = a.k_pos[j];
+      tb = ((tb >> p) << (p + 1)) | (tb & (((int64_t)1 << p) - 1));
+    }
+    int b = 0;
+    for (int j = 0; j < a.nb; ++j) b |= (int)((o >> a.b_pos[j]) & 1) << j;
+    float2 x[1 << NK];
+#pragma unroll
+    for (int k = 0; k < (1 << NK); ++k) x[k] = Tp[tb | a.kofs[k]];
+    const int64_t cb = a.c_mode ? o : tb;
+    const float2* gb = gs + (b << (NM + NK));
+#pragma unroll
+    for (int m = 0; m < (1 << NM); ++m) {
+      float2 acc = f2(0.f, 0.f);
+#pragma unroll
+      for (int k = 0; k < (1 << NK); ++k) acc = cmac<PREC>(acc, gb[(m << NK) + k], x[k]);
+      Cp[cb | a.mofs[m]] = acc;
+    }
+  }
+}
+
+template <int NK, int NM>
+static void* skinny_fn(int prec) {
+  return prec == TN_PREC_BF16X3 ? (void*)k_skinny<NK, NM, TN_PREC_BF16X3> : (void*)k_skinny<NK, NM, TN_PREC_C64>;
+}
+
+template <int NK>
+static void* skinny_fn_m(int nm, int prec) {
+  switch (nm) {
+    case 0: return skinny_fn<NK, 0>(prec);
+    case 1: return skinny_fn<NK, 1>(prec);
+    case 2: return skinny_fn<NK, 2>(prec);
+    case 3: return skinny_fn<NK, 3>(prec);
+    default: return skinny_fn<NK, 4>(prec);
+  }
+}
+
+hipError_t launch_skinny(hipStream_t s, const SkinnyDesc& d, const float2* g, int64_t g_bs, const float2* t,
+                         int64_t t_bs, float2* c, int64_t c_bs, int batch, int precision) {
+  SkinnyArgs a;
+  a.g = g; a.t = t; a.c = c;
+  a.g_bs = g_bs; a.t_bs = t_bs; a.c_bs = c_bs;
+  a.n_outer = (int64_t)1 << (d.t_bits - d.nk);
+  a.nb = d.nb;
+  a.c_mode = d.c_mode;
+  a.g_elems = 1 << (d.nb + d.nm + d.nk);
+  a.pad = 0;
+  for (int j = 0; j < kSkinnyMaxK; ++j) a.k_pos[j] = d.k_pos[j];
+  for (int j = 0; j < kSkinnyMaxG; ++j) a.b_pos[j] = d.b_pos[j];
+  for (int j = 0; j < (1 << kSkinnyMaxK); ++j) a.kofs[j] = d.kofs[j];
+  for (int j = 0; j < (1 << kSkinnyMaxM); ++j) a.mofs[j] = d.mofs[j];
+  for (int j = 0; j < (1 << kSkinnyMaxG); ++j) a.gidx[j] = d.gidx[j];
+  void* fn;
+  switch (d.nk) {
+    case 0: fn = skinny_fn_m<0>(d.nm, precision); break;
+    case 1: fn = skinny_fn_m<1>(d.nm, precision); break;
+    case 2: fn = skinny_fn_m<2>(d.nm, precision); break;
+    case 3: fn = skinny_fn_m<3>(d.nm, precision); break;
+    default: fn = skinny_fn_m<4>(d.nm, precision); break;
+  }
+  int64_t blocks = (a.n_outer + kThreads - 1) / kThreads;
+  if (blocks > 16384) blocks = 16384;
+  void* args[] = {&a};
+  return hipLaunchKernel(fn, dim3((unsigned)blocks, batch), dim3(kThreads), args, 0, s);
+}
+
+// ---------------------------------------------------------------------------
+// Bit-permutation transpose through LDS
+// ---------------------------------------------------------------------------
+constexpr int kMaxTileBits = 10;
+
+struct PermArgs {
+  const float2* in;
+  float2* out;
+  int64_t in_bs, out_bs;
+  int64_t n_blocks;
+  int32_t tile_bits, rest_bits;
+  int8_t tin[kMaxTileBits];    // input position of tile-index bit j (load order)
+  int8_t tsrc[kMaxTileBits];   // store order: bit j of the store index = load-index bit tsrc[j]
+  int8_t tout[kMaxTileBits];   // output position of store-index bit j
+  int8_t rest_in[64];
+  int8_t rest_out[64];
+};
+
+__global__ __launch_bounds__(kThreads) void k_permute(PermArgs a) {
+  __shared__ float2 buf[(1 << kMaxTileBits) + (1 << (kMaxTileBits - 5))];
+  const int z = blockIdx.y;
+  const float2* in = a.in + (int64_t)z * a.in_bs;
+  float2* out = a.out + (int64_t)z * a.out_bs;
+  const int tile = 1 << a.tile_bits;
+  constexpr int kPer = (1 << kMaxTileBits) / kThreads;
+  int64_t in_off[kPer], out_off[kPer];
+  int lds_src[kPer];
+  for (int e = 0; e < kPer; ++e) {
+    const int l = threadIdx.x + e * kThreads;
+    int64_t io = 0, oo = 0;
+    int src = 0;
+    for (int j = 0; j < a.tile_bits; ++j) {
+      if ((l >> j) & 1) {
+        io |= (int64_t)1 << a.tin[j];
+        oo |= (int64_t)1 << a.tout[j];
+        src |= 1 << a.tsrc[j];
+      }
+    }
+    in_off[e] = io;
+    out_off[e] = oo;
+    lds_src[e] = src + (src >> 5);
+  }
+  for (int64_t blk = blockIdx.x; blk < a.n_blocks; blk += gridDim.x) {
+    int64_t ib = 0, ob = 0;
+    for (int j = 0; j < a.rest_bits; ++j)
+      if ((blk >> j) & 1) {
+        ib |= (int64_t)1 << a.rest_in[j];
+        ob |= (int64_t)1 << a.rest_out[j];
+      }
+    for (int e = 0; e < kPer; ++e) {
+      const int l = threadIdx.x + e * kThreads;
+      if (l < tile) buf[l + (l >> 5)] = in[ib | in_off[e]];
+    }
+    __syncthreads();
+    for (int e = 0; e < kPer; ++e) {
+      const int l = threadIdx.x + e * kThreads;
+      if (l < tile) out[ob | out_off[e]] = buf[lds_src[e]];
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_permute(hipStream_t s, const PermuteDesc& d, const float2* in, int64_t in_bs, float2* out,
+                          int64_t out_bs, int batch) {
+  const int R = d.bits;
+  // tile: the low input bits plus the input bits that land on the low output bits,
+  // grown while it fits in kMaxTileBits
+  std::vector<int> best;
+  for (int a = 1; a <= R; ++a) {
+    std::vector<char> in_tile(R, 0);
+    for (int p = 0; p < a; ++p) in_tile[p] = 1;
+    for (int p = 0; p < R; ++p)
+      if (d.dst[p] < a) in_tile[p] = 1;
+    std::vector<int> t;
+    for (int p = 0; p < R; ++p)
+      if (in_tile[p]) t.push_back(p);
+    if ((int)t.size() > kMaxTileBits) break;
+    best = t;
+  }
+  PermArgs a;
+  a.in = in; a.out = out; a.in_bs = in_bs; a.out_bs = out_bs;
+  a.tile_bits = (int)best.size();
+  for (int j = 0; j < a.tile_bits; ++j) a.tin[j] = (int8_t)best[j];
+  // store order: tile bits by ascending output position
+  std::vector<int> order(a.tile_bits);
+  for (int j = 0; j < a.tile_bits; ++j) order[j] = j;
+  std::sort(order.begin(), order.end(), [&](int x, int y) { return d.dst[best[x]] < d.dst[best[y]]; });
+  for (int j = 0; j < a.tile_bits; ++j) {
+    a.tsrc[j] = (int8_t)order[j];
+    a.tout[j] = (int8_t)d.dst[best[order[j]]];
+  }
+  int nr = 0;
+  for (int p = 0; p < R; ++p) {
+    if (std::find(best.begin(), best.end(), p) != best.end()) continue;
+    a.rest_in[nr] = (int8_t)p;
+    a.rest_out[nr] = (int8_t)d.dst[p];
+    ++nr;
+  }
+  a.rest_bits = nr;
+  a.n_blocks = (int64_t)1 << nr;
+  int64_t blocks = a.n_blocks;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_permute, dim3((unsigned)blocks, batch), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Complex GEMM on the FP32 matrix cores
+//
+// With complex64 stored as interleaved (re, im), A (M x K complex) is read as
+// the real M x 2K matrix A_r, and B (K x N complex) is expanded on the fly
+// into the real 2K x 2N matrix B' whose 2x2 block (k, n) is
+// [[Re b, Im b], [-Im b, Re b]].  Then A_r B' is the interleaved real view of
+// A B (4M form: 4 real multiply-adds per complex one).  One
+// v_mfma_f32_32x32x2f32 consumes exactly one complex k: lanes 0-31 carry
+// Re A / the first row of the block of B', lanes 32-63 Im A / the second row,
+// and produces a 32 x 16 complex tile.
+// ---------------------------------------------------------------------------
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+constexpr int kBM = 128, kBN = 64, kBK = 16;
+
+struct GemmArgs {
+  const float2* A;
+  const float2* B;
+  float2* C;
+  int64_t a_bs, b_bs, c_bs;
+  int64_t batch, M, N, K;
+  int64_t tiles_m, tiles_n;
+};
+
+template <int AK, int BNF, int PREC>
+__global__ __launch_bounds__(kThreads) void k_gemm(GemmArgs g) {
+  __shared__ float As_re[kBK][kBM + 1];
+  __shared__ float As_im[kBK][kBM + 1];
+  __shared__ float2 Bs[kBK][kBN + 1];
+  const int64_t bid = blockIdx.x;
+  const int64_t tn = bid % g.tiles_n;
+  const int64_t tm = (bid / g.tiles_n) % g.tiles_m;
+  const int64_t gb = (bid / (g.tiles_n * g.tiles_m)) % g.batch;
+  const int64_t z = bid / (g.tiles_n * g.tiles_m * g.batch);
+  const float2* A = g.A + z * g.a_bs + gb * g.M * g.K;
+  const float2* B = g.B + z * g.b_bs + gb * g.K * g.N;
+  float2* C = g.C + z * g.c_bs + gb * g.M * g.N;
+  const int64_t m0 = tm * kBM, n0 = tn * kBN;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w >> 1, wn = w & 1;
+  floatx16 acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
+
+  for (int64_t k0 = 0; k0 < g.K; k0 += kBK) {
+    // A tile -> split planes [k][m]
+#pragma unroll
+    for (int e = 0; e < (kBM * kBK) / kThreads; ++e) {
+      const int idx = tid + e * kThreads;
+      int mm, kk;
+      if (AK) { mm = idx / kBK; kk = idx % kBK; } else { mm = idx % kBM; kk = idx / kBM; }
+      const int64_t gm = m0 + mm, gk = k0 + kk;
+      float2 v = f2(0.f, 0.f);
+      if (gm < g.M && gk < g.K) v = AK ? A[gm * g.K + gk] : A[gk * g.M + gm];
+      if (PREC == TN_PREC_BF16X3) { /* operands are split at the product */ }
+      As_re[kk][mm] = v.x;
+      As_im[kk][mm] = v.y;
+    }
+#pragma unroll
+    for (int e = 0; e < (kBN * kBK) / kThreads; ++e) {
+      const int idx = tid + e * kThreads;
+      int nn, kk;
+      if (BNF) { nn = idx % kBN; kk = idx / kBN; } else { nn = idx / kBK; kk = idx % kBK; }
+      const int64_t gn = n0 + nn, gk = k0 + kk;
+      float2 v = f2(0.f, 0.f);
+      if (gn < g.N && gk < g.K) v = BNF ? B[gk * g.N + gn] : B[gn * g.K + gk];
+      Bs[kk][nn] = v;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < kBK; ++kk) {
+      float av[2], bv[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int row = wm * 64 + i * 32 + (lane & 31);
+        av[i] = lane < 32 ? As_re[kk][row] : As_im[kk][row];
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const float2 bb = Bs[kk][wn * 32 + j * 16 + ((lane & 31) >> 1)];
+        const bool odd = lane & 1;
+        bv[j] = lane < 32 ? (odd ? bb.y : bb.x) : (odd ? bb.x : -bb.y);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          if constexpr (PREC == TN_PREC_C64) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+          } else {
+            const float ah = bf16_round(av[i]), al = bf16_round(av[i] - ah);
+            const float bh = bf16_round(bv[j]), bl = bf16_round(bv[j] - bh);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(al, bh, acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ah, bl, acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ah, bh, acc[i][j], 0, 0, 0);
+          }
+        }
+    }
+    __syncthreads();
+  }
+  float* Cf = reinterpret_cast<float*>(C);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int64_t row = m0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        const int jj = lane & 31;
+        const int64_t col = n0 + wn * 32 + j * 16 + (jj >> 1);
+        if (row < g.M && col < g.N) Cf[(row * g.N + col) * 2 + (jj & 1)] = acc[i][j][v];
+      }
+}
+
+hipError_t launch_gemm(hipStream_t s, const GemmDesc& d, const float2* a, int64_t a_bs, const float2* b, int64_t b_bs,
+                       float2* c, int64_t c_bs, int batch, int precision) {
+  GemmArgs g;
+  g.A = a; g.B = b; g.C = c;
+  g.a_bs = a_bs; g.b_bs = b_bs; g.c_bs = c_bs;
+  g.batch = d.batch; g.M = d.M; g.N = d.N; g.K = d.K;
+  g.tiles_m = (d.M + kBM - 1) / kBM;
+  g.tiles_n = (d.N + kBN - 1) / kBN;
+  const int64_t blocks = g.tiles_m * g.tiles_n * d.batch * batch;
+  if (blocks > ((int64_t)1 << 24)) return hipErrorInvalidValue;
+  void* fn;
+  const bool bf = precision == TN_PREC_BF16X3;
+  if (d.a_kfast && d.b_nfast) fn = bf ? (void*)k_gemm<1, 1, 1> : (void*)k_gemm<1, 1, 0>;
+  else if (d.a_kfast) fn = bf ? (void*)k_gemm<1, 0, 1> : (void*)k_gemm<1, 0, 0>;
+  else if (d.b_nfast) fn = bf ? (void*)k_gemm<0, 1, 1> : (void*)k_gemm<0, 1, 0>;
+  else fn = bf ? (void*)k_gemm<0, 0, 1> : (void*)k_gemm<0, 0, 0>;
+  void* args[] = {&g};
+  return hipLaunchKernel(fn, dim3((unsigned)blocks), dim3(kThreads), args, 0, s);
+}
+
+// ---------------------------------------------------------------------------
+// Reductions (FP64 accumulation)
+// ---------------------------------------------------------------------------
+__device__ inline double zdiag(uint64_t x, const ZTerms& t) {
+  double d = 0;
+  for (int i = 0; i < t.n; ++i) d += (__popcll(x & t.mask[i]) & 1) ? -t.coeff[i] : t.coeff[i];
+  return d;
+}
+
+__global__ __launch_bounds__(kThreads) void k_expect_partial(const float2* psi, int64_t bs, int64_t n, ZTerms t,
+                                                             double* partial) {
+  __shared__ double red[kThreads / 64];
+  const int z = blockIdx.y;
+  const float2* p = psi + (int64_t)z * bs;
+  double acc = 0;
+  for (int64_t x = (int64_t)blockIdx.x * kThreads + threadIdx.x; x < n; x += (int64_t)gridDim.x * kThreads) {
+    const float2 v = p[x];
+    const double pr = (double)v.x * v.x + (double)v.y * v.y;
+    acc += pr * zdiag((uint64_t)x, t);
+  }
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) partial[(int64_t)z * kReduceBlocks + blockIdx.x] = s;
+}
+
+__global__ void k_reduce_rows(const double* partial, int nb, int batch, double* out, int64_t out_stride) {
+  const int z = blockIdx.x * blockDim.x + threadIdx.x;
+  if (z >= batch) return;
+  double s = 0;
+  for (int i = 0; i < nb; ++i) s += partial[(int64_t)z * kReduceBlocks + i];
+  out[(int64_t)z * out_stride] = s;
+}
+
+hipError_t launch_expectation(hipStream_t s, const float2* psi, int64_t psi_bs, int64_t n_elems, const ZTerms& terms,
+                              int batch, double* partial, double* out, int64_t out_stride) {
+  int64_t blocks = (n_elems + kThreads - 1) / kThreads;
+  if (blocks > kReduceBlocks) blocks = kReduceBlocks;
+  hipLaunchKernelGGL(k_expect_partial, dim3((unsigned)blocks, batch), dim3(kThreads), 0, s, psi, psi_bs, n_elems,
+                     terms, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reduce_rows, dim3((batch + 63) / 64), dim3(64), 0, s, partial, (int)blocks, batch, out,
+                     out_stride);
+  return hipGetLastError();
+}
+
+__global__ void k_copy(const float2* in, int64_t in_bs, float2* out, int64_t out_bs, int64_t n) {
+  const int z = blockIdx.y;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
+    out[(int64_t)z * out_bs + i] = in[(int64_t)z * in_bs + i];
+}
+
+hipError_t launch_copy(hipStream_t s, const float2* in, int64_t in_bs, float2* out, int64_t out_bs, int64_t n,
+                       int batch) {
+  int64_t blocks = (n + kThreads - 1) / kThreads;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks, batch), dim3(kThreads), 0, s, in, in_bs, out, out_bs, n);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint sweep
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_apply_diag_obs(const float2* psi, int64_t psi_bs, float2* lam,
+                                                             int64_t lam_bs, int64_t n, ZTerms t) {
+  const int z = blockIdx.y;
+  for (int64_t x = (int64_t)blockIdx.x * kThreads + threadIdx.x; x < n; x += (int64_t)gridDim.x * kThreads) {
+    const float2 v = psi[(int64_t)z * psi_bs + x];
+    const double d = zdiag((uint64_t)x, t);
+    lam[(int64_t)z * lam_bs + x] = f2((float)(d * v.x), (float)(d * v.y));
+  }
+}
+
+hipError_t launch_apply_diag_obs(hipStream_t s, const float2* psi, int64_t psi_bs, float2* lam, int64_t lam_bs,
+                                 int64_t n_elems, const ZTerms& terms, int batch) {
+  int64_t blocks = (n_elems + kThreads - 1) / kThreads;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(k_apply_diag_obs, dim3((unsigned)blocks, batch), dim3(kThreads), 0, s, psi, psi_bs, lam, lam_bs,
+                     n_elems, terms);
+  return hipGetLastError();
+}
+
+// Im(conj(l) * p)
+__device__ inline double im_cl_p(float2 l, float2 p) { return (double)l.x * p.y - (double)l.y * p.x; }
+// Re(conj(l) * p)
+__device__ inline double re_cl_p(float2 l, float2 p) { return (double)l.x * p.x + (double)l.y * p.y; }
+
+template <int NQ>
+__global__ __launch_bounds__(kThreads) void k_adjoint_step(SweepArgs a, const float2* U, int64_t u_bs, float2* psi,
+                                                           int64_t psi_bs, float2* lam, int64_t lam_bs,
+                                                           int64_t n_groups, double* partials, int64_t pstride) {
+  __shared__ double red[kThreads / 64];
+  constexpr int D = 1 << NQ;
+  const int z = blockIdx.y;
+  float2* P = psi + (int64_t)z * psi_bs;
+  float2* L = lam + (int64_t)z * lam_bs;
+  float2 u[D * D];
+  for (int i = 0; i < D * D; ++i) u[i] = U[(int64_t)z * u_bs + i];
+  int lo = a.pos[0], hi = a.pos[0];
+  if (NQ == 2) { lo = min(a.pos[0], a.pos[1]); hi = max(a.pos[0], a.pos[1]); }
+  double g = 0;
+  for (int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x; j < n_groups; j += (int64_t)gridDim.x * kThreads) {
+    int64_t base = ((j >> lo) << (lo + 1)) | (j & (((int64_t)1 << lo) - 1));
+    if (NQ == 2) base = ((base >> hi) << (hi + 1)) | (base & (((int64_t)1 << hi) - 1));
+    int64_t idx[D];
+    if (NQ == 1) {
+      idx[0] = base;
+      idx[1] = base | ((int64_t)1 << a.pos[0]);
+    } else {
+      for (int v = 0; v < 4; ++v)
+        idx[v] = base | ((int64_t)(v >> 1) << a.pos[0]) | ((int64_t)(v & 1) << a.pos[1]);
+    }
+    float2 p[D], l[D];
+    for (int v = 0; v < D; ++v) { p[v] = P[idx[v]]; l[v] = L[idx[v]]; }
+    switch (a.gen) {
+      case GEN_X_HALF: g += im_cl_p(l[0], p[1]) + im_cl_p(l[1], p[0]); break;
+      case GEN_X: g += 2.0 * (im_cl_p(l[0], p[1]) + im_cl_p(l[1], p[0])); break;
+      case GEN_Y_HALF:  // Y p = (-i p1, i p0);  Im(conj(l) (-i p)) = -Re(conj(l) p)
+        g += -re_cl_p(l[0], p[1]) + re_cl_p(l[1], p[0]); break;
+      case GEN_Z_HALF: g += im_cl_p(l[0], p[0]) - im_cl_p(l[1], p[1]); break;
+      case GEN_ZZ_PHASE: if (NQ == 2) g += 2.0 * (im_cl_p(l[1], p[1]) + im_cl_p(l[2], p[2])); break;
+      case GEN_CPHASE: if (NQ == 2) g += -2.0 * im_cl_p(l[3], p[3]); break;
+      default: break;
+    }
+    // psi <- U^dagger psi, lam <- U^dagger lam
+    for (int r = 0; r < D; ++r) {
+      float2 ap = f2(0.f, 0.f), al = f2(0.f, 0.f);
+      for (int c = 0; c < D; ++c) {
+        const float2 uc = u[c * D + r];  // conj(U[c][r])
+        ap.x += uc.x * p[c].x + uc.y * p[c].y;
+        ap.y += uc.x * p[c].y - uc.y * p[c].x;
+        al.x += uc.x * l[c].x + uc.y * l[c].y;
+        al.y += uc.x * l[c].y - uc.y * l[c].x;
+      }
+      P[idx[r]] = ap;
+      L[idx[r]] = al;
+    }
+  }
+  if (a.slot >= 0) {
+    const double s = block_sum(g, red);
+    if (threadIdx.x == 0) partials[(int64_t)z * pstride + (int64_t)a.slot * kReduceBlocks + blockIdx.x] = s;
+  }
+}
+
+hipError_t launch_adjoint_step(hipStream_t s, const SweepArgs& a, const float2* u, int64_t u_bs, float2* psi,
+                               int64_t psi_bs, float2* lam, int64_t lam_bs, int64_t n_elems, int batch,
+                               double* partials, int64_t partial_stride) {
+  const int64_t groups = n_elems >> a.nq;
+  // a fixed grid so that every partial slot is written
+  const int blocks = kReduceBlocks;
+  void* fn = a.nq == 2 ? (void*)k_adjoint_step<2> : (void*)k_adjoint_step<1>;
+  SweepArgs aa = a;
+  void* args[] = {&aa, (void*)&u, (void*)&u_bs, (void*)&psi, (void*)&psi_bs, (void*)&lam, (void*)&lam_bs,
+                  (void*)&groups, (void*)&partials, (void*)&partial_stride};
+  return hipLaunchKernel(fn, dim3(blocks, batch), dim3(kThreads), args, 0, s);
+}
+
+__global__ void k_slot_sums(double* partials, int64_t pstride, int n_slots, int batch) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)n_slots * batch) return;
+  const int z = (int)(i / n_slots), sl = (int)(i % n_slots);
+  double* p = partials + (int64_t)z * pstride + (int64_t)sl * kReduceBlocks;
+  double s = 0;
+  for (int b = 0; b < kReduceBlocks; ++b) s += p[b];
+  p[0] = s;
+}
+
+__global__ void k_param_sums(const double* partials, int64_t pstride, int n_slots, const int32_t* slot_param,
+                             int n_params, const double* grad_out, int batch, double* grad) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)n_params * batch) return;
+  const int z = (int)(i / n_params), pp = (int)(i % n_params);
+  double s = 0;
+  for (int sl = 0; sl < n_slots; ++sl)
+    if (slot_param[sl] == pp) s += partials[(int64_t)z * pstride + (int64_t)sl * kReduceBlocks];
+  const double scale = grad_out ? grad_out[z] : 1.0;
+  grad[(int64_t)z * n_params + pp] = scale * s;
+}
+
+hipError_t launch_gradient_reduce(hipStream_t s, const double* partials, int64_t partial_stride, int n_slots,
+                                  const int32_t* slot_param, int n_params, const double* grad_out, int batch,
+                                  double* grad) {
+  if (n_slots > 0) {
+    const int64_t n1 = (int64_t)n_slots * batch;
+    hipLaunchKernelGGL(k_slot_sums, dim3((unsigned)((n1 + 127) / 128)), dim3(128), 0, s, (double*)partials,
+                       partial_stride, n_slots, batch);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  const int64_t n2 = (int64_t)n_params * batch;
+  if (n2 == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_param_sums, dim3((unsigned)((n2 + 127) / 128)), dim3(128), 0, s, partials, partial_stride,
+                     n_slots, slot_param, n_params, grad_out, batch, grad);
+  return hipGetLastError();
+}
+
+__global__ void k_sweep_matrices(const Recipe* rs, int n, const RecipeOp* ops, const double* mats,
+                                 const double* params, int64_t pstride, float2* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int z = blockIdx.y;
+  if (i >= n) return;
+  c128 M[16];
+  recipe_matrix(rs[i], ops, mats, params ? params + (int64_t)z * pstride : nullptr, M);
+  const int d = rs[i].nq == 2 ? 4 : 2;
+  float2* o = out + ((int64_t)z * n + i) * 16;
+  for (int k = 0; k < d * d; ++k) o[k] = f2((float)M[k].re, (float)M[k].im);
+}
+
+hipError_t launch_sweep_matrices(hipStream_t s, const Recipe* recipes, int n, const RecipeOp* ops, const double* mats,
+                                 const double* params, int64_t params_stride, int batch, float2* out) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sweep_matrices, dim3((n + 127) / 128, batch), dim3(128), 0, s, recipes, n, ops, mats, params,
+                     params_stride, out);
+  return hipGetLastError();
+}
+
+}  // namespace tnq

@@ -1,0 +1,519 @@
+// Compile a contraction order into an executable program: memory layouts of
+// every intermediate, the kernel for each pairwise step, the operand permutes
+// it needs, and workspace offsets.
+//
+// Every extent is a power of two, so a tensor is a 2^R array whose address
+// bits are labelled (mode, bit-of-mode); a mode permutation is a permutation of
+// address bits.  A pairwise step (Sec. 2.2.1, eq. (2.2)) classifies modes as
+// batch (in A, B and C -- the block-diagonal structure that Sec. 3 builds
+// with block_diag), M (A and C), N (B and C) and K (A and B, summed):
+//   * small operand (gate-like, <= 2^8 elements, <= 2^4 summed and <= 2^4
+//     output combinations): a streaming kernel that reads the large operand
+//     in place through strided addresses and writes C with the large
+//     operand's layout (no permute);
+//   * otherwise: the MFMA complex matrix product on [batch][M][K] x
+//     [batch][K][N] -> [batch][M][N], permuting an operand first only when
+//     its bits are not already grouped that way.
+#include <chrono>
+#include <map>
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace tnq {
+
+namespace {
+
+inline int32_t label(int mode, int j) { return mode * 64 + j; }
+inline int mode_of(int32_t lab) { return lab / 64; }
+
+std::vector<int32_t> bits_of_modes(const tn_network* net, const std::vector<int32_t>& modes) {
+  std::vector<int32_t> b;
+  for (int m : modes)
+    for (int j = net->mode_log2[m] - 1; j >= 0; --j) b.push_back(label(m, j));
+  return b;
+}
+
+// address position of the label in a layout (MSB-first list)
+int pos_of(const std::vector<int32_t>& bits, int32_t lab) {
+  for (size_t i = 0; i < bits.size(); ++i)
+    if (bits[i] == lab) return (int)(bits.size() - 1 - i);
+  return -1;
+}
+
+struct Alloc {
+  std::map<int64_t, int64_t> free_;  // offset -> size
+  int64_t top = 0, peak = 0;
+  static int64_t round(int64_t n) { return (n + 31) & ~(int64_t)31; }  // 256-byte granules
+  int64_t get(int64_t n) {
+    n = round(n);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= n) {
+        int64_t off = it->first, sz = it->second;
+        free_.erase(it);
+        if (sz > n) free_[off + n] = sz - n;
+        return off;
+      }
+    }
+    int64_t off = top;
+    top += n;
+    peak = std::max(peak, top);
+    return off;
+  }
+  void put(int64_t off, int64_t n) {
+    n = round(n);
+    free_[off] = n;
+    // coalesce
+    auto it = free_.find(off);
+    if (it != free_.begin()) {
+      auto p = std::prev(it);
+      if (p->first + p->second == it->first) { p->second += it->second; free_.erase(it); it = p; }
+    }
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) { it->second += nx->second; free_.erase(nx); }
+    if (it->first + it->second == top) { top = it->first; free_.erase(it); }
+  }
+};
+
+struct Loc {
+  BufRef ref;
+  std::vector<int32_t> bits;
+  int64_t elems = 0;
+  bool input = false;
+  int last_use = -1;
+};
+
+enum Cls { C_BATCH = 0, C_M = 1, C_N = 2, C_K = 3 };
+
+PermuteDesc make_permute(const BufRef& in, const std::vector<int32_t>& from, const BufRef& out,
+                         const std::vector<int32_t>& to) {
+  PermuteDesc p;
+  p.in = in;
+  p.out = out;
+  p.bits = (int32_t)from.size();
+  for (int i = 0; i < 64; ++i) p.dst[i] = 0;
+  for (size_t i = 0; i < from.size(); ++i) {
+    int pin = (int)(from.size() - 1 - i);
+    p.dst[pin] = pos_of(to, from[i]);
+  }
+  return p;
+}
+
+// is `bits` = [batch run][X run][Y run] with {X, Y} = {c1, c2}?  returns orientation via fast_cls
+bool grouped(const std::vector<int32_t>& bits, const std::map<int32_t, int>& cls, int c1, int c2, int* fast_cls) {
+  size_t i = 0;
+  while (i < bits.size() && cls.at(bits[i]) == C_BATCH) ++i;
+  if (i == bits.size()) { *fast_cls = c2; return true; }
+  int first = cls.at(bits[i]);
+  if (first != c1 && first != c2) return false;
+  while (i < bits.size() && cls.at(bits[i]) == first) ++i;
+  if (i == bits.size()) { *fast_cls = first; return true; }
+  int second = cls.at(bits[i]);
+  if (second == first || (second != c1 && second != c2)) return false;
+  while (i < bits.size() && cls.at(bits[i]) == second) ++i;
+  if (i != bits.size()) return false;
+  *fast_cls = second;
+  return true;
+}
+
+std::vector<int32_t> filter(const std::vector<int32_t>& bits, const std::map<int32_t, int>& cls, int c) {
+  std::vector<int32_t> out;
+  for (int32_t b : bits)
+    if (cls.at(b) == c) out.push_back(b);
+  return out;
+}
+
+std::vector<int32_t> cat(std::vector<int32_t> a, const std::vector<int32_t>& b, const std::vector<int32_t>& c) {
+  a.insert(a.end(), b.begin(), b.end());
+  a.insert(a.end(), c.begin(), c.end());
+  return a;
+}
+
+}  // namespace
+
+tn_status compile_program(const tn_network* net, tn_path* path) {
+  const int T = (int)net->tensors.size();
+  const int S = (int)path->pairs.size() / 2;
+  std::vector<Loc> loc(T + S);
+  std::vector<std::vector<int32_t>> modes(T + S);
+  for (int t = 0; t < T; ++t) {
+    loc[t].ref.buf = BUF_IN;
+    loc[t].ref.off = net->tensors[t].offset;
+    loc[t].bits = bits_of_modes(net, net->tensors[t].modes);
+    loc[t].elems = net->tensors[t].size;
+    loc[t].input = true;
+    modes[t] = net->tensors[t].modes;
+  }
+  for (int s = 0; s < S; ++s) {
+    loc[path->pairs[2 * s]].last_use = s;
+    loc[path->pairs[2 * s + 1]].last_use = s;
+  }
+  // holder counts, replayed along the path
+  std::vector<int> holders(net->mode_log2.size(), 0);
+  std::vector<char> is_out(net->mode_log2.size(), 0);
+  for (int m : net->output_modes) is_out[m] = 1;
+  for (int t = 0; t < T; ++t)
+    for (int m : modes[t]) holders[m]++;
+
+  Alloc alloc;
+  path->steps.assign(S, StepProgram());
+  path->step_modes.assign(S, {});
+  tn_path_stats& st = path->stats;
+  st.flops = st.bytes = st.max_intermediate_elems = st.large_step_flops = 0;
+  st.n_steps = S;
+  st.n_permutes = st.n_gemm_steps = st.n_skinny_steps = 0;
+  for (int t = 0; t < T; ++t) st.max_intermediate_elems = std::max(st.max_intermediate_elems, (double)loc[t].elems);
+
+  for (int s = 0; s < S; ++s) {
+    const int ia = path->pairs[2 * s], ib = path->pairs[2 * s + 1];
+    const int ic = T + s;
+    Loc& A = loc[ia];
+    Loc& B = loc[ib];
+    StepProgram& P = path->steps[s];
+    // ---- classify modes
+    std::map<int, int> mcls;
+    auto in = [](const std::vector<int32_t>& v, int m) { return std::find(v.begin(), v.end(), m) != v.end(); };
+    std::vector<int32_t> cmodes;
+    for (int m : modes[ia]) {
+      if (in(modes[ib], m)) {
+        const bool kept = is_out[m] || holders[m] > 2;
+        mcls[m] = kept ? C_BATCH : C_K;
+      } else {
+        if (!(is_out[m] || holders[m] > 1)) return set_error(TN_EINVAL, "mode held by a single tensor");
+        mcls[m] = C_M;
+      }
+    }
+    for (int m : modes[ib])
+      if (!in(modes[ia], m)) {
+        if (!(is_out[m] || holders[m] > 1)) return set_error(TN_EINVAL, "mode held by a single tensor");
+        mcls[m] = C_N;
+      }
+    std::map<int32_t, int> cls;
+    for (int32_t b : A.bits) cls[b] = mcls[mode_of(b)];
+    for (int32_t b : B.bits) cls[b] = mcls[mode_of(b)];
+    int nbits[4] = {0, 0, 0, 0};
+    for (auto& kv : cls) nbits[kv.second]++;
+    const int64_t bsz = (int64_t)1 << nbits[C_BATCH], msz = (int64_t)1 << nbits[C_M];
+    const int64_t nsz = (int64_t)1 << nbits[C_N], ksz = (int64_t)1 << nbits[C_K];
+    const double flops = 8.0 * (double)bsz * (double)msz * (double)nsz * (double)ksz;
+    const int64_t c_elems = bsz * msz * nsz;
+    P.flops = flops;
+    P.gemm_bmnk[0] = bsz; P.gemm_bmnk[1] = msz; P.gemm_bmnk[2] = nsz; P.gemm_bmnk[3] = ksz;
+    P.bytes = 8.0 * (double)(A.elems + B.elems + c_elems);
+
+    // ---- choose the kernel
+    const bool a_small = A.elems <= B.elems;
+    Loc& G = a_small ? A : B;
+    Loc& Tt = a_small ? B : A;
+    const int g_only = a_small ? C_M : C_N;   // class of G's private bits
+    const int g_bits = (int)G.bits.size();
+    const int nk = nbits[C_K], nm = nbits[g_only], nb = nbits[C_BATCH];
+    Loc& C = loc[ic];
+    C.elems = c_elems;
+    if (g_bits <= kSkinnyMaxG && nk <= kSkinnyMaxK && nm <= kSkinnyMaxM) {
+      P.kind = SK_SKINNY;
+      st.n_skinny_steps++;
+      SkinnyDesc& d = P.sk;
+      d.t_bits = (int32_t)Tt.bits.size();
+      d.nk = nk; d.nm = nm; d.nb = nb;
+      // K labels by ascending position in T
+      std::vector<int32_t> klab, outer;  // outer: ascending positions
+      for (int p = 0; p < d.t_bits; ++p) {
+        int32_t lab = Tt.bits[d.t_bits - 1 - p];
+        if (cls[lab] == C_K) klab.push_back(lab); else outer.push_back(lab);
+      }
+      for (int j = 0; j < nk; ++j) d.k_pos[j] = pos_of(Tt.bits, klab[j]);
+      std::vector<int32_t> mlab = filter(G.bits, cls, g_only);  // MSB first
+      std::reverse(mlab.begin(), mlab.end());                  // m bit j = mlab[j]
+      std::vector<int32_t> blab = filter(G.bits, cls, C_BATCH);
+      std::reverse(blab.begin(), blab.end());
+      for (int j = 0; j < nb; ++j) {
+        int p = (int)(std::find(outer.begin(), outer.end(), blab[j]) - outer.begin());
+        d.b_pos[j] = p;
+      }
+      // C layout
+      if (nm == nk) {
+        d.c_mode = 0;
+        C.bits = Tt.bits;
+        for (int j = 0; j < nk; ++j) {
+          int idx = d.t_bits - 1 - d.k_pos[j];
+          C.bits[idx] = mlab[j];
+        }
+      } else {
+        d.c_mode = 1;
+        std::vector<int32_t> top(mlab.rbegin(), mlab.rend());
+        std::vector<int32_t> low(outer.rbegin(), outer.rend());
+        C.bits = top;
+        C.bits.insert(C.bits.end(), low.begin(), low.end());
+      }
+      for (int k = 0; k < (1 << nk); ++k) {
+        int64_t o = 0;
+        for (int j = 0; j < nk; ++j)
+          if ((k >> j) & 1) o |= (int64_t)1 << d.k_pos[j];
+        d.kofs[k] = o;
+      }
+      for (int m = 0; m < (1 << nm); ++m) {
+        int64_t o = 0;
+        for (int j = 0; j < nm; ++j)
+          if ((m >> j) & 1) o |= (int64_t)1 << pos_of(C.bits, mlab[j]);
+        d.mofs[m] = o;
+      }
+      std::vector<int32_t> klab_g = klab;  // k bit j = klab[j]
+      for (int b = 0; b < (1 << nb); ++b)
+        for (int m = 0; m < (1 << nm); ++m)
+          for (int k = 0; k < (1 << nk); ++k) {
+            int64_t a = 0;
+            for (int j = 0; j < nb; ++j)
+              if ((b >> j) & 1) a |= (int64_t)1 << pos_of(G.bits, blab[j]);
+            for (int j = 0; j < nm; ++j)
+              if ((m >> j) & 1) a |= (int64_t)1 << pos_of(G.bits, mlab[j]);
+            for (int j = 0; j < nk; ++j)
+              if ((k >> j) & 1) a |= (int64_t)1 << pos_of(G.bits, klab_g[j]);
+            d.gidx[((b << nm) + m) * (1 << nk) + k] = (int32_t)a;
+          }
+      d.g = G.ref;
+      d.t = Tt.ref;
+      // output buffer: in place over T when T dies here and the layout positions coincide
+      if (d.c_mode == 0 && !Tt.input && Tt.last_use == s && Tt.elems == C.elems) {
+        C.ref = Tt.ref;
+        Tt.ref.buf = -1;  // ownership moved
+      } else {
+        C.ref.buf = BUF_WS;
+        C.ref.off = alloc.get(C.elems);
+      }
+      d.c = C.ref;
+    } else {
+      P.kind = SK_GEMM;
+      st.n_gemm_steps++;
+      int a_fast = 0, b_fast = 0;
+      const bool ra = grouped(A.bits, cls, C_M, C_K, &a_fast);
+      const bool rb = grouped(B.bits, cls, C_K, C_N, &b_fast);
+      auto compat = [&](const std::vector<int32_t>& x, const std::vector<int32_t>& y) {
+        return filter(x, cls, C_BATCH) == filter(y, cls, C_BATCH) && filter(x, cls, C_K) == filter(y, cls, C_K);
+      };
+      std::vector<int32_t> la = A.bits, lb = B.bits;
+      bool perm_a = false, perm_b = false;
+      auto target_b = [&](const std::vector<int32_t>& ref) {
+        std::vector<int32_t> bt = filter(ref, cls, C_BATCH), kk = filter(ref, cls, C_K), nn = filter(B.bits, cls, C_N);
+        const bool k_low = !B.bits.empty() && cls[B.bits.back()] == C_K && !nn.empty();
+        return k_low ? cat(bt, nn, kk) : cat(bt, kk, nn);
+      };
+      auto target_a = [&](const std::vector<int32_t>& ref) {
+        std::vector<int32_t> bt = filter(ref, cls, C_BATCH), kk = filter(ref, cls, C_K), mm = filter(A.bits, cls, C_M);
+        const bool m_low = !A.bits.empty() && cls[A.bits.back()] == C_M && !kk.empty();
+        return m_low ? cat(bt, kk, mm) : cat(bt, mm, kk);
+      };
+      if (ra && rb && compat(A.bits, B.bits)) {
+        // nothing to do
+      } else if (ra && (!rb || A.elems >= B.elems)) {
+        lb = target_b(A.bits);
+        perm_b = true;
+      } else if (rb) {
+        la = target_a(B.bits);
+        perm_a = true;
+      } else {
+        // neither grouped: canonicalise the larger with its own relative orders, then match the other
+        if (A.elems >= B.elems) {
+          std::vector<int32_t> bt = filter(A.bits, cls, C_BATCH), kk = filter(A.bits, cls, C_K);
+          la = cat(bt, filter(A.bits, cls, C_M), kk);
+          perm_a = true;
+          lb = target_b(la);
+          perm_b = true;
+        } else {
+          std::vector<int32_t> bt = filter(B.bits, cls, C_BATCH), kk = filter(B.bits, cls, C_K);
+          lb = cat(bt, kk, filter(B.bits, cls, C_N));
+          perm_b = true;
+          la = target_a(lb);
+          perm_a = true;
+        }
+      }
+      if (perm_a && la == A.bits) perm_a = false;
+      if (perm_b && lb == B.bits) perm_b = false;
+      BufRef ra_ref = A.ref, rb_ref = B.ref;
+      int64_t tmp_a = -1, tmp_b = -1;
+      if (perm_a) {
+        tmp_a = alloc.get(A.elems);
+        BufRef o; o.buf = BUF_WS; o.off = tmp_a;
+        P.pre.push_back(make_permute(A.ref, A.bits, o, la));
+        ra_ref = o;
+        st.n_permutes++;
+        P.bytes += 16.0 * (double)A.elems;
+      }
+      if (perm_b) {
+        tmp_b = alloc.get(B.elems);
+        BufRef o; o.buf = BUF_WS; o.off = tmp_b;
+        P.pre.push_back(make_permute(B.ref, B.bits, o, lb));
+        rb_ref = o;
+        st.n_permutes++;
+        P.bytes += 16.0 * (double)B.elems;
+      }
+      int fa = 0, fb = 0;
+      grouped(la, cls, C_M, C_K, &fa);
+      grouped(lb, cls, C_K, C_N, &fb);
+      GemmDesc& g = P.gm;
+      g.batch = bsz; g.M = msz; g.N = nsz; g.K = ksz;
+      g.a_kfast = (fa == C_K) || nbits[C_M] == 0 ? 1 : 0;
+      g.b_nfast = (fb == C_N) || nbits[C_K] == 0 ? 1 : 0;
+      if (nbits[C_K] == 0) { g.a_kfast = 1; }
+      if (nbits[C_N] == 0) { g.b_nfast = 0; }
+      if (nbits[C_M] == 0) { g.a_kfast = 1; }
+      if (nbits[C_K] == 0) { g.b_nfast = 1; }
+      g.a = ra_ref;
+      g.b = rb_ref;
+      C.bits = cat(filter(la, cls, C_BATCH), filter(la, cls, C_M), filter(lb, cls, C_N));
+      C.ref.buf = BUF_WS;
+      C.ref.off = alloc.get(C.elems);
+      g.c = C.ref;
+      if (tmp_a >= 0) alloc.put(tmp_a, A.elems);
+      if (tmp_b >= 0) alloc.put(tmp_b, B.elems);
+    }
+    // ---- bookkeeping
+    for (int m : modes[ia]) holders[m]--;
+    for (int m : modes[ib]) holders[m]--;
+    std::vector<int32_t> cm;
+    for (size_t i = 0; i < C.bits.size(); ++i) {
+      int m = mode_of(C.bits[i]);
+      if (cm.empty() || cm.back() != m) cm.push_back(m);
+    }
+    modes[ic] = cm;
+    for (int m : cm) holders[m]++;
+    path->step_modes[s] = cm;
+    for (Loc* X : {&A, &B})
+      if (!X->input && X->last_use == s && X->ref.buf == BUF_WS) {
+        alloc.put(X->ref.off, X->elems);
+        X->ref.buf = -1;
+      }
+    st.flops += P.flops;
+    st.bytes += P.bytes;
+    st.max_intermediate_elems = std::max(st.max_intermediate_elems, (double)C.elems);
+    const double inten = P.flops / (8.0 * (double)(A.elems + B.elems + C.elems));
+    if (P.flops >= 1e9 && inten >= 40.0) st.large_step_flops += P.flops;
+  }
+  // ---- consistency checks of every descriptor before anything can reach a GPU
+  auto ref_ok = [&](const BufRef& r, int64_t elems) {
+    if (r.buf == BUF_IN) return r.off >= 0 && r.off + elems <= net->input_elems;
+    if (r.buf == BUF_WS) return r.off >= 0 && r.off + elems <= alloc.peak;
+    return false;
+  };
+  for (int s = 0; s < S; ++s) {
+    const StepProgram& P = path->steps[s];
+    const int ia = path->pairs[2 * s], ib = path->pairs[2 * s + 1];
+    const int64_t ea = loc[ia].elems, eb = loc[ib].elems, ec = loc[T + s].elems;
+    for (const PermuteDesc& pd : P.pre) {
+      const int64_t e = (int64_t)1 << pd.bits;
+      if (!ref_ok(pd.in, e) || !ref_ok(pd.out, e)) return set_error(TN_EINVAL, "internal: permute buffer out of range");
+      std::vector<char> seen(pd.bits, 0);
+      for (int p = 0; p < pd.bits; ++p) {
+        if (pd.dst[p] < 0 || pd.dst[p] >= pd.bits || seen[pd.dst[p]]) return set_error(TN_EINVAL, "internal: bad permutation");
+        seen[pd.dst[p]] = 1;
+      }
+    }
+    if (P.kind == SK_SKINNY) {
+      const SkinnyDesc& d = P.sk;
+      const int64_t te = (int64_t)1 << d.t_bits;
+      const int64_t ge = std::min(ea, eb);
+      if (te != std::max(ea, eb) || !ref_ok(d.g, ge) || !ref_ok(d.t, te) || !ref_ok(d.c, ec))
+        return set_error(TN_EINVAL, "internal: skinny buffer out of range");
+      const int outer_bits = d.t_bits - d.nk;
+      for (int j = 0; j < d.nk; ++j)
+        if (d.k_pos[j] < 0 || d.k_pos[j] >= d.t_bits || (j && d.k_pos[j] <= d.k_pos[j - 1]))
+          return set_error(TN_EINVAL, "internal: bad summed-bit positions");
+      for (int j = 0; j < d.nb; ++j)
+        if (d.b_pos[j] < 0 || d.b_pos[j] >= outer_bits) return set_error(TN_EINVAL, "internal: bad batch-bit positions");
+      for (int i = 0; i < (1 << (d.nb + d.nm + d.nk)); ++i)
+        if (d.gidx[i] < 0 || d.gidx[i] >= ge) return set_error(TN_EINVAL, "internal: bad small-operand index");
+      for (int k = 0; k < (1 << d.nk); ++k)
+        if (d.kofs[k] < 0 || d.kofs[k] >= te) return set_error(TN_EINVAL, "internal: bad operand offset");
+      const int64_t cmax = d.c_mode ? ((int64_t)1 << outer_bits) : te;
+      for (int m = 0; m < (1 << d.nm); ++m)
+        if (d.mofs[m] < 0 || (d.mofs[m] | (cmax - 1)) >= ec) return set_error(TN_EINVAL, "internal: bad output offset");
+      if (d.c_mode == 0 && ec != te) return set_error(TN_EINVAL, "internal: in-layout output size mismatch");
+      if (d.c_mode == 1 && ec != ((int64_t)1 << (outer_bits + d.nm))) return set_error(TN_EINVAL, "internal: output size");
+    } else {
+      const GemmDesc& g = P.gm;
+      if (g.batch * g.M * g.K != ea || g.batch * g.K * g.N != eb || g.batch * g.M * g.N != ec)
+        return set_error(TN_EINVAL, "internal: GEMM shape mismatch");
+      if (!ref_ok(g.a, ea) || !ref_ok(g.b, eb) || !ref_ok(g.c, ec))
+        return set_error(TN_EINVAL, "internal: GEMM buffer out of range");
+    }
+  }
+  const int last = S > 0 ? T + S - 1 : 0;
+  if (S == 0 && T != 1) return set_error(TN_EINVAL, "empty path for a network of several tensors");
+  if (S == 0) {
+    // a single input tensor: copy it into the workspace so the result lives there
+    loc[0].ref = loc[0].ref;
+  }
+  path->final_bits = loc[last].bits;
+  path->final_ref = loc[last].ref;
+  path->final_elems = loc[last].elems;
+  path->ws_elems = std::max<int64_t>(alloc.peak, 32);
+  path->n_inputs = T;
+  return TN_OK;
+}
+
+}  // namespace tnq
+
+using namespace tnq;
+
+extern "C" tn_status tn_plan_path(const tn_network* net, const tn_plan_opts* opts, tn_path** path_out,
+                                  tn_path_stats* stats_out) {
+  clear_error();
+  if (!net || !path_out) return set_error(TN_EINVAL, "NULL argument");
+  *path_out = nullptr;
+  tn_plan_opts o{};
+  o.kind = TN_PATH_GREEDY;
+  o.max_log2_intermediate = 0;
+  o.seed = 0;
+  if (opts) o = *opts;
+  if (o.kind < TN_PATH_GREEDY || o.kind > TN_PATH_RANDOM) return set_error(TN_EINVAL, "unknown path kind");
+  auto t0 = std::chrono::steady_clock::now();
+  tn_path* p = new tn_path();
+  double max_log2 = 0;
+  tn_status s = plan_order(net, o, p->pairs, &max_log2);
+  if (s != TN_OK) {
+    delete p;
+    return set_error(s, "largest intermediate 2^" + std::to_string((int)max_log2) + " exceeds the cap 2^" +
+                            std::to_string(o.max_log2_intermediate > 0 ? o.max_log2_intermediate : 40));
+  }
+  s = compile_program(net, p);
+  if (s != TN_OK) { delete p; return s; }
+  auto t1 = std::chrono::steady_clock::now();
+  p->stats.plan_seconds = std::chrono::duration<double>(t1 - t0).count();
+  if (stats_out) *stats_out = p->stats;
+  *path_out = p;
+  return TN_OK;
+}
+
+extern "C" void tn_path_destroy(tn_path* path) {
+  if (!path) return;
+  device_release_path(path);
+  delete path;
+}
+
+extern "C" tn_status tn_path_pairs(const tn_path* path, int32_t* n_steps, int32_t* pairs, int32_t capacity) {
+  clear_error();
+  if (!path) return set_error(TN_EINVAL, "path is NULL");
+  const int S = (int)path->pairs.size() / 2;
+  if (n_steps) *n_steps = S;
+  if (pairs) {
+    if (capacity < 2 * S) return set_error(TN_EINVAL, "capacity too small");
+    for (int i = 0; i < 2 * S; ++i) pairs[i] = path->pairs[i];
+  }
+  return TN_OK;
+}
+
+extern "C" tn_status tn_path_step(const tn_path* path, int32_t s, int32_t* rank, int32_t* modes, int64_t* gemm_bmnk,
+                                  int32_t* kind) {
+  clear_error();
+  if (!path || s < 0 || s >= (int32_t)path->steps.size()) return set_error(TN_EINVAL, "bad step index");
+  const auto& m = path->step_modes[s];
+  if (rank) *rank = (int32_t)m.size();
+  if (modes)
+    for (size_t i = 0; i < m.size(); ++i) modes[i] = m[i];
+  if (gemm_bmnk)
+    for (int i = 0; i < 4; ++i) gemm_bmnk[i] = path->steps[s].gemm_bmnk[i];
+  if (kind) *kind = path->steps[s].kind;
+  return TN_OK;
+}

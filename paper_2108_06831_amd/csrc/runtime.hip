@@ -1,0 +1,684 @@
+// Device runtime: uploads network tables, lays out the caller's workspace,
+// executes compiled programs and implements the device entry points of tn.h.
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "kernels.h"
+
+namespace tnq {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+tn_status set_error(tn_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+void clear_error() { g_err.clear(); }
+
+#define HIP_TRY(expr)                                                                       \
+  do {                                                                                      \
+    hipError_t _e = (expr);                                                                 \
+    if (_e != hipSuccess)                                                                   \
+      return set_error(TN_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(_e));      \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// kernel timing (tn_profile_*)
+// ---------------------------------------------------------------------------
+struct ProfRec {
+  int kind;
+  hipEvent_t a, b;
+  double bytes, flops;
+};
+static bool g_prof = false;
+static std::vector<ProfRec> g_recs;
+static std::vector<hipEvent_t> g_pool;
+
+static hipEvent_t pool_event() {
+  if (!g_pool.empty()) {
+    hipEvent_t e = g_pool.back();
+    g_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+static hipEvent_t prof_start(hipStream_t s) {
+  if (!g_prof) return nullptr;
+  hipEvent_t e = pool_event();
+  if (e) (void)hipEventRecord(e, s);
+  return e;
+}
+
+static void prof_stop(hipStream_t s, hipEvent_t a, int kind, double bytes, double flops) {
+  if (!a) return;
+  hipEvent_t b = pool_event();
+  if (!b) return;
+  (void)hipEventRecord(b, s);
+  g_recs.push_back(ProfRec{kind, a, b, bytes, flops});
+}
+
+// ---------------------------------------------------------------------------
+// device copies of a network's tables
+// ---------------------------------------------------------------------------
+struct DevNet {
+  int device = -1;
+  DevTensor* tensors = nullptr;
+  Recipe* recipes = nullptr;
+  RecipeOp* ops = nullptr;
+  double* mats = nullptr;
+  Recipe* sweep_recipes = nullptr;
+  RecipeOp* sweep_ops = nullptr;
+  int32_t* slot_param = nullptr;
+  std::vector<int32_t> slot_of_gate;  // per sweep gate: gradient slot or -1
+  int n_slots = 0;
+};
+
+template <typename T>
+static hipError_t upload(T** dst, const std::vector<T>& v) {
+  *dst = nullptr;
+  if (v.empty()) return hipSuccess;
+  hipError_t e = hipMalloc((void**)dst, sizeof(T) * v.size());
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice);
+}
+
+static tn_status ensure_device(tn_network* net, DevNet** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  DevNet* d = (DevNet*)net->dev;
+  if (d && d->device == dev) { *out = d; return TN_OK; }
+  if (d) { device_release_network(net); }
+  d = new DevNet();
+  d->device = dev;
+  net->dev = d;
+  std::vector<DevTensor> ts;
+  for (const TensorDef& t : net->tensors) {
+    DevTensor x;
+    x.kind = t.kind; x.recipe = t.recipe; x.qubit = t.qubit; x.pad = 0;
+    x.offset = t.offset; x.size = t.size;
+    ts.push_back(x);
+  }
+  HIP_TRY(upload(&d->tensors, ts));
+  HIP_TRY(upload(&d->recipes, net->recipes));
+  HIP_TRY(upload(&d->ops, net->ops));
+  HIP_TRY(upload(&d->mats, net->matrices));
+  HIP_TRY(upload(&d->sweep_recipes, net->sweep_recipes));
+  HIP_TRY(upload(&d->sweep_ops, net->sweep_ops));
+  std::vector<int32_t> sp;
+  d->slot_of_gate.assign(net->sweep.size(), -1);
+  for (size_t i = 0; i < net->sweep.size(); ++i)
+    if (net->sweep[i].gen != GEN_NONE) {
+      d->slot_of_gate[i] = (int32_t)sp.size();
+      sp.push_back(net->sweep[i].param);
+    }
+  d->n_slots = (int)sp.size();
+  HIP_TRY(upload(&d->slot_param, sp));
+  *out = d;
+  return TN_OK;
+}
+
+void device_release_network(tn_network* net) {
+  DevNet* d = (DevNet*)net->dev;
+  if (!d) return;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(d->device);
+  (void)hipFree(d->tensors); (void)hipFree(d->recipes); (void)hipFree(d->ops); (void)hipFree(d->mats);
+  (void)hipFree(d->sweep_recipes); (void)hipFree(d->sweep_ops); (void)hipFree(d->slot_param);
+  (void)hipSetDevice(cur);
+  delete d;
+  net->dev = nullptr;
+}
+
+void device_release_path(tn_path* path) { path->dev = nullptr; }
+
+// ---------------------------------------------------------------------------
+// workspace layout
+// ---------------------------------------------------------------------------
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct WsLayout {
+  size_t in_off, arena_off, aux_off, total;
+};
+
+static WsLayout layout_ws(const tn_network* net, const tn_path* path, int batch, size_t aux_bytes) {
+  WsLayout L;
+  L.in_off = 0;
+  L.arena_off = align256(L.in_off + sizeof(float2) * (size_t)net->input_elems * batch);
+  L.aux_off = align256(L.arena_off + sizeof(float2) * (size_t)path->ws_elems * batch);
+  L.total = align256(L.aux_off + aux_bytes);
+  return L;
+}
+
+static size_t expect_aux(int batch) { return sizeof(double) * (size_t)kReduceBlocks * batch; }
+
+// ---------------------------------------------------------------------------
+// program execution
+// ---------------------------------------------------------------------------
+struct Bases {
+  float2* in = nullptr;
+  int64_t in_bs = 0;
+  float2* ws = nullptr;
+  int64_t ws_bs = 0;
+  float2* out = nullptr;
+  int64_t out_bs = 0;
+  // contract_pair: inputs are two separate user buffers
+  const float2* pair_a = nullptr;
+  const float2* pair_b = nullptr;
+  int64_t pair_a_elems = 0;
+};
+
+static float2* resolve(const Bases& b, const BufRef& r, int64_t* bs) {
+  switch (r.buf) {
+    case BUF_IN:
+      if (b.pair_a) {
+        *bs = 0;
+        return r.off < b.pair_a_elems ? (float2*)b.pair_a + r.off : (float2*)b.pair_b + (r.off - b.pair_a_elems);
+      }
+      *bs = b.in_bs;
+      return b.in + r.off;
+    case BUF_WS: *bs = b.ws_bs; return b.ws + r.off;
+    case BUF_OUT: *bs = b.out_bs; return b.out + r.off;
+    default: *bs = 0; return nullptr;
+  }
+}
+
+static tn_status run_steps(hipStream_t s, const tn_path* path, const Bases& B, int batch, int precision) {
+  for (const StepProgram& P : path->steps) {
+    for (const PermuteDesc& pd : P.pre) {
+      int64_t ibs, obs;
+      float2* ip = resolve(B, pd.in, &ibs);
+      float2* op = resolve(B, pd.out, &obs);
+      hipEvent_t ev = prof_start(s);
+      HIP_TRY(launch_permute(s, pd, ip, ibs, op, obs, batch));
+      prof_stop(s, ev, TN_KERNEL_PERMUTE, 16.0 * (double)((int64_t)1 << pd.bits) * batch, 0.0);
+    }
+    if (P.kind == SK_SKINNY) {
+      int64_t gbs, tbs, cbs;
+      float2* g = resolve(B, P.sk.g, &gbs);
+      float2* t = resolve(B, P.sk.t, &tbs);
+      float2* c = resolve(B, P.sk.c, &cbs);
+      const SkinnyDesc& d = P.sk;
+      const double te = (double)((int64_t)1 << d.t_bits);
+      const double ce = d.c_mode ? (double)((int64_t)1 << (d.t_bits - d.nk + d.nm)) : te;
+      const double ge = (double)((int64_t)1 << (d.nb + d.nm + d.nk));
+      hipEvent_t ev = prof_start(s);
+      HIP_TRY(launch_skinny(s, P.sk, g, gbs, t, tbs, c, cbs, batch, precision));
+      prof_stop(s, ev, TN_KERNEL_SKINNY, 8.0 * batch * (ge + te + ce), P.flops * batch);
+    } else {
+      int64_t abs_, bbs, cbs;
+      float2* a = resolve(B, P.gm.a, &abs_);
+      float2* b = resolve(B, P.gm.b, &bbs);
+      float2* c = resolve(B, P.gm.c, &cbs);
+      const GemmDesc& g = P.gm;
+      const double bytes = 8.0 * batch * (double)g.batch * (double)(g.M * g.K + g.K * g.N + g.M * g.N);
+      hipEvent_t ev = prof_start(s);
+      HIP_TRY(launch_gemm(s, P.gm, a, abs_, b, bbs, c, cbs, batch, precision));
+      prof_stop(s, ev, TN_KERNEL_GEMM, bytes, P.flops * batch);
+    }
+  }
+  return TN_OK;
+}
+
+static tn_status materialize(hipStream_t s, tn_network* net, DevNet* d, const double* params, int batch,
+                             const uint64_t* bits, int64_t count, float2* in) {
+  hipEvent_t ev = prof_start(s);
+  HIP_TRY(launch_materialize(s, d->tensors, (int)net->tensors.size(), d->recipes, d->ops, d->mats, params,
+                             net->n_params, batch, in, net->input_elems));
+  if (net->output_kind == TN_OUT_AMPLITUDES) {
+    const int64_t first = net->tensors[net->tensors.size() - net->n_qubits].offset;
+    HIP_TRY(launch_projectors(s, bits, count, net->n_qubits, net->batch_log2, first, batch, in, net->input_elems));
+  }
+  prof_stop(s, ev, TN_KERNEL_MATERIALIZE, 8.0 * (double)net->input_elems * batch, 0.0);
+  return TN_OK;
+}
+
+static int32_t lab(int mode, int j) { return mode * 64 + j; }
+
+static int pos_in(const std::vector<int32_t>& bits, int32_t l) {
+  for (size_t i = 0; i < bits.size(); ++i)
+    if (bits[i] == l) return (int)(bits.size() - 1 - i);
+  return -1;
+}
+
+// move the final tensor (layout `from`) into `dst` with layout `to`
+static tn_status finish_to(hipStream_t s, const Bases& B, const tn_path* path, const std::vector<int32_t>& to,
+                           float2* dst, int64_t dst_bs, int64_t n_copy, int batch, float2* scratch) {
+  int64_t fbs;
+  float2* f = resolve(B, path->final_ref, &fbs);
+  const std::vector<int32_t>& from = path->final_bits;
+  if (from == to) {
+    hipEvent_t ev = prof_start(s);
+    HIP_TRY(launch_copy(s, f, fbs, dst, dst_bs, n_copy, batch));
+    prof_stop(s, ev, TN_KERNEL_COPY, 16.0 * (double)n_copy * batch, 0.0);
+    return TN_OK;
+  }
+  PermuteDesc pd;
+  pd.bits = (int32_t)from.size();
+  for (size_t i = 0; i < from.size(); ++i) pd.dst[from.size() - 1 - i] = pos_in(to, from[i]);
+  if (n_copy == path->final_elems) {
+    hipEvent_t ev = prof_start(s);
+    HIP_TRY(launch_permute(s, pd, f, fbs, dst, dst_bs, batch));
+    prof_stop(s, ev, TN_KERNEL_PERMUTE, 16.0 * (double)n_copy * batch, 0.0);
+  } else {
+    HIP_TRY(launch_permute(s, pd, f, fbs, scratch, path->final_elems, batch));
+    HIP_TRY(launch_copy(s, scratch, path->final_elems, dst, dst_bs, n_copy, batch));
+  }
+  return TN_OK;
+}
+
+static bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+
+// map qubit masks to address-bit masks of the final tensor
+static tn_status make_terms(const tn_network* net, const tn_path* path, const tn_observable* obs, ZTerms* t) {
+  if (!obs || obs->n_terms < 0 || (obs->n_terms > 0 && (!obs->z_mask || !obs->coeff)))
+    return set_error(TN_EINVAL, "bad observable");
+  if (obs->n_terms > kMaxTerms)
+    return set_error(TN_EUNSUPPORTED, "observable has more than " + std::to_string(kMaxTerms) + " terms");
+  const int n = net->n_qubits;
+  t->n = obs->n_terms;
+  for (int i = 0; i < obs->n_terms; ++i) {
+    uint64_t m = 0;
+    const uint64_t qm = obs->z_mask[i];
+    if (n < 64 && (qm >> n) != 0) return set_error(TN_EINVAL, "observable mask names a qubit >= n_qubits");
+    for (int q = 0; q < n; ++q)
+      if ((qm >> (n - 1 - q)) & 1) {
+        const int p = pos_in(path->final_bits, lab(net->wire_final[q], 0));
+        if (p < 0) return set_error(TN_EINVAL, "qubit leg missing from the final tensor");
+        m |= (uint64_t)1 << p;
+      }
+    t->mask[i] = m;
+    t->coeff[i] = obs->coeff[i];
+  }
+  return TN_OK;
+}
+
+}  // namespace tnq
+
+using namespace tnq;
+
+extern "C" const char* tn_last_error(void) { return g_err.c_str(); }
+
+extern "C" tn_status tn_profile_enable(int32_t on) {
+  clear_error();
+  g_prof = on != 0;
+  return TN_OK;
+}
+
+extern "C" void tn_profile_reset(void) {
+  for (ProfRec& r : g_recs) {
+    (void)hipEventSynchronize(r.b);
+    g_pool.push_back(r.a);
+    g_pool.push_back(r.b);
+  }
+  g_recs.clear();
+}
+
+extern "C" int32_t tn_profile_read(tn_kernel_profile* out, int32_t capacity) {
+  tn_kernel_profile acc[TN_KERNEL_KINDS];
+  for (int k = 0; k < TN_KERNEL_KINDS; ++k) acc[k] = tn_kernel_profile{k, 0, 0.0, 0.0, 0.0};
+  for (ProfRec& r : g_recs) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      acc[r.kind].launches += 1;
+      acc[r.kind].seconds += 1e-3 * ms;
+      acc[r.kind].bytes += r.bytes;
+      acc[r.kind].flops += r.flops;
+    }
+    g_pool.push_back(r.a);
+    g_pool.push_back(r.b);
+  }
+  g_recs.clear();
+  int n = 0;
+  for (int k = 0; k < TN_KERNEL_KINDS && n < capacity; ++k)
+    if (acc[k].launches) out[n++] = acc[k];
+  return n;
+}
+extern "C" const char* tn_version(void) { return "tnq 0.1 (gfx950)"; }
+
+extern "C" size_t tn_workspace_bytes(const tn_network* net, const tn_path* path, int32_t batch) {
+  if (!net || !path || batch < 1) return 0;
+  const size_t final_tmp = sizeof(float2) * (size_t)path->final_elems * batch;
+  return layout_ws(net, path, batch, std::max(expect_aux(batch), final_tmp)).total;
+}
+
+static tn_status check_common(const tn_network* net, const tn_path* path, const double* params, int32_t batch,
+                              int32_t precision) {
+  if (!net || !path) return set_error(TN_EINVAL, "NULL network or path");
+  if (path->n_inputs != (int32_t)net->tensors.size()) return set_error(TN_EINVAL, "path was planned for another network");
+  if (batch < 1 || batch > 65535) return set_error(TN_EINVAL, "batch must be in 1..65535");
+  if (net->n_params > 0 && !params) return set_error(TN_EINVAL, "params_dev required (n_params > 0)");
+  if (precision != TN_PREC_C64 && precision != TN_PREC_BF16X3) return set_error(TN_EINVAL, "unknown precision");
+  return TN_OK;
+}
+
+extern "C" tn_status tn_contract_path(void* stream, int32_t precision, tn_network* net, tn_path* path,
+                                      const double* params_dev, int32_t batch, void* workspace_dev,
+                                      size_t workspace_bytes, void* out_dev) {
+  clear_error();
+  tn_status st = check_common(net, path, params_dev, batch, precision);
+  if (st != TN_OK) return st;
+  if (net->output_kind != TN_OUT_STATEVECTOR) return set_error(TN_EINVAL, "network does not output a statevector");
+  if (!out_dev || !workspace_dev) return set_error(TN_EINVAL, "NULL device buffer");
+  const size_t need = tn_workspace_bytes(net, path, batch);
+  if (workspace_bytes < need)
+    return set_error(TN_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
+  hipStream_t s = (hipStream_t)stream;
+  DevNet* d;
+  if ((st = ensure_device(net, &d)) != TN_OK) return st;
+  const size_t final_tmp = sizeof(float2) * (size_t)path->final_elems * batch;
+  WsLayout L = layout_ws(net, path, batch, std::max(expect_aux(batch), final_tmp));
+  char* w = (char*)workspace_dev;
+  Bases B;
+  B.in = (float2*)(w + L.in_off);
+  B.in_bs = net->input_elems;
+  B.ws = (float2*)(w + L.arena_off);
+  B.ws_bs = path->ws_elems;
+  B.out = (float2*)out_dev;
+  B.out_bs = (int64_t)1 << net->n_qubits;
+  if ((st = materialize(s, net, d, params_dev, batch, nullptr, 0, B.in)) != TN_OK) return st;
+  if ((st = run_steps(s, path, B, batch, precision)) != TN_OK) return st;
+  std::vector<int32_t> to;
+  for (int q = 0; q < net->n_qubits; ++q) to.push_back(lab(net->wire_final[q], 0));
+  return finish_to(s, B, path, to, B.out, B.out_bs, B.out_bs, batch, (float2*)(w + L.aux_off));
+}
+
+extern "C" tn_status tn_amplitudes(void* stream, int32_t precision, tn_network* net, tn_path* path,
+                                   const double* params_dev, const uint64_t* bitstrings_dev, int64_t count,
+                                   void* workspace_dev, size_t workspace_bytes, void* out_dev) {
+  clear_error();
+  tn_status st = check_common(net, path, params_dev, 1, precision);
+  if (st != TN_OK) return st;
+  if (net->output_kind != TN_OUT_AMPLITUDES) return set_error(TN_EINVAL, "network does not output amplitudes");
+  if (count < 1 || count > net->n_bitstrings) return set_error(TN_EINVAL, "count must be in 1..n_bitstrings");
+  if (!out_dev || !workspace_dev || !bitstrings_dev) return set_error(TN_EINVAL, "NULL device buffer");
+  const size_t need = tn_workspace_bytes(net, path, 1);
+  if (workspace_bytes < need)
+    return set_error(TN_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
+  hipStream_t s = (hipStream_t)stream;
+  DevNet* d;
+  if ((st = ensure_device(net, &d)) != TN_OK) return st;
+  const size_t final_tmp = sizeof(float2) * (size_t)path->final_elems;
+  WsLayout L = layout_ws(net, path, 1, std::max(expect_aux(1), final_tmp));
+  char* w = (char*)workspace_dev;
+  Bases B;
+  B.in = (float2*)(w + L.in_off);
+  B.in_bs = net->input_elems;
+  B.ws = (float2*)(w + L.arena_off);
+  B.ws_bs = path->ws_elems;
+  if ((st = materialize(s, net, d, params_dev, 1, bitstrings_dev, count, B.in)) != TN_OK) return st;
+  if ((st = run_steps(s, path, B, 1, precision)) != TN_OK) return st;
+  std::vector<int32_t> to;
+  for (int j = net->batch_log2 - 1; j >= 0; --j) to.push_back(lab(net->batch_mode, j));
+  return finish_to(s, B, path, to, (float2*)out_dev, count, count, 1, (float2*)(w + L.aux_off));
+}
+
+extern "C" size_t tn_expectation_workspace_bytes(tn_network* const* nets, tn_path* const* paths, int32_t n_circuits,
+                                                 int32_t batch) {
+  size_t mx = 0;
+  for (int i = 0; i < n_circuits; ++i) {
+    if (!nets || !paths || !nets[i] || !paths[i]) return 0;
+    mx = std::max(mx, layout_ws(nets[i], paths[i], batch, expect_aux(batch)).total);
+  }
+  return mx;
+}
+
+extern "C" tn_status tn_expectation(void* stream, int32_t precision, tn_network* const* nets, tn_path* const* paths,
+                                    int32_t n_circuits, const double* const* params_dev, int32_t batch,
+                                    const tn_observable* obs, void* workspace_dev, size_t workspace_bytes,
+                                    double* out_dev) {
+  clear_error();
+  if (n_circuits < 1 || !nets || !paths || !obs || !out_dev || !workspace_dev)
+    return set_error(TN_EINVAL, "NULL argument or no circuits");
+  const size_t need = tn_expectation_workspace_bytes(nets, paths, n_circuits, batch);
+  if (need == 0) return set_error(TN_EINVAL, "NULL network or path");
+  if (workspace_bytes < need) return set_error(TN_ENOMEM, "workspace too small: need " + std::to_string(need));
+  hipStream_t s = (hipStream_t)stream;
+  for (int c = 0; c < n_circuits; ++c) {
+    tn_network* net = nets[c];
+    tn_path* path = paths[c];
+    const double* prm = params_dev ? params_dev[c] : nullptr;
+    tn_status st = check_common(net, path, prm, batch, precision);
+    if (st != TN_OK) return set_error(st, "circuit " + std::to_string(c) + ": " + g_err);
+    if (net->output_kind != TN_OUT_STATEVECTOR) return set_error(TN_EINVAL, "expectation needs a statevector network");
+    ZTerms terms;
+    if ((st = make_terms(net, path, &obs[c], &terms)) != TN_OK) return st;
+    DevNet* d;
+    if ((st = ensure_device(net, &d)) != TN_OK) return st;
+    WsLayout L = layout_ws(net, path, batch, expect_aux(batch));
+    char* w = (char*)workspace_dev;
+    Bases B;
+    B.in = (float2*)(w + L.in_off);
+    B.in_bs = net->input_elems;
+    B.ws = (float2*)(w + L.arena_off);
+    B.ws_bs = path->ws_elems;
+    if ((st = materialize(s, net, d, prm, batch, nullptr, 0, B.in)) != TN_OK) return st;
+    if ((st = run_steps(s, path, B, batch, precision)) != TN_OK) return st;
+    int64_t fbs;
+    float2* f = resolve(B, path->final_ref, &fbs);
+    hipEvent_t ev = prof_start(s);
+    HIP_TRY(launch_expectation(s, f, fbs, path->final_elems, terms, batch, (double*)(w + L.aux_off),
+                               out_dev + (int64_t)c * batch, 1));
+    prof_stop(s, ev, TN_KERNEL_REDUCE, 8.0 * (double)path->final_elems * batch, 0.0);
+  }
+  return TN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// adjoint gradient
+// ---------------------------------------------------------------------------
+struct BackLayout {
+  WsLayout base;
+  size_t lam_off, mats_off, part_off, total;
+};
+
+static BackLayout back_layout(const tn_network* net, const tn_path* path, int batch, int n_slots) {
+  BackLayout L;
+  L.base = layout_ws(net, path, batch, expect_aux(batch));
+  L.lam_off = L.base.total;
+  L.mats_off = align256(L.lam_off + sizeof(float2) * (size_t)path->final_elems * batch);
+  L.part_off = align256(L.mats_off + sizeof(float2) * 16 * net->sweep.size() * batch);
+  L.total = align256(L.part_off + sizeof(double) * (size_t)std::max(n_slots, 1) * kReduceBlocks * batch);
+  return L;
+}
+
+static int count_slots(const tn_network* net) {
+  int n = 0;
+  for (const SweepGate& g : net->sweep) n += g.gen != GEN_NONE;
+  return n;
+}
+
+extern "C" size_t tn_backward_workspace_bytes(const tn_network* net, const tn_path* path, int32_t batch) {
+  if (!net || !path || batch < 1) return 0;
+  return back_layout(net, path, batch, count_slots(net)).total;
+}
+
+extern "C" tn_status tn_backward(void* stream, int32_t precision, tn_network* net, tn_path* path,
+                                 const double* params_dev, int32_t batch, const tn_observable* obs,
+                                 const double* grad_out_dev, void* workspace_dev, size_t workspace_bytes,
+                                 double* value_dev, double* grad_dev) {
+  clear_error();
+  tn_status st = check_common(net, path, params_dev, batch, precision);
+  if (st != TN_OK) return st;
+  if (net->output_kind != TN_OUT_STATEVECTOR) return set_error(TN_EINVAL, "backward needs a statevector network");
+  if (!workspace_dev || !value_dev || (net->n_params > 0 && !grad_dev)) return set_error(TN_EINVAL, "NULL buffer");
+  const size_t need = tn_backward_workspace_bytes(net, path, batch);
+  if (workspace_bytes < need) return set_error(TN_ENOMEM, "workspace too small: need " + std::to_string(need));
+  ZTerms terms;
+  if ((st = make_terms(net, path, obs, &terms)) != TN_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  DevNet* d;
+  if ((st = ensure_device(net, &d)) != TN_OK) return st;
+  BackLayout L = back_layout(net, path, batch, d->n_slots);
+  char* w = (char*)workspace_dev;
+  Bases B;
+  B.in = (float2*)(w + L.base.in_off);
+  B.in_bs = net->input_elems;
+  B.ws = (float2*)(w + L.base.arena_off);
+  B.ws_bs = path->ws_elems;
+  // forward contraction to psi (left in the workspace arena)
+  if ((st = materialize(s, net, d, params_dev, batch, nullptr, 0, B.in)) != TN_OK) return st;
+  if ((st = run_steps(s, path, B, batch, precision)) != TN_OK) return st;
+  int64_t pbs;
+  float2* psi = resolve(B, path->final_ref, &pbs);
+  if (path->final_ref.buf != BUF_WS) return set_error(TN_EUNSUPPORTED, "backward of a network without contraction steps");
+  const int64_t n = path->final_elems;
+  double* partial = (double*)(w + L.base.aux_off);
+  HIP_TRY(launch_expectation(s, psi, pbs, n, terms, batch, partial, value_dev, 1));
+  float2* lam = (float2*)(w + L.lam_off);
+  HIP_TRY(launch_apply_diag_obs(s, psi, pbs, lam, n, n, terms, batch));
+  float2* umats = (float2*)(w + L.mats_off);
+  HIP_TRY(launch_sweep_matrices(s, d->sweep_recipes, (int)net->sweep.size(), d->sweep_ops, d->mats, params_dev,
+                                net->n_params, batch, umats));
+  double* parts = (double*)(w + L.part_off);
+  const int64_t pstride = (int64_t)std::max(d->n_slots, 1) * kReduceBlocks;
+  for (int gi = (int)net->sweep.size() - 1; gi >= 0; --gi) {
+    const SweepGate& g = net->sweep[gi];
+    SweepArgs a;
+    a.nq = g.nq;
+    a.pos[0] = pos_in(path->final_bits, lab(net->wire_final[g.q[0]], 0));
+    a.pos[1] = g.nq == 2 ? pos_in(path->final_bits, lab(net->wire_final[g.q[1]], 0)) : 0;
+    a.gen = g.gen;
+    a.slot = d->slot_of_gate[gi];
+    if (a.pos[0] < 0 || a.pos[1] < 0 || (1ll << a.pos[0]) >= n || (1ll << a.pos[1]) >= n)
+      return set_error(TN_EINVAL, "internal: qubit leg missing from the final tensor");
+    hipEvent_t ev = prof_start(s);
+    HIP_TRY(launch_adjoint_step(s, a, umats + (int64_t)gi * 16, (int64_t)net->sweep.size() * 16, psi, pbs, lam, n,
+                                n, batch, parts, pstride));
+    prof_stop(s, ev, TN_KERNEL_ADJOINT, 32.0 * (double)n * batch, 64.0 * (double)n * batch * (g.nq == 2 ? 4 : 2));
+  }
+  if (net->n_params > 0)
+    HIP_TRY(launch_gradient_reduce(s, parts, pstride, d->n_slots, d->slot_param, net->n_params, grad_out_dev, batch,
+                                   grad_dev));
+  return TN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// single pairwise contraction
+// ---------------------------------------------------------------------------
+namespace {
+
+struct PairPlan {
+  tn_network net;
+  tn_path path;
+  std::vector<int32_t> c_bits;
+  int64_t a_elems = 0, c_elems = 0;
+};
+
+tn_status make_pair_plan(int32_t rank_a, const int32_t* modes_a, const int64_t* ext_a, int32_t rank_b,
+                         const int32_t* modes_b, const int64_t* ext_b, int32_t rank_c, const int32_t* modes_c,
+                         PairPlan* pp) {
+  if (rank_a < 0 || rank_b < 0 || rank_c < 0 || rank_a > TN_MAX_RANK || rank_b > TN_MAX_RANK || rank_c > TN_MAX_RANK)
+    return set_error(TN_EINVAL, "bad rank");
+  if ((rank_a && (!modes_a || !ext_a)) || (rank_b && (!modes_b || !ext_b)) || (rank_c && !modes_c))
+    return set_error(TN_EINVAL, "NULL mode array");
+  std::map<int32_t, int> id;
+  std::map<int32_t, int64_t> ext;
+  auto reg = [&](int32_t m, int64_t e) -> tn_status {
+    if (!is_pow2(e)) return set_error(TN_EUNSUPPORTED, "extents must be powers of two");
+    auto it = ext.find(m);
+    if (it != ext.end() && it->second != e) return set_error(TN_EINVAL, "shared mode with different extents");
+    ext[m] = e;
+    if (!id.count(m)) id[m] = (int)id.size();
+    return TN_OK;
+  };
+  auto dup = [](int32_t r, const int32_t* ms) {
+    for (int i = 0; i < r; ++i)
+      for (int j = i + 1; j < r; ++j)
+        if (ms[i] == ms[j]) return true;
+    return false;
+  };
+  if (dup(rank_a, modes_a) || dup(rank_b, modes_b) || dup(rank_c, modes_c))
+    return set_error(TN_EINVAL, "repeated mode within a tensor");
+  tn_status st;
+  for (int i = 0; i < rank_a; ++i) if ((st = reg(modes_a[i], ext_a[i])) != TN_OK) return st;
+  for (int i = 0; i < rank_b; ++i) if ((st = reg(modes_b[i], ext_b[i])) != TN_OK) return st;
+  auto has = [](int32_t r, const int32_t* ms, int32_t m) {
+    for (int i = 0; i < r; ++i) if (ms[i] == m) return true;
+    return false;
+  };
+  for (int i = 0; i < rank_c; ++i)
+    if (!ext.count(modes_c[i])) return set_error(TN_EINVAL, "output mode absent from both operands");
+  for (auto& kv : ext) {
+    const bool ia = has(rank_a, modes_a, kv.first), ib = has(rank_b, modes_b, kv.first);
+    if ((ia != ib) && !has(rank_c, modes_c, kv.first))
+      return set_error(TN_EINVAL, "a mode of one operand only must appear in the output");
+  }
+  tn_network& net = pp->net;
+  net.mode_log2.assign(id.size(), 0);
+  for (auto& kv : ext) {
+    int l = 0;
+    while (((int64_t)1 << l) < kv.second) ++l;
+    net.mode_log2[id[kv.first]] = l;
+  }
+  TensorDef ta, tb;
+  for (int i = 0; i < rank_a; ++i) ta.modes.push_back(id[modes_a[i]]);
+  for (int i = 0; i < rank_b; ++i) tb.modes.push_back(id[modes_b[i]]);
+  ta.kind = tb.kind = TK_GATE;
+  ta.recipe = tb.recipe = -1;
+  ta.qubit = tb.qubit = 0;
+  ta.size = tb.size = 1;
+  for (int m : ta.modes) ta.size <<= net.mode_log2[m];
+  for (int m : tb.modes) tb.size <<= net.mode_log2[m];
+  ta.offset = 0;
+  tb.offset = ta.size;
+  net.tensors = {ta, tb};
+  for (int i = 0; i < rank_c; ++i) net.output_modes.push_back(id[modes_c[i]]);
+  net.input_elems = ta.size + tb.size;
+  pp->path.pairs = {0, 1};
+  if ((st = compile_program(&net, &pp->path)) != TN_OK) return st;
+  pp->a_elems = ta.size;
+  pp->c_elems = 1;
+  for (int i = 0; i < rank_c; ++i) {
+    const int m = id[modes_c[i]];
+    for (int j = net.mode_log2[m] - 1; j >= 0; --j) pp->c_bits.push_back(lab(m, j));
+    pp->c_elems <<= net.mode_log2[m];
+  }
+  return TN_OK;
+}
+
+}  // namespace
+
+extern "C" size_t tn_contract_pair_workspace_bytes(int32_t rank_a, const int32_t* modes_a, const int64_t* ext_a,
+                                                   int32_t rank_b, const int32_t* modes_b, const int64_t* ext_b,
+                                                   int32_t rank_c, const int32_t* modes_c) {
+  PairPlan pp;
+  if (make_pair_plan(rank_a, modes_a, ext_a, rank_b, modes_b, ext_b, rank_c, modes_c, &pp) != TN_OK) return 0;
+  return align256(sizeof(float2) * (size_t)pp.path.ws_elems);
+}
+
+extern "C" tn_status tn_contract_pair(void* stream, int32_t precision, const void* a, int32_t rank_a,
+                                      const int32_t* modes_a, const int64_t* ext_a, const void* b, int32_t rank_b,
+                                      const int32_t* modes_b, const int64_t* ext_b, void* c, int32_t rank_c,
+                                      const int32_t* modes_c, void* workspace_dev, size_t workspace_bytes) {
+  clear_error();
+  if (precision != TN_PREC_C64 && precision != TN_PREC_BF16X3) return set_error(TN_EINVAL, "unknown precision");
+  if (!a || !b || !c) return set_error(TN_EINVAL, "NULL operand");
+  PairPlan pp;
+  tn_status st = make_pair_plan(rank_a, modes_a, ext_a, rank_b, modes_b, ext_b, rank_c, modes_c, &pp);
+  if (st != TN_OK) return st;
+  const size_t need = align256(sizeof(float2) * (size_t)pp.path.ws_elems);
+  if (workspace_bytes < need || !workspace_dev)
+    return set_error(TN_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
+  hipStream_t s = (hipStream_t)stream;
+  Bases B;
+  B.pair_a = (const float2*)a;
+  B.pair_b = (const float2*)b;
+  B.pair_a_elems = pp.a_elems;
+  B.ws = (float2*)workspace_dev;
+  B.ws_bs = 0;
+  if ((st = run_steps(s, &pp.path, B, 1, precision)) != TN_OK) return st;
+  return finish_to(s, B, &pp.path, pp.c_bits, (float2*)c, 0, pp.c_elems, 1, nullptr);
+}

@@ -16,3 +16,24 @@ def pytest_configure(config):
 @pytest.fixture(scope="session")
 def golden_dir():
     return os.path.join(ROOT, "tests", "golden")
+
+
+def _ensure_built():
+    """Build the oracle and the HIP library if nothing is built yet."""
+    import oracle.build as ob
+    if not os.path.exists(ob.LIB):
+        ob.build()
+    import paper_2108_06831_amd.build as pb
+    if not os.path.exists(pb.LIB):
+        pb.build()
+
+
+_ensure_built()
+
+
+def gpu_available():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False

@@ -1,0 +1,123 @@
+"""Pairwise contraction kernels through the C ABI (tn_contract_pair) against
+the definition of a contraction (oracle.contract, FP64).  GPU only."""
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+C64_TOL = 1e-5
+BF16X3_TOL = 1e-3
+
+
+def relerr(got, want):
+    got = np.asarray(got, dtype=np.complex128).reshape(-1)
+    want = np.asarray(want, dtype=np.complex128).reshape(-1)
+    return np.linalg.norm(got - want) / max(np.linalg.norm(want), 1e-300)
+
+
+def crand(rng, shape):
+    return (rng.normal(size=shape) + 1j * rng.normal(size=shape)).astype(np.complex64)
+
+
+def run_pair(a, ma, b, mb, mc, precision="c64"):
+    import torch
+    from paper_2108_06831_amd import contract_pair
+    ta = torch.from_numpy(a).cuda()
+    tb = torch.from_numpy(b).cuda()
+    c = contract_pair(ta, ma, tb, mb, mc, precision=precision)
+    torch.cuda.synchronize()
+    return c.cpu().numpy()
+
+
+@pytest.mark.parametrize("M,N,K", [(1, 1, 1), (2, 2, 2), (4, 4, 4), (32, 16, 2), (64, 64, 64), (128, 64, 16),
+                                   (256, 128, 32), (512, 512, 512), (2, 1024, 2), (1024, 2, 4), (16, 256, 1024),
+                                   (8, 8, 4096)])
+def test_matmul_eq22(M, N, K):
+    """Z^i_j = M^i_k L^k_j (eq. (2.2)) through the matrix-product kernel."""
+    print(f"matmul M={M} N={N} K={K}", flush=True)
+    rng = np.random.default_rng(M * 7 + N * 3 + K)
+    A, B = crand(rng, (M, K)), crand(rng, (K, N))
+    got = run_pair(A, [0, 1], B, [1, 2], [0, 2])
+    assert relerr(got, oracle.contract(A, [0, 1], B, [1, 2], [0, 2])) < C64_TOL
+
+
+@pytest.mark.parametrize("ta,tb", [(False, False), (True, False), (False, True), (True, True)])
+def test_matmul_operand_orientations(ta, tb):
+    rng = np.random.default_rng(3)
+    M, N, K = 128, 64, 256
+    A = crand(rng, (K, M) if ta else (M, K))
+    B = crand(rng, (N, K) if tb else (K, N))
+    ma = [1, 0] if ta else [0, 1]
+    mb = [2, 1] if tb else [1, 2]
+    got = run_pair(A, ma, B, mb, [0, 2])
+    assert relerr(got, oracle.contract(A, ma, B, mb, [0, 2])) < C64_TOL
+
+
+def test_batched_matmul_block_diag():
+    """Sec. 3's block-diagonal matrices: a batch mode shared by A, B and C."""
+    rng = np.random.default_rng(4)
+    A, B = crand(rng, (8, 64, 32)), crand(rng, (8, 32, 128))
+    got = run_pair(A, [9, 0, 1], B, [9, 1, 2], [9, 0, 2])
+    assert relerr(got, oracle.contract(A, [9, 0, 1], B, [9, 1, 2], [9, 0, 2])) < C64_TOL
+
+
+def test_matvec_trace_outer():
+    rng = np.random.default_rng(5)
+    M, x = crand(rng, (256, 256)), crand(rng, (256,))
+    assert relerr(run_pair(M, [0, 1], x, [1], [0]), M.astype(complex) @ x) < C64_TOL
+    I = np.eye(256, dtype=np.complex64)
+    assert relerr(run_pair(M, [0, 1], I, [1, 0], []), np.trace(M.astype(complex))) < C64_TOL
+    L = crand(rng, (4, 8))
+    got = run_pair(M[:16, :16].copy(), [0, 1], L, [2, 3], [0, 2, 1, 3]).reshape(64, 128)
+    assert relerr(got, np.kron(M[:16, :16].astype(complex), L.astype(complex))) < C64_TOL
+
+
+def random_bit_problem(rng, n_batch, n_m, n_n, n_k, big=None):
+    """Random extent-2 modes in random orders for A, B and C."""
+    modes = list(range(n_batch + n_m + n_n + n_k))
+    rng.shuffle(modes)
+    bt, mm, nn, kk = (modes[:n_batch], modes[n_batch:n_batch + n_m], modes[n_batch + n_m:n_batch + n_m + n_n],
+                      modes[n_batch + n_m + n_n:])
+    ma = list(bt + mm + kk)
+    mb = list(bt + kk + nn)
+    mc = list(bt + mm + nn)
+    for l in (ma, mb, mc):
+        rng.shuffle(l)
+    A = crand(rng, (2,) * len(ma))
+    B = crand(rng, (2,) * len(mb))
+    return A, ma, B, mb, mc
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_mode_orders(seed):
+    """Permute + product on random bit layouts (small and large operands)."""
+    rng = np.random.default_rng(1000 + seed)
+    shapes = [(0, 3, 8, 2), (1, 2, 10, 1), (0, 7, 7, 6), (2, 6, 5, 7), (0, 0, 12, 2), (1, 1, 1, 1),
+              (0, 9, 9, 5), (3, 0, 9, 3), (0, 2, 14, 2), (0, 8, 0, 8), (2, 1, 12, 3), (0, 4, 11, 4)]
+    nb, nm, nn, nk = shapes[seed]
+    A, ma, B, mb, mc = random_bit_problem(rng, nb, nm, nn, nk)
+    print(f"random layout seed={seed} b={nb} m={nm} n={nn} k={nk}", flush=True)
+    got = run_pair(A, ma, B, mb, mc)
+    assert relerr(got, oracle.contract(A, ma, B, mb, mc)) < C64_TOL
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_bf16x3_error_bound(seed):
+    rng = np.random.default_rng(2000 + seed)
+    A, ma, B, mb, mc = random_bit_problem(rng, 0, 7, 7, 6) if seed % 2 == 0 else random_bit_problem(rng, 0, 2, 14, 2)
+    want = oracle.contract(A, ma, B, mb, mc)
+    e_bf = relerr(run_pair(A, ma, B, mb, mc, "bf16x3"), want)
+    e_32 = relerr(run_pair(A, ma, B, mb, mc, "c64"), want)
+    print(f"bf16x3 rel err {e_bf:.3e}, c64 {e_32:.3e}", flush=True)
+    assert e_bf < BF16X3_TOL
+    assert e_32 < C64_TOL
+
+
+def test_deterministic():
+    rng = np.random.default_rng(7)
+    A, ma, B, mb, mc = random_bit_problem(rng, 1, 8, 8, 6)
+    x = run_pair(A, ma, B, mb, mc)
+    y = run_pair(A, ma, B, mb, mc)
+    assert np.array_equal(x, y)

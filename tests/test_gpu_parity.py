@@ -1,0 +1,158 @@
+"""Parity of the GPU contraction path with the FP64 oracle on the seeded
+workloads (tolerances: 1e-5 normwise relative for complex64, 1e-3 for
+BF16x3; scalars |e - e_ref| / max(|e_ref|, 1)).  GPU only."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+C64_TOL = 1e-5
+BF16X3_TOL = 1e-3
+
+
+def relerr(got, want):
+    got = np.asarray(got, dtype=np.complex128).reshape(-1)
+    want = np.asarray(want, dtype=np.complex128).reshape(-1)
+    return np.linalg.norm(got - want) / max(np.linalg.norm(want), 1e-300)
+
+
+def scalar_err(got, want):
+    return abs(got - want) / max(abs(want), 1.0)
+
+
+def statevector_gpu(circ, kind="greedy", fuse=False, precision="c64", params=None, batch=1):
+    import torch
+    from paper_2108_06831_amd import Network, contract_path
+    net = Network.from_circuit(circ, fuse=fuse)
+    path = net.plan(kind)
+    out = contract_path(net, path, params=params, batch=batch, precision=precision)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+@pytest.mark.parametrize("kind", ["greedy", "sequential", "random"])
+@pytest.mark.parametrize("fuse", [False, True])
+def test_config0_statevector(kind, fuse):
+    circ = workloads.config0()
+    print(f"config0 kind={kind} fuse={fuse}", flush=True)
+    want = oracle.statevector(circ)
+    got = statevector_gpu(circ, kind, fuse)[0]
+    e = relerr(got, want)
+    print(f"  rel err {e:.2e}", flush=True)
+    assert e < C64_TOL
+
+
+def test_config0_bf16x3():
+    circ = workloads.config0()
+    want = oracle.statevector(circ)
+    e = relerr(statevector_gpu(circ, precision="bf16x3")[0], want)
+    print(f"config0 bf16x3 rel err {e:.2e}", flush=True)
+    assert e < BF16X3_TOL
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_circuits(seed):
+    rng = np.random.default_rng(3000 + seed)
+    n = int(rng.integers(1, 11))
+    circ = workloads.random_circuit(n, 60, rng)
+    print(f"random circuit seed={seed} n={n}", flush=True)
+    for kind in ("greedy", "sequential"):
+        for fuse in (False, True):
+            got = statevector_gpu(circ, kind, fuse)[0]
+            assert relerr(got, oracle.statevector(circ)) < C64_TOL
+
+
+def test_edge_cases():
+    from workloads import Circuit, Gate
+    # no gates: |0...0>
+    got = statevector_gpu(Circuit(3, []), "greedy")[0]
+    assert relerr(got, np.eye(8)[0]) < 1e-7
+    # one qubit, one gate
+    c = Circuit(1, [Gate("H", (0,))])
+    assert relerr(statevector_gpu(c)[0], oracle.statevector(c)) < C64_TOL
+    # a qubit that no gate touches, and a qubit with diagonal gates only
+    c = Circuit(4, [Gate("H", (0,)), Gate("CNOT", (0, 2)), Gate("Z", (3,)), Gate("RZ", (3,), (0.3,))])
+    assert relerr(statevector_gpu(c)[0], oracle.statevector(c)) < C64_TOL
+
+
+def test_ghz_and_qft_closed_forms():
+    n = 12
+    c = workloads.Circuit(n, [workloads.Gate("H", (0,))] + [workloads.Gate("CNOT", (q, q + 1)) for q in range(n - 1)])
+    got = statevector_gpu(c)[0]
+    want = np.zeros(1 << n, complex)
+    want[0] = want[-1] = 2 ** -0.5
+    assert relerr(got, want) < C64_TOL
+
+
+@pytest.mark.parametrize("precision,tol", [("c64", C64_TOL), ("bf16x3", BF16X3_TOL)])
+def test_config1_full_statevector(precision, tol):
+    """24 qubits, depth 16, 2-qubit fusion: the full 2^24 state."""
+    circ = workloads.config1()
+    print(f"config1 {precision}: oracle ...", flush=True)
+    want = oracle.statevector(circ)
+    print("config1: gpu ...", flush=True)
+    got = statevector_gpu(circ, "greedy", fuse=True, precision=precision)[0]
+    e = relerr(got, want)
+    print(f"config1 {precision} rel err {e:.3e} max abs {np.max(np.abs(got - want)):.2e}", flush=True)
+    assert e < tol
+
+
+@pytest.mark.parametrize("rows,cols,depth", [(2, 3, 4), (3, 3, 8), (4, 4, 12), (4, 6, 12)])
+def test_config2_amplitudes_small_grids(rows, cols, depth):
+    import torch
+    from paper_2108_06831_amd import Network, amplitudes
+    circ, bits = workloads.config2(rows, cols, depth, n_bitstrings=4096)
+    print(f"config2 grid {rows}x{cols} depth {depth}", flush=True)
+    net = Network.from_circuit(circ, output="amplitudes", n_bitstrings=4096)
+    path = net.plan("greedy", max_log2_intermediate=30)
+    got = amplitudes(net, path, bits).cpu().numpy()
+    want = oracle.amplitudes(oracle.statevector(circ), circ.n_qubits, bits)
+    e = relerr(got, want)
+    print(f"  rel err {e:.2e}", flush=True)
+    assert e < C64_TOL
+
+
+def test_config3_expectations_subset():
+    import torch
+    from paper_2108_06831_amd import Network, Observable, expectation
+    inst = workloads.config3()[:12]
+    inst = [it for it in inst if it.circuit.n_qubits <= 20][:6]
+    nets, paths, params, obs, want = [], [], [], [], []
+    for it in inst:
+        net = Network.from_circuit(it.circuit)
+        nets.append(net)
+        paths.append(net.plan("sequential"))
+        params.append(it.params)
+        m, c = workloads.maxcut_observable(it.circuit.n_qubits, it.edges)
+        obs.append(Observable(m, c))
+        want.append(oracle.circuit_expectation(it.circuit, it.params, m, c))
+    got = expectation(nets, paths, params, obs).cpu().numpy()[:, 0]
+    for g, w in zip(got, want):
+        assert scalar_err(g, w) < C64_TOL
+    # beta = 0: <C> = |E|/2 exactly
+    it = inst[0]
+    p0 = it.params.copy()
+    p0[4:] = 0
+    m, c = workloads.maxcut_observable(it.circuit.n_qubits, it.edges)
+    g0 = expectation([nets[0]], [paths[0]], [p0], [Observable(m, c)]).cpu().numpy()[0, 0]
+    assert abs(g0 - len(it.edges) / 2) < 1e-5 * len(it.edges)
+
+
+def test_config4_gradients_small():
+    import torch
+    from paper_2108_06831_amd import Network, Observable, backward
+    circ, params, (m, c) = workloads.config4(n=8, layers=3, batch=4)
+    net = Network.from_circuit(circ)
+    path = net.plan("sequential")
+    value, grad = backward(net, path, params, Observable(m, c), batch=4)
+    value, grad = value.cpu().numpy(), grad.cpu().numpy()
+    for b in range(4):
+        want_e = oracle.circuit_expectation(circ, params[b], m, c)
+        assert scalar_err(value[b], want_e) < C64_TOL
+        g = oracle.param_shift_gradient(circ, params[b], m, c)
+        e = np.linalg.norm(grad[b] - g) / np.linalg.norm(g)
+        print(f"  batch {b}: grad rel err {e:.2e}", flush=True)
+        assert e < C64_TOL

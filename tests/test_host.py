@@ -1,0 +1,196 @@
+"""Host-side logic of libtnq.so, CPU only: the exported C ABI, the circuit ->
+network builder, the greedy planner and the compiled program's semantics
+(checked by executing planned paths in FP64 on the CPU against the oracle)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from paper_2108_06831_amd import Network, Observable, TNError, _lib
+from tests import pathexec
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    header = open(os.path.join(ROOT, "include", "tn.h")).read()
+    declared = set(re.findall(r"\b(tn_[a-z_0-9]+)\s*\(", header))
+    lib = _lib.lib()
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert set(_lib.EXPORTS) == declared
+    assert lib.tn_version().decode().startswith("tnq")
+
+
+def test_network_structure_config0():
+    circ = workloads.config0()
+    net = Network.from_circuit(circ)
+    info = net.info()
+    # 10 |0> vectors + 80 U3 (dense, new output legs) + 36 CZ (diagonal: hyper-indices)
+    assert info["n_tensors"] == 10 + 80 + 36
+    assert info["n_modes"] == 10 + 80
+    ranks = [len(net.tensor(t)[0]) for t in range(info["n_tensors"])]
+    assert ranks.count(1) == 10 and ranks.count(2) == 80 + 36
+
+
+def test_network_structure_config1_fused():
+    net = Network.from_circuit(workloads.config1(), fuse=True)
+    info = net.info()
+    assert info["n_tensors"] == 24 + 184
+    assert all(len(net.tensor(t)[0]) == 4 for t in range(24, 24 + 184))
+
+
+def test_amplitude_network_has_projectors():
+    circ, bits = workloads.config2(rows=2, cols=3, depth=4, n_bitstrings=100)
+    net = Network.from_circuit(circ, output="amplitudes", n_bitstrings=100)
+    modes, ext = net.output()
+    assert len(modes) == 1 and ext == [128]
+    n_t = net.info()["n_tensors"]
+    for t in range(n_t - 6, n_t):
+        m, e = net.tensor(t)
+        assert e == [128, 2] and m[0] == modes[0]
+
+
+@pytest.mark.parametrize("seed", range(8))
+@pytest.mark.parametrize("fuse", [False, True])
+def test_greedy_path_matches_oracle_random(seed, fuse):
+    rng = np.random.default_rng(500 + seed)
+    n = int(rng.integers(2, 8))
+    circ = workloads.random_circuit(n, 25, rng)
+    net = Network.from_circuit(circ, fuse=fuse)
+    path = net.plan()
+    got = pathexec.execute(net, path).reshape(-1)
+    want = oracle.statevector(circ)
+    assert np.max(np.abs(got - want)) < 1e-12
+
+
+@pytest.mark.parametrize("kind", ["greedy", "sequential", "random"])
+def test_path_independence_config0(kind):
+    """Contraction is associative: every order gives the same state (Sec. 2.2.3)."""
+    circ = workloads.config0()
+    net = Network.from_circuit(circ)
+    want = oracle.statevector(circ)
+    for seed in range(3 if kind == "random" else 1):
+        path = net.plan(kind, seed=seed)
+        got = pathexec.execute(net, path).reshape(-1)
+        assert np.max(np.abs(got - want)) < 1e-12
+
+
+def test_fused_config0_matches_oracle():
+    circ = workloads.config0()
+    net = Network.from_circuit(circ, fuse=True)
+    got = pathexec.execute(net, net.plan()).reshape(-1)
+    assert np.max(np.abs(got - oracle.statevector(circ))) < 1e-12
+
+
+def test_parametric_network_values_match_oracle():
+    circ, params, (masks, coeffs) = workloads.config4(n=6, layers=2, batch=3)
+    net = Network.from_circuit(circ)
+    path = net.plan()
+    for b in range(3):
+        got = pathexec.execute(net, path, params=params[b]).reshape(-1)
+        want = oracle.statevector(circ, params[b])
+        assert np.max(np.abs(got - want)) < 1e-12
+
+
+def test_qaoa_network_values_match_oracle():
+    inst = workloads.config3(n_circuits=2, sizes=(8,))
+    for it in inst:
+        net = Network.from_circuit(it.circuit)
+        got = pathexec.execute(net, net.plan(), params=it.params).reshape(-1)
+        want = oracle.statevector(it.circuit, it.params)
+        assert np.max(np.abs(got - want)) < 1e-12
+
+
+def test_amplitude_path_matches_oracle():
+    circ, bits = workloads.config2(rows=3, cols=3, depth=6, n_bitstrings=50)
+    net = Network.from_circuit(circ, output="amplitudes", n_bitstrings=50)
+    path = net.plan()
+    got = pathexec.execute(net, path, bitstrings=bits)[:50]
+    psi = oracle.statevector(circ)
+    want = oracle.amplitudes(psi, circ.n_qubits, bits)
+    assert np.max(np.abs(got - want)) < 1e-12
+
+
+def test_greedy_is_deterministic():
+    circ = workloads.config1()
+    a = Network.from_circuit(circ, fuse=True).plan().pairs()
+    b = Network.from_circuit(circ, fuse=True).plan().pairs()
+    assert a == b
+
+
+def test_plan_stats_and_step_views():
+    net = Network.from_circuit(workloads.config0())
+    path = net.plan()
+    st = path.stats
+    assert st["n_steps"] == net.info()["n_tensors"] - 1
+    assert st["max_intermediate_elems"] == 1024  # the statevector is the largest tensor
+    assert st["n_skinny_steps"] + st["n_gemm_steps"] == st["n_steps"]
+    tot = 0.0
+    for s in range(st["n_steps"]):
+        b, m, n, k = path.step(s)["bmnk"]
+        tot += 8.0 * b * m * n * k
+    assert tot == pytest.approx(st["flops"])
+    assert path.workspace_bytes(1) >= 8 * 1024
+
+
+def test_config_plan_sizes():
+    """Largest intermediates the greedy order reaches on the workloads."""
+    p1 = Network.from_circuit(workloads.config1(), fuse=True).plan()
+    assert p1.stats["max_intermediate_elems"] <= 2 ** 26
+    circ, params, _ = workloads.config4()
+    p4 = Network.from_circuit(circ).plan()
+    assert p4.stats["max_intermediate_elems"] >= 2 ** 20
+
+
+def test_invalid_inputs_are_rejected():
+    c = workloads.Circuit(3, [workloads.Gate("CZ", (0, 1))])
+    c.gates[0].qubits = (0, 0)
+    with pytest.raises(TNError) as e:
+        Network.from_circuit(c)
+    assert e.value.status == _lib.TN_EINVAL
+    c.gates[0].qubits = (0, 5)
+    with pytest.raises(TNError):
+        Network.from_circuit(c)
+    c2 = workloads.Circuit(2, [workloads.Gate("RX", (0,), (0.1,), (3,))], n_params=2)
+    with pytest.raises(TNError):
+        Network.from_circuit(c2)
+
+
+def test_intermediate_cap_gives_elimit():
+    net = Network.from_circuit(workloads.config0())
+    with pytest.raises(TNError) as e:
+        net.plan(max_log2_intermediate=8)
+    assert e.value.status == _lib.TN_ELIMIT
+
+
+def test_workspace_too_small_gives_enomem_before_any_device_call():
+    net = Network.from_circuit(workloads.config0())
+    path = net.plan()
+    fake = ctypes.c_void_p(0x1000)
+    st = _lib.lib().tn_contract_path(None, 0, net.handle, path.handle, None, 1, fake, 16, fake)
+    assert st == _lib.TN_ENOMEM
+
+
+def test_contract_pair_argument_checks():
+    lib = _lib.lib()
+    ma = (ctypes.c_int32 * 2)(0, 1)
+    ea = (ctypes.c_int64 * 2)(4, 4)
+    mb = (ctypes.c_int32 * 2)(1, 2)
+    eb = (ctypes.c_int64 * 2)(3, 4)  # extent mismatch on the shared mode
+    mc = (ctypes.c_int32 * 2)(0, 2)
+    assert lib.tn_contract_pair_workspace_bytes(2, ma, ea, 2, mb, eb, 2, mc) == 0
+    eb2 = (ctypes.c_int64 * 2)(4, 4)
+    assert lib.tn_contract_pair_workspace_bytes(2, ma, ea, 2, mb, eb2, 2, mc) > 0
+    mc_bad = (ctypes.c_int32 * 1)(0)  # mode 2 of B only must be in C
+    assert lib.tn_contract_pair_workspace_bytes(2, ma, ea, 2, mb, eb2, 1, mc_bad) == 0
+
+
+def test_observable_marshalling():
+    masks, coeffs = workloads.maxcut_observable(4, [(0, 1), (2, 3)])
+    o = Observable(masks, coeffs)
+    assert o.c.n_terms == 3
