@@ -34,7 +34,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--path", default="greedy", help="greedy | sequential | random")
+    ap.add_argument("--path", default="search", help="search | greedy | sequential | random")
+    ap.add_argument("--trials", type=int, default=128, help="randomised orders tried by the search")
+    ap.add_argument("--fuse", default="split", help="split | dense | none")
     ap.add_argument("--precision", default="c64", help="c64 | bf16x3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true", help="skip the parity check against the oracle")
@@ -56,8 +58,8 @@ def main():
     circ = workloads.config1()
     n = circ.n_qubits
     t0 = time.perf_counter()
-    net = tnq.Network.from_circuit(circ, fuse=True)
-    path = net.plan(args.path)
+    net = tnq.Network.from_circuit(circ, fuse=False if args.fuse == "none" else args.fuse)
+    path = net.plan(args.path, trials=args.trials)
     plan_s = time.perf_counter() - t0
     out = torch.empty(1, 1 << n, dtype=torch.complex64, device=dev)
     ws = torch.empty(path.workspace_bytes(1), dtype=torch.uint8, device=dev)
@@ -115,9 +117,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": "24-qubit random brickwork circuit, depth 16 (384 U3 + 184 CZ, seeded), "
                                "2-qubit fusion, full 2^24 complex64 statevector",
-                   "n_qubits": n, "depth": 16, "path": args.path, "precision": args.precision,
+                   "n_qubits": n, "depth": 16, "path": args.path, "fuse": args.fuse, "precision": args.precision,
                    "plan_seconds": plan_s, "path_flops": path.stats["flops"], "path_bytes": path.stats["bytes"],
-                   "max_intermediate": path.stats["max_intermediate_elems"], "n_steps": path.stats["n_steps"]},
+                   "max_intermediate": path.stats["max_intermediate_elems"], "n_steps": path.stats["n_steps"],
+                   "n_small_steps": path.stats["n_small_steps"], "modeled_ms": path.stats["modeled_seconds"] * 1e3},
         "path_tflops": path.stats["flops"] / (ms * 1e-3) / 1e12,
         "roofline": roof,
         "kernels": kernels,

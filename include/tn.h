@@ -110,13 +110,19 @@ typedef struct {
 typedef enum {
   TN_PATH_GREEDY = 0,     /* size-minimising greedy (default) */
   TN_PATH_SEQUENTIAL = 1, /* input tensors in network order (gate-by-gate state vector) */
-  TN_PATH_RANDOM = 2      /* a seeded random connected order (for testing order independence) */
+  TN_PATH_RANDOM = 2,     /* a seeded random connected order (for testing order independence) */
+  TN_PATH_SEARCH = 3      /* strategy selection (Sec. 3): the greedy order, the sequential order and `trials`
+                             randomised greedy orders (objective |C| - alpha(|A|+|B|) with Gumbel noise, alpha
+                             and the noise scale drawn per trial), each compiled and scored by a model of its
+                             run time on the GPU; the fastest order within the intermediate cap is kept */
 } tn_path_kind;
 
 typedef struct {
   int32_t kind;                  /* tn_path_kind */
   int32_t max_log2_intermediate; /* TN_ELIMIT if an intermediate exceeds 2^this elements; <= 0: 40 */
-  uint64_t seed;                 /* TN_PATH_RANDOM only */
+  uint64_t seed;                 /* TN_PATH_RANDOM and TN_PATH_SEARCH */
+  int32_t trials;                /* TN_PATH_SEARCH: randomised trials; <= 0: 64 */
+  int32_t reserved;
 } tn_plan_opts;
 
 typedef struct {
@@ -125,10 +131,13 @@ typedef struct {
   double max_intermediate_elems; /* largest intermediate, elements */
   double large_step_flops;       /* flops of the steps with >= 1e9 flops and >= 40 flop/byte */
   double plan_seconds;           /* host time spent planning */
+  double modeled_seconds;        /* the planner's model of the program's GPU run time */
   int32_t n_steps;
   int32_t n_permutes;            /* explicit permute launches in the compiled program */
   int32_t n_gemm_steps;          /* steps executed by the MFMA matrix-product kernel */
   int32_t n_skinny_steps;        /* steps executed by the small-operand streaming kernel */
+  int32_t n_small_steps;         /* leading small steps run together by one interpreter launch */
+  int32_t n_small_lists;         /* independent work lists of that launch (one workgroup each) */
 } tn_path_stats;
 
 typedef struct tn_network tn_network;
@@ -136,6 +145,9 @@ typedef struct tn_path tn_path;
 
 /* Flags for tn_build_network. */
 #define TN_FUSE_2Q 1 /* pre-contract each run of one-qubit gates into the adjacent two-qubit gate (Sec. 3) */
+#define TN_FUSE_SPLIT 2 /* with TN_FUSE_2Q: keep a fused block whose two-qubit gate is block-diagonal in one
+                           qubit's value (CZ, CNOT, CPHASE, ZZPHASE, ...) in its exact operator-Schmidt form,
+                           two 3-leg tensors joined by a bond of extent 2, so that orders can cut through it */
 
 /*
  * Circuit -> tensor network (Sec. 2.2.2-2.2.3; the "pre-contract the first
@@ -187,7 +199,7 @@ void tn_path_destroy(tn_path* path);
 tn_status tn_path_pairs(const tn_path* path, int32_t* n_steps, int32_t* pairs, int32_t capacity);
 /* Modes of the tensor produced by step s (C order, as laid out in memory),
  * and the step's GEMM view. kind: 0 = streaming small-operand kernel,
- * 1 = MFMA matrix product. */
+ * 1 = MFMA matrix product, 2 = interpreter of small steps. */
 tn_status tn_path_step(const tn_path* path, int32_t s, int32_t* rank, int32_t* modes, int64_t* gemm_bmnk,
                        int32_t* kind);
 

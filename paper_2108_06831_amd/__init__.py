@@ -20,14 +20,15 @@ import numpy as np
 
 from . import _lib
 from ._lib import (TN_FUSE_2Q, TN_OUT_AMPLITUDES, TN_OUT_STATEVECTOR, TN_PATH_GREEDY, TN_PATH_RANDOM,
-                   TN_PATH_SEQUENTIAL, TN_PREC_BF16X3, TN_PREC_C64, TNError, check, lib)
+                   TN_PATH_SEARCH, TN_PATH_SEQUENTIAL, TN_PREC_BF16X3, TN_PREC_C64, TNError, check, lib)
 
 __all__ = ["Network", "Path", "contract_path", "amplitudes", "expectation", "backward", "contract_pair",
            "Expectation", "Observable", "TNError", "tn_build_network", "tn_plan_path", "tn_contract_pair",
            "tn_contract_path", "tn_amplitudes", "tn_expectation", "tn_backward"]
 
 PRECISION = {"c64": TN_PREC_C64, "bf16x3": TN_PREC_BF16X3}
-PATH_KIND = {"greedy": TN_PATH_GREEDY, "sequential": TN_PATH_SEQUENTIAL, "random": TN_PATH_RANDOM}
+PATH_KIND = {"greedy": TN_PATH_GREEDY, "sequential": TN_PATH_SEQUENTIAL, "random": TN_PATH_RANDOM,
+             "search": TN_PATH_SEARCH}
 
 
 def _prec(p) -> int:
@@ -103,12 +104,16 @@ class Network:
         self.n_bitstrings = n_bitstrings
 
     @classmethod
-    def from_circuit(cls, circ, output: str = "statevector", n_bitstrings: int = 0, fuse: bool = False,
+    def from_circuit(cls, circ, output: str = "statevector", n_bitstrings: int = 0, fuse=False,
                      matrices=None):
+        """fuse: False, "dense" (one 4x4 tensor per fused block) or "split" / True
+        (operator-Schmidt halves where the two-qubit gate allows)."""
         arr, n, _keep = gates_from_circuit(circ, matrices)
         kind = TN_OUT_STATEVECTOR if output == "statevector" else TN_OUT_AMPLITUDES
-        return tn_build_network(circ.n_qubits, arr, n, circ.n_params, kind, n_bitstrings,
-                                TN_FUSE_2Q if fuse else 0)
+        flags = 0
+        if fuse:
+            flags = _lib.TN_FUSE_2Q | (0 if fuse == "dense" else _lib.TN_FUSE_SPLIT)
+        return tn_build_network(circ.n_qubits, arr, n, circ.n_params, kind, n_bitstrings, flags)
 
     def __del__(self):
         try:
@@ -156,8 +161,8 @@ class Network:
             off += sz
         return vals
 
-    def plan(self, kind: str = "greedy", max_log2_intermediate: int = 0, seed: int = 0) -> "Path":
-        return tn_plan_path(self, kind, max_log2_intermediate, seed)
+    def plan(self, kind: str = "greedy", max_log2_intermediate: int = 0, seed: int = 0, trials: int = 0) -> "Path":
+        return tn_plan_path(self, kind, max_log2_intermediate, seed, trials)
 
 
 class Path:
@@ -187,7 +192,8 @@ class Path:
         bmnk = (ctypes.c_int64 * 4)()
         kind = ctypes.c_int32()
         check(lib().tn_path_step(self.handle, s, ctypes.byref(rank), modes, bmnk, ctypes.byref(kind)))
-        return {"modes": list(modes[: rank.value]), "bmnk": tuple(bmnk), "kind": "gemm" if kind.value else "skinny"}
+        return {"modes": list(modes[: rank.value]), "bmnk": tuple(bmnk),
+                "kind": ["skinny", "gemm", "small"][kind.value]}
 
     def workspace_bytes(self, batch: int = 1) -> int:
         return int(lib().tn_workspace_bytes(self.net.handle, self.handle, batch))
@@ -203,8 +209,9 @@ def tn_build_network(n_qubits, gates, n_gates, n_params, output_kind, n_bitstrin
     return Network(h, n_qubits, n_params, output_kind, n_bitstrings)
 
 
-def tn_plan_path(net: Network, kind="greedy", max_log2_intermediate: int = 0, seed: int = 0) -> Path:
-    opts = _lib.tn_plan_opts(PATH_KIND[kind] if isinstance(kind, str) else int(kind), max_log2_intermediate, seed)
+def tn_plan_path(net: Network, kind="greedy", max_log2_intermediate: int = 0, seed: int = 0, trials: int = 0) -> Path:
+    opts = _lib.tn_plan_opts(PATH_KIND[kind] if isinstance(kind, str) else int(kind), max_log2_intermediate, seed,
+                             trials, 0)
     h = ctypes.c_void_p()
     st = _lib.tn_path_stats()
     check(lib().tn_plan_path(net.handle, ctypes.byref(opts), ctypes.byref(h), ctypes.byref(st)))

@@ -16,8 +16,9 @@ TN_OK, TN_EINVAL, TN_ENOMEM, TN_ELIMIT, TN_EDEVICE, TN_EUNSUPPORTED = range(6)
 STATUS_NAMES = {0: "TN_OK", 1: "TN_EINVAL", 2: "TN_ENOMEM", 3: "TN_ELIMIT", 4: "TN_EDEVICE", 5: "TN_EUNSUPPORTED"}
 TN_PREC_C64, TN_PREC_BF16X3 = 0, 1
 TN_OUT_STATEVECTOR, TN_OUT_AMPLITUDES = 0, 1
-TN_PATH_GREEDY, TN_PATH_SEQUENTIAL, TN_PATH_RANDOM = 0, 1, 2
+TN_PATH_GREEDY, TN_PATH_SEQUENTIAL, TN_PATH_RANDOM, TN_PATH_SEARCH = 0, 1, 2, 3
 TN_FUSE_2Q = 1
+TN_FUSE_SPLIT = 2
 TN_MAX_RANK = 64
 
 GATE_KIND = {name: i + 1 for i, name in enumerate(
@@ -36,14 +37,17 @@ class tn_observable(ctypes.Structure):
 
 
 class tn_plan_opts(ctypes.Structure):
-    _fields_ = [("kind", ctypes.c_int32), ("max_log2_intermediate", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+    _fields_ = [("kind", ctypes.c_int32), ("max_log2_intermediate", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("trials", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class tn_path_stats(ctypes.Structure):
     _fields_ = [("flops", ctypes.c_double), ("bytes", ctypes.c_double), ("max_intermediate_elems", ctypes.c_double),
                 ("large_step_flops", ctypes.c_double), ("plan_seconds", ctypes.c_double),
+                ("modeled_seconds", ctypes.c_double),
                 ("n_steps", ctypes.c_int32), ("n_permutes", ctypes.c_int32), ("n_gemm_steps", ctypes.c_int32),
-                ("n_skinny_steps", ctypes.c_int32)]
+                ("n_skinny_steps", ctypes.c_int32), ("n_small_steps", ctypes.c_int32),
+                ("n_small_lists", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -99,7 +99,9 @@ struct Recipe {
   int32_t nq;
   int32_t diag;
   int32_t op_begin, op_end;
-  int64_t offset;  // element offset of the tensor in the per-batch input buffer
+  int32_t split_side;  // -1: the whole block; else the half of a split block on block qubit 0 or 1
+  int32_t split_on;    // block qubit (0 or 1) in whose value the block's two-qubit gate is block-diagonal
+  int64_t offset;      // element offset of the tensor in the per-batch input buffer
 };
 
 // d x d matrix (d = 2^nq) of a recipe, FP64.
@@ -151,6 +153,69 @@ __host__ __device__ inline void recipe_matrix(const Recipe& r, const RecipeOp* o
         T[d * i + j] = acc;
       }
     for (int i = 0; i < d * d; ++i) M[i] = T[i];
+  }
+}
+
+// A two-qubit block whose two-qubit gate is block-diagonal in the value of one
+// of its qubits (CZ, CPHASE, ZZPHASE, CNOT on its control, ...) has the exact
+// operator-Schmidt form  sum_k X_k (x) Y_k : with `on` the bond qubit, the
+// half on qubit `on` is post . |k><k| . pre and the other half is
+// post . G_k . pre with G_k the 2x2 block of the gate at bond value k (pre/post:
+// the block's one-qubit gates on that side before/after the two-qubit gate).
+// Writes the half on block qubit `side` as the tensor [k][o][i] (8 entries).
+__host__ __device__ inline void recipe_split_half(const Recipe& r, const RecipeOp* ops, const double* mats,
+                                                  const double* params, c128* out) {
+  const int side = r.split_side, on = r.split_on;
+  c128 pre[4], post[4], U[16];
+  for (int i = 0; i < 4; ++i) pre[i] = post[i] = cm((i == 0 || i == 3) ? 1.0 : 0.0, 0.0);
+  for (int i = 0; i < 16; ++i) U[i] = cm((i / 4) == (i % 4) ? 1.0 : 0.0, 0.0);
+  bool after = false;
+  for (int o = r.op_begin; o < r.op_end; ++o) {
+    const RecipeOp& op = ops[o];
+    double ang[3];
+    for (int j = 0; j < 3; ++j) ang[j] = op.param[j] >= 0 ? params[op.param[j]] : op.angle[j];
+    c128 u[16];
+    if (op.kind == TN_GATE_MATRIX1 || op.kind == TN_GATE_MATRIX2) {
+      const int du = op.kind == TN_GATE_MATRIX2 ? 4 : 2;
+      for (int i = 0; i < du * du; ++i) u[i] = cm(mats[32 * op.mat + 2 * i], mats[32 * op.mat + 2 * i + 1]);
+    } else {
+      gate_matrix(op.kind, ang, u);
+    }
+    if (gate_is_two_qubit(op.kind)) {
+      for (int x = 0; x < 4; ++x)
+        for (int y = 0; y < 4; ++y) {
+          const int xs = op.pos ? ((x & 1) << 1) | (x >> 1) : x;
+          const int ys = op.pos ? ((y & 1) << 1) | (y >> 1) : y;
+          U[4 * x + y] = u[4 * xs + ys];
+        }
+      after = true;
+      continue;
+    }
+    if (op.pos != side) continue;
+    c128* M = after ? post : pre;
+    c128 T[4];
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j) T[2 * i + j] = cadd(cmul(u[2 * i], M[j]), cmul(u[2 * i + 1], M[2 + j]));
+    for (int i = 0; i < 4; ++i) M[i] = T[i];
+  }
+  for (int k = 0; k < 2; ++k) {
+    c128 G[4];
+    for (int x = 0; x < 2; ++x)
+      for (int y = 0; y < 2; ++y) {
+        if (side == on) {
+          G[2 * x + y] = cm((x == k && y == k) ? 1.0 : 0.0, 0.0);
+        } else if (on == 0) {
+          G[2 * x + y] = U[4 * (2 * k + x) + (2 * k + y)];
+        } else {
+          G[2 * x + y] = U[4 * (2 * x + k) + (2 * y + k)];
+        }
+      }
+    c128 T[4], V[4];
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j) T[2 * i + j] = cadd(cmul(G[2 * i], pre[j]), cmul(G[2 * i + 1], pre[2 + j]));
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j) V[2 * i + j] = cadd(cmul(post[2 * i], T[j]), cmul(post[2 * i + 1], T[2 + j]));
+    for (int i = 0; i < 4; ++i) out[4 * k + i] = V[i];
   }
 }
 

@@ -113,10 +113,24 @@ struct GemmDesc {
   int32_t b_nfast;  // B stored [batch][K][N] (1) or [batch][N][K] (0)
 };
 
-enum StepKind { SK_SKINNY = 0, SK_GEMM = 1 };
+// A small step executed inside the interpreter kernel: every operand and the
+// result fit in a few KB.  C's address bit p comes from A's bit apos[p] and/or
+// B's bit bpos[p] (-1: absent); summed bit j sits at A bit ka[j] and B bit kb[j].
+constexpr int kSmallMaxBits = 12;
+constexpr int kSmallMaxMacLog2 = 20;
+struct SmallStep {
+  int32_t a_buf, b_buf, c_buf;
+  int32_t c_bits, k_bits, pad;
+  int64_t a_off, b_off, c_off;
+  int8_t apos[kSmallMaxBits], bpos[kSmallMaxBits];
+  int8_t ka[kSmallMaxBits], kb[kSmallMaxBits];
+};
+
+enum StepKind { SK_SKINNY = 0, SK_GEMM = 1, SK_SMALL = 2 };
 
 struct StepProgram {
   int32_t kind;
+  SmallStep sm;
   std::vector<PermuteDesc> pre;  // operand permutes before the product
   SkinnyDesc sk;
   GemmDesc gm;
@@ -136,6 +150,11 @@ struct tn_path {
   int64_t final_elems = 0;
   int64_t ws_elems = 0;  // per batch item (complex64 elements)
   int32_t n_inputs = 0;
+  // leading steps run by the interpreter kernel: independent sub-trees, one work list each
+  int32_t n_small = 0;
+  std::vector<tnq::SmallStep> small_steps;   // grouped by work list
+  std::vector<int32_t> small_lists;          // offsets into small_steps, size n_lists + 1
+  int64_t small_region = 0;                  // workspace elements reserved for their results
   tn_path_stats stats{};
   void* dev = nullptr;   // device-side cache
 };
@@ -143,9 +162,14 @@ struct tn_path {
 namespace tnq {
 // planner.cpp
 tn_status plan_order(const tn_network* net, const tn_plan_opts& opts, std::vector<int32_t>& pairs,
-                     double* max_log2_out);
+                     double* max_log2_out, double alpha = 1.0, double temp = 0.0, uint64_t seed = 0);
+uint64_t splitmix(uint64_t& s);
+double modeled_seconds(const tn_path* path);
 // program.cpp
 tn_status compile_program(const tn_network* net, tn_path* path);
+// moves every step that is small and depends only on inputs or such steps to the front
+std::vector<int32_t> reorder_small_first(const tn_network* net, const std::vector<int32_t>& pairs, int* n_small,
+                                         int64_t* small_region);
 // network.cpp
 void network_values_host(const tn_network* net, const double* params, const uint64_t* bits, double* out);
 // runtime

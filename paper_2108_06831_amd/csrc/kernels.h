@@ -46,6 +46,12 @@ constexpr int kReduceBlocks = 512;
 hipError_t launch_expectation(hipStream_t s, const float2* psi, int64_t psi_bs, int64_t n_elems, const ZTerms& terms,
                               int batch, double* partial, double* out, int64_t out_stride);
 
+// Interpreter of small steps: work list w (steps list_off[w] .. list_off[w+1]-1,
+// each depending only on inputs or earlier steps of the same list) runs in
+// workgroup (w, batch item).
+hipError_t launch_small_steps(hipStream_t s, const SmallStep* steps, const int32_t* list_off, int n_lists,
+                              float2* in, int64_t in_bs, float2* ws, int64_t ws_bs, int batch, int precision);
+
 // Contiguous copy of `n` complex64 per batch item.
 hipError_t launch_copy(hipStream_t s, const float2* in, int64_t in_bs, float2* out, int64_t out_bs, int64_t n,
                        int batch);

@@ -83,6 +83,11 @@ __global__ void k_materialize(const DevTensor* ts, int nt, const Recipe* rs, con
   } else if (d.kind == TK_GATE) {
     const Recipe r = rs[d.recipe];
     c128 M[16];
+    if (r.split_side >= 0) {
+      recipe_split_half(r, ops, mats, params ? params + (int64_t)z * pstride : nullptr, M);
+      for (int i = 0; i < 8; ++i) o[i] = f2((float)M[i].re, (float)M[i].im);
+      return;
+    }
     recipe_matrix(r, ops, mats, params ? params + (int64_t)z * pstride : nullptr, M);
     const int dd = r.nq == 2 ? 4 : 2;
     if (r.diag) {
@@ -219,6 +224,76 @@ hipError_t launch_skinny(hipStream_t s, const SkinnyDesc& d, const float2* g, in
   if (blocks > 16384) blocks = 16384;
   void* args[] = {&a};
   return hipLaunchKernel(fn, dim3((unsigned)blocks, batch), dim3(kThreads), args, 0, s);
+}
+
+// ---------------------------------------------------------------------------
+// Interpreter of small steps (one launch for all the tiny contractions that
+// only depend on inputs): each workgroup walks one independent work list.
+// A step is computed into registers, then written after a barrier, so a step
+// may overwrite one of its own operands.
+// ---------------------------------------------------------------------------
+constexpr int kSmallPerThread = (1 << kSmallMaxBits) / kThreads;
+
+template <int PREC>
+__global__ __launch_bounds__(kThreads) void k_small_steps(const SmallStep* steps, const int32_t* list_off,
+                                                          float2* in, int64_t in_bs, float2* ws, int64_t ws_bs) {
+  __shared__ SmallStep st;
+  const int w = blockIdx.x, z = blockIdx.y;
+  float2* IN = in + (int64_t)z * in_bs;
+  float2* WS = ws + (int64_t)z * ws_bs;
+  const int s0 = list_off[w], s1 = list_off[w + 1];
+  for (int s = s0; s < s1; ++s) {
+    if (threadIdx.x == 0) st = steps[s];
+    __syncthreads();
+    const float2* A = (st.a_buf == BUF_IN ? IN : WS) + st.a_off;
+    const float2* B = (st.b_buf == BUF_IN ? IN : WS) + st.b_off;
+    float2* C = (st.c_buf == BUF_IN ? IN : WS) + st.c_off;
+    const int n_out = 1 << st.c_bits, n_k = 1 << st.k_bits;
+    float2 res[kSmallPerThread];
+#pragma unroll
+    for (int r = 0; r < kSmallPerThread; ++r) {
+      const int o = threadIdx.x + r * kThreads;
+      res[r] = f2(0.f, 0.f);
+      if (o < n_out) {
+        int ab = 0, bb = 0;
+        for (int p = 0; p < st.c_bits; ++p)
+          if ((o >> p) & 1) {
+            if (st.apos[p] >= 0) ab |= 1 << st.apos[p];
+            if (st.bpos[p] >= 0) bb |= 1 << st.bpos[p];
+          }
+        float2 acc = f2(0.f, 0.f);
+        for (int k = 0; k < n_k; ++k) {
+          int ao = ab, bo = bb;
+          for (int j = 0; j < st.k_bits; ++j)
+            if ((k >> j) & 1) {
+              ao |= 1 << st.ka[j];
+              bo |= 1 << st.kb[j];
+            }
+          acc = cmac<PREC>(acc, A[ao], B[bo]);
+        }
+        res[r] = acc;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kSmallPerThread; ++r) {
+      const int o = threadIdx.x + r * kThreads;
+      if (o < n_out) C[o] = res[r];
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_small_steps(hipStream_t s, const SmallStep* steps, const int32_t* list_off, int n_lists,
+                              float2* in, int64_t in_bs, float2* ws, int64_t ws_bs, int batch, int precision) {
+  if (n_lists == 0) return hipSuccess;
+  if (precision == TN_PREC_BF16X3)
+    hipLaunchKernelGGL(k_small_steps<TN_PREC_BF16X3>, dim3(n_lists, batch), dim3(kThreads), 0, s, steps, list_off, in,
+                       in_bs, ws, ws_bs);
+  else
+    hipLaunchKernelGGL(k_small_steps<TN_PREC_C64>, dim3(n_lists, batch), dim3(kThreads), 0, s, steps, list_off, in,
+                       in_bs, ws, ws_bs);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

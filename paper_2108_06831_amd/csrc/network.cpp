@@ -45,6 +45,31 @@ bool ops_diagonal(const std::vector<RecipeOp>& ops, const std::vector<double>& m
   return true;
 }
 
+// block qubit (0 or 1) in whose value the block's two-qubit gate is
+// block-diagonal, or -1
+int split_qubit(const std::vector<RecipeOp>& ops, const std::vector<double>& mats) {
+  for (const RecipeOp& op : ops) {
+    if (!gate_is_two_qubit(op.kind)) continue;
+    if (op.kind == TN_GATE_CZ || op.kind == TN_GATE_CPHASE || op.kind == TN_GATE_ZZPHASE) return 0;
+    if (op.kind == TN_GATE_CNOT) return op.pos;  // the control
+    if (op.kind == TN_GATE_MATRIX2) {
+      const double* m = &mats[32 * op.mat];
+      auto zero = [&](int x, int y) { return m[2 * (4 * x + y)] == 0.0 && m[2 * (4 * x + y) + 1] == 0.0; };
+      for (int q = 0; q < 2; ++q) {  // q: gate-order qubit tested for block-diagonality
+        bool ok = true;
+        for (int x = 0; x < 4 && ok; ++x)
+          for (int y = 0; y < 4 && ok; ++y) {
+            const int bx = q == 0 ? (x >> 1) : (x & 1), by = q == 0 ? (y >> 1) : (y & 1);
+            if (bx != by && !zero(x, y)) ok = false;
+          }
+        if (ok) return op.pos ? 1 - q : q;
+      }
+    }
+    return -1;
+  }
+  return -1;
+}
+
 int gen_of(int kind) {
   switch (kind) {
     case TN_GATE_RX: return GEN_X_HALF;
@@ -76,6 +101,11 @@ void network_values_host(const tn_network* net, const double* params, const uint
     } else {
       const Recipe& r = net->recipes[t.recipe];
       c128 M[16];
+      if (r.split_side >= 0) {
+        recipe_split_half(r, net->ops.data(), net->matrices.data(), params, M);
+        for (int i = 0; i < 8; ++i) { o[2 * i] = M[i].re; o[2 * i + 1] = M[i].im; }
+        continue;
+      }
       recipe_matrix(r, net->ops.data(), net->matrices.data(), params, M);
       const int d = r.nq == 2 ? 4 : 2;
       if (r.diag) {
@@ -213,9 +243,32 @@ extern "C" tn_status tn_build_network(int32_t n_qubits, const tn_gate* gates, in
     Recipe r;
     r.nq = b.nq;
     r.diag = ops_diagonal(b.ops, net->matrices) ? 1 : 0;
+    r.split_side = -1;
+    r.split_on = 0;
     r.op_begin = (int32_t)net->ops.size();
     for (const RecipeOp& op : b.ops) net->ops.push_back(op);
     r.op_end = (int32_t)net->ops.size();
+    const int on = (b.nq == 2 && !r.diag && (flags & TN_FUSE_SPLIT)) ? split_qubit(b.ops, net->matrices) : -1;
+    if (on >= 0) {
+      // operator-Schmidt form: two 3-leg tensors [k][o][i] joined by the bond k
+      const int32_t k = new_mode(1);
+      for (int side = 0; side < 2; ++side) {
+        Recipe h = r;
+        h.split_side = side;
+        h.split_on = on;
+        TensorDef t;
+        t.kind = TK_GATE;
+        t.qubit = b.q[side];
+        t.recipe = (int32_t)net->recipes.size();
+        const int32_t o = new_mode(1);
+        t.modes = {k, o, cur[b.q[side]]};
+        cur[b.q[side]] = o;
+        h.offset = offset;
+        net->recipes.push_back(h);
+        add_tensor(t);
+      }
+      continue;
+    }
     TensorDef t;
     t.kind = TK_GATE;
     t.qubit = b.q[0];
@@ -275,6 +328,8 @@ extern "C" tn_status tn_build_network(int32_t n_qubits, const tn_gate* gates, in
       Recipe r;
       r.nq = s.nq;
       r.diag = 0;
+      r.split_side = -1;
+      r.split_on = 0;
       r.op_begin = (int32_t)net->sweep_ops.size();
       RecipeOp op;
       op.kind = kind;

@@ -8,6 +8,7 @@
 // batch index) stay open until their last holder.  All extents are powers of
 // two, so sizes are exact integers kept as log2.
 #include <algorithm>
+#include <cmath>
 #include <map>
 #include <set>
 #include <tuple>
@@ -30,17 +31,20 @@ using i128 = __int128;
 i128 pow2(int e) { return e >= 120 ? ((i128)1 << 120) : ((i128)1 << e); }
 
 struct Cost {
+  double score;   // randomised objective of the search trials (0 for the plain greedy)
   i128 delta;     // |C| - |A| - |B|
   int32_t c_log2; // log2 |C|
   int32_t f_log2; // log2 of the multiply-add count
   int32_t lo, hi; // ids
   bool operator<(const Cost& o) const {
-    return std::tie(delta, c_log2, f_log2, lo, hi) < std::tie(o.delta, o.c_log2, o.f_log2, o.lo, o.hi);
+    return std::tie(score, delta, c_log2, f_log2, lo, hi) < std::tie(o.score, o.delta, o.c_log2, o.f_log2, o.lo, o.hi);
   }
 };
 
 struct State {
   const tn_network* net;
+  double alpha = 1.0, temp = 0.0;  // search trials: |C| - alpha (|A| + |B|) with Gumbel noise of scale temp
+  mutable uint64_t rng = 0;
   std::vector<LiveTensor> ts;
   std::vector<std::vector<int32_t>> holders;  // per mode: live tensors holding it
   std::vector<char> is_output;
@@ -89,11 +93,20 @@ struct State {
     Cost k;
     result(a, b, tmp, &k.c_log2, &k.f_log2);
     k.delta = pow2(k.c_log2) - pow2(ts[a].log2size) - pow2(ts[b].log2size);
+    k.score = 0.0;
+    if (alpha != 1.0 || temp != 0.0) {
+      const double sa = std::ldexp(1.0, ts[a].log2size), sb = std::ldexp(1.0, ts[b].log2size);
+      const double u = ((double)(splitmix(rng) >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+      const double gumbel = -std::log(-std::log(u));
+      k.score = std::ldexp(1.0, k.c_log2) - alpha * (sa + sb) - temp * (sa + sb) * gumbel;
+    }
     k.lo = std::min(a, b);
     k.hi = std::max(a, b);
     return k;
   }
 };
+
+}  // namespace
 
 uint64_t splitmix(uint64_t& s) {
   uint64_t z = (s += 0x9E3779B97F4A7C15ull);
@@ -102,13 +115,14 @@ uint64_t splitmix(uint64_t& s) {
   return z ^ (z >> 31);
 }
 
-}  // namespace
-
 tn_status plan_order(const tn_network* net, const tn_plan_opts& opts, std::vector<int32_t>& pairs,
-                     double* max_log2_out) {
+                     double* max_log2_out, double alpha, double temp, uint64_t seed) {
   const int T = (int)net->tensors.size();
   State st;
   st.net = net;
+  st.alpha = alpha;
+  st.temp = temp;
+  st.rng = seed;
   st.holders.assign(net->mode_log2.size(), {});
   st.is_output.assign(net->mode_log2.size(), 0);
   for (int m : net->output_modes) st.is_output[m] = 1;

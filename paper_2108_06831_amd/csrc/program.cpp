@@ -133,6 +133,60 @@ std::vector<int32_t> cat(std::vector<int32_t> a, const std::vector<int32_t>& b, 
 
 }  // namespace
 
+std::vector<int32_t> reorder_small_first(const tn_network* net, const std::vector<int32_t>& pairs, int* n_small,
+                                         int64_t* small_region) {
+  const int T = (int)net->tensors.size();
+  const int S = (int)pairs.size() / 2;
+  std::vector<std::vector<int32_t>> modes(T + S);
+  std::vector<int> lsz(T + S, 0);
+  std::vector<int> holders(net->mode_log2.size(), 0);
+  std::vector<char> is_out(net->mode_log2.size(), 0);
+  for (int m : net->output_modes) is_out[m] = 1;
+  for (int t = 0; t < T; ++t) {
+    modes[t] = net->tensors[t].modes;
+    for (int m : modes[t]) { holders[m]++; lsz[t] += net->mode_log2[m]; }
+  }
+  std::vector<char> small(S, 0), early(S, 0);
+  for (int s = 0; s < S; ++s) {
+    const int a = pairs[2 * s], b = pairs[2 * s + 1];
+    auto in = [](const std::vector<int32_t>& v, int m) { return std::find(v.begin(), v.end(), m) != v.end(); };
+    std::vector<int32_t> cm;
+    int f = 0;
+    for (int m : modes[a]) {
+      f += net->mode_log2[m];
+      const bool sh = in(modes[b], m);
+      if (is_out[m] || holders[m] > (sh ? 2 : 1)) cm.push_back(m);
+    }
+    for (int m : modes[b])
+      if (!in(modes[a], m)) { f += net->mode_log2[m]; cm.push_back(m); }
+    for (int m : modes[a]) holders[m]--;
+    for (int m : modes[b]) holders[m]--;
+    for (int m : cm) holders[m]++;
+    modes[T + s] = cm;
+    for (int m : cm) lsz[T + s] += net->mode_log2[m];
+    small[s] = lsz[a] <= kSmallMaxBits && lsz[b] <= kSmallMaxBits && lsz[T + s] <= kSmallMaxBits &&
+               f <= kSmallMaxMacLog2 && (f - lsz[T + s]) <= kSmallMaxBits;
+    early[s] = small[s] && (a < T || early[a - T]) && (b < T || early[b - T]);
+  }
+  std::vector<int> order;
+  for (int s = 0; s < S; ++s)
+    if (early[s]) order.push_back(s);
+  *n_small = (int)order.size();
+  *small_region = 0;
+  for (int s : order) *small_region += ((((int64_t)1 << lsz[T + s]) + 31) & ~(int64_t)31);
+  for (int s = 0; s < S; ++s)
+    if (!early[s]) order.push_back(s);
+  std::vector<int> newid(T + S);
+  for (int t = 0; t < T; ++t) newid[t] = t;
+  for (int i = 0; i < S; ++i) newid[T + order[i]] = T + i;
+  std::vector<int32_t> out(2 * S);
+  for (int i = 0; i < S; ++i) {
+    out[2 * i] = newid[pairs[2 * order[i]]];
+    out[2 * i + 1] = newid[pairs[2 * order[i] + 1]];
+  }
+  return out;
+}
+
 tn_status compile_program(const tn_network* net, tn_path* path) {
   const int T = (int)net->tensors.size();
   const int S = (int)path->pairs.size() / 2;
@@ -158,6 +212,8 @@ tn_status compile_program(const tn_network* net, tn_path* path) {
     for (int m : modes[t]) holders[m]++;
 
   Alloc alloc;
+  alloc.top = alloc.peak = path->small_region;  // [0, small_region): results of the interpreter's steps
+  int64_t small_bump = 0;
   path->steps.assign(S, StepProgram());
   path->step_modes.assign(S, {});
   tn_path_stats& st = path->stats;
@@ -212,7 +268,56 @@ tn_status compile_program(const tn_network* net, tn_path* path) {
     const int nk = nbits[C_K], nm = nbits[g_only], nb = nbits[C_BATCH];
     Loc& C = loc[ic];
     C.elems = c_elems;
-    if (g_bits <= kSkinnyMaxG && nk <= kSkinnyMaxK && nm <= kSkinnyMaxM) {
+    if (s < path->n_small) {
+      P.kind = SK_SMALL;
+      // C's layout: the large operand's, with a gate-sized operand's output bits at the summed
+      // positions when the counts match; else [batch | M | N]
+      const bool skinny_like = g_bits <= kSkinnyMaxG && nk == nm && nk <= kSkinnyMaxK;
+      if (skinny_like) {
+        std::vector<int32_t> klab;
+        for (int p = 0; p < (int)Tt.bits.size(); ++p) {
+          int32_t lab = Tt.bits[Tt.bits.size() - 1 - p];
+          if (cls[lab] == C_K) klab.push_back(lab);
+        }
+        std::vector<int32_t> mlab = filter(G.bits, cls, g_only);
+        std::reverse(mlab.begin(), mlab.end());
+        C.bits = Tt.bits;
+        for (int j = 0; j < nk; ++j) C.bits[Tt.bits.size() - 1 - pos_of(Tt.bits, klab[j])] = mlab[j];
+      } else {
+        C.bits = cat(filter(A.bits, cls, C_BATCH), filter(A.bits, cls, C_M), filter(B.bits, cls, C_N));
+      }
+      if (skinny_like && !Tt.input && Tt.last_use == s && Tt.elems == C.elems) {
+        C.ref = Tt.ref;  // in place (the interpreter reads a whole step before writing it)
+        Tt.ref.buf = -1;
+      } else {
+        C.ref.buf = BUF_WS;
+        C.ref.off = small_bump;
+        small_bump += Alloc::round(C.elems);
+      }
+      SmallStep& d = P.sm;
+      d.a_buf = A.ref.buf == -1 ? BUF_WS : A.ref.buf;
+      d.b_buf = B.ref.buf == -1 ? BUF_WS : B.ref.buf;
+      d.a_off = A.ref.off;
+      d.b_off = B.ref.off;
+      d.c_buf = C.ref.buf;
+      d.c_off = C.ref.off;
+      d.c_bits = (int32_t)C.bits.size();
+      d.pad = 0;
+      for (int p = 0; p < kSmallMaxBits; ++p) d.apos[p] = d.bpos[p] = d.ka[p] = d.kb[p] = -1;
+      for (int p = 0; p < d.c_bits; ++p) {
+        const int32_t lab = C.bits[C.bits.size() - 1 - p];
+        d.apos[p] = (int8_t)pos_of(A.bits, lab);
+        d.bpos[p] = (int8_t)pos_of(B.bits, lab);
+      }
+      int j = 0;
+      for (int32_t lab : A.bits)
+        if (cls[lab] == C_K) {
+          d.ka[j] = (int8_t)pos_of(A.bits, lab);
+          d.kb[j] = (int8_t)pos_of(B.bits, lab);
+          ++j;
+        }
+      d.k_bits = j;
+    } else if (g_bits <= kSkinnyMaxG && nk <= kSkinnyMaxK && nm <= kSkinnyMaxM) {
       P.kind = SK_SKINNY;
       st.n_skinny_steps++;
       SkinnyDesc& d = P.sk;
@@ -382,9 +487,15 @@ tn_status compile_program(const tn_network* net, tn_path* path) {
     path->step_modes[s] = cm;
     for (Loc* X : {&A, &B})
       if (!X->input && X->last_use == s && X->ref.buf == BUF_WS) {
-        alloc.put(X->ref.off, X->elems);
+        // buffers of the interpreter's results are released only once the interpreter has run
+        if (s >= path->n_small) alloc.put(X->ref.off, X->elems);
         X->ref.buf = -1;
       }
+    if (s == path->n_small - 1) {
+      // the interpreter's results that later steps read stay where they are; the rest of
+      // the small region becomes free
+      if (small_bump > path->small_region) return set_error(TN_EINVAL, "internal: small region overflow");
+    }
     st.flops += P.flops;
     st.bytes += P.bytes;
     st.max_intermediate_elems = std::max(st.max_intermediate_elems, (double)C.elems);
@@ -397,7 +508,7 @@ tn_status compile_program(const tn_network* net, tn_path* path) {
     if (r.buf == BUF_WS) return r.off >= 0 && r.off + elems <= alloc.peak;
     return false;
   };
-  for (int s = 0; s < S; ++s) {
+  for (int s = path->n_small; s < S; ++s) {
     const StepProgram& P = path->steps[s];
     const int ia = path->pairs[2 * s], ib = path->pairs[2 * s + 1];
     const int64_t ea = loc[ia].elems, eb = loc[ib].elems, ec = loc[T + s].elems;
@@ -439,6 +550,51 @@ tn_status compile_program(const tn_network* net, tn_path* path) {
         return set_error(TN_EINVAL, "internal: GEMM buffer out of range");
     }
   }
+  for (int s = 0; s < path->n_small; ++s) {
+    const SmallStep& d = path->steps[s].sm;
+    const int ia = path->pairs[2 * s], ib = path->pairs[2 * s + 1];
+    auto buf_ok = [&](int buf, int64_t off, int64_t elems) {
+      if (buf == BUF_IN) return off >= 0 && off + elems <= net->input_elems;
+      if (buf == BUF_WS) return off >= 0 && off + elems <= alloc.peak;
+      return false;
+    };
+    if (d.c_bits > kSmallMaxBits || d.k_bits > kSmallMaxBits || !buf_ok(d.a_buf, d.a_off, loc[ia].elems) ||
+        !buf_ok(d.b_buf, d.b_off, loc[ib].elems) || !buf_ok(d.c_buf, d.c_off, loc[T + s].elems) ||
+        ((int64_t)1 << d.c_bits) != loc[T + s].elems)
+      return set_error(TN_EINVAL, "internal: bad small step");
+    const int abits = (int)loc[ia].bits.size(), bbits = (int)loc[ib].bits.size();
+    for (int p = 0; p < d.c_bits; ++p)
+      if (d.apos[p] >= abits || d.bpos[p] >= bbits || (d.apos[p] < 0 && d.bpos[p] < 0))
+        return set_error(TN_EINVAL, "internal: bad small-step bit map");
+    for (int j = 0; j < d.k_bits; ++j)
+      if (d.ka[j] < 0 || d.ka[j] >= abits || d.kb[j] < 0 || d.kb[j] >= bbits)
+        return set_error(TN_EINVAL, "internal: bad small-step summed bits");
+  }
+  // independent sub-trees of the interpreter's steps -> one work list each
+  path->small_steps.clear();
+  path->small_lists.clear();
+  if (path->n_small > 0) {
+    std::vector<int> consumer(S, -1);
+    for (int s = 0; s < S; ++s)
+      for (int k = 0; k < 2; ++k) {
+        const int id = path->pairs[2 * s + k];
+        if (id >= T) consumer[id - T] = s;
+      }
+    std::vector<int> root(path->n_small);
+    for (int s = path->n_small - 1; s >= 0; --s) {
+      const int c = consumer[s];
+      root[s] = (c >= 0 && c < path->n_small) ? root[c] : s;
+    }
+    std::map<int, std::vector<int>> trees;
+    for (int s = 0; s < path->n_small; ++s) trees[root[s]].push_back(s);
+    path->small_lists.push_back(0);
+    for (auto& kv : trees) {
+      for (int s : kv.second) path->small_steps.push_back(path->steps[s].sm);
+      path->small_lists.push_back((int32_t)path->small_steps.size());
+    }
+  }
+  st.n_small_steps = path->n_small;
+  st.n_small_lists = path->small_lists.empty() ? 0 : (int32_t)path->small_lists.size() - 1;
   const int last = S > 0 ? T + S - 1 : 0;
   if (S == 0 && T != 1) return set_error(TN_EINVAL, "empty path for a network of several tensors");
   if (S == 0) {
@@ -451,6 +607,37 @@ tn_status compile_program(const tn_network* net, tn_path* path) {
   path->ws_elems = std::max<int64_t>(alloc.peak, 32);
   path->n_inputs = T;
   return TN_OK;
+}
+
+// A coarse model of the program's run time on MI355X, used to choose between
+// orders: launch overhead per kernel, streaming kernels at a sustained HBM rate,
+// permutes at their measured rate, matrix products at the sustained FP32
+// matrix-core rate scaled down for tiles the shape leaves partly empty.
+double modeled_seconds(const tn_path* path) {
+  constexpr double kLaunch = 5e-6, kHbm = 6.0e12, kPerm = 1.6e12, kMfma = 95e12;
+  double t = 0;
+  if (path->n_small > 0) {
+    size_t longest = 0;
+    for (size_t i = 0; i + 1 < path->small_lists.size(); ++i)
+      longest = std::max(longest, (size_t)(path->small_lists[i + 1] - path->small_lists[i]));
+    t += kLaunch + 1.5e-6 * (double)longest;
+  }
+  for (const StepProgram& P : path->steps) {
+    if (P.kind == SK_SMALL) continue;
+    t += kLaunch;
+    for (const PermuteDesc& pd : P.pre) t += kLaunch + 16.0 * std::ldexp(1.0, pd.bits) / kPerm;
+    if (P.kind == SK_SKINNY) {
+      t += P.bytes / kHbm;
+    } else {
+      const GemmDesc& g = P.gm;
+      const double tiles = (double)((g.M + 127) / 128) * (double)((g.N + 63) / 64) * (double)g.batch;
+      const double eff = std::min(1.0, g.M / 128.0) * std::min(1.0, g.N / 64.0) * std::min(1.0, g.K / 32.0) *
+                         std::min(1.0, tiles / 256.0);
+      const double bytes = 8.0 * (double)g.batch * (double)(g.M * g.K + g.K * g.N + g.M * g.N);
+      t += std::max(P.flops / (kMfma * std::max(eff, 1e-3)), bytes / kHbm);
+    }
+  }
+  return t;
 }
 
 }  // namespace tnq
@@ -467,18 +654,69 @@ extern "C" tn_status tn_plan_path(const tn_network* net, const tn_plan_opts* opt
   o.max_log2_intermediate = 0;
   o.seed = 0;
   if (opts) o = *opts;
-  if (o.kind < TN_PATH_GREEDY || o.kind > TN_PATH_RANDOM) return set_error(TN_EINVAL, "unknown path kind");
+  if (o.kind < TN_PATH_GREEDY || o.kind > TN_PATH_SEARCH) return set_error(TN_EINVAL, "unknown path kind");
   auto t0 = std::chrono::steady_clock::now();
-  tn_path* p = new tn_path();
+  tn_path* p = nullptr;
   double max_log2 = 0;
-  tn_status s = plan_order(net, o, p->pairs, &max_log2);
-  if (s != TN_OK) {
-    delete p;
-    return set_error(s, "largest intermediate 2^" + std::to_string((int)max_log2) + " exceeds the cap 2^" +
-                            std::to_string(o.max_log2_intermediate > 0 ? o.max_log2_intermediate : 40));
+  const std::string cap_msg =
+      " exceeds the cap 2^" + std::to_string(o.max_log2_intermediate > 0 ? o.max_log2_intermediate : 40);
+  if (o.kind != TN_PATH_SEARCH) {
+    p = new tn_path();
+    tn_status s = plan_order(net, o, p->pairs, &max_log2);
+    if (s != TN_OK) {
+      delete p;
+      return set_error(s, "largest intermediate 2^" + std::to_string((int)max_log2) + cap_msg);
+    }
+    p->pairs = reorder_small_first(net, p->pairs, &p->n_small, &p->small_region);
+    s = compile_program(net, p);
+    if (s != TN_OK) { delete p; return s; }
+    p->stats.modeled_seconds = modeled_seconds(p);
+  } else {
+    const int trials = o.trials > 0 ? o.trials : 64;
+    uint64_t rng = o.seed ^ 0x3f5a1c0de2108ull;
+    double best_t = 0;
+    int min_log2 = 1 << 20;
+    for (int trial = -2; trial < trials; ++trial) {
+      tn_plan_opts oo = o;
+      double alpha = 1.0, temp = 0.0;
+      uint64_t seed = splitmix(rng);
+      if (trial == -2) {
+        oo.kind = TN_PATH_GREEDY;
+      } else if (trial == -1) {
+        oo.kind = TN_PATH_SEQUENTIAL;
+      } else {
+        oo.kind = TN_PATH_GREEDY;
+        alpha = 0.25 + 1.75 * (double)(splitmix(rng) >> 11) / 9007199254740992.0;
+        temp = (double)(splitmix(rng) >> 11) / 9007199254740992.0;
+        temp = temp * temp;
+      }
+      tn_path* q = new tn_path();
+      double ml = 0;
+      tn_status s = plan_order(net, oo, q->pairs, &ml, alpha, temp, seed);
+      min_log2 = std::min(min_log2, (int)ml);
+      if (s == TN_OK) {
+        q->pairs = reorder_small_first(net, q->pairs, &q->n_small, &q->small_region);
+        s = compile_program(net, q);
+      }
+      if (s != TN_OK) {
+        delete q;
+        if (s != TN_ELIMIT) return s;
+        continue;
+      }
+      const double t = modeled_seconds(q);
+      q->stats.modeled_seconds = t;
+      if (!p || t < best_t) {
+        delete p;
+        p = q;
+        best_t = t;
+      } else {
+        delete q;
+      }
+    }
+    if (!p) return set_error(TN_ELIMIT, "every searched order's largest intermediate (at best 2^" +
+                                            std::to_string(min_log2) + ")" + cap_msg);
+    clear_error();
   }
-  s = compile_program(net, p);
-  if (s != TN_OK) { delete p; return s; }
   auto t1 = std::chrono::steady_clock::now();
   p->stats.plan_seconds = std::chrono::duration<double>(t1 - t0).count();
   if (stats_out) *stats_out = p->stats;

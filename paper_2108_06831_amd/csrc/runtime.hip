@@ -142,7 +142,39 @@ void device_release_network(tn_network* net) {
   net->dev = nullptr;
 }
 
-void device_release_path(tn_path* path) { path->dev = nullptr; }
+struct DevPath {
+  int device = -1;
+  SmallStep* steps = nullptr;
+  int32_t* lists = nullptr;
+};
+
+static tn_status ensure_path_device(tn_path* path, DevPath** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  DevPath* d = (DevPath*)path->dev;
+  if (d && d->device == dev) { *out = d; return TN_OK; }
+  if (d) device_release_path(path);
+  d = new DevPath();
+  d->device = dev;
+  path->dev = d;
+  HIP_TRY(upload(&d->steps, path->small_steps));
+  HIP_TRY(upload(&d->lists, path->small_lists));
+  *out = d;
+  return TN_OK;
+}
+
+void device_release_path(tn_path* path) {
+  DevPath* d = (DevPath*)path->dev;
+  if (!d) return;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(d->device);
+  (void)hipFree(d->steps);
+  (void)hipFree(d->lists);
+  (void)hipSetDevice(cur);
+  delete d;
+  path->dev = nullptr;
+}
 
 // ---------------------------------------------------------------------------
 // workspace layout
@@ -195,8 +227,27 @@ static float2* resolve(const Bases& b, const BufRef& r, int64_t* bs) {
   }
 }
 
-static tn_status run_steps(hipStream_t s, const tn_path* path, const Bases& B, int batch, int precision) {
-  for (const StepProgram& P : path->steps) {
+static tn_status run_steps(hipStream_t s, tn_path* path, const Bases& B, int batch, int precision) {
+  if (path->n_small > 0) {
+    DevPath* dp;
+    tn_status st = ensure_path_device(path, &dp);
+    if (st != TN_OK) return st;
+    int64_t ibs, wbs;
+    BufRef ri, rw;
+    ri.buf = BUF_IN;
+    rw.buf = BUF_WS;
+    float2* ip = resolve(B, ri, &ibs);
+    float2* wp = resolve(B, rw, &wbs);
+    if (B.pair_a) return set_error(TN_EINVAL, "internal: interpreter steps in a single pairwise contraction");
+    hipEvent_t ev = prof_start(s);
+    HIP_TRY(launch_small_steps(s, dp->steps, dp->lists, (int)path->small_lists.size() - 1, ip, ibs, wp, wbs, batch,
+                               precision));
+    double fl = 0, by = 0;
+    for (int i = 0; i < path->n_small; ++i) { fl += path->steps[i].flops; by += path->steps[i].bytes; }
+    prof_stop(s, ev, TN_KERNEL_FUSED, by * batch, fl * batch);
+  }
+  for (size_t si = path->n_small; si < path->steps.size(); ++si) {
+    const StepProgram& P = path->steps[si];
     for (const PermuteDesc& pd : P.pre) {
       int64_t ibs, obs;
       float2* ip = resolve(B, pd.in, &ibs);

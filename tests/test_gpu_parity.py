@@ -27,14 +27,14 @@ def statevector_gpu(circ, kind="greedy", fuse=False, precision="c64", params=Non
     import torch
     from paper_2108_06831_amd import Network, contract_path
     net = Network.from_circuit(circ, fuse=fuse)
-    path = net.plan(kind)
+    path = net.plan(kind, trials=32)
     out = contract_path(net, path, params=params, batch=batch, precision=precision)
     torch.cuda.synchronize()
     return out.cpu().numpy()
 
 
-@pytest.mark.parametrize("kind", ["greedy", "sequential", "random"])
-@pytest.mark.parametrize("fuse", [False, True])
+@pytest.mark.parametrize("kind", ["greedy", "sequential", "random", "search"])
+@pytest.mark.parametrize("fuse", [False, "dense", "split"])
 def test_config0_statevector(kind, fuse):
     circ = workloads.config0()
     print(f"config0 kind={kind} fuse={fuse}", flush=True)
@@ -59,8 +59,8 @@ def test_random_circuits(seed):
     n = int(rng.integers(1, 11))
     circ = workloads.random_circuit(n, 60, rng)
     print(f"random circuit seed={seed} n={n}", flush=True)
-    for kind in ("greedy", "sequential"):
-        for fuse in (False, True):
+    for kind in ("greedy", "sequential", "search"):
+        for fuse in (False, "dense", "split"):
             got = statevector_gpu(circ, kind, fuse)[0]
             assert relerr(got, oracle.statevector(circ)) < C64_TOL
 
@@ -87,16 +87,27 @@ def test_ghz_and_qft_closed_forms():
     assert relerr(got, want) < C64_TOL
 
 
-@pytest.mark.parametrize("precision,tol", [("c64", C64_TOL), ("bf16x3", BF16X3_TOL)])
-def test_config1_full_statevector(precision, tol):
+_C1_REF = {}
+
+
+def config1_reference():
+    if "psi" not in _C1_REF:
+        _C1_REF["psi"] = oracle.statevector(workloads.config1())
+    return _C1_REF["psi"]
+
+
+@pytest.mark.parametrize("kind,fuse,precision,tol", [
+    ("search", "split", "c64", C64_TOL), ("search", "split", "bf16x3", BF16X3_TOL),
+    ("greedy", "dense", "c64", C64_TOL), ("sequential", "split", "c64", C64_TOL)])
+def test_config1_full_statevector(kind, fuse, precision, tol):
     """24 qubits, depth 16, 2-qubit fusion: the full 2^24 state."""
     circ = workloads.config1()
-    print(f"config1 {precision}: oracle ...", flush=True)
-    want = oracle.statevector(circ)
+    print(f"config1 {kind} {fuse} {precision}: oracle ...", flush=True)
+    want = config1_reference()
     print("config1: gpu ...", flush=True)
-    got = statevector_gpu(circ, "greedy", fuse=True, precision=precision)[0]
+    got = statevector_gpu(circ, kind, fuse=fuse, precision=precision)[0]
     e = relerr(got, want)
-    print(f"config1 {precision} rel err {e:.3e} max abs {np.max(np.abs(got - want)):.2e}", flush=True)
+    print(f"config1 {kind} {fuse} {precision} rel err {e:.3e} max abs {np.max(np.abs(got - want)):.2e}", flush=True)
     assert e < tol
 
 

@@ -38,10 +38,38 @@ def test_network_structure_config0():
 
 
 def test_network_structure_config1_fused():
-    net = Network.from_circuit(workloads.config1(), fuse=True)
+    net = Network.from_circuit(workloads.config1(), fuse="dense")
     info = net.info()
     assert info["n_tensors"] == 24 + 184
     assert all(len(net.tensor(t)[0]) == 4 for t in range(24, 24 + 184))
+    # split form: every CZ block becomes two 3-leg halves [bond, out, in] sharing a bond of extent 2
+    net = Network.from_circuit(workloads.config1(), fuse="split")
+    assert net.info()["n_tensors"] == 24 + 2 * 184
+    for t in range(24, 24 + 2 * 184, 2):
+        (ma, ea), (mb, eb) = net.tensor(t), net.tensor(t + 1)
+        assert ea == eb == [2, 2, 2] and ma[0] == mb[0]
+
+
+@pytest.mark.parametrize("fuse", ["dense", "split"])
+def test_fused_networks_match_oracle(fuse):
+    rng = np.random.default_rng(77)
+    kinds = ["U3", "RX", "RZ", "H", "SX", "CZ", "CNOT", "CPHASE", "ZZPHASE", "SWAP"]
+    for trial in range(6):
+        circ = workloads.random_circuit(6, 50, rng, kinds=kinds)
+        net = Network.from_circuit(circ, fuse=fuse)
+        for kind in ("greedy", "search"):
+            got = pathexec.execute(net, net.plan(kind, trials=8)).reshape(-1)
+            assert np.max(np.abs(got - oracle.statevector(circ))) < 1e-12
+
+
+def test_small_steps_come_first_and_form_independent_lists():
+    net = Network.from_circuit(workloads.config1(), fuse=True)
+    path = net.plan("search", trials=8)
+    st = path.stats
+    assert st["n_small_steps"] > 0 and st["n_small_lists"] >= 1
+    kinds = [path.step(s)["kind"] for s in range(st["n_steps"])]
+    assert kinds[: st["n_small_steps"]] == ["small"] * st["n_small_steps"]
+    assert "small" not in kinds[st["n_small_steps"]:]
 
 
 def test_amplitude_network_has_projectors():
@@ -129,7 +157,7 @@ def test_plan_stats_and_step_views():
     st = path.stats
     assert st["n_steps"] == net.info()["n_tensors"] - 1
     assert st["max_intermediate_elems"] == 1024  # the statevector is the largest tensor
-    assert st["n_skinny_steps"] + st["n_gemm_steps"] == st["n_steps"]
+    assert st["n_skinny_steps"] + st["n_gemm_steps"] + st["n_small_steps"] == st["n_steps"]
     tot = 0.0
     for s in range(st["n_steps"]):
         b, m, n, k = path.step(s)["bmnk"]
