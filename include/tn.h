@@ -138,6 +138,8 @@ typedef struct {
   int32_t n_skinny_steps;        /* steps executed by the small-operand streaming kernel */
   int32_t n_small_steps;         /* leading small steps run together by one interpreter launch */
   int32_t n_small_lists;         /* independent work lists of that launch (one workgroup each) */
+  int32_t n_sweep_steps;         /* gate-sized steps on one large tensor executed by fused streaming passes */
+  int32_t n_sweep_passes;        /* those passes (each reads and writes the tensor once) */
 } tn_path_stats;
 
 typedef struct tn_network tn_network;
@@ -291,7 +293,8 @@ tn_status tn_contract_pair(void* stream, int32_t precision, const void* a, int32
  */
 typedef enum {
   TN_KERNEL_MATERIALIZE = 0, TN_KERNEL_SKINNY = 1, TN_KERNEL_PERMUTE = 2, TN_KERNEL_GEMM = 3,
-  TN_KERNEL_REDUCE = 4, TN_KERNEL_COPY = 5, TN_KERNEL_ADJOINT = 6, TN_KERNEL_FUSED = 7, TN_KERNEL_KINDS = 8
+  TN_KERNEL_REDUCE = 4, TN_KERNEL_COPY = 5, TN_KERNEL_ADJOINT = 6, TN_KERNEL_INTERP = 7, TN_KERNEL_SWEEP = 8,
+  TN_KERNEL_KINDS = 9
 } tn_kernel_kind;
 typedef struct {
   int32_t kind;       /* tn_kernel_kind */

@@ -47,7 +47,8 @@ class tn_path_stats(ctypes.Structure):
                 ("modeled_seconds", ctypes.c_double),
                 ("n_steps", ctypes.c_int32), ("n_permutes", ctypes.c_int32), ("n_gemm_steps", ctypes.c_int32),
                 ("n_skinny_steps", ctypes.c_int32), ("n_small_steps", ctypes.c_int32),
-                ("n_small_lists", ctypes.c_int32)]
+                ("n_small_lists", ctypes.c_int32), ("n_sweep_steps", ctypes.c_int32),
+                ("n_sweep_passes", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -67,7 +68,7 @@ EXPORTS = [
     "tn_last_error", "tn_version", "tn_profile_enable", "tn_profile_read", "tn_profile_reset",
 ]
 
-KERNEL_KINDS = ["materialize", "skinny", "permute", "gemm", "reduce", "copy", "adjoint", "fused"]
+KERNEL_KINDS = ["materialize", "skinny", "permute", "gemm", "reduce", "copy", "adjoint", "interp", "sweep"]
 
 
 class tn_kernel_profile(ctypes.Structure):

@@ -76,7 +76,7 @@ namespace tnq {
 // ---------------------------------------------------------------------------
 // Compiled program
 // ---------------------------------------------------------------------------
-enum BufId { BUF_IN = 0, BUF_WS = 1, BUF_OUT = 2, BUF_AUX = 3 };
+enum BufId { BUF_IN = 0, BUF_WS = 1, BUF_OUT = 2, BUF_AUX = 3, BUF_LDS0 = 4, BUF_LDS1 = 5 };
 
 struct BufRef {
   int32_t buf = BUF_WS;
@@ -98,6 +98,47 @@ struct SkinnyDesc {
   int64_t kofs[1 << kSkinnyMaxK];   // offset in T of summed index k
   int64_t mofs[1 << kSkinnyMaxM];   // offset in C of output index m
   int32_t gidx[1 << kSkinnyMaxG];   // G element of (b, m, k), b slowest
+  int32_t bt_pos[kSkinnyMaxG];      // position in T of G's batch bit j
+  int32_t g_unit;                   // G is a diagonal gate whose entries all have modulus one
+};
+
+// Fused streaming of a chain of gate-sized steps on one large tensor: the
+// chain is split into passes; a pass keeps a chunk of 2^l elements (the bits
+// `lpos`, ascending, always including the lowest bits) in LDS and applies all
+// its gates there, so each pass reads and writes the tensor once.
+constexpr int kSweepMaxLocal = 12;
+constexpr int kSweepMinLocal = 8;
+struct SweepGateDesc {
+  int32_t diag;          // 0: dense gate on n local bits (G[m][k]); 1: diagonal factor G[b] on n bits
+  int32_t n;             // 1 or 2
+  int32_t lidx[2];       // local bit index of bit j of the gate's index; a diagonal gate's bit outside
+                         // the chunk is -(address position + 1)
+  int32_t rb[2];         // dense gates: index in the segment's register bits of bit j
+  int32_t unit;          // diagonal with unit-modulus entries: applied as accumulated phase angles
+  int32_t g_buf;
+  int32_t pad;
+  int64_t g_off;
+  int32_t gidx[16];      // element of G for (m, k) (dense, m*2^n + k) or b (diagonal)
+};
+// Inside a pass, gates run in segments: a segment names four local bits
+// (`rbits`, indices into lpos) that each thread holds in registers (16
+// elements per thread); its dense gates act only on those bits, its diagonal
+// gates on any bits.  Between segments the chunk goes through LDS once.
+struct SweepSegment {
+  int8_t rbits[4];
+  int32_t first_gate, n_gates;
+};
+struct SweepPass {
+  int32_t l;
+  int8_t lpos[kSweepMaxLocal];
+  int32_t first_gate, n_gates;
+  int32_t first_seg, n_segs;
+};
+struct SweepChain {
+  BufRef in, out;
+  int32_t bits;
+  int32_t first_pass, n_passes;
+  int32_t n_steps;
 };
 
 struct PermuteDesc {
@@ -106,11 +147,21 @@ struct PermuteDesc {
   int32_t dst[64];              // input bit p goes to output bit dst[p]
 };
 
+// Batched complex product over arbitrary bit layouts: bit j of the batch, m,
+// n or k index sits at address position x_y[j] of operand x (no permute
+// kernel; the product reads and writes through per-tile deposit tables).
+constexpr int kGemmMaxBits = 40;
 struct GemmDesc {
   BufRef a, b, c;
   int64_t batch, M, N, K;
-  int32_t a_kfast;  // A stored [batch][M][K] (1) or [batch][K][M] (0)
-  int32_t b_nfast;  // B stored [batch][K][N] (1) or [batch][N][K] (0)
+  int32_t nbb, nbm, nbn, nbk;  // bit counts of the batch, m, n, k indices
+  int32_t a_kfast;  // A tile loads walk k fastest (A's lowest m/k address bit is a k bit)
+  int32_t b_nfast;  // B tile loads walk n fastest
+  int8_t a_b[kGemmMaxBits], a_m[kGemmMaxBits], a_k[kGemmMaxBits];
+  int8_t b_b[kGemmMaxBits], b_k[kGemmMaxBits], b_n[kGemmMaxBits];
+  int8_t c_b[kGemmMaxBits], c_m[kGemmMaxBits], c_n[kGemmMaxBits];
+  int32_t split;  // > 1: K is cut into `split` ranges whose partial products land in `tmp` and are summed
+  BufRef tmp;
 };
 
 // A small step executed inside the interpreter kernel: every operand and the
@@ -118,9 +169,11 @@ struct GemmDesc {
 // B's bit bpos[p] (-1: absent); summed bit j sits at A bit ka[j] and B bit kb[j].
 constexpr int kSmallMaxBits = 12;
 constexpr int kSmallMaxMacLog2 = 20;
+constexpr int kSmallDescCache = 128;  // step descriptors staged in LDS at a time
 struct SmallStep {
-  int32_t a_buf, b_buf, c_buf;
-  int32_t c_bits, k_bits, pad;
+  int32_t a_buf, b_buf, c_buf;  // BUF_IN / BUF_WS, or an LDS slot for a result the next step consumes
+  int32_t c_bits, k_bits;
+  int32_t alias;                // C overwrites an operand in memory: read the whole step before writing
   int64_t a_off, b_off, c_off;
   int8_t apos[kSmallMaxBits], bpos[kSmallMaxBits];
   int8_t ka[kSmallMaxBits], kb[kSmallMaxBits];
@@ -130,6 +183,7 @@ enum StepKind { SK_SKINNY = 0, SK_GEMM = 1, SK_SMALL = 2 };
 
 struct StepProgram {
   int32_t kind;
+  int32_t chain = -1;  // >= 0: first step of fused chain `chain`; -2: inside a chain (skipped)
   SmallStep sm;
   std::vector<PermuteDesc> pre;  // operand permutes before the product
   SkinnyDesc sk;
@@ -155,6 +209,11 @@ struct tn_path {
   std::vector<tnq::SmallStep> small_steps;   // grouped by work list
   std::vector<int32_t> small_lists;          // offsets into small_steps, size n_lists + 1
   int64_t small_region = 0;                  // workspace elements reserved for their results
+  // fused streaming chains
+  std::vector<tnq::SweepChain> chains;
+  std::vector<tnq::SweepPass> passes;
+  std::vector<tnq::SweepSegment> segments;
+  std::vector<tnq::SweepGateDesc> sweep_gates;
   tn_path_stats stats{};
   void* dev = nullptr;   // device-side cache
 };
@@ -166,7 +225,8 @@ tn_status plan_order(const tn_network* net, const tn_plan_opts& opts, std::vecto
 uint64_t splitmix(uint64_t& s);
 double modeled_seconds(const tn_path* path);
 // program.cpp
-tn_status compile_program(const tn_network* net, tn_path* path);
+tn_status compile_program(const tn_network* net, tn_path* path, const std::vector<int32_t>* final_layout = nullptr);
+std::vector<int32_t> output_layout(const tn_network* net);
 // moves every step that is small and depends only on inputs or such steps to the front
 std::vector<int32_t> reorder_small_first(const tn_network* net, const std::vector<int32_t>& pairs, int* n_small,
                                          int64_t* small_region);

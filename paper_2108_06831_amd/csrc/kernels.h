@@ -31,8 +31,9 @@ hipError_t launch_permute(hipStream_t s, const PermuteDesc& d, const float2* in,
                           int64_t out_bs, int batch);
 
 // C[b] = A[b] B[b] on complex64 with FP32 MFMA accumulation.
+// With d.split > 1 the partial products go to `tmp` ([split][C], same layout as C) and are summed into C.
 hipError_t launch_gemm(hipStream_t s, const GemmDesc& d, const float2* a, int64_t a_bs, const float2* b, int64_t b_bs,
-                       float2* c, int64_t c_bs, int batch, int precision);
+                       float2* c, int64_t c_bs, float2* tmp, int64_t tmp_bs, int batch, int precision);
 
 // Expectation of a diagonal Z-string observable: out[z] = sum_x |psi_z[x]|^2 D(x),
 // FP64 accumulation (block partials + a fixed-order second pass).
@@ -42,7 +43,8 @@ struct ZTerms {
   uint64_t mask[kMaxTerms];  // address-bit masks
   double coeff[kMaxTerms];
 };
-constexpr int kReduceBlocks = 512;
+constexpr int kReduceBlocks = 512;   // blocks of the adjoint step (one partial per block and gate)
+constexpr int kExpectBlocks = 4096;  // blocks of the expectation reduction
 hipError_t launch_expectation(hipStream_t s, const float2* psi, int64_t psi_bs, int64_t n_elems, const ZTerms& terms,
                               int batch, double* partial, double* out, int64_t out_stride);
 
@@ -51,6 +53,12 @@ hipError_t launch_expectation(hipStream_t s, const float2* psi, int64_t psi_bs, 
 // workgroup (w, batch item).
 hipError_t launch_small_steps(hipStream_t s, const SmallStep* steps, const int32_t* list_off, int n_lists,
                               float2* in, int64_t in_bs, float2* ws, int64_t ws_bs, int batch, int precision);
+
+// One fused streaming pass over a 2^bits tensor (see SweepPass).
+hipError_t launch_sweep_pass(hipStream_t s, const SweepPass& ps, int bits, const SweepGateDesc* gates_dev,
+                             const SweepSegment* segs_dev, const float2* in, int64_t in_bs, float2* out,
+                             int64_t out_bs, float2* IN, int64_t IN_bs, float2* WS, int64_t WS_bs, int batch,
+                             int precision);
 
 // Contiguous copy of `n` complex64 per batch item.
 hipError_t launch_copy(hipStream_t s, const float2* in, int64_t in_bs, float2* out, int64_t out_bs, int64_t n,

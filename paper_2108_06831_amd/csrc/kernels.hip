@@ -237,50 +237,64 @@ constexpr int kSmallPerThread = (1 << kSmallMaxBits) / kThreads;
 template <int PREC>
 __global__ __launch_bounds__(kThreads) void k_small_steps(const SmallStep* steps, const int32_t* list_off,
                                                           float2* in, int64_t in_bs, float2* ws, int64_t ws_bs) {
-  __shared__ SmallStep st;
+  __shared__ SmallStep desc[kSmallDescCache];
+  __shared__ float2 slot[2][1 << kSmallMaxBits];
   const int w = blockIdx.x, z = blockIdx.y;
   float2* IN = in + (int64_t)z * in_bs;
   float2* WS = ws + (int64_t)z * ws_bs;
+  auto ptr = [&](int buf, int64_t off) -> float2* {
+    return buf == BUF_LDS0 ? slot[0] : buf == BUF_LDS1 ? slot[1] : (buf == BUF_IN ? IN : WS) + off;
+  };
   const int s0 = list_off[w], s1 = list_off[w + 1];
-  for (int s = s0; s < s1; ++s) {
-    if (threadIdx.x == 0) st = steps[s];
+  for (int cb = s0; cb < s1; cb += kSmallDescCache) {
+    const int ce = min(s1, cb + kSmallDescCache);
+    {
+      // stage this chunk of descriptors in LDS (copied as 32-bit words)
+      const int words = (ce - cb) * (int)(sizeof(SmallStep) / 4);
+      const uint32_t* src = reinterpret_cast<const uint32_t*>(steps + cb);
+      uint32_t* dst = reinterpret_cast<uint32_t*>(desc);
+      for (int i = threadIdx.x; i < words; i += kThreads) dst[i] = src[i];
+    }
     __syncthreads();
-    const float2* A = (st.a_buf == BUF_IN ? IN : WS) + st.a_off;
-    const float2* B = (st.b_buf == BUF_IN ? IN : WS) + st.b_off;
-    float2* C = (st.c_buf == BUF_IN ? IN : WS) + st.c_off;
-    const int n_out = 1 << st.c_bits, n_k = 1 << st.k_bits;
-    float2 res[kSmallPerThread];
+    for (int s = cb; s < ce; ++s) {
+      const SmallStep& st = desc[s - cb];
+      const float2* A = ptr(st.a_buf, st.a_off);
+      const float2* B = ptr(st.b_buf, st.b_off);
+      float2* C = ptr(st.c_buf, st.c_off);
+      const int n_out = 1 << st.c_bits, n_k = 1 << st.k_bits;
+      float2 res[kSmallPerThread];
 #pragma unroll
-    for (int r = 0; r < kSmallPerThread; ++r) {
-      const int o = threadIdx.x + r * kThreads;
-      res[r] = f2(0.f, 0.f);
-      if (o < n_out) {
-        int ab = 0, bb = 0;
-        for (int p = 0; p < st.c_bits; ++p)
-          if ((o >> p) & 1) {
-            if (st.apos[p] >= 0) ab |= 1 << st.apos[p];
-            if (st.bpos[p] >= 0) bb |= 1 << st.bpos[p];
-          }
-        float2 acc = f2(0.f, 0.f);
-        for (int k = 0; k < n_k; ++k) {
-          int ao = ab, bo = bb;
-          for (int j = 0; j < st.k_bits; ++j)
-            if ((k >> j) & 1) {
-              ao |= 1 << st.ka[j];
-              bo |= 1 << st.kb[j];
+      for (int r = 0; r < kSmallPerThread; ++r) {
+        const int o = threadIdx.x + r * kThreads;
+        res[r] = f2(0.f, 0.f);
+        if (o < n_out) {
+          int ab = 0, bb = 0;
+          for (int p = 0; p < st.c_bits; ++p)
+            if ((o >> p) & 1) {
+              if (st.apos[p] >= 0) ab |= 1 << st.apos[p];
+              if (st.bpos[p] >= 0) bb |= 1 << st.bpos[p];
             }
-          acc = cmac<PREC>(acc, A[ao], B[bo]);
+          float2 acc = f2(0.f, 0.f);
+          for (int k = 0; k < n_k; ++k) {
+            int ao = ab, bo = bb;
+            for (int j = 0; j < st.k_bits; ++j)
+              if ((k >> j) & 1) {
+                ao |= 1 << st.ka[j];
+                bo |= 1 << st.kb[j];
+              }
+            acc = cmac<PREC>(acc, A[ao], B[bo]);
+          }
+          res[r] = acc;
         }
-        res[r] = acc;
       }
-    }
-    __syncthreads();
+      if (st.alias) __syncthreads();  // every read of the step before any write over an operand
 #pragma unroll
-    for (int r = 0; r < kSmallPerThread; ++r) {
-      const int o = threadIdx.x + r * kThreads;
-      if (o < n_out) C[o] = res[r];
+      for (int r = 0; r < kSmallPerThread; ++r) {
+        const int o = threadIdx.x + r * kThreads;
+        if (o < n_out) C[o] = res[r];
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
 }
 
@@ -293,6 +307,187 @@ hipError_t launch_small_steps(hipStream_t s, const SmallStep* steps, const int32
   else
     hipLaunchKernelGGL(k_small_steps<TN_PREC_C64>, dim3(n_lists, batch), dim3(kThreads), 0, s, steps, list_off, in,
                        in_bs, ws, ws_bs);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Fused streaming pass: a chunk of 2^l elements (address bits lpos, the five
+// lowest always among them so that loads and stores move 256-byte runs) is
+// staged in LDS and every gate of the pass is applied to it before it is
+// written back: one HBM read and one write for the whole pass.  Gates run in
+// segments: each thread holds the 16 elements that differ in the segment's
+// four register bits, applies the segment's gates in registers, and the chunk
+// goes through LDS only between segments.
+// ---------------------------------------------------------------------------
+struct SweepPassArgs {
+  const float2* in;
+  float2* out;
+  int64_t in_bs, out_bs;
+  float2* IN;
+  float2* WS;
+  int64_t IN_bs, WS_bs;
+  const SweepGateDesc* gates;
+  const SweepSegment* segs;
+  int32_t n_segs, l, n_rest, pad;
+  int8_t lpos[kSweepMaxLocal];
+  int8_t rest[64];
+};
+
+__device__ inline int64_t ins0(int64_t x, int p) { return ((x >> p) << (p + 1)) | (x & (((int64_t)1 << p) - 1)); }
+__device__ inline int lds_phys(int i) { return i + (i >> 5); }
+
+template <int PREC, int U>
+__device__ inline void reg_apply1(float2 (&x)[16], const float2* g) {
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    if (r & (1 << U)) continue;
+    const int r1 = r | (1 << U);
+    const float2 a = x[r], b = x[r1];
+    x[r] = cmac<PREC>(cmac<PREC>(f2(0.f, 0.f), g[0], a), g[1], b);
+    x[r1] = cmac<PREC>(cmac<PREC>(f2(0.f, 0.f), g[2], a), g[3], b);
+  }
+}
+
+template <int PREC, int U0, int U1>
+__device__ inline void reg_apply2(float2 (&x)[16], const float2* g) {
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    if (r & ((1 << U0) | (1 << U1))) continue;
+    const int id[4] = {r, r | (1 << U0), r | (1 << U1), r | (1 << U0) | (1 << U1)};
+    float2 v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = x[id[k]];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      float2 acc = f2(0.f, 0.f);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) acc = cmac<PREC>(acc, g[4 * m + k], v[k]);
+      x[id[m]] = acc;
+    }
+  }
+}
+
+template <int PREC>
+__global__ __launch_bounds__(kThreads) void k_sweep_pass(SweepPassArgs a) {
+  __shared__ float2 buf[(1 << kSweepMaxLocal) + (1 << (kSweepMaxLocal - 5))];
+  __shared__ int64_t dep_hi[1 << (kSweepMaxLocal - 5)];
+  const int z = blockIdx.y;
+  const int64_t c = blockIdx.x;
+  const int L = 1 << a.l;
+  const int nt = blockDim.x, tid = threadIdx.x;
+  int64_t base = 0;
+  for (int j = 0; j < a.n_rest; ++j)
+    if ((c >> j) & 1) base |= (int64_t)1 << a.rest[j];
+  for (int h = tid; h < (L >> 5); h += nt) {
+    int64_t d = 0;
+    for (int j = 5; j < a.l; ++j)
+      if ((h >> (j - 5)) & 1) d |= (int64_t)1 << a.lpos[j];
+    dep_hi[h] = d;
+  }
+  __syncthreads();
+  const float2* in = a.in + (int64_t)z * a.in_bs;
+  float2* out = a.out + (int64_t)z * a.out_bs;
+  const float2* INz = a.IN + (int64_t)z * a.IN_bs;
+  const float2* WSz = a.WS + (int64_t)z * a.WS_bs;
+  for (int i = tid; i < L; i += nt) buf[lds_phys(i)] = in[base | (i & 31) | dep_hi[i >> 5]];
+  __syncthreads();
+  for (int sg = 0; sg < a.n_segs; ++sg) {
+    const SweepSegment seg = a.segs[sg];
+    // thread index bits -> the local bits outside the register set
+    int ob = 0;
+    {
+      int tb = 0;
+      for (int b = 0; b < a.l; ++b) {
+        if (b == seg.rbits[0] || b == seg.rbits[1] || b == seg.rbits[2] || b == seg.rbits[3]) continue;
+        if ((tid >> tb) & 1) ob |= 1 << b;
+        ++tb;
+      }
+    }
+    int li[16];
+    float2 x[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      li[r] = ob | ((r & 1) << seg.rbits[0]) | (((r >> 1) & 1) << seg.rbits[1]) | (((r >> 2) & 1) << seg.rbits[2]) |
+              (((r >> 3) & 1) << seg.rbits[3]);
+      x[r] = buf[lds_phys(li[r])];
+    }
+    for (int gi = seg.first_gate; gi < seg.first_gate + seg.n_gates; ++gi) {
+      const SweepGateDesc& gd = a.gates[gi];
+      const float2* G = (gd.g_buf == BUF_IN ? INz : WSz) + gd.g_off;
+      if (gd.diag) {
+        // unused entries of gidx are 0, so all four loads stay in bounds
+        const float2 d0 = G[gd.gidx[0]], d1 = G[gd.gidx[1]], d2 = G[gd.gidx[2]], d3 = G[gd.gidx[3]];
+        const int j0 = gd.lidx[0], j1 = gd.n == 2 ? gd.lidx[1] : 0;
+        int fixed = 0, m0 = 0, s0 = 0, m1 = 0, s1 = 0;
+        if (j0 >= 0) { m0 = 1; s0 = j0; } else { fixed |= (int)((base >> (-j0 - 1)) & 1); }
+        if (gd.n == 2) {
+          if (j1 >= 0) { m1 = 1; s1 = j1; } else { fixed |= (int)((base >> (-j1 - 1)) & 1) << 1; }
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int b = fixed | (m0 & (li[r] >> s0)) | ((m1 & (li[r] >> s1)) << 1);
+          const float2 f = b == 0 ? d0 : b == 1 ? d1 : b == 2 ? d2 : d3;
+          x[r] = cmac<PREC>(f2(0.f, 0.f), f, x[r]);
+        }
+      } else if (gd.n == 1) {
+        float2 g[4];
+        for (int e = 0; e < 4; ++e) g[e] = G[gd.gidx[e]];
+        switch (gd.rb[0]) {
+          case 0: reg_apply1<PREC, 0>(x, g); break;
+          case 1: reg_apply1<PREC, 1>(x, g); break;
+          case 2: reg_apply1<PREC, 2>(x, g); break;
+          default: reg_apply1<PREC, 3>(x, g); break;
+        }
+      } else {
+        float2 g[16];
+        for (int e = 0; e < 16; ++e) g[e] = G[gd.gidx[e]];
+        switch (gd.rb[0] * 4 + gd.rb[1]) {
+          case 1: reg_apply2<PREC, 0, 1>(x, g); break;
+          case 2: reg_apply2<PREC, 0, 2>(x, g); break;
+          case 3: reg_apply2<PREC, 0, 3>(x, g); break;
+          case 6: reg_apply2<PREC, 1, 2>(x, g); break;
+          case 7: reg_apply2<PREC, 1, 3>(x, g); break;
+          default: reg_apply2<PREC, 2, 3>(x, g); break;
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) buf[lds_phys(li[r])] = x[r];
+    __syncthreads();
+  }
+  for (int i = tid; i < L; i += nt) out[base | (i & 31) | dep_hi[i >> 5]] = buf[lds_phys(i)];
+}
+
+hipError_t launch_sweep_pass(hipStream_t s, const SweepPass& ps, int bits, const SweepGateDesc* gates_dev,
+                             const SweepSegment* segs_dev, const float2* in, int64_t in_bs, float2* out,
+                             int64_t out_bs, float2* IN, int64_t IN_bs, float2* WS, int64_t WS_bs, int batch,
+                             int precision) {
+  SweepPassArgs a;
+  a.in = in; a.out = out; a.in_bs = in_bs; a.out_bs = out_bs;
+  a.IN = IN; a.WS = WS; a.IN_bs = IN_bs; a.WS_bs = WS_bs;
+  a.gates = gates_dev;
+  a.segs = segs_dev + ps.first_seg;
+  a.n_segs = ps.n_segs;
+  a.l = ps.l;
+  a.pad = 0;
+  if (ps.l < kSweepMinLocal || ps.l > kSweepMaxLocal) return hipErrorInvalidValue;
+  std::vector<char> local(bits, 0);
+  for (int j = 0; j < ps.l; ++j) {
+    a.lpos[j] = ps.lpos[j];
+    if (ps.lpos[j] < 0 || ps.lpos[j] >= bits || (j < 5 && ps.lpos[j] != j)) return hipErrorInvalidValue;
+    local[ps.lpos[j]] = 1;
+  }
+  int nr = 0;
+  for (int p = 0; p < bits; ++p)
+    if (!local[p]) a.rest[nr++] = (int8_t)p;
+  a.n_rest = nr;
+  const int64_t chunks = (int64_t)1 << nr;
+  if (chunks > ((int64_t)1 << 24)) return hipErrorInvalidValue;
+  const int threads = 1 << (ps.l - 4);
+  if (precision == TN_PREC_BF16X3)
+    hipLaunchKernelGGL(k_sweep_pass<TN_PREC_BF16X3>, dim3((unsigned)chunks, batch), dim3(threads), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_sweep_pass<TN_PREC_C64>, dim3((unsigned)chunks, batch), dim3(threads), 0, s, a);
   return hipGetLastError();
 }
 
@@ -418,6 +613,11 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 constexpr int kBM = 128, kBN = 64, kBK = 16;
 
+// Operands and result are read and written through bit-deposit maps: the
+// address of logical index x of an operand is the OR of x's bits moved to
+// their positions in that operand's layout.  A tile's base address is the
+// deposit of its (multiple-of-tile) origin; the offsets inside a tile come
+// from small LDS tables, so no separate permute pass is needed.
 struct GemmArgs {
   const float2* A;
   const float2* B;
@@ -425,54 +625,110 @@ struct GemmArgs {
   int64_t a_bs, b_bs, c_bs;
   int64_t batch, M, N, K;
   int64_t tiles_m, tiles_n;
+  int64_t c_elems;  // elements of C per parameter vector (split-K partial stride)
+  int32_t nbb, nbm, nbn, nbk, split, pad;
+  int8_t a_b[kGemmMaxBits], a_m[kGemmMaxBits], a_k[kGemmMaxBits];
+  int8_t b_b[kGemmMaxBits], b_k[kGemmMaxBits], b_n[kGemmMaxBits];
+  int8_t c_b[kGemmMaxBits], c_m[kGemmMaxBits], c_n[kGemmMaxBits];
 };
+
+__device__ inline int64_t deposit(int64_t x, const int8_t* pos, int nbits) {
+  int64_t r = 0;
+  for (int j = 0; j < nbits; ++j)
+    if ((x >> j) & 1) r |= (int64_t)1 << pos[j];
+  return r;
+}
 
 template <int AK, int BNF, int PREC>
 __global__ __launch_bounds__(kThreads) void k_gemm(GemmArgs g) {
   __shared__ float As_re[kBK][kBM + 1];
   __shared__ float As_im[kBK][kBM + 1];
   __shared__ float2 Bs[kBK][kBN + 1];
-  const int64_t bid = blockIdx.x;
+  __shared__ int64_t TAm[kBM], TCm[kBM], TBn[kBN], TCn[kBN], TAk[kBK], TBk[kBK];
+  int64_t bid = blockIdx.x;
   const int64_t tn = bid % g.tiles_n;
-  const int64_t tm = (bid / g.tiles_n) % g.tiles_m;
-  const int64_t gb = (bid / (g.tiles_n * g.tiles_m)) % g.batch;
-  const int64_t z = bid / (g.tiles_n * g.tiles_m * g.batch);
-  const float2* A = g.A + z * g.a_bs + gb * g.M * g.K;
-  const float2* B = g.B + z * g.b_bs + gb * g.K * g.N;
-  float2* C = g.C + z * g.c_bs + gb * g.M * g.N;
+  bid /= g.tiles_n;
+  const int64_t tm = bid % g.tiles_m;
+  bid /= g.tiles_m;
+  const int64_t ks = bid % g.split;
+  bid /= g.split;
+  const int64_t gb = bid % g.batch;
+  const int64_t z = bid / g.batch;
+  const float2* A = g.A + z * g.a_bs;
+  const float2* B = g.B + z * g.b_bs;
+  float2* C = g.C + z * g.c_bs + ks * g.c_elems;
   const int64_t m0 = tm * kBM, n0 = tn * kBN;
+  const int64_t kchunk = g.K / g.split;
+  const int64_t kbeg = ks * kchunk, kend = kbeg + kchunk;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w >> 1, wn = w & 1;
+  const int64_t base_a = deposit(gb, g.a_b, g.nbb) | deposit(m0, g.a_m, g.nbm);
+  const int64_t base_b = deposit(gb, g.b_b, g.nbb) | deposit(n0, g.b_n, g.nbn);
+  const int64_t base_c = deposit(gb, g.c_b, g.nbb) | deposit(m0, g.c_m, g.nbm) | deposit(n0, g.c_n, g.nbn);
+  if (tid < kBM) {
+    const int nb = min(g.nbm, 7);
+    TAm[tid] = deposit(tid, g.a_m, nb);
+    TCm[tid] = deposit(tid, g.c_m, nb);
+  }
+  if (tid < kBN) {
+    const int nb = min(g.nbn, 6);
+    TBn[tid] = deposit(tid, g.b_n, nb);
+    TCn[tid] = deposit(tid, g.c_n, nb);
+  }
+  if (tid < kBK) {
+    const int nb = min(g.nbk, 4);
+    TAk[tid] = deposit(tid, g.a_k, nb);
+    TBk[tid] = deposit(tid, g.b_k, nb);
+  }
   floatx16 acc[2][2];
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j)
       for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
+  __syncthreads();
 
-  for (int64_t k0 = 0; k0 < g.K; k0 += kBK) {
-    // A tile -> split planes [k][m]
+  // software pipeline: the next K tile is fetched into registers while the
+  // current one is multiplied out of LDS
+  constexpr int kPA = (kBM * kBK) / kThreads, kPB = (kBN * kBK) / kThreads;
+  float2 ra[kPA], rb[kPB];
+  auto fetch = [&](int64_t k0) {
+    const int64_t ka = deposit(k0, g.a_k, g.nbk), kb = deposit(k0, g.b_k, g.nbk);
 #pragma unroll
-    for (int e = 0; e < (kBM * kBK) / kThreads; ++e) {
+    for (int e = 0; e < kPA; ++e) {
       const int idx = tid + e * kThreads;
       int mm, kk;
       if (AK) { mm = idx / kBK; kk = idx % kBK; } else { mm = idx % kBM; kk = idx / kBM; }
-      const int64_t gm = m0 + mm, gk = k0 + kk;
-      float2 v = f2(0.f, 0.f);
-      if (gm < g.M && gk < g.K) v = AK ? A[gm * g.K + gk] : A[gk * g.M + gm];
-      if (PREC == TN_PREC_BF16X3) { /* operands are split at the product */ }
-      As_re[kk][mm] = v.x;
-      As_im[kk][mm] = v.y;
+      ra[e] = (m0 + mm < g.M && k0 + kk < kend) ? A[base_a | TAm[mm] | ka | TAk[kk]] : f2(0.f, 0.f);
     }
 #pragma unroll
-    for (int e = 0; e < (kBN * kBK) / kThreads; ++e) {
+    for (int e = 0; e < kPB; ++e) {
       const int idx = tid + e * kThreads;
       int nn, kk;
       if (BNF) { nn = idx % kBN; kk = idx / kBN; } else { nn = idx / kBK; kk = idx % kBK; }
-      const int64_t gn = n0 + nn, gk = k0 + kk;
-      float2 v = f2(0.f, 0.f);
-      if (gn < g.N && gk < g.K) v = BNF ? B[gk * g.N + gn] : B[gn * g.K + gk];
-      Bs[kk][nn] = v;
+      rb[e] = (n0 + nn < g.N && k0 + kk < kend) ? B[base_b | TBn[nn] | kb | TBk[kk]] : f2(0.f, 0.f);
     }
+  };
+  auto stage = [&]() {
+#pragma unroll
+    for (int e = 0; e < kPA; ++e) {
+      const int idx = tid + e * kThreads;
+      int mm, kk;
+      if (AK) { mm = idx / kBK; kk = idx % kBK; } else { mm = idx % kBM; kk = idx / kBM; }
+      As_re[kk][mm] = ra[e].x;
+      As_im[kk][mm] = ra[e].y;
+    }
+#pragma unroll
+    for (int e = 0; e < kPB; ++e) {
+      const int idx = tid + e * kThreads;
+      int nn, kk;
+      if (BNF) { nn = idx % kBN; kk = idx / kBN; } else { nn = idx / kBK; kk = idx % kBK; }
+      Bs[kk][nn] = rb[e];
+    }
+  };
+  fetch(kbeg);
+  for (int64_t k0 = kbeg; k0 < kend; k0 += kBK) {
+    stage();
     __syncthreads();
+    if (k0 + kBK < kend) fetch(k0 + kBK);
 #pragma unroll 4
     for (int kk = 0; kk < kBK; ++kk) {
       float av[2], bv[2];
@@ -511,22 +767,52 @@ __global__ __launch_bounds__(kThreads) void k_gemm(GemmArgs g) {
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
-        const int64_t row = m0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        const int rl = wm * 64 + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
         const int jj = lane & 31;
-        const int64_t col = n0 + wn * 32 + j * 16 + (jj >> 1);
-        if (row < g.M && col < g.N) Cf[(row * g.N + col) * 2 + (jj & 1)] = acc[i][j][v];
+        const int cl = wn * 32 + j * 16 + (jj >> 1);
+        if (m0 + rl < g.M && n0 + cl < g.N) Cf[(base_c | TCm[rl] | TCn[cl]) * 2 + (jj & 1)] = acc[i][j][v];
       }
 }
 
+// C[i] = sum over s of partial[s][i] (split-K), contiguous per parameter vector
+__global__ void k_sum_partials(const float2* part, int64_t part_bs, int split, int64_t n, float2* C, int64_t c_bs) {
+  const int z = blockIdx.y;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+    float2 acc = f2(0.f, 0.f);
+    for (int s = 0; s < split; ++s) {
+      const float2 v = part[(int64_t)z * part_bs + (int64_t)s * n + i];
+      acc.x += v.x;
+      acc.y += v.y;
+    }
+    C[(int64_t)z * c_bs + i] = acc;
+  }
+}
+
 hipError_t launch_gemm(hipStream_t s, const GemmDesc& d, const float2* a, int64_t a_bs, const float2* b, int64_t b_bs,
-                       float2* c, int64_t c_bs, int batch, int precision) {
+                       float2* c, int64_t c_bs, float2* tmp, int64_t tmp_bs, int batch, int precision) {
   GemmArgs g;
-  g.A = a; g.B = b; g.C = c;
-  g.a_bs = a_bs; g.b_bs = b_bs; g.c_bs = c_bs;
+  g.A = a; g.B = b;
   g.batch = d.batch; g.M = d.M; g.N = d.N; g.K = d.K;
   g.tiles_m = (d.M + kBM - 1) / kBM;
   g.tiles_n = (d.N + kBN - 1) / kBN;
-  const int64_t blocks = g.tiles_m * g.tiles_n * d.batch * batch;
+  g.split = d.split > 1 ? d.split : 1;
+  g.c_elems = d.batch * d.M * d.N;
+  if (g.split > 1) {
+    if (d.K % g.split != 0 || !tmp) return hipErrorInvalidValue;
+    g.C = tmp;
+    g.c_bs = tmp_bs;
+  } else {
+    g.C = c;
+    g.c_bs = c_bs;
+  }
+  g.a_bs = a_bs; g.b_bs = b_bs;
+  g.nbb = d.nbb; g.nbm = d.nbm; g.nbn = d.nbn; g.nbk = d.nbk; g.pad = 0;
+  for (int j = 0; j < kGemmMaxBits; ++j) {
+    g.a_b[j] = d.a_b[j]; g.a_m[j] = d.a_m[j]; g.a_k[j] = d.a_k[j];
+    g.b_b[j] = d.b_b[j]; g.b_k[j] = d.b_k[j]; g.b_n[j] = d.b_n[j];
+    g.c_b[j] = d.c_b[j]; g.c_m[j] = d.c_m[j]; g.c_n[j] = d.c_n[j];
+  }
+  const int64_t blocks = g.tiles_m * g.tiles_n * g.split * d.batch * batch;
   if (blocks > ((int64_t)1 << 24)) return hipErrorInvalidValue;
   void* fn;
   const bool bf = precision == TN_PREC_BF16X3;
@@ -535,7 +821,13 @@ hipError_t launch_gemm(hipStream_t s, const GemmDesc& d, const float2* a, int64_
   else if (d.b_nfast) fn = bf ? (void*)k_gemm<0, 1, 1> : (void*)k_gemm<0, 1, 0>;
   else fn = bf ? (void*)k_gemm<0, 0, 1> : (void*)k_gemm<0, 0, 0>;
   void* args[] = {&g};
-  return hipLaunchKernel(fn, dim3((unsigned)blocks), dim3(kThreads), args, 0, s);
+  hipError_t e = hipLaunchKernel(fn, dim3((unsigned)blocks), dim3(kThreads), args, 0, s);
+  if (e != hipSuccess || g.split == 1) return e;
+  int64_t rb = (g.c_elems + kThreads - 1) / kThreads;
+  if (rb > 16384) rb = 16384;
+  hipLaunchKernelGGL(k_sum_partials, dim3((unsigned)rb, batch), dim3(kThreads), 0, s, tmp, tmp_bs, g.split, g.c_elems,
+                     c, c_bs);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -559,21 +851,21 @@ __global__ __launch_bounds__(kThreads) void k_expect_partial(const float2* psi, 
     acc += pr * zdiag((uint64_t)x, t);
   }
   const double s = block_sum(acc, red);
-  if (threadIdx.x == 0) partial[(int64_t)z * kReduceBlocks + blockIdx.x] = s;
+  if (threadIdx.x == 0) partial[(int64_t)z * kExpectBlocks + blockIdx.x] = s;
 }
 
 __global__ void k_reduce_rows(const double* partial, int nb, int batch, double* out, int64_t out_stride) {
   const int z = blockIdx.x * blockDim.x + threadIdx.x;
   if (z >= batch) return;
   double s = 0;
-  for (int i = 0; i < nb; ++i) s += partial[(int64_t)z * kReduceBlocks + i];
+  for (int i = 0; i < nb; ++i) s += partial[(int64_t)z * kExpectBlocks + i];
   out[(int64_t)z * out_stride] = s;
 }
 
 hipError_t launch_expectation(hipStream_t s, const float2* psi, int64_t psi_bs, int64_t n_elems, const ZTerms& terms,
                               int batch, double* partial, double* out, int64_t out_stride) {
   int64_t blocks = (n_elems + kThreads - 1) / kThreads;
-  if (blocks > kReduceBlocks) blocks = kReduceBlocks;
+  if (blocks > kExpectBlocks) blocks = kExpectBlocks;
   hipLaunchKernelGGL(k_expect_partial, dim3((unsigned)blocks, batch), dim3(kThreads), 0, s, psi, psi_bs, n_elems,
                      terms, partial);
   hipError_t e = hipGetLastError();

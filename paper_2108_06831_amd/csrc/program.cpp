@@ -187,7 +187,204 @@ std::vector<int32_t> reorder_small_first(const tn_network* net, const std::vecto
   return out;
 }
 
-tn_status compile_program(const tn_network* net, tn_path* path) {
+namespace {
+
+// Group chains of consecutive gate-sized steps on one large tensor into fused
+// streaming passes (light-cone rule: a gate joins the current pass if its bits
+// fit in the pass's local set and no earlier gate left out of the pass touches
+// them; gates on disjoint bits commute).
+void build_chains(tn_path* path, int T) {
+  path->chains.clear();
+  path->passes.clear();
+  path->segments.clear();
+  path->sweep_gates.clear();
+  const int S = (int)path->steps.size();
+  auto sweepable = [&](int s) {
+    const StepProgram& P = path->steps[s];
+    if (P.kind != SK_SKINNY || P.sk.c_mode != 0 || P.sk.t_bits < 16 || !P.pre.empty()) return false;
+    const SkinnyDesc& d = P.sk;
+    if (d.nb == 0) return d.nk == d.nm && d.nk >= 1 && d.nk <= 2;
+    return d.nk == 0 && d.nm == 0 && d.nb <= 2;
+  };
+  for (int s = path->n_small; s < S;) {
+    if (!sweepable(s)) { ++s; continue; }
+    int e = s + 1;
+    while (e < S && sweepable(e)) {
+      // the next step must act on this step's result
+      const int ia = path->pairs[2 * e], ib = path->pairs[2 * e + 1];
+      if (ia != T + e - 1 && ib != T + e - 1) break;
+      const StepProgram& Q = path->steps[e];
+      const StepProgram& P = path->steps[e - 1];
+      if (Q.sk.t.buf != P.sk.c.buf || Q.sk.t.off != P.sk.c.off || Q.sk.t_bits != P.sk.t_bits) break;
+      ++e;
+    }
+    if (e - s < 2) { s = e; continue; }
+    SweepChain ch;
+    ch.in = path->steps[s].sk.t;
+    ch.out = path->steps[e - 1].sk.c;
+    ch.bits = path->steps[s].sk.t_bits;
+    ch.first_pass = (int32_t)path->passes.size();
+    ch.n_steps = e - s;
+    const int R = ch.bits;
+    const int lmax = std::min(kSweepMaxLocal, R - 8);  // >= kSweepMinLocal since R >= 16
+    const int low = 5;  // lmax >= 6 + 2 since R >= 16: room for any two-qubit gate next to the low bits
+    // gate list: positions in T
+    struct G { std::vector<int> pos; int step; };
+    std::vector<G> gates;
+    for (int i = s; i < e; ++i) {
+      const SkinnyDesc& d = path->steps[i].sk;
+      G g;
+      g.step = i;
+      if (d.nb == 0) for (int j = 0; j < d.nk; ++j) g.pos.push_back(d.k_pos[j]);
+      else for (int j = 0; j < d.nb; ++j) g.pos.push_back(d.bt_pos[j]);
+      gates.push_back(g);
+    }
+    std::vector<char> done(gates.size(), 0);
+    size_t remaining = gates.size();
+    while (remaining > 0) {
+      // blk_any[p]: a gate left out of this pass touches p (later dense gates on p wait);
+      // blk_dense[p]: a dense gate left out touches p (later diagonal gates on p wait too).
+      // Diagonal gates commute with each other and need no local bits: a bit outside the
+      // chunk is constant over it and read from the chunk's base address.
+      std::vector<char> local(R, 0), blk_any(R, 0), blk_dense(R, 0);
+      int nl = 0;
+      for (int p = 0; p < low; ++p) { local[p] = 1; ++nl; }
+      SweepPass ps;
+      ps.first_gate = (int32_t)path->sweep_gates.size();
+      std::vector<int> members;
+      for (size_t gi = 0; gi < gates.size(); ++gi) {
+        if (done[gi]) continue;
+        const auto& pos = gates[gi].pos;
+        const bool diag = path->steps[gates[gi].step].sk.nb > 0;
+        bool take;
+        if (diag) {
+          take = true;
+          for (int p : pos) take &= !blk_dense[p];
+        } else {
+          int extra = 0;
+          take = true;
+          for (int p : pos) { take &= !blk_any[p]; extra += !local[p]; }
+          take &= nl + extra <= lmax;
+        }
+        if (take) {
+          if (!diag)
+            for (int p : pos) if (!local[p]) { local[p] = 1; ++nl; }
+          members.push_back((int)gi);
+          done[gi] = 1;
+          --remaining;
+        } else {
+          for (int p : pos) {
+            blk_any[p] = 1;
+            if (!diag) blk_dense[p] = 1;
+          }
+        }
+      }
+      // fill the local set up to lmax with the lowest remaining bits (longer contiguous runs)
+      for (int p = 0; p < R && nl < lmax; ++p) if (!local[p]) { local[p] = 1; ++nl; }
+      std::vector<int> lpos;
+      for (int p = 0; p < R; ++p) if (local[p]) lpos.push_back(p);
+      ps.l = (int32_t)lpos.size();
+      for (int j = 0; j < kSweepMaxLocal; ++j) ps.lpos[j] = j < ps.l ? (int8_t)lpos[j] : 0;
+      auto lidx_of = [&](int p) { return (int32_t)(std::find(lpos.begin(), lpos.end(), p) - lpos.begin()); };
+      for (int gi : members) {
+        const SkinnyDesc& d = path->steps[gates[gi].step].sk;
+        SweepGateDesc gd;
+        gd.diag = d.nb > 0;
+        gd.n = (int32_t)gates[gi].pos.size();
+        gd.pad = 0;
+        for (int j = 0; j < 2; ++j) {
+          gd.lidx[j] = 0;
+          if (j >= gd.n) continue;
+          const int p = gates[gi].pos[j];
+          // a diagonal gate's bit outside the chunk is encoded as -(position + 1)
+          gd.lidx[j] = local[p] ? lidx_of(p) : -(p + 1);
+        }
+        gd.g_buf = d.g.buf;
+        gd.unit = gd.diag ? d.g_unit : 0;
+        gd.g_off = d.g.off;
+        for (int j = 0; j < 16; ++j) gd.gidx[j] = 0;
+        const int ne = gd.diag ? (1 << gd.n) : (1 << (2 * gd.n));
+        for (int j = 0; j < ne; ++j) gd.gidx[j] = d.gidx[j];
+        path->sweep_gates.push_back(gd);
+      }
+      ps.n_gates = (int32_t)members.size();
+      if (members.empty()) break;  // cannot happen with lmax >= low + 2; guards the loop
+      // segments: consecutive runs whose dense gates' local bits fit in four register bits
+      ps.first_seg = (int32_t)path->segments.size();
+      {
+        std::vector<int> rset;
+        SweepSegment seg;
+        seg.first_gate = ps.first_gate;
+        seg.n_gates = 0;
+        auto close = [&]() {
+          // complete the register set with other local bits (the lowest unused ones)
+          for (int b = 0; b < ps.l && (int)rset.size() < 4; ++b)
+            if (std::find(rset.begin(), rset.end(), b) == rset.end()) rset.push_back(b);
+          std::sort(rset.begin(), rset.end());
+          for (int j = 0; j < 4; ++j) seg.rbits[j] = (int8_t)rset[j];
+          for (int g = seg.first_gate; g < seg.first_gate + seg.n_gates; ++g) {
+            SweepGateDesc& gd = path->sweep_gates[g];
+            gd.rb[0] = gd.rb[1] = 0;
+            if (gd.diag) continue;
+            for (int j = 0; j < gd.n; ++j)
+              gd.rb[j] = (int32_t)(std::find(rset.begin(), rset.end(), gd.lidx[j]) - rset.begin());
+          }
+          path->segments.push_back(seg);
+        };
+        for (int g = ps.first_gate; g < ps.first_gate + ps.n_gates; ++g) {
+          const SweepGateDesc& gd = path->sweep_gates[g];
+          if (!gd.diag) {
+            std::vector<int> u = rset;
+            for (int j = 0; j < gd.n; ++j)
+              if (std::find(u.begin(), u.end(), gd.lidx[j]) == u.end()) u.push_back(gd.lidx[j]);
+            if ((int)u.size() > 4) {
+              close();
+              rset.clear();
+              seg.first_gate = g;
+              seg.n_gates = 0;
+              u.clear();
+              for (int j = 0; j < gd.n; ++j) u.push_back(gd.lidx[j]);
+            }
+            rset = u;
+          }
+          seg.n_gates++;
+        }
+        close();
+      }
+      ps.n_segs = (int32_t)path->segments.size() - ps.first_seg;
+      path->passes.push_back(ps);
+    }
+    if (remaining > 0) {  // leave the chain to the per-step kernels
+      const bool any = path->passes.size() > (size_t)ch.first_pass;
+      const int32_t fg = any ? path->passes[ch.first_pass].first_gate : (int32_t)path->sweep_gates.size();
+      const int32_t fs = any ? path->passes[ch.first_pass].first_seg : (int32_t)path->segments.size();
+      path->passes.resize(ch.first_pass);
+      path->sweep_gates.resize(fg);
+      path->segments.resize(fs);
+      s = e;
+      continue;
+    }
+    ch.n_passes = (int32_t)path->passes.size() - ch.first_pass;
+    path->steps[s].chain = (int32_t)path->chains.size();
+    for (int i = s + 1; i < e; ++i) path->steps[i].chain = -2;
+    path->chains.push_back(ch);
+    s = e;
+  }
+}
+
+}  // namespace
+
+std::vector<int32_t> output_layout(const tn_network* net) {
+  std::vector<int32_t> to;
+  if (net->output_kind == TN_OUT_STATEVECTOR) {
+    for (int q = 0; q < net->n_qubits; ++q) to.push_back(label(net->wire_final[q], 0));
+  } else {
+    for (int j = net->batch_log2 - 1; j >= 0; --j) to.push_back(label(net->batch_mode, j));
+  }
+  return to;
+}
+
+tn_status compile_program(const tn_network* net, tn_path* path, const std::vector<int32_t>* final_layout) {
   const int T = (int)net->tensors.size();
   const int S = (int)path->pairs.size() / 2;
   std::vector<Loc> loc(T + S);
@@ -302,7 +499,7 @@ tn_status compile_program(const tn_network* net, tn_path* path) {
       d.c_buf = C.ref.buf;
       d.c_off = C.ref.off;
       d.c_bits = (int32_t)C.bits.size();
-      d.pad = 0;
+      d.alias = 0;
       for (int p = 0; p < kSmallMaxBits; ++p) d.apos[p] = d.bpos[p] = d.ka[p] = d.kb[p] = -1;
       for (int p = 0; p < d.c_bits; ++p) {
         const int32_t lab = C.bits[C.bits.size() - 1 - p];
@@ -337,6 +534,7 @@ tn_status compile_program(const tn_network* net, tn_path* path) {
       for (int j = 0; j < nb; ++j) {
         int p = (int)(std::find(outer.begin(), outer.end(), blab[j]) - outer.begin());
         d.b_pos[j] = p;
+        d.bt_pos[j] = pos_of(Tt.bits, blab[j]);
       }
       // C layout
       if (nm == nk) {
@@ -379,6 +577,22 @@ tn_status compile_program(const tn_network* net, tn_path* path) {
             d.gidx[((b << nm) + m) * (1 << nk) + k] = (int32_t)a;
           }
       d.g = G.ref;
+      // a diagonal gate tensor from the unit-modulus family (its phases can be accumulated as angles)
+      d.g_unit = 0;
+      {
+        const int gid = a_small ? ia : ib;
+        if (gid < T && net->tensors[gid].kind == TK_GATE && net->tensors[gid].recipe >= 0 && d.nk == 0 &&
+            d.nm == 0) {
+          const Recipe& r = net->recipes[net->tensors[gid].recipe];
+          bool unit = r.diag && r.split_side < 0;
+          for (int o = r.op_begin; o < r.op_end && unit; ++o) {
+            const int k = net->ops[o].kind;
+            unit = k == TN_GATE_Z || k == TN_GATE_S || k == TN_GATE_T || k == TN_GATE_RZ || k == TN_GATE_CZ ||
+                   k == TN_GATE_CPHASE || k == TN_GATE_ZZPHASE;
+          }
+          d.g_unit = unit ? 1 : 0;
+        }
+      }
       d.t = Tt.ref;
       // output buffer: in place over T when T dies here and the layout positions coincide
       if (d.c_mode == 0 && !Tt.input && Tt.last_use == s && Tt.elems == C.elems) {
@@ -392,87 +606,75 @@ tn_status compile_program(const tn_network* net, tn_path* path) {
     } else {
       P.kind = SK_GEMM;
       st.n_gemm_steps++;
-      int a_fast = 0, b_fast = 0;
-      const bool ra = grouped(A.bits, cls, C_M, C_K, &a_fast);
-      const bool rb = grouped(B.bits, cls, C_K, C_N, &b_fast);
-      auto compat = [&](const std::vector<int32_t>& x, const std::vector<int32_t>& y) {
-        return filter(x, cls, C_BATCH) == filter(y, cls, C_BATCH) && filter(x, cls, C_K) == filter(y, cls, C_K);
-      };
-      std::vector<int32_t> la = A.bits, lb = B.bits;
-      bool perm_a = false, perm_b = false;
-      auto target_b = [&](const std::vector<int32_t>& ref) {
-        std::vector<int32_t> bt = filter(ref, cls, C_BATCH), kk = filter(ref, cls, C_K), nn = filter(B.bits, cls, C_N);
-        const bool k_low = !B.bits.empty() && cls[B.bits.back()] == C_K && !nn.empty();
-        return k_low ? cat(bt, nn, kk) : cat(bt, kk, nn);
-      };
-      auto target_a = [&](const std::vector<int32_t>& ref) {
-        std::vector<int32_t> bt = filter(ref, cls, C_BATCH), kk = filter(ref, cls, C_K), mm = filter(A.bits, cls, C_M);
-        const bool m_low = !A.bits.empty() && cls[A.bits.back()] == C_M && !kk.empty();
-        return m_low ? cat(bt, kk, mm) : cat(bt, mm, kk);
-      };
-      if (ra && rb && compat(A.bits, B.bits)) {
-        // nothing to do
-      } else if (ra && (!rb || A.elems >= B.elems)) {
-        lb = target_b(A.bits);
-        perm_b = true;
-      } else if (rb) {
-        la = target_a(B.bits);
-        perm_a = true;
+      // C: the requested output layout for the last step, else [batch | M | N] in the operands' orders
+      if (s == S - 1 && final_layout && final_layout->size() == (size_t)nbits[0] + nbits[1] + nbits[2]) {
+        C.bits = *final_layout;
       } else {
-        // neither grouped: canonicalise the larger with its own relative orders, then match the other
-        if (A.elems >= B.elems) {
-          std::vector<int32_t> bt = filter(A.bits, cls, C_BATCH), kk = filter(A.bits, cls, C_K);
-          la = cat(bt, filter(A.bits, cls, C_M), kk);
-          perm_a = true;
-          lb = target_b(la);
-          perm_b = true;
-        } else {
-          std::vector<int32_t> bt = filter(B.bits, cls, C_BATCH), kk = filter(B.bits, cls, C_K);
-          lb = cat(bt, kk, filter(B.bits, cls, C_N));
-          perm_b = true;
-          la = target_a(lb);
-          perm_a = true;
+        C.bits = cat(filter(A.bits, cls, C_BATCH), filter(A.bits, cls, C_M), filter(B.bits, cls, C_N));
+      }
+      // logical bit orders: batch, m, n by ascending position in C; k by ascending position in A
+      auto by_pos = [&](const std::vector<int32_t>& layout, int c) {
+        std::vector<int32_t> v;
+        for (int p = 0; p < (int)layout.size(); ++p) {
+          const int32_t lab = layout[layout.size() - 1 - p];
+          if (cls[lab] == c) v.push_back(lab);
         }
-      }
-      if (perm_a && la == A.bits) perm_a = false;
-      if (perm_b && lb == B.bits) perm_b = false;
-      BufRef ra_ref = A.ref, rb_ref = B.ref;
-      int64_t tmp_a = -1, tmp_b = -1;
-      if (perm_a) {
-        tmp_a = alloc.get(A.elems);
-        BufRef o; o.buf = BUF_WS; o.off = tmp_a;
-        P.pre.push_back(make_permute(A.ref, A.bits, o, la));
-        ra_ref = o;
-        st.n_permutes++;
-        P.bytes += 16.0 * (double)A.elems;
-      }
-      if (perm_b) {
-        tmp_b = alloc.get(B.elems);
-        BufRef o; o.buf = BUF_WS; o.off = tmp_b;
-        P.pre.push_back(make_permute(B.ref, B.bits, o, lb));
-        rb_ref = o;
-        st.n_permutes++;
-        P.bytes += 16.0 * (double)B.elems;
-      }
-      int fa = 0, fb = 0;
-      grouped(la, cls, C_M, C_K, &fa);
-      grouped(lb, cls, C_K, C_N, &fb);
+        return v;
+      };
+      const std::vector<int32_t> lb_ = by_pos(C.bits, C_BATCH), lm = by_pos(C.bits, C_M), ln = by_pos(C.bits, C_N),
+                                 lk = by_pos(A.bits, C_K);
       GemmDesc& g = P.gm;
       g.batch = bsz; g.M = msz; g.N = nsz; g.K = ksz;
-      g.a_kfast = (fa == C_K) || nbits[C_M] == 0 ? 1 : 0;
-      g.b_nfast = (fb == C_N) || nbits[C_K] == 0 ? 1 : 0;
-      if (nbits[C_K] == 0) { g.a_kfast = 1; }
-      if (nbits[C_N] == 0) { g.b_nfast = 0; }
-      if (nbits[C_M] == 0) { g.a_kfast = 1; }
-      if (nbits[C_K] == 0) { g.b_nfast = 1; }
-      g.a = ra_ref;
-      g.b = rb_ref;
-      C.bits = cat(filter(la, cls, C_BATCH), filter(la, cls, C_M), filter(lb, cls, C_N));
+      g.nbb = (int32_t)lb_.size(); g.nbm = (int32_t)lm.size(); g.nbn = (int32_t)ln.size(); g.nbk = (int32_t)lk.size();
+      if (g.nbb > kGemmMaxBits || g.nbm > kGemmMaxBits || g.nbn > kGemmMaxBits || g.nbk > kGemmMaxBits)
+        return set_error(TN_EUNSUPPORTED, "contraction index wider than 2^40");
+      for (int j = 0; j < kGemmMaxBits; ++j)
+        g.a_b[j] = g.a_m[j] = g.a_k[j] = g.b_b[j] = g.b_k[j] = g.b_n[j] = g.c_b[j] = g.c_m[j] = g.c_n[j] = 0;
+      for (int j = 0; j < g.nbb; ++j) {
+        g.a_b[j] = (int8_t)pos_of(A.bits, lb_[j]);
+        g.b_b[j] = (int8_t)pos_of(B.bits, lb_[j]);
+        g.c_b[j] = (int8_t)pos_of(C.bits, lb_[j]);
+      }
+      for (int j = 0; j < g.nbm; ++j) {
+        g.a_m[j] = (int8_t)pos_of(A.bits, lm[j]);
+        g.c_m[j] = (int8_t)pos_of(C.bits, lm[j]);
+      }
+      for (int j = 0; j < g.nbn; ++j) {
+        g.b_n[j] = (int8_t)pos_of(B.bits, ln[j]);
+        g.c_n[j] = (int8_t)pos_of(C.bits, ln[j]);
+      }
+      for (int j = 0; j < g.nbk; ++j) {
+        g.a_k[j] = (int8_t)pos_of(A.bits, lk[j]);
+        g.b_k[j] = (int8_t)pos_of(B.bits, lk[j]);
+      }
+      // tile-load orientation: walk the index owning the operand's lowest m/k (k/n) address bit fastest
+      auto lowest_cls = [&](const std::vector<int32_t>& layout, int c1, int c2) {
+        for (int p = 0; p < (int)layout.size(); ++p) {
+          const int c = cls[layout[layout.size() - 1 - p]];
+          if (c == c1 || c == c2) return c;
+        }
+        return c2;
+      };
+      g.a_kfast = lowest_cls(A.bits, C_M, C_K) == C_K ? 1 : 0;
+      g.b_nfast = lowest_cls(B.bits, C_K, C_N) == C_N ? 1 : 0;
+      g.a = A.ref;
+      g.b = B.ref;
       C.ref.buf = BUF_WS;
       C.ref.off = alloc.get(C.elems);
       g.c = C.ref;
-      if (tmp_a >= 0) alloc.put(tmp_a, A.elems);
-      if (tmp_b >= 0) alloc.put(tmp_b, B.elems);
+      // too few output tiles to fill the chip and a long K loop: split K
+      const int64_t tiles = ((g.M + 127) / 128) * ((g.N + 63) / 64) * g.batch;
+      g.split = 1;
+      if (tiles < 128 && g.K >= 256) {
+        int64_t sp = 1;
+        while (sp < 32 && tiles * sp * 2 <= 512 && g.K / (sp * 2) >= 32) sp *= 2;
+        g.split = (int32_t)sp;
+      }
+      if (g.split > 1) {
+        g.tmp.buf = BUF_WS;
+        g.tmp.off = alloc.get((int64_t)g.split * C.elems);
+        alloc.put(g.tmp.off, (int64_t)g.split * C.elems);  // scratch for this step only
+      }
     }
     // ---- bookkeeping
     for (int m : modes[ia]) holders[m]--;
@@ -546,6 +748,25 @@ tn_status compile_program(const tn_network* net, tn_path* path) {
       const GemmDesc& g = P.gm;
       if (g.batch * g.M * g.K != ea || g.batch * g.K * g.N != eb || g.batch * g.M * g.N != ec)
         return set_error(TN_EINVAL, "internal: GEMM shape mismatch");
+      const int ra = (int)loc[ia].bits.size(), rb = (int)loc[ib].bits.size(), rc = (int)loc[T + s].bits.size();
+      if (g.nbb + g.nbm + g.nbk != ra || g.nbb + g.nbk + g.nbn != rb || g.nbb + g.nbm + g.nbn != rc)
+        return set_error(TN_EINVAL, "internal: GEMM bit counts");
+      auto perm_ok = [](int r, std::initializer_list<std::pair<const int8_t*, int>> parts) {
+        std::vector<char> seen(r, 0);
+        for (auto& pr : parts)
+          for (int j = 0; j < pr.second; ++j) {
+            const int p = pr.first[j];
+            if (p < 0 || p >= r || seen[p]) return false;
+            seen[p] = 1;
+          }
+        return true;
+      };
+      if (g.split > 1 && !ref_ok(g.tmp, (int64_t)g.split * ec))
+        return set_error(TN_EINVAL, "internal: split-K scratch out of range");
+      if (!perm_ok(ra, {{g.a_b, g.nbb}, {g.a_m, g.nbm}, {g.a_k, g.nbk}}) ||
+          !perm_ok(rb, {{g.b_b, g.nbb}, {g.b_k, g.nbk}, {g.b_n, g.nbn}}) ||
+          !perm_ok(rc, {{g.c_b, g.nbb}, {g.c_m, g.nbm}, {g.c_n, g.nbn}}))
+        return set_error(TN_EINVAL, "internal: GEMM bit positions");
       if (!ref_ok(g.a, ea) || !ref_ok(g.b, eb) || !ref_ok(g.c, ec))
         return set_error(TN_EINVAL, "internal: GEMM buffer out of range");
     }
@@ -589,9 +810,33 @@ tn_status compile_program(const tn_network* net, tn_path* path) {
     for (int s = 0; s < path->n_small; ++s) trees[root[s]].push_back(s);
     path->small_lists.push_back(0);
     for (auto& kv : trees) {
-      for (int s : kv.second) path->small_steps.push_back(path->steps[s].sm);
+      const std::vector<int>& lst = kv.second;
+      const size_t first = path->small_steps.size();
+      for (int s : lst) path->small_steps.push_back(path->steps[s].sm);
+      // a result consumed by the very next step of the list stays in an LDS slot (alternating)
+      for (size_t i = 0; i + 1 < lst.size(); ++i) {
+        const int s = lst[i], nx = lst[i + 1];
+        if (loc[T + s].elems > (1 << kSmallMaxBits)) continue;
+        SmallStep& c = path->small_steps[first + i];
+        SmallStep& n = path->small_steps[first + i + 1];
+        const int slot = (i % 2) ? BUF_LDS1 : BUF_LDS0;
+        bool used = false;
+        if (path->pairs[2 * nx] == T + s) { n.a_buf = slot; n.a_off = 0; used = true; }
+        if (path->pairs[2 * nx + 1] == T + s) { n.b_buf = slot; n.b_off = 0; used = true; }
+        if (used) { c.c_buf = slot; c.c_off = 0; }
+      }
+      for (size_t i = first; i < path->small_steps.size(); ++i) {
+        SmallStep& d = path->small_steps[i];
+        d.alias = (d.c_buf == d.a_buf && d.c_off == d.a_off) || (d.c_buf == d.b_buf && d.c_off == d.b_off);
+      }
       path->small_lists.push_back((int32_t)path->small_steps.size());
     }
+  }
+  build_chains(path, T);
+  st.n_sweep_steps = st.n_sweep_passes = 0;
+  for (const SweepChain& ch : path->chains) {
+    st.n_sweep_steps += ch.n_steps;
+    st.n_sweep_passes += ch.n_passes;
   }
   st.n_small_steps = path->n_small;
   st.n_small_lists = path->small_lists.empty() ? 0 : (int32_t)path->small_lists.size() - 1;
@@ -622,8 +867,15 @@ double modeled_seconds(const tn_path* path) {
       longest = std::max(longest, (size_t)(path->small_lists[i + 1] - path->small_lists[i]));
     t += kLaunch + 1.5e-6 * (double)longest;
   }
+  constexpr double kLds = 40e12;  // sustained LDS traffic of the fused passes, bytes/s
+  for (const SweepChain& ch : path->chains)
+    for (int i = 0; i < ch.n_passes; ++i) {
+      const SweepPass& ps = path->passes[ch.first_pass + i];
+      const double e = std::ldexp(1.0, ch.bits);
+      t += kLaunch + 16.0 * e / kHbm + 16.0 * e * ps.n_segs / kLds + 2.0 * e * ps.n_gates / 60e12;
+    }
   for (const StepProgram& P : path->steps) {
-    if (P.kind == SK_SMALL) continue;
+    if (P.kind == SK_SMALL || P.chain != -1) continue;
     t += kLaunch;
     for (const PermuteDesc& pd : P.pre) t += kLaunch + 16.0 * std::ldexp(1.0, pd.bits) / kPerm;
     if (P.kind == SK_SKINNY) {
@@ -668,7 +920,8 @@ extern "C" tn_status tn_plan_path(const tn_network* net, const tn_plan_opts* opt
       return set_error(s, "largest intermediate 2^" + std::to_string((int)max_log2) + cap_msg);
     }
     p->pairs = reorder_small_first(net, p->pairs, &p->n_small, &p->small_region);
-    s = compile_program(net, p);
+    const std::vector<int32_t> fl = output_layout(net);
+    s = compile_program(net, p, &fl);
     if (s != TN_OK) { delete p; return s; }
     p->stats.modeled_seconds = modeled_seconds(p);
   } else {
@@ -696,7 +949,8 @@ extern "C" tn_status tn_plan_path(const tn_network* net, const tn_plan_opts* opt
       min_log2 = std::min(min_log2, (int)ml);
       if (s == TN_OK) {
         q->pairs = reorder_small_first(net, q->pairs, &q->n_small, &q->small_region);
-        s = compile_program(net, q);
+        const std::vector<int32_t> fl = output_layout(net);
+        s = compile_program(net, q, &fl);
       }
       if (s != TN_OK) {
         delete q;

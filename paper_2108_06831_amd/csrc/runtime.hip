@@ -1,6 +1,7 @@
 // Device runtime: uploads network tables, lays out the caller's workspace,
 // executes compiled programs and implements the device entry points of tn.h.
 #include <hip/hip_runtime.h>
+#include <math.h>
 #include <string.h>
 
 #include <algorithm>
@@ -146,6 +147,8 @@ struct DevPath {
   int device = -1;
   SmallStep* steps = nullptr;
   int32_t* lists = nullptr;
+  SweepGateDesc* sweep_gates = nullptr;
+  SweepSegment* segments = nullptr;
 };
 
 static tn_status ensure_path_device(tn_path* path, DevPath** out) {
@@ -159,6 +162,8 @@ static tn_status ensure_path_device(tn_path* path, DevPath** out) {
   path->dev = d;
   HIP_TRY(upload(&d->steps, path->small_steps));
   HIP_TRY(upload(&d->lists, path->small_lists));
+  HIP_TRY(upload(&d->sweep_gates, path->sweep_gates));
+  HIP_TRY(upload(&d->segments, path->segments));
   *out = d;
   return TN_OK;
 }
@@ -171,6 +176,8 @@ void device_release_path(tn_path* path) {
   (void)hipSetDevice(d->device);
   (void)hipFree(d->steps);
   (void)hipFree(d->lists);
+  (void)hipFree(d->sweep_gates);
+  (void)hipFree(d->segments);
   (void)hipSetDevice(cur);
   delete d;
   path->dev = nullptr;
@@ -194,7 +201,7 @@ static WsLayout layout_ws(const tn_network* net, const tn_path* path, int batch,
   return L;
 }
 
-static size_t expect_aux(int batch) { return sizeof(double) * (size_t)kReduceBlocks * batch; }
+static size_t expect_aux(int batch) { return sizeof(double) * (size_t)kExpectBlocks * batch; }
 
 // ---------------------------------------------------------------------------
 // program execution
@@ -206,6 +213,9 @@ struct Bases {
   int64_t ws_bs = 0;
   float2* out = nullptr;
   int64_t out_bs = 0;
+  // when set, the last step (a matrix product) writes here instead of its workspace buffer
+  float2* final_out = nullptr;
+  int64_t final_out_bs = 0;
   // contract_pair: inputs are two separate user buffers
   const float2* pair_a = nullptr;
   const float2* pair_b = nullptr;
@@ -228,10 +238,12 @@ static float2* resolve(const Bases& b, const BufRef& r, int64_t* bs) {
 }
 
 static tn_status run_steps(hipStream_t s, tn_path* path, const Bases& B, int batch, int precision) {
-  if (path->n_small > 0) {
-    DevPath* dp;
+  DevPath* dp = nullptr;
+  if (path->n_small > 0 || !path->chains.empty()) {
     tn_status st = ensure_path_device(path, &dp);
     if (st != TN_OK) return st;
+  }
+  if (path->n_small > 0) {
     int64_t ibs, wbs;
     BufRef ri, rw;
     ri.buf = BUF_IN;
@@ -244,10 +256,36 @@ static tn_status run_steps(hipStream_t s, tn_path* path, const Bases& B, int bat
                                precision));
     double fl = 0, by = 0;
     for (int i = 0; i < path->n_small; ++i) { fl += path->steps[i].flops; by += path->steps[i].bytes; }
-    prof_stop(s, ev, TN_KERNEL_FUSED, by * batch, fl * batch);
+    prof_stop(s, ev, TN_KERNEL_INTERP, by * batch, fl * batch);
   }
   for (size_t si = path->n_small; si < path->steps.size(); ++si) {
     const StepProgram& P = path->steps[si];
+    if (P.chain == -2) continue;
+    if (P.chain >= 0) {
+      const SweepChain& ch = path->chains[P.chain];
+      int64_t ibs, obs, IN_bs, WS_bs;
+      float2* ip = resolve(B, ch.in, &ibs);
+      float2* op = resolve(B, ch.out, &obs);
+      BufRef ri, rw;
+      ri.buf = BUF_IN;
+      rw.buf = BUF_WS;
+      float2* INp = resolve(B, ri, &IN_bs);
+      float2* WSp = resolve(B, rw, &WS_bs);
+      for (int k = 0; k < ch.n_passes; ++k) {
+        const SweepPass& ps = path->passes[ch.first_pass + k];
+        hipEvent_t ev = prof_start(s);
+        HIP_TRY(launch_sweep_pass(s, ps, ch.bits, dp->sweep_gates, dp->segments, k == 0 ? ip : op,
+                                  k == 0 ? ibs : obs, op, obs, INp, IN_bs, WSp, WS_bs, batch, precision));
+        double fl = 0;
+        for (int g = 0; g < ps.n_gates; ++g) {
+          const SweepGateDesc& gd = path->sweep_gates[ps.first_gate + g];
+          fl += gd.diag ? 8.0 : 8.0 * (1 << gd.n);
+        }
+        prof_stop(s, ev, TN_KERNEL_SWEEP, 16.0 * std::ldexp(1.0, ch.bits) * batch,
+                  fl * std::ldexp(1.0, ch.bits) * batch);
+      }
+      continue;
+    }
     for (const PermuteDesc& pd : P.pre) {
       int64_t ibs, obs;
       float2* ip = resolve(B, pd.in, &ibs);
@@ -275,8 +313,14 @@ static tn_status run_steps(hipStream_t s, tn_path* path, const Bases& B, int bat
       float2* c = resolve(B, P.gm.c, &cbs);
       const GemmDesc& g = P.gm;
       const double bytes = 8.0 * batch * (double)g.batch * (double)(g.M * g.K + g.K * g.N + g.M * g.N);
+      int64_t tbs = 0;
+      float2* tmp = g.split > 1 ? resolve(B, g.tmp, &tbs) : nullptr;
+      if (si + 1 == path->steps.size() && B.final_out) {
+        c = B.final_out;  // the last product writes the caller's output directly
+        cbs = B.final_out_bs;
+      }
       hipEvent_t ev = prof_start(s);
-      HIP_TRY(launch_gemm(s, P.gm, a, abs_, b, bbs, c, cbs, batch, precision));
+      HIP_TRY(launch_gemm(s, P.gm, a, abs_, b, bbs, c, cbs, tmp, tbs, batch, precision));
       prof_stop(s, ev, TN_KERNEL_GEMM, bytes, P.flops * batch);
     }
   }
@@ -439,10 +483,17 @@ extern "C" tn_status tn_contract_path(void* stream, int32_t precision, tn_networ
   B.ws_bs = path->ws_elems;
   B.out = (float2*)out_dev;
   B.out_bs = (int64_t)1 << net->n_qubits;
-  if ((st = materialize(s, net, d, params_dev, batch, nullptr, 0, B.in)) != TN_OK) return st;
-  if ((st = run_steps(s, path, B, batch, precision)) != TN_OK) return st;
   std::vector<int32_t> to;
   for (int q = 0; q < net->n_qubits; ++q) to.push_back(lab(net->wire_final[q], 0));
+  const bool direct = !path->steps.empty() && path->steps.back().kind == SK_GEMM && path->steps.back().chain == -1 &&
+                      path->final_bits == to;
+  if (direct) {
+    B.final_out = B.out;
+    B.final_out_bs = B.out_bs;
+  }
+  if ((st = materialize(s, net, d, params_dev, batch, nullptr, 0, B.in)) != TN_OK) return st;
+  if ((st = run_steps(s, path, B, batch, precision)) != TN_OK) return st;
+  if (direct) return TN_OK;
   return finish_to(s, B, path, to, B.out, B.out_bs, B.out_bs, batch, (float2*)(w + L.aux_off));
 }
 
@@ -469,10 +520,17 @@ extern "C" tn_status tn_amplitudes(void* stream, int32_t precision, tn_network* 
   B.in_bs = net->input_elems;
   B.ws = (float2*)(w + L.arena_off);
   B.ws_bs = path->ws_elems;
-  if ((st = materialize(s, net, d, params_dev, 1, bitstrings_dev, count, B.in)) != TN_OK) return st;
-  if ((st = run_steps(s, path, B, 1, precision)) != TN_OK) return st;
   std::vector<int32_t> to;
   for (int j = net->batch_log2 - 1; j >= 0; --j) to.push_back(lab(net->batch_mode, j));
+  const bool direct = !path->steps.empty() && path->steps.back().kind == SK_GEMM && path->steps.back().chain == -1 &&
+                      path->final_bits == to && count == path->final_elems;
+  if (direct) {
+    B.final_out = (float2*)out_dev;
+    B.final_out_bs = count;
+  }
+  if ((st = materialize(s, net, d, params_dev, 1, bitstrings_dev, count, B.in)) != TN_OK) return st;
+  if ((st = run_steps(s, path, B, 1, precision)) != TN_OK) return st;
+  if (direct) return TN_OK;
   return finish_to(s, B, path, to, (float2*)out_dev, count, count, 1, (float2*)(w + L.aux_off));
 }
 
@@ -689,7 +747,6 @@ tn_status make_pair_plan(int32_t rank_a, const int32_t* modes_a, const int64_t* 
   for (int i = 0; i < rank_c; ++i) net.output_modes.push_back(id[modes_c[i]]);
   net.input_elems = ta.size + tb.size;
   pp->path.pairs = {0, 1};
-  if ((st = compile_program(&net, &pp->path)) != TN_OK) return st;
   pp->a_elems = ta.size;
   pp->c_elems = 1;
   for (int i = 0; i < rank_c; ++i) {
@@ -697,6 +754,7 @@ tn_status make_pair_plan(int32_t rank_a, const int32_t* modes_a, const int64_t* 
     for (int j = net.mode_log2[m] - 1; j >= 0; --j) pp->c_bits.push_back(lab(m, j));
     pp->c_elems <<= net.mode_log2[m];
   }
+  if ((st = compile_program(&net, &pp->path, &pp->c_bits)) != TN_OK) return st;
   return TN_OK;
 }
 
@@ -730,6 +788,12 @@ extern "C" tn_status tn_contract_pair(void* stream, int32_t precision, const voi
   B.pair_a_elems = pp.a_elems;
   B.ws = (float2*)workspace_dev;
   B.ws_bs = 0;
+  const bool direct = pp.path.steps.back().kind == SK_GEMM && pp.path.final_bits == pp.c_bits;
+  if (direct) {
+    B.final_out = (float2*)c;
+    B.final_out_bs = 0;
+  }
   if ((st = run_steps(s, &pp.path, B, 1, precision)) != TN_OK) return st;
+  if (direct) return TN_OK;
   return finish_to(s, B, &pp.path, pp.c_bits, (float2*)c, 0, pp.c_elems, 1, nullptr);
 }

@@ -98,7 +98,9 @@ def config1_reference():
 
 @pytest.mark.parametrize("kind,fuse,precision,tol", [
     ("search", "split", "c64", C64_TOL), ("search", "split", "bf16x3", BF16X3_TOL),
-    ("greedy", "dense", "c64", C64_TOL), ("sequential", "split", "c64", C64_TOL)])
+    ("greedy", "dense", "c64", C64_TOL), ("sequential", "split", "c64", C64_TOL),
+    ("sequential", "dense", "c64", C64_TOL), ("sequential", "dense", "bf16x3", BF16X3_TOL),
+    ("search", "dense", "c64", C64_TOL)])
 def test_config1_full_statevector(kind, fuse, precision, tol):
     """24 qubits, depth 16, 2-qubit fusion: the full 2^24 state."""
     circ = workloads.config1()
@@ -167,3 +169,84 @@ def test_config4_gradients_small():
         e = np.linalg.norm(grad[b] - g) / np.linalg.norm(g)
         print(f"  batch {b}: grad rel err {e:.2e}", flush=True)
         assert e < C64_TOL
+
+
+def test_config2_full_size_orders_agree():
+    """32-qubit grid, 4096 amplitudes: the FP64 state (64 GiB) is out of the
+    oracle's reach here, so the full-size check is a property of the method:
+    two different contraction orders give the same amplitudes (Sec. 2.2.3)."""
+    from paper_2108_06831_amd import Network, amplitudes
+    circ, bits = workloads.config2()
+    net = Network.from_circuit(circ, output="amplitudes", n_bitstrings=4096)
+    a1 = amplitudes(net, net.plan("search", max_log2_intermediate=28, trials=32), bits).cpu().numpy()
+    a2 = amplitudes(net, net.plan("greedy", max_log2_intermediate=28), bits).cpu().numpy()
+    a3 = amplitudes(net, net.plan("search", max_log2_intermediate=28, trials=32, seed=7), bits).cpu().numpy()
+    e12, e13 = relerr(a1, a2), relerr(a1, a3)
+    print(f"config2 full: order agreement {e12:.2e} {e13:.2e}; mean 2^n|a|^2 = "
+          f"{np.mean(np.abs(a1) ** 2) * 2 ** 32:.3f}", flush=True)
+    assert e12 < 2 * C64_TOL and e13 < 2 * C64_TOL
+    # Porter-Thomas: for a random circuit E[2^n |a|^2] = 1 (loose statistical sanity, 4096 samples)
+    assert 0.8 < np.mean(np.abs(a1) ** 2) * 2 ** 32 < 1.2
+
+
+def test_config3_full_batch():
+    """All 512 QAOA circuits in one call: the oracle on a sample spanning every
+    size, beta = 0 (<C> = |E|/2) on all 512, and the p = 1 closed form on the
+    same 512 graphs."""
+    from paper_2108_06831_amd import Network, Observable, expectation
+    from tests.test_oracle import qaoa_p1_closed_form
+    inst = workloads.config3()
+    nets = [Network.from_circuit(it.circuit) for it in inst]
+    paths = [nt.plan("sequential") for nt in nets]
+    obs = [Observable(*workloads.maxcut_observable(it.circuit.n_qubits, it.edges)) for it in inst]
+    got = expectation(nets, paths, [it.params for it in inst], obs).cpu().numpy()[:, 0]
+    sample = []
+    for n in (16, 18, 20, 22, 24, 26):
+        sample += [i for i, it in enumerate(inst) if it.circuit.n_qubits == n][:1]
+    for i in sample:
+        it = inst[i]
+        m, c = workloads.maxcut_observable(it.circuit.n_qubits, it.edges)
+        want = oracle.circuit_expectation(it.circuit, it.params, m, c)
+        print(f"  circuit {i} n={it.circuit.n_qubits}: {got[i]:.8f} vs {want:.8f}", flush=True)
+        assert scalar_err(got[i], want) < C64_TOL
+    p0 = [np.concatenate([it.params[:4], np.zeros(4)]) for it in inst]
+    g0 = expectation(nets, paths, p0, obs).cpu().numpy()[:, 0]
+    for it, g in zip(inst, g0):
+        assert scalar_err(g, len(it.edges) / 2) < C64_TOL
+    p1 = [workloads.qaoa_circuit(it.circuit.n_qubits, it.edges, 1) for it in inst]
+    nets1 = [Network.from_circuit(c) for c in p1]
+    paths1 = [nt.plan("sequential") for nt in nets1]
+    prm1 = [np.array([it.params[0], it.params[4]]) for it in inst]
+    g1 = expectation(nets1, paths1, prm1, obs).cpu().numpy()[:, 0]
+    worst = 0.0
+    for it, g, pr in zip(inst, g1, prm1):
+        want = qaoa_p1_closed_form(it.circuit.n_qubits, it.edges, pr[0], pr[1])
+        worst = max(worst, scalar_err(g, want))
+    print(f"  p=1 closed form, worst error over 512 circuits {worst:.2e}", flush=True)
+    assert worst < C64_TOL
+
+
+def test_config4_full_gradients():
+    """20 qubits, 10 layers, 64 parameter vectors: adjoint gradients against
+    the oracle's exact parameter shift on sampled angles of vectors 0 and 63,
+    and against central differences (h = 1e-3, FD = g sin(h)/h exactly)."""
+    from paper_2108_06831_amd import Network, Observable, backward
+    circ, params, (m, c) = workloads.config4()
+    net = Network.from_circuit(circ)
+    path = net.plan("sequential")
+    value, grad = backward(net, path, params, Observable(m, c), batch=64)
+    value, grad = value.cpu().numpy(), grad.cpu().numpy()
+    rng = np.random.default_rng(99)
+    which = sorted(rng.choice(circ.n_params, size=8, replace=False).tolist())
+    for b in (0, 63):
+        want_e = oracle.circuit_expectation(circ, params[b], m, c)
+        assert scalar_err(value[b], want_e) < C64_TOL
+        g = oracle.param_shift_gradient(circ, params[b], m, c, which=which)
+        e = np.linalg.norm(grad[b, which] - g[which]) / np.linalg.norm(g[which])
+        print(f"  vector {b}: value err {scalar_err(value[b], want_e):.2e}, grad rel err {e:.2e}", flush=True)
+        assert e < C64_TOL
+    h = 1e-3
+    fd = oracle.finite_difference_gradient(circ, params[0], m, c, h=h, which=which[:4])
+    e = np.linalg.norm(grad[0, which[:4]] - fd[which[:4]] / (np.sin(h) / h)) / np.linalg.norm(fd[which[:4]])
+    print(f"  FD check rel err {e:.2e}", flush=True)
+    assert e < C64_TOL

@@ -222,3 +222,27 @@ def test_observable_marshalling():
     masks, coeffs = workloads.maxcut_observable(4, [(0, 1), (2, 3)])
     o = Observable(masks, coeffs)
     assert o.c.n_terms == 3
+
+
+@pytest.mark.parametrize("shapes", [
+    ([1, 1], [1, 1], [0, 2]),          # M = N = K = 1
+    ([], [2, 2], [1, 2]),              # scalar times a matrix (no shared mode)
+    ([2], [2, 4], [2]),                # vector-matrix, summed mode
+    ([4, 4], [4, 4], [0, 1, 2]),       # batch mode shared by both and kept
+])
+def test_contract_pair_plans_tiny_shapes(shapes):
+    """Planning a single pairwise contraction (no device call): operands that
+    are not gate tensors of a network, including extent-1 and rank-0 ones."""
+    ea, eb, mc = shapes
+    lib = _lib.lib()
+    ma = list(range(len(ea)))
+    mb = [1, 2][: len(eb)] if len(ea) != 0 else [1, 2]
+    if shapes[2] == [0, 1, 2]:
+        ma, mb = [0, 1], [1, 2]
+    if len(ea) == 1:
+        ma, mb = [1], [1, 2]
+    arr = lambda t, v: (t * max(len(v), 1))(*v)
+    n = lib.tn_contract_pair_workspace_bytes(len(ma), arr(ctypes.c_int32, ma), arr(ctypes.c_int64, ea), len(mb),
+                                             arr(ctypes.c_int32, mb), arr(ctypes.c_int64, eb), len(mc),
+                                             arr(ctypes.c_int32, mc))
+    assert n > 0, _lib.lib().tn_last_error()
