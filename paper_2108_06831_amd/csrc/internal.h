@@ -173,7 +173,7 @@ constexpr int kSmallDescCache = 128;  // step descriptors staged in LDS at a tim
 struct SmallStep {
   int32_t a_buf, b_buf, c_buf;  // BUF_IN / BUF_WS, or an LDS slot for a result the next step consumes
   int32_t c_bits, k_bits;
-  int32_t alias;                // C overwrites an operand in memory: read the whole step before writing
+  int16_t a_bits, b_bits;       // operand sizes (log2 elements)
   int64_t a_off, b_off, c_off;
   int8_t apos[kSmallMaxBits], bpos[kSmallMaxBits];
   int8_t ka[kSmallMaxBits], kb[kSmallMaxBits];
@@ -206,8 +206,9 @@ struct tn_path {
   int32_t n_inputs = 0;
   // leading steps run by the interpreter kernel: independent sub-trees, one work list each
   int32_t n_small = 0;
-  std::vector<tnq::SmallStep> small_steps;   // grouped by work list
-  std::vector<int32_t> small_lists;          // offsets into small_steps, size n_lists + 1
+  std::vector<tnq::SmallStep> small_steps;   // grouped by work list, and by level inside a list
+  std::vector<int32_t> small_lists;          // list w owns levels small_lists[w] .. small_lists[w+1]-1
+  std::vector<int32_t> small_levels;         // level i owns steps small_levels[i] .. small_levels[i+1]-1
   int64_t small_region = 0;                  // workspace elements reserved for their results
   // fused streaming chains
   std::vector<tnq::SweepChain> chains;

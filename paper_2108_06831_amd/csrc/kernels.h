@@ -31,6 +31,8 @@ hipError_t launch_permute(hipStream_t s, const PermuteDesc& d, const float2* in,
                           int64_t out_bs, int batch);
 
 // C[b] = A[b] B[b] on complex64 with FP32 MFMA accumulation.
+// Products too narrow for matrix-core tiles run one output per thread on the vector ALUs.
+inline bool gemm_uses_vector_alu(const GemmDesc& d) { return (d.M < 64 || d.N < 32) && d.K <= 1024; }
 // With d.split > 1 the partial products go to `tmp` ([split][C], same layout as C) and are summed into C.
 hipError_t launch_gemm(hipStream_t s, const GemmDesc& d, const float2* a, int64_t a_bs, const float2* b, int64_t b_bs,
                        float2* c, int64_t c_bs, float2* tmp, int64_t tmp_bs, int batch, int precision);
@@ -48,11 +50,12 @@ constexpr int kExpectBlocks = 4096;  // blocks of the expectation reduction
 hipError_t launch_expectation(hipStream_t s, const float2* psi, int64_t psi_bs, int64_t n_elems, const ZTerms& terms,
                               int batch, double* partial, double* out, int64_t out_stride);
 
-// Interpreter of small steps: work list w (steps list_off[w] .. list_off[w+1]-1,
-// each depending only on inputs or earlier steps of the same list) runs in
-// workgroup (w, batch item).
-hipError_t launch_small_steps(hipStream_t s, const SmallStep* steps, const int32_t* list_off, int n_lists,
-                              float2* in, int64_t in_bs, float2* ws, int64_t ws_bs, int batch, int precision);
+// Interpreter of small steps: work list w (levels list_off[w] .. list_off[w+1]-1,
+// level i = steps level_off[i] .. level_off[i+1]-1, each depending only on
+// inputs or on earlier levels of the same list) runs in workgroup (w, batch item).
+hipError_t launch_small_steps(hipStream_t s, const SmallStep* steps, const int32_t* list_off,
+                              const int32_t* level_off, int n_lists, float2* in, int64_t in_bs, float2* ws,
+                              int64_t ws_bs, int batch, int precision);
 
 // One fused streaming pass over a 2^bits tensor (see SweepPass).
 hipError_t launch_sweep_pass(hipStream_t s, const SweepPass& ps, int bits, const SweepGateDesc* gates_dev,

@@ -232,81 +232,107 @@ hipError_t launch_skinny(hipStream_t s, const SkinnyDesc& d, const float2* g, in
 // A step is computed into registers, then written after a barrier, so a step
 // may overwrite one of its own operands.
 // ---------------------------------------------------------------------------
-constexpr int kSmallPerThread = (1 << kSmallMaxBits) / kThreads;
+constexpr int kSmallStage = 12288;  // operand elements staged in LDS per round (96 KB)
 
 template <int PREC>
 __global__ __launch_bounds__(kThreads) void k_small_steps(const SmallStep* steps, const int32_t* list_off,
-                                                          float2* in, int64_t in_bs, float2* ws, int64_t ws_bs) {
+                                                          const int32_t* level_off, float2* in, int64_t in_bs,
+                                                          float2* ws, int64_t ws_bs) {
   __shared__ SmallStep desc[kSmallDescCache];
-  __shared__ float2 slot[2][1 << kSmallMaxBits];
+  __shared__ int32_t first_out[kSmallDescCache + 1];  // prefix of output counts over a round's steps
+  __shared__ int32_t a_at[kSmallDescCache], b_at[kSmallDescCache];  // staging offsets of the operands
+  __shared__ int32_t round_end;
+  __shared__ float2 stage[kSmallStage];
   const int w = blockIdx.x, z = blockIdx.y;
   float2* IN = in + (int64_t)z * in_bs;
   float2* WS = ws + (int64_t)z * ws_bs;
-  auto ptr = [&](int buf, int64_t off) -> float2* {
-    return buf == BUF_LDS0 ? slot[0] : buf == BUF_LDS1 ? slot[1] : (buf == BUF_IN ? IN : WS) + off;
-  };
-  const int s0 = list_off[w], s1 = list_off[w + 1];
-  for (int cb = s0; cb < s1; cb += kSmallDescCache) {
-    const int ce = min(s1, cb + kSmallDescCache);
-    {
-      // stage this chunk of descriptors in LDS (copied as 32-bit words)
-      const int words = (ce - cb) * (int)(sizeof(SmallStep) / 4);
-      const uint32_t* src = reinterpret_cast<const uint32_t*>(steps + cb);
-      uint32_t* dst = reinterpret_cast<uint32_t*>(desc);
-      for (int i = threadIdx.x; i < words; i += kThreads) dst[i] = src[i];
-    }
-    __syncthreads();
-    for (int s = cb; s < ce; ++s) {
-      const SmallStep& st = desc[s - cb];
-      const float2* A = ptr(st.a_buf, st.a_off);
-      const float2* B = ptr(st.b_buf, st.b_off);
-      float2* C = ptr(st.c_buf, st.c_off);
-      const int n_out = 1 << st.c_bits, n_k = 1 << st.k_bits;
-      float2 res[kSmallPerThread];
-#pragma unroll
-      for (int r = 0; r < kSmallPerThread; ++r) {
-        const int o = threadIdx.x + r * kThreads;
-        res[r] = f2(0.f, 0.f);
-        if (o < n_out) {
+  for (int lv = list_off[w]; lv < list_off[w + 1]; ++lv) {
+    const int l0 = level_off[lv], l1 = level_off[lv + 1];
+    for (int cb = l0; cb < l1; cb += kSmallDescCache) {
+      const int ce = min(l1, cb + kSmallDescCache), ns = ce - cb;
+      {
+        const int words = ns * (int)(sizeof(SmallStep) / 4);
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(steps + cb);
+        uint32_t* dst = reinterpret_cast<uint32_t*>(desc);
+        for (int i = threadIdx.x; i < words; i += kThreads) dst[i] = src[i];
+      }
+      __syncthreads();
+      // rounds: as many of the level's (independent) steps as their operands fit in LDS
+      for (int r0 = 0; r0 < ns;) {
+        if (threadIdx.x == 0) {
+          int used = 0, outs = 0, i = r0;
+          for (; i < ns; ++i) {
+            const int need = (1 << desc[i].a_bits) + (1 << desc[i].b_bits);
+            if (i > r0 && used + need > kSmallStage) break;
+            a_at[i] = used;
+            b_at[i] = used + (1 << desc[i].a_bits);
+            used += need;
+            first_out[i] = outs;
+            outs += 1 << desc[i].c_bits;
+          }
+          first_out[i] = outs;
+          round_end = i;
+        }
+        __syncthreads();
+        const int r1 = round_end;
+        // stage the operands with coalesced copies
+        for (int i = r0; i < r1; ++i) {
+          const SmallStep& st = desc[i];
+          const float2* A = (st.a_buf == BUF_IN ? IN : WS) + st.a_off;
+          const float2* B = (st.b_buf == BUF_IN ? IN : WS) + st.b_off;
+          for (int e = threadIdx.x; e < (1 << st.a_bits); e += kThreads) stage[a_at[i] + e] = A[e];
+          for (int e = threadIdx.x; e < (1 << st.b_bits); e += kThreads) stage[b_at[i] + e] = B[e];
+        }
+        __syncthreads();
+        const int total = first_out[r1] - first_out[r0];
+        for (int g = threadIdx.x; g < total; g += kThreads) {
+          const int gg = g + first_out[r0];
+          int lo = r0, hi = r1 - 1;  // the step owning output gg
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (first_out[mid] <= gg) lo = mid; else hi = mid - 1;
+          }
+          const SmallStep& st = desc[lo];
+          const int o = gg - first_out[lo];
+          const float2* As = stage + a_at[lo];
+          const float2* Bs = stage + b_at[lo];
+          float2* C = (st.c_buf == BUF_IN ? IN : WS) + st.c_off;
           int ab = 0, bb = 0;
           for (int p = 0; p < st.c_bits; ++p)
             if ((o >> p) & 1) {
               if (st.apos[p] >= 0) ab |= 1 << st.apos[p];
               if (st.bpos[p] >= 0) bb |= 1 << st.bpos[p];
             }
+          const int kb = st.k_bits;
           float2 acc = f2(0.f, 0.f);
-          for (int k = 0; k < n_k; ++k) {
+          for (int k = 0; k < (1 << kb); ++k) {
             int ao = ab, bo = bb;
-            for (int j = 0; j < st.k_bits; ++j)
+            for (int j = 0; j < kb; ++j)
               if ((k >> j) & 1) {
                 ao |= 1 << st.ka[j];
                 bo |= 1 << st.kb[j];
               }
-            acc = cmac<PREC>(acc, A[ao], B[bo]);
+            acc = cmac<PREC>(acc, As[ao], Bs[bo]);
           }
-          res[r] = acc;
+          C[o] = acc;
         }
+        __syncthreads();
+        r0 = r1;
       }
-      if (st.alias) __syncthreads();  // every read of the step before any write over an operand
-#pragma unroll
-      for (int r = 0; r < kSmallPerThread; ++r) {
-        const int o = threadIdx.x + r * kThreads;
-        if (o < n_out) C[o] = res[r];
-      }
-      __syncthreads();
     }
   }
 }
 
-hipError_t launch_small_steps(hipStream_t s, const SmallStep* steps, const int32_t* list_off, int n_lists,
-                              float2* in, int64_t in_bs, float2* ws, int64_t ws_bs, int batch, int precision) {
+hipError_t launch_small_steps(hipStream_t s, const SmallStep* steps, const int32_t* list_off,
+                              const int32_t* level_off, int n_lists, float2* in, int64_t in_bs, float2* ws,
+                              int64_t ws_bs, int batch, int precision) {
   if (n_lists == 0) return hipSuccess;
   if (precision == TN_PREC_BF16X3)
-    hipLaunchKernelGGL(k_small_steps<TN_PREC_BF16X3>, dim3(n_lists, batch), dim3(kThreads), 0, s, steps, list_off, in,
-                       in_bs, ws, ws_bs);
+    hipLaunchKernelGGL(k_small_steps<TN_PREC_BF16X3>, dim3(n_lists, batch), dim3(kThreads), 0, s, steps, list_off,
+                       level_off, in, in_bs, ws, ws_bs);
   else
-    hipLaunchKernelGGL(k_small_steps<TN_PREC_C64>, dim3(n_lists, batch), dim3(kThreads), 0, s, steps, list_off, in,
-                       in_bs, ws, ws_bs);
+    hipLaunchKernelGGL(k_small_steps<TN_PREC_C64>, dim3(n_lists, batch), dim3(kThreads), 0, s, steps, list_off,
+                       level_off, in, in_bs, ws, ws_bs);
   return hipGetLastError();
 }
 
@@ -774,6 +800,38 @@ __global__ __launch_bounds__(kThreads) void k_gemm(GemmArgs g) {
       }
 }
 
+// Products too narrow for the matrix-core tiles (M < 64 or N < 32, e.g. a
+// 4096-way batch of 2x2 outer products): one thread per output element, the
+// same deposit-map addressing, K loop on the vector ALUs.
+constexpr int kElemMaxK = 1024;
+
+template <int PREC>
+__global__ __launch_bounds__(kThreads) void k_contract_elem(GemmArgs g) {
+  __shared__ int64_t TKa[kElemMaxK], TKb[kElemMaxK];
+  const int z = blockIdx.y;
+  const float2* A = g.A + (int64_t)z * g.a_bs;
+  const float2* B = g.B + (int64_t)z * g.b_bs;
+  float2* C = g.C + (int64_t)z * g.c_bs;
+  const int K = (int)g.K;
+  for (int k = threadIdx.x; k < K; k += kThreads) {
+    TKa[k] = deposit(k, g.a_k, g.nbk);
+    TKb[k] = deposit(k, g.b_k, g.nbk);
+  }
+  __syncthreads();
+  const int64_t total = g.batch * g.M * g.N;
+  for (int64_t o = (int64_t)blockIdx.x * kThreads + threadIdx.x; o < total; o += (int64_t)gridDim.x * kThreads) {
+    const int64_t n = o & (g.N - 1);
+    const int64_t m = (o >> g.nbn) & (g.M - 1);
+    const int64_t b = o >> (g.nbn + g.nbm);
+    const int64_t db_a = deposit(b, g.a_b, g.nbb), db_b = deposit(b, g.b_b, g.nbb);
+    const int64_t ab = db_a | deposit(m, g.a_m, g.nbm);
+    const int64_t bb = db_b | deposit(n, g.b_n, g.nbn);
+    float2 acc = f2(0.f, 0.f);
+    for (int k = 0; k < K; ++k) acc = cmac<PREC>(acc, A[ab | TKa[k]], B[bb | TKb[k]]);
+    C[deposit(b, g.c_b, g.nbb) | deposit(m, g.c_m, g.nbm) | deposit(n, g.c_n, g.nbn)] = acc;
+  }
+}
+
 // C[i] = sum over s of partial[s][i] (split-K), contiguous per parameter vector
 __global__ void k_sum_partials(const float2* part, int64_t part_bs, int split, int64_t n, float2* C, int64_t c_bs) {
   const int z = blockIdx.y;
@@ -811,6 +869,18 @@ hipError_t launch_gemm(hipStream_t s, const GemmDesc& d, const float2* a, int64_
     g.a_b[j] = d.a_b[j]; g.a_m[j] = d.a_m[j]; g.a_k[j] = d.a_k[j];
     g.b_b[j] = d.b_b[j]; g.b_k[j] = d.b_k[j]; g.b_n[j] = d.b_n[j];
     g.c_b[j] = d.c_b[j]; g.c_m[j] = d.c_m[j]; g.c_n[j] = d.c_n[j];
+  }
+  if (gemm_uses_vector_alu(d)) {
+    g.C = c;
+    g.c_bs = c_bs;
+    g.split = 1;
+    int64_t eb = (g.c_elems + kThreads - 1) / kThreads;
+    if (eb > 65535) eb = 65535;
+    if (precision == TN_PREC_BF16X3)
+      hipLaunchKernelGGL(k_contract_elem<TN_PREC_BF16X3>, dim3((unsigned)eb, batch), dim3(kThreads), 0, s, g);
+    else
+      hipLaunchKernelGGL(k_contract_elem<TN_PREC_C64>, dim3((unsigned)eb, batch), dim3(kThreads), 0, s, g);
+    return hipGetLastError();
   }
   const int64_t blocks = g.tiles_m * g.tiles_n * g.split * d.batch * batch;
   if (blocks > ((int64_t)1 << 24)) return hipErrorInvalidValue;

@@ -483,14 +483,11 @@ tn_status compile_program(const tn_network* net, tn_path* path, const std::vecto
       } else {
         C.bits = cat(filter(A.bits, cls, C_BATCH), filter(A.bits, cls, C_M), filter(B.bits, cls, C_N));
       }
-      if (skinny_like && !Tt.input && Tt.last_use == s && Tt.elems == C.elems) {
-        C.ref = Tt.ref;  // in place (the interpreter reads a whole step before writing it)
-        Tt.ref.buf = -1;
-      } else {
-        C.ref.buf = BUF_WS;
-        C.ref.off = small_bump;
-        small_bump += Alloc::round(C.elems);
-      }
+      // every result of the interpreter gets a buffer of its own: independent steps of a
+      // level run concurrently, so none may overwrite another's operand
+      C.ref.buf = BUF_WS;
+      C.ref.off = small_bump;
+      small_bump += Alloc::round(C.elems);
       SmallStep& d = P.sm;
       d.a_buf = A.ref.buf == -1 ? BUF_WS : A.ref.buf;
       d.b_buf = B.ref.buf == -1 ? BUF_WS : B.ref.buf;
@@ -499,7 +496,8 @@ tn_status compile_program(const tn_network* net, tn_path* path, const std::vecto
       d.c_buf = C.ref.buf;
       d.c_off = C.ref.off;
       d.c_bits = (int32_t)C.bits.size();
-      d.alias = 0;
+      d.a_bits = (int16_t)A.bits.size();
+      d.b_bits = (int16_t)B.bits.size();
       for (int p = 0; p < kSmallMaxBits; ++p) d.apos[p] = d.bpos[p] = d.ka[p] = d.kb[p] = -1;
       for (int p = 0; p < d.c_bits; ++p) {
         const int32_t lab = C.bits[C.bits.size() - 1 - p];
@@ -665,7 +663,8 @@ tn_status compile_program(const tn_network* net, tn_path* path, const std::vecto
       // too few output tiles to fill the chip and a long K loop: split K
       const int64_t tiles = ((g.M + 127) / 128) * ((g.N + 63) / 64) * g.batch;
       g.split = 1;
-      if (tiles < 128 && g.K >= 256) {
+      const bool vector_alu = (g.M < 64 || g.N < 32) && g.K <= 1024;  // the per-output kernel
+      if (!vector_alu && tiles < 128 && g.K >= 256) {
         int64_t sp = 1;
         while (sp < 32 && tiles * sp * 2 <= 512 && g.K / (sp * 2) >= 32) sp *= 2;
         g.split = (int32_t)sp;
@@ -806,31 +805,32 @@ tn_status compile_program(const tn_network* net, tn_path* path, const std::vecto
       const int c = consumer[s];
       root[s] = (c >= 0 && c < path->n_small) ? root[c] : s;
     }
+    // level of a step = 1 + the deepest level among the steps producing its operands;
+    // steps of one level are independent
+    std::vector<int> level(path->n_small, 0);
+    for (int s = 0; s < path->n_small; ++s) {
+      int lv = 0;
+      for (int k = 0; k < 2; ++k) {
+        const int id = path->pairs[2 * s + k];
+        if (id >= T) lv = std::max(lv, level[id - T] + 1);
+      }
+      level[s] = lv;
+    }
     std::map<int, std::vector<int>> trees;
     for (int s = 0; s < path->n_small; ++s) trees[root[s]].push_back(s);
+    path->small_levels.clear();
     path->small_lists.push_back(0);
     for (auto& kv : trees) {
-      const std::vector<int>& lst = kv.second;
-      const size_t first = path->small_steps.size();
-      for (int s : lst) path->small_steps.push_back(path->steps[s].sm);
-      // a result consumed by the very next step of the list stays in an LDS slot (alternating)
-      for (size_t i = 0; i + 1 < lst.size(); ++i) {
-        const int s = lst[i], nx = lst[i + 1];
-        if (loc[T + s].elems > (1 << kSmallMaxBits)) continue;
-        SmallStep& c = path->small_steps[first + i];
-        SmallStep& n = path->small_steps[first + i + 1];
-        const int slot = (i % 2) ? BUF_LDS1 : BUF_LDS0;
-        bool used = false;
-        if (path->pairs[2 * nx] == T + s) { n.a_buf = slot; n.a_off = 0; used = true; }
-        if (path->pairs[2 * nx + 1] == T + s) { n.b_buf = slot; n.b_off = 0; used = true; }
-        if (used) { c.c_buf = slot; c.c_off = 0; }
+      std::vector<int> lst = kv.second;
+      std::stable_sort(lst.begin(), lst.end(), [&](int x, int y) { return level[x] < level[y]; });
+      for (size_t i = 0; i < lst.size(); ++i) {
+        if (i == 0 || level[lst[i]] != level[lst[i - 1]])
+          path->small_levels.push_back((int32_t)path->small_steps.size());
+        path->small_steps.push_back(path->steps[lst[i]].sm);
       }
-      for (size_t i = first; i < path->small_steps.size(); ++i) {
-        SmallStep& d = path->small_steps[i];
-        d.alias = (d.c_buf == d.a_buf && d.c_off == d.a_off) || (d.c_buf == d.b_buf && d.c_off == d.b_off);
-      }
-      path->small_lists.push_back((int32_t)path->small_steps.size());
+      path->small_lists.push_back((int32_t)path->small_levels.size());
     }
+    path->small_levels.push_back((int32_t)path->small_steps.size());
   }
   build_chains(path, T);
   st.n_sweep_steps = st.n_sweep_passes = 0;
@@ -862,17 +862,18 @@ double modeled_seconds(const tn_path* path) {
   constexpr double kLaunch = 5e-6, kHbm = 6.0e12, kPerm = 1.6e12, kMfma = 95e12;
   double t = 0;
   if (path->n_small > 0) {
-    size_t longest = 0;
+    size_t deepest = 0;  // levels of the deepest work list
     for (size_t i = 0; i + 1 < path->small_lists.size(); ++i)
-      longest = std::max(longest, (size_t)(path->small_lists[i + 1] - path->small_lists[i]));
-    t += kLaunch + 1.5e-6 * (double)longest;
+      deepest = std::max(deepest, (size_t)(path->small_lists[i + 1] - path->small_lists[i]));
+    t += kLaunch + 2.0e-6 * (double)deepest;
   }
   constexpr double kLds = 40e12;  // sustained LDS traffic of the fused passes, bytes/s
   for (const SweepChain& ch : path->chains)
     for (int i = 0; i < ch.n_passes; ++i) {
       const SweepPass& ps = path->passes[ch.first_pass + i];
       const double e = std::ldexp(1.0, ch.bits);
-      t += kLaunch + 16.0 * e / kHbm + 16.0 * e * ps.n_segs / kLds + 2.0 * e * ps.n_gates / 60e12;
+      // measured: about 20 vector instructions per element and gate on 64 lanes per CU
+      t += kLaunch + 16.0 * e / kHbm + 16.0 * e * ps.n_segs / kLds + 5.0e-13 * e * ps.n_gates;
     }
   for (const StepProgram& P : path->steps) {
     if (P.kind == SK_SMALL || P.chain != -1) continue;
@@ -882,11 +883,15 @@ double modeled_seconds(const tn_path* path) {
       t += P.bytes / kHbm;
     } else {
       const GemmDesc& g = P.gm;
-      const double tiles = (double)((g.M + 127) / 128) * (double)((g.N + 63) / 64) * (double)g.batch;
+      const double bytes = 8.0 * (double)g.batch * (double)(g.M * g.K + g.K * g.N + g.M * g.N);
+      if ((g.M < 64 || g.N < 32) && g.K <= 1024) {  // per-output vector kernel
+        t += std::max(P.flops / 20e12, bytes / kHbm);
+        continue;
+      }
+      const double tiles = (double)((g.M + 127) / 128) * (double)((g.N + 63) / 64) * (double)g.batch * g.split;
       const double eff = std::min(1.0, g.M / 128.0) * std::min(1.0, g.N / 64.0) * std::min(1.0, g.K / 32.0) *
                          std::min(1.0, tiles / 256.0);
-      const double bytes = 8.0 * (double)g.batch * (double)(g.M * g.K + g.K * g.N + g.M * g.N);
-      t += std::max(P.flops / (kMfma * std::max(eff, 1e-3)), bytes / kHbm);
+      t += std::max(P.flops / (kMfma * std::max(eff, 1e-3)), bytes / kHbm) + (g.split > 1 ? kLaunch : 0.0);
     }
   }
   return t;

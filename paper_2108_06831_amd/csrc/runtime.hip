@@ -147,6 +147,7 @@ struct DevPath {
   int device = -1;
   SmallStep* steps = nullptr;
   int32_t* lists = nullptr;
+  int32_t* levels = nullptr;
   SweepGateDesc* sweep_gates = nullptr;
   SweepSegment* segments = nullptr;
 };
@@ -162,6 +163,7 @@ static tn_status ensure_path_device(tn_path* path, DevPath** out) {
   path->dev = d;
   HIP_TRY(upload(&d->steps, path->small_steps));
   HIP_TRY(upload(&d->lists, path->small_lists));
+  HIP_TRY(upload(&d->levels, path->small_levels));
   HIP_TRY(upload(&d->sweep_gates, path->sweep_gates));
   HIP_TRY(upload(&d->segments, path->segments));
   *out = d;
@@ -176,6 +178,7 @@ void device_release_path(tn_path* path) {
   (void)hipSetDevice(d->device);
   (void)hipFree(d->steps);
   (void)hipFree(d->lists);
+  (void)hipFree(d->levels);
   (void)hipFree(d->sweep_gates);
   (void)hipFree(d->segments);
   (void)hipSetDevice(cur);
@@ -252,8 +255,8 @@ static tn_status run_steps(hipStream_t s, tn_path* path, const Bases& B, int bat
     float2* wp = resolve(B, rw, &wbs);
     if (B.pair_a) return set_error(TN_EINVAL, "internal: interpreter steps in a single pairwise contraction");
     hipEvent_t ev = prof_start(s);
-    HIP_TRY(launch_small_steps(s, dp->steps, dp->lists, (int)path->small_lists.size() - 1, ip, ibs, wp, wbs, batch,
-                               precision));
+    HIP_TRY(launch_small_steps(s, dp->steps, dp->lists, dp->levels, (int)path->small_lists.size() - 1, ip, ibs, wp,
+                               wbs, batch, precision));
     double fl = 0, by = 0;
     for (int i = 0; i < path->n_small; ++i) { fl += path->steps[i].flops; by += path->steps[i].bytes; }
     prof_stop(s, ev, TN_KERNEL_INTERP, by * batch, fl * batch);
