@@ -282,6 +282,39 @@ tn_status tn_contract_pair(void* stream, int32_t precision, const void* a, int32
                            void* workspace_dev, size_t workspace_bytes);
 
 /*
+ * Autotuner for the launch shapes of the matrix-product steps.
+ * Runs the path's steps once on `stream` (gate tensors from params_dev, for
+ * `batch` parameter vectors; amplitude projectors are left zero), then for
+ * every matrix-product step times each candidate launch shape -- an MFMA tile
+ * of 128x64, 128x32, 64x64 or 64x32 complex, K cut into 1, 2, 4 or 8 ranges
+ * where the step's result is small, the one-output-per-thread vector kernel
+ * where K <= 1024, each for C = A B and for C = B^T A^T -- over `reps` launches (hipEvents on `stream`) and
+ * keeps the fastest in the path for `precision`.  Synchronises the stream.
+ * Later contractions along the path give the same results up to rounding
+ * order (a K split sums partial products in another order).
+ *   workspace_dev: >= tn_workspace_bytes(net, path, batch) bytes (contents
+ *   overwritten);  report (may be NULL): number of product steps, steps whose
+ *   shape changed, and the sum of their measured times before and after.
+ */
+typedef struct {
+  int32_t n_products, n_changed;
+  double seconds_before, seconds_after;
+} tn_tune_report;
+tn_status tn_autotune(void* stream, int32_t precision, tn_network* net, tn_path* path, const double* params_dev,
+                      int32_t batch, void* workspace_dev, size_t workspace_bytes, int32_t reps,
+                      tn_tune_report* report);
+/* Launch shape of matrix-product step `step` for `precision`: read (set == 0)
+ * into *tile / *split / *transposed, or replace it (set != 0) with the values
+ * given, e.g. to restore shapes tuned earlier.  tile: 0..3 = MFMA tiles
+ * 128x64, 128x32, 64x64, 64x32 complex; 4 = vector kernel (K <= 1024 only,
+ * split 1).  split: 1, 2, 4 or 8, dividing K, at most the step's reserved
+ * maximum.  transposed: 0 computes C = A B, 1 computes C = B^T A^T (operands
+ * trade places; same result layout).  TN_EINVAL for a step that is not a
+ * matrix product or an invalid shape. */
+tn_status tn_path_gemm_config(tn_path* path, int32_t step, int32_t precision, int32_t* tile, int32_t* split,
+                              int32_t* transposed, int32_t set);
+
+/*
  * Kernel timing for measurement.  While enabled, every kernel launch of the
  * entry points above is bracketed by a pair of hipEvents recorded on the
  * launch's own stream, and tagged with the launch's algorithmic work: bytes

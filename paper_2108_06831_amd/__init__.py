@@ -195,6 +195,29 @@ class Path:
         return {"modes": list(modes[: rank.value]), "bmnk": tuple(bmnk),
                 "kind": ["skinny", "gemm", "small"][kind.value]}
 
+    def gemm_config(self, s: int, precision="c64"):
+        """(tile, split, transposed) launch shape of matrix-product step s."""
+        t, sp, tr = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        check(lib().tn_path_gemm_config(self.handle, s, _prec(precision), ctypes.byref(t), ctypes.byref(sp),
+                                        ctypes.byref(tr), 0))
+        return t.value, sp.value, tr.value
+
+    def set_gemm_config(self, s: int, tile: int, split: int, transposed: int = 0, precision="c64"):
+        t, sp, tr = ctypes.c_int32(tile), ctypes.c_int32(split), ctypes.c_int32(transposed)
+        check(lib().tn_path_gemm_config(self.handle, s, _prec(precision), ctypes.byref(t), ctypes.byref(sp),
+                                        ctypes.byref(tr), 1))
+
+    def gemm_configs(self, precision="c64"):
+        """{step: (tile, split, transposed)} for every matrix-product step (e.g. to cache tuned shapes)."""
+        out = {}
+        for s in range(self.stats["n_steps"]):
+            if self.step(s)["kind"] == "gemm":
+                try:
+                    out[s] = self.gemm_config(s, precision)
+                except TNError:
+                    pass
+        return out
+
     def workspace_bytes(self, batch: int = 1) -> int:
         return int(lib().tn_workspace_bytes(self.net.handle, self.handle, batch))
 
@@ -271,6 +294,20 @@ def contract_path(net: Network, path: Path, params=None, batch: int = 1, precisi
     tn_contract_path(_stream_handle(stream), _prec(precision), net, path, _ptr(p), batch, _ptr(ws), ws.numel(),
                      _ptr(out))
     return out
+
+
+def autotune(net: Network, path: Path, params=None, batch: int = 1, precision="c64", reps: int = 5, device="cuda",
+             workspace=None, stream=None) -> dict:
+    """Times the candidate launch shapes of every matrix-product step of `path`
+    on the GPU and keeps the fastest (see tn_autotune).  Returns the report."""
+    p = _params_tensor(net, params, batch, device)
+    nbytes = path.workspace_bytes(batch)
+    ws = workspace if workspace is not None else _workspace(nbytes, device)
+    rep = _lib.tn_tune_report()
+    check(lib().tn_autotune(_stream_handle(stream), _prec(precision), net.handle, path.handle, _ptr(p), batch,
+                            _ptr(ws), ws.numel(), reps, ctypes.byref(rep)))
+    return {"n_products": rep.n_products, "n_changed": rep.n_changed, "seconds_before": rep.seconds_before,
+            "seconds_after": rep.seconds_after}
 
 
 def amplitudes(net: Network, path: Path, bitstrings, params=None, precision="c64", device="cuda", out=None,

@@ -65,10 +65,16 @@ EXPORTS = [
     "tn_network_values", "tn_plan_path", "tn_path_destroy", "tn_path_pairs", "tn_path_step", "tn_workspace_bytes",
     "tn_contract_path", "tn_amplitudes", "tn_expectation_workspace_bytes", "tn_expectation",
     "tn_backward_workspace_bytes", "tn_backward", "tn_contract_pair_workspace_bytes", "tn_contract_pair",
-    "tn_last_error", "tn_version", "tn_profile_enable", "tn_profile_read", "tn_profile_reset",
+    "tn_last_error", "tn_version", "tn_profile_enable", "tn_profile_read", "tn_profile_reset", "tn_autotune",
+    "tn_path_gemm_config",
 ]
 
 KERNEL_KINDS = ["materialize", "skinny", "permute", "gemm", "reduce", "copy", "adjoint", "interp", "sweep"]
+
+
+class tn_tune_report(ctypes.Structure):
+    _fields_ = [("n_products", ctypes.c_int32), ("n_changed", ctypes.c_int32), ("seconds_before", ctypes.c_double),
+                ("seconds_after", ctypes.c_double)]
 
 
 class tn_kernel_profile(ctypes.Structure):
@@ -128,6 +134,10 @@ def _declare(lib):
     lib.tn_profile_read.restype = i32
     lib.tn_profile_reset.argtypes = []
     lib.tn_profile_reset.restype = None
+    lib.tn_autotune.argtypes = [P, i32, P, P, P, i32, P, sz, i32, P]
+    lib.tn_autotune.restype = st
+    lib.tn_path_gemm_config.argtypes = [P, i32, i32, P, P, P, i32]
+    lib.tn_path_gemm_config.restype = st
     del i64, u64, dbl
 
 

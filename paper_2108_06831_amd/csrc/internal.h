@@ -155,14 +155,28 @@ struct GemmDesc {
   BufRef a, b, c;
   int64_t batch, M, N, K;
   int32_t nbb, nbm, nbn, nbk;  // bit counts of the batch, m, n, k indices
+  int32_t swapped;  // A and B are the step's second and first operands (C = B^T A^T)
   int32_t a_kfast;  // A tile loads walk k fastest (A's lowest m/k address bit is a k bit)
   int32_t b_nfast;  // B tile loads walk n fastest
   int8_t a_b[kGemmMaxBits], a_m[kGemmMaxBits], a_k[kGemmMaxBits];
   int8_t b_b[kGemmMaxBits], b_k[kGemmMaxBits], b_n[kGemmMaxBits];
   int8_t c_b[kGemmMaxBits], c_m[kGemmMaxBits], c_n[kGemmMaxBits];
-  int32_t split;  // > 1: K is cut into `split` ranges whose partial products land in `tmp` and are summed
+  // launch shape per precision (index TN_PREC_*): tile[p] < kGemmVector is an
+  // MFMA tile of kGemmTileM x kGemmTileN complex, kGemmVector the per-output
+  // vector kernel; split[p] > 1 cuts K into ranges whose partial products land
+  // in `tmp` and are summed.  `tmp` holds max_split copies of C.
+  int32_t tile[2], split[2];
+  int32_t max_split;
   BufRef tmp;
 };
+constexpr int kGemmVector = 4;
+constexpr int kGemmTileM[4] = {128, 128, 64, 64};
+constexpr int kGemmTileN[4] = {64, 32, 64, 32};
+constexpr int kGemmMaxSplit = 8;
+constexpr int kGemmBK = 16;      // complex k per staged K tile of the MFMA kernels
+constexpr int kElemMaxK = 1024;  // longest K of the per-output kernel
+// default launch shape of a product (before any measurement)
+void gemm_default_launch(const GemmDesc& g, int* tile, int* split);
 
 // A small step executed inside the interpreter kernel: every operand and the
 // result fit in a few KB.  C's address bit p comes from A's bit apos[p] and/or
@@ -187,7 +201,8 @@ struct StepProgram {
   SmallStep sm;
   std::vector<PermuteDesc> pre;  // operand permutes before the product
   SkinnyDesc sk;
-  GemmDesc gm;
+  GemmDesc gm[2];       // matrix product as C = A B (0) and as C = B^T A^T (1)
+  int32_t orient[2];    // per precision: which of the two runs
   double flops = 0, bytes = 0;
   int64_t gemm_bmnk[4] = {0, 0, 0, 0};
 };

@@ -30,12 +30,14 @@ hipError_t launch_skinny(hipStream_t s, const SkinnyDesc& d, const float2* g, in
 hipError_t launch_permute(hipStream_t s, const PermuteDesc& d, const float2* in, int64_t in_bs, float2* out,
                           int64_t out_bs, int batch);
 
-// C[b] = A[b] B[b] on complex64 with FP32 MFMA accumulation.
-// Products too narrow for matrix-core tiles run one output per thread on the vector ALUs.
-inline bool gemm_uses_vector_alu(const GemmDesc& d) { return (d.M < 64 || d.N < 32) && d.K <= 1024; }
-// With d.split > 1 the partial products go to `tmp` ([split][C], same layout as C) and are summed into C.
-hipError_t launch_gemm(hipStream_t s, const GemmDesc& d, const float2* a, int64_t a_bs, const float2* b, int64_t b_bs,
-                       float2* c, int64_t c_bs, float2* tmp, int64_t tmp_bs, int batch, int precision);
+// C[b] = A[b] B[b] on complex64, FP32 accumulation: FP32 matrix cores, or the
+// BF16x3 split on the bf16 matrix cores (precision TN_PREC_BF16X3).  `tile`
+// (< kGemmVector: MFMA tile shape; kGemmVector: one output per thread on the
+// vector ALUs) and `split` (K ranges, partials in `tmp` = [split][C], summed
+// into C) choose the launch shape.
+hipError_t launch_gemm(hipStream_t s, const GemmDesc& d, int tile, int split, const float2* a, int64_t a_bs,
+                       const float2* b, int64_t b_bs, float2* c, int64_t c_bs, float2* tmp, int64_t tmp_bs, int batch,
+                       int precision);
 
 // Expectation of a diagonal Z-string observable: out[z] = sum_x |psi_z[x]|^2 D(x),
 // FP64 accumulation (block partials + a fixed-order second pass).

@@ -636,8 +636,11 @@ hipError_t launch_permute(hipStream_t s, const PermuteDesc& d, const float2* in,
 // and produces a 32 x 16 complex tile.
 // ---------------------------------------------------------------------------
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
-constexpr int kBM = 128, kBN = 64, kBK = 16;
+constexpr int kBK = kGemmBK;          // complex k per staged K tile
+constexpr int kB3Row = 2 * kBK + 8;   // bf16 per LDS row of a split-precision K tile (16-byte pad)
 
 // Operands and result are read and written through bit-deposit maps: the
 // address of logical index x of an operand is the OR of x's bits moved to
@@ -665,12 +668,61 @@ __device__ inline int64_t deposit(int64_t x, const int8_t* pos, int nbits) {
   return r;
 }
 
-template <int AK, int BNF, int PREC>
+// BF16x3 split precision: x_hi = bf16(x), x_lo = bf16(x - x_hi), both round
+// to nearest even; the product keeps a_hi b_hi + a_hi b_lo + a_lo b_hi.
+__device__ inline void split_bf16(float2 v, uint32_t* hi, uint32_t* lo) {
+  const __bf16 h0 = (__bf16)v.x, h1 = (__bf16)v.y;
+  const __bf16 l0 = (__bf16)(v.x - (float)h0), l1 = (__bf16)(v.y - (float)h1);
+  const bf16x2 H = {h0, h1}, L = {l0, l1};
+  *hi = __builtin_bit_cast(uint32_t, H);
+  *lo = __builtin_bit_cast(uint32_t, L);
+}
+
+// (re, im) bf16 pairs of B -> the B' column entries of real column parity d:
+// (re, -im) for even real columns, (im, re) for odd ones
+__device__ inline bf16x8 b_embed(uint4 w, int d) {
+  uint4 r;
+  r.x = d ? ((w.x >> 16) | (w.x << 16)) : (w.x ^ 0x80000000u);
+  r.y = d ? ((w.y >> 16) | (w.y << 16)) : (w.y ^ 0x80000000u);
+  r.z = d ? ((w.z >> 16) | (w.z << 16)) : (w.z ^ 0x80000000u);
+  r.w = d ? ((w.w >> 16) | (w.w << 16)) : (w.w ^ 0x80000000u);
+  return __builtin_bit_cast(bf16x8, r);
+}
+
+// Complex GEMM on the matrix cores.
+//
+// With complex64 stored as interleaved (re, im), A (M x K complex) is read as
+// the real M x 2K matrix A_r, and B (K x N complex) is expanded on the fly
+// into the real 2K x 2N matrix B' whose 2x2 block (k, n) is
+// [[Re b, Im b], [-Im b, Re b]].  Then A_r B' is the interleaved real view of
+// A B (4M form: 4 real multiply-adds per complex one).
+//
+// Four waves in a 2 x 2 arrangement; each wave owns TM x TN result tiles of
+// 32 x 16 complex, so a block computes (64 TM) x (32 TN).  Form F = 0: FP32,
+// one v_mfma_f32_32x32x2f32 per complex k (lanes 0-31 carry Re A / the first
+// row of B's 2x2 block, lanes 32-63 Im A / the second row).  Form F = 1:
+// BF16x3 on the bf16 matrix cores, v_mfma_f32_32x32x16_bf16 covering 8
+// complex k: lane l holds the eight consecutive k' = 8*(l/32) .. +7 of row
+// (A) or column (B) l%32, i.e. four complex values of one A row as stored,
+// or four complex values of one B column turned into B' entries (b_embed).
+// Operands are split into hi/lo once, while a tile is staged into LDS.
+template <int AK, int BNF, int TM, int TN, int F>
 __global__ __launch_bounds__(kThreads) void k_gemm(GemmArgs g) {
-  __shared__ float As_re[kBK][kBM + 1];
-  __shared__ float As_im[kBK][kBM + 1];
-  __shared__ float2 Bs[kBK][kBN + 1];
-  __shared__ int64_t TAm[kBM], TCm[kBM], TBn[kBN], TCn[kBN], TAk[kBK], TBk[kBK];
+  constexpr int BM = 64 * TM, BN = 32 * TN;
+  constexpr int kPA = (BM * kBK) / kThreads, kPB = (BN * kBK) / kThreads;
+  constexpr int kF32Bytes = 2 * kBK * (BM + 1) * 4 + kBK * (BN + 1) * 8;
+  constexpr int kB3Bytes = 2 * BM * kB3Row * 2 + 2 * BN * kB3Row * 2;
+  constexpr int kSmem = F == 0 ? kF32Bytes : kB3Bytes;
+  __shared__ __attribute__((aligned(16))) char smem[kSmem];
+  __shared__ int64_t TAm[BM], TCm[BM], TBn[BN], TCn[BN], TAk[kBK], TBk[kBK];
+  float (*As_re)[BM + 1] = reinterpret_cast<float (*)[BM + 1]>(smem);
+  float (*As_im)[BM + 1] = reinterpret_cast<float (*)[BM + 1]>(smem + kBK * (BM + 1) * 4);
+  float2 (*Bs)[BN + 1] = reinterpret_cast<float2 (*)[BN + 1]>(smem + 2 * kBK * (BM + 1) * 4);
+  __bf16 (*Ah)[kB3Row] = reinterpret_cast<__bf16 (*)[kB3Row]>(smem);
+  __bf16 (*Al)[kB3Row] = reinterpret_cast<__bf16 (*)[kB3Row]>(smem + BM * kB3Row * 2);
+  __bf16 (*Bh)[kB3Row] = reinterpret_cast<__bf16 (*)[kB3Row]>(smem + 2 * BM * kB3Row * 2);
+  __bf16 (*Bl)[kB3Row] = reinterpret_cast<__bf16 (*)[kB3Row]>(smem + 2 * BM * kB3Row * 2 + BN * kB3Row * 2);
+
   int64_t bid = blockIdx.x;
   const int64_t tn = bid % g.tiles_n;
   bid /= g.tiles_n;
@@ -683,7 +735,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm(GemmArgs g) {
   const float2* A = g.A + z * g.a_bs;
   const float2* B = g.B + z * g.b_bs;
   float2* C = g.C + z * g.c_bs + ks * g.c_elems;
-  const int64_t m0 = tm * kBM, n0 = tn * kBN;
+  const int64_t m0 = tm * BM, n0 = tn * BN;
   const int64_t kchunk = g.K / g.split;
   const int64_t kbeg = ks * kchunk, kend = kbeg + kchunk;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -691,13 +743,14 @@ __global__ __launch_bounds__(kThreads) void k_gemm(GemmArgs g) {
   const int64_t base_a = deposit(gb, g.a_b, g.nbb) | deposit(m0, g.a_m, g.nbm);
   const int64_t base_b = deposit(gb, g.b_b, g.nbb) | deposit(n0, g.b_n, g.nbn);
   const int64_t base_c = deposit(gb, g.c_b, g.nbb) | deposit(m0, g.c_m, g.nbm) | deposit(n0, g.c_n, g.nbn);
-  if (tid < kBM) {
-    const int nb = min(g.nbm, 7);
+  constexpr int kLogBM = 6 + (TM == 2), kLogBN = 5 + (TN == 2);
+  if (tid < BM) {
+    const int nb = min(g.nbm, kLogBM);
     TAm[tid] = deposit(tid, g.a_m, nb);
     TCm[tid] = deposit(tid, g.c_m, nb);
   }
-  if (tid < kBN) {
-    const int nb = min(g.nbn, 6);
+  if (tid < BN) {
+    const int nb = min(g.nbn, kLogBN);
     TBn[tid] = deposit(tid, g.b_n, nb);
     TCn[tid] = deposit(tid, g.c_n, nb);
   }
@@ -706,48 +759,69 @@ __global__ __launch_bounds__(kThreads) void k_gemm(GemmArgs g) {
     TAk[tid] = deposit(tid, g.a_k, nb);
     TBk[tid] = deposit(tid, g.b_k, nb);
   }
-  floatx16 acc[2][2];
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j)
+  floatx16 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
       for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
   __syncthreads();
 
+  // tile element e of this thread: (row or column, k) inside the tile
+  auto a_elem = [&](int e, int& mm, int& kk) {
+    const int idx = tid + e * kThreads;
+    if (AK) { mm = idx / kBK; kk = idx % kBK; } else { mm = idx % BM; kk = idx / BM; }
+  };
+  auto b_elem = [&](int e, int& nn, int& kk) {
+    const int idx = tid + e * kThreads;
+    if (BNF) { nn = idx % BN; kk = idx / BN; } else { nn = idx / kBK; kk = idx % kBK; }
+  };
   // software pipeline: the next K tile is fetched into registers while the
   // current one is multiplied out of LDS
-  constexpr int kPA = (kBM * kBK) / kThreads, kPB = (kBN * kBK) / kThreads;
   float2 ra[kPA], rb[kPB];
   auto fetch = [&](int64_t k0) {
     const int64_t ka = deposit(k0, g.a_k, g.nbk), kb = deposit(k0, g.b_k, g.nbk);
 #pragma unroll
     for (int e = 0; e < kPA; ++e) {
-      const int idx = tid + e * kThreads;
       int mm, kk;
-      if (AK) { mm = idx / kBK; kk = idx % kBK; } else { mm = idx % kBM; kk = idx / kBM; }
+      a_elem(e, mm, kk);
       ra[e] = (m0 + mm < g.M && k0 + kk < kend) ? A[base_a | TAm[mm] | ka | TAk[kk]] : f2(0.f, 0.f);
     }
 #pragma unroll
     for (int e = 0; e < kPB; ++e) {
-      const int idx = tid + e * kThreads;
       int nn, kk;
-      if (BNF) { nn = idx % kBN; kk = idx / kBN; } else { nn = idx / kBK; kk = idx % kBK; }
+      b_elem(e, nn, kk);
       rb[e] = (n0 + nn < g.N && k0 + kk < kend) ? B[base_b | TBn[nn] | kb | TBk[kk]] : f2(0.f, 0.f);
     }
   };
   auto stage = [&]() {
 #pragma unroll
     for (int e = 0; e < kPA; ++e) {
-      const int idx = tid + e * kThreads;
       int mm, kk;
-      if (AK) { mm = idx / kBK; kk = idx % kBK; } else { mm = idx % kBM; kk = idx / kBM; }
-      As_re[kk][mm] = ra[e].x;
-      As_im[kk][mm] = ra[e].y;
+      a_elem(e, mm, kk);
+      if constexpr (F == 0) {
+        As_re[kk][mm] = ra[e].x;
+        As_im[kk][mm] = ra[e].y;
+      } else {
+        uint32_t h, l;
+        split_bf16(ra[e], &h, &l);
+        *reinterpret_cast<uint32_t*>(&Ah[mm][2 * kk]) = h;
+        *reinterpret_cast<uint32_t*>(&Al[mm][2 * kk]) = l;
+      }
     }
 #pragma unroll
     for (int e = 0; e < kPB; ++e) {
-      const int idx = tid + e * kThreads;
       int nn, kk;
-      if (BNF) { nn = idx % kBN; kk = idx / kBN; } else { nn = idx / kBK; kk = idx % kBK; }
-      Bs[kk][nn] = rb[e];
+      b_elem(e, nn, kk);
+      if constexpr (F == 0) {
+        Bs[kk][nn] = rb[e];
+      } else {
+        uint32_t h, l;
+        split_bf16(rb[e], &h, &l);
+        *reinterpret_cast<uint32_t*>(&Bh[nn][2 * kk]) = h;
+        *reinterpret_cast<uint32_t*>(&Bl[nn][2 * kk]) = l;
+      }
     }
   };
   fetch(kbeg);
@@ -755,47 +829,74 @@ __global__ __launch_bounds__(kThreads) void k_gemm(GemmArgs g) {
     stage();
     __syncthreads();
     if (k0 + kBK < kend) fetch(k0 + kBK);
+    if constexpr (F == 0) {
 #pragma unroll 4
-    for (int kk = 0; kk < kBK; ++kk) {
-      float av[2], bv[2];
+      for (int kk = 0; kk < kBK; ++kk) {
+        float av[TM], bv[TN];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const int row = wm * 64 + i * 32 + (lane & 31);
-        av[i] = lane < 32 ? As_re[kk][row] : As_im[kk][row];
-      }
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const float2 bb = Bs[kk][wn * 32 + j * 16 + ((lane & 31) >> 1)];
-        const bool odd = lane & 1;
-        bv[j] = lane < 32 ? (odd ? bb.y : bb.x) : (odd ? bb.x : -bb.y);
-      }
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          if constexpr (PREC == TN_PREC_C64) {
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i], bv[j], acc[i][j], 0, 0, 0);
-          } else {
-            const float ah = bf16_round(av[i]), al = bf16_round(av[i] - ah);
-            const float bh = bf16_round(bv[j]), bl = bf16_round(bv[j] - bh);
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(al, bh, acc[i][j], 0, 0, 0);
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ah, bl, acc[i][j], 0, 0, 0);
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ah, bh, acc[i][j], 0, 0, 0);
-          }
+        for (int i = 0; i < TM; ++i) {
+          const int row = wm * 32 * TM + i * 32 + (lane & 31);
+          av[i] = lane < 32 ? As_re[kk][row] : As_im[kk][row];
         }
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          const float2 bb = Bs[kk][wn * 16 * TN + j * 16 + ((lane & 31) >> 1)];
+          const bool odd = lane & 1;
+          bv[j] = lane < 32 ? (odd ? bb.y : bb.x) : (odd ? bb.x : -bb.y);
+        }
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+      }
+    } else {
+      const int half = lane >> 5, d = lane & 1;
+#pragma unroll
+      for (int kq = 0; kq < kBK / 8; ++kq) {
+        const int col = kq * 16 + half * 8;  // first bf16 of this lane's eight
+        bf16x8 ah[TM], al[TM], bh[TN], bl[TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+          const int row = wm * 32 * TM + i * 32 + (lane & 31);
+          ah[i] = *reinterpret_cast<const bf16x8*>(&Ah[row][col]);
+          al[i] = *reinterpret_cast<const bf16x8*>(&Al[row][col]);
+        }
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          const int nn = wn * 16 * TN + j * 16 + ((lane & 31) >> 1);
+          bh[j] = b_embed(*reinterpret_cast<const uint4*>(&Bh[nn][col]), d);
+          bl[j] = b_embed(*reinterpret_cast<const uint4*>(&Bl[nn][col]), d);
+        }
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+      }
     }
     __syncthreads();
   }
   float* Cf = reinterpret_cast<float*>(C);
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < TM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < TN; ++j)
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
-        const int rl = wm * 64 + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        const int rl = wm * 32 * TM + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
         const int jj = lane & 31;
-        const int cl = wn * 32 + j * 16 + (jj >> 1);
+        const int cl = wn * 16 * TN + j * 16 + (jj >> 1);
         if (m0 + rl < g.M && n0 + cl < g.N) Cf[(base_c | TCm[rl] | TCn[cl]) * 2 + (jj & 1)] = acc[i][j][v];
       }
 }
@@ -803,8 +904,6 @@ __global__ __launch_bounds__(kThreads) void k_gemm(GemmArgs g) {
 // Products too narrow for the matrix-core tiles (M < 64 or N < 32, e.g. a
 // 4096-way batch of 2x2 outer products): one thread per output element, the
 // same deposit-map addressing, K loop on the vector ALUs.
-constexpr int kElemMaxK = 1024;
-
 template <int PREC>
 __global__ __launch_bounds__(kThreads) void k_contract_elem(GemmArgs g) {
   __shared__ int64_t TKa[kElemMaxK], TKb[kElemMaxK];
@@ -846,23 +945,33 @@ __global__ void k_sum_partials(const float2* part, int64_t part_bs, int split, i
   }
 }
 
-hipError_t launch_gemm(hipStream_t s, const GemmDesc& d, const float2* a, int64_t a_bs, const float2* b, int64_t b_bs,
-                       float2* c, int64_t c_bs, float2* tmp, int64_t tmp_bs, int batch, int precision) {
+template <int TM, int TN, int F>
+static void* gemm_fn(int ak, int bnf) {
+  if (ak && bnf) return (void*)k_gemm<1, 1, TM, TN, F>;
+  if (ak) return (void*)k_gemm<1, 0, TM, TN, F>;
+  if (bnf) return (void*)k_gemm<0, 1, TM, TN, F>;
+  return (void*)k_gemm<0, 0, TM, TN, F>;
+}
+
+template <int F>
+static void* gemm_fn_tile(int tile, int ak, int bnf) {
+  switch (tile) {
+    case 0: return gemm_fn<2, 2, F>(ak, bnf);
+    case 1: return gemm_fn<2, 1, F>(ak, bnf);
+    case 2: return gemm_fn<1, 2, F>(ak, bnf);
+    default: return gemm_fn<1, 1, F>(ak, bnf);
+  }
+}
+
+hipError_t launch_gemm(hipStream_t s, const GemmDesc& d, int tile, int split, const float2* a, int64_t a_bs,
+                       const float2* b, int64_t b_bs, float2* c, int64_t c_bs, float2* tmp, int64_t tmp_bs, int batch,
+                       int precision) {
+  if (tile < 0 || tile > kGemmVector) return hipErrorInvalidValue;
   GemmArgs g;
   g.A = a; g.B = b;
   g.batch = d.batch; g.M = d.M; g.N = d.N; g.K = d.K;
-  g.tiles_m = (d.M + kBM - 1) / kBM;
-  g.tiles_n = (d.N + kBN - 1) / kBN;
-  g.split = d.split > 1 ? d.split : 1;
+  g.split = split > 1 ? split : 1;
   g.c_elems = d.batch * d.M * d.N;
-  if (g.split > 1) {
-    if (d.K % g.split != 0 || !tmp) return hipErrorInvalidValue;
-    g.C = tmp;
-    g.c_bs = tmp_bs;
-  } else {
-    g.C = c;
-    g.c_bs = c_bs;
-  }
   g.a_bs = a_bs; g.b_bs = b_bs;
   g.nbb = d.nbb; g.nbm = d.nbm; g.nbn = d.nbn; g.nbk = d.nbk; g.pad = 0;
   for (int j = 0; j < kGemmMaxBits; ++j) {
@@ -870,10 +979,12 @@ hipError_t launch_gemm(hipStream_t s, const GemmDesc& d, const float2* a, int64_
     g.b_b[j] = d.b_b[j]; g.b_k[j] = d.b_k[j]; g.b_n[j] = d.b_n[j];
     g.c_b[j] = d.c_b[j]; g.c_m[j] = d.c_m[j]; g.c_n[j] = d.c_n[j];
   }
-  if (gemm_uses_vector_alu(d)) {
+  if (tile == kGemmVector) {
+    if (d.K > kElemMaxK) return hipErrorInvalidValue;
     g.C = c;
     g.c_bs = c_bs;
     g.split = 1;
+    g.tiles_m = g.tiles_n = 1;
     int64_t eb = (g.c_elems + kThreads - 1) / kThreads;
     if (eb > 65535) eb = 65535;
     if (precision == TN_PREC_BF16X3)
@@ -882,14 +993,20 @@ hipError_t launch_gemm(hipStream_t s, const GemmDesc& d, const float2* a, int64_
       hipLaunchKernelGGL(k_contract_elem<TN_PREC_C64>, dim3((unsigned)eb, batch), dim3(kThreads), 0, s, g);
     return hipGetLastError();
   }
+  if (g.split > 1) {
+    if (d.K % g.split != 0 || g.split > d.max_split || !tmp) return hipErrorInvalidValue;
+    g.C = tmp;
+    g.c_bs = tmp_bs;
+  } else {
+    g.C = c;
+    g.c_bs = c_bs;
+  }
+  g.tiles_m = (d.M + kGemmTileM[tile] - 1) / kGemmTileM[tile];
+  g.tiles_n = (d.N + kGemmTileN[tile] - 1) / kGemmTileN[tile];
   const int64_t blocks = g.tiles_m * g.tiles_n * g.split * d.batch * batch;
-  if (blocks > ((int64_t)1 << 24)) return hipErrorInvalidValue;
-  void* fn;
-  const bool bf = precision == TN_PREC_BF16X3;
-  if (d.a_kfast && d.b_nfast) fn = bf ? (void*)k_gemm<1, 1, 1> : (void*)k_gemm<1, 1, 0>;
-  else if (d.a_kfast) fn = bf ? (void*)k_gemm<1, 0, 1> : (void*)k_gemm<1, 0, 0>;
-  else if (d.b_nfast) fn = bf ? (void*)k_gemm<0, 1, 1> : (void*)k_gemm<0, 1, 0>;
-  else fn = bf ? (void*)k_gemm<0, 0, 1> : (void*)k_gemm<0, 0, 0>;
+  if (blocks > ((int64_t)1 << 24)) return hipErrorInvalidValue;  // grid of < 2^32 work-items
+  void* fn = precision == TN_PREC_BF16X3 ? gemm_fn_tile<1>(tile, d.a_kfast, d.b_nfast)
+                                         : gemm_fn_tile<0>(tile, d.a_kfast, d.b_nfast);
   void* args[] = {&g};
   hipError_t e = hipLaunchKernel(fn, dim3((unsigned)blocks), dim3(kThreads), args, 0, s);
   if (e != hipSuccess || g.split == 1) return e;

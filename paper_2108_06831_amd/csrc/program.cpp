@@ -15,6 +15,7 @@
 //     [batch][K][N] -> [batch][M][N], permuting an operand first only when
 //     its bits are not already grouped that way.
 #include <chrono>
+#include <cmath>
 #include <map>
 #include <algorithm>
 #include <string>
@@ -610,70 +611,87 @@ tn_status compile_program(const tn_network* net, tn_path* path, const std::vecto
       } else {
         C.bits = cat(filter(A.bits, cls, C_BATCH), filter(A.bits, cls, C_M), filter(B.bits, cls, C_N));
       }
-      // logical bit orders: batch, m, n by ascending position in C; k by ascending position in A
-      auto by_pos = [&](const std::vector<int32_t>& layout, int c) {
-        std::vector<int32_t> v;
-        for (int p = 0; p < (int)layout.size(); ++p) {
-          const int32_t lab = layout[layout.size() - 1 - p];
-          if (cls[lab] == c) v.push_back(lab);
-        }
-        return v;
-      };
-      const std::vector<int32_t> lb_ = by_pos(C.bits, C_BATCH), lm = by_pos(C.bits, C_M), ln = by_pos(C.bits, C_N),
-                                 lk = by_pos(A.bits, C_K);
-      GemmDesc& g = P.gm;
-      g.batch = bsz; g.M = msz; g.N = nsz; g.K = ksz;
-      g.nbb = (int32_t)lb_.size(); g.nbm = (int32_t)lm.size(); g.nbn = (int32_t)ln.size(); g.nbk = (int32_t)lk.size();
-      if (g.nbb > kGemmMaxBits || g.nbm > kGemmMaxBits || g.nbn > kGemmMaxBits || g.nbk > kGemmMaxBits)
-        return set_error(TN_EUNSUPPORTED, "contraction index wider than 2^40");
-      for (int j = 0; j < kGemmMaxBits; ++j)
-        g.a_b[j] = g.a_m[j] = g.a_k[j] = g.b_b[j] = g.b_k[j] = g.b_n[j] = g.c_b[j] = g.c_m[j] = g.c_n[j] = 0;
-      for (int j = 0; j < g.nbb; ++j) {
-        g.a_b[j] = (int8_t)pos_of(A.bits, lb_[j]);
-        g.b_b[j] = (int8_t)pos_of(B.bits, lb_[j]);
-        g.c_b[j] = (int8_t)pos_of(C.bits, lb_[j]);
-      }
-      for (int j = 0; j < g.nbm; ++j) {
-        g.a_m[j] = (int8_t)pos_of(A.bits, lm[j]);
-        g.c_m[j] = (int8_t)pos_of(C.bits, lm[j]);
-      }
-      for (int j = 0; j < g.nbn; ++j) {
-        g.b_n[j] = (int8_t)pos_of(B.bits, ln[j]);
-        g.c_n[j] = (int8_t)pos_of(C.bits, ln[j]);
-      }
-      for (int j = 0; j < g.nbk; ++j) {
-        g.a_k[j] = (int8_t)pos_of(A.bits, lk[j]);
-        g.b_k[j] = (int8_t)pos_of(B.bits, lk[j]);
-      }
-      // tile-load orientation: walk the index owning the operand's lowest m/k (k/n) address bit fastest
-      auto lowest_cls = [&](const std::vector<int32_t>& layout, int c1, int c2) {
-        for (int p = 0; p < (int)layout.size(); ++p) {
-          const int c = cls[layout[layout.size() - 1 - p]];
-          if (c == c1 || c == c2) return c;
-        }
-        return c2;
-      };
-      g.a_kfast = lowest_cls(A.bits, C_M, C_K) == C_K ? 1 : 0;
-      g.b_nfast = lowest_cls(B.bits, C_K, C_N) == C_N ? 1 : 0;
-      g.a = A.ref;
-      g.b = B.ref;
       C.ref.buf = BUF_WS;
       C.ref.off = alloc.get(C.elems);
-      g.c = C.ref;
-      // too few output tiles to fill the chip and a long K loop: split K
-      const int64_t tiles = ((g.M + 127) / 128) * ((g.N + 63) / 64) * g.batch;
-      g.split = 1;
-      const bool vector_alu = (g.M < 64 || g.N < 32) && g.K <= 1024;  // the per-output kernel
-      if (!vector_alu && tiles < 128 && g.K >= 256) {
-        int64_t sp = 1;
-        while (sp < 32 && tiles * sp * 2 <= 512 && g.K / (sp * 2) >= 32) sp *= 2;
-        g.split = (int32_t)sp;
+      // Two orientations: C = A B, or C = B^T A^T (operands trade places, m and
+      // n trade roles).  The kernel stores its result tile with consecutive
+      // lanes along n, so the transposed form suits a result whose lowest
+      // address bits are m bits; which one runs is a launch-shape choice.
+      for (int o = 0; o < 2; ++o) {
+        const bool swap = o == 1;
+        Loc& GA = swap ? B : A;
+        Loc& GB = swap ? A : B;
+        const int CM = swap ? C_N : C_M, CN = swap ? C_M : C_N;
+        // logical bit orders: batch, m, n by ascending position in C; k by ascending position in A
+        auto by_pos = [&](const std::vector<int32_t>& layout, int c) {
+          std::vector<int32_t> v;
+          for (int p = 0; p < (int)layout.size(); ++p) {
+            const int32_t lab = layout[layout.size() - 1 - p];
+            if (cls[lab] == c) v.push_back(lab);
+          }
+          return v;
+        };
+        const std::vector<int32_t> lb_ = by_pos(C.bits, C_BATCH), lm = by_pos(C.bits, CM), ln = by_pos(C.bits, CN),
+                                   lk = by_pos(GA.bits, C_K);
+        GemmDesc& g = P.gm[o];
+        g.swapped = o;
+        g.batch = bsz; g.M = swap ? nsz : msz; g.N = swap ? msz : nsz; g.K = ksz;
+        g.nbb = (int32_t)lb_.size(); g.nbm = (int32_t)lm.size(); g.nbn = (int32_t)ln.size();
+        g.nbk = (int32_t)lk.size();
+        if (g.nbb > kGemmMaxBits || g.nbm > kGemmMaxBits || g.nbn > kGemmMaxBits || g.nbk > kGemmMaxBits)
+          return set_error(TN_EUNSUPPORTED, "contraction index wider than 2^40");
+        for (int j = 0; j < kGemmMaxBits; ++j)
+          g.a_b[j] = g.a_m[j] = g.a_k[j] = g.b_b[j] = g.b_k[j] = g.b_n[j] = g.c_b[j] = g.c_m[j] = g.c_n[j] = 0;
+        for (int j = 0; j < g.nbb; ++j) {
+          g.a_b[j] = (int8_t)pos_of(GA.bits, lb_[j]);
+          g.b_b[j] = (int8_t)pos_of(GB.bits, lb_[j]);
+          g.c_b[j] = (int8_t)pos_of(C.bits, lb_[j]);
+        }
+        for (int j = 0; j < g.nbm; ++j) {
+          g.a_m[j] = (int8_t)pos_of(GA.bits, lm[j]);
+          g.c_m[j] = (int8_t)pos_of(C.bits, lm[j]);
+        }
+        for (int j = 0; j < g.nbn; ++j) {
+          g.b_n[j] = (int8_t)pos_of(GB.bits, ln[j]);
+          g.c_n[j] = (int8_t)pos_of(C.bits, ln[j]);
+        }
+        for (int j = 0; j < g.nbk; ++j) {
+          g.a_k[j] = (int8_t)pos_of(GA.bits, lk[j]);
+          g.b_k[j] = (int8_t)pos_of(GB.bits, lk[j]);
+        }
+        // tile-load orientation: walk the index owning the operand's lowest m/k (k/n) address bit fastest
+        auto lowest_cls = [&](const std::vector<int32_t>& layout, int c1, int c2) {
+          for (int p = 0; p < (int)layout.size(); ++p) {
+            const int c = cls[layout[layout.size() - 1 - p]];
+            if (c == c1 || c == c2) return c;
+          }
+          return c2;
+        };
+        g.a_kfast = lowest_cls(GA.bits, CM, C_K) == C_K ? 1 : 0;
+        g.b_nfast = lowest_cls(GB.bits, C_K, CN) == CN ? 1 : 0;
+        g.a = GA.ref;
+        g.b = GB.ref;
+        g.c = C.ref;
+        int tile, split;
+        gemm_default_launch(g, &tile, &split);
+        g.tile[0] = g.tile[1] = tile;
+        g.split[0] = g.split[1] = split;
+        // room for the autotuner to try K splits of products with a small result
+        g.max_split = split;
+        if (tile != kGemmVector && C.elems * kGemmMaxSplit <= ((int64_t)1 << 22) && g.K >= 64)
+          g.max_split = kGemmMaxSplit;
       }
-      if (g.split > 1) {
-        g.tmp.buf = BUF_WS;
-        g.tmp.off = alloc.get((int64_t)g.split * C.elems);
-        alloc.put(g.tmp.off, (int64_t)g.split * C.elems);  // scratch for this step only
+      P.orient[0] = P.orient[1] = 0;
+      const int max_split = std::max(P.gm[0].max_split, P.gm[1].max_split);
+      if (max_split > 1) {
+        BufRef tmp;
+        tmp.buf = BUF_WS;
+        tmp.off = alloc.get((int64_t)max_split * C.elems);
+        alloc.put(tmp.off, (int64_t)max_split * C.elems);  // scratch for this step only
+        for (GemmDesc& g : P.gm) g.tmp = tmp;
       }
+      P.gemm_bmnk[1] = P.gm[0].M;
+      P.gemm_bmnk[2] = P.gm[0].N;
     }
     // ---- bookkeeping
     for (int m : modes[ia]) holders[m]--;
@@ -744,10 +762,12 @@ tn_status compile_program(const tn_network* net, tn_path* path, const std::vecto
       if (d.c_mode == 0 && ec != te) return set_error(TN_EINVAL, "internal: in-layout output size mismatch");
       if (d.c_mode == 1 && ec != ((int64_t)1 << (outer_bits + d.nm))) return set_error(TN_EINVAL, "internal: output size");
     } else {
-      const GemmDesc& g = P.gm;
+     for (const GemmDesc& g : P.gm) {
+      const int xa = g.swapped ? ib : ia, xb = g.swapped ? ia : ib;  // the kernel's A and B
+      const int64_t ea = loc[xa].elems, eb = loc[xb].elems;
       if (g.batch * g.M * g.K != ea || g.batch * g.K * g.N != eb || g.batch * g.M * g.N != ec)
         return set_error(TN_EINVAL, "internal: GEMM shape mismatch");
-      const int ra = (int)loc[ia].bits.size(), rb = (int)loc[ib].bits.size(), rc = (int)loc[T + s].bits.size();
+      const int ra = (int)loc[xa].bits.size(), rb = (int)loc[xb].bits.size(), rc = (int)loc[T + s].bits.size();
       if (g.nbb + g.nbm + g.nbk != ra || g.nbb + g.nbk + g.nbn != rb || g.nbb + g.nbm + g.nbn != rc)
         return set_error(TN_EINVAL, "internal: GEMM bit counts");
       auto perm_ok = [](int r, std::initializer_list<std::pair<const int8_t*, int>> parts) {
@@ -760,7 +780,7 @@ tn_status compile_program(const tn_network* net, tn_path* path, const std::vecto
           }
         return true;
       };
-      if (g.split > 1 && !ref_ok(g.tmp, (int64_t)g.split * ec))
+      if (g.max_split > 1 && !ref_ok(g.tmp, (int64_t)g.max_split * ec))
         return set_error(TN_EINVAL, "internal: split-K scratch out of range");
       if (!perm_ok(ra, {{g.a_b, g.nbb}, {g.a_m, g.nbm}, {g.a_k, g.nbk}}) ||
           !perm_ok(rb, {{g.b_b, g.nbb}, {g.b_k, g.nbk}, {g.b_n, g.nbn}}) ||
@@ -768,6 +788,7 @@ tn_status compile_program(const tn_network* net, tn_path* path, const std::vecto
         return set_error(TN_EINVAL, "internal: GEMM bit positions");
       if (!ref_ok(g.a, ea) || !ref_ok(g.b, eb) || !ref_ok(g.c, ec))
         return set_error(TN_EINVAL, "internal: GEMM buffer out of range");
+     }
     }
   }
   for (int s = 0; s < path->n_small; ++s) {
@@ -858,6 +879,29 @@ tn_status compile_program(const tn_network* net, tn_path* path, const std::vecto
 // orders: launch overhead per kernel, streaming kernels at a sustained HBM rate,
 // permutes at their measured rate, matrix products at the sustained FP32
 // matrix-core rate scaled down for tiles the shape leaves partly empty.
+void gemm_default_launch(const GemmDesc& g, int* tile, int* split) {
+  *split = 1;
+  if ((g.M < 64 || g.N < 32) && g.K <= kElemMaxK) {
+    *tile = kGemmVector;
+    return;
+  }
+  // the largest tile that still gives two blocks per compute unit
+  for (int t = 0; t < kGemmVector; ++t) {
+    const int64_t blocks =
+        ((g.M + kGemmTileM[t] - 1) / kGemmTileM[t]) * ((g.N + kGemmTileN[t] - 1) / kGemmTileN[t]) * g.batch;
+    if (blocks >= 512) {
+      *tile = t;
+      return;
+    }
+  }
+  // else the smallest tile, and K cut into ranges while that adds blocks
+  *tile = kGemmVector - 1;
+  const int64_t blocks = ((g.M + 63) / 64) * ((g.N + 31) / 32) * g.batch;
+  int sp = 1;
+  while (sp < kGemmMaxSplit && blocks * sp * 2 <= 1024 && g.K / (sp * 2) >= 32 && g.K % (sp * 2) == 0) sp *= 2;
+  *split = sp;
+}
+
 double modeled_seconds(const tn_path* path) {
   constexpr double kLaunch = 5e-6, kHbm = 6.0e12, kPerm = 1.6e12, kMfma = 95e12;
   double t = 0;
@@ -882,16 +926,18 @@ double modeled_seconds(const tn_path* path) {
     if (P.kind == SK_SKINNY) {
       t += P.bytes / kHbm;
     } else {
-      const GemmDesc& g = P.gm;
+      const GemmDesc& g = P.gm[P.orient[0]];
       const double bytes = 8.0 * (double)g.batch * (double)(g.M * g.K + g.K * g.N + g.M * g.N);
-      if ((g.M < 64 || g.N < 32) && g.K <= 1024) {  // per-output vector kernel
+      const int tl = g.tile[0];
+      if (tl == kGemmVector) {  // per-output vector kernel
         t += std::max(P.flops / 20e12, bytes / kHbm);
         continue;
       }
-      const double tiles = (double)((g.M + 127) / 128) * (double)((g.N + 63) / 64) * (double)g.batch * g.split;
-      const double eff = std::min(1.0, g.M / 128.0) * std::min(1.0, g.N / 64.0) * std::min(1.0, g.K / 32.0) *
-                         std::min(1.0, tiles / 256.0);
-      t += std::max(P.flops / (kMfma * std::max(eff, 1e-3)), bytes / kHbm) + (g.split > 1 ? kLaunch : 0.0);
+      const double tm = kGemmTileM[tl], tn = kGemmTileN[tl];
+      const double tiles = std::ceil(g.M / tm) * std::ceil(g.N / tn) * (double)g.batch * g.split[0];
+      const double eff = std::min(1.0, g.M / tm) * std::min(1.0, g.N / tn) * std::min(1.0, g.K / 32.0) *
+                         std::min(1.0, tiles / 256.0) * (tm * tn >= 8192 ? 1.0 : 0.8);
+      t += std::max(P.flops / (kMfma * std::max(eff, 1e-3)), bytes / kHbm) + (g.split[0] > 1 ? kLaunch : 0.0);
     }
   }
   return t;

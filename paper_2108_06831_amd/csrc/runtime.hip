@@ -311,19 +311,20 @@ static tn_status run_steps(hipStream_t s, tn_path* path, const Bases& B, int bat
       prof_stop(s, ev, TN_KERNEL_SKINNY, 8.0 * batch * (ge + te + ce), P.flops * batch);
     } else {
       int64_t abs_, bbs, cbs;
-      float2* a = resolve(B, P.gm.a, &abs_);
-      float2* b = resolve(B, P.gm.b, &bbs);
-      float2* c = resolve(B, P.gm.c, &cbs);
-      const GemmDesc& g = P.gm;
+      const GemmDesc& g = P.gm[P.orient[precision]];
+      float2* a = resolve(B, g.a, &abs_);
+      float2* b = resolve(B, g.b, &bbs);
+      float2* c = resolve(B, g.c, &cbs);
       const double bytes = 8.0 * batch * (double)g.batch * (double)(g.M * g.K + g.K * g.N + g.M * g.N);
       int64_t tbs = 0;
-      float2* tmp = g.split > 1 ? resolve(B, g.tmp, &tbs) : nullptr;
+      float2* tmp = g.max_split > 1 ? resolve(B, g.tmp, &tbs) : nullptr;
       if (si + 1 == path->steps.size() && B.final_out) {
         c = B.final_out;  // the last product writes the caller's output directly
         cbs = B.final_out_bs;
       }
       hipEvent_t ev = prof_start(s);
-      HIP_TRY(launch_gemm(s, P.gm, a, abs_, b, bbs, c, cbs, tmp, tbs, batch, precision));
+      HIP_TRY(launch_gemm(s, g, g.tile[precision], g.split[precision], a, abs_, b, bbs, c, cbs, tmp, tbs, batch,
+                          precision));
       prof_stop(s, ev, TN_KERNEL_GEMM, bytes, P.flops * batch);
     }
   }
@@ -675,6 +676,126 @@ extern "C" tn_status tn_backward(void* stream, int32_t precision, tn_network* ne
     HIP_TRY(launch_gradient_reduce(s, parts, pstride, d->n_slots, d->slot_param, net->n_params, grad_out_dev, batch,
                                    grad_dev));
   return TN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// launch-shape autotuner
+// ---------------------------------------------------------------------------
+static bool gemm_shape_ok(const GemmDesc& g, int tile, int split) {
+  if (tile < 0 || tile > kGemmVector) return false;
+  if (split != 1 && split != 2 && split != 4 && split != 8) return false;
+  if (tile == kGemmVector) return split == 1 && g.K <= kElemMaxK;
+  return split <= std::max(g.max_split, 1) && g.K % split == 0;
+}
+
+extern "C" tn_status tn_path_gemm_config(tn_path* path, int32_t step, int32_t precision, int32_t* tile,
+                                         int32_t* split, int32_t* transposed, int32_t set) {
+  clear_error();
+  if (!path || !tile || !split || !transposed) return set_error(TN_EINVAL, "NULL argument");
+  if (precision != TN_PREC_C64 && precision != TN_PREC_BF16X3) return set_error(TN_EINVAL, "unknown precision");
+  if (step < 0 || step >= (int32_t)path->steps.size() || path->steps[step].kind != SK_GEMM ||
+      path->steps[step].chain != -1)
+    return set_error(TN_EINVAL, "step is not a matrix product");
+  StepProgram& P = path->steps[step];
+  if (!set) {
+    const GemmDesc& g = P.gm[P.orient[precision]];
+    *tile = g.tile[precision];
+    *split = g.split[precision];
+    *transposed = P.orient[precision];
+    return TN_OK;
+  }
+  if (*transposed != 0 && *transposed != 1) return set_error(TN_EINVAL, "transposed must be 0 or 1");
+  GemmDesc& g = P.gm[*transposed];
+  if (!gemm_shape_ok(g, *tile, *split)) return set_error(TN_EINVAL, "launch shape not valid for this step");
+  g.tile[precision] = *tile;
+  g.split[precision] = *split;
+  P.orient[precision] = *transposed;
+  return TN_OK;
+}
+
+extern "C" tn_status tn_autotune(void* stream, int32_t precision, tn_network* net, tn_path* path,
+                                 const double* params_dev, int32_t batch, void* workspace_dev, size_t workspace_bytes,
+                                 int32_t reps, tn_tune_report* report) {
+  clear_error();
+  tn_status st = check_common(net, path, params_dev, batch, precision);
+  if (st != TN_OK) return st;
+  if (!workspace_dev) return set_error(TN_EINVAL, "NULL workspace");
+  if (reps < 1 || reps > 1000) return set_error(TN_EINVAL, "reps must be in 1..1000");
+  const size_t need = tn_workspace_bytes(net, path, batch);
+  if (workspace_bytes < need) return set_error(TN_ENOMEM, "workspace too small: need " + std::to_string(need));
+  hipStream_t s = (hipStream_t)stream;
+  DevNet* d;
+  if ((st = ensure_device(net, &d)) != TN_OK) return st;
+  WsLayout L = layout_ws(net, path, batch, 0);
+  char* w = (char*)workspace_dev;
+  Bases B;
+  B.in = (float2*)(w + L.in_off);
+  B.in_bs = net->input_elems;
+  B.ws = (float2*)(w + L.arena_off);
+  B.ws_bs = path->ws_elems;
+  HIP_TRY(hipMemsetAsync(w, 0, L.aux_off, s));
+  HIP_TRY(launch_materialize(s, d->tensors, (int)net->tensors.size(), d->recipes, d->ops, d->mats, params_dev,
+                             net->n_params, batch, B.in, net->input_elems));
+  if ((st = run_steps(s, path, B, batch, precision)) != TN_OK) return st;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  tn_tune_report rep{0, 0, 0.0, 0.0};
+  tn_status result = TN_OK;
+  for (size_t si = 0; si < path->steps.size() && result == TN_OK; ++si) {
+    StepProgram& P = path->steps[si];
+    if (P.kind != SK_GEMM || P.chain != -1) continue;
+    auto time_shape = [&](const GemmDesc& g, int tile, int split, double* sec) -> hipError_t {
+      int64_t abs_, bbs, cbs, tbs = 0;
+      float2* a = resolve(B, g.a, &abs_);
+      float2* b = resolve(B, g.b, &bbs);
+      float2* c = resolve(B, g.c, &cbs);
+      float2* tmp = g.max_split > 1 ? resolve(B, g.tmp, &tbs) : nullptr;
+      hipError_t e = launch_gemm(s, g, tile, split, a, abs_, b, bbs, c, cbs, tmp, tbs, batch, precision);
+      if (e != hipSuccess) return e;
+      if ((e = hipEventRecord(e0, s)) != hipSuccess) return e;
+      for (int r = 0; r < reps; ++r)
+        if ((e = launch_gemm(s, g, tile, split, a, abs_, b, bbs, c, cbs, tmp, tbs, batch, precision)) != hipSuccess)
+          return e;
+      if ((e = hipEventRecord(e1, s)) != hipSuccess) return e;
+      if ((e = hipEventSynchronize(e1)) != hipSuccess) return e;
+      float ms = 0;
+      if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) return e;
+      *sec = 1e-3 * ms / reps;
+      return hipSuccess;
+    };
+    const int o0 = P.orient[precision];
+    const int t0 = P.gm[o0].tile[precision], s0 = P.gm[o0].split[precision];
+    double best = 0;
+    hipError_t e = time_shape(P.gm[o0], t0, s0, &best);
+    if (e != hipSuccess) { result = set_error(TN_EDEVICE, std::string("autotune: ") + hipGetErrorString(e)); break; }
+    rep.n_products++;
+    rep.seconds_before += best;
+    int bo = o0, bt = t0, bs = s0;
+    for (int o = 0; o < 2 && result == TN_OK; ++o)
+      for (int tile = 0; tile <= kGemmVector && result == TN_OK; ++tile)
+        for (int split = 1; split <= kGemmMaxSplit; split *= 2) {
+          const GemmDesc& g = P.gm[o];
+          if ((o == o0 && tile == t0 && split == s0) || !gemm_shape_ok(g, tile, split)) continue;
+          if (tile != kGemmVector && split > 1 && g.K / split < kGemmBK) continue;
+          double sec = 0;
+          e = time_shape(g, tile, split, &sec);
+          if (e != hipSuccess) {
+            result = set_error(TN_EDEVICE, std::string("autotune: ") + hipGetErrorString(e));
+            break;
+          }
+          if (sec < 0.97 * best) { best = sec; bo = o; bt = tile; bs = split; }
+        }
+    if (bo != o0 || bt != t0 || bs != s0) rep.n_changed++;
+    P.orient[precision] = bo;
+    P.gm[bo].tile[precision] = bt;
+    P.gm[bo].split[precision] = bs;
+    rep.seconds_after += best;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (report) *report = rep;
+  return result;
 }
 
 // ---------------------------------------------------------------------------

@@ -121,3 +121,56 @@ def test_deterministic():
     x = run_pair(A, ma, B, mb, mc)
     y = run_pair(A, ma, B, mb, mc)
     assert np.array_equal(x, y)
+
+
+def _bw16_path():
+    import workloads
+    from paper_2108_06831_amd import Network
+    circ = workloads.brickwork(16, 12, np.random.default_rng(5))
+    net = Network.from_circuit(circ)
+    return circ, net, net.plan(kind="greedy")
+
+
+@pytest.mark.parametrize("precision", ["c64", "bf16x3"])
+def test_every_gemm_launch_shape(precision):
+    """Every valid (tile, K split) launch shape of every product step of a
+    16-qubit brickwork contraction gives the oracle's statevector."""
+    import torch
+    from paper_2108_06831_amd import TNError, contract_path
+    circ, net, path = _bw16_path()
+    want = oracle.statevector(circ)
+    tol = C64_TOL if precision == "c64" else BF16X3_TOL
+    shapes = path.gemm_configs(precision)
+    assert shapes
+    tried = 0
+    for s, (t0, s0, o0) in shapes.items():
+        for tr in (0, 1):
+            for tile in range(5):
+                for split in (1, 2, 4, 8):
+                    try:
+                        path.set_gemm_config(s, tile, split, tr, precision)
+                    except TNError:
+                        continue
+                    print(f"step {s} bmnk {path.step(s)['bmnk']} tile {tile} split {split} transposed {tr} "
+                          f"{precision}", flush=True)
+                    got = contract_path(net, path, precision=precision)
+                    torch.cuda.synchronize()
+                    err = relerr(got.cpu().numpy()[0], want)
+                    assert err < tol, (s, tile, split, tr, err)
+                    tried += 1
+        path.set_gemm_config(s, t0, s0, o0, precision)
+    assert tried >= 8 * len(shapes)
+
+
+def test_autotune_keeps_results():
+    import torch
+    from paper_2108_06831_amd import autotune, contract_path
+    circ, net, path = _bw16_path()
+    want = oracle.statevector(circ)
+    rep = autotune(net, path, reps=3)
+    print("autotune", rep, flush=True)
+    assert rep["n_products"] == len(path.gemm_configs())
+    assert rep["seconds_after"] <= rep["seconds_before"] * 1.0001
+    got = contract_path(net, path)
+    torch.cuda.synchronize()
+    assert relerr(got.cpu().numpy()[0], want) < C64_TOL

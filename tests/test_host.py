@@ -246,3 +246,29 @@ def test_contract_pair_plans_tiny_shapes(shapes):
                                              arr(ctypes.c_int32, mb), arr(ctypes.c_int64, eb), len(mc),
                                              arr(ctypes.c_int32, mc))
     assert n > 0, _lib.lib().tn_last_error()
+
+
+def test_gemm_launch_shape_get_set():
+    """Launch shapes of product steps: defaults are valid, invalid shapes are refused."""
+    from paper_2108_06831_amd import TNError
+    circ = workloads.brickwork(16, 12, np.random.default_rng(5))
+    path = Network.from_circuit(circ).plan(kind="greedy")
+    shapes = path.gemm_configs()
+    assert shapes
+    for s, (tile, split, tr) in shapes.items():
+        b, m, n, k = path.step(s)["bmnk"]
+        assert 0 <= tile <= 4 and split in (1, 2, 4, 8) and k % split == 0 and tr == 0
+        if tile == 4:
+            assert k <= 1024 and split == 1
+        with pytest.raises(TNError):
+            path.set_gemm_config(s, 5, 1)
+        with pytest.raises(TNError):
+            path.set_gemm_config(s, 0, 3)
+        with pytest.raises(TNError):
+            path.set_gemm_config(s, 0, 1, 2)
+        path.set_gemm_config(s, 0, 1, 1, "bf16x3")
+        assert path.gemm_config(s, "bf16x3") == (0, 1, 1)
+        assert path.gemm_config(s) == (tile, split, tr)  # the other precision is untouched
+    non_gemm = next(s for s in range(path.stats["n_steps"]) if s not in shapes)
+    with pytest.raises(TNError):
+        path.gemm_config(non_gemm)
