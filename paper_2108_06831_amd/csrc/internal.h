@@ -40,6 +40,7 @@ struct SweepGate {
   int32_t recipe;     // a one-op recipe giving the gate's matrix
   int32_t gen;        // generator kind for parametric gates (GEN_*), GEN_NONE otherwise
   int32_t param;      // parameter index, or -1
+  int32_t diag;       // the gate's matrix is diagonal
 };
 
 enum GenKind { GEN_NONE = 0, GEN_X_HALF, GEN_Y_HALF, GEN_Z_HALF, GEN_X, GEN_ZZ_PHASE, GEN_CPHASE };
@@ -133,6 +134,23 @@ struct SweepPass {
   int8_t lpos[kSweepMaxLocal];
   int32_t first_gate, n_gates;
   int32_t first_seg, n_segs;
+  int32_t n_red;  // adjoint passes: gradient accumulators of the pass
+};
+
+// Reverse sweep of the adjoint gradient in fused passes: psi and lambda
+// chunks of 2^l elements stay in LDS while every gate of the pass is undone
+// on both, each parametric gate first adding its chunk's share of
+// Im<lambda|G|psi> to an accumulator of its own (`red`).
+constexpr int kAdjMaxRed = 128;
+struct AdjGateDesc {
+  int32_t diag, n;
+  int32_t lidx[2];  // as in SweepGateDesc
+  int32_t rb[2];
+  int32_t gate;     // index in the network's gate sweep (matrix U of the gate)
+  int32_t red;      // accumulator of the pass, or -1 (no gradient term)
+  int32_t slot;     // gradient-partials column, or -1
+  int32_t pad;
+  float gen[8];     // generator G: dense 2x2 row-major, or diagonal entries (complex, re/im interleaved)
 };
 struct SweepChain {
   BufRef in, out;
@@ -230,6 +248,11 @@ struct tn_path {
   std::vector<tnq::SweepPass> passes;
   std::vector<tnq::SweepSegment> segments;
   std::vector<tnq::SweepGateDesc> sweep_gates;
+  // adjoint gradient passes over the final tensor (built on first use; adj_state 1: built, -1: not possible)
+  int32_t adj_state = 0;
+  std::vector<tnq::SweepPass> adj_passes;
+  std::vector<tnq::SweepSegment> adj_segments;
+  std::vector<tnq::AdjGateDesc> adj_gates;
   tn_path_stats stats{};
   void* dev = nullptr;   // device-side cache
 };
@@ -243,6 +266,8 @@ double modeled_seconds(const tn_path* path);
 // program.cpp
 tn_status compile_program(const tn_network* net, tn_path* path, const std::vector<int32_t>* final_layout = nullptr);
 std::vector<int32_t> output_layout(const tn_network* net);
+// fused passes of the adjoint sweep over the path's final tensor (sets path->adj_state)
+void build_adjoint_plan(const tn_network* net, tn_path* path, const std::vector<int32_t>& slot_of_gate);
 // moves every step that is small and depends only on inputs or such steps to the front
 std::vector<int32_t> reorder_small_first(const tn_network* net, const std::vector<int32_t>& pairs, int* n_small,
                                          int64_t* small_region);

@@ -84,6 +84,15 @@ hipError_t launch_apply_diag_obs(hipStream_t s, const float2* psi, int64_t psi_b
 hipError_t launch_adjoint_step(hipStream_t s, const SweepArgs& a, const float2* u, int64_t u_bs, float2* psi,
                                int64_t psi_bs, float2* lam, int64_t lam_bs, int64_t n_elems, int batch,
                                double* partials, int64_t partial_stride);
+// One fused pass of the reverse sweep over psi and lambda (2^bits elements
+// each, per parameter vector): for every gate of the pass, in order, its
+// gradient term (if any) into partials[z][slot][block], then both states
+// undone by U^dagger.  U: [batch][u_bs] matrices, 16 complex64 per gate.
+// Grid: kReduceBlocks blocks per parameter vector, each taking chunks in turn.
+hipError_t launch_adjoint_pass(hipStream_t s, const SweepPass& ps, int bits, const AdjGateDesc* gates_dev,
+                               const SweepSegment* segs_dev, const float2* u, int64_t u_bs, float2* psi,
+                               int64_t psi_bs, float2* lam, int64_t lam_bs, int batch, double* partials,
+                               int64_t partial_stride);
 // grad[z][p] = scale_z * sum over slots with param p and blocks of partials
 hipError_t launch_gradient_reduce(hipStream_t s, const double* partials, int64_t partial_stride, int n_slots,
                                   const int32_t* slot_param, int n_params, const double* grad_out, int batch,

@@ -393,6 +393,80 @@ __device__ inline void reg_apply2(float2 (&x)[16], const float2* g) {
   }
 }
 
+// Diagonal factor on the 16 register elements, with the bits of the factor's
+// index resolved at compile time: e_{bit U of r} ...
+template <int PREC, int U>
+__device__ inline void diag_reg1(float2 (&x)[16], float2 e0, float2 e1) {
+#pragma unroll
+  for (int r = 0; r < 16; ++r) x[r] = cmac<PREC>(f2(0.f, 0.f), (r >> U) & 1 ? e1 : e0, x[r]);
+}
+// ... or d_{bit U0 of r + 2 bit U1 of r}
+template <int PREC, int U0, int U1>
+__device__ inline void diag_reg2(float2 (&x)[16], float2 d0, float2 d1, float2 d2, float2 d3) {
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int b = ((r >> U0) & 1) | (((r >> U1) & 1) << 1);
+    x[r] = cmac<PREC>(f2(0.f, 0.f), b == 0 ? d0 : b == 1 ? d1 : b == 2 ? d2 : d3, x[r]);
+  }
+}
+
+// x[r] *= d_b, b = bit0 + 2 bit1 of the diagonal's index.  Bit j is register
+// bit k_j of r (k_j in 0..3), or, for k_j < 0, the constant bit j of c.  All
+// selections are per gate and thread, none per element.
+template <int PREC>
+__device__ inline void apply_diag(float2 (&x)[16], int n, int k0, int k1, int c, float2 d0, float2 d1, float2 d2,
+                                  float2 d3) {
+  if (n == 2 && k0 >= 0 && k1 >= 0) {
+    switch (k0 * 4 + k1) {
+      case 1: diag_reg2<PREC, 0, 1>(x, d0, d1, d2, d3); break;
+      case 2: diag_reg2<PREC, 0, 2>(x, d0, d1, d2, d3); break;
+      case 3: diag_reg2<PREC, 0, 3>(x, d0, d1, d2, d3); break;
+      case 4: diag_reg2<PREC, 1, 0>(x, d0, d1, d2, d3); break;
+      case 6: diag_reg2<PREC, 1, 2>(x, d0, d1, d2, d3); break;
+      case 7: diag_reg2<PREC, 1, 3>(x, d0, d1, d2, d3); break;
+      case 8: diag_reg2<PREC, 2, 0>(x, d0, d1, d2, d3); break;
+      case 9: diag_reg2<PREC, 2, 1>(x, d0, d1, d2, d3); break;
+      case 11: diag_reg2<PREC, 2, 3>(x, d0, d1, d2, d3); break;
+      case 12: diag_reg2<PREC, 3, 0>(x, d0, d1, d2, d3); break;
+      case 13: diag_reg2<PREC, 3, 1>(x, d0, d1, d2, d3); break;
+      default: diag_reg2<PREC, 3, 2>(x, d0, d1, d2, d3); break;
+    }
+    return;
+  }
+  int k = -1;
+  float2 e0, e1;
+  if (n == 2 && k0 >= 0) {  // bit 1 constant
+    k = k0;
+    e0 = (c & 2) ? d2 : d0;
+    e1 = (c & 2) ? d3 : d1;
+  } else if (n == 2 && k1 >= 0) {  // bit 0 constant
+    k = k1;
+    e0 = (c & 1) ? d1 : d0;
+    e1 = (c & 1) ? d3 : d2;
+  } else if (n == 1 && k0 >= 0) {
+    k = k0;
+    e0 = d0;
+    e1 = d1;
+  }
+  if (k < 0) {  // constant over the thread's elements
+    const float2 f = c == 0 ? d0 : c == 1 ? d1 : c == 2 ? d2 : d3;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) x[r] = cmac<PREC>(f2(0.f, 0.f), f, x[r]);
+    return;
+  }
+  switch (k) {
+    case 0: diag_reg1<PREC, 0>(x, e0, e1); break;
+    case 1: diag_reg1<PREC, 1>(x, e0, e1); break;
+    case 2: diag_reg1<PREC, 2>(x, e0, e1); break;
+    default: diag_reg1<PREC, 3>(x, e0, e1); break;
+  }
+}
+
+// register index of local bit b in a segment (or -1)
+__device__ inline int reg_index(const SweepSegment& seg, int b) {
+  return b == seg.rbits[0] ? 0 : b == seg.rbits[1] ? 1 : b == seg.rbits[2] ? 2 : b == seg.rbits[3] ? 3 : -1;
+}
+
 template <int PREC>
 __global__ __launch_bounds__(kThreads) void k_sweep_pass(SweepPassArgs a) {
   __shared__ float2 buf[(1 << kSweepMaxLocal) + (1 << (kSweepMaxLocal - 5))];
@@ -443,18 +517,15 @@ __global__ __launch_bounds__(kThreads) void k_sweep_pass(SweepPassArgs a) {
       if (gd.diag) {
         // unused entries of gidx are 0, so all four loads stay in bounds
         const float2 d0 = G[gd.gidx[0]], d1 = G[gd.gidx[1]], d2 = G[gd.gidx[2]], d3 = G[gd.gidx[3]];
-        const int j0 = gd.lidx[0], j1 = gd.n == 2 ? gd.lidx[1] : 0;
-        int fixed = 0, m0 = 0, s0 = 0, m1 = 0, s1 = 0;
-        if (j0 >= 0) { m0 = 1; s0 = j0; } else { fixed |= (int)((base >> (-j0 - 1)) & 1); }
-        if (gd.n == 2) {
-          if (j1 >= 0) { m1 = 1; s1 = j1; } else { fixed |= (int)((base >> (-j1 - 1)) & 1) << 1; }
-        }
+        int k[2] = {-1, -1}, c = 0;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int b = fixed | (m0 & (li[r] >> s0)) | ((m1 & (li[r] >> s1)) << 1);
-          const float2 f = b == 0 ? d0 : b == 1 ? d1 : b == 2 ? d2 : d3;
-          x[r] = cmac<PREC>(f2(0.f, 0.f), f, x[r]);
+        for (int j = 0; j < 2; ++j) {
+          if (j >= gd.n) break;
+          const int lj = gd.lidx[j];
+          if (lj < 0) c |= (int)((base >> (-lj - 1)) & 1) << j;  // outside the chunk
+          else if ((k[j] = reg_index(seg, lj)) < 0) c |= ((ob >> lj) & 1) << j;  // a thread bit
         }
+        apply_diag<PREC>(x, gd.n, k[0], k[1], c, d0, d1, d2, d3);
       } else if (gd.n == 1) {
         float2 g[4];
         for (int e = 0; e < 4; ++e) g[e] = G[gd.gidx[e]];
@@ -1171,6 +1242,293 @@ hipError_t launch_adjoint_step(hipStream_t s, const SweepArgs& a, const float2* 
   void* args[] = {&aa, (void*)&u, (void*)&u_bs, (void*)&psi, (void*)&psi_bs, (void*)&lam, (void*)&lam_bs,
                   (void*)&groups, (void*)&partials, (void*)&partial_stride};
   return hipLaunchKernel(fn, dim3(blocks, batch), dim3(kThreads), args, 0, s);
+}
+
+// Fused adjoint pass (see AdjGateDesc).  Two chunks (psi and lambda) in LDS;
+// per segment each thread holds 16 elements of each in registers.
+struct AdjPassArgs {
+  float2* psi;
+  float2* lam;
+  int64_t psi_bs, lam_bs;
+  const float2* U;
+  int64_t u_bs;
+  const AdjGateDesc* gates;
+  const SweepSegment* segs;
+  double* partials;
+  int64_t pstride;
+  int64_t n_chunks;
+  int32_t n_segs, l, n_rest, n_red;
+  int32_t first_gate, n_gates;
+  int8_t lpos[kSweepMaxLocal];
+  int8_t rest[64];
+};
+
+__device__ inline float im_conj_mul(float2 l, float2 q) { return l.x * q.y - l.y * q.x; }
+__device__ inline float2 cmulf(float2 a, float2 b) { return f2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+
+// sum over the register pairs along bit U of Im(conj(l_m) (G p)_m)
+template <int U>
+__device__ inline float reg_grad1(const float2 (&p)[16], const float2 (&l)[16], const float2* G) {
+  float g = 0.f;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    if (r & (1 << U)) continue;
+    const int r1 = r | (1 << U);
+    const float2 q0 = f2(G[0].x * p[r].x - G[0].y * p[r].y + G[1].x * p[r1].x - G[1].y * p[r1].y,
+                         G[0].x * p[r].y + G[0].y * p[r].x + G[1].x * p[r1].y + G[1].y * p[r1].x);
+    const float2 q1 = f2(G[2].x * p[r].x - G[2].y * p[r].y + G[3].x * p[r1].x - G[3].y * p[r1].y,
+                         G[2].x * p[r].y + G[2].y * p[r].x + G[3].x * p[r1].y + G[3].y * p[r1].x);
+    g += im_conj_mul(l[r], q0) + im_conj_mul(l[r1], q1);
+  }
+  return g;
+}
+
+// Sum over the 16 register elements of Im(conj(l) q_b p), b resolved as in apply_diag
+template <int U>
+__device__ inline float dgrad_reg1(const float2 (&p)[16], const float2 (&l)[16], float2 e0, float2 e1) {
+  float g = 0.f;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) g += im_conj_mul(l[r], cmulf((r >> U) & 1 ? e1 : e0, p[r]));
+  return g;
+}
+template <int U0, int U1>
+__device__ inline float dgrad_reg2(const float2 (&p)[16], const float2 (&l)[16], float2 q0, float2 q1, float2 q2,
+                                   float2 q3) {
+  float g = 0.f;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int b = ((r >> U0) & 1) | (((r >> U1) & 1) << 1);
+    g += im_conj_mul(l[r], cmulf(b == 0 ? q0 : b == 1 ? q1 : b == 2 ? q2 : q3, p[r]));
+  }
+  return g;
+}
+__device__ inline float diag_grad(const float2 (&p)[16], const float2 (&l)[16], int n, int k0, int k1, int c,
+                                  float2 q0, float2 q1, float2 q2, float2 q3) {
+  if (n == 2 && k0 >= 0 && k1 >= 0) {
+    switch (k0 * 4 + k1) {
+      case 1: return dgrad_reg2<0, 1>(p, l, q0, q1, q2, q3);
+      case 2: return dgrad_reg2<0, 2>(p, l, q0, q1, q2, q3);
+      case 3: return dgrad_reg2<0, 3>(p, l, q0, q1, q2, q3);
+      case 4: return dgrad_reg2<1, 0>(p, l, q0, q1, q2, q3);
+      case 6: return dgrad_reg2<1, 2>(p, l, q0, q1, q2, q3);
+      case 7: return dgrad_reg2<1, 3>(p, l, q0, q1, q2, q3);
+      case 8: return dgrad_reg2<2, 0>(p, l, q0, q1, q2, q3);
+      case 9: return dgrad_reg2<2, 1>(p, l, q0, q1, q2, q3);
+      case 11: return dgrad_reg2<2, 3>(p, l, q0, q1, q2, q3);
+      case 12: return dgrad_reg2<3, 0>(p, l, q0, q1, q2, q3);
+      case 13: return dgrad_reg2<3, 1>(p, l, q0, q1, q2, q3);
+      default: return dgrad_reg2<3, 2>(p, l, q0, q1, q2, q3);
+    }
+  }
+  int k = -1;
+  float2 e0, e1;
+  if (n == 2 && k0 >= 0) {
+    k = k0;
+    e0 = (c & 2) ? q2 : q0;
+    e1 = (c & 2) ? q3 : q1;
+  } else if (n == 2 && k1 >= 0) {
+    k = k1;
+    e0 = (c & 1) ? q1 : q0;
+    e1 = (c & 1) ? q3 : q2;
+  } else if (n == 1 && k0 >= 0) {
+    k = k0;
+    e0 = q0;
+    e1 = q1;
+  }
+  if (k < 0) {
+    const float2 f = c == 0 ? q0 : c == 1 ? q1 : c == 2 ? q2 : q3;
+    float g = 0.f;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) g += im_conj_mul(l[r], cmulf(f, p[r]));
+    return g;
+  }
+  switch (k) {
+    case 0: return dgrad_reg1<0>(p, l, e0, e1);
+    case 1: return dgrad_reg1<1>(p, l, e0, e1);
+    case 2: return dgrad_reg1<2>(p, l, e0, e1);
+    default: return dgrad_reg1<3>(p, l, e0, e1);
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a) {
+  constexpr int kBuf = (1 << kSweepMaxLocal) + (1 << (kSweepMaxLocal - 5));
+  __shared__ float2 bp[kBuf], bl[kBuf];
+  __shared__ int64_t dep_hi[1 << (kSweepMaxLocal - 5)];
+  __shared__ double red[kAdjMaxRed][kThreads / 64];
+  const int z = blockIdx.y;
+  const int L = 1 << a.l;
+  const int nt = blockDim.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
+  for (int i = tid; i < a.n_red * nw; i += nt) red[i / nw][i % nw] = 0.0;
+  for (int h = tid; h < (L >> 5); h += nt) {
+    int64_t d = 0;
+    for (int j = 5; j < a.l; ++j)
+      if ((h >> (j - 5)) & 1) d |= (int64_t)1 << a.lpos[j];
+    dep_hi[h] = d;
+  }
+  __syncthreads();
+  float2* P = a.psi + (int64_t)z * a.psi_bs;
+  float2* Lm = a.lam + (int64_t)z * a.lam_bs;
+  const float2* Uz = a.U + (int64_t)z * a.u_bs;
+  for (int64_t c = blockIdx.x; c < a.n_chunks; c += gridDim.x) {
+    int64_t base = 0;
+    for (int j = 0; j < a.n_rest; ++j)
+      if ((c >> j) & 1) base |= (int64_t)1 << a.rest[j];
+    for (int i = tid; i < L; i += nt) {
+      const int64_t x = base | (i & 31) | dep_hi[i >> 5];
+      bp[lds_phys(i)] = P[x];
+      bl[lds_phys(i)] = Lm[x];
+    }
+    __syncthreads();
+    for (int sg = 0; sg < a.n_segs; ++sg) {
+      const SweepSegment seg = a.segs[sg];
+      int ob = 0;
+      {
+        int tb = 0;
+        for (int b = 0; b < a.l; ++b) {
+          if (b == seg.rbits[0] || b == seg.rbits[1] || b == seg.rbits[2] || b == seg.rbits[3]) continue;
+          if ((tid >> tb) & 1) ob |= 1 << b;
+          ++tb;
+        }
+      }
+      int li[16];
+      float2 xp[16], xl[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        li[r] = ob | ((r & 1) << seg.rbits[0]) | (((r >> 1) & 1) << seg.rbits[1]) |
+                (((r >> 2) & 1) << seg.rbits[2]) | (((r >> 3) & 1) << seg.rbits[3]);
+        xp[r] = bp[lds_phys(li[r])];
+        xl[r] = bl[lds_phys(li[r])];
+      }
+      for (int gi = seg.first_gate; gi < seg.first_gate + seg.n_gates; ++gi) {
+        const AdjGateDesc& gd = a.gates[gi];
+        const float2* U = Uz + (int64_t)gd.gate * 16;
+        const float2* G = reinterpret_cast<const float2*>(gd.gen);
+        if (gd.diag) {
+          int k[2] = {-1, -1}, c = 0;
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            if (j >= gd.n) break;
+            const int lj = gd.lidx[j];
+            if (lj < 0) c |= (int)((base >> (-lj - 1)) & 1) << j;
+            else if ((k[j] = reg_index(seg, lj)) < 0) c |= ((ob >> lj) & 1) << j;
+          }
+          const bool two = gd.n == 2;
+          // U^dagger diagonal: conj(U[b][b])
+          const float2 u0 = U[0], u1 = two ? U[5] : U[3], u2 = two ? U[10] : f2(1.f, 0.f),
+                       u3 = two ? U[15] : f2(1.f, 0.f);
+          if (gd.red >= 0) {
+            const float2 q2 = two ? G[2] : f2(0.f, 0.f), q3 = two ? G[3] : f2(0.f, 0.f);
+            double v = (double)diag_grad(xp, xl, gd.n, k[0], k[1], c, G[0], G[1], q2, q3);
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+            if (lane == 0) red[gd.red][wv] += v;
+          }
+          const float2 d0 = f2(u0.x, -u0.y), d1 = f2(u1.x, -u1.y), d2 = f2(u2.x, -u2.y), d3 = f2(u3.x, -u3.y);
+          apply_diag<TN_PREC_C64>(xp, gd.n, k[0], k[1], c, d0, d1, d2, d3);
+          apply_diag<TN_PREC_C64>(xl, gd.n, k[0], k[1], c, d0, d1, d2, d3);
+        } else if (gd.n == 1) {
+          if (gd.red >= 0) {
+            float g;
+            switch (gd.rb[0]) {
+              case 0: g = reg_grad1<0>(xp, xl, G); break;
+              case 1: g = reg_grad1<1>(xp, xl, G); break;
+              case 2: g = reg_grad1<2>(xp, xl, G); break;
+              default: g = reg_grad1<3>(xp, xl, G); break;
+            }
+            double v = (double)g;
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+            if (lane == 0) red[gd.red][wv] += v;
+          }
+          // U^dagger[m][k] = conj(U[k][m])
+          float2 ud[4];
+          ud[0] = f2(U[0].x, -U[0].y);
+          ud[1] = f2(U[2].x, -U[2].y);
+          ud[2] = f2(U[1].x, -U[1].y);
+          ud[3] = f2(U[3].x, -U[3].y);
+          switch (gd.rb[0]) {
+            case 0: reg_apply1<TN_PREC_C64, 0>(xp, ud); reg_apply1<TN_PREC_C64, 0>(xl, ud); break;
+            case 1: reg_apply1<TN_PREC_C64, 1>(xp, ud); reg_apply1<TN_PREC_C64, 1>(xl, ud); break;
+            case 2: reg_apply1<TN_PREC_C64, 2>(xp, ud); reg_apply1<TN_PREC_C64, 2>(xl, ud); break;
+            default: reg_apply1<TN_PREC_C64, 3>(xp, ud); reg_apply1<TN_PREC_C64, 3>(xl, ud); break;
+          }
+        } else {
+          // dense two-qubit gates carry no gradient term (the planner checks)
+          float2 ud[16];
+#pragma unroll
+          for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) ud[4 * m + k] = f2(U[4 * k + m].x, -U[4 * k + m].y);
+          switch (gd.rb[0] * 4 + gd.rb[1]) {
+            case 1: reg_apply2<TN_PREC_C64, 0, 1>(xp, ud); reg_apply2<TN_PREC_C64, 0, 1>(xl, ud); break;
+            case 4: reg_apply2<TN_PREC_C64, 1, 0>(xp, ud); reg_apply2<TN_PREC_C64, 1, 0>(xl, ud); break;
+            case 2: reg_apply2<TN_PREC_C64, 0, 2>(xp, ud); reg_apply2<TN_PREC_C64, 0, 2>(xl, ud); break;
+            case 8: reg_apply2<TN_PREC_C64, 2, 0>(xp, ud); reg_apply2<TN_PREC_C64, 2, 0>(xl, ud); break;
+            case 3: reg_apply2<TN_PREC_C64, 0, 3>(xp, ud); reg_apply2<TN_PREC_C64, 0, 3>(xl, ud); break;
+            case 12: reg_apply2<TN_PREC_C64, 3, 0>(xp, ud); reg_apply2<TN_PREC_C64, 3, 0>(xl, ud); break;
+            case 6: reg_apply2<TN_PREC_C64, 1, 2>(xp, ud); reg_apply2<TN_PREC_C64, 1, 2>(xl, ud); break;
+            case 9: reg_apply2<TN_PREC_C64, 2, 1>(xp, ud); reg_apply2<TN_PREC_C64, 2, 1>(xl, ud); break;
+            case 7: reg_apply2<TN_PREC_C64, 1, 3>(xp, ud); reg_apply2<TN_PREC_C64, 1, 3>(xl, ud); break;
+            case 13: reg_apply2<TN_PREC_C64, 3, 1>(xp, ud); reg_apply2<TN_PREC_C64, 3, 1>(xl, ud); break;
+            case 11: reg_apply2<TN_PREC_C64, 2, 3>(xp, ud); reg_apply2<TN_PREC_C64, 2, 3>(xl, ud); break;
+            default: reg_apply2<TN_PREC_C64, 3, 2>(xp, ud); reg_apply2<TN_PREC_C64, 3, 2>(xl, ud); break;
+          }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        bp[lds_phys(li[r])] = xp[r];
+        bl[lds_phys(li[r])] = xl[r];
+      }
+      __syncthreads();
+    }
+    for (int i = tid; i < L; i += nt) {
+      const int64_t x = base | (i & 31) | dep_hi[i >> 5];
+      P[x] = bp[lds_phys(i)];
+      Lm[x] = bl[lds_phys(i)];
+    }
+    __syncthreads();
+  }
+  // every (slot, block) entry of the pass's gates is written, zero for blocks without a chunk
+  for (int gi = a.first_gate + tid; gi < a.first_gate + a.n_gates; gi += nt) {
+    const AdjGateDesc& gd = a.gates[gi];
+    if (gd.red < 0 || gd.slot < 0) continue;
+    double v = 0;
+    for (int w = 0; w < nw; ++w) v += red[gd.red][w];
+    a.partials[(int64_t)z * a.pstride + (int64_t)gd.slot * kReduceBlocks + blockIdx.x] = v;
+  }
+}
+
+hipError_t launch_adjoint_pass(hipStream_t s, const SweepPass& ps, int bits, const AdjGateDesc* gates_dev,
+                               const SweepSegment* segs_dev, const float2* u, int64_t u_bs, float2* psi,
+                               int64_t psi_bs, float2* lam, int64_t lam_bs, int batch, double* partials,
+                               int64_t partial_stride) {
+  AdjPassArgs a;
+  a.psi = psi; a.lam = lam; a.psi_bs = psi_bs; a.lam_bs = lam_bs;
+  a.U = u; a.u_bs = u_bs;
+  a.gates = gates_dev;
+  a.segs = segs_dev + ps.first_seg;
+  a.partials = partials;
+  a.pstride = partial_stride;
+  a.n_segs = ps.n_segs;
+  a.l = ps.l;
+  a.n_red = ps.n_red;
+  a.first_gate = ps.first_gate;
+  a.n_gates = ps.n_gates;
+  // 64 threads at least (whole waves for the gradient reductions), 256 at most
+  if (ps.l < 10 || ps.l > kSweepMaxLocal || ps.n_red < 0 || ps.n_red > kAdjMaxRed) return hipErrorInvalidValue;
+  std::vector<char> local(bits, 0);
+  for (int j = 0; j < ps.l; ++j) {
+    a.lpos[j] = ps.lpos[j];
+    if (ps.lpos[j] < 0 || ps.lpos[j] >= bits || (j < 5 && ps.lpos[j] != j)) return hipErrorInvalidValue;
+    local[ps.lpos[j]] = 1;
+  }
+  int nr = 0;
+  for (int p = 0; p < bits; ++p)
+    if (!local[p]) a.rest[nr++] = (int8_t)p;
+  a.n_rest = nr;
+  a.n_chunks = (int64_t)1 << nr;
+  const int threads = 1 << (ps.l - 4);
+  hipLaunchKernelGGL(k_adjoint_pass, dim3(kReduceBlocks, batch), dim3(threads), 0, s, a);
+  return hipGetLastError();
 }
 
 __global__ void k_slot_sums(double* partials, int64_t pstride, int n_slots, int batch) {

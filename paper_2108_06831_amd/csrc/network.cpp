@@ -349,6 +349,7 @@ extern "C" tn_status tn_build_network(int32_t n_qubits, const tn_gate* gates, in
       net->sweep_recipes.push_back(r);
       s.param = op.param[0];
       s.gen = s.param >= 0 ? gen_of(kind) : GEN_NONE;
+      s.diag = gate_is_diagonal(kind) ? 1 : 0;
       net->sweep.push_back(s);
     };
     if (G.kind == TN_GATE_U3 && (G.param[0] >= 0 || G.param[1] >= 0 || G.param[2] >= 0)) {

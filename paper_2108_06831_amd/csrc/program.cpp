@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "passes.h"
 
 namespace tnq {
 
@@ -227,78 +228,36 @@ void build_chains(tn_path* path, int T) {
     ch.first_pass = (int32_t)path->passes.size();
     ch.n_steps = e - s;
     const int R = ch.bits;
-    const int lmax = std::min(kSweepMaxLocal, R - 8);  // >= kSweepMinLocal since R >= 16
-    const int low = 5;  // lmax >= 6 + 2 since R >= 16: room for any two-qubit gate next to the low bits
-    // gate list: positions in T
-    struct G { std::vector<int> pos; int step; };
-    std::vector<G> gates;
+    std::vector<PassItem> items;
     for (int i = s; i < e; ++i) {
       const SkinnyDesc& d = path->steps[i].sk;
-      G g;
-      g.step = i;
-      if (d.nb == 0) for (int j = 0; j < d.nk; ++j) g.pos.push_back(d.k_pos[j]);
-      else for (int j = 0; j < d.nb; ++j) g.pos.push_back(d.bt_pos[j]);
-      gates.push_back(g);
+      PassItem it;
+      it.diag = d.nb > 0;
+      if (d.nb == 0) for (int j = 0; j < d.nk; ++j) it.pos.push_back(d.k_pos[j]);
+      else for (int j = 0; j < d.nb; ++j) it.pos.push_back(d.bt_pos[j]);
+      items.push_back(it);
     }
-    std::vector<char> done(gates.size(), 0);
-    size_t remaining = gates.size();
-    while (remaining > 0) {
-      // blk_any[p]: a gate left out of this pass touches p (later dense gates on p wait);
-      // blk_dense[p]: a dense gate left out touches p (later diagonal gates on p wait too).
-      // Diagonal gates commute with each other and need no local bits: a bit outside the
-      // chunk is constant over it and read from the chunk's base address.
-      std::vector<char> local(R, 0), blk_any(R, 0), blk_dense(R, 0);
-      int nl = 0;
-      for (int p = 0; p < low; ++p) { local[p] = 1; ++nl; }
+    std::vector<PlannedPass> planned;
+    if (!plan_passes(R, items, planned)) {  // leave the chain to the per-step kernels
+      s = e;
+      continue;
+    }
+    for (const PlannedPass& pp : planned) {
       SweepPass ps;
+      ps.l = pp.l;
+      for (int j = 0; j < kSweepMaxLocal; ++j) ps.lpos[j] = j < ps.l ? (int8_t)pp.lpos[j] : 0;
       ps.first_gate = (int32_t)path->sweep_gates.size();
-      std::vector<int> members;
-      for (size_t gi = 0; gi < gates.size(); ++gi) {
-        if (done[gi]) continue;
-        const auto& pos = gates[gi].pos;
-        const bool diag = path->steps[gates[gi].step].sk.nb > 0;
-        bool take;
-        if (diag) {
-          take = true;
-          for (int p : pos) take &= !blk_dense[p];
-        } else {
-          int extra = 0;
-          take = true;
-          for (int p : pos) { take &= !blk_any[p]; extra += !local[p]; }
-          take &= nl + extra <= lmax;
-        }
-        if (take) {
-          if (!diag)
-            for (int p : pos) if (!local[p]) { local[p] = 1; ++nl; }
-          members.push_back((int)gi);
-          done[gi] = 1;
-          --remaining;
-        } else {
-          for (int p : pos) {
-            blk_any[p] = 1;
-            if (!diag) blk_dense[p] = 1;
-          }
-        }
-      }
-      // fill the local set up to lmax with the lowest remaining bits (longer contiguous runs)
-      for (int p = 0; p < R && nl < lmax; ++p) if (!local[p]) { local[p] = 1; ++nl; }
-      std::vector<int> lpos;
-      for (int p = 0; p < R; ++p) if (local[p]) lpos.push_back(p);
-      ps.l = (int32_t)lpos.size();
-      for (int j = 0; j < kSweepMaxLocal; ++j) ps.lpos[j] = j < ps.l ? (int8_t)lpos[j] : 0;
-      auto lidx_of = [&](int p) { return (int32_t)(std::find(lpos.begin(), lpos.end(), p) - lpos.begin()); };
-      for (int gi : members) {
-        const SkinnyDesc& d = path->steps[gates[gi].step].sk;
+      ps.n_gates = (int32_t)pp.gates.size();
+      ps.n_red = 0;
+      for (const PlannedGate& pg : pp.gates) {
+        const SkinnyDesc& d = path->steps[s + pg.item].sk;
         SweepGateDesc gd;
-        gd.diag = d.nb > 0;
-        gd.n = (int32_t)gates[gi].pos.size();
+        gd.diag = pg.diag;
+        gd.n = pg.n;
         gd.pad = 0;
         for (int j = 0; j < 2; ++j) {
-          gd.lidx[j] = 0;
-          if (j >= gd.n) continue;
-          const int p = gates[gi].pos[j];
-          // a diagonal gate's bit outside the chunk is encoded as -(position + 1)
-          gd.lidx[j] = local[p] ? lidx_of(p) : -(p + 1);
+          gd.lidx[j] = pg.lidx[j];
+          gd.rb[j] = pg.rb[j];
         }
         gd.g_buf = d.g.buf;
         gd.unit = gd.diag ? d.g_unit : 0;
@@ -308,62 +267,16 @@ void build_chains(tn_path* path, int T) {
         for (int j = 0; j < ne; ++j) gd.gidx[j] = d.gidx[j];
         path->sweep_gates.push_back(gd);
       }
-      ps.n_gates = (int32_t)members.size();
-      if (members.empty()) break;  // cannot happen with lmax >= low + 2; guards the loop
-      // segments: consecutive runs whose dense gates' local bits fit in four register bits
       ps.first_seg = (int32_t)path->segments.size();
-      {
-        std::vector<int> rset;
+      for (const PlannedSeg& sg : pp.segs) {
         SweepSegment seg;
-        seg.first_gate = ps.first_gate;
-        seg.n_gates = 0;
-        auto close = [&]() {
-          // complete the register set with other local bits (the lowest unused ones)
-          for (int b = 0; b < ps.l && (int)rset.size() < 4; ++b)
-            if (std::find(rset.begin(), rset.end(), b) == rset.end()) rset.push_back(b);
-          std::sort(rset.begin(), rset.end());
-          for (int j = 0; j < 4; ++j) seg.rbits[j] = (int8_t)rset[j];
-          for (int g = seg.first_gate; g < seg.first_gate + seg.n_gates; ++g) {
-            SweepGateDesc& gd = path->sweep_gates[g];
-            gd.rb[0] = gd.rb[1] = 0;
-            if (gd.diag) continue;
-            for (int j = 0; j < gd.n; ++j)
-              gd.rb[j] = (int32_t)(std::find(rset.begin(), rset.end(), gd.lidx[j]) - rset.begin());
-          }
-          path->segments.push_back(seg);
-        };
-        for (int g = ps.first_gate; g < ps.first_gate + ps.n_gates; ++g) {
-          const SweepGateDesc& gd = path->sweep_gates[g];
-          if (!gd.diag) {
-            std::vector<int> u = rset;
-            for (int j = 0; j < gd.n; ++j)
-              if (std::find(u.begin(), u.end(), gd.lidx[j]) == u.end()) u.push_back(gd.lidx[j]);
-            if ((int)u.size() > 4) {
-              close();
-              rset.clear();
-              seg.first_gate = g;
-              seg.n_gates = 0;
-              u.clear();
-              for (int j = 0; j < gd.n; ++j) u.push_back(gd.lidx[j]);
-            }
-            rset = u;
-          }
-          seg.n_gates++;
-        }
-        close();
+        for (int j = 0; j < 4; ++j) seg.rbits[j] = sg.rbits[j];
+        seg.first_gate = ps.first_gate + sg.first;
+        seg.n_gates = sg.count;
+        path->segments.push_back(seg);
       }
-      ps.n_segs = (int32_t)path->segments.size() - ps.first_seg;
+      ps.n_segs = (int32_t)pp.segs.size();
       path->passes.push_back(ps);
-    }
-    if (remaining > 0) {  // leave the chain to the per-step kernels
-      const bool any = path->passes.size() > (size_t)ch.first_pass;
-      const int32_t fg = any ? path->passes[ch.first_pass].first_gate : (int32_t)path->sweep_gates.size();
-      const int32_t fs = any ? path->passes[ch.first_pass].first_seg : (int32_t)path->segments.size();
-      path->passes.resize(ch.first_pass);
-      path->sweep_gates.resize(fg);
-      path->segments.resize(fs);
-      s = e;
-      continue;
     }
     ch.n_passes = (int32_t)path->passes.size() - ch.first_pass;
     path->steps[s].chain = (int32_t)path->chains.size();
@@ -879,6 +792,88 @@ tn_status compile_program(const tn_network* net, tn_path* path, const std::vecto
 // orders: launch overhead per kernel, streaming kernels at a sustained HBM rate,
 // permutes at their measured rate, matrix products at the sustained FP32
 // matrix-core rate scaled down for tiles the shape leaves partly empty.
+void build_adjoint_plan(const tn_network* net, tn_path* path, const std::vector<int32_t>& slot_of_gate) {
+  path->adj_passes.clear();
+  path->adj_segments.clear();
+  path->adj_gates.clear();
+  path->adj_state = -1;
+  const int R = (int)path->final_bits.size();
+  // whole waves for the gradient reductions need chunks of 2^10 elements at least
+  if (R < 18 || path->final_elems != ((int64_t)1 << R) || path->final_ref.buf != BUF_WS) return;
+  const int G = (int)net->sweep.size();
+  if ((int)slot_of_gate.size() != G) return;
+  std::vector<PassItem> items;
+  for (int gi = G - 1; gi >= 0; --gi) {  // the reverse sweep undoes the gates last to first
+    const SweepGate& g = net->sweep[gi];
+    if (g.nq == 2 && !g.diag && g.gen != GEN_NONE) return;
+    PassItem it;
+    it.diag = g.diag != 0;
+    const int p0 = pos_of(path->final_bits, net->wire_final[g.q[0]] * 64);
+    const int p1 = g.nq == 2 ? pos_of(path->final_bits, net->wire_final[g.q[1]] * 64) : 0;
+    if (p0 < 0 || p1 < 0) return;
+    // bit 0 of the gate's own index is its second qubit (the first is the more significant)
+    if (g.nq == 2) it.pos = {p1, p0};
+    else it.pos = {p0};
+    items.push_back(it);
+  }
+  std::vector<PlannedPass> planned;
+  if (!plan_passes(R, items, planned)) return;
+  for (const PlannedPass& pp : planned) {
+    SweepPass ps;
+    ps.l = pp.l;
+    for (int j = 0; j < kSweepMaxLocal; ++j) ps.lpos[j] = j < ps.l ? (int8_t)pp.lpos[j] : 0;
+    ps.first_gate = (int32_t)path->adj_gates.size();
+    ps.n_gates = (int32_t)pp.gates.size();
+    ps.n_red = 0;
+    for (const PlannedGate& pg : pp.gates) {
+      const int gi = G - 1 - pg.item;
+      const SweepGate& g = net->sweep[gi];
+      AdjGateDesc gd;
+      gd.diag = pg.diag;
+      gd.n = pg.n;
+      for (int j = 0; j < 2; ++j) {
+        gd.lidx[j] = pg.lidx[j];
+        gd.rb[j] = pg.rb[j];
+      }
+      gd.gate = gi;
+      gd.slot = slot_of_gate[gi];
+      gd.red = gd.slot >= 0 ? ps.n_red++ : -1;
+      gd.pad = 0;
+      // generator G with g = Im<lambda|G|psi> (the derivative of the gate is -i G / 2 or -i G)
+      for (float& x : gd.gen) x = 0.f;
+      auto set = [&](int k, float re, float im) { gd.gen[2 * k] = re; gd.gen[2 * k + 1] = im; };
+      switch (gd.slot >= 0 ? g.gen : GEN_NONE) {
+        case GEN_X_HALF: set(1, 1, 0); set(2, 1, 0); break;            // X
+        case GEN_X: set(1, 2, 0); set(2, 2, 0); break;                 // 2 X
+        case GEN_Y_HALF: set(1, 0, -1); set(2, 0, 1); break;           // Y
+        case GEN_Z_HALF: set(0, 1, 0); set(1, -1, 0); break;           // Z (diagonal)
+        case GEN_ZZ_PHASE: set(1, 2, 0); set(2, 2, 0); break;          // 1 - Z Z (diagonal)
+        case GEN_CPHASE: set(3, -2, 0); break;                         // -2 |11><11| (diagonal)
+        default: break;
+      }
+      if (gd.slot >= 0 && g.gen == GEN_NONE) return;
+      path->adj_gates.push_back(gd);
+    }
+    if (ps.n_red > kAdjMaxRed) {
+      path->adj_passes.clear();
+      path->adj_segments.clear();
+      path->adj_gates.clear();
+      return;
+    }
+    ps.first_seg = (int32_t)path->adj_segments.size();
+    for (const PlannedSeg& sg : pp.segs) {
+      SweepSegment seg;
+      for (int j = 0; j < 4; ++j) seg.rbits[j] = sg.rbits[j];
+      seg.first_gate = ps.first_gate + sg.first;
+      seg.n_gates = sg.count;
+      path->adj_segments.push_back(seg);
+    }
+    ps.n_segs = (int32_t)pp.segs.size();
+    path->adj_passes.push_back(ps);
+  }
+  path->adj_state = 1;
+}
+
 void gemm_default_launch(const GemmDesc& g, int* tile, int* split) {
   *split = 1;
   if ((g.M < 64 || g.N < 32) && g.K <= kElemMaxK) {

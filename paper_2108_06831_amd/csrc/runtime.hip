@@ -150,6 +150,8 @@ struct DevPath {
   int32_t* levels = nullptr;
   SweepGateDesc* sweep_gates = nullptr;
   SweepSegment* segments = nullptr;
+  AdjGateDesc* adj_gates = nullptr;     // uploaded on the first backward call
+  SweepSegment* adj_segments = nullptr;
 };
 
 static tn_status ensure_path_device(tn_path* path, DevPath** out) {
@@ -181,6 +183,8 @@ void device_release_path(tn_path* path) {
   (void)hipFree(d->levels);
   (void)hipFree(d->sweep_gates);
   (void)hipFree(d->segments);
+  (void)hipFree(d->adj_gates);
+  (void)hipFree(d->adj_segments);
   (void)hipSetDevice(cur);
   delete d;
   path->dev = nullptr;
@@ -657,7 +661,30 @@ extern "C" tn_status tn_backward(void* stream, int32_t precision, tn_network* ne
                                 net->n_params, batch, umats));
   double* parts = (double*)(w + L.part_off);
   const int64_t pstride = (int64_t)std::max(d->n_slots, 1) * kReduceBlocks;
-  for (int gi = (int)net->sweep.size() - 1; gi >= 0; --gi) {
+  if (path->adj_state == 0) build_adjoint_plan(net, path, d->slot_of_gate);
+  if (path->adj_state == 1) {
+    // fused passes: both states stream through LDS once per pass
+    DevPath* dp;
+    if ((st = ensure_path_device(path, &dp)) != TN_OK) return st;
+    if (!dp->adj_gates) {
+      HIP_TRY(upload(&dp->adj_gates, path->adj_gates));
+      HIP_TRY(upload(&dp->adj_segments, path->adj_segments));
+    }
+    const int bits = (int)path->final_bits.size();
+    for (const SweepPass& ps : path->adj_passes) {
+      double fl = 0;
+      for (int i = ps.first_gate; i < ps.first_gate + ps.n_gates; ++i) {
+        const AdjGateDesc& gd = path->adj_gates[i];
+        const double per = gd.diag ? 12.0 : 16.0 * (double)(1 << gd.n);  // flops per element and state
+        fl += 2.0 * per * (double)n + (gd.red >= 0 ? 8.0 * (double)n : 0.0);
+      }
+      hipEvent_t ev = prof_start(s);
+      HIP_TRY(launch_adjoint_pass(s, ps, bits, dp->adj_gates, dp->adj_segments, umats,
+                                  (int64_t)net->sweep.size() * 16, psi, pbs, lam, n, batch, parts, pstride));
+      prof_stop(s, ev, TN_KERNEL_ADJOINT, 32.0 * (double)n * batch, fl * batch);
+    }
+  }
+  for (int gi = path->adj_state == 1 ? -1 : (int)net->sweep.size() - 1; gi >= 0; --gi) {
     const SweepGate& g = net->sweep[gi];
     SweepArgs a;
     a.nq = g.nq;

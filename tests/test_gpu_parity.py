@@ -250,3 +250,36 @@ def test_config4_full_gradients():
     e = np.linalg.norm(grad[0, which[:4]] - fd[which[:4]] / (np.sin(h) / h)) / np.linalg.norm(fd[which[:4]])
     print(f"  FD check rel err {e:.2e}", flush=True)
     assert e < C64_TOL
+
+
+@pytest.mark.parametrize("n,seed", [(18, 0), (19, 1)])
+def test_adjoint_passes_every_gate_kind(n, seed):
+    """Adjoint gradients through the fused reverse-sweep passes (final tensor
+    of 2^18 or more elements): random circuits with every gate kind, angles
+    sharing parameters (product rule), a Z-string observable mixing one- and
+    two-qubit terms; against the oracle's exact parameter shift."""
+    from paper_2108_06831_amd import Network, Observable, backward, profile_enable, profile_read, profile_reset
+    rng = np.random.default_rng(5150 + seed)
+    circ = workloads.random_circuit(n, 120, rng, n_params=9)
+    params = rng.uniform(0.0, 2.0 * np.pi, size=(2, circ.n_params))
+    m, c = workloads.zz_ring_observable(n)
+    m = np.concatenate([m, np.array([1 << (n - 1), 1 << 3], dtype=np.uint64)])
+    c = np.concatenate([c, np.array([0.7, -1.3])])
+    net = Network.from_circuit(circ)
+    path = net.plan("sequential")
+    profile_reset()
+    profile_enable(True)
+    value, grad = backward(net, path, params, Observable(m, c), batch=2)
+    prof = profile_read()
+    profile_enable(False)
+    value, grad = value.cpu().numpy(), grad.cpu().numpy()
+    n_sweep = sum(3 if (g.kind == "U3" and any(p >= 0 for p in g.params)) else 1 for g in circ.gates)
+    print(f"n={n}: adjoint launches {prof['adjoint']['launches']} for {n_sweep} gates", flush=True)
+    assert prof["adjoint"]["launches"] < n_sweep / 4
+    for b in range(2):
+        want_e = oracle.circuit_expectation(circ, params[b], m, c)
+        assert scalar_err(value[b], want_e) < C64_TOL
+        g = oracle.param_shift_gradient(circ, params[b], m, c)
+        e = np.linalg.norm(grad[b] - g) / np.linalg.norm(g)
+        print(f"  vector {b}: value err {scalar_err(value[b], want_e):.2e}, grad rel err {e:.2e}", flush=True)
+        assert e < C64_TOL
