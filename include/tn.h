@@ -282,6 +282,24 @@ tn_status tn_contract_pair(void* stream, int32_t precision, const void* a, int32
                            void* workspace_dev, size_t workspace_bytes);
 
 /*
+ * HIP graphs.  tn_graph_begin starts capturing `stream` (not the null stream);
+ * every entry point called on that stream by this thread until tn_graph_end
+ * is recorded instead of run, and tn_graph_end instantiates the recording.
+ * tn_graph_launch replays all of it as one graph launch, with the device
+ * pointers given at capture time (update params, inputs and bitstrings in
+ * place between launches).  Device-side tables of a network and a path are
+ * created on their first use and cannot be created during a capture: run the
+ * calls once before capturing them (TN_EDEVICE otherwise).  Kernel timing
+ * must be off while capturing.  The library's kernels clear no memory with
+ * memset nodes, so replays are self-contained.
+ */
+typedef struct tn_graph tn_graph;
+tn_status tn_graph_begin(void* stream);
+tn_status tn_graph_end(void* stream, tn_graph** graph_out);
+tn_status tn_graph_launch(const tn_graph* graph, void* stream);
+void tn_graph_destroy(tn_graph* graph);
+
+/*
  * Autotuner for the launch shapes of the matrix-product steps.
  * Runs the path's steps once on `stream` (gate tensors from params_dev, for
  * `batch` parameter vectors; amplitude projectors are left zero), then for
@@ -337,6 +355,11 @@ typedef struct {
   double flops;       /* sum of algorithmic flops */
 } tn_kernel_profile;
 tn_status tn_profile_enable(int32_t on);
+/* Kernel kinds timed while timing is enabled: bit k for tn_kernel_kind k
+ * (default: all).  An event pair costs a few microseconds of queue time per
+ * launch, so a measurement of one kind's launches should select that kind
+ * alone. */
+tn_status tn_profile_select(uint32_t kind_mask);
 int32_t tn_profile_read(tn_kernel_profile* out, int32_t capacity);
 void tn_profile_reset(void);
 

@@ -22,8 +22,8 @@ from . import _lib
 from ._lib import (TN_FUSE_2Q, TN_OUT_AMPLITUDES, TN_OUT_STATEVECTOR, TN_PATH_GREEDY, TN_PATH_RANDOM,
                    TN_PATH_SEARCH, TN_PATH_SEQUENTIAL, TN_PREC_BF16X3, TN_PREC_C64, TNError, check, lib)
 
-__all__ = ["Network", "Path", "contract_path", "amplitudes", "expectation", "backward", "contract_pair",
-           "Expectation", "Observable", "TNError", "tn_build_network", "tn_plan_path", "tn_contract_pair",
+__all__ = ["Network", "Path", "contract_path", "amplitudes", "expectation", "backward", "contract_pair", "autotune",
+           "Expectation", "Graph", "Observable", "TNError", "tn_build_network", "tn_plan_path", "tn_contract_pair",
            "tn_contract_path", "tn_amplitudes", "tn_expectation", "tn_backward"]
 
 PRECISION = {"c64": TN_PREC_C64, "bf16x3": TN_PREC_BF16X3}
@@ -327,7 +327,7 @@ def amplitudes(net: Network, path: Path, bitstrings, params=None, precision="c64
 
 
 def expectation(nets: Sequence[Network], paths: Sequence[Path], params: Sequence, observables: Sequence[Observable],
-                batch: int = 1, precision="c64", device="cuda", workspace=None, stream=None):
+                batch: int = 1, precision="c64", device="cuda", workspace=None, stream=None, out=None):
     """<psi_c|D_c|psi_c> for each circuit c and parameter vector: float64 [n_circuits, batch]."""
     torch = _torch()
     n = len(nets)
@@ -338,7 +338,8 @@ def expectation(nets: Sequence[Network], paths: Sequence[Path], params: Sequence
     obs_arr = (_lib.tn_observable * n)(*[o.c for o in observables])
     nbytes = lib().tn_expectation_workspace_bytes(net_arr, path_arr, n, batch)
     ws = workspace if workspace is not None and workspace.numel() >= nbytes else _workspace(nbytes, device)
-    out = torch.empty(n, batch, dtype=torch.float64, device=device)
+    if out is None:
+        out = torch.empty(n, batch, dtype=torch.float64, device=device)
     tn_expectation(_stream_handle(stream), _prec(precision), net_arr, path_arr, n, pptr, batch, obs_arr, _ptr(ws),
                    ws.numel(), _ptr(out))
     return out
@@ -416,10 +417,64 @@ Expectation = _LazyExpectation()
 
 
 # ---------------------------------------------------------------------------
+# HIP graphs
+# ---------------------------------------------------------------------------
+class Graph:
+    """A recording of library calls replayed as one HIP graph launch.
+
+        g = Graph(stream)            # a torch.cuda.Stream (not the null stream)
+        with g.capture():
+            expectation(..., workspace=ws, out=out, stream=stream)
+        g.launch()                   # replays every kernel of the calls above
+
+    Buffers (params, workspace, outputs) must be allocated before the capture
+    and are reused by every launch; run the calls once before capturing so
+    the library's device-side tables exist."""
+
+    def __init__(self, stream):
+        self.stream = stream
+        self.handle = None
+
+    def capture(self):
+        import contextlib
+
+        @contextlib.contextmanager
+        def _cap():
+            if self.handle is not None:
+                raise TNError(1, "graph already captured")
+            check(lib().tn_graph_begin(ctypes.c_void_p(self.stream.cuda_stream)))
+            try:
+                yield self
+            finally:
+                h = ctypes.c_void_p()
+                check(lib().tn_graph_end(ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+                self.handle = h
+
+        return _cap()
+
+    def launch(self):
+        check(lib().tn_graph_launch(self.handle, ctypes.c_void_p(self.stream.cuda_stream)))
+
+    def __del__(self):
+        try:
+            if self.handle:
+                lib().tn_graph_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
 # kernel timing
 # ---------------------------------------------------------------------------
 def profile_enable(on: bool = True):
     check(lib().tn_profile_enable(1 if on else 0))
+
+
+def profile_select(kinds=None):
+    """Time only these kernel kinds (names from profile_read; None = all)."""
+    mask = 0xFFFFFFFF if kinds is None else sum(1 << _lib.KERNEL_KINDS.index(k) for k in kinds)
+    check(lib().tn_profile_select(mask))
 
 
 def profile_reset():

@@ -66,7 +66,8 @@ EXPORTS = [
     "tn_contract_path", "tn_amplitudes", "tn_expectation_workspace_bytes", "tn_expectation",
     "tn_backward_workspace_bytes", "tn_backward", "tn_contract_pair_workspace_bytes", "tn_contract_pair",
     "tn_last_error", "tn_version", "tn_profile_enable", "tn_profile_read", "tn_profile_reset", "tn_autotune",
-    "tn_path_gemm_config",
+    "tn_path_gemm_config", "tn_graph_begin", "tn_graph_end", "tn_graph_launch", "tn_graph_destroy",
+    "tn_profile_select",
 ]
 
 KERNEL_KINDS = ["materialize", "skinny", "permute", "gemm", "reduce", "copy", "adjoint", "interp", "sweep"]
@@ -134,10 +135,20 @@ def _declare(lib):
     lib.tn_profile_read.restype = i32
     lib.tn_profile_reset.argtypes = []
     lib.tn_profile_reset.restype = None
+    lib.tn_profile_select.argtypes = [ctypes.c_uint32]
+    lib.tn_profile_select.restype = st
     lib.tn_autotune.argtypes = [P, i32, P, P, P, i32, P, sz, i32, P]
     lib.tn_autotune.restype = st
     lib.tn_path_gemm_config.argtypes = [P, i32, i32, P, P, P, i32]
     lib.tn_path_gemm_config.restype = st
+    lib.tn_graph_begin.argtypes = [P]
+    lib.tn_graph_begin.restype = st
+    lib.tn_graph_end.argtypes = [P, ctypes.POINTER(P)]
+    lib.tn_graph_end.restype = st
+    lib.tn_graph_launch.argtypes = [P, P]
+    lib.tn_graph_launch.restype = st
+    lib.tn_graph_destroy.argtypes = [P]
+    lib.tn_graph_destroy.restype = None
     del i64, u64, dbl
 
 

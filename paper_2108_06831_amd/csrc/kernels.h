@@ -44,8 +44,9 @@ hipError_t launch_gemm(hipStream_t s, const GemmDesc& d, int tile, int split, co
 constexpr int kMaxTerms = 128;
 struct ZTerms {
   int32_t n;
-  uint64_t mask[kMaxTerms];  // address-bit masks
+  uint64_t mask[kMaxTerms];  // address-bit masks, sorted by their bits 8..11
   double coeff[kMaxTerms];
+  int32_t mu_start[17];      // terms whose bits 8..11 equal mu: [mu_start[mu], mu_start[mu + 1])
 };
 constexpr int kReduceBlocks = 512;   // blocks of the adjoint step (one partial per block and gate)
 constexpr int kExpectBlocks = 4096;  // blocks of the expectation reduction

@@ -1112,24 +1112,77 @@ __global__ __launch_bounds__(kThreads) void k_expect_partial(const float2* psi, 
   if (threadIdx.x == 0) partial[(int64_t)z * kExpectBlocks + blockIdx.x] = s;
 }
 
-__global__ void k_reduce_rows(const double* partial, int nb, int batch, double* out, int64_t out_stride) {
-  const int z = blockIdx.x * blockDim.x + threadIdx.x;
-  if (z >= batch) return;
+// one block per parameter vector; fixed summation order (deterministic)
+__global__ __launch_bounds__(kThreads) void k_reduce_rows(const double* partial, int nb, double* out,
+                                                          int64_t out_stride) {
+  __shared__ double red[kThreads / 64];
+  const int z = blockIdx.x;
   double s = 0;
-  for (int i = 0; i < nb; ++i) s += partial[(int64_t)z * kExpectBlocks + i];
-  out[(int64_t)z * out_stride] = s;
+  for (int i = threadIdx.x; i < nb; i += kThreads) s += partial[(int64_t)z * kExpectBlocks + i];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) out[(int64_t)z * out_stride] = s;
+}
+
+// D at the 16 addresses base + 256 j (j = 0..15, base with bits 8..11 clear):
+// each term's sign over the bits other than 8..11 is taken once per thread,
+// the sums per pattern mu of bits 8..11 go into w[mu], and a 16-point
+// Walsh-Hadamard transform gives D(base + 256 j) = sum_mu w[mu] (-1)^popc(j & mu).
+__device__ inline void zdiag16(uint64_t base, const ZTerms& t, double (&w)[16]) {
+#pragma unroll
+  for (int mu = 0; mu < 16; ++mu) {
+    double acc = 0;
+    for (int i = t.mu_start[mu]; i < t.mu_start[mu + 1]; ++i)
+      acc += (__popcll(base & t.mask[i]) & 1) ? -t.coeff[i] : t.coeff[i];
+    w[mu] = acc;
+  }
+#pragma unroll
+  for (int h = 1; h < 16; h <<= 1)
+#pragma unroll
+    for (int a = 0; a < 16; a += 2 * h)
+#pragma unroll
+      for (int b = a; b < a + h; ++b) {
+        const double u = w[b], v = w[b + h];
+        w[b] = u + v;
+        w[b + h] = u - v;
+      }
+}
+
+// blocks of 4096 consecutive elements: thread t takes base + t + 256 j
+__global__ __launch_bounds__(kThreads) void k_expect_partial16(const float2* psi, int64_t bs, int64_t n, ZTerms t,
+                                                               double* partial) {
+  __shared__ double red[kThreads / 64];
+  const int z = blockIdx.y;
+  const float2* p = psi + (int64_t)z * bs;
+  double acc = 0;
+  for (int64_t c = blockIdx.x; c < (n >> 12); c += gridDim.x) {
+    const int64_t base = (c << 12) | threadIdx.x;
+    double w[16];
+    zdiag16((uint64_t)base, t, w);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const float2 v = p[base + 256 * j];
+      acc += ((double)v.x * v.x + (double)v.y * v.y) * w[j];
+    }
+  }
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) partial[(int64_t)z * kExpectBlocks + blockIdx.x] = s;
 }
 
 hipError_t launch_expectation(hipStream_t s, const float2* psi, int64_t psi_bs, int64_t n_elems, const ZTerms& terms,
                               int batch, double* partial, double* out, int64_t out_stride) {
-  int64_t blocks = (n_elems + kThreads - 1) / kThreads;
-  if (blocks > kExpectBlocks) blocks = kExpectBlocks;
-  hipLaunchKernelGGL(k_expect_partial, dim3((unsigned)blocks, batch), dim3(kThreads), 0, s, psi, psi_bs, n_elems,
-                     terms, partial);
+  int64_t blocks;
+  if (n_elems >= 4096) {
+    blocks = std::min<int64_t>(n_elems >> 12, kExpectBlocks);
+    hipLaunchKernelGGL(k_expect_partial16, dim3((unsigned)blocks, batch), dim3(kThreads), 0, s, psi, psi_bs, n_elems,
+                       terms, partial);
+  } else {
+    blocks = std::min<int64_t>((n_elems + kThreads - 1) / kThreads, kExpectBlocks);
+    hipLaunchKernelGGL(k_expect_partial, dim3((unsigned)blocks, batch), dim3(kThreads), 0, s, psi, psi_bs, n_elems,
+                       terms, partial);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_reduce_rows, dim3((batch + 63) / 64), dim3(64), 0, s, partial, (int)blocks, batch, out,
-                     out_stride);
+  hipLaunchKernelGGL(k_reduce_rows, dim3(batch), dim3(kThreads), 0, s, partial, (int)blocks, out, out_stride);
   return hipGetLastError();
 }
 
@@ -1160,8 +1213,29 @@ __global__ __launch_bounds__(kThreads) void k_apply_diag_obs(const float2* psi, 
   }
 }
 
+__global__ __launch_bounds__(kThreads) void k_apply_diag_obs16(const float2* psi, int64_t psi_bs, float2* lam,
+                                                               int64_t lam_bs, int64_t n, ZTerms t) {
+  const int z = blockIdx.y;
+  for (int64_t c = blockIdx.x; c < (n >> 12); c += gridDim.x) {
+    const int64_t base = (c << 12) | threadIdx.x;
+    double w[16];
+    zdiag16((uint64_t)base, t, w);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const float2 v = psi[(int64_t)z * psi_bs + base + 256 * j];
+      lam[(int64_t)z * lam_bs + base + 256 * j] = f2((float)(w[j] * v.x), (float)(w[j] * v.y));
+    }
+  }
+}
+
 hipError_t launch_apply_diag_obs(hipStream_t s, const float2* psi, int64_t psi_bs, float2* lam, int64_t lam_bs,
                                  int64_t n_elems, const ZTerms& terms, int batch) {
+  if (n_elems >= 4096) {
+    const int64_t blocks = std::min<int64_t>(n_elems >> 12, 16384);
+    hipLaunchKernelGGL(k_apply_diag_obs16, dim3((unsigned)blocks, batch), dim3(kThreads), 0, s, psi, psi_bs, lam,
+                       lam_bs, n_elems, terms);
+    return hipGetLastError();
+  }
   int64_t blocks = (n_elems + kThreads - 1) / kThreads;
   if (blocks > 16384) blocks = 16384;
   hipLaunchKernelGGL(k_apply_diag_obs, dim3((unsigned)blocks, batch), dim3(kThreads), 0, s, psi, psi_bs, lam, lam_bs,

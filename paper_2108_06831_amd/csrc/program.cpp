@@ -14,7 +14,10 @@
 //   * otherwise: the MFMA complex matrix product on [batch][M][K] x
 //     [batch][K][N] -> [batch][M][N], permuting an operand first only when
 //     its bits are not already grouped that way.
+#include <atomic>
 #include <chrono>
+#include <cstdlib>
+#include <thread>
 #include <cmath>
 #include <map>
 #include <algorithm>
@@ -972,47 +975,98 @@ extern "C" tn_status tn_plan_path(const tn_network* net, const tn_plan_opts* opt
     p->stats.modeled_seconds = modeled_seconds(p);
   } else {
     const int trials = o.trials > 0 ? o.trials : 64;
+    // the candidates (greedy, sequential, then randomised greedy orders) are
+    // drawn up front from one generator, so the result does not depend on
+    // how the trials are spread over host threads
+    struct Trial {
+      tn_plan_opts o;
+      double alpha, temp;
+      uint64_t seed;
+    };
+    std::vector<Trial> cand;
     uint64_t rng = o.seed ^ 0x3f5a1c0de2108ull;
-    double best_t = 0;
-    int min_log2 = 1 << 20;
     for (int trial = -2; trial < trials; ++trial) {
-      tn_plan_opts oo = o;
-      double alpha = 1.0, temp = 0.0;
-      uint64_t seed = splitmix(rng);
+      Trial c{o, 1.0, 0.0, splitmix(rng)};
       if (trial == -2) {
-        oo.kind = TN_PATH_GREEDY;
+        c.o.kind = TN_PATH_GREEDY;
       } else if (trial == -1) {
-        oo.kind = TN_PATH_SEQUENTIAL;
+        c.o.kind = TN_PATH_SEQUENTIAL;
       } else {
-        oo.kind = TN_PATH_GREEDY;
-        alpha = 0.25 + 1.75 * (double)(splitmix(rng) >> 11) / 9007199254740992.0;
-        temp = (double)(splitmix(rng) >> 11) / 9007199254740992.0;
-        temp = temp * temp;
+        c.o.kind = TN_PATH_GREEDY;
+        c.alpha = 0.25 + 1.75 * (double)(splitmix(rng) >> 11) / 9007199254740992.0;
+        const double u = (double)(splitmix(rng) >> 11) / 9007199254740992.0;
+        c.temp = u * u;
       }
-      tn_path* q = new tn_path();
-      double ml = 0;
-      tn_status s = plan_order(net, oo, q->pairs, &ml, alpha, temp, seed);
-      min_log2 = std::min(min_log2, (int)ml);
-      if (s == TN_OK) {
-        q->pairs = reorder_small_first(net, q->pairs, &q->n_small, &q->small_region);
-        const std::vector<int32_t> fl = output_layout(net);
-        s = compile_program(net, q, &fl);
+      cand.push_back(c);
+    }
+    struct Best {
+      tn_path* p = nullptr;
+      double t = 0;
+      size_t idx = 0;
+      int min_log2 = 1 << 20;
+      tn_status hard = TN_OK;  // an error other than the size cap
+      std::string msg;
+    };
+    const std::vector<int32_t> fl = output_layout(net);
+    auto worker = [&](std::atomic<size_t>* next, Best* b) {
+      for (size_t i = (*next)++; i < cand.size(); i = (*next)++) {
+        const Trial& c = cand[i];
+        tn_path* q = new tn_path();
+        double ml = 0;
+        tn_status s = plan_order(net, c.o, q->pairs, &ml, c.alpha, c.temp, c.seed);
+        b->min_log2 = std::min(b->min_log2, (int)ml);
+        if (s == TN_OK) {
+          q->pairs = reorder_small_first(net, q->pairs, &q->n_small, &q->small_region);
+          s = compile_program(net, q, &fl);
+        }
+        if (s != TN_OK) {
+          delete q;
+          if (s != TN_ELIMIT && b->hard == TN_OK) {
+            b->hard = s;
+            b->msg = tn_last_error();
+          }
+          continue;
+        }
+        const double t = modeled_seconds(q);
+        q->stats.modeled_seconds = t;
+        if (!b->p || t < b->t || (t == b->t && i < b->idx)) {
+          delete b->p;
+          b->p = q;
+          b->t = t;
+          b->idx = i;
+        } else {
+          delete q;
+        }
       }
-      if (s != TN_OK) {
-        delete q;
-        if (s != TN_ELIMIT) return s;
-        continue;
-      }
-      const double t = modeled_seconds(q);
-      q->stats.modeled_seconds = t;
-      if (!p || t < best_t) {
-        delete p;
-        p = q;
-        best_t = t;
-      } else {
-        delete q;
+    };
+    int nth = (int)std::thread::hardware_concurrency();
+    if (const char* e = std::getenv("TNQ_PLAN_THREADS")) nth = std::atoi(e);
+    nth = std::max(1, std::min({nth, 16, (int)cand.size()}));
+    std::atomic<size_t> next{0};
+    std::vector<Best> bests(nth);
+    std::vector<std::thread> pool;
+    for (int k = 1; k < nth; ++k) pool.emplace_back(worker, &next, &bests[k]);
+    worker(&next, &bests[0]);
+    for (std::thread& th : pool) th.join();
+    int min_log2 = 1 << 20;
+    for (Best& b : bests) {
+      min_log2 = std::min(min_log2, b.min_log2);
+      if (b.hard != TN_OK) {
+        for (Best& x : bests) delete x.p;
+        return set_error(b.hard, b.msg);
       }
     }
+    // the lowest modelled time wins, ties go to the earliest candidate
+    size_t best_i = SIZE_MAX;
+    for (size_t k = 0; k < bests.size(); ++k) {
+      if (!bests[k].p) continue;
+      if (best_i == SIZE_MAX || bests[k].t < bests[best_i].t ||
+          (bests[k].t == bests[best_i].t && bests[k].idx < bests[best_i].idx))
+        best_i = k;
+    }
+    for (size_t k = 0; k < bests.size(); ++k)
+      if (k != best_i) delete bests[k].p;
+    if (best_i != SIZE_MAX) p = bests[best_i].p;
     if (!p) return set_error(TN_ELIMIT, "every searched order's largest intermediate (at best 2^" +
                                             std::to_string(min_log2) + ")" + cap_msg);
     clear_error();

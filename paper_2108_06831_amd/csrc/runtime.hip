@@ -41,6 +41,7 @@ struct ProfRec {
   double bytes, flops;
 };
 static bool g_prof = false;
+static uint32_t g_prof_mask = ~0u;  // kernel kinds timed while enabled
 static std::vector<ProfRec> g_recs;
 static std::vector<hipEvent_t> g_pool;
 
@@ -50,13 +51,15 @@ static hipEvent_t pool_event() {
     g_pool.pop_back();
     return e;
   }
+  // timing-only events: no system-scope fence (no cache writeback and
+  // invalidation around the timed kernels)
   hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
   return e;
 }
 
-static hipEvent_t prof_start(hipStream_t s) {
-  if (!g_prof) return nullptr;
+static hipEvent_t prof_start(hipStream_t s, int kind) {
+  if (!g_prof || !((g_prof_mask >> kind) & 1u)) return nullptr;
   hipEvent_t e = pool_event();
   if (e) (void)hipEventRecord(e, s);
   return e;
@@ -86,10 +89,15 @@ struct DevNet {
   int n_slots = 0;
 };
 
+// set between tn_graph_begin and tn_graph_end on this thread: device-side
+// tables must exist before a capture starts (their upload is not a graph node)
+static thread_local bool g_capturing = false;
+
 template <typename T>
 static hipError_t upload(T** dst, const std::vector<T>& v) {
   *dst = nullptr;
   if (v.empty()) return hipSuccess;
+  if (g_capturing) return hipErrorStreamCaptureUnsupported;
   hipError_t e = hipMalloc((void**)dst, sizeof(T) * v.size());
   if (e != hipSuccess) return e;
   return hipMemcpy(*dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice);
@@ -258,7 +266,7 @@ static tn_status run_steps(hipStream_t s, tn_path* path, const Bases& B, int bat
     float2* ip = resolve(B, ri, &ibs);
     float2* wp = resolve(B, rw, &wbs);
     if (B.pair_a) return set_error(TN_EINVAL, "internal: interpreter steps in a single pairwise contraction");
-    hipEvent_t ev = prof_start(s);
+    hipEvent_t ev = prof_start(s, TN_KERNEL_INTERP);
     HIP_TRY(launch_small_steps(s, dp->steps, dp->lists, dp->levels, (int)path->small_lists.size() - 1, ip, ibs, wp,
                                wbs, batch, precision));
     double fl = 0, by = 0;
@@ -280,7 +288,7 @@ static tn_status run_steps(hipStream_t s, tn_path* path, const Bases& B, int bat
       float2* WSp = resolve(B, rw, &WS_bs);
       for (int k = 0; k < ch.n_passes; ++k) {
         const SweepPass& ps = path->passes[ch.first_pass + k];
-        hipEvent_t ev = prof_start(s);
+        hipEvent_t ev = prof_start(s, TN_KERNEL_SWEEP);
         HIP_TRY(launch_sweep_pass(s, ps, ch.bits, dp->sweep_gates, dp->segments, k == 0 ? ip : op,
                                   k == 0 ? ibs : obs, op, obs, INp, IN_bs, WSp, WS_bs, batch, precision));
         double fl = 0;
@@ -297,7 +305,7 @@ static tn_status run_steps(hipStream_t s, tn_path* path, const Bases& B, int bat
       int64_t ibs, obs;
       float2* ip = resolve(B, pd.in, &ibs);
       float2* op = resolve(B, pd.out, &obs);
-      hipEvent_t ev = prof_start(s);
+      hipEvent_t ev = prof_start(s, TN_KERNEL_PERMUTE);
       HIP_TRY(launch_permute(s, pd, ip, ibs, op, obs, batch));
       prof_stop(s, ev, TN_KERNEL_PERMUTE, 16.0 * (double)((int64_t)1 << pd.bits) * batch, 0.0);
     }
@@ -310,7 +318,7 @@ static tn_status run_steps(hipStream_t s, tn_path* path, const Bases& B, int bat
       const double te = (double)((int64_t)1 << d.t_bits);
       const double ce = d.c_mode ? (double)((int64_t)1 << (d.t_bits - d.nk + d.nm)) : te;
       const double ge = (double)((int64_t)1 << (d.nb + d.nm + d.nk));
-      hipEvent_t ev = prof_start(s);
+      hipEvent_t ev = prof_start(s, TN_KERNEL_SKINNY);
       HIP_TRY(launch_skinny(s, P.sk, g, gbs, t, tbs, c, cbs, batch, precision));
       prof_stop(s, ev, TN_KERNEL_SKINNY, 8.0 * batch * (ge + te + ce), P.flops * batch);
     } else {
@@ -326,7 +334,7 @@ static tn_status run_steps(hipStream_t s, tn_path* path, const Bases& B, int bat
         c = B.final_out;  // the last product writes the caller's output directly
         cbs = B.final_out_bs;
       }
-      hipEvent_t ev = prof_start(s);
+      hipEvent_t ev = prof_start(s, TN_KERNEL_GEMM);
       HIP_TRY(launch_gemm(s, g, g.tile[precision], g.split[precision], a, abs_, b, bbs, c, cbs, tmp, tbs, batch,
                           precision));
       prof_stop(s, ev, TN_KERNEL_GEMM, bytes, P.flops * batch);
@@ -337,7 +345,7 @@ static tn_status run_steps(hipStream_t s, tn_path* path, const Bases& B, int bat
 
 static tn_status materialize(hipStream_t s, tn_network* net, DevNet* d, const double* params, int batch,
                              const uint64_t* bits, int64_t count, float2* in) {
-  hipEvent_t ev = prof_start(s);
+  hipEvent_t ev = prof_start(s, TN_KERNEL_MATERIALIZE);
   HIP_TRY(launch_materialize(s, d->tensors, (int)net->tensors.size(), d->recipes, d->ops, d->mats, params,
                              net->n_params, batch, in, net->input_elems));
   if (net->output_kind == TN_OUT_AMPLITUDES) {
@@ -363,7 +371,7 @@ static tn_status finish_to(hipStream_t s, const Bases& B, const tn_path* path, c
   float2* f = resolve(B, path->final_ref, &fbs);
   const std::vector<int32_t>& from = path->final_bits;
   if (from == to) {
-    hipEvent_t ev = prof_start(s);
+    hipEvent_t ev = prof_start(s, TN_KERNEL_COPY);
     HIP_TRY(launch_copy(s, f, fbs, dst, dst_bs, n_copy, batch));
     prof_stop(s, ev, TN_KERNEL_COPY, 16.0 * (double)n_copy * batch, 0.0);
     return TN_OK;
@@ -372,7 +380,7 @@ static tn_status finish_to(hipStream_t s, const Bases& B, const tn_path* path, c
   pd.bits = (int32_t)from.size();
   for (size_t i = 0; i < from.size(); ++i) pd.dst[from.size() - 1 - i] = pos_in(to, from[i]);
   if (n_copy == path->final_elems) {
-    hipEvent_t ev = prof_start(s);
+    hipEvent_t ev = prof_start(s, TN_KERNEL_PERMUTE);
     HIP_TRY(launch_permute(s, pd, f, fbs, dst, dst_bs, batch));
     prof_stop(s, ev, TN_KERNEL_PERMUTE, 16.0 * (double)n_copy * batch, 0.0);
   } else {
@@ -405,6 +413,26 @@ static tn_status make_terms(const tn_network* net, const tn_path* path, const tn
     t->mask[i] = m;
     t->coeff[i] = obs->coeff[i];
   }
+  // group the terms by their address bits 8..11 (the reduction kernels sum
+  // each group once per thread and spread it over 16 elements)
+  std::vector<int> order(t->n);
+  for (int i = 0; i < t->n; ++i) order[i] = i;
+  auto mu = [&](int i) { return (int)((t->mask[i] >> 8) & 15); };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return mu(a) < mu(b); });
+  uint64_t mk[kMaxTerms];
+  double cf[kMaxTerms];
+  for (int i = 0; i < t->n; ++i) {
+    mk[i] = t->mask[order[i]];
+    cf[i] = t->coeff[order[i]];
+  }
+  for (int i = 0; i < t->n; ++i) {
+    t->mask[i] = mk[i];
+    t->coeff[i] = cf[i];
+  }
+  for (int m = 0, i = 0; m <= 16; ++m) {
+    while (i < t->n && mu(i) < m) ++i;
+    t->mu_start[m] = i;
+  }
   return TN_OK;
 }
 
@@ -417,6 +445,12 @@ extern "C" const char* tn_last_error(void) { return g_err.c_str(); }
 extern "C" tn_status tn_profile_enable(int32_t on) {
   clear_error();
   g_prof = on != 0;
+  return TN_OK;
+}
+
+extern "C" tn_status tn_profile_select(uint32_t kind_mask) {
+  clear_error();
+  g_prof_mask = kind_mask;
   return TN_OK;
 }
 
@@ -585,7 +619,7 @@ extern "C" tn_status tn_expectation(void* stream, int32_t precision, tn_network*
     if ((st = run_steps(s, path, B, batch, precision)) != TN_OK) return st;
     int64_t fbs;
     float2* f = resolve(B, path->final_ref, &fbs);
-    hipEvent_t ev = prof_start(s);
+    hipEvent_t ev = prof_start(s, TN_KERNEL_REDUCE);
     HIP_TRY(launch_expectation(s, f, fbs, path->final_elems, terms, batch, (double*)(w + L.aux_off),
                                out_dev + (int64_t)c * batch, 1));
     prof_stop(s, ev, TN_KERNEL_REDUCE, 8.0 * (double)path->final_elems * batch, 0.0);
@@ -678,7 +712,7 @@ extern "C" tn_status tn_backward(void* stream, int32_t precision, tn_network* ne
         const double per = gd.diag ? 12.0 : 16.0 * (double)(1 << gd.n);  // flops per element and state
         fl += 2.0 * per * (double)n + (gd.red >= 0 ? 8.0 * (double)n : 0.0);
       }
-      hipEvent_t ev = prof_start(s);
+      hipEvent_t ev = prof_start(s, TN_KERNEL_ADJOINT);
       HIP_TRY(launch_adjoint_pass(s, ps, bits, dp->adj_gates, dp->adj_segments, umats,
                                   (int64_t)net->sweep.size() * 16, psi, pbs, lam, n, batch, parts, pstride));
       prof_stop(s, ev, TN_KERNEL_ADJOINT, 32.0 * (double)n * batch, fl * batch);
@@ -694,7 +728,7 @@ extern "C" tn_status tn_backward(void* stream, int32_t precision, tn_network* ne
     a.slot = d->slot_of_gate[gi];
     if (a.pos[0] < 0 || a.pos[1] < 0 || (1ll << a.pos[0]) >= n || (1ll << a.pos[1]) >= n)
       return set_error(TN_EINVAL, "internal: qubit leg missing from the final tensor");
-    hipEvent_t ev = prof_start(s);
+    hipEvent_t ev = prof_start(s, TN_KERNEL_ADJOINT);
     HIP_TRY(launch_adjoint_step(s, a, umats + (int64_t)gi * 16, (int64_t)net->sweep.size() * 16, psi, pbs, lam, n,
                                 n, batch, parts, pstride));
     prof_stop(s, ev, TN_KERNEL_ADJOINT, 32.0 * (double)n * batch, 64.0 * (double)n * batch * (g.nq == 2 ? 4 : 2));
@@ -703,6 +737,62 @@ extern "C" tn_status tn_backward(void* stream, int32_t precision, tn_network* ne
     HIP_TRY(launch_gradient_reduce(s, parts, pstride, d->n_slots, d->slot_param, net->n_params, grad_out_dev, batch,
                                    grad_dev));
   return TN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// HIP graphs of whole calls
+// ---------------------------------------------------------------------------
+struct tn_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int device = -1;
+};
+
+extern "C" tn_status tn_graph_begin(void* stream) {
+  clear_error();
+  if (!stream) return set_error(TN_EINVAL, "capture needs a stream other than the null stream");
+  if (g_prof) return set_error(TN_EINVAL, "disable kernel timing (tn_profile_enable(0)) before capturing");
+  if (g_capturing) return set_error(TN_EINVAL, "a capture is already open on this thread");
+  HIP_TRY(hipStreamBeginCapture((hipStream_t)stream, hipStreamCaptureModeThreadLocal));
+  g_capturing = true;
+  return TN_OK;
+}
+
+extern "C" tn_status tn_graph_end(void* stream, tn_graph** out) {
+  clear_error();
+  if (!g_capturing) return set_error(TN_EINVAL, "no capture open on this thread");
+  g_capturing = false;
+  if (!stream || !out) {
+    hipGraph_t g = nullptr;
+    if (stream && hipStreamEndCapture((hipStream_t)stream, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
+    return set_error(TN_EINVAL, "NULL stream or output handle");
+  }
+  *out = nullptr;
+  tn_graph* G = new tn_graph();
+  hipError_t e = hipStreamEndCapture((hipStream_t)stream, &G->graph);
+  if (e == hipSuccess) e = hipGetDevice(&G->device);
+  if (e == hipSuccess) e = hipGraphInstantiate(&G->exec, G->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    if (G->graph) (void)hipGraphDestroy(G->graph);
+    delete G;
+    return set_error(TN_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+  }
+  *out = G;
+  return TN_OK;
+}
+
+extern "C" tn_status tn_graph_launch(const tn_graph* g, void* stream) {
+  clear_error();
+  if (!g || !g->exec) return set_error(TN_EINVAL, "NULL graph");
+  HIP_TRY(hipGraphLaunch(g->exec, (hipStream_t)stream));
+  return TN_OK;
+}
+
+extern "C" void tn_graph_destroy(tn_graph* g) {
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
 }
 
 // ---------------------------------------------------------------------------
@@ -765,8 +855,8 @@ extern "C" tn_status tn_autotune(void* stream, int32_t precision, tn_network* ne
                              net->n_params, batch, B.in, net->input_elems));
   if ((st = run_steps(s, path, B, batch, precision)) != TN_OK) return st;
   hipEvent_t e0, e1;
-  HIP_TRY(hipEventCreate(&e0));
-  HIP_TRY(hipEventCreate(&e1));
+  HIP_TRY(hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));
+  HIP_TRY(hipEventCreateWithFlags(&e1, hipEventDisableSystemFence));
   tn_tune_report rep{0, 0, 0.0, 0.0};
   tn_status result = TN_OK;
   for (size_t si = 0; si < path->steps.size() && result == TN_OK; ++si) {

@@ -283,3 +283,42 @@ def test_adjoint_passes_every_gate_kind(n, seed):
         e = np.linalg.norm(grad[b] - g) / np.linalg.norm(g)
         print(f"  vector {b}: value err {scalar_err(value[b], want_e):.2e}, grad rel err {e:.2e}", flush=True)
         assert e < C64_TOL
+
+
+def test_expectation_graph_replays():
+    """Batched QAOA expectations captured in one HIP graph: every replay, with
+    eager library work and synchronisations in between, equals the eager call;
+    parameters updated in place between replays are picked up."""
+    import torch
+    from paper_2108_06831_amd import Graph, Network, Observable, expectation
+    inst = [it for it in workloads.config3() if it.circuit.n_qubits in (16, 18)][:6]
+    nets = [Network.from_circuit(it.circuit) for it in inst]
+    paths = [nt.plan("sequential") for nt in nets]
+    obs = [Observable(*workloads.maxcut_observable(it.circuit.n_qubits, it.edges)) for it in inst]
+    stream = torch.cuda.Stream()
+    params = [torch.as_tensor(it.params, device="cuda").reshape(1, -1).contiguous() for it in inst]
+    out = torch.empty(len(inst), 1, dtype=torch.float64, device="cuda")
+    with torch.cuda.stream(stream):
+        eager = expectation(nets, paths, params, obs, stream=stream).clone()
+        ws = torch.empty(1 << 26, dtype=torch.uint8, device="cuda")
+    stream.synchronize()
+    g = Graph(stream)
+    with g.capture():
+        expectation(nets, paths, params, obs, workspace=ws, out=out, stream=stream)
+    for rep in range(3):
+        out.fill_(0.0)
+        torch.cuda.synchronize()
+        g.launch()
+        stream.synchronize()
+        assert torch.equal(out, eager), rep
+        # eager library work between replays
+        other = expectation(nets[:2], paths[:2], params[:2], obs[:2])
+        torch.cuda.synchronize()
+        assert torch.equal(other, eager[:2])
+    for p in params:
+        p[0, 4:] = 0.0  # beta = 0: <C> = |E| / 2
+    torch.cuda.synchronize()
+    g.launch()
+    stream.synchronize()
+    for i, it in enumerate(inst):
+        assert scalar_err(out[i, 0].item(), len(it.edges) / 2) < C64_TOL
