@@ -304,7 +304,8 @@ void tn_graph_destroy(tn_graph* graph);
  * Runs the path's steps once on `stream` (gate tensors from params_dev, for
  * `batch` parameter vectors; amplitude projectors are left zero), then for
  * every matrix-product step times each candidate launch shape -- an MFMA tile
- * of 128x64, 128x32, 64x64 or 64x32 complex, K cut into 1, 2, 4 or 8 ranges
+ * of 128x64, 128x32, 64x64 or 64x32 complex (4M form) or, for TN_PREC_C64,
+ * 128x64 or 64x64 in the 3M form, K cut into 1, 2, 4 or 8 ranges
  * where the step's result is small, the one-output-per-thread vector kernel
  * where K <= 1024, each for C = A B and for C = B^T A^T -- over `reps` launches (hipEvents on `stream`) and
  * keeps the fastest in the path for `precision`.  Synchronises the stream.
@@ -324,8 +325,9 @@ tn_status tn_autotune(void* stream, int32_t precision, tn_network* net, tn_path*
 /* Launch shape of matrix-product step `step` for `precision`: read (set == 0)
  * into *tile / *split / *transposed, or replace it (set != 0) with the values
  * given, e.g. to restore shapes tuned earlier.  tile: 0..3 = MFMA tiles
- * 128x64, 128x32, 64x64, 64x32 complex; 4 = vector kernel (K <= 1024 only,
- * split 1).  split: 1, 2, 4 or 8, dividing K, at most the step's reserved
+ * 128x64, 128x32, 64x64, 64x32 complex in the real-embedding (4M) form;
+ * 4 = vector kernel (K <= 1024 only, split 1); 5, 6 = MFMA tiles 128x64,
+ * 64x64 in the three-product (3M) form (TN_PREC_C64 only).  split: 1, 2, 4 or 8, dividing K, at most the step's reserved
  * maximum.  transposed: 0 computes C = A B, 1 computes C = B^T A^T (operands
  * trade places; same result layout).  TN_EINVAL for a step that is not a
  * matrix product or an invalid shape. */

@@ -179,7 +179,7 @@ struct GemmDesc {
   int8_t a_b[kGemmMaxBits], a_m[kGemmMaxBits], a_k[kGemmMaxBits];
   int8_t b_b[kGemmMaxBits], b_k[kGemmMaxBits], b_n[kGemmMaxBits];
   int8_t c_b[kGemmMaxBits], c_m[kGemmMaxBits], c_n[kGemmMaxBits];
-  // launch shape per precision (index TN_PREC_*): tile[p] < kGemmVector is an
+  // launch shape per precision (index TN_PREC_*): tile[p] != kGemmVector is an
   // MFMA tile of kGemmTileM x kGemmTileN complex, kGemmVector the per-output
   // vector kernel; split[p] > 1 cuts K into ranges whose partial products land
   // in `tmp` and are summed.  `tmp` holds max_split copies of C.
@@ -187,9 +187,12 @@ struct GemmDesc {
   int32_t max_split;
   BufRef tmp;
 };
+// tiles 0-3: real-embedding (4M) MFMA tiles; 4: vector kernel; 5-6: 3M MFMA
+// tiles (FP32 only)
 constexpr int kGemmVector = 4;
-constexpr int kGemmTileM[4] = {128, 128, 64, 64};
-constexpr int kGemmTileN[4] = {64, 32, 64, 32};
+constexpr int kGemmTiles = 7;
+constexpr int kGemmTileM[kGemmTiles] = {128, 128, 64, 64, 1, 128, 64};
+constexpr int kGemmTileN[kGemmTiles] = {64, 32, 64, 32, 1, 64, 64};
 constexpr int kGemmMaxSplit = 8;
 constexpr int kGemmBK = 16;      // complex k per staged K tile of the MFMA kernels
 constexpr int kElemMaxK = 1024;  // longest K of the per-output kernel

@@ -972,6 +972,139 @@ __global__ __launch_bounds__(kThreads) void k_gemm(GemmArgs g) {
       }
 }
 
+// 3M form on the FP32 matrix cores: with A = Ar + i Ai and B = Br + i Bi,
+//   Re C = Ar Br - Ai Bi,   Im C = (Ar + Ai)(Br + Bi) - Ar Br - Ai Bi,
+// three real products instead of the four of the real embedding.  Operands
+// are staged as real and imaginary planes; one v_mfma_f32_32x32x2f32 takes
+// two complex k (lanes 0-31 the first, 32-63 the second) and a 32 x 32
+// complex tile keeps three accumulators (P1 = Ar Br, P2 = Ai Bi,
+// P3 = (Ar + Ai)(Br + Bi)).  Four waves in a 2 x 2 arrangement, each owning
+// TM tiles of 32 x 32 complex: the block computes (64 TM) x 64.
+template <int AK, int BNF, int TM, int BK>
+__global__ __launch_bounds__(kThreads) void k_gemm3m(GemmArgs g) {
+  constexpr int BM = 64 * TM, BN = 64;
+  constexpr int kPA = (BM * BK) / kThreads, kPB = (BN * BK) / kThreads;
+  constexpr int kLogBK = BK == 32 ? 5 : 4;
+  __shared__ float Ar[BK][BM + 1], Ai[BK][BM + 1], Br[BK][BN + 1], Bi[BK][BN + 1];
+  __shared__ int64_t TAm[BM], TCm[BM], TBn[BN], TCn[BN], TAk[BK], TBk[BK];
+  int64_t bid = blockIdx.x;
+  const int64_t tn = bid % g.tiles_n;
+  bid /= g.tiles_n;
+  const int64_t tm = bid % g.tiles_m;
+  bid /= g.tiles_m;
+  const int64_t ks = bid % g.split;
+  bid /= g.split;
+  const int64_t gb = bid % g.batch;
+  const int64_t z = bid / g.batch;
+  const float2* A = g.A + z * g.a_bs;
+  const float2* B = g.B + z * g.b_bs;
+  float2* C = g.C + z * g.c_bs + ks * g.c_elems;
+  const int64_t m0 = tm * BM, n0 = tn * BN;
+  const int64_t kchunk = g.K / g.split;
+  const int64_t kbeg = ks * kchunk, kend = kbeg + kchunk;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w >> 1, wn = w & 1;
+  const int64_t base_a = deposit(gb, g.a_b, g.nbb) | deposit(m0, g.a_m, g.nbm);
+  const int64_t base_b = deposit(gb, g.b_b, g.nbb) | deposit(n0, g.b_n, g.nbn);
+  const int64_t base_c = deposit(gb, g.c_b, g.nbb) | deposit(m0, g.c_m, g.nbm) | deposit(n0, g.c_n, g.nbn);
+  constexpr int kLogBM = 6 + (TM == 2);
+  if (tid < BM) {
+    const int nb = min(g.nbm, kLogBM);
+    TAm[tid] = deposit(tid, g.a_m, nb);
+    TCm[tid] = deposit(tid, g.c_m, nb);
+  }
+  if (tid < BN) {
+    const int nb = min(g.nbn, 6);
+    TBn[tid] = deposit(tid, g.b_n, nb);
+    TCn[tid] = deposit(tid, g.c_n, nb);
+  }
+  if (tid < BK) {
+    const int nb = min(g.nbk, kLogBK);
+    TAk[tid] = deposit(tid, g.a_k, nb);
+    TBk[tid] = deposit(tid, g.b_k, nb);
+  }
+  floatx16 p1[TM], p2[TM], p3[TM];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) p1[i][v] = p2[i][v] = p3[i][v] = 0.f;
+  __syncthreads();
+
+  auto a_elem = [&](int e, int& mm, int& kk) {
+    const int idx = tid + e * kThreads;
+    if (AK) { mm = idx / BK; kk = idx % BK; } else { mm = idx % BM; kk = idx / BM; }
+  };
+  auto b_elem = [&](int e, int& nn, int& kk) {
+    const int idx = tid + e * kThreads;
+    if (BNF) { nn = idx % BN; kk = idx / BN; } else { nn = idx / BK; kk = idx % BK; }
+  };
+  float2 ra[kPA], rb[kPB];
+  auto fetch = [&](int64_t k0) {
+    const int64_t ka = deposit(k0, g.a_k, g.nbk), kb = deposit(k0, g.b_k, g.nbk);
+#pragma unroll
+    for (int e = 0; e < kPA; ++e) {
+      int mm, kk;
+      a_elem(e, mm, kk);
+      ra[e] = (m0 + mm < g.M && k0 + kk < kend) ? A[base_a | TAm[mm] | ka | TAk[kk]] : f2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int e = 0; e < kPB; ++e) {
+      int nn, kk;
+      b_elem(e, nn, kk);
+      rb[e] = (n0 + nn < g.N && k0 + kk < kend) ? B[base_b | TBn[nn] | kb | TBk[kk]] : f2(0.f, 0.f);
+    }
+  };
+  auto stage = [&]() {
+#pragma unroll
+    for (int e = 0; e < kPA; ++e) {
+      int mm, kk;
+      a_elem(e, mm, kk);
+      Ar[kk][mm] = ra[e].x;
+      Ai[kk][mm] = ra[e].y;
+    }
+#pragma unroll
+    for (int e = 0; e < kPB; ++e) {
+      int nn, kk;
+      b_elem(e, nn, kk);
+      Br[kk][nn] = rb[e].x;
+      Bi[kk][nn] = rb[e].y;
+    }
+  };
+  const int h = lane >> 5, r32 = lane & 31;
+  fetch(kbeg);
+  for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
+    stage();
+    __syncthreads();
+    if (k0 + BK < kend) fetch(k0 + BK);
+#pragma unroll 2
+    for (int kk = 0; kk < BK; kk += 2) {
+      const int col = wn * 32 + r32;
+      const float br = Br[kk + h][col], bi = Bi[kk + h][col];
+      const float bs = br + bi;
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        const int row = wm * 32 * TM + i * 32 + r32;
+        const float ar = Ar[kk + h][row], ai = Ai[kk + h][row];
+        p1[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, br, p1[i], 0, 0, 0);
+        p2[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, bi, p2[i], 0, 0, 0);
+        p3[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar + ai, bs, p3[i], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int rl = wm * 32 * TM + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+      const int cl = wn * 32 + r32;
+      if (m0 + rl < g.M && n0 + cl < g.N) {
+        const float a = p1[i][v], b = p2[i][v];
+        C[base_c | TCm[rl] | TCn[cl]] = f2(a - b, p3[i][v] - a - b);
+      }
+    }
+}
+
 // Products too narrow for the matrix-core tiles (M < 64 or N < 32, e.g. a
 // 4096-way batch of 2x2 outer products): one thread per output element, the
 // same deposit-map addressing, K loop on the vector ALUs.
@@ -1024,20 +1157,31 @@ static void* gemm_fn(int ak, int bnf) {
   return (void*)k_gemm<0, 0, TM, TN, F>;
 }
 
+template <int TM, int BK>
+static void* gemm3m_fn(int ak, int bnf) {
+  if (ak && bnf) return (void*)k_gemm3m<1, 1, TM, BK>;
+  if (ak) return (void*)k_gemm3m<1, 0, TM, BK>;
+  if (bnf) return (void*)k_gemm3m<0, 1, TM, BK>;
+  return (void*)k_gemm3m<0, 0, TM, BK>;
+}
+
 template <int F>
 static void* gemm_fn_tile(int tile, int ak, int bnf) {
   switch (tile) {
     case 0: return gemm_fn<2, 2, F>(ak, bnf);
     case 1: return gemm_fn<2, 1, F>(ak, bnf);
     case 2: return gemm_fn<1, 2, F>(ak, bnf);
-    default: return gemm_fn<1, 1, F>(ak, bnf);
+    case 3: return gemm_fn<1, 1, F>(ak, bnf);
+    case 5: return gemm3m_fn<2, 16>(ak, bnf);
+    default: return gemm3m_fn<1, 16>(ak, bnf);
   }
 }
 
 hipError_t launch_gemm(hipStream_t s, const GemmDesc& d, int tile, int split, const float2* a, int64_t a_bs,
                        const float2* b, int64_t b_bs, float2* c, int64_t c_bs, float2* tmp, int64_t tmp_bs, int batch,
                        int precision) {
-  if (tile < 0 || tile > kGemmVector) return hipErrorInvalidValue;
+  if (tile < 0 || tile >= kGemmTiles) return hipErrorInvalidValue;
+  if (tile > kGemmVector && precision != TN_PREC_C64) return hipErrorInvalidValue;  // 3M: FP32 only
   GemmArgs g;
   g.A = a; g.B = b;
   g.batch = d.batch; g.M = d.M; g.N = d.N; g.K = d.K;

@@ -592,6 +592,8 @@ tn_status compile_program(const tn_network* net, tn_path* path, const std::vecto
         gemm_default_launch(g, &tile, &split);
         g.tile[0] = g.tile[1] = tile;
         g.split[0] = g.split[1] = split;
+        // FP32: the three-product form where its 64-column tiles fit
+        if ((tile == 0 || tile == 2) && g.N >= 64) g.tile[TN_PREC_C64] = tile == 0 ? 5 : 6;
         // room for the autotuner to try K splits of products with a small result
         g.max_split = split;
         if (tile != kGemmVector && C.elems * kGemmMaxSplit <= ((int64_t)1 << 22) && g.K >= 64)
@@ -933,7 +935,9 @@ double modeled_seconds(const tn_path* path) {
       }
       const double tm = kGemmTileM[tl], tn = kGemmTileN[tl];
       const double tiles = std::ceil(g.M / tm) * std::ceil(g.N / tn) * (double)g.batch * g.split[0];
-      const double eff = std::min(1.0, g.M / tm) * std::min(1.0, g.N / tn) * std::min(1.0, g.K / 32.0) *
+      // the 3M tiles do three real products where the real embedding does four
+      const double form = tl > kGemmVector ? 4.0 / 3.0 : 1.0;
+      const double eff = form * std::min(1.0, g.M / tm) * std::min(1.0, g.N / tn) * std::min(1.0, g.K / 32.0) *
                          std::min(1.0, tiles / 256.0) * (tm * tn >= 8192 ? 1.0 : 0.8);
       t += std::max(P.flops / (kMfma * std::max(eff, 1e-3)), bytes / kHbm) + (g.split[0] > 1 ? kLaunch : 0.0);
     }

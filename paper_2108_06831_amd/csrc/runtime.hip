@@ -798,8 +798,9 @@ extern "C" void tn_graph_destroy(tn_graph* g) {
 // ---------------------------------------------------------------------------
 // launch-shape autotuner
 // ---------------------------------------------------------------------------
-static bool gemm_shape_ok(const GemmDesc& g, int tile, int split) {
-  if (tile < 0 || tile > kGemmVector) return false;
+static bool gemm_shape_ok(const GemmDesc& g, int tile, int split, int precision) {
+  if (tile < 0 || tile >= kGemmTiles) return false;
+  if (tile > kGemmVector && precision != TN_PREC_C64) return false;  // 3M tiles: FP32 only
   if (split != 1 && split != 2 && split != 4 && split != 8) return false;
   if (tile == kGemmVector) return split == 1 && g.K <= kElemMaxK;
   return split <= std::max(g.max_split, 1) && g.K % split == 0;
@@ -823,7 +824,8 @@ extern "C" tn_status tn_path_gemm_config(tn_path* path, int32_t step, int32_t pr
   }
   if (*transposed != 0 && *transposed != 1) return set_error(TN_EINVAL, "transposed must be 0 or 1");
   GemmDesc& g = P.gm[*transposed];
-  if (!gemm_shape_ok(g, *tile, *split)) return set_error(TN_EINVAL, "launch shape not valid for this step");
+  if (!gemm_shape_ok(g, *tile, *split, precision))
+    return set_error(TN_EINVAL, "launch shape not valid for this step");
   g.tile[precision] = *tile;
   g.split[precision] = *split;
   P.orient[precision] = *transposed;
@@ -890,10 +892,10 @@ extern "C" tn_status tn_autotune(void* stream, int32_t precision, tn_network* ne
     rep.seconds_before += best;
     int bo = o0, bt = t0, bs = s0;
     for (int o = 0; o < 2 && result == TN_OK; ++o)
-      for (int tile = 0; tile <= kGemmVector && result == TN_OK; ++tile)
+      for (int tile = 0; tile < kGemmTiles && result == TN_OK; ++tile)
         for (int split = 1; split <= kGemmMaxSplit; split *= 2) {
           const GemmDesc& g = P.gm[o];
-          if ((o == o0 && tile == t0 && split == s0) || !gemm_shape_ok(g, tile, split)) continue;
+          if ((o == o0 && tile == t0 && split == s0) || !gemm_shape_ok(g, tile, split, precision)) continue;
           if (tile != kGemmVector && split > 1 && g.K / split < kGemmBK) continue;
           double sec = 0;
           e = time_shape(g, tile, split, &sec);

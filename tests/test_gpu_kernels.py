@@ -145,7 +145,7 @@ def test_every_gemm_launch_shape(precision):
     tried = 0
     for s, (t0, s0, o0) in shapes.items():
         for tr in (0, 1):
-            for tile in range(5):
+            for tile in range(7):
                 for split in (1, 2, 4, 8):
                     try:
                         path.set_gemm_config(s, tile, split, tr, precision)

@@ -257,11 +257,13 @@ def test_gemm_launch_shape_get_set():
     assert shapes
     for s, (tile, split, tr) in shapes.items():
         b, m, n, k = path.step(s)["bmnk"]
-        assert 0 <= tile <= 4 and split in (1, 2, 4, 8) and k % split == 0 and tr == 0
+        assert 0 <= tile <= 6 and split in (1, 2, 4, 8) and k % split == 0 and tr == 0
         if tile == 4:
             assert k <= 1024 and split == 1
         with pytest.raises(TNError):
-            path.set_gemm_config(s, 5, 1)
+            path.set_gemm_config(s, 7, 1)
+        with pytest.raises(TNError):
+            path.set_gemm_config(s, 5, 1, 0, "bf16x3")  # the 3M tiles are FP32 only
         with pytest.raises(TNError):
             path.set_gemm_config(s, 0, 3)
         with pytest.raises(TNError):
