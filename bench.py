@@ -34,6 +34,7 @@ METRIC = "TN contraction TFLOP/s (% MFMA peak), amplitudes/s, grads/s at ≤1e-5
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_BF16_MFMA_TFLOPS = 2500.0
+PEAK_FP32_VECTOR_TFLOPS = 157.3  # 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2 (packed) x 2.4 GHz
 
 
 def relerr(got, want):
@@ -383,13 +384,13 @@ def main():
     torch.cuda.synchronize()
     tnq.profile_enable(False)
     breakdown = tnq.profile_read()
-    dominant = max(breakdown.items(), key=lambda kv: kv[1]["seconds"])[0]
+    dominant = max(((k, v) for k, v in breakdown.items() if k != "gemm_large"), key=lambda kv: kv[1]["seconds"])[0]
     print(f"[bench] config {args.config}: warmup done ({args.warmup} steps), dominant kernel {dominant}, "
           f"timing {args.steps} steps", file=sys.stderr, flush=True)
 
     # timed region: HIP events around the dominant kernel's launches only (an
     # event pair costs queue time; timing every launch would inflate the step)
-    tnq.profile_select([dominant])
+    tnq.profile_select([dominant, "gemm_large"] if dominant == "gemm" else [dominant])
     tnq.profile_reset()
     tnq.profile_enable(True)
     torch.cuda.synchronize()
@@ -415,6 +416,12 @@ def main():
         achieved = rec["flops"] / rec["seconds"] / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                 "traffic": traffic}
+    elif kind in ("sweep", "adjoint"):
+        # fused gate passes: every gate on every element in registers, bound by the vector ALUs
+        achieved = rec["flops"] / rec["seconds"] / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": traffic,
+                "hbm_GBs": rec["bytes"] / rec["seconds"] / 1e9}
     else:
         achieved = rec["bytes"] / rec["seconds"] / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -424,6 +431,14 @@ def main():
                  "avg_launch_us": rec["seconds"] / rec["launches"] * 1e6,
                  "timing": "HIP events over the timed region" if prof_steps == args.steps
                  else "HIP events over one eager pass (graph replays carry no events)"})
+    if "gemm_large" in prof:
+        # products with >= 1e9 flops and >= 40 flop/B, where the matrix cores should be the bound
+        lg = prof["gemm_large"]
+        peak = PEAK_FP32_MFMA_TFLOPS if args.precision == "c64" else PEAK_BF16_MFMA_TFLOPS / 3
+        ach = lg["flops"] / lg["seconds"] / 1e12
+        roof["large_products"] = {"launches_per_step": lg["launches"] / prof_steps,
+                                  "ms_per_step": lg["seconds"] * 1e3 / prof_steps, "achieved": ach, "peak": peak,
+                                  "unit": "TFLOP/s", "frac": ach / peak}
     # per-kind breakdown from the fully profiled pass
     kernels = {k: {"launches_per_step": v["launches"], "ms_per_step": v["seconds"] * 1e3,
                    "GB/s": v["bytes"] / max(v["seconds"], 1e-30) / 1e9,

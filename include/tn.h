@@ -347,7 +347,9 @@ tn_status tn_path_gemm_config(tn_path* path, int32_t step, int32_t precision, in
 typedef enum {
   TN_KERNEL_MATERIALIZE = 0, TN_KERNEL_SKINNY = 1, TN_KERNEL_PERMUTE = 2, TN_KERNEL_GEMM = 3,
   TN_KERNEL_REDUCE = 4, TN_KERNEL_COPY = 5, TN_KERNEL_ADJOINT = 6, TN_KERNEL_INTERP = 7, TN_KERNEL_SWEEP = 8,
-  TN_KERNEL_KINDS = 9
+  TN_KERNEL_GEMM_LARGE = 9, /* the subset of TN_KERNEL_GEMM launches with >= 1e9 flops and >= 40 flops per
+                                algorithmic byte, counted again under this kind (same events) */
+  TN_KERNEL_KINDS = 10
 } tn_kernel_kind;
 typedef struct {
   int32_t kind;       /* tn_kernel_kind */

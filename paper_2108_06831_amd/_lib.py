@@ -70,7 +70,8 @@ EXPORTS = [
     "tn_profile_select",
 ]
 
-KERNEL_KINDS = ["materialize", "skinny", "permute", "gemm", "reduce", "copy", "adjoint", "interp", "sweep"]
+KERNEL_KINDS = ["materialize", "skinny", "permute", "gemm", "reduce", "copy", "adjoint", "interp", "sweep",
+                "gemm_large"]
 
 
 class tn_tune_report(ctypes.Structure):

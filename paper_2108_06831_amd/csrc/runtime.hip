@@ -39,6 +39,7 @@ struct ProfRec {
   int kind;
   hipEvent_t a, b;
   double bytes, flops;
+  bool owner;  // the record that returns a and b to the pool (a launch may be counted under two kinds)
 };
 static bool g_prof = false;
 static uint32_t g_prof_mask = ~0u;  // kernel kinds timed while enabled
@@ -70,7 +71,10 @@ static void prof_stop(hipStream_t s, hipEvent_t a, int kind, double bytes, doubl
   hipEvent_t b = pool_event();
   if (!b) return;
   (void)hipEventRecord(b, s);
-  g_recs.push_back(ProfRec{kind, a, b, bytes, flops});
+  g_recs.push_back(ProfRec{kind, a, b, bytes, flops, true});
+  // products that are large by flops and intensity are also tallied on their own
+  if (kind == TN_KERNEL_GEMM && flops >= 1e9 && flops >= 40.0 * bytes)
+    g_recs.push_back(ProfRec{TN_KERNEL_GEMM_LARGE, a, b, bytes, flops, false});
 }
 
 // ---------------------------------------------------------------------------
@@ -457,8 +461,10 @@ extern "C" tn_status tn_profile_select(uint32_t kind_mask) {
 extern "C" void tn_profile_reset(void) {
   for (ProfRec& r : g_recs) {
     (void)hipEventSynchronize(r.b);
-    g_pool.push_back(r.a);
-    g_pool.push_back(r.b);
+    if (r.owner) {
+      g_pool.push_back(r.a);
+      g_pool.push_back(r.b);
+    }
   }
   g_recs.clear();
 }
@@ -474,8 +480,10 @@ extern "C" int32_t tn_profile_read(tn_kernel_profile* out, int32_t capacity) {
       acc[r.kind].bytes += r.bytes;
       acc[r.kind].flops += r.flops;
     }
-    g_pool.push_back(r.a);
-    g_pool.push_back(r.b);
+    if (r.owner) {
+      g_pool.push_back(r.a);
+      g_pool.push_back(r.b);
+    }
   }
   g_recs.clear();
   int n = 0;

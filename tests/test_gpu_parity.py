@@ -177,10 +177,17 @@ def test_config2_full_size_orders_agree():
     two different contraction orders give the same amplitudes (Sec. 2.2.3)."""
     from paper_2108_06831_amd import Network, amplitudes
     circ, bits = workloads.config2()
-    net = Network.from_circuit(circ, output="amplitudes", n_bitstrings=4096)
-    a1 = amplitudes(net, net.plan("search", max_log2_intermediate=28, trials=32), bits).cpu().numpy()
-    a2 = amplitudes(net, net.plan("greedy", max_log2_intermediate=28), bits).cpu().numpy()
-    a3 = amplitudes(net, net.plan("search", max_log2_intermediate=28, trials=32, seed=7), bits).cpu().numpy()
+    # three genuinely different contractions: the unfused network (largest
+    # intermediate 2^22), and the two-qubit-fused networks in dense and split
+    # form (intermediates up to 2^27 and 2^28 elements)
+    runs = []
+    for fuse in (False, "dense", "split"):
+        net = Network.from_circuit(circ, output="amplitudes", n_bitstrings=4096, fuse=fuse)
+        path = net.plan("search", max_log2_intermediate=28, trials=64, seed=7)
+        print(f"  fuse={fuse}: {path.stats['flops']:.3e} flops, largest intermediate "
+              f"2^{int(np.log2(path.stats['max_intermediate_elems']))}", flush=True)
+        runs.append(amplitudes(net, path, bits).cpu().numpy())
+    a1, a2, a3 = runs
     e12, e13 = relerr(a1, a2), relerr(a1, a3)
     print(f"config2 full: order agreement {e12:.2e} {e13:.2e}; mean 2^n|a|^2 = "
           f"{np.mean(np.abs(a1) ** 2) * 2 ** 32:.3f}", flush=True)
