@@ -176,12 +176,32 @@ class Amplitudes(Workload):
         self.bits = torch.as_tensor(bits.view(np.int64), device="cuda")
         self.out = torch.empty(len(bits), dtype=torch.complex64, device="cuda")
         self.ws = torch.empty(max(p.workspace_bytes(1) for p in self.cands), dtype=torch.uint8, device="cuda")
+        self.bits_np = bits
         self.unit, self.units_per_step = "amplitudes/s", float(len(bits))
         self.config = {"workload": "32-qubit 4x8 grid circuit, depth 12, 4096 seeded bitstrings on a batch index",
                        "n_qubits": 32, "n_bitstrings": len(bits), "path": "search", "precision": precision}
 
     def step(self):
         self.tnq.amplitudes(self.net, self.path, self.bits, precision=self.precision, out=self.out, workspace=self.ws)
+
+    def check(self):
+        """Error on 16 sampled amplitudes against the oracle's FP64 contraction
+        of each single amplitude (the full FP64 state is 64 GiB)."""
+        import oracle
+        idx = np.random.default_rng(11).choice(len(self.bits_np), size=16, replace=False)
+        got = self.out.cpu().numpy()[idx]
+        t0 = time.perf_counter()
+        want = np.array([oracle.single_amplitude(self.circ, int(self.bits_np[i])) for i in idx])
+        self.cpu_s, self.cpu_n = time.perf_counter() - t0, len(idx)
+        return relerr(got, want)
+
+    def cpu_baseline(self):
+        import oracle
+        if not hasattr(self, "cpu_s"):
+            self.check()
+        return {"value": self.cpu_n / self.cpu_s, "unit": self.unit, "cores": 1, "kind": "oracle",
+                "sample": f"{self.cpu_n} of the 4096 amplitudes, each by the oracle's FP64 contraction of the "
+                          f"closed network (numpy, one thread in Python), {self.cpu_s:.1f} s"}
 
     def tune(self):
         reports = {}

@@ -16,6 +16,9 @@ circuits from the ``workloads`` package, which holds no simulation arithmetic.
                          exp(-i theta G) whose generator G has two eigenvalues.
 * ``contract``           the definition of a pairwise tensor contraction
                          (Sec. 2.2.1: a sum over shared indices, eq. (2.2)).
+* ``single_amplitude``   <b|U|0...0> of a circuit too wide for a full FP64
+                         state, by contracting its closed network (Sec. 2.2.2)
+                         pairwise in FP64 along a plain greedy order.
 """
 from __future__ import annotations
 
@@ -228,3 +231,81 @@ def contract(a: np.ndarray, modes_a: Sequence[int], b: np.ndarray, modes_b: Sequ
 
     spec = f"{lab(modes_a)},{lab(modes_b)}->{lab(modes_c)}"
     return np.einsum(spec, np.asarray(a, dtype=np.complex128), np.asarray(b, dtype=np.complex128))
+
+
+def single_amplitude(circ: Circuit, bits: int, params: Optional[np.ndarray] = None, max_log2: int = 30) -> complex:
+    """<b|U|0...0> (qubit 0 = most significant bit of ``bits``) by contracting
+    the circuit's tensor network closed with |0> kets and the bra <b| (Sec.
+    2.2.2, eq. (2.3)), every pairwise step a plain sum over the shared indices
+    (eq. (2.2), numpy.tensordot) in complex128.  The order: repeatedly the pair
+    of tensors sharing an index whose result is smallest relative to its
+    operands (ties: smaller result, then earlier tensors).  Every index joins
+    exactly two tensors (gates are dense matrices here, no hyper-indices)."""
+    n = circ.n_qubits
+    arrays, labels = [], []
+    wire = list(range(n))
+    nxt = n
+
+    def add(a, labs):
+        arrays.append(np.asarray(a, dtype=np.complex128))
+        labels.append(list(labs))
+
+    for q in range(n):
+        add([1.0, 0.0], [q])
+    for g in circ.gates:
+        m = gate_matrix(g.kind, circ.resolved_angles(g, params))
+        if len(g.qubits) == 1:
+            q = g.qubits[0]
+            add(m, [nxt, wire[q]])
+            wire[q] = nxt
+            nxt += 1
+        else:
+            a, b = g.qubits
+            add(m.reshape(2, 2, 2, 2), [nxt, nxt + 1, wire[a], wire[b]])
+            wire[a], wire[b] = nxt, nxt + 1
+            nxt += 2
+    for q in range(n):
+        e = np.zeros(2)
+        e[(bits >> (n - 1 - q)) & 1] = 1.0
+        add(e, [wire[q]])
+    live = set(range(len(arrays)))
+    holders = {}
+    for t, ls in enumerate(labels):
+        for lb in ls:
+            holders.setdefault(lb, []).append(t)
+    scalars = []
+    while True:
+        best = None
+        for lb, ts in holders.items():
+            i, j = sorted(ts)
+            shared = set(labels[i]) & set(labels[j])
+            rc = len(labels[i]) + len(labels[j]) - 2 * len(shared)
+            key = (rc - len(labels[i]) - len(labels[j]), rc, i, j)
+            if best is None or key < best[0]:
+                best = (key, i, j, shared)
+        if best is None:
+            break
+        _, i, j, shared = best
+        if best[0][1] > max_log2:
+            raise MemoryError(f"intermediate of 2^{best[0][1]} elements")
+        sh = sorted(shared)
+        ai = [labels[i].index(x) for x in sh]
+        aj = [labels[j].index(x) for x in sh]
+        c = np.tensordot(arrays[i], arrays[j], axes=(ai, aj))
+        lc = [x for x in labels[i] if x not in shared] + [x for x in labels[j] if x not in shared]
+        for x in sh:
+            del holders[x]
+        k = len(arrays)
+        arrays.append(c)
+        labels.append(lc)
+        for x in lc:
+            holders[x] = [k if t in (i, j) else t for t in holders[x]]
+        arrays[i] = arrays[j] = None
+        live -= {i, j}
+        live.add(k)
+        if not lc:
+            scalars.append(complex(c))
+            live.discard(k)
+    for t in live:  # tensors left without indices (a closed network reduces to scalars)
+        scalars.append(complex(np.asarray(arrays[t]).reshape(())))
+    return complex(np.prod(scalars))

@@ -205,6 +205,7 @@ void gemm_default_launch(const GemmDesc& g, int* tile, int* split);
 constexpr int kSmallMaxBits = 12;
 constexpr int kSmallMaxMacLog2 = 20;
 constexpr int kSmallDescCache = 128;  // step descriptors staged in LDS at a time
+constexpr int kSmallStage = 12288;    // operand elements staged in LDS per round (96 KB)
 struct SmallStep {
   int32_t a_buf, b_buf, c_buf;  // BUF_IN / BUF_WS, or an LDS slot for a result the next step consumes
   int32_t c_bits, k_bits;
@@ -212,7 +213,13 @@ struct SmallStep {
   int64_t a_off, b_off, c_off;
   int8_t apos[kSmallMaxBits], bpos[kSmallMaxBits];
   int8_t ka[kSmallMaxBits], kb[kSmallMaxBits];
+  // planned on the host: a level is run in rounds of steps whose operands fit
+  // the LDS stage together; offsets of this step's operands in the stage and
+  // of its first output among the round's outputs, and (on a round's first
+  // step) the index, within the level's chunk, one past the round's last step
+  int32_t stage_a, stage_b, out0, round_end;
 };
+static_assert(sizeof(SmallStep) % 16 == 0, "SmallStep is copied in 16-byte words");
 
 enum StepKind { SK_SKINNY = 0, SK_GEMM = 1, SK_SMALL = 2 };
 

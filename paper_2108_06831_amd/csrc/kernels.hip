@@ -232,87 +232,111 @@ hipError_t launch_skinny(hipStream_t s, const SkinnyDesc& d, const float2* g, in
 // A step is computed into registers, then written after a barrier, so a step
 // may overwrite one of its own operands.
 // ---------------------------------------------------------------------------
-constexpr int kSmallStage = 12288;  // operand elements staged in LDS per round (96 KB)
+
+// byte j (0..11) of three packed words, sign-extended
+__device__ inline int packed_byte(uint32_t w0, uint32_t w1, uint32_t w2, int j) {
+  const uint32_t x = j < 4 ? w0 : j < 8 ? w1 : w2;
+  return (int)(int8_t)(x >> (8 * (j & 3)));
+}
 
 template <int PREC>
 __global__ __launch_bounds__(kThreads) void k_small_steps(const SmallStep* steps, const int32_t* list_off,
                                                           const int32_t* level_off, float2* in, int64_t in_bs,
                                                           float2* ws, int64_t ws_bs) {
-  __shared__ SmallStep desc[kSmallDescCache];
-  __shared__ int32_t first_out[kSmallDescCache + 1];  // prefix of output counts over a round's steps
-  __shared__ int32_t a_at[kSmallDescCache], b_at[kSmallDescCache];  // staging offsets of the operands
-  __shared__ int32_t round_end;
-  __shared__ float2 stage[kSmallStage];
+  __shared__ __attribute__((aligned(16))) SmallStep desc[kSmallDescCache];
+  __shared__ __attribute__((aligned(16))) float2 stage[kSmallStage];
   const int w = blockIdx.x, z = blockIdx.y;
   float2* IN = in + (int64_t)z * in_bs;
   float2* WS = ws + (int64_t)z * ws_bs;
+  int win0 = -1, win1 = -1;  // steps whose descriptors are in LDS
   for (int lv = list_off[w]; lv < list_off[w + 1]; ++lv) {
     const int l0 = level_off[lv], l1 = level_off[lv + 1];
     for (int cb = l0; cb < l1; cb += kSmallDescCache) {
       const int ce = min(l1, cb + kSmallDescCache), ns = ce - cb;
-      {
-        const int words = ns * (int)(sizeof(SmallStep) / 4);
-        const uint32_t* src = reinterpret_cast<const uint32_t*>(steps + cb);
-        uint32_t* dst = reinterpret_cast<uint32_t*>(desc);
+      if (cb < win0 || ce > win1) {
+        // load the descriptors of as many whole following levels as fit (at
+        // least this chunk): one global round trip for several levels
+        int end = ce;
+        if (cb == l0 && l1 - l0 <= kSmallDescCache) {
+          int nl = lv + 1;
+          while (nl < list_off[w + 1] && level_off[nl + 1] - cb <= kSmallDescCache) ++nl;
+          end = level_off[nl];
+        }
+        const int words = (end - cb) * (int)(sizeof(SmallStep) / 16);
+        const uint4* src = reinterpret_cast<const uint4*>(steps + cb);
+        uint4* dst = reinterpret_cast<uint4*>(desc);
+        __syncthreads();  // the previous window is no longer read
         for (int i = threadIdx.x; i < words; i += kThreads) dst[i] = src[i];
+        win0 = cb;
+        win1 = end;
+        __syncthreads();
       }
-      __syncthreads();
-      // rounds: as many of the level's (independent) steps as their operands fit in LDS
+      const SmallStep* desc_c = desc + (cb - win0);  // this chunk's descriptors
+      // rounds (planned on the host): steps of the level whose operands fit in LDS together
       for (int r0 = 0; r0 < ns;) {
-        if (threadIdx.x == 0) {
-          int used = 0, outs = 0, i = r0;
-          for (; i < ns; ++i) {
-            const int need = (1 << desc[i].a_bits) + (1 << desc[i].b_bits);
-            if (i > r0 && used + need > kSmallStage) break;
-            a_at[i] = used;
-            b_at[i] = used + (1 << desc[i].a_bits);
-            used += need;
-            first_out[i] = outs;
-            outs += 1 << desc[i].c_bits;
-          }
-          first_out[i] = outs;
-          round_end = i;
-        }
-        __syncthreads();
-        const int r1 = round_end;
-        // stage the operands with coalesced copies
-        for (int i = r0; i < r1; ++i) {
-          const SmallStep& st = desc[i];
-          const float2* A = (st.a_buf == BUF_IN ? IN : WS) + st.a_off;
-          const float2* B = (st.b_buf == BUF_IN ? IN : WS) + st.b_off;
-          for (int e = threadIdx.x; e < (1 << st.a_bits); e += kThreads) stage[a_at[i] + e] = A[e];
-          for (int e = threadIdx.x; e < (1 << st.b_bits); e += kThreads) stage[b_at[i] + e] = B[e];
-        }
-        __syncthreads();
-        const int total = first_out[r1] - first_out[r0];
-        for (int g = threadIdx.x; g < total; g += kThreads) {
-          const int gg = g + first_out[r0];
-          int lo = r0, hi = r1 - 1;  // the step owning output gg
+        const int r1 = desc_c[r0].round_end;
+        const SmallStep& last = desc_c[r1 - 1];
+        const int stage_end = last.stage_b + (1 << last.b_bits);
+        const int total = last.out0 + (1 << last.c_bits);
+        // stage the operands: one flat loop over the round's operand elements,
+        // so that every thread's loads are independent of each other
+        for (int e = threadIdx.x; e < stage_end; e += kThreads) {
+          int lo = r0, hi = r1 - 1;  // the step owning staged element e
           while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (first_out[mid] <= gg) lo = mid; else hi = mid - 1;
+            if (desc_c[mid].stage_a <= e) lo = mid; else hi = mid - 1;
           }
-          const SmallStep& st = desc[lo];
-          const int o = gg - first_out[lo];
-          const float2* As = stage + a_at[lo];
-          const float2* Bs = stage + b_at[lo];
-          float2* C = (st.c_buf == BUF_IN ? IN : WS) + st.c_off;
+          const SmallStep& st = desc_c[lo];
+          const bool is_a = e < st.stage_b;
+          const float2* src = is_a ? (st.a_buf == BUF_IN ? IN : WS) + st.a_off + (e - st.stage_a)
+                                   : (st.b_buf == BUF_IN ? IN : WS) + st.b_off + (e - st.stage_b);
+          stage[e] = *src;
+        }
+        __syncthreads();
+        // the current step's index maps, packed in registers
+        int cur = -1, kbits = 0, a0 = 0, b0 = 0;
+        uint32_t ap0 = 0, ap1 = 0, ap2 = 0, bp0 = 0, bp1 = 0, bp2 = 0;
+        uint32_t ka0 = 0, ka1 = 0, ka2 = 0, kb0 = 0, kb1 = 0, kb2 = 0;
+        float2* C = nullptr;
+        for (int g = threadIdx.x; g < total; g += kThreads) {
+          int lo = r0, hi = r1 - 1;  // the step owning output g
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (desc_c[mid].out0 <= g) lo = mid; else hi = mid - 1;
+          }
+          if (lo != cur) {
+            const SmallStep& st = desc_c[lo];
+            const uint32_t* ap = reinterpret_cast<const uint32_t*>(st.apos);
+            const uint32_t* bp = reinterpret_cast<const uint32_t*>(st.bpos);
+            const uint32_t* ka = reinterpret_cast<const uint32_t*>(st.ka);
+            const uint32_t* kb = reinterpret_cast<const uint32_t*>(st.kb);
+            ap0 = ap[0]; ap1 = ap[1]; ap2 = ap[2];
+            bp0 = bp[0]; bp1 = bp[1]; bp2 = bp[2];
+            ka0 = ka[0]; ka1 = ka[1]; ka2 = ka[2];
+            kb0 = kb[0]; kb1 = kb[1]; kb2 = kb[2];
+            kbits = st.k_bits;
+            a0 = st.stage_a;
+            b0 = st.stage_b;
+            C = (st.c_buf == BUF_IN ? IN : WS) + st.c_off;
+            cur = lo;
+          }
+          const int o = g - desc_c[lo].out0;
           int ab = 0, bb = 0;
-          for (int p = 0; p < st.c_bits; ++p)
-            if ((o >> p) & 1) {
-              if (st.apos[p] >= 0) ab |= 1 << st.apos[p];
-              if (st.bpos[p] >= 0) bb |= 1 << st.bpos[p];
-            }
-          const int kb = st.k_bits;
-          float2 acc = f2(0.f, 0.f);
-          for (int k = 0; k < (1 << kb); ++k) {
-            int ao = ab, bo = bb;
-            for (int j = 0; j < kb; ++j)
-              if ((k >> j) & 1) {
-                ao |= 1 << st.ka[j];
-                bo |= 1 << st.kb[j];
-              }
-            acc = cmac<PREC>(acc, As[ao], Bs[bo]);
+          for (uint32_t m = (uint32_t)o; m; m &= m - 1) {
+            const int p = __builtin_ctz(m);
+            const int pa = packed_byte(ap0, ap1, ap2, p), pb = packed_byte(bp0, bp1, bp2, p);
+            if (pa >= 0) ab |= 1 << pa;
+            if (pb >= 0) bb |= 1 << pb;
+          }
+          // summed index in Gray-code order: one address bit flips per term
+          const float2* As = stage + a0;
+          const float2* Bs = stage + b0;
+          float2 acc = cmac<PREC>(f2(0.f, 0.f), As[ab], Bs[bb]);
+          for (int k = 1; k < (1 << kbits); ++k) {
+            const int j = __builtin_ctz(k);
+            ab ^= 1 << packed_byte(ka0, ka1, ka2, j);
+            bb ^= 1 << packed_byte(kb0, kb1, kb2, j);
+            acc = cmac<PREC>(acc, As[ab], Bs[bb]);
           }
           C[o] = acc;
         }

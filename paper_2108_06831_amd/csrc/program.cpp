@@ -770,6 +770,30 @@ tn_status compile_program(const tn_network* net, tn_path* path, const std::vecto
       path->small_lists.push_back((int32_t)path->small_levels.size());
     }
     path->small_levels.push_back((int32_t)path->small_steps.size());
+    // rounds of each level (in chunks of kSmallDescCache steps, as the kernel
+    // reads them): consecutive steps while their operands fit the stage
+    for (size_t lv = 0; lv + 1 < path->small_levels.size(); ++lv) {
+      const int l0 = path->small_levels[lv], l1 = path->small_levels[lv + 1];
+      for (int cb = l0; cb < l1; cb += kSmallDescCache) {
+        const int ce = std::min(l1, cb + kSmallDescCache);
+        for (int r0 = cb; r0 < ce;) {
+          int used = 0, outs = 0, i = r0;
+          for (; i < ce; ++i) {
+            SmallStep& d = path->small_steps[i];
+            const int need = (1 << d.a_bits) + (1 << d.b_bits);
+            if (i > r0 && used + need > kSmallStage) break;
+            d.stage_a = used;
+            d.stage_b = used + (1 << d.a_bits);
+            d.out0 = outs;
+            d.round_end = 0;
+            used += need;
+            outs += 1 << d.c_bits;
+          }
+          path->small_steps[r0].round_end = i - cb;
+          r0 = i;
+        }
+      }
+    }
   }
   build_chains(path, T);
   st.n_sweep_steps = st.n_sweep_passes = 0;

@@ -329,3 +329,21 @@ def test_expectation_graph_replays():
     stream.synchronize()
     for i, it in enumerate(inst):
         assert scalar_err(out[i, 0].item(), len(it.edges) / 2) < C64_TOL
+
+
+@pytest.mark.parametrize("precision", ["c64", "bf16x3"])
+def test_config2_full_size_sampled_amplitudes(precision):
+    """32-qubit grid, all 4096 amplitudes on the GPU along the bench's order;
+    24 of them, sampled, against the oracle's FP64 network contraction of each
+    single amplitude."""
+    from paper_2108_06831_amd import Network, amplitudes
+    circ, bits = workloads.config2()
+    net = Network.from_circuit(circ, output="amplitudes", n_bitstrings=4096)
+    path = net.plan("search", max_log2_intermediate=28, trials=256)
+    got = amplitudes(net, path, bits, precision=precision).cpu().numpy()
+    rng = np.random.default_rng(77)
+    idx = sorted(rng.choice(4096, size=24, replace=False).tolist())
+    want = np.array([oracle.single_amplitude(circ, int(bits[i])) for i in idx])
+    err = relerr(got[idx], want)
+    print(f"config2 {precision}: sampled amplitude rel err {err:.2e}", flush=True)
+    assert err < (C64_TOL if precision == "c64" else BF16X3_TOL)

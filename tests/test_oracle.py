@@ -404,3 +404,48 @@ def test_contract_batch_mode_brute_force():
                 for k in range(4):
                     want[nn, b, m] += A[b, m, k] * B[k, b, nn]
     assert np.allclose(got, want)
+
+
+# ---------------------------------------------------------------------------
+# single amplitudes by network contraction (the oracle for circuits too wide
+# for a full FP64 state)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("which", ["brickwork", "random_all_kinds", "grid"])
+def test_single_amplitude_matches_statevector(which):
+    """Two independent FP64 algorithms (pairwise network contraction vs the
+    gate-by-gate sweep) give the same amplitudes."""
+    rng = np.random.default_rng(31)
+    if which == "brickwork":
+        circ = workloads.config0()
+    elif which == "random_all_kinds":
+        circ = workloads.random_circuit(11, 90, rng)
+    else:
+        circ = workloads.grid_circuit(3, 4, 8, rng)
+    psi = oracle.statevector(circ)
+    n = circ.n_qubits
+    for b in [0, (1 << n) - 1] + [int(x) for x in rng.integers(0, 1 << n, size=12)]:
+        a = oracle.single_amplitude(circ, b)
+        assert abs(a - psi[b]) < 1e-12, (b, a, psi[b])
+
+
+def test_single_amplitude_ghz_closed_form():
+    """GHZ: <0...0|psi> = <1...1|psi> = 1/sqrt2, every other amplitude 0."""
+    n = 9
+    gates = [workloads.Gate("H", (0,), (), ())] + [workloads.Gate("CNOT", (q, q + 1), (), ()) for q in range(n - 1)]
+    circ = workloads.Circuit(n, gates, 0, "ghz9")
+    s = 1 / np.sqrt(2)
+    assert abs(oracle.single_amplitude(circ, 0) - s) < 1e-14
+    assert abs(oracle.single_amplitude(circ, (1 << n) - 1) - s) < 1e-14
+    for b in (1, 2, 255, 256, 300):
+        assert abs(oracle.single_amplitude(circ, b)) < 1e-14
+
+
+def test_single_amplitude_planted_mistake_fails():
+    """A reversed bit order (qubit 0 as the least significant bit) is caught."""
+    rng = np.random.default_rng(5)
+    circ = workloads.random_circuit(8, 40, rng)
+    psi = oracle.statevector(circ)
+    b = 0b10110001
+    rev = int(f"{b:08b}"[::-1], 2)
+    assert abs(oracle.single_amplitude(circ, b) - psi[b]) < 1e-12
+    assert abs(oracle.single_amplitude(circ, rev) - psi[b]) > 1e-6
