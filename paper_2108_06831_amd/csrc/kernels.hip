@@ -810,6 +810,8 @@ __global__ __launch_bounds__(kThreads) void k_gemm(GemmArgs g) {
   constexpr int kSmem = F == 0 ? kF32Bytes : kB3Bytes;
   __shared__ __attribute__((aligned(16))) char smem[kSmem];
   __shared__ int64_t TAm[BM], TCm[BM], TBn[BN], TCn[BN], TAk[kBK], TBk[kBK];
+  constexpr int kKt = 64;  // K tiles whose origin deposits are tabulated (the rest computed on the fly)
+  __shared__ int64_t TAt[kKt], TBt[kKt];
   float (*As_re)[BM + 1] = reinterpret_cast<float (*)[BM + 1]>(smem);
   float (*As_im)[BM + 1] = reinterpret_cast<float (*)[BM + 1]>(smem + kBK * (BM + 1) * 4);
   float2 (*Bs)[BN + 1] = reinterpret_cast<float2 (*)[BN + 1]>(smem + 2 * kBK * (BM + 1) * 4);
@@ -854,6 +856,10 @@ __global__ __launch_bounds__(kThreads) void k_gemm(GemmArgs g) {
     TAk[tid] = deposit(tid, g.a_k, nb);
     TBk[tid] = deposit(tid, g.b_k, nb);
   }
+  if (tid < kKt && kbeg + (int64_t)tid * kBK < kend) {
+    TAt[tid] = deposit(kbeg + (int64_t)tid * kBK, g.a_k, g.nbk);
+    TBt[tid] = deposit(kbeg + (int64_t)tid * kBK, g.b_k, g.nbk);
+  }
   floatx16 acc[TM][TN];
 #pragma unroll
   for (int i = 0; i < TM; ++i)
@@ -874,20 +880,45 @@ __global__ __launch_bounds__(kThreads) void k_gemm(GemmArgs g) {
   };
   // software pipeline: the next K tile is fetched into registers while the
   // current one is multiplied out of LDS
+  // per-thread element addresses without the K tile's origin, fixed for the block
+  const float2* pa[kPA];
+  const float2* pb[kPB];
+  bool va[kPA], vb[kPB];
+  int ka_e[kPA], kb_e[kPB];
+#pragma unroll
+  for (int e = 0; e < kPA; ++e) {
+    int mm, kk;
+    a_elem(e, mm, kk);
+    pa[e] = A + (base_a | TAm[mm] | TAk[kk]);
+    va[e] = m0 + mm < g.M;
+    ka_e[e] = kk;
+  }
+#pragma unroll
+  for (int e = 0; e < kPB; ++e) {
+    int nn, kk;
+    b_elem(e, nn, kk);
+    pb[e] = B + (base_b | TBn[nn] | TBk[kk]);
+    vb[e] = n0 + nn < g.N;
+    kb_e[e] = kk;
+  }
+  const bool interior = m0 + BM <= g.M && n0 + BN <= g.N;
   float2 ra[kPA], rb[kPB];
   auto fetch = [&](int64_t k0) {
-    const int64_t ka = deposit(k0, g.a_k, g.nbk), kb = deposit(k0, g.b_k, g.nbk);
+    const int64_t t = (k0 - kbeg) / kBK;
+    const int64_t ka = t < kKt ? TAt[t] : deposit(k0, g.a_k, g.nbk);
+    const int64_t kb = t < kKt ? TBt[t] : deposit(k0, g.b_k, g.nbk);
+    const int64_t rem = kend - k0;
+    const int kleft = rem < kBK ? (int)rem : kBK;  // valid k of this tile
+    if (interior && kleft == kBK) {  // whole tile inside the operands: no guards
 #pragma unroll
-    for (int e = 0; e < kPA; ++e) {
-      int mm, kk;
-      a_elem(e, mm, kk);
-      ra[e] = (m0 + mm < g.M && k0 + kk < kend) ? A[base_a | TAm[mm] | ka | TAk[kk]] : f2(0.f, 0.f);
-    }
+      for (int e = 0; e < kPA; ++e) ra[e] = pa[e][ka];
 #pragma unroll
-    for (int e = 0; e < kPB; ++e) {
-      int nn, kk;
-      b_elem(e, nn, kk);
-      rb[e] = (n0 + nn < g.N && k0 + kk < kend) ? B[base_b | TBn[nn] | kb | TBk[kk]] : f2(0.f, 0.f);
+      for (int e = 0; e < kPB; ++e) rb[e] = pb[e][kb];
+    } else {
+#pragma unroll
+      for (int e = 0; e < kPA; ++e) ra[e] = (va[e] && ka_e[e] < kleft) ? pa[e][ka] : f2(0.f, 0.f);
+#pragma unroll
+      for (int e = 0; e < kPB; ++e) rb[e] = (vb[e] && kb_e[e] < kleft) ? pb[e][kb] : f2(0.f, 0.f);
     }
   };
   auto stage = [&]() {
@@ -1011,6 +1042,8 @@ __global__ __launch_bounds__(kThreads) void k_gemm3m(GemmArgs g) {
   constexpr int kLogBK = BK == 32 ? 5 : 4;
   __shared__ float Ar[BK][BM + 1], Ai[BK][BM + 1], Br[BK][BN + 1], Bi[BK][BN + 1];
   __shared__ int64_t TAm[BM], TCm[BM], TBn[BN], TCn[BN], TAk[BK], TBk[BK];
+  constexpr int kKt = 64;  // K tiles whose origin deposits are tabulated (the rest computed on the fly)
+  __shared__ int64_t TAt[kKt], TBt[kKt];
   int64_t bid = blockIdx.x;
   const int64_t tn = bid % g.tiles_n;
   bid /= g.tiles_n;
@@ -1047,6 +1080,10 @@ __global__ __launch_bounds__(kThreads) void k_gemm3m(GemmArgs g) {
     TAk[tid] = deposit(tid, g.a_k, nb);
     TBk[tid] = deposit(tid, g.b_k, nb);
   }
+  if (tid < kKt && kbeg + (int64_t)tid * BK < kend) {
+    TAt[tid] = deposit(kbeg + (int64_t)tid * BK, g.a_k, g.nbk);
+    TBt[tid] = deposit(kbeg + (int64_t)tid * BK, g.b_k, g.nbk);
+  }
   floatx16 p1[TM], p2[TM], p3[TM];
 #pragma unroll
   for (int i = 0; i < TM; ++i)
@@ -1062,20 +1099,45 @@ __global__ __launch_bounds__(kThreads) void k_gemm3m(GemmArgs g) {
     const int idx = tid + e * kThreads;
     if (BNF) { nn = idx % BN; kk = idx / BN; } else { nn = idx / BK; kk = idx % BK; }
   };
+  // per-thread element addresses without the K tile's origin, fixed for the block
+  const float2* pa[kPA];
+  const float2* pb[kPB];
+  bool va[kPA], vb[kPB];
+  int ka_e[kPA], kb_e[kPB];
+#pragma unroll
+  for (int e = 0; e < kPA; ++e) {
+    int mm, kk;
+    a_elem(e, mm, kk);
+    pa[e] = A + (base_a | TAm[mm] | TAk[kk]);
+    va[e] = m0 + mm < g.M;
+    ka_e[e] = kk;
+  }
+#pragma unroll
+  for (int e = 0; e < kPB; ++e) {
+    int nn, kk;
+    b_elem(e, nn, kk);
+    pb[e] = B + (base_b | TBn[nn] | TBk[kk]);
+    vb[e] = n0 + nn < g.N;
+    kb_e[e] = kk;
+  }
+  const bool interior = m0 + BM <= g.M && n0 + BN <= g.N;
   float2 ra[kPA], rb[kPB];
   auto fetch = [&](int64_t k0) {
-    const int64_t ka = deposit(k0, g.a_k, g.nbk), kb = deposit(k0, g.b_k, g.nbk);
+    const int64_t t = (k0 - kbeg) / BK;
+    const int64_t ka = t < kKt ? TAt[t] : deposit(k0, g.a_k, g.nbk);
+    const int64_t kb = t < kKt ? TBt[t] : deposit(k0, g.b_k, g.nbk);
+    const int64_t rem = kend - k0;
+    const int kleft = rem < BK ? (int)rem : BK;  // valid k of this tile
+    if (interior && kleft == BK) {  // whole tile inside the operands: no guards
 #pragma unroll
-    for (int e = 0; e < kPA; ++e) {
-      int mm, kk;
-      a_elem(e, mm, kk);
-      ra[e] = (m0 + mm < g.M && k0 + kk < kend) ? A[base_a | TAm[mm] | ka | TAk[kk]] : f2(0.f, 0.f);
-    }
+      for (int e = 0; e < kPA; ++e) ra[e] = pa[e][ka];
 #pragma unroll
-    for (int e = 0; e < kPB; ++e) {
-      int nn, kk;
-      b_elem(e, nn, kk);
-      rb[e] = (n0 + nn < g.N && k0 + kk < kend) ? B[base_b | TBn[nn] | kb | TBk[kk]] : f2(0.f, 0.f);
+      for (int e = 0; e < kPB; ++e) rb[e] = pb[e][kb];
+    } else {
+#pragma unroll
+      for (int e = 0; e < kPA; ++e) ra[e] = (va[e] && ka_e[e] < kleft) ? pa[e][ka] : f2(0.f, 0.f);
+#pragma unroll
+      for (int e = 0; e < kPB; ++e) rb[e] = (vb[e] && kb_e[e] < kleft) ? pb[e][kb] : f2(0.f, 0.f);
     }
   };
   auto stage = [&]() {
@@ -1100,18 +1162,41 @@ __global__ __launch_bounds__(kThreads) void k_gemm3m(GemmArgs g) {
     stage();
     __syncthreads();
     if (k0 + BK < kend) fetch(k0 + BK);
-#pragma unroll 2
+    // operands of step kk + 2 are read from LDS before the products of step kk
+    const int col = wn * 32 + r32;
+    float br = Br[h][col], bi = Bi[h][col], ar[TM], ai[TM];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      ar[i] = Ar[h][wm * 32 * TM + i * 32 + r32];
+      ai[i] = Ai[h][wm * 32 * TM + i * 32 + r32];
+    }
+#pragma unroll
     for (int kk = 0; kk < BK; kk += 2) {
-      const int col = wn * 32 + r32;
-      const float br = Br[kk + h][col], bi = Bi[kk + h][col];
+      float nbr = 0.f, nbi = 0.f, nar[TM], nai[TM];
+      if (kk + 2 < BK) {
+        nbr = Br[kk + 2 + h][col];
+        nbi = Bi[kk + 2 + h][col];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+          nar[i] = Ar[kk + 2 + h][wm * 32 * TM + i * 32 + r32];
+          nai[i] = Ai[kk + 2 + h][wm * 32 * TM + i * 32 + r32];
+        }
+      }
       const float bs = br + bi;
 #pragma unroll
       for (int i = 0; i < TM; ++i) {
-        const int row = wm * 32 * TM + i * 32 + r32;
-        const float ar = Ar[kk + h][row], ai = Ai[kk + h][row];
-        p1[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, br, p1[i], 0, 0, 0);
-        p2[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, bi, p2[i], 0, 0, 0);
-        p3[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar + ai, bs, p3[i], 0, 0, 0);
+        p1[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[i], br, p1[i], 0, 0, 0);
+        p2[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[i], bi, p2[i], 0, 0, 0);
+        p3[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[i] + ai[i], bs, p3[i], 0, 0, 0);
+      }
+      if (kk + 2 < BK) {
+        br = nbr;
+        bi = nbi;
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+          ar[i] = nar[i];
+          ai[i] = nai[i];
+        }
       }
     }
     __syncthreads();
