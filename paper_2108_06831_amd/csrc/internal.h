@@ -149,9 +149,13 @@ struct AdjGateDesc {
   int32_t gate;     // index in the network's gate sweep (matrix U of the gate)
   int32_t red;      // accumulator of the pass, or -1 (no gradient term)
   int32_t slot;     // gradient-partials column, or -1
-  int32_t pad;
+  int32_t form;     // ADJ_*: shape of the generator (dense gates) / of U (diagonal gates)
   float gen[8];     // generator G: dense 2x2 row-major, or diagonal entries (complex, re/im interleaved)
 };
+// dense one-qubit generators c X or Y, real diagonal generators, diagonal
+// gates whose entries are all +1 or -1 (applied as sign flips; bit b of
+// `form >> 8` set: entry b is -1)
+enum AdjForm { ADJ_GENERIC = 0, ADJ_GEN_X = 1, ADJ_GEN_Y = 2, ADJ_DIAG_SIGNS = 4 };
 struct SweepChain {
   BufRef in, out;
   int32_t bits;

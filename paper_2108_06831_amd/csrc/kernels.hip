@@ -386,20 +386,26 @@ struct SweepPassArgs {
 __device__ inline int64_t ins0(int64_t x, int p) { return ((x >> p) << (p + 1)) | (x & (((int64_t)1 << p) - 1)); }
 __device__ inline int lds_phys(int i) { return i + (i >> 5); }
 
+// real: the matrix has no imaginary part (RY, H, X, ...), half the multiplies
 template <int PREC, int U>
-__device__ inline void reg_apply1(float2 (&x)[16], const float2* g) {
+__device__ __forceinline__ void reg_apply1(float2 (&x)[16], const float2* g, bool real = false) {
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     if (r & (1 << U)) continue;
     const int r1 = r | (1 << U);
     const float2 a = x[r], b = x[r1];
-    x[r] = cmac<PREC>(cmac<PREC>(f2(0.f, 0.f), g[0], a), g[1], b);
-    x[r1] = cmac<PREC>(cmac<PREC>(f2(0.f, 0.f), g[2], a), g[3], b);
+    if (PREC == TN_PREC_C64 && real) {
+      x[r] = f2(g[0].x * a.x + g[1].x * b.x, g[0].x * a.y + g[1].x * b.y);
+      x[r1] = f2(g[2].x * a.x + g[3].x * b.x, g[2].x * a.y + g[3].x * b.y);
+    } else {
+      x[r] = cmac<PREC>(cmac<PREC>(f2(0.f, 0.f), g[0], a), g[1], b);
+      x[r1] = cmac<PREC>(cmac<PREC>(f2(0.f, 0.f), g[2], a), g[3], b);
+    }
   }
 }
 
 template <int PREC, int U0, int U1>
-__device__ inline void reg_apply2(float2 (&x)[16], const float2* g) {
+__device__ __forceinline__ void reg_apply2(float2 (&x)[16], const float2* g) {
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     if (r & ((1 << U0) | (1 << U1))) continue;
@@ -420,13 +426,13 @@ __device__ inline void reg_apply2(float2 (&x)[16], const float2* g) {
 // Diagonal factor on the 16 register elements, with the bits of the factor's
 // index resolved at compile time: e_{bit U of r} ...
 template <int PREC, int U>
-__device__ inline void diag_reg1(float2 (&x)[16], float2 e0, float2 e1) {
+__device__ __forceinline__ void diag_reg1(float2 (&x)[16], float2 e0, float2 e1) {
 #pragma unroll
   for (int r = 0; r < 16; ++r) x[r] = cmac<PREC>(f2(0.f, 0.f), (r >> U) & 1 ? e1 : e0, x[r]);
 }
 // ... or d_{bit U0 of r + 2 bit U1 of r}
 template <int PREC, int U0, int U1>
-__device__ inline void diag_reg2(float2 (&x)[16], float2 d0, float2 d1, float2 d2, float2 d3) {
+__device__ __forceinline__ void diag_reg2(float2 (&x)[16], float2 d0, float2 d1, float2 d2, float2 d3) {
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int b = ((r >> U0) & 1) | (((r >> U1) & 1) << 1);
@@ -438,7 +444,7 @@ __device__ inline void diag_reg2(float2 (&x)[16], float2 d0, float2 d1, float2 d
 // bit k_j of r (k_j in 0..3), or, for k_j < 0, the constant bit j of c.  All
 // selections are per gate and thread, none per element.
 template <int PREC>
-__device__ inline void apply_diag(float2 (&x)[16], int n, int k0, int k1, int c, float2 d0, float2 d1, float2 d2,
+__device__ __forceinline__ void apply_diag(float2 (&x)[16], int n, int k0, int k1, int c, float2 d0, float2 d1, float2 d2,
                                   float2 d3) {
   if (n == 2 && k0 >= 0 && k1 >= 0) {
     switch (k0 * 4 + k1) {
@@ -483,6 +489,64 @@ __device__ inline void apply_diag(float2 (&x)[16], int n, int k0, int k1, int c,
     case 1: diag_reg1<PREC, 1>(x, e0, e1); break;
     case 2: diag_reg1<PREC, 2>(x, e0, e1); break;
     default: diag_reg1<PREC, 3>(x, e0, e1); break;
+  }
+}
+
+// x[r] = -x[r] where the diagonal's entry b is -1 (bit b of mask), b resolved as in apply_diag
+template <int U>
+__device__ __forceinline__ void signs_reg1(float2 (&x)[16], int m01) {
+#pragma unroll
+  for (int r = 0; r < 16; ++r)
+    if ((m01 >> ((r >> U) & 1)) & 1) x[r] = f2(-x[r].x, -x[r].y);
+}
+template <int U0, int U1>
+__device__ __forceinline__ void signs_reg2(float2 (&x)[16], int mask) {
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int b = ((r >> U0) & 1) | (((r >> U1) & 1) << 1);
+    if ((mask >> b) & 1) x[r] = f2(-x[r].x, -x[r].y);
+  }
+}
+__device__ __forceinline__ void apply_signs(float2 (&x)[16], int n, int k0, int k1, int c, int mask) {
+  if (n == 2 && k0 >= 0 && k1 >= 0) {
+    switch (k0 * 4 + k1) {
+      case 1: signs_reg2<0, 1>(x, mask); break;
+      case 2: signs_reg2<0, 2>(x, mask); break;
+      case 3: signs_reg2<0, 3>(x, mask); break;
+      case 4: signs_reg2<1, 0>(x, mask); break;
+      case 6: signs_reg2<1, 2>(x, mask); break;
+      case 7: signs_reg2<1, 3>(x, mask); break;
+      case 8: signs_reg2<2, 0>(x, mask); break;
+      case 9: signs_reg2<2, 1>(x, mask); break;
+      case 11: signs_reg2<2, 3>(x, mask); break;
+      case 12: signs_reg2<3, 0>(x, mask); break;
+      case 13: signs_reg2<3, 1>(x, mask); break;
+      default: signs_reg2<3, 2>(x, mask); break;
+    }
+    return;
+  }
+  int k = -1, m01 = 0;  // signs of the register bit's two values
+  if (n == 2 && k0 >= 0) {
+    k = k0;
+    m01 = (c & 2) ? (mask >> 2) & 3 : mask & 3;
+  } else if (n == 2 && k1 >= 0) {
+    k = k1;
+    m01 = (c & 1) ? ((mask >> 1) & 1) | (((mask >> 3) & 1) << 1) : (mask & 1) | (((mask >> 2) & 1) << 1);
+  } else if (n == 1 && k0 >= 0) {
+    k = k0;
+    m01 = mask & 3;
+  }
+  if (k < 0) {
+    if ((mask >> c) & 1)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) x[r] = f2(-x[r].x, -x[r].y);
+    return;
+  }
+  switch (k) {
+    case 0: signs_reg1<0>(x, m01); break;
+    case 1: signs_reg1<1>(x, m01); break;
+    case 2: signs_reg1<2>(x, m01); break;
+    default: signs_reg1<3>(x, m01); break;
   }
 }
 
@@ -553,11 +617,12 @@ __global__ __launch_bounds__(kThreads) void k_sweep_pass(SweepPassArgs a) {
       } else if (gd.n == 1) {
         float2 g[4];
         for (int e = 0; e < 4; ++e) g[e] = G[gd.gidx[e]];
+        const bool real = g[0].y == 0.f && g[1].y == 0.f && g[2].y == 0.f && g[3].y == 0.f;
         switch (gd.rb[0]) {
-          case 0: reg_apply1<PREC, 0>(x, g); break;
-          case 1: reg_apply1<PREC, 1>(x, g); break;
-          case 2: reg_apply1<PREC, 2>(x, g); break;
-          default: reg_apply1<PREC, 3>(x, g); break;
+          case 0: reg_apply1<PREC, 0>(x, g, real); break;
+          case 1: reg_apply1<PREC, 1>(x, g, real); break;
+          case 2: reg_apply1<PREC, 2>(x, g, real); break;
+          default: reg_apply1<PREC, 3>(x, g, real); break;
         }
       } else {
         float2 g[16];
@@ -1595,7 +1660,7 @@ __device__ inline float2 cmulf(float2 a, float2 b) { return f2(a.x * b.x - a.y *
 
 // sum over the register pairs along bit U of Im(conj(l_m) (G p)_m)
 template <int U>
-__device__ inline float reg_grad1(const float2 (&p)[16], const float2 (&l)[16], const float2* G) {
+__device__ __forceinline__ float reg_grad1(const float2 (&p)[16], const float2 (&l)[16], const float2* G) {
   float g = 0.f;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
@@ -1610,27 +1675,28 @@ __device__ inline float reg_grad1(const float2 (&p)[16], const float2 (&l)[16], 
   return g;
 }
 
-// Sum over the 16 register elements of Im(conj(l) q_b p), b resolved as in apply_diag
+// Sum over the 16 register elements of q_b Im(conj(l) p), b resolved as in
+// apply_diag (the diagonal generators Z, 1 - ZZ and |11><11| are real)
 template <int U>
-__device__ inline float dgrad_reg1(const float2 (&p)[16], const float2 (&l)[16], float2 e0, float2 e1) {
+__device__ __forceinline__ float dgrad_reg1(const float2 (&p)[16], const float2 (&l)[16], float e0, float e1) {
   float g = 0.f;
 #pragma unroll
-  for (int r = 0; r < 16; ++r) g += im_conj_mul(l[r], cmulf((r >> U) & 1 ? e1 : e0, p[r]));
+  for (int r = 0; r < 16; ++r) g += ((r >> U) & 1 ? e1 : e0) * im_conj_mul(l[r], p[r]);
   return g;
 }
 template <int U0, int U1>
-__device__ inline float dgrad_reg2(const float2 (&p)[16], const float2 (&l)[16], float2 q0, float2 q1, float2 q2,
-                                   float2 q3) {
+__device__ __forceinline__ float dgrad_reg2(const float2 (&p)[16], const float2 (&l)[16], float q0, float q1, float q2,
+                                   float q3) {
   float g = 0.f;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int b = ((r >> U0) & 1) | (((r >> U1) & 1) << 1);
-    g += im_conj_mul(l[r], cmulf(b == 0 ? q0 : b == 1 ? q1 : b == 2 ? q2 : q3, p[r]));
+    g += (b == 0 ? q0 : b == 1 ? q1 : b == 2 ? q2 : q3) * im_conj_mul(l[r], p[r]);
   }
   return g;
 }
-__device__ inline float diag_grad(const float2 (&p)[16], const float2 (&l)[16], int n, int k0, int k1, int c,
-                                  float2 q0, float2 q1, float2 q2, float2 q3) {
+__device__ __forceinline__ float diag_grad(const float2 (&p)[16], const float2 (&l)[16], int n, int k0, int k1, int c,
+                                  float q0, float q1, float q2, float q3) {
   if (n == 2 && k0 >= 0 && k1 >= 0) {
     switch (k0 * 4 + k1) {
       case 1: return dgrad_reg2<0, 1>(p, l, q0, q1, q2, q3);
@@ -1648,7 +1714,7 @@ __device__ inline float diag_grad(const float2 (&p)[16], const float2 (&l)[16], 
     }
   }
   int k = -1;
-  float2 e0, e1;
+  float e0 = 0.f, e1 = 0.f;
   if (n == 2 && k0 >= 0) {
     k = k0;
     e0 = (c & 2) ? q2 : q0;
@@ -1663,11 +1729,11 @@ __device__ inline float diag_grad(const float2 (&p)[16], const float2 (&l)[16], 
     e1 = q1;
   }
   if (k < 0) {
-    const float2 f = c == 0 ? q0 : c == 1 ? q1 : c == 2 ? q2 : q3;
+    const float f = c == 0 ? q0 : c == 1 ? q1 : c == 2 ? q2 : q3;
     float g = 0.f;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) g += im_conj_mul(l[r], cmulf(f, p[r]));
-    return g;
+    for (int r = 0; r < 16; ++r) g += im_conj_mul(l[r], p[r]);
+    return f * g;
   }
   switch (k) {
     case 0: return dgrad_reg1<0>(p, l, e0, e1);
@@ -1675,6 +1741,31 @@ __device__ inline float diag_grad(const float2 (&p)[16], const float2 (&l)[16], 
     case 2: return dgrad_reg1<2>(p, l, e0, e1);
     default: return dgrad_reg1<3>(p, l, e0, e1);
   }
+}
+
+// dense generators: c X (gradient c [Im(conj(l0) p1) + Im(conj(l1) p0)]) and Y
+template <int U>
+__device__ __forceinline__ float reg_grad_x(const float2 (&p)[16], const float2 (&l)[16], float c) {
+  float g = 0.f;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    if (r & (1 << U)) continue;
+    const int r1 = r | (1 << U);
+    g += im_conj_mul(l[r], p[r1]) + im_conj_mul(l[r1], p[r]);
+  }
+  return c * g;
+}
+template <int U>
+__device__ __forceinline__ float reg_grad_y(const float2 (&p)[16], const float2 (&l)[16]) {
+  float g = 0.f;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    if (r & (1 << U)) continue;
+    const int r1 = r | (1 << U);
+    // Y p = (-i p1, i p0): Im(conj(l0)(-i p1)) + Im(conj(l1)(i p0)) = -Re(conj(l0) p1) + Re(conj(l1) p0)
+    g += (l[r1].x * p[r].x + l[r1].y * p[r].y) - (l[r].x * p[r1].x + l[r].y * p[r1].y);
+  }
+  return g;
 }
 
 __global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a) {
@@ -1740,12 +1831,17 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a) {
             else if ((k[j] = reg_index(seg, lj)) < 0) c |= ((ob >> lj) & 1) << j;
           }
           const bool two = gd.n == 2;
+          if (gd.form & ADJ_DIAG_SIGNS) {  // Z, CZ: U^dagger = U, entries +-1
+            apply_signs(xp, gd.n, k[0], k[1], c, gd.form >> 8);
+            apply_signs(xl, gd.n, k[0], k[1], c, gd.form >> 8);
+            continue;
+          }
           // U^dagger diagonal: conj(U[b][b])
           const float2 u0 = U[0], u1 = two ? U[5] : U[3], u2 = two ? U[10] : f2(1.f, 0.f),
                        u3 = two ? U[15] : f2(1.f, 0.f);
           if (gd.red >= 0) {
-            const float2 q2 = two ? G[2] : f2(0.f, 0.f), q3 = two ? G[3] : f2(0.f, 0.f);
-            double v = (double)diag_grad(xp, xl, gd.n, k[0], k[1], c, G[0], G[1], q2, q3);
+            const float q2 = two ? G[2].x : 0.f, q3 = two ? G[3].x : 0.f;
+            double v = (double)diag_grad(xp, xl, gd.n, k[0], k[1], c, G[0].x, G[1].x, q2, q3);
             for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
             if (lane == 0) red[gd.red][wv] += v;
           }
@@ -1755,27 +1851,45 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a) {
         } else if (gd.n == 1) {
           if (gd.red >= 0) {
             float g;
-            switch (gd.rb[0]) {
-              case 0: g = reg_grad1<0>(xp, xl, G); break;
-              case 1: g = reg_grad1<1>(xp, xl, G); break;
-              case 2: g = reg_grad1<2>(xp, xl, G); break;
-              default: g = reg_grad1<3>(xp, xl, G); break;
+            if (gd.form == ADJ_GEN_X) {
+              const float cx = G[2].x;
+              switch (gd.rb[0]) {
+                case 0: g = reg_grad_x<0>(xp, xl, cx); break;
+                case 1: g = reg_grad_x<1>(xp, xl, cx); break;
+                case 2: g = reg_grad_x<2>(xp, xl, cx); break;
+                default: g = reg_grad_x<3>(xp, xl, cx); break;
+              }
+            } else if (gd.form == ADJ_GEN_Y) {
+              switch (gd.rb[0]) {
+                case 0: g = reg_grad_y<0>(xp, xl); break;
+                case 1: g = reg_grad_y<1>(xp, xl); break;
+                case 2: g = reg_grad_y<2>(xp, xl); break;
+                default: g = reg_grad_y<3>(xp, xl); break;
+              }
+            } else {
+              switch (gd.rb[0]) {
+                case 0: g = reg_grad1<0>(xp, xl, G); break;
+                case 1: g = reg_grad1<1>(xp, xl, G); break;
+                case 2: g = reg_grad1<2>(xp, xl, G); break;
+                default: g = reg_grad1<3>(xp, xl, G); break;
+              }
             }
             double v = (double)g;
             for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
             if (lane == 0) red[gd.red][wv] += v;
           }
           // U^dagger[m][k] = conj(U[k][m])
+          const bool real = U[0].y == 0.f && U[1].y == 0.f && U[2].y == 0.f && U[3].y == 0.f;
           float2 ud[4];
           ud[0] = f2(U[0].x, -U[0].y);
           ud[1] = f2(U[2].x, -U[2].y);
           ud[2] = f2(U[1].x, -U[1].y);
           ud[3] = f2(U[3].x, -U[3].y);
           switch (gd.rb[0]) {
-            case 0: reg_apply1<TN_PREC_C64, 0>(xp, ud); reg_apply1<TN_PREC_C64, 0>(xl, ud); break;
-            case 1: reg_apply1<TN_PREC_C64, 1>(xp, ud); reg_apply1<TN_PREC_C64, 1>(xl, ud); break;
-            case 2: reg_apply1<TN_PREC_C64, 2>(xp, ud); reg_apply1<TN_PREC_C64, 2>(xl, ud); break;
-            default: reg_apply1<TN_PREC_C64, 3>(xp, ud); reg_apply1<TN_PREC_C64, 3>(xl, ud); break;
+            case 0: reg_apply1<TN_PREC_C64, 0>(xp, ud, real); reg_apply1<TN_PREC_C64, 0>(xl, ud, real); break;
+            case 1: reg_apply1<TN_PREC_C64, 1>(xp, ud, real); reg_apply1<TN_PREC_C64, 1>(xl, ud, real); break;
+            case 2: reg_apply1<TN_PREC_C64, 2>(xp, ud, real); reg_apply1<TN_PREC_C64, 2>(xl, ud, real); break;
+            default: reg_apply1<TN_PREC_C64, 3>(xp, ud, real); reg_apply1<TN_PREC_C64, 3>(xl, ud, real); break;
           }
         } else {
           // dense two-qubit gates carry no gradient term (the planner checks)

@@ -867,7 +867,7 @@ void build_adjoint_plan(const tn_network* net, tn_path* path, const std::vector<
       gd.gate = gi;
       gd.slot = slot_of_gate[gi];
       gd.red = gd.slot >= 0 ? ps.n_red++ : -1;
-      gd.pad = 0;
+      gd.form = ADJ_GENERIC;
       // generator G with g = Im<lambda|G|psi> (the derivative of the gate is -i G / 2 or -i G)
       for (float& x : gd.gen) x = 0.f;
       auto set = [&](int k, float re, float im) { gd.gen[2 * k] = re; gd.gen[2 * k + 1] = im; };
@@ -881,6 +881,13 @@ void build_adjoint_plan(const tn_network* net, tn_path* path, const std::vector<
         default: break;
       }
       if (gd.slot >= 0 && g.gen == GEN_NONE) return;
+      if (gd.slot >= 0 && (g.gen == GEN_X_HALF || g.gen == GEN_X)) gd.form = ADJ_GEN_X;  // gen[2] holds c
+      if (gd.slot >= 0 && g.gen == GEN_Y_HALF) gd.form = ADJ_GEN_Y;
+      // fixed diagonal gates of +-1 entries (Z, CZ) are sign flips
+      const Recipe& rc = net->sweep_recipes[g.recipe];
+      const int kind0 = rc.op_end > rc.op_begin ? net->sweep_ops[rc.op_begin].kind : -1;
+      if (g.diag && gd.slot < 0 && (kind0 == TN_GATE_Z || kind0 == TN_GATE_CZ))
+        gd.form = ADJ_DIAG_SIGNS | ((g.nq == 2 ? 8 : 2) << 8);  // the -1 entry: |11> (b = 3) or |1> (b = 1)
       path->adj_gates.push_back(gd);
     }
     if (ps.n_red > kAdjMaxRed) {
