@@ -140,6 +140,9 @@ typedef struct {
   int32_t n_small_lists;         /* independent work lists of that launch (one workgroup each) */
   int32_t n_sweep_steps;         /* gate-sized steps on one large tensor executed by fused streaming passes */
   int32_t n_sweep_passes;        /* those passes (each reads and writes the tensor once) */
+  int32_t n_product_launches;    /* launches of the steps outside the interpreter and the fused passes, with
+                                    the default launch shapes in complex64: independent per-output products
+                                    that follow each other share a launch */
 } tn_path_stats;
 
 typedef struct tn_network tn_network;
@@ -335,14 +338,16 @@ tn_status tn_path_gemm_config(tn_path* path, int32_t step, int32_t precision, in
                               int32_t* transposed, int32_t set);
 
 /*
- * Kernel timing for measurement.  While enabled, every kernel launch of the
- * entry points above is bracketed by a pair of hipEvents recorded on the
- * launch's own stream, and tagged with the launch's algorithmic work: bytes
- * that must cross HBM (operands read once, result written once) and flops
- * (8 per complex multiply-add).  tn_profile_read synchronises on the recorded
- * events and returns one record per kernel kind (at most `capacity`, returns
- * the number written).  Not thread-safe; enabling it adds an event pair per
- * launch.
+ * Kernel timing for measurement.  While enabled, the kernel launches of the
+ * entry points above are bracketed by hipEvents recorded on the launch's own
+ * stream, and tagged with the launch's algorithmic work: bytes that must
+ * cross HBM (operands read once, result written once) and flops (8 per
+ * complex multiply-add).  Within the steps of a contraction, consecutive
+ * timed launches of one kind share one event pair (an event recorded between
+ * two kernels idles the GPU for a few microseconds); a TN_KERNEL_GEMM_LARGE
+ * product and every other launch get a pair of their own.  tn_profile_read
+ * synchronises on the recorded events and returns one record per kernel kind
+ * (at most `capacity`, returns the number written).  Not thread-safe.
  */
 typedef enum {
   TN_KERNEL_MATERIALIZE = 0, TN_KERNEL_SKINNY = 1, TN_KERNEL_PERMUTE = 2, TN_KERNEL_GEMM = 3,
@@ -354,15 +359,14 @@ typedef enum {
 typedef struct {
   int32_t kind;       /* tn_kernel_kind */
   int64_t launches;
-  double seconds;     /* sum of event-measured launch durations */
+  double seconds;     /* sum of event-measured durations (of single launches or runs of launches) */
   double bytes;       /* sum of algorithmic bytes */
   double flops;       /* sum of algorithmic flops */
 } tn_kernel_profile;
 tn_status tn_profile_enable(int32_t on);
 /* Kernel kinds timed while timing is enabled: bit k for tn_kernel_kind k
- * (default: all).  An event pair costs a few microseconds of queue time per
- * launch, so a measurement of one kind's launches should select that kind
- * alone. */
+ * (default: all).  Every event pair costs a few microseconds of queue time,
+ * so a measurement of one kind's launches should select that kind alone. */
 tn_status tn_profile_select(uint32_t kind_mask);
 int32_t tn_profile_read(tn_kernel_profile* out, int32_t capacity);
 void tn_profile_reset(void);

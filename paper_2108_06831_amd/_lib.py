@@ -48,7 +48,7 @@ class tn_path_stats(ctypes.Structure):
                 ("n_steps", ctypes.c_int32), ("n_permutes", ctypes.c_int32), ("n_gemm_steps", ctypes.c_int32),
                 ("n_skinny_steps", ctypes.c_int32), ("n_small_steps", ctypes.c_int32),
                 ("n_small_lists", ctypes.c_int32), ("n_sweep_steps", ctypes.c_int32),
-                ("n_sweep_passes", ctypes.c_int32)]
+                ("n_sweep_passes", ctypes.c_int32), ("n_product_launches", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

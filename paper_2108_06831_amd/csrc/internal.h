@@ -200,6 +200,21 @@ constexpr int kGemmTileN[kGemmTiles] = {64, 32, 64, 32, 1, 64, 64};
 constexpr int kGemmMaxSplit = 8;
 constexpr int kGemmBK = 16;      // complex k per staged K tile of the MFMA kernels
 constexpr int kElemMaxK = 1024;  // longest K of the per-output kernel
+// Grouped per-output launches: up to kElemGroupMax independent products in one
+// launch, each with a result of at most 2^kElemGroupOutBits elements per batch
+// item and at most 2^kElemKBits summed terms.
+constexpr int kElemGroupMax = 16;
+constexpr int kElemGroupOutBits = 16;
+constexpr int kElemKBits = 10;
+// small gate-sized products (result of at most 2^kElemSkinnyBits elements)
+// become per-output products, which can share a launch
+constexpr int kElemSkinnyBits = 15;
+// A product (bit counts of its result, of A's and B's own indices and of the
+// summed index) that the default launch shape runs on the per-output kernel
+// and that may share a launch with its neighbours.
+inline bool elem_group_shape(int out_bits, int m_bits, int n_bits, int k_bits) {
+  return out_bits <= kElemGroupOutBits && k_bits <= kElemKBits && (m_bits < 6 || n_bits < 5 || k_bits <= 5);
+}
 // default launch shape of a product (before any measurement)
 void gemm_default_launch(const GemmDesc& g, int* tile, int* split);
 
@@ -235,9 +250,19 @@ struct StepProgram {
   SkinnyDesc sk;
   GemmDesc gm[2];       // matrix product as C = A B (0) and as C = B^T A^T (1)
   int32_t orient[2];    // per precision: which of the two runs
+  // steps grp_from..this one are pairwise independent and touch disjoint
+  // workspace ranges where one of them writes (they may run in one launch)
+  int32_t grp_from = -1;
   double flops = 0, bytes = 0;
   int64_t gemm_bmnk[4] = {0, 0, 0, 0};
 };
+
+// a product step the grouped per-output kernel can run at `precision`
+inline bool elem_groupable(const StepProgram& P, int precision) {
+  if (P.kind != SK_GEMM || P.chain != -1 || !P.pre.empty()) return false;
+  const GemmDesc& g = P.gm[P.orient[precision]];
+  return g.tile[precision] == kGemmVector && g.nbb + g.nbm + g.nbn <= kElemGroupOutBits && g.nbk <= kElemKBits;
+}
 
 }  // namespace tnq
 
@@ -282,7 +307,9 @@ tn_status compile_program(const tn_network* net, tn_path* path, const std::vecto
 std::vector<int32_t> output_layout(const tn_network* net);
 // fused passes of the adjoint sweep over the path's final tensor (sets path->adj_state)
 void build_adjoint_plan(const tn_network* net, tn_path* path, const std::vector<int32_t>& slot_of_gate);
-// moves every step that is small and depends only on inputs or such steps to the front
+// moves every step that is small and depends only on inputs or such steps to the
+// front; of the rest, likely per-output products that are ready together are
+// placed next to each other
 std::vector<int32_t> reorder_small_first(const tn_network* net, const std::vector<int32_t>& pairs, int* n_small,
                                          int64_t* small_region);
 // network.cpp

@@ -39,6 +39,28 @@ hipError_t launch_gemm(hipStream_t s, const GemmDesc& d, int tile, int split, co
                        const float2* b, int64_t b_bs, float2* c, int64_t c_bs, float2* tmp, int64_t tmp_bs, int batch,
                        int precision);
 
+// Several independent per-output products in one launch.  Member i owns
+// blocks [block0_i, block0_{i+1}); result element o (per batch item) has bit j
+// at position co[j] of C and reads A at ao[j] and B at bo[j] (-1: absent),
+// summed bit j at A position ak[j] and B position bk[j].
+struct ElemMember {
+  const float2* A;
+  const float2* B;
+  float2* C;
+  int64_t a_bs, b_bs, c_bs;  // strides between parameter vectors
+  int32_t block0;
+  int32_t out_bits;  // 2^out_bits result elements per batch item
+  int32_t k_bits;    // 2^k_bits summed terms
+  int32_t pad;
+  int8_t ao[kElemGroupOutBits], bo[kElemGroupOutBits], co[kElemGroupOutBits];
+  int8_t ak[kElemKBits], bk[kElemKBits];
+};
+struct ElemGroupArgs {
+  int32_t n, total_blocks;
+  ElemMember m[kElemGroupMax];
+};
+hipError_t launch_elem_group(hipStream_t s, const ElemGroupArgs& a, int batch, int precision);
+
 // Expectation of a diagonal Z-string observable: out[z] = sum_x |psi_z[x]|^2 D(x),
 // FP64 accumulation (block partials + a fixed-order second pass).
 constexpr int kMaxTerms = 128;

@@ -239,6 +239,8 @@ __device__ inline int packed_byte(uint32_t w0, uint32_t w1, uint32_t w2, int j) 
   return (int)(int8_t)(x >> (8 * (j & 3)));
 }
 
+constexpr int kStageInFlight = 8;  // operand loads each interpreter thread issues before it waits
+
 template <int PREC>
 __global__ __launch_bounds__(kThreads) void k_small_steps(const SmallStep* steps, const int32_t* list_off,
                                                           const int32_t* level_off, float2* in, int64_t in_bs,
@@ -279,18 +281,30 @@ __global__ __launch_bounds__(kThreads) void k_small_steps(const SmallStep* steps
         const int stage_end = last.stage_b + (1 << last.b_bits);
         const int total = last.out0 + (1 << last.c_bits);
         // stage the operands: one flat loop over the round's operand elements,
-        // so that every thread's loads are independent of each other
-        for (int e = threadIdx.x; e < stage_end; e += kThreads) {
-          int lo = r0, hi = r1 - 1;  // the step owning staged element e
-          while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (desc_c[mid].stage_a <= e) lo = mid; else hi = mid - 1;
+        // every thread keeping kStageInFlight independent loads in flight
+        for (int e0 = threadIdx.x; e0 < stage_end; e0 += kStageInFlight * kThreads) {
+          float2 v[kStageInFlight];
+#pragma unroll
+          for (int u = 0; u < kStageInFlight; ++u) {
+            const int e = e0 + u * kThreads;
+            if (e >= stage_end) break;
+            int lo = r0, hi = r1 - 1;  // the step owning staged element e
+            while (lo < hi) {
+              const int mid = (lo + hi + 1) >> 1;
+              if (desc_c[mid].stage_a <= e) lo = mid; else hi = mid - 1;
+            }
+            const SmallStep& st = desc_c[lo];
+            const bool is_a = e < st.stage_b;
+            const float2* src = is_a ? (st.a_buf == BUF_IN ? IN : WS) + st.a_off + (e - st.stage_a)
+                                     : (st.b_buf == BUF_IN ? IN : WS) + st.b_off + (e - st.stage_b);
+            v[u] = *src;
           }
-          const SmallStep& st = desc_c[lo];
-          const bool is_a = e < st.stage_b;
-          const float2* src = is_a ? (st.a_buf == BUF_IN ? IN : WS) + st.a_off + (e - st.stage_a)
-                                   : (st.b_buf == BUF_IN ? IN : WS) + st.b_off + (e - st.stage_b);
-          stage[e] = *src;
+#pragma unroll
+          for (int u = 0; u < kStageInFlight; ++u) {
+            const int e = e0 + u * kThreads;
+            if (e >= stage_end) break;
+            stage[e] = v[u];
+          }
         }
         __syncthreads();
         // the current step's index maps, packed in registers
@@ -821,10 +835,16 @@ struct GemmArgs {
   int8_t c_b[kGemmMaxBits], c_m[kGemmMaxBits], c_n[kGemmMaxBits];
 };
 
+// Unrolled to the maximum map length: the positions sit in the kernel's
+// argument block at constant offsets, so they are read with scalar loads
+// issued together, not one dependent vector load per bit.
 __device__ inline int64_t deposit(int64_t x, const int8_t* pos, int nbits) {
   int64_t r = 0;
-  for (int j = 0; j < nbits; ++j)
-    if ((x >> j) & 1) r |= (int64_t)1 << pos[j];
+#pragma unroll
+  for (int j = 0; j < kGemmMaxBits; ++j) {
+    if (j >= nbits) break;
+    r |= ((x >> j) & 1) << pos[j];
+  }
   return r;
 }
 
@@ -1304,9 +1324,107 @@ __global__ __launch_bounds__(kThreads) void k_contract_elem(GemmArgs g) {
     const int64_t ab = db_a | deposit(m, g.a_m, g.nbm);
     const int64_t bb = db_b | deposit(n, g.b_n, g.nbn);
     float2 acc = f2(0.f, 0.f);
-    for (int k = 0; k < K; ++k) acc = cmac<PREC>(acc, A[ab | TKa[k]], B[bb | TKb[k]]);
+    int k = 0;
+    // eight operand pairs in flight at a time (the loads do not wait on the sum)
+    for (; k + 8 <= K; k += 8) {
+      float2 av[8], bv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        av[u] = A[ab | TKa[k + u]];
+        bv[u] = B[bb | TKb[k + u]];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc = cmac<PREC>(acc, av[u], bv[u]);
+    }
+    for (; k < K; ++k) acc = cmac<PREC>(acc, A[ab | TKa[k]], B[bb | TKb[k]]);
     C[deposit(b, g.c_b, g.nbb) | deposit(m, g.c_m, g.nbm) | deposit(n, g.c_n, g.nbn)] = acc;
   }
+}
+
+// Grouped form of the per-output products: every member's address maps are
+// turned into LDS tables (three 6-bit chunks of the result index, one table of
+// summed offsets per operand), so an output costs nine table reads before its
+// sum.
+template <int PREC>
+__global__ __launch_bounds__(kThreads) void k_elem_group(ElemGroupArgs g) {
+  __shared__ int64_t TO[3 * 3 * 64];  // [operand A, B, C][chunk][chunk value]
+  __shared__ int64_t TKa[kElemMaxK], TKb[kElemMaxK];
+  const int bx = blockIdx.x, z = blockIdx.y;
+  int mi = 0;
+  for (int i = 1; i < g.n; ++i)
+    if (bx >= g.m[i].block0) mi = i;
+  const ElemMember& e = g.m[mi];
+  const int nblk = (mi + 1 < g.n ? g.m[mi + 1].block0 : g.total_blocks) - e.block0;
+  const int ob = e.out_bits, kb = e.k_bits;
+  for (int t = threadIdx.x; t < 3 * 3 * 64; t += kThreads) {
+    const int map = t / 192, ch = (t >> 6) % 3, x = t & 63;
+    const int8_t* pos = map == 0 ? e.ao : map == 1 ? e.bo : e.co;
+    int64_t r = 0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const int bit = ch * 6 + j;
+      if (bit < ob && ((x >> j) & 1)) {
+        const int p = pos[bit];
+        if (p >= 0) r |= (int64_t)1 << p;
+      }
+    }
+    TO[t] = r;
+  }
+  const int K = 1 << kb;
+  for (int k = threadIdx.x; k < K; k += kThreads) {
+    int64_t ra = 0, rb = 0;
+#pragma unroll
+    for (int j = 0; j < kElemKBits; ++j)
+      if (j < kb && ((k >> j) & 1)) {
+        ra |= (int64_t)1 << e.ak[j];
+        rb |= (int64_t)1 << e.bk[j];
+      }
+    TKa[k] = ra;
+    TKb[k] = rb;
+  }
+  __syncthreads();
+  const float2* A = e.A + (int64_t)z * e.a_bs;
+  const float2* B = e.B + (int64_t)z * e.b_bs;
+  float2* C = e.C + (int64_t)z * e.c_bs;
+  const int n_out = 1 << ob;
+  for (int o = (bx - e.block0) * kThreads + threadIdx.x; o < n_out; o += nblk * kThreads) {
+    const int c0 = o & 63, c1 = 64 + ((o >> 6) & 63), c2 = 128 + ((o >> 12) & 63);
+    const int64_t ab = TO[c0] | TO[c1] | TO[c2];
+    const int64_t bb = TO[192 + c0] | TO[192 + c1] | TO[192 + c2];
+    const int64_t cc = TO[384 + c0] | TO[384 + c1] | TO[384 + c2];
+    float2 acc = f2(0.f, 0.f);
+    int k = 0;
+    for (; k + 8 <= K; k += 8) {
+      float2 av[8], bv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        av[u] = A[ab | TKa[k + u]];
+        bv[u] = B[bb | TKb[k + u]];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc = cmac<PREC>(acc, av[u], bv[u]);
+    }
+    for (; k < K; ++k) acc = cmac<PREC>(acc, A[ab | TKa[k]], B[bb | TKb[k]]);
+    C[cc] = acc;
+  }
+}
+
+hipError_t launch_elem_group(hipStream_t s, const ElemGroupArgs& a, int batch, int precision) {
+  if (a.n < 1 || a.n > kElemGroupMax || batch < 1) return hipErrorInvalidValue;
+  ElemGroupArgs g = a;
+  int32_t blocks = 0;  // one thread per result element
+  for (int i = 0; i < g.n; ++i) {
+    ElemMember& m = g.m[i];
+    if (m.out_bits < 0 || m.out_bits > kElemGroupOutBits || m.k_bits < 0 || m.k_bits > kElemKBits)
+      return hipErrorInvalidValue;
+    m.block0 = blocks;
+    blocks += (int32_t)((((int64_t)1 << m.out_bits) + kThreads - 1) / kThreads);
+  }
+  g.total_blocks = blocks;
+  const void* fn = precision == TN_PREC_BF16X3 ? (const void*)k_elem_group<TN_PREC_BF16X3>
+                                               : (const void*)k_elem_group<TN_PREC_C64>;
+  void* args[] = {&g};
+  return hipLaunchKernel(fn, dim3((unsigned)blocks, batch), dim3(kThreads), args, 0, s);
 }
 
 // C[i] = sum over s of partial[s][i] (split-K), contiguous per parameter vector

@@ -20,6 +20,7 @@
 #include <thread>
 #include <cmath>
 #include <map>
+#include <set>
 #include <algorithm>
 #include <string>
 #include <vector>
@@ -151,19 +152,22 @@ std::vector<int32_t> reorder_small_first(const tn_network* net, const std::vecto
     modes[t] = net->tensors[t].modes;
     for (int m : modes[t]) { holders[m]++; lsz[t] += net->mode_log2[m]; }
   }
-  std::vector<char> small(S, 0), early(S, 0);
+  std::vector<char> small(S, 0), early(S, 0), groupable(S, 0);
   for (int s = 0; s < S; ++s) {
     const int a = pairs[2 * s], b = pairs[2 * s + 1];
     auto in = [](const std::vector<int32_t>& v, int m) { return std::find(v.begin(), v.end(), m) != v.end(); };
     std::vector<int32_t> cm;
-    int f = 0;
+    int f = 0, kb = 0, mb = 0, nb = 0;
     for (int m : modes[a]) {
       f += net->mode_log2[m];
       const bool sh = in(modes[b], m);
-      if (is_out[m] || holders[m] > (sh ? 2 : 1)) cm.push_back(m);
+      const bool kept = is_out[m] || holders[m] > (sh ? 2 : 1);
+      if (kept) cm.push_back(m);
+      if (sh && !kept) kb += net->mode_log2[m];
+      if (!sh) mb += net->mode_log2[m];
     }
     for (int m : modes[b])
-      if (!in(modes[a], m)) { f += net->mode_log2[m]; cm.push_back(m); }
+      if (!in(modes[a], m)) { f += net->mode_log2[m]; nb += net->mode_log2[m]; cm.push_back(m); }
     for (int m : modes[a]) holders[m]--;
     for (int m : modes[b]) holders[m]--;
     for (int m : cm) holders[m]++;
@@ -172,6 +176,8 @@ std::vector<int32_t> reorder_small_first(const tn_network* net, const std::vecto
     small[s] = lsz[a] <= kSmallMaxBits && lsz[b] <= kSmallMaxBits && lsz[T + s] <= kSmallMaxBits &&
                f <= kSmallMaxMacLog2 && (f - lsz[T + s]) <= kSmallMaxBits;
     early[s] = small[s] && (a < T || early[a - T]) && (b < T || early[b - T]);
+    // a likely per-output product (narrow result side, short sum) with a small result
+    groupable[s] = elem_group_shape(lsz[T + s], mb, nb, kb);
   }
   std::vector<int> order;
   for (int s = 0; s < S; ++s)
@@ -179,8 +185,39 @@ std::vector<int32_t> reorder_small_first(const tn_network* net, const std::vecto
   *n_small = (int)order.size();
   *small_region = 0;
   for (int s : order) *small_region += ((((int64_t)1 << lsz[T + s]) + 31) & ~(int64_t)31);
+  // the rest in path order, except that next to a likely per-output product
+  // the other such products that are ready at the same time move up, so that
+  // one launch can run them together
+  std::vector<int> pending(S, 0);  // operands not yet available
+  std::vector<int> consumer(T + S, -1);
   for (int s = 0; s < S; ++s)
-    if (!early[s]) order.push_back(s);
+    for (int k = 0; k < 2; ++k) {
+      const int id = pairs[2 * s + k];
+      consumer[id] = s;
+      if (id >= T && !early[id - T]) pending[s]++;
+    }
+  std::set<int> ready;
+  for (int s = 0; s < S; ++s)
+    if (!early[s] && pending[s] == 0) ready.insert(s);
+  auto emit = [&](int s) {
+    order.push_back(s);
+    ready.erase(s);
+    const int c = consumer[T + s];
+    if (c >= 0 && --pending[c] == 0) ready.insert(c);
+  };
+  while (!ready.empty()) {
+    const int s = *ready.begin();
+    if (!groupable[s]) {
+      emit(s);
+      continue;
+    }
+    std::vector<int> mates;  // ready now, so independent of s and of each other
+    for (int t : ready)
+      if (t != s && groupable[t] && (int)mates.size() + 1 < kElemGroupMax) mates.push_back(t);
+    emit(s);
+    for (int t : mates) emit(t);
+  }
+  if ((int)order.size() != S) return pairs;  // not a tree over the inputs: keep the path order
   std::vector<int> newid(T + S);
   for (int t = 0; t < T; ++t) newid[t] = t;
   for (int i = 0; i < S; ++i) newid[T + order[i]] = T + i;
@@ -325,6 +362,16 @@ tn_status compile_program(const tn_network* net, tn_path* path, const std::vecto
   for (int t = 0; t < T; ++t)
     for (int m : modes[t]) holders[m]++;
 
+  // workspace ranges each step reads and writes (for grouping steps into one launch)
+  struct Foot {
+    BufRef rd[2], wr[2];
+    int64_t n_rd[2] = {0, 0}, n_wr[2] = {0, 0};
+  };
+  std::vector<Foot> foot(S);
+  std::vector<std::pair<int64_t, int64_t>> deferred;  // frees held back until the current run ends
+  std::vector<int> run;
+  std::vector<char> in_run(S, 0);
+  int run_len = 0;
   Alloc alloc;
   alloc.top = alloc.peak = path->small_region;  // [0, small_region): results of the interpreter's steps
   int64_t small_bump = 0;
@@ -342,6 +389,10 @@ tn_status compile_program(const tn_network* net, tn_path* path, const std::vecto
     Loc& A = loc[ia];
     Loc& B = loc[ib];
     StepProgram& P = path->steps[s];
+    foot[s].rd[0] = A.ref;
+    foot[s].rd[1] = B.ref;
+    foot[s].n_rd[0] = A.elems;
+    foot[s].n_rd[1] = B.elems;
     // ---- classify modes
     std::map<int, int> mcls;
     auto in = [](const std::vector<int32_t>& v, int m) { return std::find(v.begin(), v.end(), m) != v.end(); };
@@ -382,6 +433,29 @@ tn_status compile_program(const tn_network* net, tn_path* path, const std::vecto
     const int nk = nbits[C_K], nm = nbits[g_only], nb = nbits[C_BATCH];
     Loc& C = loc[ic];
     C.elems = c_elems;
+    const bool skinny_kind = g_bits <= kSkinnyMaxG && nk <= kSkinnyMaxK && nm <= kSkinnyMaxM &&
+                             c_elems > ((int64_t)1 << kElemSkinnyBits);
+    // products that may share a launch with the run before them: what they
+    // free stays reserved until the run ends, so no member overwrites another's operand
+    const bool cand = s >= path->n_small && !skinny_kind &&
+                      elem_group_shape(nbits[C_BATCH] + nbits[C_M] + nbits[C_N], nbits[C_M], nbits[C_N], nbits[C_K]);
+    {
+      bool joins = cand && run_len > 0 && run_len < kElemGroupMax;
+      for (int k = 0; k < 2 && joins; ++k)
+        if (path->pairs[2 * s + k] >= T && in_run[path->pairs[2 * s + k] - T]) joins = false;
+      if (!joins) {
+        for (const auto& f : deferred) alloc.put(f.first, f.second);
+        deferred.clear();
+        for (int m : run) in_run[m] = 0;
+        run.clear();
+        run_len = 0;
+      }
+      if (cand) {
+        run.push_back(s);
+        in_run[s] = 1;
+        ++run_len;
+      }
+    }
     if (s < path->n_small) {
       P.kind = SK_SMALL;
       // C's layout: the large operand's, with a gate-sized operand's output bits at the summed
@@ -429,7 +503,7 @@ tn_status compile_program(const tn_network* net, tn_path* path, const std::vecto
           ++j;
         }
       d.k_bits = j;
-    } else if (g_bits <= kSkinnyMaxG && nk <= kSkinnyMaxK && nm <= kSkinnyMaxM) {
+    } else if (skinny_kind) {
       P.kind = SK_SKINNY;
       st.n_skinny_steps++;
       SkinnyDesc& d = P.sk;
@@ -611,6 +685,12 @@ tn_status compile_program(const tn_network* net, tn_path* path, const std::vecto
       P.gemm_bmnk[1] = P.gm[0].M;
       P.gemm_bmnk[2] = P.gm[0].N;
     }
+    foot[s].wr[0] = C.ref;
+    foot[s].n_wr[0] = C.elems;
+    if (P.kind == SK_GEMM && P.gm[0].max_split > 1) {
+      foot[s].wr[1] = P.gm[0].tmp;
+      foot[s].n_wr[1] = (int64_t)std::max(P.gm[0].max_split, P.gm[1].max_split) * C.elems;
+    }
     // ---- bookkeeping
     for (int m : modes[ia]) holders[m]--;
     for (int m : modes[ib]) holders[m]--;
@@ -625,7 +705,10 @@ tn_status compile_program(const tn_network* net, tn_path* path, const std::vecto
     for (Loc* X : {&A, &B})
       if (!X->input && X->last_use == s && X->ref.buf == BUF_WS) {
         // buffers of the interpreter's results are released only once the interpreter has run
-        if (s >= path->n_small) alloc.put(X->ref.off, X->elems);
+        if (s >= path->n_small) {
+          if (cand) deferred.emplace_back(X->ref.off, X->elems);
+          else alloc.put(X->ref.off, X->elems);
+        }
         X->ref.buf = -1;
       }
     if (s == path->n_small - 1) {
@@ -729,6 +812,37 @@ tn_status compile_program(const tn_network* net, tn_path* path, const std::vecto
       if (d.ka[j] < 0 || d.ka[j] >= abits || d.kb[j] < 0 || d.kb[j] >= bbits)
         return set_error(TN_EINVAL, "internal: bad small-step summed bits");
   }
+  // steps that may share a launch: pairwise independent, and no step writes a
+  // workspace range another one reads or writes
+  {
+    auto overlap = [](const BufRef& x, int64_t nx, const BufRef& y, int64_t ny) {
+      return nx > 0 && ny > 0 && x.buf == y.buf && x.off < y.off + ny && y.off < x.off + nx;
+    };
+    auto compatible = [&](int i, int j) {
+      for (int k = 0; k < 2; ++k)
+        if (path->pairs[2 * j + k] == T + i || path->pairs[2 * i + k] == T + j) return false;
+      const Foot &fi = foot[i], &fj = foot[j];
+      for (int w = 0; w < 2; ++w)
+        for (int k = 0; k < 2; ++k)
+          if (overlap(fi.wr[w], fi.n_wr[w], fj.rd[k], fj.n_rd[k]) ||
+              overlap(fj.wr[w], fj.n_wr[w], fi.rd[k], fi.n_rd[k]) ||
+              overlap(fi.wr[w], fi.n_wr[w], fj.wr[k], fj.n_wr[k]))
+            return false;
+      return true;
+    };
+    for (int s = path->n_small; s < S; ++s) {
+      StepProgram& P = path->steps[s];
+      P.grp_from = s;
+      if (P.kind != SK_GEMM) continue;
+      for (int g = s - 1; g >= path->n_small && s - g < kElemGroupMax; --g) {
+        if (path->steps[g].kind != SK_GEMM) break;
+        bool ok = true;
+        for (int t = g + 1; t <= s && ok; ++t) ok = compatible(g, t);
+        if (!ok) break;
+        P.grp_from = g;
+      }
+    }
+  }
   // independent sub-trees of the interpreter's steps -> one work list each
   path->small_steps.clear();
   path->small_lists.clear();
@@ -796,6 +910,21 @@ tn_status compile_program(const tn_network* net, tn_path* path, const std::vecto
     }
   }
   build_chains(path, T);
+  st.n_product_launches = 0;
+  for (int s = path->n_small, run0 = -1, run_len = 0; s < S; ++s) {
+    const StepProgram& P = path->steps[s];
+    if (P.chain != -1) {
+      run0 = -1;
+      continue;
+    }
+    if (elem_groupable(P, TN_PREC_C64) && run0 >= 0 && P.grp_from <= run0 && run_len < kElemGroupMax) {
+      ++run_len;
+    } else {
+      st.n_product_launches++;
+      run0 = elem_groupable(P, TN_PREC_C64) ? s : -1;
+      run_len = 1;
+    }
+  }
   st.n_sweep_steps = st.n_sweep_passes = 0;
   for (const SweepChain& ch : path->chains) {
     st.n_sweep_steps += ch.n_steps;
@@ -912,7 +1041,10 @@ void build_adjoint_plan(const tn_network* net, tn_path* path, const std::vector<
 
 void gemm_default_launch(const GemmDesc& g, int* tile, int* split) {
   *split = 1;
-  if ((g.M < 64 || g.N < 32) && g.K <= kElemMaxK) {
+  // narrow products, and small ones with a short sum (latency-bound either way;
+  // on the per-output kernel they can share a launch)
+  if (((g.M < 64 || g.N < 32) && g.K <= kElemMaxK) ||
+      (g.batch * g.M * g.N <= ((int64_t)1 << kElemGroupOutBits) && g.K <= 32)) {
     *tile = kGemmVector;
     return;
   }
@@ -950,9 +1082,17 @@ double modeled_seconds(const tn_path* path) {
       // measured: about 20 vector instructions per element and gate on 64 lanes per CU
       t += kLaunch + 16.0 * e / kHbm + 16.0 * e * ps.n_segs / kLds + 5.0e-13 * e * ps.n_gates;
     }
-  for (const StepProgram& P : path->steps) {
+  int run0 = -1, run_len = 0;  // current run of products that share one launch
+  for (int s = 0; s < (int)path->steps.size(); ++s) {
+    const StepProgram& P = path->steps[s];
     if (P.kind == SK_SMALL || P.chain != -1) continue;
-    t += kLaunch;
+    if (elem_groupable(P, TN_PREC_C64) && run0 >= 0 && P.grp_from <= run0 && run_len < kElemGroupMax) {
+      ++run_len;  // joins the previous launch
+    } else {
+      t += kLaunch;
+      run0 = elem_groupable(P, TN_PREC_C64) ? s : -1;
+      run_len = 1;
+    }
     for (const PermuteDesc& pd : P.pre) t += kLaunch + 16.0 * std::ldexp(1.0, pd.bits) / kPerm;
     if (P.kind == SK_SKINNY) {
       t += P.bytes / kHbm;

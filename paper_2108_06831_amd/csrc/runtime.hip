@@ -39,7 +39,8 @@ struct ProfRec {
   int kind;
   hipEvent_t a, b;
   double bytes, flops;
-  bool owner;  // the record that returns a and b to the pool (a launch may be counted under two kinds)
+  int launches;  // timed launches between a and b
+  bool owner;    // the record that returns a and b to the pool (a launch may be counted under two kinds)
 };
 static bool g_prof = false;
 static uint32_t g_prof_mask = ~0u;  // kernel kinds timed while enabled
@@ -59,8 +60,45 @@ static hipEvent_t pool_event() {
   return e;
 }
 
-static hipEvent_t prof_start(hipStream_t s, int kind) {
-  if (!g_prof || !((g_prof_mask >> kind) & 1u)) return nullptr;
+// Every event recorded between two kernels leaves the GPU idle for a few
+// microseconds.  Inside a contraction, consecutive timed launches of one kind
+// therefore share one event pair (a run, closed by the next launch of another
+// kind or by the end of the steps); a large product keeps a pair of its own.
+static bool g_coalesce = false;
+static bool g_run_open = false;
+static ProfRec g_run;
+static hipEvent_t const kRunMember = reinterpret_cast<hipEvent_t>(&g_run);  // prof_start's token for a run member
+
+static bool large_product(double bytes, double flops) { return flops >= 1e9 && flops >= 40.0 * bytes; }
+
+static void prof_close_run(hipStream_t s) {
+  if (!g_run_open) return;
+  g_run_open = false;
+  hipEvent_t b = pool_event();
+  if (!b) {
+    g_pool.push_back(g_run.a);
+    return;
+  }
+  (void)hipEventRecord(b, s);
+  g_run.b = b;
+  g_recs.push_back(g_run);
+}
+
+// own_pair: time this launch alone even inside a run
+static hipEvent_t prof_start(hipStream_t s, int kind, bool own_pair = false) {
+  const bool timed = g_prof && ((g_prof_mask >> kind) & 1u);
+  if (g_run_open && (!timed || own_pair || g_run.kind != kind)) prof_close_run(s);
+  if (!timed) return nullptr;
+  if (g_coalesce && !own_pair) {
+    if (!g_run_open) {
+      hipEvent_t e = pool_event();
+      if (!e) return nullptr;
+      (void)hipEventRecord(e, s);
+      g_run = ProfRec{kind, e, nullptr, 0.0, 0.0, 0, true};
+      g_run_open = true;
+    }
+    return kRunMember;
+  }
   hipEvent_t e = pool_event();
   if (e) (void)hipEventRecord(e, s);
   return e;
@@ -68,13 +106,19 @@ static hipEvent_t prof_start(hipStream_t s, int kind) {
 
 static void prof_stop(hipStream_t s, hipEvent_t a, int kind, double bytes, double flops) {
   if (!a) return;
+  if (a == kRunMember) {
+    g_run.bytes += bytes;
+    g_run.flops += flops;
+    g_run.launches += 1;
+    return;
+  }
   hipEvent_t b = pool_event();
   if (!b) return;
   (void)hipEventRecord(b, s);
-  g_recs.push_back(ProfRec{kind, a, b, bytes, flops, true});
+  g_recs.push_back(ProfRec{kind, a, b, bytes, flops, 1, true});
   // products that are large by flops and intensity are also tallied on their own
-  if (kind == TN_KERNEL_GEMM && flops >= 1e9 && flops >= 40.0 * bytes)
-    g_recs.push_back(ProfRec{TN_KERNEL_GEMM_LARGE, a, b, bytes, flops, false});
+  if (kind == TN_KERNEL_GEMM && large_product(bytes, flops))
+    g_recs.push_back(ProfRec{TN_KERNEL_GEMM_LARGE, a, b, bytes, flops, 1, false});
 }
 
 // ---------------------------------------------------------------------------
@@ -256,7 +300,18 @@ static float2* resolve(const Bases& b, const BufRef& r, int64_t* bs) {
   }
 }
 
-static tn_status run_steps(hipStream_t s, tn_path* path, const Bases& B, int batch, int precision) {
+// End (exclusive) of the run of products starting at step si that share one
+// launch of the grouped per-output kernel (si + 1: si runs alone).
+static size_t group_end(const tn_path* path, size_t si, int precision) {
+  size_t e = si + 1;
+  if (!elem_groupable(path->steps[si], precision)) return e;
+  while (e < path->steps.size() && e - si < (size_t)kElemGroupMax && elem_groupable(path->steps[e], precision) &&
+         path->steps[e].grp_from <= (int)si)
+    ++e;
+  return e;
+}
+
+static tn_status run_steps_body(hipStream_t s, tn_path* path, const Bases& B, int batch, int precision) {
   DevPath* dp = nullptr;
   if (path->n_small > 0 || !path->chains.empty()) {
     tn_status st = ensure_path_device(path, &dp);
@@ -326,6 +381,61 @@ static tn_status run_steps(hipStream_t s, tn_path* path, const Bases& B, int bat
       HIP_TRY(launch_skinny(s, P.sk, g, gbs, t, tbs, c, cbs, batch, precision));
       prof_stop(s, ev, TN_KERNEL_SKINNY, 8.0 * batch * (ge + te + ce), P.flops * batch);
     } else {
+      {
+        const size_t e = group_end(path, si, precision);
+        if (e - si >= 2) {
+          ElemGroupArgs ga;
+          ga.n = (int32_t)(e - si);
+          double bytes = 0, flops = 0;
+          for (size_t t = si; t < e; ++t) {
+            const StepProgram& Q = path->steps[t];
+            const GemmDesc& d = Q.gm[Q.orient[precision]];
+            ElemMember& m = ga.m[t - si];
+            int64_t abs_, bbs, cbs;
+            m.A = resolve(B, d.a, &abs_);
+            m.B = resolve(B, d.b, &bbs);
+            m.C = resolve(B, d.c, &cbs);
+            if (t + 1 == path->steps.size() && B.final_out) {
+              m.C = B.final_out;
+              cbs = B.final_out_bs;
+            }
+            m.a_bs = abs_;
+            m.b_bs = bbs;
+            m.c_bs = cbs;
+            m.out_bits = d.nbb + d.nbm + d.nbn;
+            m.k_bits = d.nbk;
+            m.pad = 0;
+            // result index bits: n lowest, then m, then batch
+            for (int j = 0; j < kElemGroupOutBits; ++j) {
+              m.ao[j] = m.bo[j] = m.co[j] = -1;
+              if (j < d.nbn) {
+                m.bo[j] = d.b_n[j];
+                m.co[j] = d.c_n[j];
+              } else if (j < d.nbn + d.nbm) {
+                m.ao[j] = d.a_m[j - d.nbn];
+                m.co[j] = d.c_m[j - d.nbn];
+              } else if (j < m.out_bits) {
+                m.ao[j] = d.a_b[j - d.nbn - d.nbm];
+                m.bo[j] = d.b_b[j - d.nbn - d.nbm];
+                m.co[j] = d.c_b[j - d.nbn - d.nbm];
+              }
+            }
+            for (int j = 0; j < kElemKBits; ++j) {
+              m.ak[j] = j < d.nbk ? d.a_k[j] : 0;
+              m.bk[j] = j < d.nbk ? d.b_k[j] : 0;
+            }
+            m.block0 = 0;  // laid out by the launcher
+            bytes += 8.0 * batch * (double)d.batch * (double)(d.M * d.K + d.K * d.N + d.M * d.N);
+            flops += Q.flops * batch;
+          }
+          ga.total_blocks = 0;
+          hipEvent_t ev = prof_start(s, TN_KERNEL_GEMM);
+          HIP_TRY(launch_elem_group(s, ga, batch, precision));
+          prof_stop(s, ev, TN_KERNEL_GEMM, bytes, flops);
+          si = e - 1;
+          continue;
+        }
+      }
       int64_t abs_, bbs, cbs;
       const GemmDesc& g = P.gm[P.orient[precision]];
       float2* a = resolve(B, g.a, &abs_);
@@ -338,13 +448,21 @@ static tn_status run_steps(hipStream_t s, tn_path* path, const Bases& B, int bat
         c = B.final_out;  // the last product writes the caller's output directly
         cbs = B.final_out_bs;
       }
-      hipEvent_t ev = prof_start(s, TN_KERNEL_GEMM);
+      hipEvent_t ev = prof_start(s, TN_KERNEL_GEMM, large_product(bytes, P.flops * batch));
       HIP_TRY(launch_gemm(s, g, g.tile[precision], g.split[precision], a, abs_, b, bbs, c, cbs, tmp, tbs, batch,
                           precision));
       prof_stop(s, ev, TN_KERNEL_GEMM, bytes, P.flops * batch);
     }
   }
   return TN_OK;
+}
+
+static tn_status run_steps(hipStream_t s, tn_path* path, const Bases& B, int batch, int precision) {
+  g_coalesce = true;
+  const tn_status st = run_steps_body(s, path, B, batch, precision);
+  prof_close_run(s);
+  g_coalesce = false;
+  return st;
 }
 
 static tn_status materialize(hipStream_t s, tn_network* net, DevNet* d, const double* params, int batch,
@@ -475,7 +593,7 @@ extern "C" int32_t tn_profile_read(tn_kernel_profile* out, int32_t capacity) {
   for (ProfRec& r : g_recs) {
     float ms = 0.f;
     if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
-      acc[r.kind].launches += 1;
+      acc[r.kind].launches += r.launches;
       acc[r.kind].seconds += 1e-3 * ms;
       acc[r.kind].bytes += r.bytes;
       acc[r.kind].flops += r.flops;
@@ -869,6 +987,15 @@ extern "C" tn_status tn_autotune(void* stream, int32_t precision, tn_network* ne
   HIP_TRY(hipEventCreateWithFlags(&e1, hipEventDisableSystemFence));
   tn_tune_report rep{0, 0, 0.0, 0.0};
   tn_status result = TN_OK;
+  // products that share a launch keep their shape: alone, another shape would
+  // have to save more than the launch it adds
+  std::vector<char> grouped(path->steps.size(), 0);
+  for (size_t si = path->n_small; si < path->steps.size();) {
+    const size_t e = group_end(path, si, precision);
+    if (e - si >= 2)
+      for (size_t t = si; t < e; ++t) grouped[t] = 1;
+    si = e;
+  }
   for (size_t si = 0; si < path->steps.size() && result == TN_OK; ++si) {
     StepProgram& P = path->steps[si];
     if (P.kind != SK_GEMM || P.chain != -1) continue;
@@ -899,7 +1026,7 @@ extern "C" tn_status tn_autotune(void* stream, int32_t precision, tn_network* ne
     rep.n_products++;
     rep.seconds_before += best;
     int bo = o0, bt = t0, bs = s0;
-    for (int o = 0; o < 2 && result == TN_OK; ++o)
+    for (int o = 0; o < 2 && result == TN_OK && !grouped[si]; ++o)
       for (int tile = 0; tile < kGemmTiles && result == TN_OK; ++tile)
         for (int split = 1; split <= kGemmMaxSplit; split *= 2) {
           const GemmDesc& g = P.gm[o];

@@ -174,3 +174,32 @@ def test_autotune_keeps_results():
     got = contract_path(net, path)
     torch.cuda.synchronize()
     assert relerr(got.cpu().numpy()[0], want) < C64_TOL
+
+
+def test_profile_counts_every_launch():
+    """Kernel timing with runs of product launches sharing one event pair:
+    every product launch (a launch may run several grouped products) is
+    counted once and the products' algorithmic flops in full, whether all
+    kinds or the products alone are timed, and the results are unchanged."""
+    import torch
+    from paper_2108_06831_amd import contract_path, profile_enable, profile_read, profile_reset, profile_select
+    circ, net, path = _bw16_path()
+    want = oracle.statevector(circ)
+    n_gemm = len(path.gemm_configs())
+    flops = sum(8.0 * np.prod(path.step(s)["bmnk"]) for s in path.gemm_configs())
+    for kinds in (None, ["gemm"]):
+        profile_reset()
+        profile_select(kinds)
+        profile_enable(True)
+        got = contract_path(net, path)
+        prof = profile_read()
+        profile_enable(False)
+        profile_select(None)
+        print(kinds, {k: (v["launches"], round(v["seconds"] * 1e6, 1)) for k, v in prof.items()}, flush=True)
+        assert prof["gemm"]["launches"] == path.stats["n_product_launches"] <= n_gemm
+        assert prof["gemm"]["flops"] == pytest.approx(flops, rel=1e-12)
+        assert prof["gemm"]["seconds"] > 0
+        if kinds is not None:
+            assert set(prof) <= {"gemm", "gemm_large"}
+        torch.cuda.synchronize()
+        assert relerr(got.cpu().numpy()[0], want) < C64_TOL

@@ -347,3 +347,46 @@ def test_config2_full_size_sampled_amplitudes(precision):
     err = relerr(got[idx], want)
     print(f"config2 {precision}: sampled amplitude rel err {err:.2e}", flush=True)
     assert err < (C64_TOL if precision == "c64" else BF16X3_TOL)
+
+
+@pytest.mark.parametrize("precision,tol", [("c64", C64_TOL), ("bf16x3", BF16X3_TOL)])
+def test_grouped_products(precision, tol):
+    """Independent per-output products sharing launches (the batched outer
+    products of a 4x6 grid's amplitude network): the launch count equals the
+    planned one and is below the product count, results match the oracle, and
+    moving one member to a matrix-core tile (which splits its group) changes
+    nothing."""
+    import torch
+    from paper_2108_06831_amd import Network, amplitudes, profile_enable, profile_read, profile_reset, profile_select
+    circ, bits = workloads.config2(4, 6, 12, n_bitstrings=4096)
+    net = Network.from_circuit(circ, output="amplitudes", n_bitstrings=4096)
+    path = net.plan("greedy", max_log2_intermediate=30)
+    st = path.stats
+    n_products = st["n_gemm_steps"] + st["n_skinny_steps"]
+    print(f"products {n_products}, planned launches {st['n_product_launches']}", flush=True)
+    assert st["n_product_launches"] < n_products
+    want = oracle.amplitudes(oracle.statevector(circ), circ.n_qubits, bits)
+    profile_reset()
+    profile_select(["gemm", "skinny"])
+    profile_enable(True)
+    got = amplitudes(net, path, bits, precision=precision).cpu().numpy()
+    prof = profile_read()
+    profile_enable(False)
+    profile_select(None)
+    launches = sum(prof[k]["launches"] for k in ("gemm", "skinny") if k in prof)
+    print(f"  launches {launches}, rel err {relerr(got, want):.2e}", flush=True)
+    if precision == "c64":
+        assert launches == st["n_product_launches"]
+    assert relerr(got, want) < tol
+    # a member of the first group on an MFMA tile: the group splits around it
+    elem = [s for s, (t, sp, tr) in path.gemm_configs(precision).items() if t == 4]
+    s = elem[len(elem) // 2]
+    for tile in (3, 2, 1, 0):
+        try:
+            path.set_gemm_config(s, tile, 1, 0, precision)
+            break
+        except Exception:
+            continue
+    got2 = amplitudes(net, path, bits, precision=precision).cpu().numpy()
+    torch.cuda.synchronize()
+    assert relerr(got2, want) < tol

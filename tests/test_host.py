@@ -274,3 +274,20 @@ def test_gemm_launch_shape_get_set():
     non_gemm = next(s for s in range(path.stats["n_steps"]) if s not in shapes)
     with pytest.raises(TNError):
         path.gemm_config(non_gemm)
+
+
+def test_grouped_launch_plan():
+    """Planning places independent per-output products next to each other so
+    that they share launches: the 32-qubit amplitude network's batched outer
+    products go from one launch each to a few grouped launches, and the
+    statevector network's small products also group."""
+    import workloads
+    from paper_2108_06831_amd import Network
+    circ, bits = workloads.config2()
+    net = Network.from_circuit(circ, output="amplitudes", n_bitstrings=len(bits))
+    st = net.plan("greedy", max_log2_intermediate=28).stats
+    n = st["n_gemm_steps"] + st["n_skinny_steps"]
+    print(n, st["n_product_launches"])
+    assert st["n_product_launches"] <= n // 2
+    st1 = Network.from_circuit(workloads.config1(), fuse="split").plan("greedy").stats
+    assert st1["n_product_launches"] < st1["n_gemm_steps"] + st1["n_skinny_steps"]
