@@ -237,7 +237,14 @@ struct SmallStep {
   // of its first output among the round's outputs, and (on a round's first
   // step) the index, within the level's chunk, one past the round's last step
   int32_t stage_a, stage_b, out0, round_end;
+  // on a round's first step: the round's work items (kSmallItem*), one per
+  // thread, small_items[item0 .. item0 + n_items)
+  int32_t item0, n_items, pad2[2];
 };
+// A work item of the interpreter: `count` consecutive outputs of one step of
+// the round, packed as step (index in the level's chunk, 8 bits) | first
+// output << 8 (12 bits) | (count - 1) << 20 (12 bits).
+constexpr int kSmallMaxItems = 512;  // per round: at most two per thread
 static_assert(sizeof(SmallStep) % 16 == 0, "SmallStep is copied in 16-byte words");
 
 enum StepKind { SK_SKINNY = 0, SK_GEMM = 1, SK_SMALL = 2 };
@@ -281,6 +288,7 @@ struct tn_path {
   std::vector<tnq::SmallStep> small_steps;   // grouped by work list, and by level inside a list
   std::vector<int32_t> small_lists;          // list w owns levels small_lists[w] .. small_lists[w+1]-1
   std::vector<int32_t> small_levels;         // level i owns steps small_levels[i] .. small_levels[i+1]-1
+  std::vector<uint32_t> small_items;         // work items of every round (see SmallStep::item0)
   int64_t small_region = 0;                  // workspace elements reserved for their results
   // fused streaming chains
   std::vector<tnq::SweepChain> chains;

@@ -77,10 +77,11 @@ hipError_t launch_expectation(hipStream_t s, const float2* psi, int64_t psi_bs, 
 
 // Interpreter of small steps: work list w (levels list_off[w] .. list_off[w+1]-1,
 // level i = steps level_off[i] .. level_off[i+1]-1, each depending only on
-// inputs or on earlier levels of the same list) runs in workgroup (w, batch item).
+// inputs or on earlier levels of the same list) runs in workgroup (w, batch item);
+// items: the rounds' work items (SmallStep::item0).
 hipError_t launch_small_steps(hipStream_t s, const SmallStep* steps, const int32_t* list_off,
-                              const int32_t* level_off, int n_lists, float2* in, int64_t in_bs, float2* ws,
-                              int64_t ws_bs, int batch, int precision);
+                              const int32_t* level_off, const uint32_t* items, int n_lists, float2* in,
+                              int64_t in_bs, float2* ws, int64_t ws_bs, int batch, int precision);
 
 // One fused streaming pass over a 2^bits tensor (see SweepPass).
 hipError_t launch_sweep_pass(hipStream_t s, const SweepPass& ps, int bits, const SweepGateDesc* gates_dev,

@@ -243,8 +243,8 @@ constexpr int kStageInFlight = 8;  // operand loads each interpreter thread issu
 
 template <int PREC>
 __global__ __launch_bounds__(kThreads) void k_small_steps(const SmallStep* steps, const int32_t* list_off,
-                                                          const int32_t* level_off, float2* in, int64_t in_bs,
-                                                          float2* ws, int64_t ws_bs) {
+                                                          const int32_t* level_off, const uint32_t* items,
+                                                          float2* in, int64_t in_bs, float2* ws, int64_t ws_bs) {
   __shared__ __attribute__((aligned(16))) SmallStep desc[kSmallDescCache];
   __shared__ __attribute__((aligned(16))) float2 stage[kSmallStage];
   const int w = blockIdx.x, z = blockIdx.y;
@@ -279,7 +279,10 @@ __global__ __launch_bounds__(kThreads) void k_small_steps(const SmallStep* steps
         const int r1 = desc_c[r0].round_end;
         const SmallStep& last = desc_c[r1 - 1];
         const int stage_end = last.stage_b + (1 << last.b_bits);
-        const int total = last.out0 + (1 << last.c_bits);
+        // this thread's work items, fetched while the operands are staged
+        const int it0 = desc_c[r0].item0, nit = desc_c[r0].n_items;
+        const uint32_t my0 = (int)threadIdx.x < nit ? items[it0 + threadIdx.x] : 0u;
+        const uint32_t my1 = (int)threadIdx.x + kThreads < nit ? items[it0 + threadIdx.x + kThreads] : 0u;
         // stage the operands: one flat loop over the round's operand elements,
         // every thread keeping kStageInFlight independent loads in flight
         for (int e0 = threadIdx.x; e0 < stage_end; e0 += kStageInFlight * kThreads) {
@@ -307,52 +310,50 @@ __global__ __launch_bounds__(kThreads) void k_small_steps(const SmallStep* steps
           }
         }
         __syncthreads();
-        // the current step's index maps, packed in registers
-        int cur = -1, kbits = 0, a0 = 0, b0 = 0;
-        uint32_t ap0 = 0, ap1 = 0, ap2 = 0, bp0 = 0, bp1 = 0, bp2 = 0;
-        uint32_t ka0 = 0, ka1 = 0, ka2 = 0, kb0 = 0, kb1 = 0, kb2 = 0;
-        float2* C = nullptr;
-        for (int g = threadIdx.x; g < total; g += kThreads) {
-          int lo = r0, hi = r1 - 1;  // the step owning output g
-          while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (desc_c[mid].out0 <= g) lo = mid; else hi = mid - 1;
-          }
-          if (lo != cur) {
-            const SmallStep& st = desc_c[lo];
-            const uint32_t* ap = reinterpret_cast<const uint32_t*>(st.apos);
-            const uint32_t* bp = reinterpret_cast<const uint32_t*>(st.bpos);
-            const uint32_t* ka = reinterpret_cast<const uint32_t*>(st.ka);
-            const uint32_t* kb = reinterpret_cast<const uint32_t*>(st.kb);
-            ap0 = ap[0]; ap1 = ap[1]; ap2 = ap[2];
-            bp0 = bp[0]; bp1 = bp[1]; bp2 = bp[2];
-            ka0 = ka[0]; ka1 = ka[1]; ka2 = ka[2];
-            kb0 = kb[0]; kb1 = kb[1]; kb2 = kb[2];
-            kbits = st.k_bits;
-            a0 = st.stage_a;
-            b0 = st.stage_b;
-            C = (st.c_buf == BUF_IN ? IN : WS) + st.c_off;
-            cur = lo;
-          }
-          const int o = g - desc_c[lo].out0;
+        // each item: consecutive outputs of one step; the operand addresses of
+        // the first come from the step's index maps (packed in registers), the
+        // next ones by flipping the address bits of the output bits that change
+        for (int q = 0; q < 2; ++q) {
+          if ((int)threadIdx.x + q * kThreads >= nit) break;
+          const uint32_t wd = q == 0 ? my0 : my1;
+          const SmallStep& st = desc_c[wd & 255u];
+          const int o0 = (int)((wd >> 8) & 4095u), o1 = o0 + (int)(wd >> 20) + 1;
+          const uint32_t* ap = reinterpret_cast<const uint32_t*>(st.apos);
+          const uint32_t* bp = reinterpret_cast<const uint32_t*>(st.bpos);
+          const uint32_t* ka = reinterpret_cast<const uint32_t*>(st.ka);
+          const uint32_t* kb = reinterpret_cast<const uint32_t*>(st.kb);
+          const uint32_t ap0 = ap[0], ap1 = ap[1], ap2 = ap[2], bp0 = bp[0], bp1 = bp[1], bp2 = bp[2];
+          const uint32_t ka0 = ka[0], ka1 = ka[1], ka2 = ka[2], kb0 = kb[0], kb1 = kb[1], kb2 = kb[2];
+          const int nk = 1 << st.k_bits;
+          const float2* As = stage + st.stage_a;
+          const float2* Bs = stage + st.stage_b;
+          float2* C = (st.c_buf == BUF_IN ? IN : WS) + st.c_off;
           int ab = 0, bb = 0;
-          for (uint32_t m = (uint32_t)o; m; m &= m - 1) {
+          for (uint32_t m = (uint32_t)o0; m; m &= m - 1) {
             const int p = __builtin_ctz(m);
             const int pa = packed_byte(ap0, ap1, ap2, p), pb = packed_byte(bp0, bp1, bp2, p);
             if (pa >= 0) ab |= 1 << pa;
             if (pb >= 0) bb |= 1 << pb;
           }
-          // summed index in Gray-code order: one address bit flips per term
-          const float2* As = stage + a0;
-          const float2* Bs = stage + b0;
-          float2 acc = cmac<PREC>(f2(0.f, 0.f), As[ab], Bs[bb]);
-          for (int k = 1; k < (1 << kbits); ++k) {
-            const int j = __builtin_ctz(k);
-            ab ^= 1 << packed_byte(ka0, ka1, ka2, j);
-            bb ^= 1 << packed_byte(kb0, kb1, kb2, j);
-            acc = cmac<PREC>(acc, As[ab], Bs[bb]);
+          for (int o = o0; o < o1; ++o) {
+            if (o != o0)
+              for (uint32_t f = (uint32_t)(o ^ (o - 1)); f; f &= f - 1) {
+                const int p = __builtin_ctz(f);
+                const int pa = packed_byte(ap0, ap1, ap2, p), pb = packed_byte(bp0, bp1, bp2, p);
+                if (pa >= 0) ab ^= 1 << pa;
+                if (pb >= 0) bb ^= 1 << pb;
+              }
+            // summed index in Gray-code order: one address bit flips per term
+            int a = ab, b = bb;
+            float2 acc = cmac<PREC>(f2(0.f, 0.f), As[a], Bs[b]);
+            for (int k = 1; k < nk; ++k) {
+              const int j = __builtin_ctz(k);
+              a ^= 1 << packed_byte(ka0, ka1, ka2, j);
+              b ^= 1 << packed_byte(kb0, kb1, kb2, j);
+              acc = cmac<PREC>(acc, As[a], Bs[b]);
+            }
+            C[o] = acc;
           }
-          C[o] = acc;
         }
         __syncthreads();
         r0 = r1;
@@ -362,15 +363,15 @@ __global__ __launch_bounds__(kThreads) void k_small_steps(const SmallStep* steps
 }
 
 hipError_t launch_small_steps(hipStream_t s, const SmallStep* steps, const int32_t* list_off,
-                              const int32_t* level_off, int n_lists, float2* in, int64_t in_bs, float2* ws,
-                              int64_t ws_bs, int batch, int precision) {
+                              const int32_t* level_off, const uint32_t* items, int n_lists, float2* in,
+                              int64_t in_bs, float2* ws, int64_t ws_bs, int batch, int precision) {
   if (n_lists == 0) return hipSuccess;
   if (precision == TN_PREC_BF16X3)
     hipLaunchKernelGGL(k_small_steps<TN_PREC_BF16X3>, dim3(n_lists, batch), dim3(kThreads), 0, s, steps, list_off,
-                       level_off, in, in_bs, ws, ws_bs);
+                       level_off, items, in, in_bs, ws, ws_bs);
   else
     hipLaunchKernelGGL(k_small_steps<TN_PREC_C64>, dim3(n_lists, batch), dim3(kThreads), 0, s, steps, list_off,
-                       level_off, in, in_bs, ws, ws_bs);
+                       level_off, items, in, in_bs, ws, ws_bs);
   return hipGetLastError();
 }
 

@@ -872,6 +872,7 @@ tn_status compile_program(const tn_network* net, tn_path* path, const std::vecto
     std::map<int, std::vector<int>> trees;
     for (int s = 0; s < path->n_small; ++s) trees[root[s]].push_back(s);
     path->small_levels.clear();
+    path->small_items.clear();
     path->small_lists.push_back(0);
     for (auto& kv : trees) {
       std::vector<int> lst = kv.second;
@@ -900,10 +901,47 @@ tn_status compile_program(const tn_network* net, tn_path* path, const std::vecto
             d.stage_b = used + (1 << d.a_bits);
             d.out0 = outs;
             d.round_end = 0;
+            d.item0 = d.n_items = d.pad2[0] = d.pad2[1] = 0;
             used += need;
             outs += 1 << d.c_bits;
           }
           path->small_steps[r0].round_end = i - cb;
+          // work items: about equal work (outputs times summed terms, plus the
+          // store) per thread, each a run of consecutive outputs of one step
+          int64_t total = 0;
+          for (int q = r0; q < i; ++q) {
+            const SmallStep& d = path->small_steps[q];
+            total += ((int64_t)1 << d.c_bits) * (((int64_t)1 << d.k_bits) + 4);
+          }
+          for (int64_t target = std::max<int64_t>(1, (total + 255) / 256);; target *= 2) {
+            std::vector<uint32_t> items;
+            for (int q = r0; q < i; ++q) {
+              const SmallStep& d = path->small_steps[q];
+              const int64_t outs = (int64_t)1 << d.c_bits, per = ((int64_t)1 << d.k_bits) + 4;
+              const int64_t run = std::min<int64_t>(outs, std::max<int64_t>(1, target / per));
+              for (int64_t o = 0; o < outs; o += run) {
+                const int64_t cnt = std::min(run, outs - o);
+                items.push_back((uint32_t)(q - cb) | ((uint32_t)o << 8) | ((uint32_t)(cnt - 1) << 20));
+              }
+            }
+            if ((int)items.size() <= kSmallMaxItems) {
+              // every output of every step of the round exactly once, in range
+              std::vector<int64_t> covered(i - r0, 0);
+              for (uint32_t it : items) {
+                const int q = (int)(it & 255u) + cb, o = (int)((it >> 8) & 4095u), cnt = (int)(it >> 20) + 1;
+                if (q < r0 || q >= i || o + cnt > (1 << path->small_steps[q].c_bits))
+                  return set_error(TN_EINVAL, "internal: bad interpreter work item");
+                covered[q - r0] += cnt;
+              }
+              for (int q = r0; q < i; ++q)
+                if (covered[q - r0] != ((int64_t)1 << path->small_steps[q].c_bits))
+                  return set_error(TN_EINVAL, "internal: interpreter work items miss outputs");
+              path->small_steps[r0].item0 = (int32_t)path->small_items.size();
+              path->small_steps[r0].n_items = (int32_t)items.size();
+              path->small_items.insert(path->small_items.end(), items.begin(), items.end());
+              break;
+            }
+          }
           r0 = i;
         }
       }

@@ -204,6 +204,7 @@ struct DevPath {
   SmallStep* steps = nullptr;
   int32_t* lists = nullptr;
   int32_t* levels = nullptr;
+  uint32_t* items = nullptr;
   SweepGateDesc* sweep_gates = nullptr;
   SweepSegment* segments = nullptr;
   AdjGateDesc* adj_gates = nullptr;     // uploaded on the first backward call
@@ -222,6 +223,7 @@ static tn_status ensure_path_device(tn_path* path, DevPath** out) {
   HIP_TRY(upload(&d->steps, path->small_steps));
   HIP_TRY(upload(&d->lists, path->small_lists));
   HIP_TRY(upload(&d->levels, path->small_levels));
+  HIP_TRY(upload(&d->items, path->small_items));
   HIP_TRY(upload(&d->sweep_gates, path->sweep_gates));
   HIP_TRY(upload(&d->segments, path->segments));
   *out = d;
@@ -237,6 +239,7 @@ void device_release_path(tn_path* path) {
   (void)hipFree(d->steps);
   (void)hipFree(d->lists);
   (void)hipFree(d->levels);
+  (void)hipFree(d->items);
   (void)hipFree(d->sweep_gates);
   (void)hipFree(d->segments);
   (void)hipFree(d->adj_gates);
@@ -326,8 +329,8 @@ static tn_status run_steps_body(hipStream_t s, tn_path* path, const Bases& B, in
     float2* wp = resolve(B, rw, &wbs);
     if (B.pair_a) return set_error(TN_EINVAL, "internal: interpreter steps in a single pairwise contraction");
     hipEvent_t ev = prof_start(s, TN_KERNEL_INTERP);
-    HIP_TRY(launch_small_steps(s, dp->steps, dp->lists, dp->levels, (int)path->small_lists.size() - 1, ip, ibs, wp,
-                               wbs, batch, precision));
+    HIP_TRY(launch_small_steps(s, dp->steps, dp->lists, dp->levels, dp->items, (int)path->small_lists.size() - 1, ip,
+                               ibs, wp, wbs, batch, precision));
     double fl = 0, by = 0;
     for (int i = 0; i < path->n_small; ++i) { fl += path->steps[i].flops; by += path->steps[i].bytes; }
     prof_stop(s, ev, TN_KERNEL_INTERP, by * batch, fl * batch);
