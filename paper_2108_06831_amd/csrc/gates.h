@@ -104,55 +104,113 @@ struct Recipe {
   int64_t offset;      // element offset of the tensor in the per-batch input buffer
 };
 
-// d x d matrix (d = 2^nq) of a recipe, FP64.
-__host__ __device__ inline void recipe_matrix(const Recipe& r, const RecipeOp* ops, const double* mats,
-                                              const double* params, c128* M) {
-  const int d = r.nq == 2 ? 4 : 2;
-  for (int i = 0; i < d * d; ++i) M[i] = cm((i / d) == (i % d) ? 1.0 : 0.0, 0.0);
+// Every array below is indexed by compile-time constants only (loops over
+// fixed extents, unrolled; run-time choices made by selects), so that on the
+// device the matrices stay in registers instead of per-thread scratch memory.
+
+// The elementary matrix of one recipe op (16 entries, 2x2 or 4x4 row-major).
+__host__ __device__ inline void op_matrix(const RecipeOp& op, const double* mats, const double* params, c128* u) {
+  double ang[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) ang[j] = op.param[j] >= 0 ? params[op.param[j]] : op.angle[j];
+  if (op.kind == TN_GATE_MATRIX1 || op.kind == TN_GATE_MATRIX2) {
+    const int n = op.kind == TN_GATE_MATRIX2 ? 16 : 4;
+    const double* m = mats + 32 * op.mat;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) u[i] = i < n ? cm(m[2 * i], m[2 * i + 1]) : cm(0, 0);
+  } else {
+    gate_matrix(op.kind, ang, u);
+  }
+}
+
+// M <- G M for the 4x4 block matrix M, G = a one-qubit u on block qubit POS
+// (0: the first, more significant qubit).
+template <int POS>
+__host__ __device__ inline void left_apply1_at(const c128* u, c128* M) {
+  c128 T[16];
+#pragma unroll
+  for (int x = 0; x < 4; ++x) {
+    const int xa = x >> 1, xb = x & 1;
+    const int r = POS ? xb : xa;                                    // row of u
+    const int y0 = POS ? 4 * (2 * xa) : 4 * xb, y1 = POS ? 4 * (2 * xa + 1) : 4 * (2 + xb);  // rows of M
+#pragma unroll
+    for (int j = 0; j < 4; ++j) T[4 * x + j] = cadd(cmul(u[2 * r], M[y0 + j]), cmul(u[2 * r + 1], M[y1 + j]));
+  }
+#pragma unroll
+  for (int i = 0; i < 16; ++i) M[i] = T[i];
+}
+
+__host__ __device__ inline void left_apply1(const c128* u, int pos, c128* M) {
+  if (pos) left_apply1_at<1>(u, M); else left_apply1_at<0>(u, M);
+}
+
+// a two-qubit u in the block's qubit order (POS 0) or reversed (POS 1)
+template <int POS>
+__host__ __device__ inline void block_two_qubit_at(const c128* u, c128* G) {
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+      const int xs = POS ? ((x & 1) << 1) | (x >> 1) : x, ys = POS ? ((y & 1) << 1) | (y >> 1) : y;
+      G[4 * x + y] = u[4 * xs + ys];
+    }
+}
+
+__host__ __device__ inline void block_two_qubit(const c128* u, int pos, c128* G) {
+  if (pos) block_two_qubit_at<1>(u, G); else block_two_qubit_at<0>(u, G);
+}
+
+// d x d matrix (d = 2^nq = D) of a recipe, FP64; get_u(o, u) gives op o's
+// elementary matrix.
+template <int D, class GetU>
+__host__ __device__ inline void recipe_matrix_dg(const Recipe& r, const RecipeOp* ops, GetU get_u, c128* M) {
+#pragma unroll
+  for (int i = 0; i < D * D; ++i) M[i] = cm((i / D) == (i % D) ? 1.0 : 0.0, 0.0);
   for (int o = r.op_begin; o < r.op_end; ++o) {
     const RecipeOp& op = ops[o];
-    double ang[3];
-    for (int j = 0; j < 3; ++j) ang[j] = op.param[j] >= 0 ? params[op.param[j]] : op.angle[j];
     c128 u[16];
-    if (op.kind == TN_GATE_MATRIX1 || op.kind == TN_GATE_MATRIX2) {
-      const int du = op.kind == TN_GATE_MATRIX2 ? 4 : 2;
-      for (int i = 0; i < du * du; ++i) u[i] = cm(mats[32 * op.mat + 2 * i], mats[32 * op.mat + 2 * i + 1]);
-    } else {
-      gate_matrix(op.kind, ang, u);
-    }
-    // embed into the block: G (d x d)
-    c128 G[16];
-    const bool two = gate_is_two_qubit(op.kind);
-    if (d == 2) {
-      for (int i = 0; i < 4; ++i) G[i] = u[i];
-    } else if (two) {
-      for (int x = 0; x < 4; ++x)
-        for (int y = 0; y < 4; ++y) {
-          int xs = op.pos ? ((x & 1) << 1) | (x >> 1) : x;
-          int ys = op.pos ? ((y & 1) << 1) | (y >> 1) : y;
-          G[4 * x + y] = u[4 * xs + ys];
+    get_u(o, u);
+    if (D == 2) {
+      c128 T[4];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) T[2 * i + j] = cadd(cmul(u[2 * i], M[j]), cmul(u[2 * i + 1], M[2 + j]));
+#pragma unroll
+      for (int i = 0; i < 4; ++i) M[i] = T[i];
+    } else if (gate_is_two_qubit(op.kind)) {
+      c128 G[16], T[16];
+      block_two_qubit(u, op.pos, G);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          c128 acc = cm(0, 0);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) acc = cadd(acc, cmul(G[4 * i + k], M[4 * k + j]));
+          T[4 * i + j] = acc;
         }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) M[i] = T[i];
     } else {
-      for (int x = 0; x < 4; ++x)
-        for (int y = 0; y < 4; ++y) {
-          int xa = x >> 1, xb = x & 1, ya = y >> 1, yb = y & 1;
-          c128 v = cm(0, 0);
-          if (op.pos == 0) {
-            if (xb == yb) v = u[2 * xa + ya];
-          } else {
-            if (xa == ya) v = u[2 * xb + yb];
-          }
-          G[4 * x + y] = v;
-        }
+      left_apply1(u, op.pos, M);
     }
-    c128 T[16];
-    for (int i = 0; i < d; ++i)
-      for (int j = 0; j < d; ++j) {
-        c128 acc = cm(0, 0);
-        for (int k = 0; k < d; ++k) acc = cadd(acc, cmul(G[d * i + k], M[d * k + j]));
-        T[d * i + j] = acc;
-      }
-    for (int i = 0; i < d * d; ++i) M[i] = T[i];
+  }
+}
+
+template <int D>
+__host__ __device__ inline void recipe_matrix_d(const Recipe& r, const RecipeOp* ops, const double* mats,
+                                                const double* params, c128* M) {
+  recipe_matrix_dg<D>(r, ops, [&](int o, c128* u) { op_matrix(ops[o], mats, params, u); }, M);
+}
+
+// d x d matrix (d = 2^nq) of a recipe into M[0 .. d*d), FP64.
+__host__ __device__ inline void recipe_matrix(const Recipe& r, const RecipeOp* ops, const double* mats,
+                                              const double* params, c128* M) {
+  if (r.nq == 2) {
+    recipe_matrix_d<4>(r, ops, mats, params, M);
+  } else {
+    recipe_matrix_d<2>(r, ops, mats, params, M);
   }
 }
 
@@ -162,61 +220,76 @@ __host__ __device__ inline void recipe_matrix(const Recipe& r, const RecipeOp* o
 // half on qubit `on` is post . |k><k| . pre and the other half is
 // post . G_k . pre with G_k the 2x2 block of the gate at bond value k (pre/post:
 // the block's one-qubit gates on that side before/after the two-qubit gate).
-// Writes the half on block qubit `side` as the tensor [k][o][i] (8 entries).
-__host__ __device__ inline void recipe_split_half(const Recipe& r, const RecipeOp* ops, const double* mats,
-                                                  const double* params, c128* out) {
+// Writes the half on block qubit `side` as the tensor [k][o][i] (8 entries);
+// get_u(o, u) gives op o's elementary matrix.
+template <class GetU>
+__host__ __device__ inline void recipe_split_half_g(const Recipe& r, const RecipeOp* ops, GetU get_u, c128* out) {
   const int side = r.split_side, on = r.split_on;
-  c128 pre[4], post[4], U[16];
-  for (int i = 0; i < 4; ++i) pre[i] = post[i] = cm((i == 0 || i == 3) ? 1.0 : 0.0, 0.0);
+  // cur: product of this side's one-qubit gates since the two-qubit gate (or
+  // the start); it becomes `pre` when the two-qubit gate arrives
+  c128 cur[4], pre[4], post[4], U[16];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) cur[i] = pre[i] = cm((i == 0 || i == 3) ? 1.0 : 0.0, 0.0);
+#pragma unroll
   for (int i = 0; i < 16; ++i) U[i] = cm((i / 4) == (i % 4) ? 1.0 : 0.0, 0.0);
   bool after = false;
   for (int o = r.op_begin; o < r.op_end; ++o) {
     const RecipeOp& op = ops[o];
-    double ang[3];
-    for (int j = 0; j < 3; ++j) ang[j] = op.param[j] >= 0 ? params[op.param[j]] : op.angle[j];
     c128 u[16];
-    if (op.kind == TN_GATE_MATRIX1 || op.kind == TN_GATE_MATRIX2) {
-      const int du = op.kind == TN_GATE_MATRIX2 ? 4 : 2;
-      for (int i = 0; i < du * du; ++i) u[i] = cm(mats[32 * op.mat + 2 * i], mats[32 * op.mat + 2 * i + 1]);
-    } else {
-      gate_matrix(op.kind, ang, u);
-    }
+    get_u(o, u);
     if (gate_is_two_qubit(op.kind)) {
-      for (int x = 0; x < 4; ++x)
-        for (int y = 0; y < 4; ++y) {
-          const int xs = op.pos ? ((x & 1) << 1) | (x >> 1) : x;
-          const int ys = op.pos ? ((y & 1) << 1) | (y >> 1) : y;
-          U[4 * x + y] = u[4 * xs + ys];
-        }
+      block_two_qubit(u, op.pos, U);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        pre[i] = cur[i];
+        cur[i] = cm((i == 0 || i == 3) ? 1.0 : 0.0, 0.0);
+      }
       after = true;
       continue;
     }
     if (op.pos != side) continue;
-    c128* M = after ? post : pre;
     c128 T[4];
+#pragma unroll
     for (int i = 0; i < 2; ++i)
-      for (int j = 0; j < 2; ++j) T[2 * i + j] = cadd(cmul(u[2 * i], M[j]), cmul(u[2 * i + 1], M[2 + j]));
-    for (int i = 0; i < 4; ++i) M[i] = T[i];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) T[2 * i + j] = cadd(cmul(u[2 * i], cur[j]), cmul(u[2 * i + 1], cur[2 + j]));
+#pragma unroll
+    for (int i = 0; i < 4; ++i) cur[i] = T[i];
   }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const c128 id = cm((i == 0 || i == 3) ? 1.0 : 0.0, 0.0);
+    post[i] = after ? cur[i] : id;
+    pre[i] = after ? pre[i] : cur[i];
+  }
+#pragma unroll
   for (int k = 0; k < 2; ++k) {
     c128 G[4];
+#pragma unroll
     for (int x = 0; x < 2; ++x)
+#pragma unroll
       for (int y = 0; y < 2; ++y) {
-        if (side == on) {
-          G[2 * x + y] = cm((x == k && y == k) ? 1.0 : 0.0, 0.0);
-        } else if (on == 0) {
-          G[2 * x + y] = U[4 * (2 * k + x) + (2 * k + y)];
-        } else {
-          G[2 * x + y] = U[4 * (2 * x + k) + (2 * y + k)];
-        }
+        const c128 own = cm((x == k && y == k) ? 1.0 : 0.0, 0.0);
+        const c128 g0 = U[4 * (2 * k + x) + (2 * k + y)], g1 = U[4 * (2 * x + k) + (2 * y + k)];
+        G[2 * x + y] = side == on ? own : (on == 0 ? g0 : g1);
       }
     c128 T[4], V[4];
+#pragma unroll
     for (int i = 0; i < 2; ++i)
+#pragma unroll
       for (int j = 0; j < 2; ++j) T[2 * i + j] = cadd(cmul(G[2 * i], pre[j]), cmul(G[2 * i + 1], pre[2 + j]));
+#pragma unroll
     for (int i = 0; i < 2; ++i)
+#pragma unroll
       for (int j = 0; j < 2; ++j) V[2 * i + j] = cadd(cmul(post[2 * i], T[j]), cmul(post[2 * i + 1], T[2 + j]));
+#pragma unroll
     for (int i = 0; i < 4; ++i) out[4 * k + i] = V[i];
   }
+}
+
+__host__ __device__ inline void recipe_split_half(const Recipe& r, const RecipeOp* ops, const double* mats,
+                                                  const double* params, c128* out) {
+  recipe_split_half_g(r, ops, [&](int o, c128* u) { op_matrix(ops[o], mats, params, u); }, out);
 }
 
 }  // namespace tnq

@@ -70,30 +70,76 @@ __device__ inline double block_sum(double v, double* red) {
 // ---------------------------------------------------------------------------
 // Materialisation of the network's input tensors
 // ---------------------------------------------------------------------------
-__global__ void k_materialize(const DevTensor* ts, int nt, const Recipe* rs, const RecipeOp* ops, const double* mats,
-                              const double* params, int64_t pstride, float2* in, int64_t in_bs) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+// One block per tensor: the elementary matrices of the tensor's ops (the FP64
+// trigonometry) are evaluated in parallel, one op per thread, into LDS; one
+// thread then multiplies them in order, with the block matrices in registers
+// (every array below is indexed by constants).  Rounded once to complex64.
+constexpr int kRecipeThreads = 64;
+
+template <class GetU>
+__device__ void write_recipe(const Recipe& r, const RecipeOp* ops, GetU get_u, float2* o) {
+  if (r.split_side >= 0) {
+    c128 H[8];
+    recipe_split_half_g(r, ops, get_u, H);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) o[i] = f2((float)H[i].re, (float)H[i].im);
+  } else if (r.nq == 2) {
+    c128 M[16];
+    recipe_matrix_dg<4>(r, ops, get_u, M);
+    if (r.diag) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) o[i] = f2((float)M[5 * i].re, (float)M[5 * i].im);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) o[i] = f2((float)M[i].re, (float)M[i].im);
+    }
+  } else {
+    c128 M[4];
+    recipe_matrix_dg<2>(r, ops, get_u, M);
+    if (r.diag) {
+      o[0] = f2((float)M[0].re, (float)M[0].im);
+      o[1] = f2((float)M[3].re, (float)M[3].im);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) o[i] = f2((float)M[i].re, (float)M[i].im);
+    }
+  }
+}
+
+__global__ __launch_bounds__(kRecipeThreads) void k_materialize(const DevTensor* ts, int nt, const Recipe* rs,
+                                                                const RecipeOp* ops, const double* mats,
+                                                                const double* params, int64_t pstride, float2* in,
+                                                                int64_t in_bs) {
+  __shared__ c128 U[kRecipeThreads][16];
+  const int t = blockIdx.x;
   const int z = blockIdx.y;
   if (t >= nt) return;
   const DevTensor d = ts[t];
   float2* o = in + (int64_t)z * in_bs + d.offset;
   if (d.kind == TK_KET0) {
-    o[0] = f2(1.f, 0.f);
-    o[1] = f2(0.f, 0.f);
+    if (threadIdx.x == 0) {
+      o[0] = f2(1.f, 0.f);
+      o[1] = f2(0.f, 0.f);
+    }
   } else if (d.kind == TK_GATE) {
     const Recipe r = rs[d.recipe];
-    c128 M[16];
-    if (r.split_side >= 0) {
-      recipe_split_half(r, ops, mats, params ? params + (int64_t)z * pstride : nullptr, M);
-      for (int i = 0; i < 8; ++i) o[i] = f2((float)M[i].re, (float)M[i].im);
-      return;
-    }
-    recipe_matrix(r, ops, mats, params ? params + (int64_t)z * pstride : nullptr, M);
-    const int dd = r.nq == 2 ? 4 : 2;
-    if (r.diag) {
-      for (int i = 0; i < dd; ++i) o[i] = f2((float)M[dd * i + i].re, (float)M[dd * i + i].im);
-    } else {
-      for (int i = 0; i < dd * dd; ++i) o[i] = f2((float)M[i].re, (float)M[i].im);
+    const double* p = params ? params + (int64_t)z * pstride : nullptr;
+    const int n = r.op_end - r.op_begin;
+    if (n <= kRecipeThreads) {
+      if ((int)threadIdx.x < n) {
+        c128 u[16];
+        op_matrix(ops[r.op_begin + threadIdx.x], mats, p, u);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) U[threadIdx.x][i] = u[i];
+      }
+      __syncthreads();
+      if (threadIdx.x == 0)
+        write_recipe(r, ops, [&](int op, c128* u) {
+#pragma unroll
+          for (int i = 0; i < 16; ++i) u[i] = U[op - r.op_begin][i];
+        }, o);
+    } else if (threadIdx.x == 0) {
+      write_recipe(r, ops, [&](int op, c128* u) { op_matrix(ops[op], mats, p, u); }, o);
     }
   }
 }
@@ -116,9 +162,8 @@ hipError_t launch_materialize(hipStream_t s, const DevTensor* ts, int nt, const 
                               const double* mats, const double* params, int64_t params_stride, int batch,
                               float2* in, int64_t in_bs) {
   if (nt == 0) return hipSuccess;
-  dim3 grid((nt + 127) / 128, batch);
-  hipLaunchKernelGGL(k_materialize, grid, dim3(128), 0, s, ts, nt, recipes, ops, mats, params, params_stride, in,
-                     in_bs);
+  hipLaunchKernelGGL(k_materialize, dim3(nt, batch), dim3(kRecipeThreads), 0, s, ts, nt, recipes, ops, mats, params,
+                     params_stride, in, in_bs);
   return hipGetLastError();
 }
 
@@ -2130,23 +2175,32 @@ hipError_t launch_gradient_reduce(hipStream_t s, const double* partials, int64_t
   return hipGetLastError();
 }
 
-__global__ void k_sweep_matrices(const Recipe* rs, int n, const RecipeOp* ops, const double* mats,
+__global__ __launch_bounds__(kRecipeThreads) void k_sweep_matrices(const Recipe* rs, int n, const RecipeOp* ops,
+                                                                    const double* mats,
                                  const double* params, int64_t pstride, float2* out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int z = blockIdx.y;
   if (i >= n) return;
-  c128 M[16];
-  recipe_matrix(rs[i], ops, mats, params ? params + (int64_t)z * pstride : nullptr, M);
-  const int d = rs[i].nq == 2 ? 4 : 2;
+  const double* p = params ? params + (int64_t)z * pstride : nullptr;
   float2* o = out + ((int64_t)z * n + i) * 16;
-  for (int k = 0; k < d * d; ++k) o[k] = f2((float)M[k].re, (float)M[k].im);
+  if (rs[i].nq == 2) {
+    c128 M[16];
+    recipe_matrix_d<4>(rs[i], ops, mats, p, M);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) o[k] = f2((float)M[k].re, (float)M[k].im);
+  } else {
+    c128 M[4];
+    recipe_matrix_d<2>(rs[i], ops, mats, p, M);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) o[k] = f2((float)M[k].re, (float)M[k].im);
+  }
 }
 
 hipError_t launch_sweep_matrices(hipStream_t s, const Recipe* recipes, int n, const RecipeOp* ops, const double* mats,
                                  const double* params, int64_t params_stride, int batch, float2* out) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_sweep_matrices, dim3((n + 127) / 128, batch), dim3(128), 0, s, recipes, n, ops, mats, params,
-                     params_stride, out);
+  hipLaunchKernelGGL(k_sweep_matrices, dim3((n + kRecipeThreads - 1) / kRecipeThreads, batch), dim3(kRecipeThreads),
+                     0, s, recipes, n, ops, mats, params, params_stride, out);
   return hipGetLastError();
 }
 
