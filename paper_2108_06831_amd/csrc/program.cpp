@@ -456,6 +456,29 @@ tn_status compile_program(const tn_network* net, tn_path* path, const std::vecto
         ++run_len;
       }
     }
+    // result layout of a gate-sized product, as the streaming kernel writes it:
+    // the large operand's layout with the small operand's own bits at the summed
+    // positions when the counts match, else [G's own bits | T's other bits]
+    const bool skinny_shape = g_bits <= kSkinnyMaxG && nk <= kSkinnyMaxK && nm <= kSkinnyMaxM;
+    auto skinny_layout = [&]() {
+      const int tb = (int)Tt.bits.size();
+      std::vector<int32_t> klab, outer;  // by ascending position in T
+      for (int p = 0; p < tb; ++p) {
+        const int32_t lab = Tt.bits[tb - 1 - p];
+        if (cls[lab] == C_K) klab.push_back(lab); else outer.push_back(lab);
+      }
+      std::vector<int32_t> mlab = filter(G.bits, cls, g_only);
+      std::reverse(mlab.begin(), mlab.end());
+      std::vector<int32_t> out;
+      if (nm == nk) {
+        out = Tt.bits;
+        for (int j = 0; j < nk; ++j) out[tb - 1 - pos_of(Tt.bits, klab[j])] = mlab[j];
+      } else {
+        out.assign(mlab.rbegin(), mlab.rend());
+        out.insert(out.end(), outer.rbegin(), outer.rend());
+      }
+      return out;
+    };
     if (s < path->n_small) {
       P.kind = SK_SMALL;
       // C's layout: the large operand's, with a gate-sized operand's output bits at the summed
@@ -526,20 +549,8 @@ tn_status compile_program(const tn_network* net, tn_path* path, const std::vecto
         d.bt_pos[j] = pos_of(Tt.bits, blab[j]);
       }
       // C layout
-      if (nm == nk) {
-        d.c_mode = 0;
-        C.bits = Tt.bits;
-        for (int j = 0; j < nk; ++j) {
-          int idx = d.t_bits - 1 - d.k_pos[j];
-          C.bits[idx] = mlab[j];
-        }
-      } else {
-        d.c_mode = 1;
-        std::vector<int32_t> top(mlab.rbegin(), mlab.rend());
-        std::vector<int32_t> low(outer.rbegin(), outer.rend());
-        C.bits = top;
-        C.bits.insert(C.bits.end(), low.begin(), low.end());
-      }
+      d.c_mode = nm == nk ? 0 : 1;
+      C.bits = skinny_layout();
       for (int k = 0; k < (1 << nk); ++k) {
         int64_t o = 0;
         for (int j = 0; j < nk; ++j)
@@ -598,6 +609,8 @@ tn_status compile_program(const tn_network* net, tn_path* path, const std::vecto
       // C: the requested output layout for the last step, else [batch | M | N] in the operands' orders
       if (s == S - 1 && final_layout && final_layout->size() == (size_t)nbits[0] + nbits[1] + nbits[2]) {
         C.bits = *final_layout;
+      } else if (skinny_shape) {
+        C.bits = skinny_layout();  // a small gate-sized product keeps the streaming kernel's layout
       } else {
         C.bits = cat(filter(A.bits, cls, C_BATCH), filter(A.bits, cls, C_M), filter(B.bits, cls, C_N));
       }
