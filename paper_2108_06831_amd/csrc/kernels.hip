@@ -659,6 +659,10 @@ __global__ __launch_bounds__(kThreads) void k_sweep_pass(SweepPassArgs a) {
               (((r >> 3) & 1) << seg.rbits[3]);
       x[r] = buf[lds_phys(li[r])];
     }
+    // diagonal factors that are the same for all of a thread's elements (every
+    // bit of the gate outside the register set) commute with every gate of the
+    // segment: they are multiplied into one per-thread factor, applied once
+    float2 ph = f2(1.f, 0.f);
     for (int gi = seg.first_gate; gi < seg.first_gate + seg.n_gates; ++gi) {
       const SweepGateDesc& gd = a.gates[gi];
       const float2* G = (gd.g_buf == BUF_IN ? INz : WSz) + gd.g_off;
@@ -673,7 +677,12 @@ __global__ __launch_bounds__(kThreads) void k_sweep_pass(SweepPassArgs a) {
           if (lj < 0) c |= (int)((base >> (-lj - 1)) & 1) << j;  // outside the chunk
           else if ((k[j] = reg_index(seg, lj)) < 0) c |= ((ob >> lj) & 1) << j;  // a thread bit
         }
-        apply_diag<PREC>(x, gd.n, k[0], k[1], c, d0, d1, d2, d3);
+        if (k[0] < 0 && k[1] < 0) {
+          const float2 f = c == 0 ? d0 : c == 1 ? d1 : c == 2 ? d2 : d3;
+          ph = f2(ph.x * f.x - ph.y * f.y, ph.x * f.y + ph.y * f.x);
+        } else {
+          apply_diag<PREC>(x, gd.n, k[0], k[1], c, d0, d1, d2, d3);
+        }
       } else if (gd.n == 1) {
         float2 g[4];
         for (int e = 0; e < 4; ++e) g[e] = G[gd.gidx[e]];
@@ -698,7 +707,8 @@ __global__ __launch_bounds__(kThreads) void k_sweep_pass(SweepPassArgs a) {
       }
     }
 #pragma unroll
-    for (int r = 0; r < 16; ++r) buf[lds_phys(li[r])] = x[r];
+    for (int r = 0; r < 16; ++r)
+      buf[lds_phys(li[r])] = f2(ph.x * x[r].x - ph.y * x[r].y, ph.x * x[r].y + ph.y * x[r].x);
     __syncthreads();
   }
   for (int i = tid; i < L; i += nt) out[base | (i & 31) | dep_hi[i >> 5]] = buf[lds_phys(i)];
@@ -1981,6 +1991,11 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a) {
         xp[r] = bp[lds_phys(li[r])];
         xl[r] = bl[lds_phys(li[r])];
       }
+      // unit-modulus diagonal factors that are the same for all of a thread's
+      // elements go into one per-thread factor, applied to both states at the
+      // segment's end; they commute with the segment's gates and leave every
+      // gradient term Im<lambda|G|psi> unchanged (|factor|^2 = 1)
+      float2 ph = f2(1.f, 0.f);
       for (int gi = seg.first_gate; gi < seg.first_gate + seg.n_gates; ++gi) {
         const AdjGateDesc& gd = a.gates[gi];
         const float2* U = Uz + (int64_t)gd.gate * 16;
@@ -1995,7 +2010,12 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a) {
             else if ((k[j] = reg_index(seg, lj)) < 0) c |= ((ob >> lj) & 1) << j;
           }
           const bool two = gd.n == 2;
+          const bool uniform = k[0] < 0 && k[1] < 0;  // the same entry for every element of the thread
           if (gd.form & ADJ_DIAG_SIGNS) {  // Z, CZ: U^dagger = U, entries +-1
+            if (uniform) {
+              if (((gd.form >> 8) >> c) & 1) ph = f2(-ph.x, -ph.y);
+              continue;
+            }
             apply_signs(xp, gd.n, k[0], k[1], c, gd.form >> 8);
             apply_signs(xl, gd.n, k[0], k[1], c, gd.form >> 8);
             continue;
@@ -2010,6 +2030,11 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a) {
             if (lane == 0) red[gd.red][wv] += v;
           }
           const float2 d0 = f2(u0.x, -u0.y), d1 = f2(u1.x, -u1.y), d2 = f2(u2.x, -u2.y), d3 = f2(u3.x, -u3.y);
+          if (uniform) {
+            const float2 f = c == 0 ? d0 : c == 1 ? d1 : c == 2 ? d2 : d3;
+            ph = f2(ph.x * f.x - ph.y * f.y, ph.x * f.y + ph.y * f.x);
+            continue;
+          }
           apply_diag<TN_PREC_C64>(xp, gd.n, k[0], k[1], c, d0, d1, d2, d3);
           apply_diag<TN_PREC_C64>(xl, gd.n, k[0], k[1], c, d0, d1, d2, d3);
         } else if (gd.n == 1) {
@@ -2080,8 +2105,8 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a) {
       }
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        bp[lds_phys(li[r])] = xp[r];
-        bl[lds_phys(li[r])] = xl[r];
+        bp[lds_phys(li[r])] = f2(ph.x * xp[r].x - ph.y * xp[r].y, ph.x * xp[r].y + ph.y * xp[r].x);
+        bl[lds_phys(li[r])] = f2(ph.x * xl[r].x - ph.y * xl[r].y, ph.x * xl[r].y + ph.y * xl[r].x);
       }
       __syncthreads();
     }
