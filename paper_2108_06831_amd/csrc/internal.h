@@ -200,11 +200,14 @@ constexpr int kGemmTileN[kGemmTiles] = {64, 32, 64, 32, 1, 64, 64};
 constexpr int kGemmMaxSplit = 8;
 constexpr int kGemmBK = 16;      // complex k per staged K tile of the MFMA kernels
 constexpr int kElemMaxK = 1024;  // longest K of the per-output kernel
-// Grouped per-output launches: up to kElemGroupMax independent products in one
-// launch, each with a result of at most 2^kElemGroupOutBits elements per batch
-// item and at most 2^kElemKBits summed terms.
+// The table-driven per-output kernel (k_elem_group): up to kElemGroupMax
+// independent products in one launch, each with a result of at most
+// 2^kElemGroupOutBits elements per batch item and at most 2^kElemKBits summed
+// terms.  The planner places products with results of at most 2^kElemSmallBits
+// elements side by side so that they can share a launch.
 constexpr int kElemGroupMax = 16;
-constexpr int kElemGroupOutBits = 16;
+constexpr int kElemGroupOutBits = 18;
+constexpr int kElemSmallBits = 16;
 constexpr int kElemKBits = 10;
 // small gate-sized products (result of at most 2^kElemSkinnyBits elements)
 // become per-output products, which can share a launch
@@ -213,7 +216,7 @@ constexpr int kElemSkinnyBits = 15;
 // summed index) that the default launch shape runs on the per-output kernel
 // and that may share a launch with its neighbours.
 inline bool elem_group_shape(int out_bits, int m_bits, int n_bits, int k_bits) {
-  return out_bits <= kElemGroupOutBits && k_bits <= kElemKBits && (m_bits < 6 || n_bits < 5 || k_bits <= 5);
+  return out_bits <= kElemSmallBits && k_bits <= kElemKBits && (m_bits < 6 || n_bits < 5 || k_bits <= 5);
 }
 // default launch shape of a product (before any measurement)
 void gemm_default_launch(const GemmDesc& g, int* tile, int* split);

@@ -60,6 +60,9 @@ struct ElemGroupArgs {
   ElemMember m[kElemGroupMax];
 };
 hipError_t launch_elem_group(hipStream_t s, const ElemGroupArgs& a, int batch, int precision);
+// The member for product d (orientation as given) with operands a, b and result c.
+ElemMember elem_member(const GemmDesc& d, const float2* a, int64_t a_bs, const float2* b, int64_t b_bs, float2* c,
+                       int64_t c_bs);
 
 // Expectation of a diagonal Z-string observable: out[z] = sum_x |psi_z[x]|^2 D(x),
 // FP64 accumulation (block partials + a fixed-order second pass).

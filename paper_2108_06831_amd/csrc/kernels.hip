@@ -1465,6 +1465,41 @@ __global__ __launch_bounds__(kThreads) void k_elem_group(ElemGroupArgs g) {
   }
 }
 
+ElemMember elem_member(const GemmDesc& d, const float2* a, int64_t a_bs, const float2* b, int64_t b_bs, float2* c,
+                       int64_t c_bs) {
+  ElemMember m;
+  m.A = a;
+  m.B = b;
+  m.C = c;
+  m.a_bs = a_bs;
+  m.b_bs = b_bs;
+  m.c_bs = c_bs;
+  m.block0 = 0;  // laid out by the launcher
+  m.out_bits = d.nbb + d.nbm + d.nbn;
+  m.k_bits = d.nbk;
+  m.pad = 0;
+  // result index bits: n lowest, then m, then batch
+  for (int j = 0; j < kElemGroupOutBits; ++j) {
+    m.ao[j] = m.bo[j] = m.co[j] = -1;
+    if (j < d.nbn) {
+      m.bo[j] = d.b_n[j];
+      m.co[j] = d.c_n[j];
+    } else if (j < d.nbn + d.nbm) {
+      m.ao[j] = d.a_m[j - d.nbn];
+      m.co[j] = d.c_m[j - d.nbn];
+    } else if (j < m.out_bits) {
+      m.ao[j] = d.a_b[j - d.nbn - d.nbm];
+      m.bo[j] = d.b_b[j - d.nbn - d.nbm];
+      m.co[j] = d.c_b[j - d.nbn - d.nbm];
+    }
+  }
+  for (int j = 0; j < kElemKBits; ++j) {
+    m.ak[j] = j < d.nbk ? d.a_k[j] : 0;
+    m.bk[j] = j < d.nbk ? d.b_k[j] : 0;
+  }
+  return m;
+}
+
 hipError_t launch_elem_group(hipStream_t s, const ElemGroupArgs& a, int batch, int precision) {
   if (a.n < 1 || a.n > kElemGroupMax || batch < 1) return hipErrorInvalidValue;
   ElemGroupArgs g = a;
@@ -1544,6 +1579,13 @@ hipError_t launch_gemm(hipStream_t s, const GemmDesc& d, int tile, int split, co
   }
   if (tile == kGemmVector) {
     if (d.K > kElemMaxK) return hipErrorInvalidValue;
+    if (d.nbb + d.nbm + d.nbn <= kElemGroupOutBits && d.nbk <= kElemKBits) {  // the table-driven kernel
+      ElemGroupArgs ga;
+      ga.n = 1;
+      ga.total_blocks = 0;
+      ga.m[0] = elem_member(d, a, a_bs, b, b_bs, c, c_bs);
+      return launch_elem_group(s, ga, batch, precision);
+    }
     g.C = c;
     g.c_bs = c_bs;
     g.split = 1;

@@ -1095,7 +1095,7 @@ void gemm_default_launch(const GemmDesc& g, int* tile, int* split) {
   // narrow products, and small ones with a short sum (latency-bound either way;
   // on the per-output kernel they can share a launch)
   if (((g.M < 64 || g.N < 32) && g.K <= kElemMaxK) ||
-      (g.batch * g.M * g.N <= ((int64_t)1 << kElemGroupOutBits) && g.K <= 32)) {
+      (g.batch * g.M * g.N <= ((int64_t)1 << kElemSmallBits) && g.K <= 32)) {
     *tile = kGemmVector;
     return;
   }

@@ -393,41 +393,15 @@ static tn_status run_steps_body(hipStream_t s, tn_path* path, const Bases& B, in
           for (size_t t = si; t < e; ++t) {
             const StepProgram& Q = path->steps[t];
             const GemmDesc& d = Q.gm[Q.orient[precision]];
-            ElemMember& m = ga.m[t - si];
             int64_t abs_, bbs, cbs;
-            m.A = resolve(B, d.a, &abs_);
-            m.B = resolve(B, d.b, &bbs);
-            m.C = resolve(B, d.c, &cbs);
+            const float2* ma = resolve(B, d.a, &abs_);
+            const float2* mb = resolve(B, d.b, &bbs);
+            float2* mc = resolve(B, d.c, &cbs);
             if (t + 1 == path->steps.size() && B.final_out) {
-              m.C = B.final_out;
+              mc = B.final_out;
               cbs = B.final_out_bs;
             }
-            m.a_bs = abs_;
-            m.b_bs = bbs;
-            m.c_bs = cbs;
-            m.out_bits = d.nbb + d.nbm + d.nbn;
-            m.k_bits = d.nbk;
-            m.pad = 0;
-            // result index bits: n lowest, then m, then batch
-            for (int j = 0; j < kElemGroupOutBits; ++j) {
-              m.ao[j] = m.bo[j] = m.co[j] = -1;
-              if (j < d.nbn) {
-                m.bo[j] = d.b_n[j];
-                m.co[j] = d.c_n[j];
-              } else if (j < d.nbn + d.nbm) {
-                m.ao[j] = d.a_m[j - d.nbn];
-                m.co[j] = d.c_m[j - d.nbn];
-              } else if (j < m.out_bits) {
-                m.ao[j] = d.a_b[j - d.nbn - d.nbm];
-                m.bo[j] = d.b_b[j - d.nbn - d.nbm];
-                m.co[j] = d.c_b[j - d.nbn - d.nbm];
-              }
-            }
-            for (int j = 0; j < kElemKBits; ++j) {
-              m.ak[j] = j < d.nbk ? d.a_k[j] : 0;
-              m.bk[j] = j < d.nbk ? d.b_k[j] : 0;
-            }
-            m.block0 = 0;  // laid out by the launcher
+            ga.m[t - si] = elem_member(d, ma, abs_, mb, bbs, mc, cbs);
             bytes += 8.0 * batch * (double)d.batch * (double)(d.M * d.K + d.K * d.N + d.M * d.N);
             flops += Q.flops * batch;
           }
