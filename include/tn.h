@@ -344,10 +344,12 @@ tn_status tn_path_gemm_config(tn_path* path, int32_t step, int32_t precision, in
  * cross HBM (operands read once, result written once) and flops (8 per
  * complex multiply-add).  Within the steps of a contraction, consecutive
  * timed launches of one kind share one event pair (an event recorded between
- * two kernels idles the GPU for a few microseconds); a TN_KERNEL_GEMM_LARGE
- * product and every other launch get a pair of their own.  tn_profile_read
- * synchronises on the recorded events and returns one record per kernel kind
- * (at most `capacity`, returns the number written).  Not thread-safe.
+ * two kernels idles the GPU for a few microseconds); every other launch gets a
+ * pair of its own, and so does a TN_KERNEL_GEMM_LARGE product while that kind
+ * is selected (it is then counted under TN_KERNEL_GEMM too if that is
+ * selected).  tn_profile_read synchronises on the recorded events and returns
+ * one record per kernel kind (at most `capacity`, returns the number
+ * written).  Not thread-safe.
  */
 typedef enum {
   TN_KERNEL_MATERIALIZE = 0, TN_KERNEL_SKINNY = 1, TN_KERNEL_PERMUTE = 2, TN_KERNEL_GEMM = 3,

@@ -84,9 +84,13 @@ static void prof_close_run(hipStream_t s) {
   g_recs.push_back(g_run);
 }
 
-// own_pair: time this launch alone even inside a run
-static hipEvent_t prof_start(hipStream_t s, int kind, bool own_pair = false) {
-  const bool timed = g_prof && ((g_prof_mask >> kind) & 1u);
+static bool prof_selected(int kind) { return g_prof && ((g_prof_mask >> kind) & 1u); }
+
+// large: a large product, timed alone (a pair of its own, even inside a run)
+// when TN_KERNEL_GEMM_LARGE is selected
+static hipEvent_t prof_start(hipStream_t s, int kind, bool large = false) {
+  const bool own_pair = large && prof_selected(TN_KERNEL_GEMM_LARGE);
+  const bool timed = prof_selected(kind) || own_pair;
   if (g_run_open && (!timed || own_pair || g_run.kind != kind)) prof_close_run(s);
   if (!timed) return nullptr;
   if (g_coalesce && !own_pair) {
@@ -115,10 +119,14 @@ static void prof_stop(hipStream_t s, hipEvent_t a, int kind, double bytes, doubl
   hipEvent_t b = pool_event();
   if (!b) return;
   (void)hipEventRecord(b, s);
-  g_recs.push_back(ProfRec{kind, a, b, bytes, flops, 1, true});
-  // products that are large by flops and intensity are also tallied on their own
-  if (kind == TN_KERNEL_GEMM && large_product(bytes, flops))
-    g_recs.push_back(ProfRec{TN_KERNEL_GEMM_LARGE, a, b, bytes, flops, 1, false});
+  const bool large = kind == TN_KERNEL_GEMM && large_product(bytes, flops) && prof_selected(TN_KERNEL_GEMM_LARGE);
+  if (prof_selected(kind)) {
+    g_recs.push_back(ProfRec{kind, a, b, bytes, flops, 1, true});
+    // products that are large by flops and intensity are also tallied on their own
+    if (large) g_recs.push_back(ProfRec{TN_KERNEL_GEMM_LARGE, a, b, bytes, flops, 1, false});
+  } else if (large) {
+    g_recs.push_back(ProfRec{TN_KERNEL_GEMM_LARGE, a, b, bytes, flops, 1, true});
+  }
 }
 
 // ---------------------------------------------------------------------------
