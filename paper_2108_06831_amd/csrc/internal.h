@@ -244,10 +244,13 @@ struct SmallStep {
   // thread, small_items[item0 .. item0 + n_items)
   int32_t item0, n_items, pad2[2];
 };
-// A work item of the interpreter: `count` consecutive outputs of one step of
-// the round, packed as step (index in the level's chunk, 8 bits) | first
-// output << 8 (12 bits) | (count - 1) << 20 (12 bits).
-constexpr int kSmallMaxItems = 512;  // per round: at most two per thread
+// A work item of the interpreter: the outputs j + t 2^q (t = 0 .. 2^(c - q) - 1)
+// of one step of the round with 2^c outputs, packed as step (index in the
+// level's chunk, 8 bits) | j << 8 (12 bits) | q << 20 (4 bits).  The 2^q items
+// of a step take interleaved outputs, so that neighbouring threads touch
+// neighbouring elements.
+constexpr int kSmallThreads = 1024;  // threads of an interpreter workgroup (one work list each)
+constexpr int kSmallMaxItems = 2 * kSmallThreads;  // per round: at most two per thread
 static_assert(sizeof(SmallStep) % 16 == 0, "SmallStep is copied in 16-byte words");
 
 enum StepKind { SK_SKINNY = 0, SK_GEMM = 1, SK_SMALL = 2 };

@@ -287,7 +287,7 @@ __device__ inline int packed_byte(uint32_t w0, uint32_t w1, uint32_t w2, int j) 
 constexpr int kStageInFlight = 8;  // operand loads each interpreter thread issues before it waits
 
 template <int PREC>
-__global__ __launch_bounds__(kThreads) void k_small_steps(const SmallStep* steps, const int32_t* list_off,
+__global__ __launch_bounds__(kSmallThreads) void k_small_steps(const SmallStep* steps, const int32_t* list_off,
                                                           const int32_t* level_off, const uint32_t* items,
                                                           float2* in, int64_t in_bs, float2* ws, int64_t ws_bs) {
   __shared__ __attribute__((aligned(16))) SmallStep desc[kSmallDescCache];
@@ -313,7 +313,7 @@ __global__ __launch_bounds__(kThreads) void k_small_steps(const SmallStep* steps
         const uint4* src = reinterpret_cast<const uint4*>(steps + cb);
         uint4* dst = reinterpret_cast<uint4*>(desc);
         __syncthreads();  // the previous window is no longer read
-        for (int i = threadIdx.x; i < words; i += kThreads) dst[i] = src[i];
+        for (int i = threadIdx.x; i < words; i += kSmallThreads) dst[i] = src[i];
         win0 = cb;
         win1 = end;
         __syncthreads();
@@ -327,14 +327,14 @@ __global__ __launch_bounds__(kThreads) void k_small_steps(const SmallStep* steps
         // this thread's work items, fetched while the operands are staged
         const int it0 = desc_c[r0].item0, nit = desc_c[r0].n_items;
         const uint32_t my0 = (int)threadIdx.x < nit ? items[it0 + threadIdx.x] : 0u;
-        const uint32_t my1 = (int)threadIdx.x + kThreads < nit ? items[it0 + threadIdx.x + kThreads] : 0u;
+        const uint32_t my1 = (int)threadIdx.x + kSmallThreads < nit ? items[it0 + threadIdx.x + kSmallThreads] : 0u;
         // stage the operands: one flat loop over the round's operand elements,
         // every thread keeping kStageInFlight independent loads in flight
-        for (int e0 = threadIdx.x; e0 < stage_end; e0 += kStageInFlight * kThreads) {
+        for (int e0 = threadIdx.x; e0 < stage_end; e0 += kStageInFlight * kSmallThreads) {
           float2 v[kStageInFlight];
 #pragma unroll
           for (int u = 0; u < kStageInFlight; ++u) {
-            const int e = e0 + u * kThreads;
+            const int e = e0 + u * kSmallThreads;
             if (e >= stage_end) break;
             int lo = r0, hi = r1 - 1;  // the step owning staged element e
             while (lo < hi) {
@@ -349,20 +349,20 @@ __global__ __launch_bounds__(kThreads) void k_small_steps(const SmallStep* steps
           }
 #pragma unroll
           for (int u = 0; u < kStageInFlight; ++u) {
-            const int e = e0 + u * kThreads;
+            const int e = e0 + u * kSmallThreads;
             if (e >= stage_end) break;
             stage[e] = v[u];
           }
         }
         __syncthreads();
-        // each item: consecutive outputs of one step; the operand addresses of
-        // the first come from the step's index maps (packed in registers), the
-        // next ones by flipping the address bits of the output bits that change
+        // each item: the outputs j + t 2^qb of one step; the operand addresses
+        // of the first come from the step's index maps (packed in registers),
+        // the next ones by flipping the address bits of the output bits that change
         for (int q = 0; q < 2; ++q) {
-          if ((int)threadIdx.x + q * kThreads >= nit) break;
+          if ((int)threadIdx.x + q * kSmallThreads >= nit) break;
           const uint32_t wd = q == 0 ? my0 : my1;
           const SmallStep& st = desc_c[wd & 255u];
-          const int o0 = (int)((wd >> 8) & 4095u), o1 = o0 + (int)(wd >> 20) + 1;
+          const int o0 = (int)((wd >> 8) & 4095u), qb = (int)(wd >> 20), nt_ = 1 << (st.c_bits - qb);
           const uint32_t* ap = reinterpret_cast<const uint32_t*>(st.apos);
           const uint32_t* bp = reinterpret_cast<const uint32_t*>(st.bpos);
           const uint32_t* ka = reinterpret_cast<const uint32_t*>(st.ka);
@@ -380,9 +380,10 @@ __global__ __launch_bounds__(kThreads) void k_small_steps(const SmallStep* steps
             if (pa >= 0) ab |= 1 << pa;
             if (pb >= 0) bb |= 1 << pb;
           }
-          for (int o = o0; o < o1; ++o) {
-            if (o != o0)
-              for (uint32_t f = (uint32_t)(o ^ (o - 1)); f; f &= f - 1) {
+          for (int t = 0; t < nt_; ++t) {
+            const int o = o0 | (t << qb);
+            if (t != 0)
+              for (uint32_t f = (uint32_t)((t ^ (t - 1)) << qb); f; f &= f - 1) {
                 const int p = __builtin_ctz(f);
                 const int pa = packed_byte(ap0, ap1, ap2, p), pb = packed_byte(bp0, bp1, bp2, p);
                 if (pa >= 0) ab ^= 1 << pa;
@@ -412,10 +413,10 @@ hipError_t launch_small_steps(hipStream_t s, const SmallStep* steps, const int32
                               int64_t in_bs, float2* ws, int64_t ws_bs, int batch, int precision) {
   if (n_lists == 0) return hipSuccess;
   if (precision == TN_PREC_BF16X3)
-    hipLaunchKernelGGL(k_small_steps<TN_PREC_BF16X3>, dim3(n_lists, batch), dim3(kThreads), 0, s, steps, list_off,
+    hipLaunchKernelGGL(k_small_steps<TN_PREC_BF16X3>, dim3(n_lists, batch), dim3(kSmallThreads), 0, s, steps, list_off,
                        level_off, items, in, in_bs, ws, ws_bs);
   else
-    hipLaunchKernelGGL(k_small_steps<TN_PREC_C64>, dim3(n_lists, batch), dim3(kThreads), 0, s, steps, list_off,
+    hipLaunchKernelGGL(k_small_steps<TN_PREC_C64>, dim3(n_lists, batch), dim3(kSmallThreads), 0, s, steps, list_off,
                        level_off, items, in, in_bs, ws, ws_bs);
   return hipGetLastError();
 }

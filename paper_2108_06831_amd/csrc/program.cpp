@@ -926,25 +926,25 @@ tn_status compile_program(const tn_network* net, tn_path* path, const std::vecto
             const SmallStep& d = path->small_steps[q];
             total += ((int64_t)1 << d.c_bits) * (((int64_t)1 << d.k_bits) + 4);
           }
-          for (int64_t target = std::max<int64_t>(1, (total + 255) / 256);; target *= 2) {
+          for (int64_t target = std::max<int64_t>(1, (total + kSmallThreads - 1) / kSmallThreads);; target *= 2) {
             std::vector<uint32_t> items;
             for (int q = r0; q < i; ++q) {
               const SmallStep& d = path->small_steps[q];
-              const int64_t outs = (int64_t)1 << d.c_bits, per = ((int64_t)1 << d.k_bits) + 4;
-              const int64_t run = std::min<int64_t>(outs, std::max<int64_t>(1, target / per));
-              for (int64_t o = 0; o < outs; o += run) {
-                const int64_t cnt = std::min(run, outs - o);
-                items.push_back((uint32_t)(q - cb) | ((uint32_t)o << 8) | ((uint32_t)(cnt - 1) << 20));
-              }
+              const int64_t per = ((int64_t)1 << d.k_bits) + 4;
+              int lc = 0;  // log2 of the outputs per item
+              while (lc < d.c_bits && ((int64_t)2 << lc) * per <= target) ++lc;
+              const int qb = d.c_bits - lc;
+              for (int64_t j = 0; j < ((int64_t)1 << qb); ++j)
+                items.push_back((uint32_t)(q - cb) | ((uint32_t)j << 8) | ((uint32_t)qb << 20));
             }
             if ((int)items.size() <= kSmallMaxItems) {
               // every output of every step of the round exactly once, in range
               std::vector<int64_t> covered(i - r0, 0);
               for (uint32_t it : items) {
-                const int q = (int)(it & 255u) + cb, o = (int)((it >> 8) & 4095u), cnt = (int)(it >> 20) + 1;
-                if (q < r0 || q >= i || o + cnt > (1 << path->small_steps[q].c_bits))
+                const int q = (int)(it & 255u) + cb, j = (int)((it >> 8) & 4095u), qb = (int)(it >> 20);
+                if (q < r0 || q >= i || qb > path->small_steps[q].c_bits || j >= (1 << qb))
                   return set_error(TN_EINVAL, "internal: bad interpreter work item");
-                covered[q - r0] += cnt;
+                covered[q - r0] += (int64_t)1 << (path->small_steps[q].c_bits - qb);
               }
               for (int q = r0; q < i; ++q)
                 if (covered[q - r0] != ((int64_t)1 << path->small_steps[q].c_bits))
