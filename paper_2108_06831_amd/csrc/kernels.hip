@@ -1178,11 +1178,16 @@ __global__ __launch_bounds__(kThreads) void k_gemm(GemmArgs g) {
 // P3 = (Ar + Ai)(Br + Bi)).  Four waves in a 2 x 2 arrangement, each owning
 // TM tiles of 32 x 32 complex: the block computes (64 TM) x 64.
 template <int AK, int BNF, int TM, int BK>
-__global__ __launch_bounds__(kThreads) void k_gemm3m(GemmArgs g) {
+__global__ __launch_bounds__(kThreads, TM == 1 ? 4 : 2) void k_gemm3m(GemmArgs g) {
   constexpr int BM = 64 * TM, BN = 64;
   constexpr int kPA = (BM * BK) / kThreads, kPB = (BN * BK) / kThreads;
   constexpr int kLogBK = BK == 32 ? 5 : 4;
-  __shared__ float Ar[BK][BM + 1], Ai[BK][BM + 1], Br[BK][BN + 1], Bi[BK][BN + 1];
+  // operand planes with k contiguous per row (A) or column (B), rows padded to
+  // BK + 4 floats: a lane reads its eight k values of a tile as two 16-byte
+  // loads, and the rows of a half-wave fall on distinct banks
+  static_assert(BK == 16, "the k order of the MFMA steps assumes 16 k per tile");
+  constexpr int kRow = BK + 4;
+  __shared__ __attribute__((aligned(16))) float Ar[BM][kRow], Ai[BM][kRow], Br[BN][kRow], Bi[BN][kRow];
   __shared__ int64_t TAm[BM], TCm[BM], TBn[BN], TCn[BN], TAk[BK], TBk[BK];
   constexpr int kKt = 64;  // K tiles whose origin deposits are tabulated (the rest computed on the fly)
   __shared__ int64_t TAt[kKt], TBt[kKt];
@@ -1287,57 +1292,49 @@ __global__ __launch_bounds__(kThreads) void k_gemm3m(GemmArgs g) {
     for (int e = 0; e < kPA; ++e) {
       int mm, kk;
       a_elem(e, mm, kk);
-      Ar[kk][mm] = ra[e].x;
-      Ai[kk][mm] = ra[e].y;
+      Ar[mm][kk] = ra[e].x;
+      Ai[mm][kk] = ra[e].y;
     }
 #pragma unroll
     for (int e = 0; e < kPB; ++e) {
       int nn, kk;
       b_elem(e, nn, kk);
-      Br[kk][nn] = rb[e].x;
-      Bi[kk][nn] = rb[e].y;
+      Br[nn][kk] = rb[e].x;
+      Bi[nn][kk] = rb[e].y;
     }
   };
   const int h = lane >> 5, r32 = lane & 31;
+  const int col = wn * 32 + r32;
   fetch(kbeg);
   for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
     stage();
     __syncthreads();
     if (k0 + BK < kend) fetch(k0 + BK);
-    // operands of step kk + 2 are read from LDS before the products of step kk
-    const int col = wn * 32 + r32;
-    float br = Br[h][col], bi = Bi[h][col], ar[TM], ai[TM];
+    // MFMA step s takes k = s on lanes 0-31 and k = 8 + s on lanes 32-63 (the
+    // same order for A and B), so a lane's operands for the whole tile are the
+    // eight contiguous k values 8h .. 8h + 7 of its row or column
 #pragma unroll
-    for (int i = 0; i < TM; ++i) {
-      ar[i] = Ar[h][wm * 32 * TM + i * 32 + r32];
-      ai[i] = Ai[h][wm * 32 * TM + i * 32 + r32];
-    }
-#pragma unroll
-    for (int kk = 0; kk < BK; kk += 2) {
-      float nbr = 0.f, nbi = 0.f, nar[TM], nai[TM];
-      if (kk + 2 < BK) {
-        nbr = Br[kk + 2 + h][col];
-        nbi = Bi[kk + 2 + h][col];
-#pragma unroll
-        for (int i = 0; i < TM; ++i) {
-          nar[i] = Ar[kk + 2 + h][wm * 32 * TM + i * 32 + r32];
-          nai[i] = Ai[kk + 2 + h][wm * 32 * TM + i * 32 + r32];
-        }
-      }
-      const float bs = br + bi;
+    for (int hh = 0; hh < 2; ++hh) {  // two halves of four steps: four k values per lane and plane
+      const float4 b4 = *reinterpret_cast<const float4*>(&Br[col][8 * h + 4 * hh]);
+      const float4 c4 = *reinterpret_cast<const float4*>(&Bi[col][8 * h + 4 * hh]);
+      const float br[4] = {b4.x, b4.y, b4.z, b4.w}, bi[4] = {c4.x, c4.y, c4.z, c4.w};
+      float ar[TM][4], ai[TM][4];
 #pragma unroll
       for (int i = 0; i < TM; ++i) {
-        p1[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[i], br, p1[i], 0, 0, 0);
-        p2[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[i], bi, p2[i], 0, 0, 0);
-        p3[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[i] + ai[i], bs, p3[i], 0, 0, 0);
+        const int row = wm * 32 * TM + i * 32 + r32;
+        const float4 a4 = *reinterpret_cast<const float4*>(&Ar[row][8 * h + 4 * hh]);
+        const float4 d4 = *reinterpret_cast<const float4*>(&Ai[row][8 * h + 4 * hh]);
+        ar[i][0] = a4.x; ar[i][1] = a4.y; ar[i][2] = a4.z; ar[i][3] = a4.w;
+        ai[i][0] = d4.x; ai[i][1] = d4.y; ai[i][2] = d4.z; ai[i][3] = d4.w;
       }
-      if (kk + 2 < BK) {
-        br = nbr;
-        bi = nbi;
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        const float bs = br[st] + bi[st];
 #pragma unroll
         for (int i = 0; i < TM; ++i) {
-          ar[i] = nar[i];
-          ai[i] = nai[i];
+          p1[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[i][st], br[st], p1[i], 0, 0, 0);
+          p2[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[i][st], bi[st], p2[i], 0, 0, 0);
+          p3[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[i][st] + ai[i][st], bs, p3[i], 0, 0, 0);
         }
       }
     }
