@@ -1185,7 +1185,7 @@ __global__ __launch_bounds__(kThreads, TM == 1 ? 4 : 2) void k_gemm3m(GemmArgs g
   // operand planes with k contiguous per row (A) or column (B), rows padded to
   // BK + 4 floats: a lane reads its eight k values of a tile as two 16-byte
   // loads, and the rows of a half-wave fall on distinct banks
-  static_assert(BK == 16, "the k order of the MFMA steps assumes 16 k per tile");
+  static_assert(BK % 8 == 0, "whole 16-byte operand reads");
   constexpr int kRow = BK + 4;
   __shared__ __attribute__((aligned(16))) float Ar[BM][kRow], Ai[BM][kRow], Br[BN][kRow], Bi[BN][kRow];
   __shared__ int64_t TAm[BM], TCm[BM], TBn[BN], TCn[BN], TAk[BK], TBk[BK];
@@ -1310,20 +1310,21 @@ __global__ __launch_bounds__(kThreads, TM == 1 ? 4 : 2) void k_gemm3m(GemmArgs g
     stage();
     __syncthreads();
     if (k0 + BK < kend) fetch(k0 + BK);
-    // MFMA step s takes k = s on lanes 0-31 and k = 8 + s on lanes 32-63 (the
-    // same order for A and B), so a lane's operands for the whole tile are the
-    // eight contiguous k values 8h .. 8h + 7 of its row or column
+    // MFMA step s takes k = s on lanes 0-31 and k = BK/2 + s on lanes 32-63
+    // (the same order for A and B), so a lane's operands for the whole tile are
+    // the BK/2 contiguous k values of its row or column starting at h BK/2
+    constexpr int kHalf = BK / 2;
 #pragma unroll
-    for (int hh = 0; hh < 2; ++hh) {  // two halves of four steps: four k values per lane and plane
-      const float4 b4 = *reinterpret_cast<const float4*>(&Br[col][8 * h + 4 * hh]);
-      const float4 c4 = *reinterpret_cast<const float4*>(&Bi[col][8 * h + 4 * hh]);
+    for (int hh = 0; hh < kHalf / 4; ++hh) {  // groups of four steps: four k values per lane and plane
+      const float4 b4 = *reinterpret_cast<const float4*>(&Br[col][kHalf * h + 4 * hh]);
+      const float4 c4 = *reinterpret_cast<const float4*>(&Bi[col][kHalf * h + 4 * hh]);
       const float br[4] = {b4.x, b4.y, b4.z, b4.w}, bi[4] = {c4.x, c4.y, c4.z, c4.w};
       float ar[TM][4], ai[TM][4];
 #pragma unroll
       for (int i = 0; i < TM; ++i) {
         const int row = wm * 32 * TM + i * 32 + r32;
-        const float4 a4 = *reinterpret_cast<const float4*>(&Ar[row][8 * h + 4 * hh]);
-        const float4 d4 = *reinterpret_cast<const float4*>(&Ai[row][8 * h + 4 * hh]);
+        const float4 a4 = *reinterpret_cast<const float4*>(&Ar[row][kHalf * h + 4 * hh]);
+        const float4 d4 = *reinterpret_cast<const float4*>(&Ai[row][kHalf * h + 4 * hh]);
         ar[i][0] = a4.x; ar[i][1] = a4.y; ar[i][2] = a4.z; ar[i][3] = a4.w;
         ai[i][0] = d4.x; ai[i][1] = d4.y; ai[i][2] = d4.z; ai[i][3] = d4.w;
       }
