@@ -206,7 +206,7 @@ constexpr int kElemMaxK = 1024;  // longest K of the per-output kernel
 // terms.  The planner places products with results of at most 2^kElemSmallBits
 // elements side by side so that they can share a launch.
 constexpr int kElemGroupMax = 16;
-constexpr int kElemGroupOutBits = 18;
+constexpr int kElemGroupOutBits = 24;
 constexpr int kElemSmallBits = 16;
 constexpr int kElemKBits = 10;
 // small gate-sized products (result of at most 2^kElemSkinnyBits elements)

@@ -1397,12 +1397,13 @@ __global__ __launch_bounds__(kThreads) void k_contract_elem(GemmArgs g) {
 }
 
 // Grouped form of the per-output products: every member's address maps are
-// turned into LDS tables (three 6-bit chunks of the result index, one table of
-// summed offsets per operand), so an output costs nine table reads before its
-// sum.
+// turned into LDS tables (four 6-bit chunks of the result index, one table of
+// summed offsets per operand), so an output costs twelve table reads before
+// its sum.
+constexpr int kElemChunks = (kElemGroupOutBits + 5) / 6;
 template <int PREC>
 __global__ __launch_bounds__(kThreads) void k_elem_group(ElemGroupArgs g) {
-  __shared__ int64_t TO[3 * 3 * 64];  // [operand A, B, C][chunk][chunk value]
+  __shared__ int64_t TO[3 * kElemChunks * 64];  // [operand A, B, C][chunk][chunk value]
   __shared__ int64_t TKa[kElemMaxK], TKb[kElemMaxK];
   const int bx = blockIdx.x, z = blockIdx.y;
   int mi = 0;
@@ -1411,8 +1412,8 @@ __global__ __launch_bounds__(kThreads) void k_elem_group(ElemGroupArgs g) {
   const ElemMember& e = g.m[mi];
   const int nblk = (mi + 1 < g.n ? g.m[mi + 1].block0 : g.total_blocks) - e.block0;
   const int ob = e.out_bits, kb = e.k_bits;
-  for (int t = threadIdx.x; t < 3 * 3 * 64; t += kThreads) {
-    const int map = t / 192, ch = (t >> 6) % 3, x = t & 63;
+  for (int t = threadIdx.x; t < 3 * kElemChunks * 64; t += kThreads) {
+    const int map = t / (kElemChunks * 64), ch = (t >> 6) % kElemChunks, x = t & 63;
     const int8_t* pos = map == 0 ? e.ao : map == 1 ? e.bo : e.co;
     int64_t r = 0;
 #pragma unroll
@@ -1443,10 +1444,14 @@ __global__ __launch_bounds__(kThreads) void k_elem_group(ElemGroupArgs g) {
   float2* C = e.C + (int64_t)z * e.c_bs;
   const int n_out = 1 << ob;
   for (int o = (bx - e.block0) * kThreads + threadIdx.x; o < n_out; o += nblk * kThreads) {
-    const int c0 = o & 63, c1 = 64 + ((o >> 6) & 63), c2 = 128 + ((o >> 12) & 63);
-    const int64_t ab = TO[c0] | TO[c1] | TO[c2];
-    const int64_t bb = TO[192 + c0] | TO[192 + c1] | TO[192 + c2];
-    const int64_t cc = TO[384 + c0] | TO[384 + c1] | TO[384 + c2];
+    int64_t ab = 0, bb = 0, cc = 0;
+#pragma unroll
+    for (int ch = 0; ch < kElemChunks; ++ch) {
+      const int i = ch * 64 + ((o >> (6 * ch)) & 63);
+      ab |= TO[i];
+      bb |= TO[kElemChunks * 64 + i];
+      cc |= TO[2 * kElemChunks * 64 + i];
+    }
     float2 acc = f2(0.f, 0.f);
     int k = 0;
     for (; k + 8 <= K; k += 8) {
