@@ -390,3 +390,33 @@ def test_grouped_products(precision, tol):
     got2 = amplitudes(net, path, bits, precision=precision).cpu().numpy()
     torch.cuda.synchronize()
     assert relerr(got2, want) < tol
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_grouped_launches_random_grids(seed):
+    """Random grid circuits (sizes, depths, bitstring batches and orders drawn
+    from the seed), amplitudes on a batch index: the planner's grouping of
+    per-output products (reordered steps, held-back buffers, shared launches)
+    against the oracle, with the default shapes and after autotuning."""
+    import torch
+    from paper_2108_06831_amd import Network, amplitudes, autotune
+    rng = np.random.default_rng(9100 + seed)
+    rows, cols = [(4, 4), (3, 6), (4, 5), (4, 6)][seed]
+    depth = int(rng.integers(8, 13))
+    circ = workloads.grid_circuit(rows, cols, depth, rng, f"grid_{rows}x{cols}_d{depth}")
+    nb = int(rng.choice([1024, 4096]))
+    bits = workloads.random_bitstrings(circ.n_qubits, nb, rng)
+    net = Network.from_circuit(circ, output="amplitudes", n_bitstrings=nb, fuse=["split", False][seed % 2])
+    path = net.plan(["greedy", "search"][seed // 2], trials=64, seed=seed, max_log2_intermediate=30)
+    st = path.stats
+    n_products = st["n_gemm_steps"] + st["n_skinny_steps"]
+    print(f"grid {rows}x{cols} depth {depth} batch {nb}: products {n_products}, "
+          f"launches {st['n_product_launches']}", flush=True)
+    assert st["n_product_launches"] < n_products  # some products share launches
+    want = oracle.amplitudes(oracle.statevector(circ), circ.n_qubits, bits)
+    got = amplitudes(net, path, bits).cpu().numpy()
+    assert relerr(got, want) < C64_TOL
+    autotune(net, path, reps=2)
+    got = amplitudes(net, path, bits).cpu().numpy()
+    torch.cuda.synchronize()
+    assert relerr(got, want) < C64_TOL
