@@ -229,7 +229,7 @@ constexpr int kSmallMaxMacLog2 = 20;
 constexpr int kSmallDescCache = 128;  // step descriptors staged in LDS at a time
 constexpr int kSmallStage = 12288;    // operand elements staged in LDS per round (96 KB)
 struct SmallStep {
-  int32_t a_buf, b_buf, c_buf;  // BUF_IN / BUF_WS, or an LDS slot for a result the next step consumes
+  int32_t a_buf, b_buf, c_buf;  // BUF_IN / BUF_WS
   int32_t c_bits, k_bits;
   int16_t a_bits, b_bits;       // operand sizes (log2 elements)
   int64_t a_off, b_off, c_off;
