@@ -1177,7 +1177,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm(GemmArgs g) {
 // complex tile keeps three accumulators (P1 = Ar Br, P2 = Ai Bi,
 // P3 = (Ar + Ai)(Br + Bi)).  Four waves in a 2 x 2 arrangement, each owning
 // TM tiles of 32 x 32 complex: the block computes (64 TM) x 64.
-template <int AK, int BNF, int TM, int BK>
+template <int AK, int BNF, int TM, int BK, int NW>
 __global__ __launch_bounds__(kThreads, TM == 1 ? 4 : 2) void k_gemm3m(GemmArgs g) {
   constexpr int BM = 64 * TM, BN = 64;
   constexpr int kPA = (BM * BK) / kThreads, kPB = (BN * BK) / kThreads;
@@ -1238,69 +1238,104 @@ __global__ __launch_bounds__(kThreads, TM == 1 ? 4 : 2) void k_gemm3m(GemmArgs g
     for (int v = 0; v < 16; ++v) p1[i][v] = p2[i][v] = p3[i][v] = 0.f;
   __syncthreads();
 
-  auto a_elem = [&](int e, int& mm, int& kk) {
-    const int idx = tid + e * kThreads;
-    if (AK) { mm = idx / BK; kk = idx % BK; } else { mm = idx % BM; kk = idx / BM; }
+  // Staging order: each quarter-wave loads 16 elements that are contiguous in
+  // the operand (a 128-byte run), and the 64 LDS words a wave writes fall on
+  // distinct banks.  With rows kRow = 20 words apart, row r starts on bank
+  // 20 r mod 64 (distinct multiples of 4 for 16 consecutive rows):
+  //  - fast operand index along the rows (m or n): 16 consecutive rows times
+  //    four k per wave;
+  //  - k fastest: 16 k of rows r, r + 4, r + 8, r + 12 per wave (start banks
+  //    16 apart).
+  // A thread's slot for its element e is (row rt + row_e(e), k kt + k_e(e)):
+  // the thread part is fixed for the block, the element part a constant.
+  static_assert(BK == 16 && kThreads == 256 && BN == 64, "staging order assumes 16-wide K tiles");
+  auto slot_t = [&](bool k_fast, int& r, int& kk) {
+    if (k_fast) {
+      kk = tid & 15;
+      r = 4 * ((tid >> 4) & 3) + ((tid >> 6) & 3);
+    } else {
+      r = (tid & 15) + 16 * (tid >> 6);
+      kk = (tid >> 4) & 3;
+    }
   };
-  auto b_elem = [&](int e, int& nn, int& kk) {
-    const int idx = tid + e * kThreads;
-    if (BNF) { nn = idx % BN; kk = idx / BN; } else { nn = idx / BK; kk = idx % BK; }
-  };
-  // per-thread element addresses without the K tile's origin, fixed for the block
-  const float2* pa[kPA];
-  const float2* pb[kPB];
-  bool va[kPA], vb[kPB];
-  int ka_e[kPA], kb_e[kPB];
+  auto row_e = [](bool k_fast, int rows, int e) { return k_fast ? 16 * e : 64 * (e % (rows / 64)); };
+  auto k_e = [](bool k_fast, int rows, int e) { return k_fast ? 0 : 4 * (e / (rows / 64)); };
+  int a_rt, a_kt, b_rt, b_kt;
+  slot_t(AK != 0, a_rt, a_kt);
+  slot_t(BNF == 0, b_rt, b_kt);
+  // element offsets within a K tile, without the tile's origin: 32-bit byte
+  // offsets from a block-uniform base when every offset of the tile stays
+  // below 2^32 bytes (NW), else full pointers
+  const float2* pa[NW ? 1 : kPA];
+  const float2* pb[NW ? 1 : kPB];
+  uint32_t oa[NW ? kPA : 1], ob[NW ? kPB : 1];
 #pragma unroll
   for (int e = 0; e < kPA; ++e) {
-    int mm, kk;
-    a_elem(e, mm, kk);
-    pa[e] = A + (base_a | TAm[mm] | TAk[kk]);
-    va[e] = m0 + mm < g.M;
-    ka_e[e] = kk;
+    const int64_t off = TAm[a_rt + row_e(AK != 0, BM, e)] | TAk[a_kt + k_e(AK != 0, BM, e)];
+    if constexpr (NW) oa[e] = (uint32_t)off * (uint32_t)sizeof(float2);
+    else pa[e] = A + (base_a | off);
   }
 #pragma unroll
   for (int e = 0; e < kPB; ++e) {
-    int nn, kk;
-    b_elem(e, nn, kk);
-    pb[e] = B + (base_b | TBn[nn] | TBk[kk]);
-    vb[e] = n0 + nn < g.N;
-    kb_e[e] = kk;
+    const int64_t off = TBn[b_rt + row_e(BNF == 0, BN, e)] | TBk[b_kt + k_e(BNF == 0, BN, e)];
+    if constexpr (NW) ob[e] = (uint32_t)off * (uint32_t)sizeof(float2);
+    else pb[e] = B + (base_b | off);
   }
   const bool interior = m0 + BM <= g.M && n0 + BN <= g.N;
   float2 ra[kPA], rb[kPB];
   auto fetch = [&](int64_t k0) {
     const int64_t t = (k0 - kbeg) / BK;
-    const int64_t ka = t < kKt ? TAt[t] : deposit(k0, g.a_k, g.nbk);
-    const int64_t kb = t < kKt ? TBt[t] : deposit(k0, g.b_k, g.nbk);
+    int64_t ka = t < kKt ? TAt[t] : deposit(k0, g.a_k, g.nbk);
+    int64_t kb = t < kKt ? TBt[t] : deposit(k0, g.b_k, g.nbk);
+    // the same value in every lane: keep it in scalar registers
+    ka = ((int64_t)__builtin_amdgcn_readfirstlane((int)(ka >> 32)) << 32) |
+         (uint32_t)__builtin_amdgcn_readfirstlane((int)ka);
+    kb = ((int64_t)__builtin_amdgcn_readfirstlane((int)(kb >> 32)) << 32) |
+         (uint32_t)__builtin_amdgcn_readfirstlane((int)kb);
+    const char* a_org = reinterpret_cast<const char*>(A + (base_a | ka));
+    const char* b_org = reinterpret_cast<const char*>(B + (base_b | kb));
+    auto lda = [&](int e) -> float2 {
+      if constexpr (NW) return *reinterpret_cast<const float2*>(a_org + oa[e]);
+      else return pa[e][ka];
+    };
+    auto ldb = [&](int e) -> float2 {
+      if constexpr (NW) return *reinterpret_cast<const float2*>(b_org + ob[e]);
+      else return pb[e][kb];
+    };
     const int64_t rem = kend - k0;
     const int kleft = rem < BK ? (int)rem : BK;  // valid k of this tile
     if (interior && kleft == BK) {  // whole tile inside the operands: no guards
 #pragma unroll
-      for (int e = 0; e < kPA; ++e) ra[e] = pa[e][ka];
+      for (int e = 0; e < kPA; ++e) ra[e] = lda(e);
 #pragma unroll
-      for (int e = 0; e < kPB; ++e) rb[e] = pb[e][kb];
+      for (int e = 0; e < kPB; ++e) rb[e] = ldb(e);
     } else {
 #pragma unroll
-      for (int e = 0; e < kPA; ++e) ra[e] = (va[e] && ka_e[e] < kleft) ? pa[e][ka] : f2(0.f, 0.f);
+      for (int e = 0; e < kPA; ++e)
+        ra[e] = (m0 + a_rt + row_e(AK != 0, BM, e) < g.M && a_kt + k_e(AK != 0, BM, e) < kleft) ? lda(e)
+                                                                                               : f2(0.f, 0.f);
 #pragma unroll
-      for (int e = 0; e < kPB; ++e) rb[e] = (vb[e] && kb_e[e] < kleft) ? pb[e][kb] : f2(0.f, 0.f);
+      for (int e = 0; e < kPB; ++e)
+        rb[e] = (n0 + b_rt + row_e(BNF == 0, BN, e) < g.N && b_kt + k_e(BNF == 0, BN, e) < kleft) ? ldb(e)
+                                                                                                  : f2(0.f, 0.f);
     }
   };
+  float* const ar_s = &Ar[a_rt][a_kt];
+  float* const ai_s = &Ai[a_rt][a_kt];
+  float* const br_s = &Br[b_rt][b_kt];
+  float* const bi_s = &Bi[b_rt][b_kt];
   auto stage = [&]() {
 #pragma unroll
     for (int e = 0; e < kPA; ++e) {
-      int mm, kk;
-      a_elem(e, mm, kk);
-      Ar[mm][kk] = ra[e].x;
-      Ai[mm][kk] = ra[e].y;
+      const int o = row_e(AK != 0, BM, e) * kRow + k_e(AK != 0, BM, e);
+      ar_s[o] = ra[e].x;
+      ai_s[o] = ra[e].y;
     }
 #pragma unroll
     for (int e = 0; e < kPB; ++e) {
-      int nn, kk;
-      b_elem(e, nn, kk);
-      Br[nn][kk] = rb[e].x;
-      Bi[nn][kk] = rb[e].y;
+      const int o = row_e(BNF == 0, BN, e) * kRow + k_e(BNF == 0, BN, e);
+      br_s[o] = rb[e].x;
+      bi_s[o] = rb[e].y;
     }
   };
   const int h = lane >> 5, r32 = lane & 31;
@@ -1544,24 +1579,38 @@ static void* gemm_fn(int ak, int bnf) {
   return (void*)k_gemm<0, 0, TM, TN, F>;
 }
 
+template <int TM, int BK, int NW>
+static void* gemm3m_fn_nw(int ak, int bnf) {
+  if (ak && bnf) return (void*)k_gemm3m<1, 1, TM, BK, NW>;
+  if (ak) return (void*)k_gemm3m<1, 0, TM, BK, NW>;
+  if (bnf) return (void*)k_gemm3m<0, 1, TM, BK, NW>;
+  return (void*)k_gemm3m<0, 0, TM, BK, NW>;
+}
+
 template <int TM, int BK>
-static void* gemm3m_fn(int ak, int bnf) {
-  if (ak && bnf) return (void*)k_gemm3m<1, 1, TM, BK>;
-  if (ak) return (void*)k_gemm3m<1, 0, TM, BK>;
-  if (bnf) return (void*)k_gemm3m<0, 1, TM, BK>;
-  return (void*)k_gemm3m<0, 0, TM, BK>;
+static void* gemm3m_fn(int ak, int bnf, bool narrow) {
+  return narrow ? gemm3m_fn_nw<TM, BK, 1>(ak, bnf) : gemm3m_fn_nw<TM, BK, 0>(ak, bnf);
 }
 
 template <int F>
-static void* gemm_fn_tile(int tile, int ak, int bnf) {
+static void* gemm_fn_tile(int tile, int ak, int bnf, bool narrow) {
   switch (tile) {
     case 0: return gemm_fn<2, 2, F>(ak, bnf);
     case 1: return gemm_fn<2, 1, F>(ak, bnf);
     case 2: return gemm_fn<1, 2, F>(ak, bnf);
     case 3: return gemm_fn<1, 1, F>(ak, bnf);
-    case 5: return gemm3m_fn<2, 16>(ak, bnf);
-    default: return gemm3m_fn<1, 16>(ak, bnf);
+    case 5: return gemm3m_fn<2, 16>(ak, bnf, narrow);
+    default: return gemm3m_fn<1, 16>(ak, bnf, narrow);
   }
+}
+
+// Whether every element offset inside one operand tile (its tile-local m or n
+// bits and k bits, without the tile's origin) is below 2^32 bytes.
+static bool tile_offsets_narrow(const int8_t* pos_mn, int n_mn, const int8_t* pos_k, int n_k) {
+  int top = -1;
+  for (int j = 0; j < n_mn; ++j) top = pos_mn[j] > top ? pos_mn[j] : top;
+  for (int j = 0; j < n_k; ++j) top = pos_k[j] > top ? pos_k[j] : top;
+  return top + 1 + 3 <= 32;  // 8-byte elements
 }
 
 hipError_t launch_gemm(hipStream_t s, const GemmDesc& d, int tile, int split, const float2* a, int64_t a_bs,
@@ -1614,8 +1663,11 @@ hipError_t launch_gemm(hipStream_t s, const GemmDesc& d, int tile, int split, co
   g.tiles_n = (d.N + kGemmTileN[tile] - 1) / kGemmTileN[tile];
   const int64_t blocks = g.tiles_m * g.tiles_n * g.split * d.batch * batch;
   if (blocks > ((int64_t)1 << 24)) return hipErrorInvalidValue;  // grid of < 2^32 work-items
-  void* fn = precision == TN_PREC_BF16X3 ? gemm_fn_tile<1>(tile, d.a_kfast, d.b_nfast)
-                                         : gemm_fn_tile<0>(tile, d.a_kfast, d.b_nfast);
+  const int lbm = kGemmTileM[tile] == 128 ? 7 : 6, lbn = kGemmTileN[tile] == 64 ? 6 : 5, lbk = 4;
+  const bool narrow = tile_offsets_narrow(d.a_m, std::min(d.nbm, lbm), d.a_k, std::min(d.nbk, lbk)) &&
+                      tile_offsets_narrow(d.b_n, std::min(d.nbn, lbn), d.b_k, std::min(d.nbk, lbk));
+  void* fn = precision == TN_PREC_BF16X3 ? gemm_fn_tile<1>(tile, d.a_kfast, d.b_nfast, narrow)
+                                         : gemm_fn_tile<0>(tile, d.a_kfast, d.b_nfast, narrow);
   void* args[] = {&g};
   hipError_t e = hipLaunchKernel(fn, dim3((unsigned)blocks), dim3(kThreads), args, 0, s);
   if (e != hipSuccess || g.split == 1) return e;

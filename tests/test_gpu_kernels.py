@@ -203,3 +203,28 @@ def test_profile_counts_every_launch():
             assert set(prof) <= {"gemm", "gemm_large"}
         torch.cuda.synchronize()
         assert relerr(got.cpu().numpy()[0], want) < C64_TOL
+
+
+def test_wide_tile_offsets():
+    """An 8 GiB operand whose top address bit is the result's lowest m bit:
+    a tile's element offsets span more than 2^32 bytes, so the matrix-core
+    kernel takes its full-pointer form.  Sampled outputs against the
+    definition of the contraction (eq. (2.2))."""
+    import torch
+    from paper_2108_06831_amd import contract_pair
+    print("wide tile offsets: A 2 x 2^20 x 512 (8 GiB), B 512 x 64", flush=True)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(11)
+    A = torch.randn((2, 1 << 20, 512), dtype=torch.complex64, device="cuda", generator=gen)
+    rng = np.random.default_rng(11)
+    B = crand(rng, (512, 64))
+    C = contract_pair(A, [0, 1, 2], torch.from_numpy(B).cuda(), [2, 3], [1, 3, 0])
+    torch.cuda.synchronize()
+    i0 = torch.as_tensor(rng.integers(0, 2, 96), device="cuda")
+    i1 = torch.as_tensor(rng.integers(0, 1 << 20, 96), device="cuda")
+    rows = A[i0, i1].cpu().numpy()
+    got = C[i1, :, i0].cpu().numpy()
+    del A, C
+    torch.cuda.empty_cache()
+    want = oracle.contract(rows, [0, 1], B, [1, 2], [0, 2])
+    assert relerr(got, want) < C64_TOL
