@@ -1172,7 +1172,8 @@ __global__ __launch_bounds__(kThreads) void k_gemm(GemmArgs g) {
 // 3M form on the FP32 matrix cores: with A = Ar + i Ai and B = Br + i Bi,
 //   Re C = Ar Br - Ai Bi,   Im C = (Ar + Ai)(Br + Bi) - Ar Br - Ai Bi,
 // three real products instead of the four of the real embedding.  Operands
-// are staged as real and imaginary planes; one v_mfma_f32_32x32x2f32 takes
+// are staged as interleaved complex and split into real and imaginary parts
+// as a lane reads them; one v_mfma_f32_32x32x2f32 takes
 // two complex k (lanes 0-31 the first, 32-63 the second) and a 32 x 32
 // complex tile keeps three accumulators (P1 = Ar Br, P2 = Ai Bi,
 // P3 = (Ar + Ai)(Br + Bi)).  Four waves in a 2 x 2 arrangement, each owning
@@ -1182,12 +1183,13 @@ __global__ __launch_bounds__(kThreads, TM == 1 ? 4 : 2) void k_gemm3m(GemmArgs g
   constexpr int BM = 64 * TM, BN = 64;
   constexpr int kPA = (BM * BK) / kThreads, kPB = (BN * BK) / kThreads;
   constexpr int kLogBK = BK == 32 ? 5 : 4;
-  // operand planes with k contiguous per row (A) or column (B), rows padded to
-  // BK + 4 floats: a lane reads its eight k values of a tile as two 16-byte
-  // loads, and the rows of a half-wave fall on distinct banks
+  // operands staged as interleaved complex with k contiguous per row of A and
+  // per column of B, rows kRow = 2 BK + 4 words apart: a lane reads four
+  // consecutive complex k of its row as two 16-byte loads, and 16 consecutive
+  // rows start on distinct multiples of 4 banks (36 r mod 64)
   static_assert(BK % 8 == 0, "whole 16-byte operand reads");
-  constexpr int kRow = BK + 4;
-  __shared__ __attribute__((aligned(16))) float Ar[BM][kRow], Ai[BM][kRow], Br[BN][kRow], Bi[BN][kRow];
+  constexpr int kRow = 2 * BK + 4;
+  __shared__ __attribute__((aligned(16))) float As[BM * kRow], Bs[BN * kRow];
   __shared__ int64_t TAm[BM], TCm[BM], TBn[BN], TCn[BN], TAk[BK], TBk[BK];
   constexpr int kKt = 64;  // K tiles whose origin deposits are tabulated (the rest computed on the fly)
   __shared__ int64_t TAt[kKt], TBt[kKt];
@@ -1238,31 +1240,31 @@ __global__ __launch_bounds__(kThreads, TM == 1 ? 4 : 2) void k_gemm3m(GemmArgs g
     for (int v = 0; v < 16; ++v) p1[i][v] = p2[i][v] = p3[i][v] = 0.f;
   __syncthreads();
 
-  // Staging order: each quarter-wave loads 16 elements that are contiguous in
-  // the operand (a 128-byte run), and the 64 LDS words a wave writes fall on
-  // distinct banks.  With rows kRow = 20 words apart, row r starts on bank
-  // 20 r mod 64 (distinct multiples of 4 for 16 consecutive rows):
-  //  - fast operand index along the rows (m or n): 16 consecutive rows times
-  //    four k per wave;
-  //  - k fastest: 16 k of rows r, r + 4, r + 8, r + 12 per wave (start banks
-  //    16 apart).
-  // A thread's slot for its element e is (row rt + row_e(e), k kt + k_e(e)):
-  // the thread part is fixed for the block, the element part a constant.
+  // Staging order (16-wide K tiles, four waves), element e of a thread at row
+  // rt + row_e(e), complex k kt + k_e(e) of its operand tile:
+  //  - k fastest in the operand: a quarter-wave loads 16 consecutive k of one
+  //    row (a 128-byte run) and writes them as 8-byte words; the two rows of
+  //    a half-wave are 8 apart (36 * 8 = 32 mod 64 banks), so its 64 words
+  //    fall on distinct banks;
+  //  - m or n fastest: a wave loads 64 consecutive rows at one k per load and
+  //    each thread writes its four consecutive k of a row as two 16-byte
+  //    words (16 consecutive rows per LDS cycle, distinct banks).
   static_assert(BK == 16 && kThreads == 256 && BN == 64, "staging order assumes 16-wide K tiles");
   auto slot_t = [&](bool k_fast, int& r, int& kk) {
     if (k_fast) {
-      kk = tid & 15;
-      r = 4 * ((tid >> 4) & 3) + ((tid >> 6) & 3);
+      r = w + 4 * ((lane >> 5) & 1) + 8 * ((lane >> 4) & 1);
+      kk = lane & 15;
     } else {
-      r = (tid & 15) + 16 * (tid >> 6);
-      kk = (tid >> 4) & 3;
+      r = lane;
+      kk = 4 * w;
     }
   };
-  auto row_e = [](bool k_fast, int rows, int e) { return k_fast ? 16 * e : 64 * (e % (rows / 64)); };
-  auto k_e = [](bool k_fast, int rows, int e) { return k_fast ? 0 : 4 * (e / (rows / 64)); };
+  auto row_e = [](bool k_fast, int e) { return k_fast ? 16 * e : 64 * (e >> 2); };
+  auto k_e = [](bool k_fast, int e) { return k_fast ? 0 : (e & 3); };
+  constexpr bool kfa = AK != 0, kfb = BNF == 0;
   int a_rt, a_kt, b_rt, b_kt;
-  slot_t(AK != 0, a_rt, a_kt);
-  slot_t(BNF == 0, b_rt, b_kt);
+  slot_t(kfa, a_rt, a_kt);
+  slot_t(kfb, b_rt, b_kt);
   // element offsets within a K tile, without the tile's origin: 32-bit byte
   // offsets from a block-uniform base when every offset of the tile stays
   // below 2^32 bytes (NW), else full pointers
@@ -1271,13 +1273,13 @@ __global__ __launch_bounds__(kThreads, TM == 1 ? 4 : 2) void k_gemm3m(GemmArgs g
   uint32_t oa[NW ? kPA : 1], ob[NW ? kPB : 1];
 #pragma unroll
   for (int e = 0; e < kPA; ++e) {
-    const int64_t off = TAm[a_rt + row_e(AK != 0, BM, e)] | TAk[a_kt + k_e(AK != 0, BM, e)];
+    const int64_t off = TAm[a_rt + row_e(kfa, e)] | TAk[a_kt + k_e(kfa, e)];
     if constexpr (NW) oa[e] = (uint32_t)off * (uint32_t)sizeof(float2);
     else pa[e] = A + (base_a | off);
   }
 #pragma unroll
   for (int e = 0; e < kPB; ++e) {
-    const int64_t off = TBn[b_rt + row_e(BNF == 0, BN, e)] | TBk[b_kt + k_e(BNF == 0, BN, e)];
+    const int64_t off = TBn[b_rt + row_e(kfb, e)] | TBk[b_kt + k_e(kfb, e)];
     if constexpr (NW) ob[e] = (uint32_t)off * (uint32_t)sizeof(float2);
     else pb[e] = B + (base_b | off);
   }
@@ -1312,31 +1314,30 @@ __global__ __launch_bounds__(kThreads, TM == 1 ? 4 : 2) void k_gemm3m(GemmArgs g
     } else {
 #pragma unroll
       for (int e = 0; e < kPA; ++e)
-        ra[e] = (m0 + a_rt + row_e(AK != 0, BM, e) < g.M && a_kt + k_e(AK != 0, BM, e) < kleft) ? lda(e)
-                                                                                               : f2(0.f, 0.f);
+        ra[e] = (m0 + a_rt + row_e(kfa, e) < g.M && a_kt + k_e(kfa, e) < kleft) ? lda(e) : f2(0.f, 0.f);
 #pragma unroll
       for (int e = 0; e < kPB; ++e)
-        rb[e] = (n0 + b_rt + row_e(BNF == 0, BN, e) < g.N && b_kt + k_e(BNF == 0, BN, e) < kleft) ? ldb(e)
-                                                                                                  : f2(0.f, 0.f);
+        rb[e] = (n0 + b_rt + row_e(kfb, e) < g.N && b_kt + k_e(kfb, e) < kleft) ? ldb(e) : f2(0.f, 0.f);
     }
   };
-  float* const ar_s = &Ar[a_rt][a_kt];
-  float* const ai_s = &Ai[a_rt][a_kt];
-  float* const br_s = &Br[b_rt][b_kt];
-  float* const bi_s = &Bi[b_rt][b_kt];
+  float* const as_t = As + a_rt * kRow + 2 * a_kt;
+  float* const bs_t = Bs + b_rt * kRow + 2 * b_kt;
+  auto put = [&](float* dst, bool k_fast, const float2* r, int n) {
+    if (k_fast) {
+#pragma unroll
+      for (int e = 0; e < n; ++e) *reinterpret_cast<float2*>(dst + row_e(true, e) * kRow) = r[e];
+    } else {
+#pragma unroll
+      for (int e = 0; e < n; e += 4) {
+        float* d = dst + row_e(false, e) * kRow;
+        *reinterpret_cast<float4*>(d) = make_float4(r[e].x, r[e].y, r[e + 1].x, r[e + 1].y);
+        *reinterpret_cast<float4*>(d + 4) = make_float4(r[e + 2].x, r[e + 2].y, r[e + 3].x, r[e + 3].y);
+      }
+    }
+  };
   auto stage = [&]() {
-#pragma unroll
-    for (int e = 0; e < kPA; ++e) {
-      const int o = row_e(AK != 0, BM, e) * kRow + k_e(AK != 0, BM, e);
-      ar_s[o] = ra[e].x;
-      ai_s[o] = ra[e].y;
-    }
-#pragma unroll
-    for (int e = 0; e < kPB; ++e) {
-      const int o = row_e(BNF == 0, BN, e) * kRow + k_e(BNF == 0, BN, e);
-      br_s[o] = rb[e].x;
-      bi_s[o] = rb[e].y;
-    }
+    put(as_t, kfa, ra, kPA);
+    put(bs_t, kfb, rb, kPB);
   };
   const int h = lane >> 5, r32 = lane & 31;
   const int col = wn * 32 + r32;
@@ -1351,17 +1352,18 @@ __global__ __launch_bounds__(kThreads, TM == 1 ? 4 : 2) void k_gemm3m(GemmArgs g
     constexpr int kHalf = BK / 2;
 #pragma unroll
     for (int hh = 0; hh < kHalf / 4; ++hh) {  // groups of four steps: four k values per lane and plane
-      const float4 b4 = *reinterpret_cast<const float4*>(&Br[col][kHalf * h + 4 * hh]);
-      const float4 c4 = *reinterpret_cast<const float4*>(&Bi[col][kHalf * h + 4 * hh]);
-      const float br[4] = {b4.x, b4.y, b4.z, b4.w}, bi[4] = {c4.x, c4.y, c4.z, c4.w};
+      const int kw = 2 * (kHalf * h + 4 * hh);  // word offset of the lane's four complex k
+      const float4 b0 = *reinterpret_cast<const float4*>(&Bs[col * kRow + kw]);
+      const float4 b1 = *reinterpret_cast<const float4*>(&Bs[col * kRow + kw + 4]);
+      const float br[4] = {b0.x, b0.z, b1.x, b1.z}, bi[4] = {b0.y, b0.w, b1.y, b1.w};
       float ar[TM][4], ai[TM][4];
 #pragma unroll
       for (int i = 0; i < TM; ++i) {
         const int row = wm * 32 * TM + i * 32 + r32;
-        const float4 a4 = *reinterpret_cast<const float4*>(&Ar[row][kHalf * h + 4 * hh]);
-        const float4 d4 = *reinterpret_cast<const float4*>(&Ai[row][kHalf * h + 4 * hh]);
-        ar[i][0] = a4.x; ar[i][1] = a4.y; ar[i][2] = a4.z; ar[i][3] = a4.w;
-        ai[i][0] = d4.x; ai[i][1] = d4.y; ai[i][2] = d4.z; ai[i][3] = d4.w;
+        const float4 a0 = *reinterpret_cast<const float4*>(&As[row * kRow + kw]);
+        const float4 a1 = *reinterpret_cast<const float4*>(&As[row * kRow + kw + 4]);
+        ar[i][0] = a0.x; ar[i][1] = a0.z; ar[i][2] = a1.x; ar[i][3] = a1.z;
+        ai[i][0] = a0.y; ai[i][1] = a0.w; ai[i][2] = a1.y; ai[i][3] = a1.w;
       }
 #pragma unroll
       for (int st = 0; st < 4; ++st) {
