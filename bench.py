@@ -339,8 +339,11 @@ class Gradients(Workload):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: 200 for configs 0-2, whose steps take under a millisecond; 20 else)")
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed warmup steps (default: 200 for configs 0-2, so that the GPU's clocks have "
+                         "ramped up before timing; 5 else)")
     ap.add_argument("--config", type=int, default=1, choices=[0, 1, 2, 3, 4])
     ap.add_argument("--path", default="search", help="search | greedy | sequential | random (configs 0, 1)")
     ap.add_argument("--trials", type=int, default=1024, help="randomised orders tried by each search")
@@ -357,6 +360,11 @@ def main():
                          "tuning record for this workload, when there is one and it matches the planned orders)")
     ap.add_argument("--retune", action="store_true", help="ignore stored tuning records")
     args = ap.parse_args()
+    short = args.config in (0, 1, 2)
+    if args.steps is None:
+        args.steps = 200 if short else 20
+    if args.warmup is None:
+        args.warmup = 200 if short else 5
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
