@@ -345,11 +345,15 @@ def main():
                     help="untimed warmup steps (default: 200 for configs 0-2, so that the GPU's clocks have "
                          "ramped up before timing; 5 else)")
     ap.add_argument("--config", type=int, default=1, choices=[0, 1, 2, 3, 4])
-    ap.add_argument("--path", default="search", help="search | greedy | sequential | random (configs 0, 1)")
+    ap.add_argument("--path", default=None,
+                    help="search | greedy | sequential | random (configs 0, 1; default: greedy for config 0, the "
+                         "order its workload names, search for config 1)")
     ap.add_argument("--trials", type=int, default=1024, help="randomised orders tried by each search")
     ap.add_argument("--plan-seeds", type=int, default=4,
                     help="searches with different seeds; the fastest measured order is kept")
-    ap.add_argument("--fuse", default="split", help="split | dense | none (configs 0, 1)")
+    ap.add_argument("--fuse", default=None,
+                    help="split | dense | none (configs 0, 1; default: none for config 0, the plain network of "
+                         "its gates, split for config 1)")
     ap.add_argument("--precision", default="c64", help="c64 | bf16x3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true", help="skip the parity check against the oracle")
@@ -361,6 +365,10 @@ def main():
     ap.add_argument("--retune", action="store_true", help="ignore stored tuning records")
     args = ap.parse_args()
     short = args.config in (0, 1, 2)
+    if args.path is None:
+        args.path = "greedy" if args.config == 0 else "search"
+    if args.fuse is None:
+        args.fuse = "none" if args.config == 0 else "split"
     if args.steps is None:
         args.steps = 200 if short else 20
     if args.warmup is None:
@@ -386,7 +394,8 @@ def main():
                          args.plan_seeds)
     elif args.config == 0:
         wl = Statevector(tnq, torch, workloads.config0(),
-                         "10-qubit random brickwork circuit, depth 8, full 2^10 complex64 statevector", fuse,
+                         f"10-qubit random brickwork circuit, depth 8, full 2^10 complex64 statevector, {args.path} "
+                         f"order, " + ("no gate fusion" if not fuse else f"{fuse} gate fusion"), fuse,
                          args.path, args.trials, args.precision, args.plan_seeds)
     elif args.config == 2:
         wl = Amplitudes(tnq, torch, args.trials, args.precision, args.plan_seeds)
