@@ -51,7 +51,7 @@ struct ElemMember {
   int32_t block0;
   int32_t out_bits;  // 2^out_bits result elements per batch item
   int32_t k_bits;    // 2^k_bits summed terms
-  int32_t pad;
+  int32_t lane_bits;  // 2^lane_bits adjacent lanes share one result's sum (set by the launcher)
   int8_t ao[kElemGroupOutBits], bo[kElemGroupOutBits], co[kElemGroupOutBits];
   int8_t ak[kElemKBits], bk[kElemKBits];
 };

@@ -1433,11 +1433,53 @@ __global__ __launch_bounds__(kThreads) void k_contract_elem(GemmArgs g) {
   }
 }
 
+constexpr int kElemChunks = (kElemGroupOutBits + 5) / 6;
+
+// A grouped member with long sums: thread t takes result o = t >> lane_bits
+// and the terms k = s, s + L, s + 2L, ... (s = t mod L, L = 2^lane_bits); the
+// L lanes of a result are adjacent lanes of one wave, leave the loop together
+// (2^(out_bits + lane_bits) is a multiple of L) and combine their partial sums
+// with cross-lane adds.
+template <int PREC>
+__device__ void elem_sum_lanes(const ElemMember& e, const int64_t* TO, const int64_t* TKa, const int64_t* TKb,
+                               const float2* A, const float2* B, float2* C, int blk, int nblk) {
+  const int lb = e.lane_bits, L = 1 << lb, s = threadIdx.x & (L - 1);
+  const int KL = (1 << e.k_bits) >> lb;  // terms per lane, at least 4
+  const int n_thr = 1 << (e.out_bits + lb);
+  for (int t = blk * kThreads + threadIdx.x; t < n_thr; t += nblk * kThreads) {
+    const int o = t >> lb;
+    int64_t ab = 0, bb = 0, cc = 0;
+#pragma unroll
+    for (int ch = 0; ch < kElemChunks; ++ch) {
+      const int i = ch * 64 + ((o >> (6 * ch)) & 63);
+      ab |= TO[i];
+      bb |= TO[kElemChunks * 64 + i];
+      cc |= TO[2 * kElemChunks * 64 + i];
+    }
+    float2 acc = f2(0.f, 0.f);
+    for (int j = 0; j < KL; j += 4) {  // four operand pairs in flight at a time
+      float2 av[4], bv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = s + ((j + u) << lb);
+        av[u] = A[ab | TKa[k]];
+        bv[u] = B[bb | TKb[k]];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc = cmac<PREC>(acc, av[u], bv[u]);
+    }
+    for (int off = L >> 1; off > 0; off >>= 1) {
+      acc.x += __shfl_xor(acc.x, off);
+      acc.y += __shfl_xor(acc.y, off);
+    }
+    if (s == 0) C[cc] = acc;
+  }
+}
+
 // Grouped form of the per-output products: every member's address maps are
 // turned into LDS tables (four 6-bit chunks of the result index, one table of
 // summed offsets per operand), so an output costs twelve table reads before
 // its sum.
-constexpr int kElemChunks = (kElemGroupOutBits + 5) / 6;
 template <int PREC>
 __global__ __launch_bounds__(kThreads) void k_elem_group(ElemGroupArgs g) {
   __shared__ int64_t TO[3 * kElemChunks * 64];  // [operand A, B, C][chunk][chunk value]
@@ -1479,6 +1521,10 @@ __global__ __launch_bounds__(kThreads) void k_elem_group(ElemGroupArgs g) {
   const float2* A = e.A + (int64_t)z * e.a_bs;
   const float2* B = e.B + (int64_t)z * e.b_bs;
   float2* C = e.C + (int64_t)z * e.c_bs;
+  if (e.lane_bits > 0) {
+    elem_sum_lanes<PREC>(e, TO, TKa, TKb, A, B, C, bx - e.block0, nblk);
+    return;
+  }
   const int n_out = 1 << ob;
   for (int o = (bx - e.block0) * kThreads + threadIdx.x; o < n_out; o += nblk * kThreads) {
     int64_t ab = 0, bb = 0, cc = 0;
@@ -1518,7 +1564,7 @@ ElemMember elem_member(const GemmDesc& d, const float2* a, int64_t a_bs, const f
   m.block0 = 0;  // laid out by the launcher
   m.out_bits = d.nbb + d.nbm + d.nbn;
   m.k_bits = d.nbk;
-  m.pad = 0;
+  m.lane_bits = 0;  // laid out by the launcher
   // result index bits: n lowest, then m, then batch
   for (int j = 0; j < kElemGroupOutBits; ++j) {
     m.ao[j] = m.bo[j] = m.co[j] = -1;
@@ -1544,13 +1590,19 @@ ElemMember elem_member(const GemmDesc& d, const float2* a, int64_t a_bs, const f
 hipError_t launch_elem_group(hipStream_t s, const ElemGroupArgs& a, int batch, int precision) {
   if (a.n < 1 || a.n > kElemGroupMax || batch < 1) return hipErrorInvalidValue;
   ElemGroupArgs g = a;
-  int32_t blocks = 0;  // one thread per result element
+  int32_t blocks = 0;
   for (int i = 0; i < g.n; ++i) {
     ElemMember& m = g.m[i];
     if (m.out_bits < 0 || m.out_bits > kElemGroupOutBits || m.k_bits < 0 || m.k_bits > kElemKBits)
       return hipErrorInvalidValue;
+    // one thread per result, or for sums of 128 terms and more 2^lane_bits
+    // lanes per result, about eight terms each (at most 32 lanes, and at most
+    // 2^20 threads for the member)
+    int lb = m.k_bits >= 7 ? std::min(m.k_bits - 3, 5) : 0;
+    while (lb > 0 && m.out_bits + lb > 20) --lb;
+    m.lane_bits = lb;
     m.block0 = blocks;
-    blocks += (int32_t)((((int64_t)1 << m.out_bits) + kThreads - 1) / kThreads);
+    blocks += (int32_t)((((int64_t)1 << (m.out_bits + lb)) + kThreads - 1) / kThreads);
   }
   g.total_blocks = blocks;
   const void* fn = precision == TN_PREC_BF16X3 ? (const void*)k_elem_group<TN_PREC_BF16X3>

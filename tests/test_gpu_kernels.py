@@ -34,7 +34,7 @@ def run_pair(a, ma, b, mb, mc, precision="c64"):
 @pytest.mark.parametrize("M,N,K", [(1, 1, 1), (2, 2, 2), (4, 4, 4), (32, 16, 2), (64, 64, 64), (128, 64, 16),
                                    (256, 128, 32), (512, 512, 512), (2, 1024, 2), (1024, 2, 4), (16, 256, 1024),
                                    (8, 8, 4096), (32, 32768, 4), (16, 1 << 20, 2), (4, 1 << 23, 1), (64, 64, 8192),
-                                   (128, 64, 4096)])
+                                   (128, 64, 4096), (1, 4096, 256), (32, 64, 128), (1, 1, 1024)])
 def test_matmul_eq22(M, N, K):
     """Z^i_j = M^i_k L^k_j (eq. (2.2)) through the matrix-product kernel."""
     print(f"matmul M={M} N={N} K={K}", flush=True)
