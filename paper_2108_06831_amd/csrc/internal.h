@@ -192,11 +192,13 @@ struct GemmDesc {
   BufRef tmp;
 };
 // tiles 0-3: real-embedding (4M) MFMA tiles; 4: vector kernel; 5-6: 3M MFMA
-// tiles (FP32 only)
+// tiles (FP32 only); 7: 3M, batch-packed (four batch items of at most 32 x 32
+// per block, one per wave; batch of at least 4, FP32 only)
 constexpr int kGemmVector = 4;
-constexpr int kGemmTiles = 7;
-constexpr int kGemmTileM[kGemmTiles] = {128, 128, 64, 64, 1, 128, 64};
-constexpr int kGemmTileN[kGemmTiles] = {64, 32, 64, 32, 1, 64, 64};
+constexpr int kGemmBatchPacked = 7;
+constexpr int kGemmTiles = 8;
+constexpr int kGemmTileM[kGemmTiles] = {128, 128, 64, 64, 1, 128, 64, 32};
+constexpr int kGemmTileN[kGemmTiles] = {64, 32, 64, 32, 1, 64, 64, 32};
 constexpr int kGemmMaxSplit = 8;
 constexpr int kGemmBK = 16;      // complex k per staged K tile of the MFMA kernels
 constexpr int kElemMaxK = 1024;  // longest K of the per-output kernel

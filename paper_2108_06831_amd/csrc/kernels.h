@@ -35,6 +35,9 @@ hipError_t launch_permute(hipStream_t s, const PermuteDesc& d, const float2* in,
 // (< kGemmVector: MFMA tile shape; kGemmVector: one output per thread on the
 // vector ALUs) and `split` (K ranges, partials in `tmp` = [split][C], summed
 // into C) choose the launch shape.
+// Whether launch shape `tile` can run product d (the batch-packed tile needs
+// M, N <= 32, a batch of at least 4 and tile offsets below 2^32 bytes).
+bool gemm_tile_supported(const GemmDesc& d, int tile);
 hipError_t launch_gemm(hipStream_t s, const GemmDesc& d, int tile, int split, const float2* a, int64_t a_bs,
                        const float2* b, int64_t b_bs, float2* c, int64_t c_bs, float2* tmp, int64_t tmp_bs, int batch,
                        int precision);

@@ -1178,9 +1178,12 @@ __global__ __launch_bounds__(kThreads) void k_gemm(GemmArgs g) {
 // complex tile keeps three accumulators (P1 = Ar Br, P2 = Ai Bi,
 // P3 = (Ar + Ai)(Br + Bi)).  Four waves in a 2 x 2 arrangement, each owning
 // TM tiles of 32 x 32 complex: the block computes (64 TM) x 64.
-template <int AK, int BNF, int TM, int BK, int NW>
-__global__ __launch_bounds__(kThreads, TM == 1 ? 4 : 2) void k_gemm3m(GemmArgs g) {
-  constexpr int BM = 64 * TM, BN = 64;
+template <int AK, int BNF, int TM, int BK, int NW, int BP>
+__global__ __launch_bounds__(kThreads, TM == 1 && !BP ? 4 : 2) void k_gemm3m(GemmArgs g) {
+  // BP (batch-packed): four batch items of at most 32 x 32 per block, wave w
+  // computing item w; operand "rows" are (item, m) for A and (item, n) for B
+  static_assert(!BP || TM == 1, "batch-packed blocks hold one 32 x 32 tile per wave");
+  constexpr int BM = BP ? 128 : 64 * TM, BN = BP ? 128 : 64;
   constexpr int kPA = (BM * BK) / kThreads, kPB = (BN * BK) / kThreads;
   constexpr int kLogBK = BK == 32 ? 5 : 4;
   // operands staged as interleaved complex with k contiguous per row of A and
@@ -1200,8 +1203,9 @@ __global__ __launch_bounds__(kThreads, TM == 1 ? 4 : 2) void k_gemm3m(GemmArgs g
   bid /= g.tiles_m;
   const int64_t ks = bid % g.split;
   bid /= g.split;
-  const int64_t gb = bid % g.batch;
-  const int64_t z = bid / g.batch;
+  const int64_t n_bgroups = BP ? g.batch / 4 : g.batch;
+  const int64_t gb = (bid % n_bgroups) * (BP ? 4 : 1);
+  const int64_t z = bid / n_bgroups;
   const float2* A = g.A + z * g.a_bs;
   const float2* B = g.B + z * g.b_bs;
   float2* C = g.C + z * g.c_bs + ks * g.c_elems;
@@ -1214,15 +1218,25 @@ __global__ __launch_bounds__(kThreads, TM == 1 ? 4 : 2) void k_gemm3m(GemmArgs g
   const int64_t base_b = deposit(gb, g.b_b, g.nbb) | deposit(n0, g.b_n, g.nbn);
   const int64_t base_c = deposit(gb, g.c_b, g.nbb) | deposit(m0, g.c_m, g.nbm) | deposit(n0, g.c_n, g.nbn);
   constexpr int kLogBM = 6 + (TM == 2);
-  if (tid < BM) {
-    const int nb = min(g.nbm, kLogBM);
-    TAm[tid] = deposit(tid, g.a_m, nb);
-    TCm[tid] = deposit(tid, g.c_m, nb);
-  }
-  if (tid < BN) {
-    const int nb = min(g.nbn, 6);
-    TBn[tid] = deposit(tid, g.b_n, nb);
-    TCn[tid] = deposit(tid, g.c_n, nb);
+  if constexpr (BP) {
+    if (tid < 128) {  // row tid: item tid >> 5 (the two lowest batch bits), m or n tid & 31
+      const int it = tid >> 5, r = tid & 31, nbi = min(g.nbb, 2);
+      TAm[tid] = deposit(r, g.a_m, min(g.nbm, 5)) | deposit(it, g.a_b, nbi);
+      TCm[tid] = deposit(r, g.c_m, min(g.nbm, 5)) | deposit(it, g.c_b, nbi);
+      TBn[tid] = deposit(r, g.b_n, min(g.nbn, 5)) | deposit(it, g.b_b, nbi);
+      TCn[tid] = deposit(r, g.c_n, min(g.nbn, 5));
+    }
+  } else {
+    if (tid < BM) {
+      const int nb = min(g.nbm, kLogBM);
+      TAm[tid] = deposit(tid, g.a_m, nb);
+      TCm[tid] = deposit(tid, g.c_m, nb);
+    }
+    if (tid < BN) {
+      const int nb = min(g.nbn, 6);
+      TBn[tid] = deposit(tid, g.b_n, nb);
+      TCn[tid] = deposit(tid, g.c_n, nb);
+    }
   }
   if (tid < BK) {
     const int nb = min(g.nbk, kLogBK);
@@ -1249,7 +1263,7 @@ __global__ __launch_bounds__(kThreads, TM == 1 ? 4 : 2) void k_gemm3m(GemmArgs g
   //  - m or n fastest: a wave loads 64 consecutive rows at one k per load and
   //    each thread writes its four consecutive k of a row as two 16-byte
   //    words (16 consecutive rows per LDS cycle, distinct banks).
-  static_assert(BK == 16 && kThreads == 256 && BN == 64, "staging order assumes 16-wide K tiles");
+  static_assert(BK == 16 && kThreads == 256 && (BN == 64 || BN == 128), "staging order assumes 16-wide K tiles");
   auto slot_t = [&](bool k_fast, int& r, int& kk) {
     if (k_fast) {
       r = w + 4 * ((lane >> 5) & 1) + 8 * ((lane >> 4) & 1);
@@ -1283,7 +1297,10 @@ __global__ __launch_bounds__(kThreads, TM == 1 ? 4 : 2) void k_gemm3m(GemmArgs g
     if constexpr (NW) ob[e] = (uint32_t)off * (uint32_t)sizeof(float2);
     else pb[e] = B + (base_b | off);
   }
-  const bool interior = m0 + BM <= g.M && n0 + BN <= g.N;
+  const bool interior = BP ? g.M == 32 && g.N == 32 : m0 + BM <= g.M && n0 + BN <= g.N;
+  // whether tile row r of A (of B) lies inside the operand
+  auto a_in = [&](int r) { return BP ? (r & 31) < g.M : m0 + r < g.M; };
+  auto b_in = [&](int r) { return BP ? (r & 31) < g.N : n0 + r < g.N; };
   float2 ra[kPA], rb[kPB];
   auto fetch = [&](int64_t k0) {
     const int64_t t = (k0 - kbeg) / BK;
@@ -1314,10 +1331,10 @@ __global__ __launch_bounds__(kThreads, TM == 1 ? 4 : 2) void k_gemm3m(GemmArgs g
     } else {
 #pragma unroll
       for (int e = 0; e < kPA; ++e)
-        ra[e] = (m0 + a_rt + row_e(kfa, e) < g.M && a_kt + k_e(kfa, e) < kleft) ? lda(e) : f2(0.f, 0.f);
+        ra[e] = (a_in(a_rt + row_e(kfa, e)) && a_kt + k_e(kfa, e) < kleft) ? lda(e) : f2(0.f, 0.f);
 #pragma unroll
       for (int e = 0; e < kPB; ++e)
-        rb[e] = (n0 + b_rt + row_e(kfb, e) < g.N && b_kt + k_e(kfb, e) < kleft) ? ldb(e) : f2(0.f, 0.f);
+        rb[e] = (b_in(b_rt + row_e(kfb, e)) && b_kt + k_e(kfb, e) < kleft) ? ldb(e) : f2(0.f, 0.f);
     }
   };
   float* const as_t = As + a_rt * kRow + 2 * a_kt;
@@ -1340,7 +1357,7 @@ __global__ __launch_bounds__(kThreads, TM == 1 ? 4 : 2) void k_gemm3m(GemmArgs g
     put(bs_t, kfb, rb, kPB);
   };
   const int h = lane >> 5, r32 = lane & 31;
-  const int col = wn * 32 + r32;
+  const int col = BP ? 32 * w + r32 : wn * 32 + r32;
   fetch(kbeg);
   for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
     stage();
@@ -1359,7 +1376,7 @@ __global__ __launch_bounds__(kThreads, TM == 1 ? 4 : 2) void k_gemm3m(GemmArgs g
       float ar[TM][4], ai[TM][4];
 #pragma unroll
       for (int i = 0; i < TM; ++i) {
-        const int row = wm * 32 * TM + i * 32 + r32;
+        const int row = BP ? 32 * w + r32 : wm * 32 * TM + i * 32 + r32;
         const float4 a0 = *reinterpret_cast<const float4*>(&As[row * kRow + kw]);
         const float4 a1 = *reinterpret_cast<const float4*>(&As[row * kRow + kw + 4]);
         ar[i][0] = a0.x; ar[i][1] = a0.z; ar[i][2] = a1.x; ar[i][3] = a1.z;
@@ -1382,9 +1399,9 @@ __global__ __launch_bounds__(kThreads, TM == 1 ? 4 : 2) void k_gemm3m(GemmArgs g
   for (int i = 0; i < TM; ++i)
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
-      const int rl = wm * 32 * TM + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
-      const int cl = wn * 32 + r32;
-      if (m0 + rl < g.M && n0 + cl < g.N) {
+      const int rl = (BP ? 32 * w : wm * 32 * TM + i * 32) + 8 * (v >> 2) + 4 * h + (v & 3);
+      const int cl = BP ? r32 : wn * 32 + r32;
+      if (a_in(rl) && (BP ? cl < g.N : n0 + cl < g.N)) {
         const float a = p1[i][v], b = p2[i][v];
         C[base_c | TCm[rl] | TCn[cl]] = f2(a - b, p3[i][v] - a - b);
       }
@@ -1633,12 +1650,12 @@ static void* gemm_fn(int ak, int bnf) {
   return (void*)k_gemm<0, 0, TM, TN, F>;
 }
 
-template <int TM, int BK, int NW>
+template <int TM, int BK, int NW, int BP = 0>
 static void* gemm3m_fn_nw(int ak, int bnf) {
-  if (ak && bnf) return (void*)k_gemm3m<1, 1, TM, BK, NW>;
-  if (ak) return (void*)k_gemm3m<1, 0, TM, BK, NW>;
-  if (bnf) return (void*)k_gemm3m<0, 1, TM, BK, NW>;
-  return (void*)k_gemm3m<0, 0, TM, BK, NW>;
+  if (ak && bnf) return (void*)k_gemm3m<1, 1, TM, BK, NW, BP>;
+  if (ak) return (void*)k_gemm3m<1, 0, TM, BK, NW, BP>;
+  if (bnf) return (void*)k_gemm3m<0, 1, TM, BK, NW, BP>;
+  return (void*)k_gemm3m<0, 0, TM, BK, NW, BP>;
 }
 
 template <int TM, int BK>
@@ -1654,23 +1671,44 @@ static void* gemm_fn_tile(int tile, int ak, int bnf, bool narrow) {
     case 2: return gemm_fn<1, 2, F>(ak, bnf);
     case 3: return gemm_fn<1, 1, F>(ak, bnf);
     case 5: return gemm3m_fn<2, 16>(ak, bnf, narrow);
+    case 7: return narrow ? gemm3m_fn_nw<1, 16, 1, 1>(ak, bnf) : nullptr;
     default: return gemm3m_fn<1, 16>(ak, bnf, narrow);
   }
 }
 
 // Whether every element offset inside one operand tile (its tile-local m or n
-// bits and k bits, without the tile's origin) is below 2^32 bytes.
-static bool tile_offsets_narrow(const int8_t* pos_mn, int n_mn, const int8_t* pos_k, int n_k) {
+// bits, k bits and, batch-packed, batch bits, without the tile's origin) is
+// below 2^32 bytes.
+static bool tile_offsets_narrow(const int8_t* pos_mn, int n_mn, const int8_t* pos_k, int n_k,
+                                const int8_t* pos_b = nullptr, int n_b = 0) {
   int top = -1;
   for (int j = 0; j < n_mn; ++j) top = pos_mn[j] > top ? pos_mn[j] : top;
   for (int j = 0; j < n_k; ++j) top = pos_k[j] > top ? pos_k[j] : top;
+  for (int j = 0; j < n_b; ++j) top = pos_b[j] > top ? pos_b[j] : top;
   return top + 1 + 3 <= 32;  // 8-byte elements
+}
+
+static bool tile_narrow(const GemmDesc& d, int tile) {
+  const int lbk = std::min(d.nbk, 4);
+  if (tile == kGemmBatchPacked)
+    return tile_offsets_narrow(d.a_m, std::min(d.nbm, 5), d.a_k, lbk, d.a_b, std::min(d.nbb, 2)) &&
+           tile_offsets_narrow(d.b_n, std::min(d.nbn, 5), d.b_k, lbk, d.b_b, std::min(d.nbb, 2));
+  const int lbm = kGemmTileM[tile] == 128 ? 7 : 6, lbn = kGemmTileN[tile] == 64 ? 6 : 5;
+  return tile_offsets_narrow(d.a_m, std::min(d.nbm, lbm), d.a_k, lbk) &&
+         tile_offsets_narrow(d.b_n, std::min(d.nbn, lbn), d.b_k, lbk);
+}
+
+bool gemm_tile_supported(const GemmDesc& d, int tile) {
+  if (tile < 0 || tile >= kGemmTiles) return false;
+  if (tile != kGemmBatchPacked) return true;
+  // four whole batch items of at most 32 x 32 per block, 32-bit tile offsets
+  return d.M <= 32 && d.N <= 32 && d.nbb >= 2 && tile_narrow(d, tile);
 }
 
 hipError_t launch_gemm(hipStream_t s, const GemmDesc& d, int tile, int split, const float2* a, int64_t a_bs,
                        const float2* b, int64_t b_bs, float2* c, int64_t c_bs, float2* tmp, int64_t tmp_bs, int batch,
                        int precision) {
-  if (tile < 0 || tile >= kGemmTiles) return hipErrorInvalidValue;
+  if (!gemm_tile_supported(d, tile)) return hipErrorInvalidValue;
   if (tile > kGemmVector && precision != TN_PREC_C64) return hipErrorInvalidValue;  // 3M: FP32 only
   GemmArgs g;
   g.A = a; g.B = b;
@@ -1715,11 +1753,10 @@ hipError_t launch_gemm(hipStream_t s, const GemmDesc& d, int tile, int split, co
   }
   g.tiles_m = (d.M + kGemmTileM[tile] - 1) / kGemmTileM[tile];
   g.tiles_n = (d.N + kGemmTileN[tile] - 1) / kGemmTileN[tile];
-  const int64_t blocks = g.tiles_m * g.tiles_n * g.split * d.batch * batch;
+  const int64_t batch_blocks = tile == kGemmBatchPacked ? d.batch / 4 : d.batch;
+  const int64_t blocks = g.tiles_m * g.tiles_n * g.split * batch_blocks * batch;
   if (blocks > ((int64_t)1 << 24)) return hipErrorInvalidValue;  // grid of < 2^32 work-items
-  const int lbm = kGemmTileM[tile] == 128 ? 7 : 6, lbn = kGemmTileN[tile] == 64 ? 6 : 5, lbk = 4;
-  const bool narrow = tile_offsets_narrow(d.a_m, std::min(d.nbm, lbm), d.a_k, std::min(d.nbk, lbk)) &&
-                      tile_offsets_narrow(d.b_n, std::min(d.nbn, lbn), d.b_k, std::min(d.nbk, lbk));
+  const bool narrow = tile_narrow(d, tile);
   void* fn = precision == TN_PREC_BF16X3 ? gemm_fn_tile<1>(tile, d.a_kfast, d.b_nfast, narrow)
                                          : gemm_fn_tile<0>(tile, d.a_kfast, d.b_nfast, narrow);
   void* args[] = {&g};

@@ -910,7 +910,7 @@ extern "C" void tn_graph_destroy(tn_graph* g) {
 // launch-shape autotuner
 // ---------------------------------------------------------------------------
 static bool gemm_shape_ok(const GemmDesc& g, int tile, int split, int precision) {
-  if (tile < 0 || tile >= kGemmTiles) return false;
+  if (!gemm_tile_supported(g, tile)) return false;
   if (tile > kGemmVector && precision != TN_PREC_C64) return false;  // 3M tiles: FP32 only
   if (split != 1 && split != 2 && split != 4 && split != 8) return false;
   if (tile == kGemmVector) return split == 1 && g.K <= kElemMaxK;
