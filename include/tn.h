@@ -332,7 +332,9 @@ tn_status tn_autotune(void* stream, int32_t precision, tn_network* net, tn_path*
  * 4 = vector kernel (K <= 1024 only, split 1); 5, 6 = MFMA tiles 128x64,
  * 64x64 in the three-product (3M) form (TN_PREC_C64 only); 7 = 3M,
  * batch-packed: four batch items of at most 32 x 32 per workgroup, one per
- * wave (TN_PREC_C64, M and N <= 32, a batch of at least 4 only).
+ * wave (TN_PREC_C64, M and N <= 32, a batch of at least 4 only); 8 = 3M,
+ * column-packed: M <= 32 and four 32-column slices of N per workgroup, one
+ * per wave (TN_PREC_C64, N >= 64 only).
  * split: 1, 2, 4 or 8, dividing K, at most the step's reserved
  * maximum.  transposed: 0 computes C = A B, 1 computes C = B^T A^T (operands
  * trade places; same result layout).  TN_EINVAL for a step that is not a

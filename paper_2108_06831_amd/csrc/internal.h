@@ -193,12 +193,15 @@ struct GemmDesc {
 };
 // tiles 0-3: real-embedding (4M) MFMA tiles; 4: vector kernel; 5-6: 3M MFMA
 // tiles (FP32 only); 7: 3M, batch-packed (four batch items of at most 32 x 32
-// per block, one per wave; batch of at least 4, FP32 only)
+// per block, one per wave; batch of at least 4, FP32 only); 8: 3M,
+// column-packed (M <= 32, four 32-column slices of N per block, one per wave;
+// FP32 only)
 constexpr int kGemmVector = 4;
 constexpr int kGemmBatchPacked = 7;
-constexpr int kGemmTiles = 8;
-constexpr int kGemmTileM[kGemmTiles] = {128, 128, 64, 64, 1, 128, 64, 32};
-constexpr int kGemmTileN[kGemmTiles] = {64, 32, 64, 32, 1, 64, 64, 32};
+constexpr int kGemmColumnPacked = 8;
+constexpr int kGemmTiles = 9;
+constexpr int kGemmTileM[kGemmTiles] = {128, 128, 64, 64, 1, 128, 64, 32, 32};
+constexpr int kGemmTileN[kGemmTiles] = {64, 32, 64, 32, 1, 64, 64, 32, 128};
 constexpr int kGemmMaxSplit = 8;
 constexpr int kGemmBK = 16;      // complex k per staged K tile of the MFMA kernels
 constexpr int kElemMaxK = 1024;  // longest K of the per-output kernel

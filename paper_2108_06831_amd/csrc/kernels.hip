@@ -1180,9 +1180,12 @@ __global__ __launch_bounds__(kThreads) void k_gemm(GemmArgs g) {
 // TM tiles of 32 x 32 complex: the block computes (64 TM) x 64.
 template <int AK, int BNF, int TM, int BK, int NW, int BP>
 __global__ __launch_bounds__(kThreads, TM == 1 && !BP ? 4 : 2) void k_gemm3m(GemmArgs g) {
-  // BP (batch-packed): four batch items of at most 32 x 32 per block, wave w
-  // computing item w; operand "rows" are (item, m) for A and (item, n) for B
-  static_assert(!BP || TM == 1, "batch-packed blocks hold one 32 x 32 tile per wave");
+  // BP = 1 (batch-packed): four batch items of at most 32 x 32 per block, wave
+  // w computing item w; operand "rows" are (item, m) for A and (item, n) for
+  // B.  BP = 2 (column-packed): M <= 32 and four 32-column slices of N per
+  // block, wave w computing slice w; A's rows repeat per slice, B's rows are
+  // n - n0.
+  static_assert(!BP || TM == 1, "packed blocks hold one 32 x 32 tile per wave");
   constexpr int BM = BP ? 128 : 64 * TM, BN = BP ? 128 : 64;
   constexpr int kPA = (BM * BK) / kThreads, kPB = (BN * BK) / kThreads;
   constexpr int kLogBK = BK == 32 ? 5 : 4;
@@ -1203,8 +1206,8 @@ __global__ __launch_bounds__(kThreads, TM == 1 && !BP ? 4 : 2) void k_gemm3m(Gem
   bid /= g.tiles_m;
   const int64_t ks = bid % g.split;
   bid /= g.split;
-  const int64_t n_bgroups = BP ? g.batch / 4 : g.batch;
-  const int64_t gb = (bid % n_bgroups) * (BP ? 4 : 1);
+  const int64_t n_bgroups = BP == 1 ? g.batch / 4 : g.batch;
+  const int64_t gb = (bid % n_bgroups) * (BP == 1 ? 4 : 1);
   const int64_t z = bid / n_bgroups;
   const float2* A = g.A + z * g.a_bs;
   const float2* B = g.B + z * g.b_bs;
@@ -1218,12 +1221,20 @@ __global__ __launch_bounds__(kThreads, TM == 1 && !BP ? 4 : 2) void k_gemm3m(Gem
   const int64_t base_b = deposit(gb, g.b_b, g.nbb) | deposit(n0, g.b_n, g.nbn);
   const int64_t base_c = deposit(gb, g.c_b, g.nbb) | deposit(m0, g.c_m, g.nbm) | deposit(n0, g.c_n, g.nbn);
   constexpr int kLogBM = 6 + (TM == 2);
-  if constexpr (BP) {
+  if constexpr (BP == 1) {
     if (tid < 128) {  // row tid: item tid >> 5 (the two lowest batch bits), m or n tid & 31
       const int it = tid >> 5, r = tid & 31, nbi = min(g.nbb, 2);
       TAm[tid] = deposit(r, g.a_m, min(g.nbm, 5)) | deposit(it, g.a_b, nbi);
       TCm[tid] = deposit(r, g.c_m, min(g.nbm, 5)) | deposit(it, g.c_b, nbi);
       TBn[tid] = deposit(r, g.b_n, min(g.nbn, 5)) | deposit(it, g.b_b, nbi);
+      TCn[tid] = deposit(r, g.c_n, min(g.nbn, 5));
+    }
+  } else if constexpr (BP == 2) {
+    if (tid < 128) {  // row tid of A: slice tid >> 5, m tid & 31; row tid of B: n - n0 = tid
+      const int r = tid & 31;
+      TAm[tid] = deposit(r, g.a_m, min(g.nbm, 5));
+      TCm[tid] = deposit(r, g.c_m, min(g.nbm, 5)) | deposit(tid & ~31, g.c_n, min(g.nbn, 7));
+      TBn[tid] = deposit(tid, g.b_n, min(g.nbn, 7));
       TCn[tid] = deposit(r, g.c_n, min(g.nbn, 5));
     }
   } else {
@@ -1297,10 +1308,12 @@ __global__ __launch_bounds__(kThreads, TM == 1 && !BP ? 4 : 2) void k_gemm3m(Gem
     if constexpr (NW) ob[e] = (uint32_t)off * (uint32_t)sizeof(float2);
     else pb[e] = B + (base_b | off);
   }
-  const bool interior = BP ? g.M == 32 && g.N == 32 : m0 + BM <= g.M && n0 + BN <= g.N;
+  const bool interior = BP == 1   ? g.M == 32 && g.N == 32
+                        : BP == 2 ? g.M == 32 && n0 + BN <= g.N
+                                  : m0 + BM <= g.M && n0 + BN <= g.N;
   // whether tile row r of A (of B) lies inside the operand
   auto a_in = [&](int r) { return BP ? (r & 31) < g.M : m0 + r < g.M; };
-  auto b_in = [&](int r) { return BP ? (r & 31) < g.N : n0 + r < g.N; };
+  auto b_in = [&](int r) { return BP == 1 ? (r & 31) < g.N : n0 + r < g.N; };
   float2 ra[kPA], rb[kPB];
   auto fetch = [&](int64_t k0) {
     const int64_t t = (k0 - kbeg) / BK;
@@ -1401,7 +1414,7 @@ __global__ __launch_bounds__(kThreads, TM == 1 && !BP ? 4 : 2) void k_gemm3m(Gem
     for (int v = 0; v < 16; ++v) {
       const int rl = (BP ? 32 * w : wm * 32 * TM + i * 32) + 8 * (v >> 2) + 4 * h + (v & 3);
       const int cl = BP ? r32 : wn * 32 + r32;
-      if (a_in(rl) && (BP ? cl < g.N : n0 + cl < g.N)) {
+      if (a_in(rl) && (BP == 1 ? cl < g.N : BP == 2 ? n0 + 32 * w + cl < g.N : n0 + cl < g.N)) {
         const float a = p1[i][v], b = p2[i][v];
         C[base_c | TCm[rl] | TCn[cl]] = f2(a - b, p3[i][v] - a - b);
       }
@@ -1672,6 +1685,7 @@ static void* gemm_fn_tile(int tile, int ak, int bnf, bool narrow) {
     case 3: return gemm_fn<1, 1, F>(ak, bnf);
     case 5: return gemm3m_fn<2, 16>(ak, bnf, narrow);
     case 7: return narrow ? gemm3m_fn_nw<1, 16, 1, 1>(ak, bnf) : nullptr;
+    case 8: return narrow ? gemm3m_fn_nw<1, 16, 1, 2>(ak, bnf) : nullptr;
     default: return gemm3m_fn<1, 16>(ak, bnf, narrow);
   }
 }
@@ -1693,6 +1707,9 @@ static bool tile_narrow(const GemmDesc& d, int tile) {
   if (tile == kGemmBatchPacked)
     return tile_offsets_narrow(d.a_m, std::min(d.nbm, 5), d.a_k, lbk, d.a_b, std::min(d.nbb, 2)) &&
            tile_offsets_narrow(d.b_n, std::min(d.nbn, 5), d.b_k, lbk, d.b_b, std::min(d.nbb, 2));
+  if (tile == kGemmColumnPacked)
+    return tile_offsets_narrow(d.a_m, std::min(d.nbm, 5), d.a_k, lbk) &&
+           tile_offsets_narrow(d.b_n, std::min(d.nbn, 7), d.b_k, lbk);
   const int lbm = kGemmTileM[tile] == 128 ? 7 : 6, lbn = kGemmTileN[tile] == 64 ? 6 : 5;
   return tile_offsets_narrow(d.a_m, std::min(d.nbm, lbm), d.a_k, lbk) &&
          tile_offsets_narrow(d.b_n, std::min(d.nbn, lbn), d.b_k, lbk);
@@ -1700,9 +1717,11 @@ static bool tile_narrow(const GemmDesc& d, int tile) {
 
 bool gemm_tile_supported(const GemmDesc& d, int tile) {
   if (tile < 0 || tile >= kGemmTiles) return false;
-  if (tile != kGemmBatchPacked) return true;
-  // four whole batch items of at most 32 x 32 per block, 32-bit tile offsets
-  return d.M <= 32 && d.N <= 32 && d.nbb >= 2 && tile_narrow(d, tile);
+  if (tile == kGemmBatchPacked)  // four whole batch items of at most 32 x 32 per block
+    return d.M <= 32 && d.N <= 32 && d.nbb >= 2 && tile_narrow(d, tile);
+  if (tile == kGemmColumnPacked)  // M <= 32, four 32-column slices per block
+    return d.M <= 32 && d.N >= 64 && tile_narrow(d, tile);
+  return true;
 }
 
 hipError_t launch_gemm(hipStream_t s, const GemmDesc& d, int tile, int split, const float2* a, int64_t a_bs,

@@ -146,7 +146,7 @@ def test_every_gemm_launch_shape(precision):
     tried = 0
     for s, (t0, s0, o0) in shapes.items():
         for tr in (0, 1):
-            for tile in range(8):
+            for tile in range(9):
                 for split in (1, 2, 4, 8):
                     try:
                         path.set_gemm_config(s, tile, split, tr, precision)
@@ -233,27 +233,30 @@ def test_wide_tile_offsets():
 
 @pytest.mark.parametrize("grid", ["4x6", "4x8"])
 def test_batch_packed_tile(grid):
-    """The batch-packed matrix-core tile (four batch items of at most 32 x 32
-    per workgroup) on every product step of a grid circuit's amplitude
-    network that admits it: ragged items (M, N in 1..16) and sums of 1 to
-    256 terms on the 4x6 grid, against its statevector; whole 32 x 32 items
-    with 8 and 32 terms on the 32-qubit grid, sampled amplitudes against the
-    oracle's contraction of each."""
+    """The packed matrix-core tiles on every product step of a grid
+    circuit's amplitude network that admits one: batch-packed (four batch
+    items of at most 32 x 32 per workgroup) where it fits, else
+    column-packed (M <= 32, four 32-column slices).  Ragged items (M, N in
+    1..16) and sums of 1 to 256 terms on the 4x6 grid, against its
+    statevector; whole 32 x 32 items with 8 and 32 terms on the 32-qubit
+    grid, sampled amplitudes against the oracle's contraction of each."""
     import workloads
     from paper_2108_06831_amd import Network, TNError, amplitudes
     rows, cols = (4, 6) if grid == "4x6" else (4, 8)
     circ, bits = workloads.config2(rows, cols, 12, n_bitstrings=4096)
     net = Network.from_circuit(circ, output="amplitudes", n_bitstrings=4096)
     path = net.plan("search", max_log2_intermediate=28, trials=64, seed=1)
-    packed = []
+    packed, columns = [], []
     for s in path.gemm_configs():
-        try:
-            path.set_gemm_config(s, 7, 1, 0, "c64")
-            packed.append(path.step(s)["bmnk"])
-        except TNError:
-            pass
-    print(f"grid {grid}: {len(packed)} products on the batch-packed tile: {sorted(set(packed))}", flush=True)
-    assert packed
+        for tile, got in ((7, packed), (8, columns)):
+            try:
+                path.set_gemm_config(s, tile, 1, 0, "c64")
+                got.append(path.step(s)["bmnk"])
+                break
+            except TNError:
+                pass
+    print(f"grid {grid}: batch-packed {sorted(set(packed))}, column-packed {sorted(set(columns))}", flush=True)
+    assert packed and columns
     got = amplitudes(net, path, bits).cpu().numpy()
     if grid == "4x6":
         want = oracle.amplitudes(oracle.statevector(circ), circ.n_qubits, bits)

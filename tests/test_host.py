@@ -261,7 +261,7 @@ def test_gemm_launch_shape_get_set():
         if tile == 4:
             assert k <= 1024 and split == 1
         with pytest.raises(TNError):
-            path.set_gemm_config(s, 8, 1)
+            path.set_gemm_config(s, 9, 1)
         with pytest.raises(TNError):
             path.set_gemm_config(s, 5, 1, 0, "bf16x3")  # the 3M tiles are FP32 only
         with pytest.raises(TNError):
