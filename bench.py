@@ -35,7 +35,9 @@ PEAK_HBM_GBS = 8000.0
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_BF16_MFMA_TFLOPS = 2500.0
 CPU_SAMPLE_SECONDS = 10.0  # minimum CPU work timed for cpu_baseline
-PEAK_FP32_VECTOR_TFLOPS = 157.3  # 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2 (packed) x 2.4 GHz
+# 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz; the library is built without packed FP32
+# arithmetic, so the packed doubling (157.3) is out of its reach
+PEAK_FP32_VECTOR_TFLOPS = 78.6
 
 
 def relerr(got, want):
@@ -103,12 +105,13 @@ def plan_candidates(net, kind, trials, seeds, **kw):
     return [net.plan(kind, trials=trials, seed=s, **kw) for s in range(seeds)]
 
 
-def refine_in_pass(tnq, torch, path, run, precision, passes=5, reps=3):
+def refine_in_pass(tnq, torch, path, run, precision, passes=5, reps=3, confirm=3):
     """Coordinate descent over the launch shapes of `path`'s product steps,
     each candidate timed by whole passes of run(path): a shape change can
     regroup launches or move data between caches, which timing a product
-    alone does not see.  A change is kept when it saves at least 0.5%.
-    Returns (ms per pass before, after, steps changed)."""
+    alone does not see.  A change is kept when it saves at least 0.5%, both in
+    the search and in `confirm` fresh timings interleaved with the current
+    shape.  Returns (ms per pass before, after, steps changed)."""
     def per_pass():
         best = None
         for _ in range(reps):
@@ -121,15 +124,21 @@ def refine_in_pass(tnq, torch, path, run, precision, passes=5, reps=3):
             best = t if best is None else min(best, t)
         return best
 
+    def timed(s, shape):
+        path.set_gemm_config(s, *shape, precision)
+        run(path)
+        return per_pass()
+
     run(path)
     before = base = per_pass()
     changed = 0
     for s, cur in path.gemm_configs(precision).items():
-        best = (base, tuple(cur))
+        cur = tuple(cur)
+        best = (base, cur)
         for tr in (0, 1):
             for tile in range(9):
                 for split in (1, 2, 4, 8):
-                    if (tile, split, tr) == tuple(cur):
+                    if (tile, split, tr) == cur:
                         continue
                     try:
                         path.set_gemm_config(s, tile, split, tr, precision)
@@ -139,10 +148,21 @@ def refine_in_pass(tnq, torch, path, run, precision, passes=5, reps=3):
                     t = per_pass()
                     if t < best[0] * 0.995:
                         best = (t, (tile, split, tr))
+        if best[1] != cur:
+            # the fastest of many candidates is biased low: confirm the winner against the
+            # current shape in fresh timings, interleaved, and keep the re-measured time
+            t_new, t_cur = [], []
+            for _ in range(confirm):
+                t_new.append(timed(s, best[1]))
+                t_cur.append(timed(s, cur))
+            t_new, t_cur = float(np.median(t_new)), float(np.median(t_cur))
+            if t_new < t_cur * 0.995:
+                changed += 1
+                base = t_new
+            else:
+                best = (t_cur, cur)
+                base = t_cur
         path.set_gemm_config(s, *best[1], precision)
-        if best[1] != tuple(cur):
-            changed += 1
-            base = best[0]
     return before, base, changed
 
 
@@ -534,11 +554,14 @@ def main():
         roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                 "traffic": traffic}
     elif kind in ("sweep", "adjoint"):
-        # fused gate passes: every gate on every element in registers, bound by the vector ALUs
-        achieved = rec["flops"] / rec["seconds"] / 1e12
-        roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": traffic,
-                "hbm_GBs": rec["bytes"] / rec["seconds"] / 1e9}
+        # fused gate passes stream the state once per pass: graded against HBM, with the vector-ALU
+        # fraction of the gates' arithmetic (every gate on every element, in registers) beside it
+        achieved = rec["bytes"] / rec["seconds"] / 1e9
+        alu = rec["flops"] / rec["seconds"] / 1e12
+        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
+                "alu": {"achieved": alu, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                        "frac": alu / PEAK_FP32_VECTOR_TFLOPS}}
     else:
         achieved = rec["bytes"] / rec["seconds"] / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",

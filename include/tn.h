@@ -63,8 +63,16 @@ typedef enum {
 /* Arithmetic of the pairwise products.  C64: complex64 operands, FP32
  * multiply-accumulate.  BF16X3: each FP32 component is split as hi + lo in
  * bfloat16 and a*b is formed as hi*hi + hi*lo + lo*hi with FP32 accumulation
- * (split-precision emulation; storage stays complex64). */
-typedef enum { TN_PREC_C64 = 0, TN_PREC_BF16X3 = 1 } tn_precision;
+ * (split-precision emulation; storage stays complex64).  Q3_28: the paper's
+ * FPGA arithmetic (Sec. 3: 32-bit fixed point, 28 bits behind the binary
+ * point), read as two's-complement Q3.28: every tensor a pair of int32
+ * (value = raw / 2^28), gate entries rounded once from FP64, every real
+ * product rounded to nearest with ties to even, every sum saturating; each step
+ * of the path one per-output product on the vector ALUs (an error-study mode,
+ * tn_contract_path and tn_amplitudes only; the output is converted to
+ * complex64; TN_EUNSUPPORTED elsewhere, or for a step wider than 2^40 results
+ * or 2^20 summed terms). */
+typedef enum { TN_PREC_C64 = 0, TN_PREC_BF16X3 = 1, TN_PREC_Q3_28 = 2 } tn_precision;
 
 /* What closes the network (Sec. 2.2.3). */
 typedef enum {
@@ -213,7 +221,11 @@ tn_status tn_path_step(const tn_path* path, int32_t s, int32_t* rank, int32_t* m
 size_t tn_workspace_bytes(const tn_network* net, const tn_path* path, int32_t batch);
 
 /*
- * Contract the network along the path on the GPU (TN_OUT_STATEVECTOR).
+ * Contract the network along the path on the GPU (TN_OUT_STATEVECTOR): the
+ * open-legged network of Sec. 2.2.2 (eq. (2.3): the state is the network of
+ * the |0> vectors and the gate tensors with the output legs left open),
+ * contracted pair by pair along the order (Sec. 2.2.3), each pairwise step a
+ * sum over shared indices (eq. (2.2)) run as a matrix product (Sec. 3, Sec. 5).
  *   params_dev: device, [batch][n_params] float64 (NULL if n_params == 0);
  *   workspace_dev: device, >= tn_workspace_bytes(net, path, batch) bytes;
  *   out_dev: device, [batch][2^n] complex64 in qubit order (qubit 0 = MSB).
@@ -228,6 +240,9 @@ tn_status tn_contract_path(void* stream, int32_t precision, tn_network* net, tn_
  * Amplitudes <b_s|U|0> for a batch of bitstrings (TN_OUT_AMPLITUDES network,
  * Sec. 2.2.3: close the network with the final basis states).
  *   bitstrings_dev: device uint64[count], count <= the network's n_bitstrings;
+ *   qubit q is bit n-1-q and bits n..63 are ignored (b and b + k 2^n give the
+ *   same amplitude); the batch slots count..padded-1 are contracted with the
+ *   all-zeros bitstring and not returned;
  *   out_dev: device complex64[count].
  */
 tn_status tn_amplitudes(void* stream, int32_t precision, tn_network* net, tn_path* path, const double* params_dev,
@@ -237,7 +252,10 @@ tn_status tn_amplitudes(void* stream, int32_t precision, tn_network* net, tn_pat
 /*
  * Expectations <psi|D|psi> of diagonal observables for several circuits
  * (TN_OUT_STATEVECTOR networks) and parameter batches in one call; the sum
- * over basis states accumulates in FP64.
+ * over basis states accumulates in FP64.  Each state is the contraction of
+ * the open-legged network of Sec. 2.2.2 (eq. (2.3)) along its order (Sec.
+ * 2.2.3); the bra is the complex conjugate of the ket (only bras conjugate,
+ * Sec. 2.2.1), and a diagonal D only weights |psi_x|^2 per basis state.
  *   nets/paths/obs: host arrays of n_circuits;
  *   params_dev: host array of n_circuits device pointers, each [batch][n_params_c] float64 (or NULL);
  *   workspace_dev: device, >= tn_expectation_workspace_bytes(...);
@@ -255,7 +273,11 @@ tn_status tn_expectation(void* stream, int32_t precision, tn_network* const* net
  * psi, set lambda = D psi, then sweep the gates in reverse, un-applying each
  * gate U_j from psi and lambda and accumulating dE/dtheta = Im<lambda|G|psi>
  * for each parametric gate exp(-i theta G) in FP64 (summed over every gate
- * that reads the parameter).
+ * that reads the parameter).  The states are the contractions of Sec. 2.2.2
+ * (eq. (2.3)); the derivative itself is not in the paper.  `precision`
+ * selects the products of both the forward contraction and the un-applied
+ * gates of the reverse sweep; the gradient terms are formed in FP32 and
+ * summed in FP64 in either mode.
  *   grad_out_dev: device float64[batch] (dL/dE, NULL = ones);
  *   value_dev: device float64[batch]; grad_dev: device float64[batch][n_params].
  * Workspace: tn_backward_workspace_bytes.  TN_EUNSUPPORTED for a parametric

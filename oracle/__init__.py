@@ -16,6 +16,8 @@ circuits from the ``workloads`` package, which holds no simulation arithmetic.
                          exp(-i theta G) whose generator G has two eigenvalues.
 * ``contract``           the definition of a pairwise tensor contraction
                          (Sec. 2.2.1: a sum over shared indices, eq. (2.2)).
+* ``statevector_q328``   the gate-by-gate sweep in Q3.28 fixed point (Sec. 3's
+                         32-bit format with 28 fractional bits).
 * ``single_amplitude``   <b|U|0...0> of a circuit too wide for a full FP64
                          state, by contracting its closed network (Sec. 2.2.2)
                          pairwise in FP64 along a plain greedy order.
@@ -60,6 +62,12 @@ def _load():
     lib.oracle_expectation_zstrings.restype = ctypes.c_double
     lib.oracle_amplitudes.argtypes = [ctypes.c_int, P, ctypes.c_int64, P, P]
     lib.oracle_amplitudes.restype = None
+    lib.oracle_statevector_q328.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, P]
+    lib.oracle_statevector_q328.restype = ctypes.c_int
+    lib.oracle_q328_mul.argtypes = [ctypes.c_int32, ctypes.c_int32]
+    lib.oracle_q328_mul.restype = ctypes.c_int32
+    lib.oracle_q328_from_double.argtypes = [ctypes.c_double]
+    lib.oracle_q328_from_double.restype = ctypes.c_int32
     lib.oracle_num_threads.argtypes = []
     lib.oracle_num_threads.restype = ctypes.c_int
     _lib = lib
@@ -118,6 +126,40 @@ def statevector(circ: Circuit, params: Optional[np.ndarray] = None, matrices=Non
     if rc != 0:
         raise ValueError("oracle_statevector rejected the circuit")
     return psi.view(np.complex128)
+
+
+Q328_ONE = 1 << 28
+
+
+def q328_mul(a: int, b: int) -> int:
+    """Q3.28 product of two raw int32 values (rounded to nearest, ties to even; saturating)."""
+    return int(_load().oracle_q328_mul(int(a), int(b)))
+
+
+def q328_from_double(x: float) -> int:
+    """The raw int32 Q3.28 value nearest to x (ties to even; saturating)."""
+    return int(_load().oracle_q328_from_double(float(x)))
+
+
+def statevector_q328(circ: Circuit, params: Optional[np.ndarray] = None) -> np.ndarray:
+    """The gate-by-gate state in Q3.28 fixed point (Sec. 3's 32-bit format with
+    28 fractional bits; reading: two's complement, products rounded to
+    nearest-even, saturating sums): raw int32 array [2^n, 2] of (re, im)."""
+    lib = _load()
+    n = circ.n_qubits
+    kinds, qubits, angles, mats = _marshal(circ, params, None)
+    psi = np.empty((1 << n, 2), dtype=np.int32)
+    rc = lib.oracle_statevector_q328(n, len(circ.gates), _ptr(kinds), _ptr(qubits), _ptr(angles), _ptr(mats),
+                                     _ptr(psi))
+    if rc != 0:
+        raise ValueError("oracle_statevector_q328 rejected the circuit")
+    return psi
+
+
+def q328_to_complex(raw: np.ndarray) -> np.ndarray:
+    """complex128 values of raw Q3.28 (re, im) pairs."""
+    raw = np.asarray(raw, dtype=np.int64).reshape(-1, 2)
+    return (raw[:, 0] + 1j * raw[:, 1]) / float(Q328_ONE)
 
 
 def dense_unitary(circ: Circuit, params: Optional[np.ndarray] = None, matrices=None) -> np.ndarray:

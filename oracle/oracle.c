@@ -294,6 +294,112 @@ void oracle_amplitudes(int n, const double *psi, int64_t count, const uint64_t *
   }
 }
 
+/*
+ * Fixed-point arithmetic of the paper's FPGA designs (Sec. 3: complex
+ * arithmetic in 32-bit fixed point with 28 bits behind the binary point).
+ * The paper leaves the sign/integer split and the rounding unstated; the
+ * reading used here is two's-complement Q3.28 (value = raw / 2^28, raw an
+ * int32), every real product rounded to the nearest Q3.28 value with ties to
+ * even, every sum saturating at the int32 range.  A complex product is formed
+ * from four rounded real products: (ar br - ai bi) + i (ar bi + ai br).
+ */
+static int32_t q_sat(int64_t v)
+{
+  if (v > INT32_MAX) return INT32_MAX;
+  if (v < INT32_MIN) return INT32_MIN;
+  return (int32_t)v;
+}
+
+/* x (a double) to the nearest Q3.28 value, ties to even (rint in the default rounding mode) */
+int32_t oracle_q328_from_double(double x)
+{
+  double r = rint(x * 268435456.0);
+  if (r > (double)INT32_MAX) return INT32_MAX;
+  if (r < (double)INT32_MIN) return INT32_MIN;
+  return (int32_t)r;
+}
+
+/* a * b: the exact product raw_a raw_b / 2^56 rounded to Q3.28, ties to even, saturated */
+int32_t oracle_q328_mul(int32_t a, int32_t b)
+{
+  const int64_t p = (int64_t)a * (int64_t)b;
+  int64_t q = p >> 28; /* floor (arithmetic shift) */
+  const int64_t rem = p - q * ((int64_t)1 << 28); /* in [0, 2^28) */
+  const int64_t half = (int64_t)1 << 27;
+  if (rem > half || (rem == half && (q & 1))) q += 1;
+  return q_sat(q);
+}
+
+typedef struct { int32_t re, im; } qcplx;
+
+static qcplx qc_mul(qcplx a, qcplx b)
+{
+  qcplx r;
+  r.re = q_sat((int64_t)oracle_q328_mul(a.re, b.re) - (int64_t)oracle_q328_mul(a.im, b.im));
+  r.im = q_sat((int64_t)oracle_q328_mul(a.re, b.im) + (int64_t)oracle_q328_mul(a.im, b.re));
+  return r;
+}
+
+static qcplx qc_add(qcplx a, qcplx b)
+{
+  qcplx r;
+  r.re = q_sat((int64_t)a.re + b.re);
+  r.im = q_sat((int64_t)a.im + b.im);
+  return r;
+}
+
+/*
+ * The gate-by-gate state vector of oracle_statevector in Q3.28: each gate's
+ * FP64 matrix rounded once to Q3.28, every output amplitude the saturating
+ * sum of the rounded products of its matrix row with the input amplitudes.
+ *   psi_out: 2^n complex Q3.28 values, interleaved int32 (re, im).
+ * Returns 0, or -1 on a bad gate.
+ */
+int oracle_statevector_q328(int n, int ngates, const int *kinds, const int *qubits, const double *angles,
+                            const double *mats, int32_t *psi_out)
+{
+  if (n < 1 || n > 34) return -1;
+  qcplx *psi = (qcplx *)psi_out;
+  const int64_t dim = (int64_t)1 << n;
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < dim; ++i) { psi[i].re = 0; psi[i].im = 0; }
+  psi[0].re = oracle_q328_from_double(1.0);
+  for (int g = 0; g < ngates; ++g) {
+    cplx u[16];
+    qcplx uq[16];
+    if (gate_mat(kinds[g], angles + 3 * g, mats, g, u) != 0) return -1;
+    for (int i = 0; i < 16; ++i) {
+      uq[i].re = oracle_q328_from_double(u[i].re);
+      uq[i].im = oracle_q328_from_double(u[i].im);
+    }
+    const int two = oracle_is_two_qubit(kinds[g]);
+    const int qa = qubits[2 * g], qb = qubits[2 * g + 1];
+    if (qa < 0 || qa >= n || (two && (qb < 0 || qb >= n || qb == qa))) return -1;
+    const int d = two ? 4 : 2;
+    const int pa = n - 1 - qa, pb = two ? n - 1 - qb : 0;
+    const int64_t groups = dim >> (two ? 2 : 1);
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < groups; ++j) {
+      /* the basis index with zero bits inserted at the gate's positions (lower one first) */
+      int64_t base = j;
+      int lo = two ? (pa < pb ? pa : pb) : pa, hi = two ? (pa < pb ? pb : pa) : -1;
+      base = ((base >> lo) << (lo + 1)) | (base & (((int64_t)1 << lo) - 1));
+      if (two) base = ((base >> hi) << (hi + 1)) | (base & (((int64_t)1 << hi) - 1));
+      int64_t idx[4];
+      for (int v = 0; v < d; ++v)
+        idx[v] = two ? base | ((int64_t)(v >> 1) << pa) | ((int64_t)(v & 1) << pb) : base | ((int64_t)v << pa);
+      qcplx in[4];
+      for (int v = 0; v < d; ++v) in[v] = psi[idx[v]];
+      for (int r = 0; r < d; ++r) {
+        qcplx acc = {0, 0};
+        for (int c = 0; c < d; ++c) acc = qc_add(acc, qc_mul(uq[d * r + c], in[c]));
+        psi[idx[r]] = acc;
+      }
+    }
+  }
+  return 0;
+}
+
 /* number of OpenMP threads a parallel region uses here */
 int oracle_num_threads(void)
 {

@@ -20,13 +20,14 @@ import numpy as np
 
 from . import _lib
 from ._lib import (TN_FUSE_2Q, TN_OUT_AMPLITUDES, TN_OUT_STATEVECTOR, TN_PATH_GREEDY, TN_PATH_RANDOM,
-                   TN_PATH_SEARCH, TN_PATH_SEQUENTIAL, TN_PREC_BF16X3, TN_PREC_C64, TNError, check, lib)
+                   TN_PATH_SEARCH, TN_PATH_SEQUENTIAL, TN_PREC_BF16X3, TN_PREC_C64, TN_PREC_Q3_28, TNError, check,
+                   lib)
 
 __all__ = ["Network", "Path", "contract_path", "amplitudes", "expectation", "backward", "contract_pair", "autotune",
            "Expectation", "Graph", "Observable", "TNError", "tn_build_network", "tn_plan_path", "tn_contract_pair",
            "tn_contract_path", "tn_amplitudes", "tn_expectation", "tn_backward"]
 
-PRECISION = {"c64": TN_PREC_C64, "bf16x3": TN_PREC_BF16X3}
+PRECISION = {"c64": TN_PREC_C64, "bf16x3": TN_PREC_BF16X3, "q3.28": TN_PREC_Q3_28}
 PATH_KIND = {"greedy": TN_PATH_GREEDY, "sequential": TN_PATH_SEQUENTIAL, "random": TN_PATH_RANDOM,
              "search": TN_PATH_SEARCH}
 
@@ -385,21 +386,38 @@ def _make_expectation_function():
     torch = _torch()
 
     class Expectation(torch.autograd.Function):
-        """E(theta) = <psi(theta)|D|psi(theta)> for a batch of parameter vectors
-        [batch, n_params]; backward by the library's adjoint sweep."""
+        """E(theta) = <psi(theta)|D|psi(theta)> of one circuit, differentiable in
+        theta.  params: [n_params] (gives a 0-d value) or [batch, n_params]
+        (gives [batch]).  The forward pass evaluates the value only
+        (tn_expectation); the backward pass runs the adjoint sweep
+        (tn_backward) with dL/dE as its output weights.  Nothing but params is
+        kept between the two: the backward pass contracts the network again
+        instead of holding the state (recomputation in place of stored
+        intermediates)."""
 
         @staticmethod
         def forward(ctx, params, net, path, obs, precision="c64"):
-            batch = params.shape[0] if params.dim() == 2 else 1
-            value, grad = backward(net, path, params.detach(), obs, batch=batch, precision=precision,
-                                   device=params.device)
-            ctx.save_for_backward(grad)
-            return value
+            if net.n_params < 1 or params.dim() not in (1, 2) or params.shape[-1] != net.n_params:
+                raise ValueError("params must be [n_params] or [batch, n_params] of a parametric network")
+            flat = params.detach().to(torch.float64).reshape(-1, net.n_params).contiguous()
+            batch = flat.shape[0]
+            value = expectation([net], [path], [flat], [obs], batch=batch, precision=precision,
+                                device=params.device)[0]
+            ctx.save_for_backward(flat)
+            ctx.meta = (net, path, obs, precision, tuple(params.shape), params.dtype)
+            return value.reshape(()) if params.dim() == 1 else value
 
         @staticmethod
         def backward(ctx, grad_value):
-            (grad,) = ctx.saved_tensors
-            return grad * grad_value.to(grad.dtype).unsqueeze(1), None, None, None, None
+            (flat,) = ctx.saved_tensors
+            net, path, obs, precision, shape, dtype = ctx.meta
+            if not ctx.needs_input_grad[0]:
+                return None, None, None, None, None
+            batch = flat.shape[0]
+            go = grad_value.detach().to(torch.float64).reshape(-1).expand(batch).contiguous()
+            _, grad = backward(net, path, flat, obs, batch=batch, grad_out=go, precision=precision,
+                               device=flat.device)
+            return grad.reshape(shape).to(dtype), None, None, None, None
 
     return Expectation
 

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(_HERE, "libtnq.so")
 
 TN_OK, TN_EINVAL, TN_ENOMEM, TN_ELIMIT, TN_EDEVICE, TN_EUNSUPPORTED = range(6)
 STATUS_NAMES = {0: "TN_OK", 1: "TN_EINVAL", 2: "TN_ENOMEM", 3: "TN_ELIMIT", 4: "TN_EDEVICE", 5: "TN_EUNSUPPORTED"}
-TN_PREC_C64, TN_PREC_BF16X3 = 0, 1
+TN_PREC_C64, TN_PREC_BF16X3, TN_PREC_Q3_28 = 0, 1, 2
 TN_OUT_STATEVECTOR, TN_OUT_AMPLITUDES = 0, 1
 TN_PATH_GREEDY, TN_PATH_SEQUENTIAL, TN_PATH_RANDOM, TN_PATH_SEARCH = 0, 1, 2, 3
 TN_FUSE_2Q = 1
@@ -162,6 +162,11 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with paper_2108_06831_amd.build.build()")
+        # torch ships its own HIP runtime under the same soname as the system one this library
+        # links; whichever is loaded first serves both.  torch goes first, so that the runtime
+        # torch initialises the GPU with is the one the library's calls reach (loading the library
+        # first left its HIP calls without a device once torch had started).
+        import torch  # noqa: F401
         l = ctypes.CDLL(LIB_PATH)
         _declare(l)
         _lib = l

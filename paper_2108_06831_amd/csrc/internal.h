@@ -282,6 +282,22 @@ inline bool elem_groupable(const StepProgram& P, int precision) {
   return g.tile[precision] == kGemmVector && g.nbb + g.nbm + g.nbn <= kElemGroupOutBits && g.nbk <= kElemKBits;
 }
 
+// Q3.28 fixed-point mode (TN_PREC_Q3_28): every step of the path is one launch
+// of a per-output product over int32 (re, im) pairs, each real product rounded
+// to Q3.28 (ties to even) and every sum saturating.  Operand and result
+// layouts: input tensors as the network stores them, each intermediate C-ordered
+// over its modes.  Result bit j (C address bit j) sits at A bit a_o[j] and/or B
+// bit b_o[j] (-1: absent); summed bit j at A bit a_k[j] and B bit b_k[j].
+constexpr int kQMaxOutBits = 40;
+constexpr int kQMaxKBits = 20;
+struct QStep {
+  int32_t a_buf, b_buf;          // BUF_IN / BUF_WS (the result is always in the workspace)
+  int64_t a_off, b_off, c_off;   // complex elements from the buffer's base
+  int32_t n_out, n_k;
+  int8_t a_o[kQMaxOutBits], b_o[kQMaxOutBits];
+  int8_t a_k[kQMaxKBits], b_k[kQMaxKBits];
+};
+
 }  // namespace tnq
 
 struct tn_path {
@@ -311,6 +327,12 @@ struct tn_path {
   std::vector<tnq::SweepPass> adj_passes;
   std::vector<tnq::SweepSegment> adj_segments;
   std::vector<tnq::AdjGateDesc> adj_gates;
+  // Q3.28 fixed-point program (q_state 1: built; -1: a step exceeds the kernel's bit limits)
+  int32_t q_state = 0;
+  std::vector<tnq::QStep> q_steps;
+  int64_t q_ws_elems = 0;            // per batch item
+  tnq::BufRef q_final;               // the final tensor, C-ordered over q_final_modes
+  std::vector<int32_t> q_final_modes;
   tn_path_stats stats{};
   void* dev = nullptr;   // device-side cache
 };
@@ -331,6 +353,8 @@ void build_adjoint_plan(const tn_network* net, tn_path* path, const std::vector<
 // placed next to each other
 std::vector<int32_t> reorder_small_first(const tn_network* net, const std::vector<int32_t>& pairs, int* n_small,
                                          int64_t* small_region);
+// fixedpoint.cpp: the Q3.28 program of a path (sets q_state)
+void build_q328_program(const tn_network* net, tn_path* path);
 // network.cpp
 void network_values_host(const tn_network* net, const double* params, const uint64_t* bits, double* out);
 // runtime

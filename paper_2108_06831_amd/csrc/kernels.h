@@ -15,12 +15,21 @@ struct DevTensor {
 
 // Gate materialisation: every KET0 and GATE tensor of the network, for each
 // of `batch` parameter vectors (params: [batch][params_stride] or NULL).
+// q328: store Q3.28 (re, im) int32 pairs instead of complex64 (same 8 bytes per element).
 hipError_t launch_materialize(hipStream_t s, const DevTensor* ts, int nt, const Recipe* recipes, const RecipeOp* ops,
                               const double* mats, const double* params, int64_t params_stride, int batch,
-                              float2* in, int64_t in_bs);
+                              float2* in, int64_t in_bs, bool q328 = false);
 // One-hot projectors P_q[s][w] = [w == bit_q(b_s)] for the last n tensors.
 hipError_t launch_projectors(hipStream_t s, const uint64_t* bits, int64_t count, int n_qubits, int blog2,
-                             int64_t first_offset, int batch, float2* in, int64_t in_bs);
+                             int64_t first_offset, int batch, float2* in, int64_t in_bs, bool q328 = false);
+
+// Q3.28 fixed point: one step (see QStep) over raw int32 pairs; and the final
+// tensor F to complex64, out[o] = F[deposit(o)] with bit j of o at F bit map.a_o[j]
+// (map.n_out bits; `count` outputs per batch item).
+hipError_t launch_q328_step(hipStream_t s, const QStep& q, const void* a, int64_t a_bs, const void* b, int64_t b_bs,
+                            void* c, int64_t c_bs, int batch);
+hipError_t launch_q328_finish(hipStream_t s, const void* f, int64_t f_bs, float2* out, int64_t out_bs, int64_t count,
+                              const QStep& map, int batch);
 
 // Small-operand contraction streaming over the large operand (see SkinnyDesc).
 hipError_t launch_skinny(hipStream_t s, const SkinnyDesc& d, const float2* g, int64_t g_bs, const float2* t,
@@ -109,11 +118,12 @@ struct SweepArgs {
 // lambda_z[x] = D(x) psi_z[x]
 hipError_t launch_apply_diag_obs(hipStream_t s, const float2* psi, int64_t psi_bs, float2* lam, int64_t lam_bs,
                                  int64_t n_elems, const ZTerms& terms, int batch);
-// one reverse step: g = 2 Im<lam|G|psi> (partials), then psi <- U^dagger psi, lam <- U^dagger lam.
+// one reverse step: g = 2 Im<lam|G|psi> (partials), then psi <- U^dagger psi, lam <- U^dagger lam, the
+// products of the un-applied gates in `precision` (the gradient terms in FP32, summed in FP64).
 // U: complex64 [batch][u_bs] matrix (2x2 or 4x4, row-major).
 hipError_t launch_adjoint_step(hipStream_t s, const SweepArgs& a, const float2* u, int64_t u_bs, float2* psi,
                                int64_t psi_bs, float2* lam, int64_t lam_bs, int64_t n_elems, int batch,
-                               double* partials, int64_t partial_stride);
+                               double* partials, int64_t partial_stride, int precision);
 // One fused pass of the reverse sweep over psi and lambda (2^bits elements
 // each, per parameter vector): for every gate of the pass, in order, its
 // gradient term (if any) into partials[z][slot][block], then both states
@@ -122,7 +132,7 @@ hipError_t launch_adjoint_step(hipStream_t s, const SweepArgs& a, const float2* 
 hipError_t launch_adjoint_pass(hipStream_t s, const SweepPass& ps, int bits, const AdjGateDesc* gates_dev,
                                const SweepSegment* segs_dev, const float2* u, int64_t u_bs, float2* psi,
                                int64_t psi_bs, float2* lam, int64_t lam_bs, int batch, double* partials,
-                               int64_t partial_stride);
+                               int64_t partial_stride, int precision);
 // grad[z][p] = scale_z * sum over slots with param p and blocks of partials
 hipError_t launch_gradient_reduce(hipStream_t s, const double* partials, int64_t partial_stride, int n_slots,
                                   const int32_t* slot_param, int n_params, const double* grad_out, int batch,

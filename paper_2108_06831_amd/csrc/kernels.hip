@@ -76,36 +76,53 @@ __device__ inline double block_sum(double v, double* red) {
 // (every array below is indexed by constants).  Rounded once to complex64.
 constexpr int kRecipeThreads = 64;
 
-template <class GetU>
+// The nearest Q3.28 value (raw int32 = value * 2^28), ties to even, saturated.
+__device__ inline int32_t q328_from_double(double x) {
+  const double r = rint(x * 268435456.0);
+  return r >= 2147483647.0 ? 2147483647 : r <= -2147483648.0 ? (int32_t)0x80000000 : (int32_t)r;
+}
+
+// One FP64 complex value stored rounded once: to complex64 (Q = false) or to
+// a Q3.28 (re, im) pair in the same 8 bytes (Q = true).
+template <bool Q>
+__device__ inline void store_c(float2* o, int i, const c128& v) {
+  if constexpr (Q)
+    reinterpret_cast<int2*>(o)[i] = make_int2(q328_from_double(v.re), q328_from_double(v.im));
+  else
+    o[i] = f2((float)v.re, (float)v.im);
+}
+
+template <bool Q, class GetU>
 __device__ void write_recipe(const Recipe& r, const RecipeOp* ops, GetU get_u, float2* o) {
   if (r.split_side >= 0) {
     c128 H[8];
     recipe_split_half_g(r, ops, get_u, H);
 #pragma unroll
-    for (int i = 0; i < 8; ++i) o[i] = f2((float)H[i].re, (float)H[i].im);
+    for (int i = 0; i < 8; ++i) store_c<Q>(o, i, H[i]);
   } else if (r.nq == 2) {
     c128 M[16];
     recipe_matrix_dg<4>(r, ops, get_u, M);
     if (r.diag) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) o[i] = f2((float)M[5 * i].re, (float)M[5 * i].im);
+      for (int i = 0; i < 4; ++i) store_c<Q>(o, i, M[5 * i]);
     } else {
 #pragma unroll
-      for (int i = 0; i < 16; ++i) o[i] = f2((float)M[i].re, (float)M[i].im);
+      for (int i = 0; i < 16; ++i) store_c<Q>(o, i, M[i]);
     }
   } else {
     c128 M[4];
     recipe_matrix_dg<2>(r, ops, get_u, M);
     if (r.diag) {
-      o[0] = f2((float)M[0].re, (float)M[0].im);
-      o[1] = f2((float)M[3].re, (float)M[3].im);
+      store_c<Q>(o, 0, M[0]);
+      store_c<Q>(o, 1, M[3]);
     } else {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) o[i] = f2((float)M[i].re, (float)M[i].im);
+      for (int i = 0; i < 4; ++i) store_c<Q>(o, i, M[i]);
     }
   }
 }
 
+template <bool Q>
 __global__ __launch_bounds__(kRecipeThreads) void k_materialize(const DevTensor* ts, int nt, const Recipe* rs,
                                                                 const RecipeOp* ops, const double* mats,
                                                                 const double* params, int64_t pstride, float2* in,
@@ -118,8 +135,8 @@ __global__ __launch_bounds__(kRecipeThreads) void k_materialize(const DevTensor*
   float2* o = in + (int64_t)z * in_bs + d.offset;
   if (d.kind == TK_KET0) {
     if (threadIdx.x == 0) {
-      o[0] = f2(1.f, 0.f);
-      o[1] = f2(0.f, 0.f);
+      store_c<Q>(o, 0, c128{1.0, 0.0});
+      store_c<Q>(o, 1, c128{0.0, 0.0});
     }
   } else if (d.kind == TK_GATE) {
     const Recipe r = rs[d.recipe];
@@ -134,18 +151,19 @@ __global__ __launch_bounds__(kRecipeThreads) void k_materialize(const DevTensor*
       }
       __syncthreads();
       if (threadIdx.x == 0)
-        write_recipe(r, ops, [&](int op, c128* u) {
+        write_recipe<Q>(r, ops, [&](int op, c128* u) {
 #pragma unroll
           for (int i = 0; i < 16; ++i) u[i] = U[op - r.op_begin][i];
         }, o);
     } else if (threadIdx.x == 0) {
-      write_recipe(r, ops, [&](int op, c128* u) { op_matrix(ops[op], mats, p, u); }, o);
+      write_recipe<Q>(r, ops, [&](int op, c128* u) { op_matrix(ops[op], mats, p, u); }, o);
     }
   }
 }
 
+// one_bits: the 32-bit pattern of the value 1 (1.0f, or 2^28 in Q3.28)
 __global__ void k_projectors(const uint64_t* bits, int64_t count, int n, int blog2, int64_t first, float2* in,
-                             int64_t in_bs) {
+                             int64_t in_bs, uint32_t one_bits) {
   const int64_t per = (int64_t)1 << blog2;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int z = blockIdx.y;
@@ -153,25 +171,169 @@ __global__ void k_projectors(const uint64_t* bits, int64_t count, int n, int blo
   const int q = (int)(i / per);
   const int64_t s = i % per;
   const int bit = s < count ? (int)((bits[s] >> (n - 1 - q)) & 1) : 0;
-  float2* o = in + (int64_t)z * in_bs + first + (int64_t)q * per * 2 + 2 * s;
-  o[0] = f2(bit == 0 ? 1.f : 0.f, 0.f);
-  o[1] = f2(bit == 1 ? 1.f : 0.f, 0.f);
+  uint2* o = reinterpret_cast<uint2*>(in + (int64_t)z * in_bs + first + (int64_t)q * per * 2 + 2 * s);
+  o[0] = make_uint2(bit == 0 ? one_bits : 0u, 0u);
+  o[1] = make_uint2(bit == 1 ? one_bits : 0u, 0u);
 }
 
 hipError_t launch_materialize(hipStream_t s, const DevTensor* ts, int nt, const Recipe* recipes, const RecipeOp* ops,
                               const double* mats, const double* params, int64_t params_stride, int batch,
-                              float2* in, int64_t in_bs) {
+                              float2* in, int64_t in_bs, bool q328) {
   if (nt == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_materialize, dim3(nt, batch), dim3(kRecipeThreads), 0, s, ts, nt, recipes, ops, mats, params,
-                     params_stride, in, in_bs);
+  if (q328)
+    hipLaunchKernelGGL(k_materialize<true>, dim3(nt, batch), dim3(kRecipeThreads), 0, s, ts, nt, recipes, ops, mats,
+                       params, params_stride, in, in_bs);
+  else
+    hipLaunchKernelGGL(k_materialize<false>, dim3(nt, batch), dim3(kRecipeThreads), 0, s, ts, nt, recipes, ops, mats,
+                       params, params_stride, in, in_bs);
   return hipGetLastError();
 }
 
 hipError_t launch_projectors(hipStream_t s, const uint64_t* bits, int64_t count, int n_qubits, int blog2,
-                             int64_t first_offset, int batch, float2* in, int64_t in_bs) {
+                             int64_t first_offset, int batch, float2* in, int64_t in_bs, bool q328) {
   const int64_t total = ((int64_t)1 << blog2) * n_qubits;
   dim3 grid((unsigned)((total + kThreads - 1) / kThreads), batch);
-  hipLaunchKernelGGL(k_projectors, grid, dim3(kThreads), 0, s, bits, count, n_qubits, blog2, first_offset, in, in_bs);
+  const uint32_t one = q328 ? (1u << 28) : 0x3f800000u;
+  hipLaunchKernelGGL(k_projectors, grid, dim3(kThreads), 0, s, bits, count, n_qubits, blog2, first_offset, in, in_bs,
+                     one);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Q3.28 fixed point: one step of a path as a per-output product over raw int32
+// (re, im) pairs (value = raw / 2^28).  Every real product is the exact 64-bit
+// product shifted back by 28 bits, rounded to nearest with ties to even and
+// saturated; every sum saturates at the int32 range.
+// ---------------------------------------------------------------------------
+__device__ inline int32_t q_sat(int64_t v) {
+  return v > 2147483647ll ? 2147483647 : v < -2147483648ll ? (int32_t)0x80000000 : (int32_t)v;
+}
+__device__ inline int64_t q_mul(int32_t a, int32_t b) {
+  const int64_t p = (int64_t)a * (int64_t)b;
+  int64_t q = p >> 28;
+  const int64_t rem = p & (((int64_t)1 << 28) - 1);
+  q += (rem > ((int64_t)1 << 27)) | ((rem == ((int64_t)1 << 27)) & (q & 1));
+  return q_sat(q);
+}
+
+constexpr int kQChunks = (kQMaxOutBits + 7) / 8;  // 8-bit chunks of a result index
+constexpr int kQKTable = 1024;                    // summed indices resolved through an LDS table
+
+struct QStepArgs {
+  const int2* a;
+  const int2* b;
+  int2* c;
+  int64_t a_bs, b_bs, c_bs;
+  QStep st;
+};
+
+__global__ __launch_bounds__(kThreads) void k_q328_step(QStepArgs g) {
+  __shared__ int64_t ta[kQChunks][256], tb[kQChunks][256];
+  __shared__ int64_t ka[kQKTable], kb[kQKTable];
+  const QStep& q = g.st;
+  const int nc = (q.n_out + 7) / 8;
+  const int nkl = q.n_k < 10 ? q.n_k : 10;  // low summed bits through the table
+  for (int i = threadIdx.x; i < nc * 256; i += kThreads) {
+    const int c = i >> 8, v = i & 255;
+    int64_t da = 0, db = 0;
+    for (int j = 0; j < 8; ++j) {
+      const int bit = 8 * c + j;
+      if (bit >= q.n_out || !((v >> j) & 1)) continue;
+      if (q.a_o[bit] >= 0) da |= (int64_t)1 << q.a_o[bit];
+      if (q.b_o[bit] >= 0) db |= (int64_t)1 << q.b_o[bit];
+    }
+    ta[c][v] = da;
+    tb[c][v] = db;
+  }
+  for (int k = threadIdx.x; k < (1 << nkl); k += kThreads) {
+    int64_t da = 0, db = 0;
+    for (int j = 0; j < nkl; ++j)
+      if ((k >> j) & 1) {
+        da |= (int64_t)1 << q.a_k[j];
+        db |= (int64_t)1 << q.b_k[j];
+      }
+    ka[k] = da;
+    kb[k] = db;
+  }
+  __syncthreads();
+  const int z = blockIdx.y;
+  const int2* A = g.a + (int64_t)z * g.a_bs;
+  const int2* B = g.b + (int64_t)z * g.b_bs;
+  int2* C = g.c + (int64_t)z * g.c_bs;
+  const int64_t n_out = (int64_t)1 << q.n_out;
+  const int64_t n_hi = (int64_t)1 << (q.n_k - nkl);
+  for (int64_t o = (int64_t)blockIdx.x * kThreads + threadIdx.x; o < n_out; o += (int64_t)gridDim.x * kThreads) {
+    int64_t a0 = 0, b0 = 0;
+    for (int c = 0; c < nc; ++c) {
+      const int v = (int)((o >> (8 * c)) & 255);
+      a0 |= ta[c][v];
+      b0 |= tb[c][v];
+    }
+    int32_t re = 0, im = 0;
+    for (int64_t h = 0; h < n_hi; ++h) {
+      int64_t ah = a0, bh = b0;
+      for (int j = nkl; j < q.n_k; ++j)
+        if ((h >> (j - nkl)) & 1) {
+          ah |= (int64_t)1 << q.a_k[j];
+          bh |= (int64_t)1 << q.b_k[j];
+        }
+      for (int k = 0; k < (1 << nkl); ++k) {
+        const int2 x = A[ah | ka[k]], y = B[bh | kb[k]];
+        const int32_t pr = q_sat(q_mul(x.x, y.x) - q_mul(x.y, y.y));
+        const int32_t pi = q_sat(q_mul(x.x, y.y) + q_mul(x.y, y.x));
+        re = q_sat((int64_t)re + pr);
+        im = q_sat((int64_t)im + pi);
+      }
+    }
+    C[o] = make_int2(re, im);
+  }
+}
+
+hipError_t launch_q328_step(hipStream_t s, const QStep& q, const void* a, int64_t a_bs, const void* b, int64_t b_bs,
+                            void* c, int64_t c_bs, int batch) {
+  if (q.n_out < 0 || q.n_out > kQMaxOutBits || q.n_k < 0 || q.n_k > kQMaxKBits) return hipErrorInvalidValue;
+  QStepArgs g;
+  g.a = (const int2*)a; g.b = (const int2*)b; g.c = (int2*)c;
+  g.a_bs = a_bs; g.b_bs = b_bs; g.c_bs = c_bs;
+  g.st = q;
+  int64_t blocks = (((int64_t)1 << q.n_out) + kThreads - 1) / kThreads;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_q328_step, dim3((unsigned)blocks, batch), dim3(kThreads), 0, s, g);
+  return hipGetLastError();
+}
+
+// out[z][o] (complex64) = the Q3.28 value at F[z][deposit(o)], where bit j of o
+// sits at bit pos[j] of F's address
+__global__ __launch_bounds__(kThreads) void k_q328_finish(const int2* F, int64_t f_bs, float2* out, int64_t out_bs,
+                                                          int64_t count, QStep map) {
+  __shared__ int64_t ta[kQChunks][256];
+  const int nc = (map.n_out + 7) / 8;
+  for (int i = threadIdx.x; i < nc * 256; i += kThreads) {
+    const int c = i >> 8, v = i & 255;
+    int64_t d = 0;
+    for (int j = 0; j < 8; ++j) {
+      const int bit = 8 * c + j;
+      if (bit < map.n_out && ((v >> j) & 1)) d |= (int64_t)1 << map.a_o[bit];
+    }
+    ta[c][v] = d;
+  }
+  __syncthreads();
+  const int z = blockIdx.y;
+  for (int64_t o = (int64_t)blockIdx.x * kThreads + threadIdx.x; o < count; o += (int64_t)gridDim.x * kThreads) {
+    int64_t a = 0;
+    for (int c = 0; c < nc; ++c) a |= ta[c][(o >> (8 * c)) & 255];
+    const int2 v = F[(int64_t)z * f_bs + a];
+    out[(int64_t)z * out_bs + o] = f2((float)((double)v.x * (1.0 / 268435456.0)), (float)((double)v.y * (1.0 / 268435456.0)));
+  }
+}
+
+hipError_t launch_q328_finish(hipStream_t s, const void* f, int64_t f_bs, float2* out, int64_t out_bs, int64_t count,
+                              const QStep& map, int batch) {
+  if (map.n_out < 0 || map.n_out > kQMaxOutBits) return hipErrorInvalidValue;
+  int64_t blocks = (count + kThreads - 1) / kThreads;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_q328_finish, dim3((unsigned)std::max<int64_t>(blocks, 1), batch), dim3(kThreads), 0, s,
+                     (const int2*)f, f_bs, out, out_bs, count, map);
   return hipGetLastError();
 }
 
@@ -1948,7 +2110,7 @@ __device__ inline double im_cl_p(float2 l, float2 p) { return (double)l.x * p.y 
 // Re(conj(l) * p)
 __device__ inline double re_cl_p(float2 l, float2 p) { return (double)l.x * p.x + (double)l.y * p.y; }
 
-template <int NQ>
+template <int NQ, int PREC>
 __global__ __launch_bounds__(kThreads) void k_adjoint_step(SweepArgs a, const float2* U, int64_t u_bs, float2* psi,
                                                            int64_t psi_bs, float2* lam, int64_t lam_bs,
                                                            int64_t n_groups, double* partials, int64_t pstride) {
@@ -1985,15 +2147,13 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_step(SweepArgs a, const fl
       case GEN_CPHASE: if (NQ == 2) g += -2.0 * im_cl_p(l[3], p[3]); break;
       default: break;
     }
-    // psi <- U^dagger psi, lam <- U^dagger lam
+    // psi <- U^dagger psi, lam <- U^dagger lam (products in the requested precision)
     for (int r = 0; r < D; ++r) {
       float2 ap = f2(0.f, 0.f), al = f2(0.f, 0.f);
       for (int c = 0; c < D; ++c) {
-        const float2 uc = u[c * D + r];  // conj(U[c][r])
-        ap.x += uc.x * p[c].x + uc.y * p[c].y;
-        ap.y += uc.x * p[c].y - uc.y * p[c].x;
-        al.x += uc.x * l[c].x + uc.y * l[c].y;
-        al.y += uc.x * l[c].y - uc.y * l[c].x;
+        const float2 uc = f2(u[c * D + r].x, -u[c * D + r].y);  // conj(U[c][r])
+        ap = cmac<PREC>(ap, uc, p[c]);
+        al = cmac<PREC>(al, uc, l[c]);
       }
       P[idx[r]] = ap;
       L[idx[r]] = al;
@@ -2007,11 +2167,13 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_step(SweepArgs a, const fl
 
 hipError_t launch_adjoint_step(hipStream_t s, const SweepArgs& a, const float2* u, int64_t u_bs, float2* psi,
                                int64_t psi_bs, float2* lam, int64_t lam_bs, int64_t n_elems, int batch,
-                               double* partials, int64_t partial_stride) {
+                               double* partials, int64_t partial_stride, int precision) {
   const int64_t groups = n_elems >> a.nq;
   // a fixed grid so that every partial slot is written
   const int blocks = kReduceBlocks;
-  void* fn = a.nq == 2 ? (void*)k_adjoint_step<2> : (void*)k_adjoint_step<1>;
+  const bool bf = precision == TN_PREC_BF16X3;
+  void* fn = a.nq == 2 ? (bf ? (void*)k_adjoint_step<2, TN_PREC_BF16X3> : (void*)k_adjoint_step<2, TN_PREC_C64>)
+                       : (bf ? (void*)k_adjoint_step<1, TN_PREC_BF16X3> : (void*)k_adjoint_step<1, TN_PREC_C64>);
   SweepArgs aa = a;
   void* args[] = {&aa, (void*)&u, (void*)&u_bs, (void*)&psi, (void*)&psi_bs, (void*)&lam, (void*)&lam_bs,
                   (void*)&groups, (void*)&partials, (void*)&partial_stride};
@@ -2150,6 +2312,7 @@ __device__ __forceinline__ float reg_grad_y(const float2 (&p)[16], const float2 
   return g;
 }
 
+template <int PREC>
 __global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a) {
   constexpr int kBuf = (1 << kSweepMaxLocal) + (1 << (kSweepMaxLocal - 5));
   __shared__ float2 bp[kBuf], bl[kBuf];
@@ -2243,8 +2406,8 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a) {
             ph = f2(ph.x * f.x - ph.y * f.y, ph.x * f.y + ph.y * f.x);
             continue;
           }
-          apply_diag<TN_PREC_C64>(xp, gd.n, k[0], k[1], c, d0, d1, d2, d3);
-          apply_diag<TN_PREC_C64>(xl, gd.n, k[0], k[1], c, d0, d1, d2, d3);
+          apply_diag<PREC>(xp, gd.n, k[0], k[1], c, d0, d1, d2, d3);
+          apply_diag<PREC>(xl, gd.n, k[0], k[1], c, d0, d1, d2, d3);
         } else if (gd.n == 1) {
           if (gd.red >= 0) {
             float g;
@@ -2283,10 +2446,10 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a) {
           ud[2] = f2(U[1].x, -U[1].y);
           ud[3] = f2(U[3].x, -U[3].y);
           switch (gd.rb[0]) {
-            case 0: reg_apply1<TN_PREC_C64, 0>(xp, ud, real); reg_apply1<TN_PREC_C64, 0>(xl, ud, real); break;
-            case 1: reg_apply1<TN_PREC_C64, 1>(xp, ud, real); reg_apply1<TN_PREC_C64, 1>(xl, ud, real); break;
-            case 2: reg_apply1<TN_PREC_C64, 2>(xp, ud, real); reg_apply1<TN_PREC_C64, 2>(xl, ud, real); break;
-            default: reg_apply1<TN_PREC_C64, 3>(xp, ud, real); reg_apply1<TN_PREC_C64, 3>(xl, ud, real); break;
+            case 0: reg_apply1<PREC, 0>(xp, ud, real); reg_apply1<PREC, 0>(xl, ud, real); break;
+            case 1: reg_apply1<PREC, 1>(xp, ud, real); reg_apply1<PREC, 1>(xl, ud, real); break;
+            case 2: reg_apply1<PREC, 2>(xp, ud, real); reg_apply1<PREC, 2>(xl, ud, real); break;
+            default: reg_apply1<PREC, 3>(xp, ud, real); reg_apply1<PREC, 3>(xl, ud, real); break;
           }
         } else {
           // dense two-qubit gates carry no gradient term (the planner checks)
@@ -2296,18 +2459,18 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) ud[4 * m + k] = f2(U[4 * k + m].x, -U[4 * k + m].y);
           switch (gd.rb[0] * 4 + gd.rb[1]) {
-            case 1: reg_apply2<TN_PREC_C64, 0, 1>(xp, ud); reg_apply2<TN_PREC_C64, 0, 1>(xl, ud); break;
-            case 4: reg_apply2<TN_PREC_C64, 1, 0>(xp, ud); reg_apply2<TN_PREC_C64, 1, 0>(xl, ud); break;
-            case 2: reg_apply2<TN_PREC_C64, 0, 2>(xp, ud); reg_apply2<TN_PREC_C64, 0, 2>(xl, ud); break;
-            case 8: reg_apply2<TN_PREC_C64, 2, 0>(xp, ud); reg_apply2<TN_PREC_C64, 2, 0>(xl, ud); break;
-            case 3: reg_apply2<TN_PREC_C64, 0, 3>(xp, ud); reg_apply2<TN_PREC_C64, 0, 3>(xl, ud); break;
-            case 12: reg_apply2<TN_PREC_C64, 3, 0>(xp, ud); reg_apply2<TN_PREC_C64, 3, 0>(xl, ud); break;
-            case 6: reg_apply2<TN_PREC_C64, 1, 2>(xp, ud); reg_apply2<TN_PREC_C64, 1, 2>(xl, ud); break;
-            case 9: reg_apply2<TN_PREC_C64, 2, 1>(xp, ud); reg_apply2<TN_PREC_C64, 2, 1>(xl, ud); break;
-            case 7: reg_apply2<TN_PREC_C64, 1, 3>(xp, ud); reg_apply2<TN_PREC_C64, 1, 3>(xl, ud); break;
-            case 13: reg_apply2<TN_PREC_C64, 3, 1>(xp, ud); reg_apply2<TN_PREC_C64, 3, 1>(xl, ud); break;
-            case 11: reg_apply2<TN_PREC_C64, 2, 3>(xp, ud); reg_apply2<TN_PREC_C64, 2, 3>(xl, ud); break;
-            default: reg_apply2<TN_PREC_C64, 3, 2>(xp, ud); reg_apply2<TN_PREC_C64, 3, 2>(xl, ud); break;
+            case 1: reg_apply2<PREC, 0, 1>(xp, ud); reg_apply2<PREC, 0, 1>(xl, ud); break;
+            case 4: reg_apply2<PREC, 1, 0>(xp, ud); reg_apply2<PREC, 1, 0>(xl, ud); break;
+            case 2: reg_apply2<PREC, 0, 2>(xp, ud); reg_apply2<PREC, 0, 2>(xl, ud); break;
+            case 8: reg_apply2<PREC, 2, 0>(xp, ud); reg_apply2<PREC, 2, 0>(xl, ud); break;
+            case 3: reg_apply2<PREC, 0, 3>(xp, ud); reg_apply2<PREC, 0, 3>(xl, ud); break;
+            case 12: reg_apply2<PREC, 3, 0>(xp, ud); reg_apply2<PREC, 3, 0>(xl, ud); break;
+            case 6: reg_apply2<PREC, 1, 2>(xp, ud); reg_apply2<PREC, 1, 2>(xl, ud); break;
+            case 9: reg_apply2<PREC, 2, 1>(xp, ud); reg_apply2<PREC, 2, 1>(xl, ud); break;
+            case 7: reg_apply2<PREC, 1, 3>(xp, ud); reg_apply2<PREC, 1, 3>(xl, ud); break;
+            case 13: reg_apply2<PREC, 3, 1>(xp, ud); reg_apply2<PREC, 3, 1>(xl, ud); break;
+            case 11: reg_apply2<PREC, 2, 3>(xp, ud); reg_apply2<PREC, 2, 3>(xl, ud); break;
+            default: reg_apply2<PREC, 3, 2>(xp, ud); reg_apply2<PREC, 3, 2>(xl, ud); break;
           }
         }
       }
@@ -2338,7 +2501,7 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a) {
 hipError_t launch_adjoint_pass(hipStream_t s, const SweepPass& ps, int bits, const AdjGateDesc* gates_dev,
                                const SweepSegment* segs_dev, const float2* u, int64_t u_bs, float2* psi,
                                int64_t psi_bs, float2* lam, int64_t lam_bs, int batch, double* partials,
-                               int64_t partial_stride) {
+                               int64_t partial_stride, int precision) {
   AdjPassArgs a;
   a.psi = psi; a.lam = lam; a.psi_bs = psi_bs; a.lam_bs = lam_bs;
   a.U = u; a.u_bs = u_bs;
@@ -2365,7 +2528,10 @@ hipError_t launch_adjoint_pass(hipStream_t s, const SweepPass& ps, int bits, con
   a.n_rest = nr;
   a.n_chunks = (int64_t)1 << nr;
   const int threads = 1 << (ps.l - 4);
-  hipLaunchKernelGGL(k_adjoint_pass, dim3(kReduceBlocks, batch), dim3(threads), 0, s, a);
+  if (precision == TN_PREC_BF16X3)
+    hipLaunchKernelGGL(k_adjoint_pass<TN_PREC_BF16X3>, dim3(kReduceBlocks, batch), dim3(threads), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_adjoint_pass<TN_PREC_C64>, dim3(kReduceBlocks, batch), dim3(threads), 0, s, a);
   return hipGetLastError();
 }
 

@@ -994,6 +994,7 @@ tn_status compile_program(const tn_network* net, tn_path* path, const std::vecto
   path->final_elems = loc[last].elems;
   path->ws_elems = std::max<int64_t>(alloc.peak, 32);
   path->n_inputs = T;
+  build_q328_program(net, path);
   return TN_OK;
 }
 

@@ -596,39 +596,96 @@ extern "C" int32_t tn_profile_read(tn_kernel_profile* out, int32_t capacity) {
 }
 extern "C" const char* tn_version(void) { return "tnq 0.1 (gfx950)"; }
 
+// workspace of the Q3.28 program: [input tensors x batch][arena x batch]
+static WsLayout layout_q328(const tn_network* net, const tn_path* path, int batch) {
+  WsLayout L;
+  L.in_off = 0;
+  L.arena_off = align256(sizeof(float2) * (size_t)net->input_elems * batch);
+  L.aux_off = align256(L.arena_off + sizeof(float2) * (size_t)path->q_ws_elems * batch);
+  L.total = L.aux_off;
+  return L;
+}
+
 extern "C" size_t tn_workspace_bytes(const tn_network* net, const tn_path* path, int32_t batch) {
   if (!net || !path || batch < 1) return 0;
   const size_t final_tmp = sizeof(float2) * (size_t)path->final_elems * batch;
-  return layout_ws(net, path, batch, std::max(expect_aux(batch), final_tmp)).total;
+  size_t n = layout_ws(net, path, batch, std::max(expect_aux(batch), final_tmp)).total;
+  if (path->q_state == 1) n = std::max(n, layout_q328(net, path, batch).total);
+  return n;
 }
 
 static tn_status check_common(const tn_network* net, const tn_path* path, const double* params, int32_t batch,
-                              int32_t precision) {
+                              int32_t precision, bool q328_ok = false) {
   if (!net || !path) return set_error(TN_EINVAL, "NULL network or path");
   if (path->n_inputs != (int32_t)net->tensors.size()) return set_error(TN_EINVAL, "path was planned for another network");
   if (batch < 1 || batch > 65535) return set_error(TN_EINVAL, "batch must be in 1..65535");
   if (net->n_params > 0 && !params) return set_error(TN_EINVAL, "params_dev required (n_params > 0)");
+  if (precision == TN_PREC_Q3_28) {
+    if (!q328_ok) return set_error(TN_EUNSUPPORTED, "TN_PREC_Q3_28 is offered by tn_contract_path and tn_amplitudes");
+    if (path->q_state != 1)
+      return set_error(TN_EUNSUPPORTED, "a step of this path exceeds the fixed-point kernel's index limits");
+    return TN_OK;
+  }
   if (precision != TN_PREC_C64 && precision != TN_PREC_BF16X3) return set_error(TN_EINVAL, "unknown precision");
   return TN_OK;
 }
 
-extern "C" tn_status tn_contract_path(void* stream, int32_t precision, tn_network* net, tn_path* path,
-                                      const double* params_dev, int32_t batch, void* workspace_dev,
-                                      size_t workspace_bytes, void* out_dev) {
-  clear_error();
-  tn_status st = check_common(net, path, params_dev, batch, precision);
-  if (st != TN_OK) return st;
-  if (net->output_kind != TN_OUT_STATEVECTOR) return set_error(TN_EINVAL, "network does not output a statevector");
-  if (!out_dev || !workspace_dev) return set_error(TN_EINVAL, "NULL device buffer");
-  const size_t need = tn_workspace_bytes(net, path, batch);
-  if (workspace_bytes < need)
-    return set_error(TN_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
-  hipStream_t s = (hipStream_t)stream;
-  DevNet* d;
-  if ((st = ensure_device(net, &d)) != TN_OK) return st;
+// The Q3.28 program (Sec. 3's fixed-point arithmetic): materialise the inputs
+// as Q3.28 pairs (bits: the amplitude network's bitstrings, `count` of them),
+// run every step of the path as one fixed-point product, then convert the
+// final tensor to complex64 in the order `to` (bit labels, most significant
+// first): `count` outputs per batch item, `out_bs` apart.
+static tn_status run_q328(hipStream_t s, tn_network* net, tn_path* path, DevNet* d, const double* params, int batch,
+                          const uint64_t* bits, int64_t count, char* w, const std::vector<int32_t>& to,
+                          float2* out, int64_t out_bs) {
+  const WsLayout L = layout_q328(net, path, batch);
+  float2* in = (float2*)(w + L.in_off);
+  char* arena = w + L.arena_off;
+  const int64_t in_bs = net->input_elems, ws_bs = path->q_ws_elems;
+  HIP_TRY(launch_materialize(s, d->tensors, (int)net->tensors.size(), d->recipes, d->ops, d->mats, params,
+                             net->n_params, batch, in, in_bs, true));
+  if (net->output_kind == TN_OUT_AMPLITUDES) {
+    const int64_t first = net->tensors[net->tensors.size() - net->n_qubits].offset;
+    HIP_TRY(launch_projectors(s, bits, count, net->n_qubits, net->batch_log2, first, batch, in, in_bs, true));
+  }
+  auto base = [&](int32_t buf, int64_t off, int64_t* bs) -> const void* {
+    *bs = buf == BUF_IN ? in_bs : ws_bs;
+    return buf == BUF_IN ? (const void*)(in + off) : (const void*)((float2*)arena + off);
+  };
+  for (const QStep& q : path->q_steps) {
+    int64_t abs_, bbs;
+    const void* a = base(q.a_buf, q.a_off, &abs_);
+    const void* b = base(q.b_buf, q.b_off, &bbs);
+    HIP_TRY(launch_q328_step(s, q, a, abs_, b, bbs, (float2*)arena + q.c_off, ws_bs, batch));
+  }
+  // result index bit j (from the least significant) -> bit of the final tensor
+  QStep map{};
+  map.n_out = (int32_t)to.size();
+  if (map.n_out > kQMaxOutBits) return set_error(TN_EUNSUPPORTED, "output too wide for the fixed-point kernel");
+  for (int j = 0; j < map.n_out; ++j) {
+    const int32_t lab = to[to.size() - 1 - j];
+    const int m = lab / 64, bit = lab % 64;
+    int below = 0, pos = -1;
+    for (size_t i = path->q_final_modes.size(); i-- > 0;) {
+      if (path->q_final_modes[i] == m) { pos = below + bit; break; }
+      below += net->mode_log2[path->q_final_modes[i]];
+    }
+    if (pos < 0) return set_error(TN_EINVAL, "internal: output leg missing from the final tensor");
+    map.a_o[j] = (int8_t)pos;
+  }
+  int64_t fbs;
+  const void* f = base(path->q_final.buf, path->q_final.off, &fbs);
+  HIP_TRY(launch_q328_finish(s, f, fbs, out, out_bs, count, map, batch));
+  return TN_OK;
+}
+
+// The statevector contraction into a workspace `w` of tn_workspace_bytes,
+// with the network's device tables `d` already in place.
+static tn_status contract_path_in(hipStream_t s, int32_t precision, tn_network* net, tn_path* path, DevNet* d,
+                                  const double* params_dev, int32_t batch, char* w, void* out_dev) {
+  tn_status st;
   const size_t final_tmp = sizeof(float2) * (size_t)path->final_elems * batch;
   WsLayout L = layout_ws(net, path, batch, std::max(expect_aux(batch), final_tmp));
-  char* w = (char*)workspace_dev;
   Bases B;
   B.in = (float2*)(w + L.in_off);
   B.in_bs = net->input_elems;
@@ -650,11 +707,35 @@ extern "C" tn_status tn_contract_path(void* stream, int32_t precision, tn_networ
   return finish_to(s, B, path, to, B.out, B.out_bs, B.out_bs, batch, (float2*)(w + L.aux_off));
 }
 
+extern "C" tn_status tn_contract_path(void* stream, int32_t precision, tn_network* net, tn_path* path,
+                                      const double* params_dev, int32_t batch, void* workspace_dev,
+                                      size_t workspace_bytes, void* out_dev) {
+  clear_error();
+  tn_status st = check_common(net, path, params_dev, batch, precision, true);
+  if (st != TN_OK) return st;
+  if (net->output_kind != TN_OUT_STATEVECTOR) return set_error(TN_EINVAL, "network does not output a statevector");
+  if (!out_dev || !workspace_dev) return set_error(TN_EINVAL, "NULL device buffer");
+  const size_t need = tn_workspace_bytes(net, path, batch);
+  if (workspace_bytes < need)
+    return set_error(TN_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
+  DevNet* d;
+  if ((st = ensure_device(net, &d)) != TN_OK) return st;
+  if (precision == TN_PREC_Q3_28) {
+    std::vector<int32_t> to;
+    for (int q = 0; q < net->n_qubits; ++q) to.push_back(lab(net->wire_final[q], 0));
+    const int64_t n_out = (int64_t)1 << net->n_qubits;
+    return run_q328((hipStream_t)stream, net, path, d, params_dev, batch, nullptr, n_out, (char*)workspace_dev, to,
+                    (float2*)out_dev, n_out);
+  }
+  return contract_path_in((hipStream_t)stream, precision, net, path, d, params_dev, batch, (char*)workspace_dev,
+                          out_dev);
+}
+
 extern "C" tn_status tn_amplitudes(void* stream, int32_t precision, tn_network* net, tn_path* path,
                                    const double* params_dev, const uint64_t* bitstrings_dev, int64_t count,
                                    void* workspace_dev, size_t workspace_bytes, void* out_dev) {
   clear_error();
-  tn_status st = check_common(net, path, params_dev, 1, precision);
+  tn_status st = check_common(net, path, params_dev, 1, precision, true);
   if (st != TN_OK) return st;
   if (net->output_kind != TN_OUT_AMPLITUDES) return set_error(TN_EINVAL, "network does not output amplitudes");
   if (count < 1 || count > net->n_bitstrings) return set_error(TN_EINVAL, "count must be in 1..n_bitstrings");
@@ -665,6 +746,12 @@ extern "C" tn_status tn_amplitudes(void* stream, int32_t precision, tn_network* 
   hipStream_t s = (hipStream_t)stream;
   DevNet* d;
   if ((st = ensure_device(net, &d)) != TN_OK) return st;
+  if (precision == TN_PREC_Q3_28) {
+    std::vector<int32_t> to;
+    for (int j = net->batch_log2 - 1; j >= 0; --j) to.push_back(lab(net->batch_mode, j));
+    return run_q328(s, net, path, d, params_dev, 1, bitstrings_dev, count, (char*)workspace_dev, to,
+                    (float2*)out_dev, count);
+  }
   const size_t final_tmp = sizeof(float2) * (size_t)path->final_elems;
   WsLayout L = layout_ws(net, path, 1, std::max(expect_aux(1), final_tmp));
   char* w = (char*)workspace_dev;
@@ -820,12 +907,15 @@ extern "C" tn_status tn_backward(void* stream, int32_t precision, tn_network* ne
       double fl = 0;
       for (int i = ps.first_gate; i < ps.first_gate + ps.n_gates; ++i) {
         const AdjGateDesc& gd = path->adj_gates[i];
-        const double per = gd.diag ? 12.0 : 16.0 * (double)(1 << gd.n);  // flops per element and state
+        // per element and state: 8 for a diagonal factor, 8 * 2^n for a dense gate on n qubits (one
+        // complex multiply-add per matrix entry); 8 more per element for a gradient term
+        const double per = gd.diag ? 8.0 : 8.0 * (double)(1 << gd.n);
         fl += 2.0 * per * (double)n + (gd.red >= 0 ? 8.0 * (double)n : 0.0);
       }
       hipEvent_t ev = prof_start(s, TN_KERNEL_ADJOINT);
       HIP_TRY(launch_adjoint_pass(s, ps, bits, dp->adj_gates, dp->adj_segments, umats,
-                                  (int64_t)net->sweep.size() * 16, psi, pbs, lam, n, batch, parts, pstride));
+                                  (int64_t)net->sweep.size() * 16, psi, pbs, lam, n, batch, parts, pstride,
+                                  precision));
       prof_stop(s, ev, TN_KERNEL_ADJOINT, 32.0 * (double)n * batch, fl * batch);
     }
   }
@@ -841,8 +931,10 @@ extern "C" tn_status tn_backward(void* stream, int32_t precision, tn_network* ne
       return set_error(TN_EINVAL, "internal: qubit leg missing from the final tensor");
     hipEvent_t ev = prof_start(s, TN_KERNEL_ADJOINT);
     HIP_TRY(launch_adjoint_step(s, a, umats + (int64_t)gi * 16, (int64_t)net->sweep.size() * 16, psi, pbs, lam, n,
-                                n, batch, parts, pstride));
-    prof_stop(s, ev, TN_KERNEL_ADJOINT, 32.0 * (double)n * batch, 64.0 * (double)n * batch * (g.nq == 2 ? 4 : 2));
+                                n, batch, parts, pstride, precision));
+    const double per = 8.0 * (double)(1 << g.nq);  // dense U^dagger on both states, as in the fused passes
+    prof_stop(s, ev, TN_KERNEL_ADJOINT, 32.0 * (double)n * batch,
+              (2.0 * per + (a.slot >= 0 ? 8.0 : 0.0)) * (double)n * batch);
   }
   if (net->n_params > 0)
     HIP_TRY(launch_gradient_reduce(s, parts, pstride, d->n_slots, d->slot_param, net->n_params, grad_out_dev, batch,

@@ -60,3 +60,20 @@ def test_no_change_restores_shapes(monkeypatch):
     path, before, after, changed = run_refine(lambda sh: 1.0 + 0.01 * (sh[10] != (3, 1, 0)), monkeypatch)
     assert path.shapes == {10: (3, 1, 0), 11: (4, 1, 0)}
     assert changed == 0 and before == after
+
+
+def test_noise_only_gain_is_rejected(monkeypatch):
+    """A candidate that looks faster once (a lucky timing) but is not faster
+    when timed again against the current shape is not kept."""
+    seen = {"n": 0}
+
+    def cost(sh):
+        if sh[10] == (6, 1, 0):
+            seen["n"] += 1
+            # the search's first timings of this shape are lucky, later ones are not
+            return 0.9 if seen["n"] <= 4 else 1.0
+        return 1.0
+
+    path, before, after, changed = run_refine(cost, monkeypatch)
+    assert path.shapes == {10: (3, 1, 0), 11: (4, 1, 0)}
+    assert changed == 0 and abs(after - 1.0) < 1e-9

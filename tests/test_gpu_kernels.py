@@ -1,5 +1,7 @@
 """Pairwise contraction kernels through the C ABI (tn_contract_pair) against
 the definition of a contraction (oracle.contract, FP64).  GPU only."""
+import os
+
 import numpy as np
 import pytest
 
@@ -266,3 +268,24 @@ def test_batch_packed_tile(grid):
         idx = sorted(np.random.default_rng(78).choice(4096, size=8, replace=False).tolist())
         want = np.array([oracle.single_amplitude(circ, int(bits[i])) for i in idx])
         assert relerr(got[idx], want) < C64_TOL
+
+
+def test_fresh_process_whose_first_call_is_the_library():
+    """A process that builds and plans through the library before it touches
+    torch: the binding loads torch's HIP runtime first, so both share it and
+    the contraction runs (regression: the library loaded first found no
+    device once torch had started its own runtime)."""
+    import subprocess
+    import sys
+    code = (
+        "import numpy as np, workloads, oracle\n"
+        "from paper_2108_06831_amd import Network, contract_path\n"
+        "c = workloads.config0(); net = Network.from_circuit(c); p = net.plan('greedy')\n"
+        "got = contract_path(net, p).cpu().numpy()[0]; want = oracle.statevector(c)\n"
+        "print('ERR', float(np.linalg.norm(got - want) / np.linalg.norm(want)))\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=240)
+    print(r.stdout[-500:], r.stderr[-500:], flush=True)
+    assert r.returncode == 0
+    err = float([ln for ln in r.stdout.splitlines() if ln.startswith("ERR")][0].split()[1])
+    assert err < 1e-5

@@ -291,3 +291,32 @@ def test_grouped_launch_plan():
     assert st["n_product_launches"] <= n // 2
     st1 = Network.from_circuit(workloads.config1(), fuse="split").plan("greedy").stats
     assert st1["n_product_launches"] < st1["n_gemm_steps"] + st1["n_skinny_steps"]
+
+
+def test_fig31_grid_plans_and_small_paths_match_oracle():
+    """The paper's test circuit (Fig. 3.1) over its whole grid, n in 2..28 and
+    k in 2..14 (even): the greedy planner orders every statevector network and
+    every network closed by <0...0| (and <1...1|), each in well under a second (Fig.
+    4.1b's third-party greedy search took up to 728.6 s); the planned paths of
+    the small ones, executed in FP64 on the host, equal the oracle."""
+    import time
+    worst = 0.0
+    for n in range(2, 29, 2):
+        for k in range(2, 15, 2):
+            circ = workloads.paper_test_circuit(n, k)
+            for output in ("statevector", "amplitudes"):
+                net = Network.from_circuit(circ, output=output, n_bitstrings=2)
+                t0 = time.perf_counter()
+                path = net.plan("greedy")
+                worst = max(worst, time.perf_counter() - t0)
+                assert path.stats["n_steps"] == net.info()["n_tensors"] - 1
+                if n <= 8 and k <= 6:
+                    psi = oracle.statevector(circ)
+                    if output == "statevector":
+                        got = pathexec.execute(net, path).reshape(-1)
+                        assert np.max(np.abs(got - psi)) < 1e-12
+                    else:
+                        bits = np.array([0, (1 << n) - 1], dtype=np.uint64)
+                        got = pathexec.execute(net, path, bitstrings=bits).reshape(-1)
+                        assert np.max(np.abs(got - psi[[0, -1]])) < 1e-12
+    assert worst < 1.0

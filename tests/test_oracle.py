@@ -352,6 +352,43 @@ def test_param_shift_vs_finite_difference():
     assert np.max(np.abs(g)) > 1e-3
 
 
+@pytest.mark.parametrize("kind", ["RX", "RY", "RZ", "U3", "CPHASE", "ZZPHASE", "MIXER"])
+def test_param_shift_every_parametric_kind_vs_finite_difference(kind):
+    """The shift rule of every parametric gate kind (each angle of a U3 on its
+    own) against the derivative's definition: with every angle its own
+    parameter, E is A + B cos(r t) + C sin(r t) in each parameter (r = 1, or
+    2 for the mixer exp(-i t X)), so the central difference is exactly
+    g sin(r h)/(r h).  Fixed gates of every kind around the parametric ones;
+    the observable mixes one- and two-qubit Z strings."""
+    n = 5
+    rng = np.random.default_rng(4242 + ALL_KINDS.index(kind) if kind in ALL_KINDS else 4242)
+    fixed = ["H", "X", "Y", "S", "T", "SX", "SY", "SW", "CZ", "CNOT", "SWAP"]
+    na = workloads.N_ANGLES[kind]
+    gates = [workloads.Gate("H", (q,)) for q in range(n)]
+    n_par = 0
+    for _ in range(6):  # random fixed gates, then one parametric gate
+        gates += workloads.random_circuit(n, 5, rng, kinds=fixed).gates
+        if kind in workloads.TWO_QUBIT:
+            qs = tuple(int(q) for q in rng.choice(n, size=2, replace=False))
+        else:
+            qs = (int(rng.integers(0, n)),)
+        gates.append(workloads.Gate(kind, qs, (0.0,) * na, tuple(range(n_par, n_par + na))))
+        n_par += na
+    # non-diagonal gates after the last parametric one, so that diagonal gates show in a Z observable
+    gates += [workloads.Gate("SX", (q,)) for q in range(n)] + [workloads.Gate("CNOT", (q, q + 1)) for q in range(n - 1)]
+    circ = workloads.Circuit(n, gates, n_par)
+    params = rng.uniform(0, 2 * np.pi, n_par)
+    masks, coeffs = workloads.zz_ring_observable(n)
+    masks = np.concatenate([masks, np.array([1 << 4, 1 << 1, (1 << 4) | (1 << 2) | 1], dtype=np.uint64)])
+    coeffs = np.concatenate([coeffs, np.array([0.8, -0.6, 1.1])])
+    g = oracle.param_shift_gradient(circ, params, masks, coeffs)
+    r = 2.0 if kind == "MIXER" else 1.0
+    h = 1e-3
+    fd = oracle.finite_difference_gradient(circ, params, masks, coeffs, h=h)
+    assert np.max(np.abs(fd / (np.sin(r * h) / (r * h)) - g)) < 1e-9
+    assert np.max(np.abs(g)) > 1e-2  # the circuit depends on its parameters
+
+
 def test_param_shift_multi_occurrence_and_mixer():
     """QAOA: gamma feeds every edge and beta every mixer (shift pi/4)."""
     n = 6
@@ -449,3 +486,115 @@ def test_single_amplitude_planted_mistake_fails():
     rev = int(f"{b:08b}"[::-1], 2)
     assert abs(oracle.single_amplitude(circ, b) - psi[b]) < 1e-12
     assert abs(oracle.single_amplitude(circ, rev) - psi[b]) > 1e-6
+
+
+# ---------------------------------------------------------------------------
+# Q3.28 fixed point (Sec. 3: 32-bit complex arithmetic, 28 bits behind the
+# binary point; reading: two's complement, products rounded to nearest with
+# ties to even, saturating sums)
+# ---------------------------------------------------------------------------
+def _rne_fraction(num, den):
+    """Nearest integer to num/den, ties to even (Python's round on a Fraction)."""
+    from fractions import Fraction
+    return round(Fraction(num, den))
+
+
+def _sat(v):
+    return max(-(1 << 31), min((1 << 31) - 1, v))
+
+
+def test_q328_multiply_against_exact_rationals():
+    """The oracle's Q3.28 product equals the exact rational a b / 2^56 rounded
+    to the nearest multiple of 2^-28 (ties to even) and saturated."""
+    rng = np.random.default_rng(328)
+    cases = [(int(a), int(b)) for a, b in rng.integers(-(1 << 31), 1 << 31, size=(2000, 2))]
+    cases += [(int(a), int(b)) for a, b in rng.integers(-(1 << 29), 1 << 29, size=(2000, 2))]
+    one = 1 << 28
+    cases += [(one, one), (-one, one), (one >> 1, 3), (3, one >> 1), (-(one >> 1), 3), (5, one >> 1),
+              (-(5), one >> 1), (1, 1), (-1, 1), (1 << 31 - 1, 1 << 31 - 1), (-(1 << 31), -(1 << 31)),
+              (-(1 << 31), (1 << 31) - 1), (8 * one - 1, 8 * one - 1), (0, 12345)]
+    ties = 0
+    for a, b in cases:
+        want = _sat(_rne_fraction(a * b, 1 << 28))
+        if (a * b) % (1 << 28) == 1 << 27:
+            ties += 1
+        assert oracle.q328_mul(a, b) == want, (a, b)
+    assert ties >= 4  # exact halves, both parities, were exercised
+
+
+def test_q328_from_double_rounds_to_nearest_even():
+    one = 1 << 28
+    for x, want in [(1.0, one), (-1.0, -one), (0.5 / one, 0), (1.5 / one, 2), (2.5 / one, 2), (-2.5 / one, -2),
+                    (1 / np.sqrt(2), 189812531), (8.0, (1 << 31) - 1), (-8.0, -(1 << 31)), (100.0, (1 << 31) - 1)]:
+        assert oracle.q328_from_double(x) == want, x
+    rng = np.random.default_rng(329)
+    from fractions import Fraction
+    for x in rng.uniform(-7.9, 7.9, 500):
+        assert oracle.q328_from_double(x) == round(Fraction(x) * one)
+
+
+def _q328_sweep_fractions(circ):
+    """Brute force with exact rationals: the state as Python integers, every
+    real product an exact rational rounded by round() (ties to even)."""
+    n = circ.n_qubits
+    one = 1 << 28
+    psi = [[0, 0] for _ in range(1 << n)]
+    psi[0][0] = one
+    for g in circ.gates:
+        u = oracle.gate_matrix(g.kind, circ.resolved_angles(g, None))
+        from fractions import Fraction
+        uq = [[(round(Fraction(v.real) * one), round(Fraction(v.imag) * one)) for v in row] for row in u]
+        qs = list(g.qubits)
+        pos = [n - 1 - q for q in qs]
+        d = len(uq)
+        new = [list(p) for p in psi]
+        for x in range(1 << n):
+            if any((x >> p) & 1 for p in pos):
+                continue
+            idx = []
+            for v in range(d):
+                bits = [(v >> (len(pos) - 1 - j)) & 1 for j in range(len(pos))]
+                idx.append(x | sum(b << p for b, p in zip(bits, pos)))
+            for r in range(d):
+                re = im = 0
+                for c in range(d):
+                    (ur, ui), (pr, pi) = uq[r][c], psi[idx[c]]
+                    m = lambda a, b: _sat(_rne_fraction(a * b, one))
+                    re = _sat(re + _sat(m(ur, pr) - m(ui, pi)))
+                    im = _sat(im + _sat(m(ur, pi) + m(ui, pr)))
+                new[idx[r]] = [re, im]
+        psi = new
+    return np.array(psi, dtype=np.int64)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_q328_sweep_brute_force_exact_rationals(seed):
+    rng = np.random.default_rng(3280 + seed)
+    circ = workloads.random_circuit(3, 14, rng)
+    got = oracle.statevector_q328(circ).astype(np.int64)
+    assert np.array_equal(got, _q328_sweep_fractions(circ))
+
+
+def test_q328_permutation_circuits_are_exact():
+    """X, CNOT, SWAP and CZ have entries 0 and +-1: every product is exact,
+    so the fixed-point state equals the FP64 one exactly."""
+    rng = np.random.default_rng(3290)
+    circ = workloads.random_circuit(9, 80, rng, kinds=["X", "CNOT", "SWAP", "CZ", "Z"])
+    want = oracle.statevector(circ)
+    got = oracle.q328_to_complex(oracle.statevector_q328(circ))
+    assert np.array_equal(got, want)
+
+
+def test_q328_error_within_rounding_bound():
+    """Against the FP64 sweep: each gate adds at most one rounding of 2^-29 per
+    real product (plus the gate entries' own rounding, at most 2^-29 each),
+    so over G gates of at most 4 terms per output the max-abs error stays
+    below G * 16 * 2^-29 * (1 + 1); in practice far below (uncorrelated)."""
+    for circ in (workloads.config0(), workloads.random_circuit(8, 120, np.random.default_rng(3300))):
+        want = oracle.statevector(circ)
+        got = oracle.q328_to_complex(oracle.statevector_q328(circ))
+        G = len(circ.gates)
+        err = np.max(np.abs(got - want))
+        assert err < G * 32 * 2.0 ** -29
+        assert err > 0  # rounding did happen
+        assert np.linalg.norm(got - want) / np.linalg.norm(want) < 1e-5
