@@ -237,6 +237,26 @@ tn_status tn_contract_path(void* stream, int32_t precision, tn_network* net, tn_
                            void* out_dev);
 
 /*
+ * tn_contract_path without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The same contraction and kernels as
+ * tn_contract_path, with the workspace in a static device array of
+ * TN_NOALLOC_SCRATCH_BYTES per GPU (held by each GPU the library runs on until
+ * the process ends) instead of a caller's buffer.  The caller still passes the
+ * parameters and the output.
+ *   Preconditions: tn_contract_path has run once with this network and path
+ *   on the current device (it creates their device tables; TN_EINVAL
+ *   otherwise).  TN_ENOMEM if tn_workspace_bytes(net, path, batch) exceeds
+ *   TN_NOALLOC_SCRATCH_BYTES.  Kernel timing (tn_profile_*) is not recorded.
+ *   Calls no hipMalloc/hipFree.  Every call on one GPU shares that GPU's array
+ *   and leaves its contents behind (nothing in it needs to start at zero):
+ *   calls that overlap on one GPU (concurrent streams or threads) race.
+ */
+#define TN_NOALLOC_SCRATCH_BYTES (64u << 20)
+tn_status tn_contract_path_noalloc(void* stream, int32_t precision, tn_network* net, tn_path* path,
+                                   const double* params_dev, int32_t batch, void* out_dev);
+
+/*
  * Amplitudes <b_s|U|0> for a batch of bitstrings (TN_OUT_AMPLITUDES network,
  * Sec. 2.2.3: close the network with the final basis states).
  *   bitstrings_dev: device uint64[count], count <= the network's n_bitstrings;

@@ -25,7 +25,7 @@ from ._lib import (TN_FUSE_2Q, TN_OUT_AMPLITUDES, TN_OUT_STATEVECTOR, TN_PATH_GR
 
 __all__ = ["Network", "Path", "contract_path", "amplitudes", "expectation", "backward", "contract_pair", "autotune",
            "Expectation", "Graph", "Observable", "TNError", "tn_build_network", "tn_plan_path", "tn_contract_pair",
-           "tn_contract_path", "tn_amplitudes", "tn_expectation", "tn_backward"]
+           "tn_contract_path", "tn_contract_path_noalloc", "tn_amplitudes", "tn_expectation", "tn_backward"]
 
 PRECISION = {"c64": TN_PREC_C64, "bf16x3": TN_PREC_BF16X3, "q3.28": TN_PREC_Q3_28}
 PATH_KIND = {"greedy": TN_PATH_GREEDY, "sequential": TN_PATH_SEQUENTIAL, "random": TN_PATH_RANDOM,
@@ -245,6 +245,10 @@ def tn_plan_path(net: Network, kind="greedy", max_log2_intermediate: int = 0, se
 def tn_contract_path(stream, precision, net, path, params_dev, batch, workspace, workspace_bytes, out_dev):
     check(lib().tn_contract_path(stream, precision, net.handle, path.handle, params_dev, batch, workspace,
                                  workspace_bytes, out_dev))
+
+
+def tn_contract_path_noalloc(stream, precision, net, path, params_dev, batch, out_dev):
+    check(lib().tn_contract_path_noalloc(stream, precision, net.handle, path.handle, params_dev, batch, out_dev))
 
 
 def tn_amplitudes(stream, precision, net, path, params_dev, bits_dev, count, workspace, workspace_bytes, out_dev):

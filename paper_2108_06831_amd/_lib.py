@@ -67,7 +67,7 @@ EXPORTS = [
     "tn_backward_workspace_bytes", "tn_backward", "tn_contract_pair_workspace_bytes", "tn_contract_pair",
     "tn_last_error", "tn_version", "tn_profile_enable", "tn_profile_read", "tn_profile_reset", "tn_autotune",
     "tn_path_gemm_config", "tn_graph_begin", "tn_graph_end", "tn_graph_launch", "tn_graph_destroy",
-    "tn_profile_select",
+    "tn_profile_select", "tn_contract_path_noalloc",
 ]
 
 KERNEL_KINDS = ["materialize", "skinny", "permute", "gemm", "reduce", "copy", "adjoint", "interp", "sweep",
@@ -112,6 +112,8 @@ def _declare(lib):
     lib.tn_workspace_bytes.restype = sz
     lib.tn_contract_path.argtypes = [P, i32, P, P, P, i32, P, sz, P]
     lib.tn_contract_path.restype = st
+    lib.tn_contract_path_noalloc.argtypes = [P, i32, P, P, P, i32, P]
+    lib.tn_contract_path_noalloc.restype = st
     lib.tn_amplitudes.argtypes = [P, i32, P, P, P, P, i64, P, sz, P]
     lib.tn_amplitudes.restype = st
     lib.tn_expectation_workspace_bytes.argtypes = [P, P, i32, i32]

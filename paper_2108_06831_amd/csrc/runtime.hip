@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -729,6 +730,71 @@ extern "C" tn_status tn_contract_path(void* stream, int32_t precision, tn_networ
   }
   return contract_path_in((hipStream_t)stream, precision, net, path, d, params_dev, batch, (char*)workspace_dev,
                           out_dev);
+}
+
+// ---------------------------------------------------------------------------
+// tn_contract_path_noalloc: the same contraction with its workspace in a
+// file-scope device array instead of a caller's buffer, for callers that
+// cannot allocate.  Host code never passes the array's name to a kernel (on
+// the host it is only a stand-in for the symbol): the device address of each
+// device's copy is looked up once with hipGetSymbolAddress and kept.  The
+// array has external linkage (in this library's namespace): with internal
+// linkage it would be a local symbol of the code object, which the runtime's
+// symbol lookup cannot see.
+// ---------------------------------------------------------------------------
+namespace tnq {
+__device__ __align__(256) char scratch[TN_NOALLOC_SCRATCH_BYTES];
+}
+
+constexpr int kMaxDevices = 64;
+static char* g_scratch_ptr[kMaxDevices];  // per device, set on the first call on that device
+static std::mutex g_scratch_mu;
+
+static tn_status scratch_for_device(int dev, char** out) {
+  if (dev < 0 || dev >= kMaxDevices) return set_error(TN_EUNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(tnq::scratch));
+    if (e != hipSuccess || !p)
+      return set_error(TN_EDEVICE, std::string("hipGetSymbolAddress(tnq::scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = (char*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return TN_OK;
+}
+
+extern "C" tn_status tn_contract_path_noalloc(void* stream, int32_t precision, tn_network* net, tn_path* path,
+                                              const double* params_dev, int32_t batch, void* out_dev) {
+  clear_error();
+  tn_status st = check_common(net, path, params_dev, batch, precision);
+  if (st != TN_OK) return st;
+  if (net->output_kind != TN_OUT_STATEVECTOR) return set_error(TN_EINVAL, "network does not output a statevector");
+  if (!out_dev) return set_error(TN_EINVAL, "NULL output buffer");
+  const size_t need = tn_workspace_bytes(net, path, batch);
+  if (need > (size_t)TN_NOALLOC_SCRATCH_BYTES)
+    return set_error(TN_ENOMEM, "workspace of " + std::to_string(need) + " bytes exceeds the static scratch of " +
+                                    std::to_string((size_t)TN_NOALLOC_SCRATCH_BYTES) + " bytes");
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  // device-side tables are created (allocated) by the other entry points only
+  DevNet* d = (DevNet*)net->dev;
+  if (!d || d->device != dev)
+    return set_error(TN_EINVAL, "the network's device tables are not on this device: run tn_contract_path once "
+                                "with this network on this device first");
+  const bool needs_path_tables = path->n_small > 0 || !path->chains.empty();
+  const DevPath* dp = (const DevPath*)path->dev;
+  if (needs_path_tables && (!dp || dp->device != dev))
+    return set_error(TN_EINVAL, "the path's device tables are not on this device: run tn_contract_path once "
+                                "with this path on this device first");
+  char* w = nullptr;
+  if ((st = scratch_for_device(dev, &w)) != TN_OK) return st;
+  // kernel timing creates events: it is left out of this call
+  const bool prof = g_prof;
+  g_prof = false;
+  st = contract_path_in((hipStream_t)stream, precision, net, path, d, params_dev, batch, w, out_dev);
+  g_prof = prof;
+  return st;
 }
 
 extern "C" tn_status tn_amplitudes(void* stream, int32_t precision, tn_network* net, tn_path* path,
