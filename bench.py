@@ -306,7 +306,7 @@ class Amplitudes(Workload):
 
 
 class QAOA(Workload):
-    def __init__(self, tnq, torch, precision):
+    def __init__(self, tnq, torch, precision, graph=True):
         import workloads
         self.tnq, self.torch, self.precision = tnq, torch, precision
         self.inst = workloads.config3()
@@ -331,16 +331,23 @@ class QAOA(Workload):
         self.stream = torch.cuda.Stream()
         self.eager()  # creates the device-side tables before the capture
         torch.cuda.synchronize()
-        self.graph = tnq.Graph(self.stream)
-        with self.graph.capture():
-            self.eager()
+        self.graph = None
+        if graph:
+            self.graph = tnq.Graph(self.stream)
+            with self.graph.capture():
+                self.eager()
+        else:
+            self.config["launch"] = "eager calls (no HIP graph)"
 
     def eager(self):
         self.tnq.expectation(self.nets, self.paths, self.params, self.obs, precision=self.precision,
                              workspace=self.ws, out=self.out, stream=self.stream)
 
     def step(self):
-        self.graph.launch()
+        if self.graph is None:
+            self.eager()
+        else:
+            self.graph.launch()
 
     def profiled_step(self):
         # kernels inside a graph carry no timing events: the breakdown comes from one eager pass
@@ -431,6 +438,8 @@ def main():
                     help="reuse a --tuning-out file instead of choosing and tuning again (default: the package's "
                          "tuning record for this workload, when there is one and it matches the planned orders)")
     ap.add_argument("--retune", action="store_true", help="ignore stored tuning records")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="config 3: eager calls instead of one HIP graph per step (e.g. for counter collection)")
     args = ap.parse_args()
     short = args.config in (0, 1, 2)
     if args.path is None:
@@ -468,7 +477,7 @@ def main():
     elif args.config == 2:
         wl = Amplitudes(tnq, torch, args.trials, args.precision, args.plan_seeds)
     elif args.config == 3:
-        wl = QAOA(tnq, torch, args.precision)
+        wl = QAOA(tnq, torch, args.precision, graph=not args.no_graph)
     else:
         wl = Gradients(tnq, torch, args.precision)
 

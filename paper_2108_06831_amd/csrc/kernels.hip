@@ -46,11 +46,27 @@ __device__ inline float rmul(float a, float b) {
   }
 }
 
+// acc + a b.  In FP32 as two fused multiply-adds per component (a separate
+// product, difference and sum would take three instructions each).
 template <int PREC>
 __device__ inline float2 cmac(float2 acc, float2 a, float2 b) {
-  acc.x += rmul<PREC>(a.x, b.x) - rmul<PREC>(a.y, b.y);
-  acc.y += rmul<PREC>(a.x, b.y) + rmul<PREC>(a.y, b.x);
+  if constexpr (PREC == TN_PREC_C64) {
+    acc.x = fmaf(a.x, b.x, fmaf(-a.y, b.y, acc.x));
+    acc.y = fmaf(a.x, b.y, fmaf(a.y, b.x, acc.y));
+  } else {
+    acc.x += rmul<PREC>(a.x, b.x) - rmul<PREC>(a.y, b.y);
+    acc.y += rmul<PREC>(a.x, b.y) + rmul<PREC>(a.y, b.x);
+  }
   return acc;
+}
+
+// a b (no accumulator): one product and one fused multiply-add per component
+template <int PREC>
+__device__ inline float2 cmul(float2 a, float2 b) {
+  if constexpr (PREC == TN_PREC_C64)
+    return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+  else
+    return make_float2(rmul<PREC>(a.x, b.x) - rmul<PREC>(a.y, b.y), rmul<PREC>(a.x, b.y) + rmul<PREC>(a.y, b.x));
 }
 
 __device__ inline double block_sum(double v, double* red) {
@@ -553,7 +569,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_steps(const SmallStep* 
               }
             // summed index in Gray-code order: one address bit flips per term
             int a = ab, b = bb;
-            float2 acc = cmac<PREC>(f2(0.f, 0.f), As[a], Bs[b]);
+            float2 acc = cmul<PREC>(As[a], Bs[b]);
             for (int k = 1; k < nk; ++k) {
               const int j = __builtin_ctz(k);
               a ^= 1 << packed_byte(ka0, ka1, ka2, j);
@@ -621,8 +637,8 @@ __device__ __forceinline__ void reg_apply1(float2 (&x)[16], const float2* g, boo
       x[r] = f2(g[0].x * a.x + g[1].x * b.x, g[0].x * a.y + g[1].x * b.y);
       x[r1] = f2(g[2].x * a.x + g[3].x * b.x, g[2].x * a.y + g[3].x * b.y);
     } else {
-      x[r] = cmac<PREC>(cmac<PREC>(f2(0.f, 0.f), g[0], a), g[1], b);
-      x[r1] = cmac<PREC>(cmac<PREC>(f2(0.f, 0.f), g[2], a), g[3], b);
+      x[r] = cmac<PREC>(cmul<PREC>(g[0], a), g[1], b);
+      x[r1] = cmac<PREC>(cmul<PREC>(g[2], a), g[3], b);
     }
   }
 }
@@ -651,7 +667,7 @@ __device__ __forceinline__ void reg_apply2(float2 (&x)[16], const float2* g) {
 template <int PREC, int U>
 __device__ __forceinline__ void diag_reg1(float2 (&x)[16], float2 e0, float2 e1) {
 #pragma unroll
-  for (int r = 0; r < 16; ++r) x[r] = cmac<PREC>(f2(0.f, 0.f), (r >> U) & 1 ? e1 : e0, x[r]);
+  for (int r = 0; r < 16; ++r) x[r] = cmul<PREC>((r >> U) & 1 ? e1 : e0, x[r]);
 }
 // ... or d_{bit U0 of r + 2 bit U1 of r}
 template <int PREC, int U0, int U1>
@@ -659,7 +675,7 @@ __device__ __forceinline__ void diag_reg2(float2 (&x)[16], float2 d0, float2 d1,
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int b = ((r >> U0) & 1) | (((r >> U1) & 1) << 1);
-    x[r] = cmac<PREC>(f2(0.f, 0.f), b == 0 ? d0 : b == 1 ? d1 : b == 2 ? d2 : d3, x[r]);
+    x[r] = cmul<PREC>(b == 0 ? d0 : b == 1 ? d1 : b == 2 ? d2 : d3, x[r]);
   }
 }
 
@@ -704,7 +720,7 @@ __device__ __forceinline__ void apply_diag(float2 (&x)[16], int n, int k0, int k
   if (k < 0) {  // constant over the thread's elements
     const float2 f = c == 0 ? d0 : c == 1 ? d1 : c == 2 ? d2 : d3;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) x[r] = cmac<PREC>(f2(0.f, 0.f), f, x[r]);
+    for (int r = 0; r < 16; ++r) x[r] = cmul<PREC>(f, x[r]);
     return;
   }
   switch (k) {
