@@ -101,7 +101,14 @@ struct SkinnyDesc {
   int32_t gidx[1 << kSkinnyMaxG];   // G element of (b, m, k), b slowest
   int32_t bt_pos[kSkinnyMaxG];      // position in T of G's batch bit j
   int32_t g_unit;                   // G is a diagonal gate whose entries all have modulus one
+  int32_t g_form;                   // shape of G's values that fewer multiplies serve (kForm*), from the gate kinds
 };
+
+// Shapes of a gate tensor's values, known from its gate kinds: a dense
+// one-qubit matrix that is real (H, X, RY, ...) or has a real diagonal and an
+// imaginary off-diagonal (RX, Y, the QAOA mixer); a diagonal whose entries are
+// all +1 or -1 (Z, CZ), or all of modulus one (RZ, S, T, CPHASE, ZZPHASE).
+enum GateForm { kFormGeneric = 0, kFormReal = 1, kFormRxLike = 2, kFormUnit = 3, kFormSigns = 4 };
 
 // Fused streaming of a chain of gate-sized steps on one large tensor: the
 // chain is split into passes; a pass keeps a chunk of 2^l elements (the bits
@@ -115,11 +122,16 @@ struct SweepGateDesc {
   int32_t lidx[2];       // local bit index of bit j of the gate's index; a diagonal gate's bit outside
                          // the chunk is -(address position + 1)
   int32_t rb[2];         // dense gates: index in the segment's register bits of bit j
-  int32_t unit;          // diagonal with unit-modulus entries: applied as accumulated phase angles
+  int32_t unit;          // diagonal with unit-modulus entries
   int32_t g_buf;
-  int32_t pad;
+  int32_t form;          // GateForm of the values
+  int32_t voff;          // the gate's values in the chain's value table: dense (m, k) row-major, diagonal by b
   int64_t g_off;
   int32_t gidx[16];      // element of G for (m, k) (dense, m*2^n + k) or b (diagonal)
+  // diagonal gates, resolved for the gate's segment: bit j of the index is register bit kreg[j]
+  // (>= 0), else the thread's local bit csrc[j] (0..l-1) or the chunk base's address bit csrc[j] - 64
+  int8_t kreg[2], csrc[2];
+  int32_t pad;
 };
 // Inside a pass, gates run in segments: a segment names four local bits
 // (`rbits`, indices into lpos) that each thread holds in registers (16
@@ -128,6 +140,10 @@ struct SweepGateDesc {
 struct SweepSegment {
   int8_t rbits[4];
   int32_t first_gate, n_gates;
+  // thread index bit t -> local bit tpos[t] (the local bits outside the registers, ascending);
+  // physoff[r]: LDS slot offset (padded) of the register combination r
+  int8_t tpos[8];
+  uint16_t physoff[16];
 };
 struct SweepPass {
   int32_t l;
@@ -151,6 +167,8 @@ struct AdjGateDesc {
   int32_t slot;     // gradient-partials column, or -1
   int32_t form;     // ADJ_*: shape of the generator (dense gates) / of U (diagonal gates)
   float gen[8];     // generator G: dense 2x2 row-major, or diagonal entries (complex, re/im interleaved)
+  int32_t uform;    // dense one-qubit gates: GateForm of U (kFormReal, kFormRxLike or kFormGeneric)
+  int8_t kreg[2], csrc[2];  // diagonal gates, resolved for the gate's segment as in SweepGateDesc
 };
 // dense one-qubit generators c X or Y, real diagonal generators, diagonal
 // gates whose entries are all +1 or -1 (applied as sign flips; bit b of
@@ -161,6 +179,10 @@ struct SweepChain {
   int32_t bits;
   int32_t first_pass, n_passes;
   int32_t n_steps;
+  // the chain's gate values, gathered into one table before its passes (sources in the path's
+  // sweep_val_src, first_val .. first_val + n_vals; the table at `vals` in the workspace)
+  int32_t first_val, n_vals;
+  BufRef vals;
 };
 
 struct PermuteDesc {
@@ -322,6 +344,7 @@ struct tn_path {
   std::vector<tnq::SweepPass> passes;
   std::vector<tnq::SweepSegment> segments;
   std::vector<tnq::SweepGateDesc> sweep_gates;
+  std::vector<int64_t> sweep_val_src;        // gate values of the chains: element offset | (buffer << 56)
   // adjoint gradient passes over the final tensor (built on first use; adj_state 1: built, -1: not possible)
   int32_t adj_state = 0;
   std::vector<tnq::SweepPass> adj_passes;

@@ -98,11 +98,14 @@ hipError_t launch_small_steps(hipStream_t s, const SmallStep* steps, const int32
                               const int32_t* level_off, const uint32_t* items, int n_lists, float2* in,
                               int64_t in_bs, float2* ws, int64_t ws_bs, int batch, int precision);
 
-// One fused streaming pass over a 2^bits tensor (see SweepPass).
+// One fused streaming pass over a 2^bits tensor (see SweepPass); vals: the
+// chain's gate values gathered by launch_gather_vals.
 hipError_t launch_sweep_pass(hipStream_t s, const SweepPass& ps, int bits, const SweepGateDesc* gates_dev,
                              const SweepSegment* segs_dev, const float2* in, int64_t in_bs, float2* out,
-                             int64_t out_bs, float2* IN, int64_t IN_bs, float2* WS, int64_t WS_bs, int batch,
-                             int precision);
+                             int64_t out_bs, const float2* vals, int64_t vals_bs, int batch, int precision);
+// out[z][i] = value i of a chain's table: src[i] = element offset | (BUF_IN or BUF_WS) << 56.
+hipError_t launch_gather_vals(hipStream_t s, const int64_t* src, int n, const float2* IN, int64_t in_bs,
+                              const float2* WS, int64_t ws_bs, float2* out, int64_t out_bs, int batch);
 
 // Contiguous copy of `n` complex64 per batch item.
 hipError_t launch_copy(hipStream_t s, const float2* in, int64_t in_bs, float2* out, int64_t out_bs, int64_t n,

@@ -612,9 +612,8 @@ struct SweepPassArgs {
   const float2* in;
   float2* out;
   int64_t in_bs, out_bs;
-  float2* IN;
-  float2* WS;
-  int64_t IN_bs, WS_bs;
+  const float2* vals;  // the chain's gathered gate values
+  int64_t vals_bs;
   const SweepGateDesc* gates;
   const SweepSegment* segs;
   int32_t n_segs, l, n_rest, pad;
@@ -625,17 +624,25 @@ struct SweepPassArgs {
 __device__ inline int64_t ins0(int64_t x, int p) { return ((x >> p) << (p + 1)) | (x & (((int64_t)1 << p) - 1)); }
 __device__ inline int lds_phys(int i) { return i + (i >> 5); }
 
-// real: the matrix has no imaginary part (RY, H, X, ...), half the multiplies
+// Shapes of a one-qubit matrix that take half the multiplies (known from the
+// gate kinds, see GateForm): every entry real (RY, H, X, ...), or a real
+// diagonal and an imaginary off-diagonal (RX, Y, the QAOA mixer exp(-i b X)).
+enum { kDenseGeneric = 0, kDenseReal = 1, kDenseRxLike = 2 };
+
 template <int PREC, int U>
-__device__ __forceinline__ void reg_apply1(float2 (&x)[16], const float2* g, bool real = false) {
+__device__ __forceinline__ void reg_apply1(float2 (&x)[16], const float2* g, int form = kDenseGeneric) {
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     if (r & (1 << U)) continue;
     const int r1 = r | (1 << U);
     const float2 a = x[r], b = x[r1];
-    if (PREC == TN_PREC_C64 && real) {
-      x[r] = f2(g[0].x * a.x + g[1].x * b.x, g[0].x * a.y + g[1].x * b.y);
-      x[r1] = f2(g[2].x * a.x + g[3].x * b.x, g[2].x * a.y + g[3].x * b.y);
+    if (PREC == TN_PREC_C64 && form == kDenseReal) {
+      x[r] = f2(fmaf(g[0].x, a.x, g[1].x * b.x), fmaf(g[0].x, a.y, g[1].x * b.y));
+      x[r1] = f2(fmaf(g[2].x, a.x, g[3].x * b.x), fmaf(g[2].x, a.y, g[3].x * b.y));
+    } else if (PREC == TN_PREC_C64 && form == kDenseRxLike) {
+      // g1 = i g1.y, g2 = i g2.y: i t (u + i v) = -t v + i t u
+      x[r] = f2(fmaf(g[0].x, a.x, -g[1].y * b.y), fmaf(g[0].x, a.y, g[1].y * b.x));
+      x[r1] = f2(fmaf(g[3].x, b.x, -g[2].y * a.y), fmaf(g[3].x, b.y, g[2].y * a.x));
     } else {
       x[r] = cmac<PREC>(cmul<PREC>(g[0], a), g[1], b);
       x[r1] = cmac<PREC>(cmul<PREC>(g[2], a), g[3], b);
@@ -731,6 +738,97 @@ __device__ __forceinline__ void apply_diag(float2 (&x)[16], int n, int k0, int k
   }
 }
 
+// Unit-modulus diagonals with the entry of index 0 factored out: the caller
+// multiplies d0 into the thread's deferred phase, and only the elements whose
+// index is not 0 are multiplied, by d_b conj(d0); an entry whose ratio is
+// exactly 1 (the ZZ phase diag(1, e, e, 1) has d3 = d0) is skipped.
+// (NS = 2: the same factors on a second state y)
+template <int PREC, int NS, int U0, int U1>
+__device__ __forceinline__ void diag_reg2_rel(float2 (&x)[16], float2 (&y)[16], float2 q1, float2 q2, float2 q3,
+                                              int skip) {
+  const bool s1 = (skip >> 1) & 1, s2 = (skip >> 2) & 1, s3 = (skip >> 3) & 1;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int b = ((r >> U0) & 1) | (((r >> U1) & 1) << 1);  // compile-time per r
+    if (b == 0 || (b == 1 && s1) || (b == 2 && s2) || (b == 3 && s3)) continue;
+    const float2 q = b == 1 ? q1 : b == 2 ? q2 : q3;
+    x[r] = cmul<PREC>(q, x[r]);
+    if (NS == 2) y[r] = cmul<PREC>(q, y[r]);
+  }
+}
+template <int PREC, int NS, int U>
+__device__ __forceinline__ void diag_reg1_rel(float2 (&x)[16], float2 (&y)[16], float2 q1) {
+#pragma unroll
+  for (int r = 0; r < 16; ++r)
+    if ((r >> U) & 1) {
+      x[r] = cmul<PREC>(q1, x[r]);
+      if (NS == 2) y[r] = cmul<PREC>(q1, y[r]);
+    }
+}
+__device__ inline bool is_one(float2 v) { return v.x == 1.f && v.y == 0.f; }
+
+// x[r] *= d_b (unit-modulus entries) as ph *= d_{b0} and x[r] *= d_b conj(d_{b0}),
+// b0 the index value of r = 0 (bits as in apply_diag: register bits k_j, else
+// bit j of c).  Returns with nothing done to x when no bit is a register bit.
+template <int PREC, int NS>
+__device__ __forceinline__ void apply_diag_unit(float2 (&x)[16], float2 (&y)[16], float2& ph, int n, int k0, int k1,
+                                                int c, float2 d0, float2 d1, float2 d2, float2 d3) {
+  auto rel = [](float2 d, float2 base) { return cmul<TN_PREC_C64>(d, f2(base.x, -base.y)); };
+  auto mulph = [&](float2 f) { ph = cmul<TN_PREC_C64>(ph, f); };
+  if (n == 2 && k0 >= 0 && k1 >= 0) {
+    mulph(d0);
+    const float2 q1 = rel(d1, d0), q2 = rel(d2, d0), q3 = rel(d3, d0);
+    const int skip = (is_one(q1) << 1) | (is_one(q2) << 2) | (is_one(q3) << 3);
+    switch (k0 * 4 + k1) {
+      case 1: diag_reg2_rel<PREC, NS, 0, 1>(x, y, q1, q2, q3, skip); break;
+      case 2: diag_reg2_rel<PREC, NS, 0, 2>(x, y, q1, q2, q3, skip); break;
+      case 3: diag_reg2_rel<PREC, NS, 0, 3>(x, y, q1, q2, q3, skip); break;
+      case 4: diag_reg2_rel<PREC, NS, 1, 0>(x, y, q1, q2, q3, skip); break;
+      case 6: diag_reg2_rel<PREC, NS, 1, 2>(x, y, q1, q2, q3, skip); break;
+      case 7: diag_reg2_rel<PREC, NS, 1, 3>(x, y, q1, q2, q3, skip); break;
+      case 8: diag_reg2_rel<PREC, NS, 2, 0>(x, y, q1, q2, q3, skip); break;
+      case 9: diag_reg2_rel<PREC, NS, 2, 1>(x, y, q1, q2, q3, skip); break;
+      case 11: diag_reg2_rel<PREC, NS, 2, 3>(x, y, q1, q2, q3, skip); break;
+      case 12: diag_reg2_rel<PREC, NS, 3, 0>(x, y, q1, q2, q3, skip); break;
+      case 13: diag_reg2_rel<PREC, NS, 3, 1>(x, y, q1, q2, q3, skip); break;
+      default: diag_reg2_rel<PREC, NS, 3, 2>(x, y, q1, q2, q3, skip); break;
+    }
+    return;
+  }
+  int k = -1;
+  float2 e0, e1;
+  if (n == 2 && k0 >= 0) {  // bit 1 constant
+    k = k0;
+    e0 = (c & 2) ? d2 : d0;
+    e1 = (c & 2) ? d3 : d1;
+  } else if (n == 2 && k1 >= 0) {  // bit 0 constant
+    k = k1;
+    e0 = (c & 1) ? d1 : d0;
+    e1 = (c & 1) ? d3 : d2;
+  } else if (n == 1 && k0 >= 0) {
+    k = k0;
+    e0 = d0;
+    e1 = d1;
+  }
+  if (k < 0) return;
+  mulph(e0);
+  const float2 q1 = rel(e1, e0);
+  switch (k) {
+    case 0: diag_reg1_rel<PREC, NS, 0>(x, y, q1); break;
+    case 1: diag_reg1_rel<PREC, NS, 1>(x, y, q1); break;
+    case 2: diag_reg1_rel<PREC, NS, 2>(x, y, q1); break;
+    default: diag_reg1_rel<PREC, NS, 3>(x, y, q1); break;
+  }
+}
+
+// Sign mask of a diagonal whose used entries are all +1 or -1 (CZ, Z), or -1.
+__device__ __forceinline__ int sign_mask(int n, float2 d0, float2 d1, float2 d2, float2 d3) {
+  auto pm1 = [](float2 d) { return d.y == 0.f && fabsf(d.x) == 1.f; };
+  const bool two = n == 2;
+  if (!pm1(d0) || !pm1(d1) || (two && (!pm1(d2) || !pm1(d3)))) return -1;
+  return (d0.x < 0.f) | ((d1.x < 0.f) << 1) | (two ? ((d2.x < 0.f) << 2) | ((d3.x < 0.f) << 3) : 0);
+}
+
 // x[r] = -x[r] where the diagonal's entry b is -1 (bit b of mask), b resolved as in apply_diag
 template <int U>
 __device__ __forceinline__ void signs_reg1(float2 (&x)[16], int m01) {
@@ -789,10 +887,6 @@ __device__ __forceinline__ void apply_signs(float2 (&x)[16], int n, int k0, int 
   }
 }
 
-// register index of local bit b in a segment (or -1)
-__device__ inline int reg_index(const SweepSegment& seg, int b) {
-  return b == seg.rbits[0] ? 0 : b == seg.rbits[1] ? 1 : b == seg.rbits[2] ? 2 : b == seg.rbits[3] ? 3 : -1;
-}
 
 template <int PREC>
 __global__ __launch_bounds__(kThreads) void k_sweep_pass(SweepPassArgs a) {
@@ -814,67 +908,66 @@ __global__ __launch_bounds__(kThreads) void k_sweep_pass(SweepPassArgs a) {
   __syncthreads();
   const float2* in = a.in + (int64_t)z * a.in_bs;
   float2* out = a.out + (int64_t)z * a.out_bs;
-  const float2* INz = a.IN + (int64_t)z * a.IN_bs;
-  const float2* WSz = a.WS + (int64_t)z * a.WS_bs;
+  const float2* V0 = a.vals + (int64_t)z * a.vals_bs;
   for (int i = tid; i < L; i += nt) buf[lds_phys(i)] = in[base | (i & 31) | dep_hi[i >> 5]];
   __syncthreads();
   for (int sg = 0; sg < a.n_segs; ++sg) {
-    const SweepSegment seg = a.segs[sg];
-    // thread index bits -> the local bits outside the register set
+    const SweepSegment& seg = a.segs[sg];
+    // the thread's local bits outside the registers, and its slots (see SweepSegment)
     int ob = 0;
-    {
-      int tb = 0;
-      for (int b = 0; b < a.l; ++b) {
-        if (b == seg.rbits[0] || b == seg.rbits[1] || b == seg.rbits[2] || b == seg.rbits[3]) continue;
-        if ((tid >> tb) & 1) ob |= 1 << b;
-        ++tb;
-      }
-    }
-    int li[16];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) ob |= ((tid >> t) & 1) << seg.tpos[t];
+    const int pob = ob + (ob >> 5);
     float2 x[16];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      li[r] = ob | ((r & 1) << seg.rbits[0]) | (((r >> 1) & 1) << seg.rbits[1]) | (((r >> 2) & 1) << seg.rbits[2]) |
-              (((r >> 3) & 1) << seg.rbits[3]);
-      x[r] = buf[lds_phys(li[r])];
-    }
+    for (int r = 0; r < 16; ++r) x[r] = buf[pob + seg.physoff[r]];
     // diagonal factors that are the same for all of a thread's elements (every
     // bit of the gate outside the register set) commute with every gate of the
     // segment: they are multiplied into one per-thread factor, applied once
     float2 ph = f2(1.f, 0.f);
     for (int gi = seg.first_gate; gi < seg.first_gate + seg.n_gates; ++gi) {
       const SweepGateDesc& gd = a.gates[gi];
-      const float2* G = (gd.g_buf == BUF_IN ? INz : WSz) + gd.g_off;
+      const float2* V = V0 + gd.voff;
       if (gd.diag) {
-        // unused entries of gidx are 0, so all four loads stay in bounds
-        const float2 d0 = G[gd.gidx[0]], d1 = G[gd.gidx[1]], d2 = G[gd.gidx[2]], d3 = G[gd.gidx[3]];
-        int k[2] = {-1, -1}, c = 0;
+        const bool two = gd.n == 2;
+        const float2 d0 = V[0], d1 = V[1];
+        const float2 d2 = two ? V[2] : f2(1.f, 0.f), d3 = two ? V[3] : f2(1.f, 0.f);
+        const int k0 = gd.kreg[0], k1 = two ? gd.kreg[1] : -1;
+        int cb = 0;  // the index bits that are constant over the thread's elements
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-          if (j >= gd.n) break;
-          const int lj = gd.lidx[j];
-          if (lj < 0) c |= (int)((base >> (-lj - 1)) & 1) << j;  // outside the chunk
-          else if ((k[j] = reg_index(seg, lj)) < 0) c |= ((ob >> lj) & 1) << j;  // a thread bit
+          if (j >= gd.n || gd.kreg[j] >= 0) continue;
+          const int cs = gd.csrc[j];
+          cb |= (cs >= 64 ? (int)((base >> (cs - 64)) & 1) : ((ob >> cs) & 1)) << j;
         }
-        if (k[0] < 0 && k[1] < 0) {
-          const float2 f = c == 0 ? d0 : c == 1 ? d1 : c == 2 ? d2 : d3;
-          ph = f2(ph.x * f.x - ph.y * f.y, ph.x * f.y + ph.y * f.x);
+        if (gd.form == kFormSigns) {  // entries +-1: sign flips, no multiplies
+          const int sm = (d0.x < 0.f) | ((d1.x < 0.f) << 1) | ((d2.x < 0.f) << 2) | ((d3.x < 0.f) << 3);
+          if (k0 < 0 && k1 < 0) {
+            if ((sm >> cb) & 1) ph = f2(-ph.x, -ph.y);
+          } else {
+            apply_signs(x, gd.n, k0, k1, cb, sm);
+          }
+        } else if (k0 < 0 && k1 < 0) {
+          const float2 f = cb == 0 ? d0 : cb == 1 ? d1 : cb == 2 ? d2 : d3;
+          ph = cmul<TN_PREC_C64>(ph, f);
+        } else if (gd.form == kFormUnit) {
+          apply_diag_unit<PREC, 1>(x, x, ph, gd.n, k0, k1, cb, d0, d1, d2, d3);
         } else {
-          apply_diag<PREC>(x, gd.n, k[0], k[1], c, d0, d1, d2, d3);
+          apply_diag<PREC>(x, gd.n, k0, k1, cb, d0, d1, d2, d3);
         }
       } else if (gd.n == 1) {
-        float2 g[4];
-        for (int e = 0; e < 4; ++e) g[e] = G[gd.gidx[e]];
-        const bool real = g[0].y == 0.f && g[1].y == 0.f && g[2].y == 0.f && g[3].y == 0.f;
+        const float2 g[4] = {V[0], V[1], V[2], V[3]};
+        const int form = gd.form == kFormReal ? kDenseReal : gd.form == kFormRxLike ? kDenseRxLike : kDenseGeneric;
         switch (gd.rb[0]) {
-          case 0: reg_apply1<PREC, 0>(x, g, real); break;
-          case 1: reg_apply1<PREC, 1>(x, g, real); break;
-          case 2: reg_apply1<PREC, 2>(x, g, real); break;
-          default: reg_apply1<PREC, 3>(x, g, real); break;
+          case 0: reg_apply1<PREC, 0>(x, g, form); break;
+          case 1: reg_apply1<PREC, 1>(x, g, form); break;
+          case 2: reg_apply1<PREC, 2>(x, g, form); break;
+          default: reg_apply1<PREC, 3>(x, g, form); break;
         }
       } else {
         float2 g[16];
-        for (int e = 0; e < 16; ++e) g[e] = G[gd.gidx[e]];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) g[e] = V[e];
         switch (gd.rb[0] * 4 + gd.rb[1]) {
           case 1: reg_apply2<PREC, 0, 1>(x, g); break;
           case 2: reg_apply2<PREC, 0, 2>(x, g); break;
@@ -886,20 +979,38 @@ __global__ __launch_bounds__(kThreads) void k_sweep_pass(SweepPassArgs a) {
       }
     }
 #pragma unroll
-    for (int r = 0; r < 16; ++r)
-      buf[lds_phys(li[r])] = f2(ph.x * x[r].x - ph.y * x[r].y, ph.x * x[r].y + ph.y * x[r].x);
+    for (int r = 0; r < 16; ++r) buf[pob + seg.physoff[r]] = cmul<TN_PREC_C64>(ph, x[r]);
     __syncthreads();
   }
   for (int i = tid; i < L; i += nt) out[base | (i & 31) | dep_hi[i >> 5]] = buf[lds_phys(i)];
 }
 
+// The gate values of a chain's passes in one table (see SweepChain).
+__global__ void k_gather_vals(const int64_t* src, int n, const float2* IN, int64_t in_bs, const float2* WS,
+                              int64_t ws_bs, float2* out, int64_t out_bs) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int z = blockIdx.y;
+  if (i >= n) return;
+  const int64_t v = src[i];
+  const int64_t off = v & (((int64_t)1 << 56) - 1);
+  const float2* b = (v >> 56) == BUF_IN ? IN + (int64_t)z * in_bs : WS + (int64_t)z * ws_bs;
+  out[(int64_t)z * out_bs + i] = b[off];
+}
+
+hipError_t launch_gather_vals(hipStream_t s, const int64_t* src, int n, const float2* IN, int64_t in_bs,
+                              const float2* WS, int64_t ws_bs, float2* out, int64_t out_bs, int batch) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_vals, dim3((unsigned)((n + kThreads - 1) / kThreads), batch), dim3(kThreads), 0, s,
+                     src, n, IN, in_bs, WS, ws_bs, out, out_bs);
+  return hipGetLastError();
+}
+
 hipError_t launch_sweep_pass(hipStream_t s, const SweepPass& ps, int bits, const SweepGateDesc* gates_dev,
                              const SweepSegment* segs_dev, const float2* in, int64_t in_bs, float2* out,
-                             int64_t out_bs, float2* IN, int64_t IN_bs, float2* WS, int64_t WS_bs, int batch,
-                             int precision) {
+                             int64_t out_bs, const float2* vals, int64_t vals_bs, int batch, int precision) {
   SweepPassArgs a;
   a.in = in; a.out = out; a.in_bs = in_bs; a.out_bs = out_bs;
-  a.IN = IN; a.WS = WS; a.IN_bs = IN_bs; a.WS_bs = WS_bs;
+  a.vals = vals; a.vals_bs = vals_bs;
   a.gates = gates_dev;
   a.segs = segs_dev + ps.first_seg;
   a.n_segs = ps.n_segs;
@@ -2359,24 +2470,16 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a) {
     }
     __syncthreads();
     for (int sg = 0; sg < a.n_segs; ++sg) {
-      const SweepSegment seg = a.segs[sg];
+      const SweepSegment& seg = a.segs[sg];
       int ob = 0;
-      {
-        int tb = 0;
-        for (int b = 0; b < a.l; ++b) {
-          if (b == seg.rbits[0] || b == seg.rbits[1] || b == seg.rbits[2] || b == seg.rbits[3]) continue;
-          if ((tid >> tb) & 1) ob |= 1 << b;
-          ++tb;
-        }
-      }
-      int li[16];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) ob |= ((tid >> t) & 1) << seg.tpos[t];
+      const int pob = ob + (ob >> 5);
       float2 xp[16], xl[16];
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        li[r] = ob | ((r & 1) << seg.rbits[0]) | (((r >> 1) & 1) << seg.rbits[1]) |
-                (((r >> 2) & 1) << seg.rbits[2]) | (((r >> 3) & 1) << seg.rbits[3]);
-        xp[r] = bp[lds_phys(li[r])];
-        xl[r] = bl[lds_phys(li[r])];
+        xp[r] = bp[pob + seg.physoff[r]];
+        xl[r] = bl[pob + seg.physoff[r]];
       }
       // unit-modulus diagonal factors that are the same for all of a thread's
       // elements go into one per-thread factor, applied to both states at the
@@ -2388,13 +2491,13 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a) {
         const float2* U = Uz + (int64_t)gd.gate * 16;
         const float2* G = reinterpret_cast<const float2*>(gd.gen);
         if (gd.diag) {
-          int k[2] = {-1, -1}, c = 0;
+          const int k[2] = {gd.kreg[0], gd.n == 2 ? gd.kreg[1] : -1};
+          int c = 0;  // the index bits that are constant over the thread's elements
 #pragma unroll
           for (int j = 0; j < 2; ++j) {
-            if (j >= gd.n) break;
-            const int lj = gd.lidx[j];
-            if (lj < 0) c |= (int)((base >> (-lj - 1)) & 1) << j;
-            else if ((k[j] = reg_index(seg, lj)) < 0) c |= ((ob >> lj) & 1) << j;
+            if (j >= gd.n || gd.kreg[j] >= 0) continue;
+            const int cs = gd.csrc[j];
+            c |= (cs >= 64 ? (int)((base >> (cs - 64)) & 1) : ((ob >> cs) & 1)) << j;
           }
           const bool two = gd.n == 2;
           const bool uniform = k[0] < 0 && k[1] < 0;  // the same entry for every element of the thread
@@ -2419,11 +2522,11 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a) {
           const float2 d0 = f2(u0.x, -u0.y), d1 = f2(u1.x, -u1.y), d2 = f2(u2.x, -u2.y), d3 = f2(u3.x, -u3.y);
           if (uniform) {
             const float2 f = c == 0 ? d0 : c == 1 ? d1 : c == 2 ? d2 : d3;
-            ph = f2(ph.x * f.x - ph.y * f.y, ph.x * f.y + ph.y * f.x);
+            ph = cmul<TN_PREC_C64>(ph, f);
             continue;
           }
-          apply_diag<PREC>(xp, gd.n, k[0], k[1], c, d0, d1, d2, d3);
-          apply_diag<PREC>(xl, gd.n, k[0], k[1], c, d0, d1, d2, d3);
+          // unitary gates: the entries have unit modulus, so the first one joins the deferred phase
+          apply_diag_unit<PREC, 2>(xp, xl, ph, gd.n, k[0], k[1], c, d0, d1, d2, d3);
         } else if (gd.n == 1) {
           if (gd.red >= 0) {
             float g;
@@ -2455,17 +2558,17 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a) {
             if (lane == 0) red[gd.red][wv] += v;
           }
           // U^dagger[m][k] = conj(U[k][m])
-          const bool real = U[0].y == 0.f && U[1].y == 0.f && U[2].y == 0.f && U[3].y == 0.f;
           float2 ud[4];
           ud[0] = f2(U[0].x, -U[0].y);
           ud[1] = f2(U[2].x, -U[2].y);
           ud[2] = f2(U[1].x, -U[1].y);
           ud[3] = f2(U[3].x, -U[3].y);
+          const int form = gd.uform == kFormReal ? kDenseReal : gd.uform == kFormRxLike ? kDenseRxLike : kDenseGeneric;
           switch (gd.rb[0]) {
-            case 0: reg_apply1<PREC, 0>(xp, ud, real); reg_apply1<PREC, 0>(xl, ud, real); break;
-            case 1: reg_apply1<PREC, 1>(xp, ud, real); reg_apply1<PREC, 1>(xl, ud, real); break;
-            case 2: reg_apply1<PREC, 2>(xp, ud, real); reg_apply1<PREC, 2>(xl, ud, real); break;
-            default: reg_apply1<PREC, 3>(xp, ud, real); reg_apply1<PREC, 3>(xl, ud, real); break;
+            case 0: reg_apply1<PREC, 0>(xp, ud, form); reg_apply1<PREC, 0>(xl, ud, form); break;
+            case 1: reg_apply1<PREC, 1>(xp, ud, form); reg_apply1<PREC, 1>(xl, ud, form); break;
+            case 2: reg_apply1<PREC, 2>(xp, ud, form); reg_apply1<PREC, 2>(xl, ud, form); break;
+            default: reg_apply1<PREC, 3>(xp, ud, form); reg_apply1<PREC, 3>(xl, ud, form); break;
           }
         } else {
           // dense two-qubit gates carry no gradient term (the planner checks)
@@ -2492,8 +2595,8 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a) {
       }
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        bp[lds_phys(li[r])] = f2(ph.x * xp[r].x - ph.y * xp[r].y, ph.x * xp[r].y + ph.y * xp[r].x);
-        bl[lds_phys(li[r])] = f2(ph.x * xl[r].x - ph.y * xl[r].y, ph.x * xl[r].y + ph.y * xl[r].x);
+        bp[pob + seg.physoff[r]] = cmul<TN_PREC_C64>(ph, xp[r]);
+        bl[pob + seg.physoff[r]] = cmul<TN_PREC_C64>(ph, xl[r]);
       }
       __syncthreads();
     }

@@ -18,6 +18,8 @@
 #include <chrono>
 #include <cstdlib>
 #include <thread>
+#include <cstdio>
+#include <cstdlib>
 #include <cmath>
 #include <map>
 #include <set>
@@ -231,6 +233,25 @@ std::vector<int32_t> reorder_small_first(const tn_network* net, const std::vecto
 
 namespace {
 
+// A segment's thread-bit map and the LDS slots of its register combinations
+// (slot of local index i: i + i/32; the map from a thread's bits and the
+// register bits are disjoint, so a slot is the sum of their two slots).
+void fill_segment_tables(SweepSegment& seg, int l) {
+  int t = 0;
+  for (int j = 0; j < 8; ++j) seg.tpos[j] = 0;
+  for (int b = 0; b < l && t < 8; ++b) {
+    bool reg = false;
+    for (int r = 0; r < 4; ++r) reg |= seg.rbits[r] == b;
+    if (!reg) seg.tpos[t++] = (int8_t)b;
+  }
+  for (int r = 0; r < 16; ++r) {
+    int off = 0;
+    for (int j = 0; j < 4; ++j)
+      if ((r >> j) & 1) off |= 1 << seg.rbits[j];
+    seg.physoff[r] = (uint16_t)(off + (off >> 5));
+  }
+}
+
 // Group chains of consecutive gate-sized steps on one large tensor into fused
 // streaming passes (light-cone rule: a gate joins the current pass if its bits
 // fit in the pass's local set and no earlier gate left out of the pass touches
@@ -240,6 +261,7 @@ void build_chains(tn_path* path, int T) {
   path->passes.clear();
   path->segments.clear();
   path->sweep_gates.clear();
+  path->sweep_val_src.clear();
   const int S = (int)path->steps.size();
   auto sweepable = [&](int s) {
     const StepProgram& P = path->steps[s];
@@ -267,6 +289,8 @@ void build_chains(tn_path* path, int T) {
     ch.bits = path->steps[s].sk.t_bits;
     ch.first_pass = (int32_t)path->passes.size();
     ch.n_steps = e - s;
+    ch.first_val = (int32_t)path->sweep_val_src.size();
+    ch.n_vals = 0;
     const int R = ch.bits;
     std::vector<PassItem> items;
     for (int i = s; i < e; ++i) {
@@ -289,22 +313,46 @@ void build_chains(tn_path* path, int T) {
       ps.first_gate = (int32_t)path->sweep_gates.size();
       ps.n_gates = (int32_t)pp.gates.size();
       ps.n_red = 0;
-      for (const PlannedGate& pg : pp.gates) {
+      for (size_t gi = 0; gi < pp.gates.size(); ++gi) {
+        const PlannedGate& pg = pp.gates[gi];
         const SkinnyDesc& d = path->steps[s + pg.item].sk;
         SweepGateDesc gd;
         gd.diag = pg.diag;
         gd.n = pg.n;
-        gd.pad = 0;
         for (int j = 0; j < 2; ++j) {
           gd.lidx[j] = pg.lidx[j];
           gd.rb[j] = pg.rb[j];
         }
         gd.g_buf = d.g.buf;
         gd.unit = gd.diag ? d.g_unit : 0;
+        gd.form = d.g_form;
         gd.g_off = d.g.off;
         for (int j = 0; j < 16; ++j) gd.gidx[j] = 0;
         const int ne = gd.diag ? (1 << gd.n) : (1 << (2 * gd.n));
         for (int j = 0; j < ne; ++j) gd.gidx[j] = d.gidx[j];
+        // the gate's values, in the order the kernel reads them
+        gd.voff = (int32_t)path->sweep_val_src.size() - ch.first_val;
+        for (int j = 0; j < ne; ++j)
+          path->sweep_val_src.push_back((d.g.off + d.gidx[j]) | ((int64_t)d.g.buf << 56));
+        gd.pad = 0;
+        // resolve the diagonal's bits for its segment
+        const PlannedSeg* segp = nullptr;
+        for (const PlannedSeg& sg : pp.segs)
+          if ((int)gi >= sg.first && (int)gi < sg.first + sg.count) segp = &sg;
+        gd.kreg[0] = gd.kreg[1] = -1;
+        gd.csrc[0] = gd.csrc[1] = 0;
+        if (gd.diag && segp) {
+          for (int j = 0; j < gd.n; ++j) {
+            const int lj = gd.lidx[j];
+            if (lj < 0) {
+              gd.csrc[j] = (int8_t)(64 + (-lj - 1));
+              continue;
+            }
+            for (int r = 0; r < 4; ++r)
+              if (segp->rbits[r] == lj) gd.kreg[j] = (int8_t)r;
+            if (gd.kreg[j] < 0) gd.csrc[j] = (int8_t)lj;
+          }
+        }
         path->sweep_gates.push_back(gd);
       }
       ps.first_seg = (int32_t)path->segments.size();
@@ -313,12 +361,14 @@ void build_chains(tn_path* path, int T) {
         for (int j = 0; j < 4; ++j) seg.rbits[j] = sg.rbits[j];
         seg.first_gate = ps.first_gate + sg.first;
         seg.n_gates = sg.count;
+        fill_segment_tables(seg, ps.l);
         path->segments.push_back(seg);
       }
       ps.n_segs = (int32_t)pp.segs.size();
       path->passes.push_back(ps);
     }
     ch.n_passes = (int32_t)path->passes.size() - ch.first_pass;
+    ch.n_vals = (int32_t)path->sweep_val_src.size() - ch.first_val;
     path->steps[s].chain = (int32_t)path->chains.size();
     for (int i = s + 1; i < e; ++i) path->steps[i].chain = -2;
     path->chains.push_back(ch);
@@ -577,20 +627,31 @@ tn_status compile_program(const tn_network* net, tn_path* path, const std::vecto
             d.gidx[((b << nm) + m) * (1 << nk) + k] = (int32_t)a;
           }
       d.g = G.ref;
-      // a diagonal gate tensor from the unit-modulus family (its phases can be accumulated as angles)
+      // the gate tensor's value shape, from its gate kinds: unit-modulus or +-1 diagonals; real or
+      // RX-like one-qubit matrices (products of real matrices are real, of RX-like ones RX-like)
       d.g_unit = 0;
+      d.g_form = kFormGeneric;
       {
         const int gid = a_small ? ia : ib;
-        if (gid < T && net->tensors[gid].kind == TK_GATE && net->tensors[gid].recipe >= 0 && d.nk == 0 &&
-            d.nm == 0) {
+        if (gid < T && net->tensors[gid].kind == TK_GATE && net->tensors[gid].recipe >= 0) {
           const Recipe& r = net->recipes[net->tensors[gid].recipe];
-          bool unit = r.diag && r.split_side < 0;
-          for (int o = r.op_begin; o < r.op_end && unit; ++o) {
+          bool unit = true, signs = true, real = true, rxl = true;
+          for (int o = r.op_begin; o < r.op_end; ++o) {
             const int k = net->ops[o].kind;
-            unit = k == TN_GATE_Z || k == TN_GATE_S || k == TN_GATE_T || k == TN_GATE_RZ || k == TN_GATE_CZ ||
-                   k == TN_GATE_CPHASE || k == TN_GATE_ZZPHASE;
+            unit &= k == TN_GATE_Z || k == TN_GATE_S || k == TN_GATE_T || k == TN_GATE_RZ || k == TN_GATE_CZ ||
+                    k == TN_GATE_CPHASE || k == TN_GATE_ZZPHASE;
+            signs &= k == TN_GATE_Z || k == TN_GATE_CZ;
+            real &= k == TN_GATE_H || k == TN_GATE_X || k == TN_GATE_Z || k == TN_GATE_RY || k == TN_GATE_CZ ||
+                    k == TN_GATE_CNOT || k == TN_GATE_SWAP;
+            rxl &= k == TN_GATE_RX || k == TN_GATE_MIXER || k == TN_GATE_Y;
           }
-          d.g_unit = unit ? 1 : 0;
+          const bool whole = r.split_side < 0 && r.op_end > r.op_begin;
+          if (d.nk == 0 && d.nm == 0 && r.diag && whole) {
+            d.g_unit = unit ? 1 : 0;
+            d.g_form = signs ? kFormSigns : unit ? kFormUnit : kFormGeneric;
+          } else if (d.nb == 0 && d.nk == 1 && d.nm == 1 && !r.diag && whole && r.nq == 1) {
+            d.g_form = real ? kFormReal : rxl ? kFormRxLike : kFormGeneric;
+          }
         }
       }
       d.t = Tt.ref;
@@ -992,6 +1053,17 @@ tn_status compile_program(const tn_network* net, tn_path* path, const std::vecto
   path->final_bits = loc[last].bits;
   path->final_ref = loc[last].ref;
   path->final_elems = loc[last].elems;
+  // the chains' gathered gate values sit above every other buffer (chains run one at a time)
+  int64_t max_vals = 0;
+  for (const SweepChain& ch : path->chains) max_vals = std::max<int64_t>(max_vals, ch.n_vals);
+  if (max_vals > 0) {
+    const int64_t off = (alloc.peak + 31) & ~(int64_t)31;
+    for (SweepChain& ch : path->chains) {
+      ch.vals.buf = BUF_WS;
+      ch.vals.off = off;
+    }
+    alloc.peak = off + max_vals;
+  }
   path->ws_elems = std::max<int64_t>(alloc.peak, 32);
   path->n_inputs = T;
   build_q328_program(net, path);
@@ -1067,8 +1139,34 @@ void build_adjoint_plan(const tn_network* net, tn_path* path, const std::vector<
       // fixed diagonal gates of +-1 entries (Z, CZ) are sign flips
       const Recipe& rc = net->sweep_recipes[g.recipe];
       const int kind0 = rc.op_end > rc.op_begin ? net->sweep_ops[rc.op_begin].kind : -1;
+      const bool single = rc.op_end - rc.op_begin == 1;
       if (g.diag && gd.slot < 0 && (kind0 == TN_GATE_Z || kind0 == TN_GATE_CZ))
         gd.form = ADJ_DIAG_SIGNS | ((g.nq == 2 ? 8 : 2) << 8);  // the -1 entry: |11> (b = 3) or |1> (b = 1)
+      // U^dagger of a real matrix is real, of an RX-like one RX-like
+      gd.uform = kFormGeneric;
+      if (!g.diag && g.nq == 1 && single) {
+        if (kind0 == TN_GATE_RY || kind0 == TN_GATE_H || kind0 == TN_GATE_X || kind0 == TN_GATE_Z) gd.uform = kFormReal;
+        if (kind0 == TN_GATE_RX || kind0 == TN_GATE_MIXER || kind0 == TN_GATE_Y) gd.uform = kFormRxLike;
+      }
+      // resolve a diagonal's bits for its segment
+      gd.kreg[0] = gd.kreg[1] = -1;
+      gd.csrc[0] = gd.csrc[1] = 0;
+      if (g.diag) {
+        const PlannedSeg* segp = nullptr;
+        const int gi_in_pass = (int)(&pg - &pp.gates[0]);
+        for (const PlannedSeg& sg : pp.segs)
+          if (gi_in_pass >= sg.first && gi_in_pass < sg.first + sg.count) segp = &sg;
+        for (int j = 0; j < gd.n && segp; ++j) {
+          const int lj = gd.lidx[j];
+          if (lj < 0) {
+            gd.csrc[j] = (int8_t)(64 + (-lj - 1));
+            continue;
+          }
+          for (int r = 0; r < 4; ++r)
+            if (segp->rbits[r] == lj) gd.kreg[j] = (int8_t)r;
+          if (gd.kreg[j] < 0) gd.csrc[j] = (int8_t)lj;
+        }
+      }
       path->adj_gates.push_back(gd);
     }
     if (ps.n_red > kAdjMaxRed) {
@@ -1083,6 +1181,7 @@ void build_adjoint_plan(const tn_network* net, tn_path* path, const std::vector<
       for (int j = 0; j < 4; ++j) seg.rbits[j] = sg.rbits[j];
       seg.first_gate = ps.first_gate + sg.first;
       seg.n_gates = sg.count;
+      fill_segment_tables(seg, ps.l);
       path->adj_segments.push_back(seg);
     }
     ps.n_segs = (int32_t)pp.segs.size();

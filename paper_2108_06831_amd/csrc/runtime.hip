@@ -216,6 +216,7 @@ struct DevPath {
   uint32_t* items = nullptr;
   SweepGateDesc* sweep_gates = nullptr;
   SweepSegment* segments = nullptr;
+  int64_t* sweep_val_src = nullptr;
   AdjGateDesc* adj_gates = nullptr;     // uploaded on the first backward call
   SweepSegment* adj_segments = nullptr;
 };
@@ -235,6 +236,7 @@ static tn_status ensure_path_device(tn_path* path, DevPath** out) {
   HIP_TRY(upload(&d->items, path->small_items));
   HIP_TRY(upload(&d->sweep_gates, path->sweep_gates));
   HIP_TRY(upload(&d->segments, path->segments));
+  HIP_TRY(upload(&d->sweep_val_src, path->sweep_val_src));
   *out = d;
   return TN_OK;
 }
@@ -251,6 +253,7 @@ void device_release_path(tn_path* path) {
   (void)hipFree(d->items);
   (void)hipFree(d->sweep_gates);
   (void)hipFree(d->segments);
+  (void)hipFree(d->sweep_val_src);
   (void)hipFree(d->adj_gates);
   (void)hipFree(d->adj_segments);
   (void)hipSetDevice(cur);
@@ -357,11 +360,16 @@ static tn_status run_steps_body(hipStream_t s, tn_path* path, const Bases& B, in
       rw.buf = BUF_WS;
       float2* INp = resolve(B, ri, &IN_bs);
       float2* WSp = resolve(B, rw, &WS_bs);
+      int64_t vbs = 0;
+      float2* vals = ch.n_vals > 0 ? resolve(B, ch.vals, &vbs) : nullptr;
+      if (ch.n_vals > 0)
+        HIP_TRY(launch_gather_vals(s, dp->sweep_val_src + ch.first_val, ch.n_vals, INp, IN_bs, WSp, WS_bs, vals, vbs,
+                                   batch));
       for (int k = 0; k < ch.n_passes; ++k) {
         const SweepPass& ps = path->passes[ch.first_pass + k];
         hipEvent_t ev = prof_start(s, TN_KERNEL_SWEEP);
         HIP_TRY(launch_sweep_pass(s, ps, ch.bits, dp->sweep_gates, dp->segments, k == 0 ? ip : op,
-                                  k == 0 ? ibs : obs, op, obs, INp, IN_bs, WSp, WS_bs, batch, precision));
+                                  k == 0 ? ibs : obs, op, obs, vals, vbs, batch, precision));
         double fl = 0;
         for (int g = 0; g < ps.n_gates; ++g) {
           const SweepGateDesc& gd = path->sweep_gates[ps.first_gate + g];
