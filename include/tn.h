@@ -130,7 +130,10 @@ typedef struct {
   int32_t max_log2_intermediate; /* TN_ELIMIT if an intermediate exceeds 2^this elements; <= 0: 40 */
   uint64_t seed;                 /* TN_PATH_RANDOM and TN_PATH_SEARCH */
   int32_t trials;                /* TN_PATH_SEARCH: randomised trials; <= 0: 64 */
-  int32_t reserved;
+  int32_t max_slice_bits;        /* index slicing: when no order of `kind` keeps every intermediate within
+                                    the cap, fix the values of bond indices of at most this many address bits
+                                    in total (2^bits slices, contracted one after another and summed);
+                                    0: never slice (TN_ELIMIT instead) */
 } tn_plan_opts;
 
 typedef struct {
@@ -151,6 +154,8 @@ typedef struct {
   int32_t n_product_launches;    /* launches of the steps outside the interpreter and the fused passes, with
                                     the default launch shapes in complex64: independent per-output products
                                     that follow each other share a launch */
+  int32_t n_slice_bits;          /* address bits of the sliced bond indices: 2^n_slice_bits slices (0: none);
+                                    flops, bytes and max_intermediate_elems are per slice */
 } tn_path_stats;
 
 typedef struct tn_network tn_network;
@@ -195,6 +200,18 @@ tn_status tn_network_values(const tn_network* net, const double* params, const u
                             double* out, int64_t out_len_doubles);
 
 /*
+ * Index slicing (opts.max_slice_bits > 0; Sec. 2.2.3: the order is a free
+ * hyperparameter, and Sec. 3 names the size of the intermediates as the
+ * binding constraint).  When no order fits the cap, bond indices (modes that
+ * are not outputs) are chosen greedily -- each time the index whose removal
+ * most reduces the largest intermediate of an uncapped greedy order -- until
+ * the order fits; the sliced network (those indices fixed) is planned again
+ * under the cap.  A sum over a bond index is the sum of the contractions with
+ * that index fixed to each value, so the 2^bits slices are contracted one
+ * after another and their results summed.  tn_contract_path, tn_amplitudes
+ * and tn_expectation run sliced paths; tn_backward, tn_autotune, the Q3.28
+ * mode and tn_contract_path_noalloc return TN_EUNSUPPORTED for them.
+ *
  * Contraction order (Sec. 2.2.3 and Sec. 3: greedy search over pairwise
  * contractions).  Greedy: among pairs of live tensors that share a mode,
  * contract the pair minimising |C| - |A| - |B| (elements); ties by smaller |C|,
@@ -210,6 +227,12 @@ tn_status tn_plan_path(const tn_network* net, const tn_plan_opts* opts, tn_path*
 void tn_path_destroy(tn_path* path);
 /* SSA pairs: step s contracts ids pairs[2s], pairs[2s+1] into id n_tensors+s. */
 tn_status tn_path_pairs(const tn_path* path, int32_t* n_steps, int32_t* pairs, int32_t capacity);
+/* Sliced bond modes of the path (index slicing; none for an unsliced path):
+ * *n_modes of them, written to modes[0..capacity).  Slice number sigma fixes
+ * the sliced modes' indices to sigma's bits, the modes in this order and each
+ * mode's bits from least significant up.  The pairs and step modes above are
+ * those of the sliced network, whose tensors lack these modes. */
+tn_status tn_path_slices(const tn_path* path, int32_t* n_modes, int32_t* modes, int32_t capacity);
 /* Modes of the tensor produced by step s (C order, as laid out in memory),
  * and the step's GEMM view. kind: 0 = streaming small-operand kernel,
  * 1 = MFMA matrix product, 2 = interpreter of small steps. */

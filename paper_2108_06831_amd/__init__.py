@@ -162,8 +162,9 @@ class Network:
             off += sz
         return vals
 
-    def plan(self, kind: str = "greedy", max_log2_intermediate: int = 0, seed: int = 0, trials: int = 0) -> "Path":
-        return tn_plan_path(self, kind, max_log2_intermediate, seed, trials)
+    def plan(self, kind: str = "greedy", max_log2_intermediate: int = 0, seed: int = 0, trials: int = 0,
+             max_slice_bits: int = 0) -> "Path":
+        return tn_plan_path(self, kind, max_log2_intermediate, seed, trials, max_slice_bits)
 
 
 class Path:
@@ -186,6 +187,14 @@ class Path:
         arr = (ctypes.c_int32 * max(2 * n.value, 1))()
         check(lib().tn_path_pairs(self.handle, ctypes.byref(n), arr, 2 * n.value))
         return [(arr[2 * i], arr[2 * i + 1]) for i in range(n.value)]
+
+    def slices(self):
+        """Sliced bond modes (slice sigma fixes them to sigma's bits, mode by mode, low bits first)."""
+        n = ctypes.c_int32()
+        check(lib().tn_path_slices(self.handle, ctypes.byref(n), None, 0))
+        arr = (ctypes.c_int32 * max(n.value, 1))()
+        check(lib().tn_path_slices(self.handle, ctypes.byref(n), arr, n.value))
+        return list(arr[: n.value])
 
     def step(self, s: int):
         rank = ctypes.c_int32()
@@ -233,9 +242,10 @@ def tn_build_network(n_qubits, gates, n_gates, n_params, output_kind, n_bitstrin
     return Network(h, n_qubits, n_params, output_kind, n_bitstrings)
 
 
-def tn_plan_path(net: Network, kind="greedy", max_log2_intermediate: int = 0, seed: int = 0, trials: int = 0) -> Path:
+def tn_plan_path(net: Network, kind="greedy", max_log2_intermediate: int = 0, seed: int = 0, trials: int = 0,
+                 max_slice_bits: int = 0) -> Path:
     opts = _lib.tn_plan_opts(PATH_KIND[kind] if isinstance(kind, str) else int(kind), max_log2_intermediate, seed,
-                             trials, 0)
+                             trials, max_slice_bits)
     h = ctypes.c_void_p()
     st = _lib.tn_path_stats()
     check(lib().tn_plan_path(net.handle, ctypes.byref(opts), ctypes.byref(h), ctypes.byref(st)))

@@ -38,7 +38,7 @@ class tn_observable(ctypes.Structure):
 
 class tn_plan_opts(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("max_log2_intermediate", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("trials", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("trials", ctypes.c_int32), ("max_slice_bits", ctypes.c_int32)]
 
 
 class tn_path_stats(ctypes.Structure):
@@ -48,7 +48,8 @@ class tn_path_stats(ctypes.Structure):
                 ("n_steps", ctypes.c_int32), ("n_permutes", ctypes.c_int32), ("n_gemm_steps", ctypes.c_int32),
                 ("n_skinny_steps", ctypes.c_int32), ("n_small_steps", ctypes.c_int32),
                 ("n_small_lists", ctypes.c_int32), ("n_sweep_steps", ctypes.c_int32),
-                ("n_sweep_passes", ctypes.c_int32), ("n_product_launches", ctypes.c_int32)]
+                ("n_sweep_passes", ctypes.c_int32), ("n_product_launches", ctypes.c_int32),
+                ("n_slice_bits", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -62,7 +63,7 @@ class TNError(RuntimeError):
 
 EXPORTS = [
     "tn_build_network", "tn_network_destroy", "tn_network_info", "tn_network_tensor", "tn_network_output",
-    "tn_network_values", "tn_plan_path", "tn_path_destroy", "tn_path_pairs", "tn_path_step", "tn_workspace_bytes",
+    "tn_network_values", "tn_plan_path", "tn_path_destroy", "tn_path_pairs", "tn_path_slices", "tn_path_step", "tn_workspace_bytes",
     "tn_contract_path", "tn_amplitudes", "tn_expectation_workspace_bytes", "tn_expectation",
     "tn_backward_workspace_bytes", "tn_backward", "tn_contract_pair_workspace_bytes", "tn_contract_pair",
     "tn_last_error", "tn_version", "tn_profile_enable", "tn_profile_read", "tn_profile_reset", "tn_autotune",
@@ -106,6 +107,8 @@ def _declare(lib):
     lib.tn_path_destroy.restype = None
     lib.tn_path_pairs.argtypes = [P, P, P, i32]
     lib.tn_path_pairs.restype = st
+    lib.tn_path_slices.argtypes = [P, P, P, i32]
+    lib.tn_path_slices.restype = st
     lib.tn_path_step.argtypes = [P, i32, P, P, P, P]
     lib.tn_path_step.restype = st
     lib.tn_workspace_bytes.argtypes = [P, P, i32]

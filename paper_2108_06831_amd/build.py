@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtnq.so")
-SOURCES = ["network.cpp", "planner.cpp", "passes.cpp", "program.cpp", "fixedpoint.cpp", "kernels.hip", "runtime.hip"]
+SOURCES = ["network.cpp", "planner.cpp", "passes.cpp", "program.cpp", "fixedpoint.cpp", "slicing.cpp", "kernels.hip", "runtime.hip"]
 ARCH = os.environ.get("TNQ_OFFLOAD_ARCH", "gfx950")
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}", "-I", os.path.join(ROOT, "include"),

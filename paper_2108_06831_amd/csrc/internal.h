@@ -3,6 +3,7 @@
 #pragma once
 #include <stdint.h>
 
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -320,6 +321,19 @@ struct QStep {
   int8_t a_k[kQMaxKBits], b_k[kQMaxKBits];
 };
 
+// Index slicing: input tensor t of the sliced network (its sliced modes take
+// no address bits) is gathered from the full tensor: sliced address bit j is
+// full address bit keep_pos[j]; full address bit cut_pos[k] is bit cut_src[k]
+// of the slice index.
+constexpr int kSliceMaxKeep = 40;
+constexpr int kSliceMaxCut = 16;
+struct SliceTensor {
+  int64_t src_off, dst_off;  // elements, in the full and in the sliced input buffer
+  int32_t n_keep, n_cut;
+  int8_t keep_pos[kSliceMaxKeep];
+  int8_t cut_pos[kSliceMaxCut], cut_src[kSliceMaxCut];
+};
+
 }  // namespace tnq
 
 struct tn_path {
@@ -350,6 +364,12 @@ struct tn_path {
   std::vector<tnq::SweepPass> adj_passes;
   std::vector<tnq::SweepSegment> adj_segments;
   std::vector<tnq::AdjGateDesc> adj_gates;
+  // index slicing: the program runs on `sliced_net` (the network with the modes slice_modes fixed);
+  // 2^slice_bits slices, slice index bits in the order of slice_modes, each mode's bits low to high
+  int32_t slice_bits = 0;
+  std::shared_ptr<tn_network> sliced_net;
+  std::vector<int32_t> slice_modes;
+  std::vector<tnq::SliceTensor> slice_tensors;
   // Q3.28 fixed-point program (q_state 1: built; -1: a step exceeds the kernel's bit limits)
   int32_t q_state = 0;
   std::vector<tnq::QStep> q_steps;
@@ -378,6 +398,14 @@ std::vector<int32_t> reorder_small_first(const tn_network* net, const std::vecto
                                          int64_t* small_region);
 // fixedpoint.cpp: the Q3.28 program of a path (sets q_state)
 void build_q328_program(const tn_network* net, tn_path* path);
+// slicing.cpp: bond modes to fix so that `pairs` keeps every intermediate within 2^cap_log2 (TN_ELIMIT if
+// more than max_bits address bits would be needed); the network with those modes fixed; and the gather
+// tables from the full input tensors to the sliced ones
+tn_status choose_slices(const tn_network* net, const std::vector<int32_t>& pairs, int cap_log2, int max_bits,
+                        std::vector<int32_t>* slice_modes);
+std::shared_ptr<tn_network> sliced_network(const tn_network* net, const std::vector<int32_t>& slice_modes);
+tn_status slice_gather_tables(const tn_network* net, const tn_network* sliced, const std::vector<int32_t>& slice_modes,
+                              std::vector<SliceTensor>* out);
 // network.cpp
 void network_values_host(const tn_network* net, const double* params, const uint64_t* bits, double* out);
 // runtime

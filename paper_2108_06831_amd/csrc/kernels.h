@@ -107,6 +107,13 @@ hipError_t launch_sweep_pass(hipStream_t s, const SweepPass& ps, int bits, const
 hipError_t launch_gather_vals(hipStream_t s, const int64_t* src, int n, const float2* IN, int64_t in_bs,
                               const float2* WS, int64_t ws_bs, float2* out, int64_t out_bs, int batch);
 
+// Index slicing: the sliced input tensors of slice `slice` from the full ones
+// (see SliceTensor), and acc = src (first != 0) or acc += src over n elements.
+hipError_t launch_slice_gather(hipStream_t s, const SliceTensor* ts, int nt, const float2* full, int64_t full_bs,
+                               float2* sl, int64_t sl_bs, int64_t slice, int batch);
+hipError_t launch_accumulate(hipStream_t s, const float2* src, int64_t src_bs, float2* acc, int64_t acc_bs, int64_t n,
+                             int first, int batch);
+
 // Contiguous copy of `n` complex64 per batch item.
 hipError_t launch_copy(hipStream_t s, const float2* in, int64_t in_bs, float2* out, int64_t out_bs, int64_t n,
                        int batch);

@@ -1038,6 +1038,53 @@ hipError_t launch_sweep_pass(hipStream_t s, const SweepPass& ps, int bits, const
 }
 
 // ---------------------------------------------------------------------------
+// Index slicing: the input tensors of one slice gathered from the full ones,
+// and the slices' results summed.
+// ---------------------------------------------------------------------------
+__global__ void k_slice_gather(const SliceTensor* ts, int nt, const float2* full, int64_t full_bs, float2* sl,
+                               int64_t sl_bs, int64_t slice) {
+  const int t = blockIdx.x, z = blockIdx.y;
+  if (t >= nt) return;
+  const SliceTensor st = ts[t];
+  int64_t cut = 0;  // the fixed bits of this slice, at their places in the full tensor
+  for (int k = 0; k < st.n_cut; ++k) cut |= ((slice >> st.cut_src[k]) & 1) << st.cut_pos[k];
+  const float2* src = full + (int64_t)z * full_bs + st.src_off;
+  float2* dst = sl + (int64_t)z * sl_bs + st.dst_off;
+  const int64_t n = (int64_t)1 << st.n_keep;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    int64_t a = cut;
+    for (int j = 0; j < st.n_keep; ++j) a |= ((i >> j) & 1) << st.keep_pos[j];
+    dst[i] = src[a];
+  }
+}
+
+hipError_t launch_slice_gather(hipStream_t s, const SliceTensor* ts, int nt, const float2* full, int64_t full_bs,
+                               float2* sl, int64_t sl_bs, int64_t slice, int batch) {
+  if (nt == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_slice_gather, dim3(nt, batch), dim3(64), 0, s, ts, nt, full, full_bs, sl, sl_bs, slice);
+  return hipGetLastError();
+}
+
+// acc = src (first) or acc += src
+__global__ void k_accumulate(const float2* src, int64_t src_bs, float2* acc, int64_t acc_bs, int64_t n, int first) {
+  const int z = blockIdx.y;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+    const float2 v = src[(int64_t)z * src_bs + i];
+    float2& a = acc[(int64_t)z * acc_bs + i];
+    a = first ? v : f2(a.x + v.x, a.y + v.y);
+  }
+}
+
+hipError_t launch_accumulate(hipStream_t s, const float2* src, int64_t src_bs, float2* acc, int64_t acc_bs, int64_t n,
+                             int first, int batch) {
+  int64_t blocks = (n + kThreads - 1) / kThreads;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(k_accumulate, dim3((unsigned)std::max<int64_t>(blocks, 1), batch), dim3(kThreads), 0, s, src,
+                     src_bs, acc, acc_bs, n, first);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Bit-permutation transpose through LDS
 // ---------------------------------------------------------------------------
 constexpr int kMaxTileBits = 10;

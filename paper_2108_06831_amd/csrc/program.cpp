@@ -1271,18 +1271,8 @@ double modeled_seconds(const tn_path* path) {
 
 using namespace tnq;
 
-extern "C" tn_status tn_plan_path(const tn_network* net, const tn_plan_opts* opts, tn_path** path_out,
-                                  tn_path_stats* stats_out) {
-  clear_error();
-  if (!net || !path_out) return set_error(TN_EINVAL, "NULL argument");
-  *path_out = nullptr;
-  tn_plan_opts o{};
-  o.kind = TN_PATH_GREEDY;
-  o.max_log2_intermediate = 0;
-  o.seed = 0;
-  if (opts) o = *opts;
-  if (o.kind < TN_PATH_GREEDY || o.kind > TN_PATH_SEARCH) return set_error(TN_EINVAL, "unknown path kind");
-  auto t0 = std::chrono::steady_clock::now();
+// An order of kind o.kind within the cap and its compiled program (TN_ELIMIT if none fits).
+static tn_status plan_path_impl(const tn_network* net, const tn_plan_opts& o, tn_path** path_out) {
   tn_path* p = nullptr;
   double max_log2 = 0;
   const std::string cap_msg =
@@ -1397,6 +1387,63 @@ extern "C" tn_status tn_plan_path(const tn_network* net, const tn_plan_opts* opt
                                             std::to_string(min_log2) + ")" + cap_msg);
     clear_error();
   }
+  *path_out = p;
+  return TN_OK;
+}
+
+extern "C" tn_status tn_plan_path(const tn_network* net, const tn_plan_opts* opts, tn_path** path_out,
+                                  tn_path_stats* stats_out) {
+  clear_error();
+  if (!net || !path_out) return set_error(TN_EINVAL, "NULL argument");
+  *path_out = nullptr;
+  tn_plan_opts o{};
+  o.kind = TN_PATH_GREEDY;
+  o.max_log2_intermediate = 0;
+  o.seed = 0;
+  if (opts) o = *opts;
+  if (o.kind < TN_PATH_GREEDY || o.kind > TN_PATH_SEARCH) return set_error(TN_EINVAL, "unknown path kind");
+  if (o.max_slice_bits < 0 || o.max_slice_bits > kSliceMaxCut)
+    return set_error(TN_EINVAL, "max_slice_bits must be in 0.." + std::to_string(kSliceMaxCut));
+  auto t0 = std::chrono::steady_clock::now();
+  tn_path* p = nullptr;
+  tn_status st = plan_path_impl(net, o, &p);
+  if (st == TN_ELIMIT && o.max_slice_bits > 0) {
+    // index slicing: bond indices chosen on an uncapped greedy order, then the sliced network planned
+    const int cap = o.max_log2_intermediate > 0 ? o.max_log2_intermediate : 40;
+    tn_plan_opts g = o;
+    g.kind = TN_PATH_GREEDY;
+    g.max_log2_intermediate = 62;
+    std::vector<int32_t> pairs, smodes;
+    double ml = 0;
+    if ((st = plan_order(net, g, pairs, &ml)) != TN_OK) return st;
+    if ((st = choose_slices(net, pairs, cap, o.max_slice_bits, &smodes)) != TN_OK) return st;
+    std::shared_ptr<tn_network> sn = sliced_network(net, smodes);
+    st = plan_path_impl(sn.get(), o, &p);
+    if (st == TN_ELIMIT) {  // the uncapped greedy order fits once sliced
+      p = new tn_path();
+      p->pairs = reorder_small_first(sn.get(), pairs, &p->n_small, &p->small_region);
+      const std::vector<int32_t> fl = output_layout(sn.get());
+      if ((st = compile_program(sn.get(), p, &fl)) != TN_OK) {
+        delete p;
+        return st;
+      }
+      p->stats.modeled_seconds = modeled_seconds(p);
+    }
+    if (st != TN_OK) return st;
+    if ((st = slice_gather_tables(net, sn.get(), smodes, &p->slice_tensors)) != TN_OK) {
+      delete p;
+      return st;
+    }
+    int bits = 0;
+    for (int m : smodes) bits += net->mode_log2[m];
+    p->slice_bits = bits;
+    p->slice_modes = smodes;
+    p->sliced_net = sn;
+    p->q_state = -1;  // the fixed-point mode runs unsliced paths only
+    p->stats.n_slice_bits = bits;
+    clear_error();
+  }
+  if (st != TN_OK) return st;
   auto t1 = std::chrono::steady_clock::now();
   p->stats.plan_seconds = std::chrono::duration<double>(t1 - t0).count();
   if (stats_out) *stats_out = p->stats;
@@ -1418,6 +1465,18 @@ extern "C" tn_status tn_path_pairs(const tn_path* path, int32_t* n_steps, int32_
   if (pairs) {
     if (capacity < 2 * S) return set_error(TN_EINVAL, "capacity too small");
     for (int i = 0; i < 2 * S; ++i) pairs[i] = path->pairs[i];
+  }
+  return TN_OK;
+}
+
+extern "C" tn_status tn_path_slices(const tn_path* path, int32_t* n_modes, int32_t* modes, int32_t capacity) {
+  clear_error();
+  if (!path) return set_error(TN_EINVAL, "path is NULL");
+  const int n = (int)path->slice_modes.size();
+  if (n_modes) *n_modes = n;
+  if (modes) {
+    if (capacity < n) return set_error(TN_EINVAL, "capacity too small");
+    for (int i = 0; i < n; ++i) modes[i] = path->slice_modes[i];
   }
   return TN_OK;
 }

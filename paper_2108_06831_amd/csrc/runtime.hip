@@ -217,6 +217,7 @@ struct DevPath {
   SweepGateDesc* sweep_gates = nullptr;
   SweepSegment* segments = nullptr;
   int64_t* sweep_val_src = nullptr;
+  SliceTensor* slice_tensors = nullptr;
   AdjGateDesc* adj_gates = nullptr;     // uploaded on the first backward call
   SweepSegment* adj_segments = nullptr;
 };
@@ -237,6 +238,7 @@ static tn_status ensure_path_device(tn_path* path, DevPath** out) {
   HIP_TRY(upload(&d->sweep_gates, path->sweep_gates));
   HIP_TRY(upload(&d->segments, path->segments));
   HIP_TRY(upload(&d->sweep_val_src, path->sweep_val_src));
+  HIP_TRY(upload(&d->slice_tensors, path->slice_tensors));
   *out = d;
   return TN_OK;
 }
@@ -254,6 +256,7 @@ void device_release_path(tn_path* path) {
   (void)hipFree(d->sweep_gates);
   (void)hipFree(d->segments);
   (void)hipFree(d->sweep_val_src);
+  (void)hipFree(d->slice_tensors);
   (void)hipFree(d->adj_gates);
   (void)hipFree(d->adj_segments);
   (void)hipSetDevice(cur);
@@ -481,10 +484,10 @@ static int pos_in(const std::vector<int32_t>& bits, int32_t l) {
 }
 
 // move the final tensor (layout `from`) into `dst` with layout `to`
-static tn_status finish_to(hipStream_t s, const Bases& B, const tn_path* path, const std::vector<int32_t>& to,
-                           float2* dst, int64_t dst_bs, int64_t n_copy, int batch, float2* scratch) {
-  int64_t fbs;
-  float2* f = resolve(B, path->final_ref, &fbs);
+// the final tensor f (stride fbs per batch item, layout path->final_bits) into dst
+static tn_status finish_to(hipStream_t s, const float2* f, int64_t fbs, const tn_path* path,
+                           const std::vector<int32_t>& to, float2* dst, int64_t dst_bs, int64_t n_copy, int batch,
+                           float2* scratch) {
   const std::vector<int32_t>& from = path->final_bits;
   if (from == to) {
     hipEvent_t ev = prof_start(s, TN_KERNEL_COPY);
@@ -605,6 +608,58 @@ extern "C" int32_t tn_profile_read(tn_kernel_profile* out, int32_t capacity) {
 }
 extern "C" const char* tn_version(void) { return "tnq 0.1 (gfx950)"; }
 
+// Workspace of a sliced path: [full input tensors x batch][sum of the slices x batch]
+// [the sliced program's workspace: its inputs, arena and aux, as layout_ws on the sliced network]
+struct SliceLayout {
+  size_t full_off, acc_off, prog_off, total;
+  WsLayout prog;  // relative to prog_off
+};
+
+static SliceLayout layout_sliced(const tn_network* net, const tn_path* path, int batch, size_t aux_bytes) {
+  SliceLayout L;
+  L.full_off = 0;
+  L.acc_off = align256(sizeof(float2) * (size_t)net->input_elems * batch);
+  L.prog_off = align256(L.acc_off + sizeof(float2) * (size_t)path->final_elems * batch);
+  L.prog = layout_ws(path->sliced_net.get(), path, batch, aux_bytes);
+  L.total = align256(L.prog_off + L.prog.total);
+  return L;
+}
+
+// Contract every slice and sum them into the accumulator (final layout, final_elems per batch item).
+static tn_status run_slices(hipStream_t s, tn_network* net, tn_path* path, DevNet* d, const double* params,
+                            int batch, const uint64_t* bits, int64_t count, char* w, const SliceLayout& L,
+                            int precision) {
+  DevPath* dp;
+  tn_status st = ensure_path_device(path, &dp);
+  if (st != TN_OK) return st;
+  const tn_network* sn = path->sliced_net.get();
+  float2* full = (float2*)(w + L.full_off);
+  float2* acc = (float2*)(w + L.acc_off);
+  char* pw = w + L.prog_off;
+  Bases B;
+  B.in = (float2*)(pw + L.prog.in_off);
+  B.in_bs = sn->input_elems;
+  B.ws = (float2*)(pw + L.prog.arena_off);
+  B.ws_bs = path->ws_elems;
+  if ((st = materialize(s, net, d, params, batch, bits, count, full)) != TN_OK) return st;
+  const int64_t n_slices = (int64_t)1 << path->slice_bits;
+  for (int64_t sl = 0; sl < n_slices; ++sl) {
+    HIP_TRY(launch_slice_gather(s, dp->slice_tensors, (int)path->slice_tensors.size(), full, net->input_elems, B.in,
+                                B.in_bs, sl, batch));
+    if ((st = run_steps(s, path, B, batch, precision)) != TN_OK) return st;
+    int64_t fbs;
+    const float2* f = resolve(B, path->final_ref, &fbs);
+    HIP_TRY(launch_accumulate(s, f, fbs, acc, path->final_elems, path->final_elems, sl == 0, batch));
+  }
+  return TN_OK;
+}
+
+static tn_status refuse_sliced(const tn_path* path, const char* what) {
+  if (path && path->slice_bits > 0)
+    return set_error(TN_EUNSUPPORTED, std::string(what) + " does not run sliced paths");
+  return TN_OK;
+}
+
 // workspace of the Q3.28 program: [input tensors x batch][arena x batch]
 static WsLayout layout_q328(const tn_network* net, const tn_path* path, int batch) {
   WsLayout L;
@@ -618,6 +673,7 @@ static WsLayout layout_q328(const tn_network* net, const tn_path* path, int batc
 extern "C" size_t tn_workspace_bytes(const tn_network* net, const tn_path* path, int32_t batch) {
   if (!net || !path || batch < 1) return 0;
   const size_t final_tmp = sizeof(float2) * (size_t)path->final_elems * batch;
+  if (path->slice_bits > 0) return layout_sliced(net, path, batch, std::max(expect_aux(batch), final_tmp)).total;
   size_t n = layout_ws(net, path, batch, std::max(expect_aux(batch), final_tmp)).total;
   if (path->q_state == 1) n = std::max(n, layout_q328(net, path, batch).total);
   return n;
@@ -631,6 +687,7 @@ static tn_status check_common(const tn_network* net, const tn_path* path, const 
   if (net->n_params > 0 && !params) return set_error(TN_EINVAL, "params_dev required (n_params > 0)");
   if (precision == TN_PREC_Q3_28) {
     if (!q328_ok) return set_error(TN_EUNSUPPORTED, "TN_PREC_Q3_28 is offered by tn_contract_path and tn_amplitudes");
+    if (path->slice_bits > 0) return set_error(TN_EUNSUPPORTED, "TN_PREC_Q3_28 does not run sliced paths");
     if (path->q_state != 1)
       return set_error(TN_EUNSUPPORTED, "a step of this path exceeds the fixed-point kernel's index limits");
     return TN_OK;
@@ -713,7 +770,9 @@ static tn_status contract_path_in(hipStream_t s, int32_t precision, tn_network* 
   if ((st = materialize(s, net, d, params_dev, batch, nullptr, 0, B.in)) != TN_OK) return st;
   if ((st = run_steps(s, path, B, batch, precision)) != TN_OK) return st;
   if (direct) return TN_OK;
-  return finish_to(s, B, path, to, B.out, B.out_bs, B.out_bs, batch, (float2*)(w + L.aux_off));
+  int64_t fbs;
+  const float2* f = resolve(B, path->final_ref, &fbs);
+  return finish_to(s, f, fbs, path, to, B.out, B.out_bs, B.out_bs, batch, (float2*)(w + L.aux_off));
 }
 
 extern "C" tn_status tn_contract_path(void* stream, int32_t precision, tn_network* net, tn_path* path,
@@ -735,6 +794,18 @@ extern "C" tn_status tn_contract_path(void* stream, int32_t precision, tn_networ
     const int64_t n_out = (int64_t)1 << net->n_qubits;
     return run_q328((hipStream_t)stream, net, path, d, params_dev, batch, nullptr, n_out, (char*)workspace_dev, to,
                     (float2*)out_dev, n_out);
+  }
+  if (path->slice_bits > 0) {
+    hipStream_t s = (hipStream_t)stream;
+    const size_t final_tmp = sizeof(float2) * (size_t)path->final_elems * batch;
+    const SliceLayout L = layout_sliced(net, path, batch, std::max(expect_aux(batch), final_tmp));
+    char* w = (char*)workspace_dev;
+    if ((st = run_slices(s, net, path, d, params_dev, batch, nullptr, 0, w, L, precision)) != TN_OK) return st;
+    std::vector<int32_t> to;
+    for (int q = 0; q < net->n_qubits; ++q) to.push_back(lab(net->wire_final[q], 0));
+    const int64_t n_out = (int64_t)1 << net->n_qubits;
+    return finish_to(s, (float2*)(w + L.acc_off), path->final_elems, path, to, (float2*)out_dev, n_out, n_out, batch,
+                     (float2*)(w + L.prog_off + L.prog.aux_off));
   }
   return contract_path_in((hipStream_t)stream, precision, net, path, d, params_dev, batch, (char*)workspace_dev,
                           out_dev);
@@ -779,6 +850,7 @@ extern "C" tn_status tn_contract_path_noalloc(void* stream, int32_t precision, t
   if (st != TN_OK) return st;
   if (net->output_kind != TN_OUT_STATEVECTOR) return set_error(TN_EINVAL, "network does not output a statevector");
   if (!out_dev) return set_error(TN_EINVAL, "NULL output buffer");
+  if ((st = refuse_sliced(path, "tn_contract_path_noalloc")) != TN_OK) return st;
   const size_t need = tn_workspace_bytes(net, path, batch);
   if (need > (size_t)TN_NOALLOC_SCRATCH_BYTES)
     return set_error(TN_ENOMEM, "workspace of " + std::to_string(need) + " bytes exceeds the static scratch of " +
@@ -826,6 +898,16 @@ extern "C" tn_status tn_amplitudes(void* stream, int32_t precision, tn_network* 
     return run_q328(s, net, path, d, params_dev, 1, bitstrings_dev, count, (char*)workspace_dev, to,
                     (float2*)out_dev, count);
   }
+  if (path->slice_bits > 0) {
+    const size_t final_tmp = sizeof(float2) * (size_t)path->final_elems;
+    const SliceLayout L = layout_sliced(net, path, 1, std::max(expect_aux(1), final_tmp));
+    char* w = (char*)workspace_dev;
+    if ((st = run_slices(s, net, path, d, params_dev, 1, bitstrings_dev, count, w, L, precision)) != TN_OK) return st;
+    std::vector<int32_t> to;
+    for (int j = net->batch_log2 - 1; j >= 0; --j) to.push_back(lab(net->batch_mode, j));
+    return finish_to(s, (float2*)(w + L.acc_off), path->final_elems, path, to, (float2*)out_dev, count, count, 1,
+                     (float2*)(w + L.prog_off + L.prog.aux_off));
+  }
   const size_t final_tmp = sizeof(float2) * (size_t)path->final_elems;
   WsLayout L = layout_ws(net, path, 1, std::max(expect_aux(1), final_tmp));
   char* w = (char*)workspace_dev;
@@ -845,7 +927,9 @@ extern "C" tn_status tn_amplitudes(void* stream, int32_t precision, tn_network* 
   if ((st = materialize(s, net, d, params_dev, 1, bitstrings_dev, count, B.in)) != TN_OK) return st;
   if ((st = run_steps(s, path, B, 1, precision)) != TN_OK) return st;
   if (direct) return TN_OK;
-  return finish_to(s, B, path, to, (float2*)out_dev, count, count, 1, (float2*)(w + L.aux_off));
+  int64_t fbs;
+  const float2* f = resolve(B, path->final_ref, &fbs);
+  return finish_to(s, f, fbs, path, to, (float2*)out_dev, count, count, 1, (float2*)(w + L.aux_off));
 }
 
 extern "C" size_t tn_expectation_workspace_bytes(tn_network* const* nets, tn_path* const* paths, int32_t n_circuits,
@@ -853,7 +937,8 @@ extern "C" size_t tn_expectation_workspace_bytes(tn_network* const* nets, tn_pat
   size_t mx = 0;
   for (int i = 0; i < n_circuits; ++i) {
     if (!nets || !paths || !nets[i] || !paths[i]) return 0;
-    mx = std::max(mx, layout_ws(nets[i], paths[i], batch, expect_aux(batch)).total);
+    mx = std::max(mx, paths[i]->slice_bits > 0 ? layout_sliced(nets[i], paths[i], batch, expect_aux(batch)).total
+                                               : layout_ws(nets[i], paths[i], batch, expect_aux(batch)).total);
   }
   return mx;
 }
@@ -880,8 +965,17 @@ extern "C" tn_status tn_expectation(void* stream, int32_t precision, tn_network*
     if ((st = make_terms(net, path, &obs[c], &terms)) != TN_OK) return st;
     DevNet* d;
     if ((st = ensure_device(net, &d)) != TN_OK) return st;
-    WsLayout L = layout_ws(net, path, batch, expect_aux(batch));
     char* w = (char*)workspace_dev;
+    if (path->slice_bits > 0) {  // the state is the sum of the slices
+      const SliceLayout SL = layout_sliced(net, path, batch, expect_aux(batch));
+      if ((st = run_slices(s, net, path, d, prm, batch, nullptr, 0, w, SL, precision)) != TN_OK) return st;
+      hipEvent_t ev = prof_start(s, TN_KERNEL_REDUCE);
+      HIP_TRY(launch_expectation(s, (float2*)(w + SL.acc_off), path->final_elems, path->final_elems, terms, batch,
+                                 (double*)(w + SL.prog_off + SL.prog.aux_off), out_dev + (int64_t)c * batch, 1));
+      prof_stop(s, ev, TN_KERNEL_REDUCE, 8.0 * (double)path->final_elems * batch, 0.0);
+      continue;
+    }
+    WsLayout L = layout_ws(net, path, batch, expect_aux(batch));
     Bases B;
     B.in = (float2*)(w + L.in_off);
     B.in_bs = net->input_elems;
@@ -935,6 +1029,7 @@ extern "C" tn_status tn_backward(void* stream, int32_t precision, tn_network* ne
   clear_error();
   tn_status st = check_common(net, path, params_dev, batch, precision);
   if (st != TN_OK) return st;
+  if ((st = refuse_sliced(path, "tn_backward")) != TN_OK) return st;
   if (net->output_kind != TN_OUT_STATEVECTOR) return set_error(TN_EINVAL, "backward needs a statevector network");
   if (!workspace_dev || !value_dev || (net->n_params > 0 && !grad_dev)) return set_error(TN_EINVAL, "NULL buffer");
   const size_t need = tn_backward_workspace_bytes(net, path, batch);
@@ -1115,6 +1210,7 @@ extern "C" tn_status tn_autotune(void* stream, int32_t precision, tn_network* ne
   clear_error();
   tn_status st = check_common(net, path, params_dev, batch, precision);
   if (st != TN_OK) return st;
+  if ((st = refuse_sliced(path, "tn_autotune")) != TN_OK) return st;
   if (!workspace_dev) return set_error(TN_EINVAL, "NULL workspace");
   if (reps < 1 || reps > 1000) return set_error(TN_EINVAL, "reps must be in 1..1000");
   const size_t need = tn_workspace_bytes(net, path, batch);
@@ -1324,5 +1420,7 @@ extern "C" tn_status tn_contract_pair(void* stream, int32_t precision, const voi
   }
   if ((st = run_steps(s, &pp.path, B, 1, precision)) != TN_OK) return st;
   if (direct) return TN_OK;
-  return finish_to(s, B, &pp.path, pp.c_bits, (float2*)c, 0, pp.c_elems, 1, nullptr);
+  int64_t fbs;
+  const float2* f = resolve(B, pp.path.final_ref, &fbs);
+  return finish_to(s, f, fbs, &pp.path, pp.c_bits, (float2*)c, 0, pp.c_elems, 1, nullptr);
 }

@@ -29,3 +29,46 @@ def execute(net, path, params=None, bitstrings=None):
     out_modes, _ = net.output()
     table = {}
     return np.einsum(f"{_letters(mx, table)}->{_letters(out_modes, table)}", X)
+
+
+def execute_sliced(net, path, params=None, bitstrings=None):
+    """The same for a sliced path: every slice fixes the sliced modes' indices
+    (np.take on each tensor that holds them), contracts the remaining network
+    along the path, and the slices' results are summed."""
+    vals = net.values(params, bitstrings)
+    info = net.info()
+    T = info["n_tensors"]
+    cut = path.slices()
+    ext = {}
+    for t in range(T):
+        modes, exts = net.tensor(t)
+        for m, e in zip(modes, exts):
+            ext[m] = e
+    total = None
+    n_slices = int(np.prod([ext[m] for m in cut])) if cut else 1
+    for sigma in range(n_slices):
+        fixed, r = {}, sigma
+        for m in cut:
+            fixed[m] = r % ext[m]
+            r //= ext[m]
+        tensors = {}
+        for t in range(T):
+            X, modes = vals[t], list(net.tensor(t)[0])
+            for m in cut:
+                while m in modes:
+                    ax = modes.index(m)
+                    X = np.take(X, fixed[m], axis=ax)
+                    modes.pop(ax)
+            tensors[t] = (X, modes)
+        for s, (i, j) in enumerate(path.pairs()):
+            (A, ma), (B, mb) = tensors.pop(i), tensors.pop(j)
+            mc = path.step(s)["modes"]
+            table = {}
+            spec = f"{_letters(ma, table)},{_letters(mb, table)}->{_letters(mc, table)}"
+            tensors[T + s] = (np.einsum(spec, A, B), mc)
+        (X, mx), = tensors.values()
+        out_modes, _ = net.output()
+        table = {}
+        X = np.einsum(f"{_letters(mx, table)}->{_letters(out_modes, table)}", X)
+        total = X if total is None else total + X
+    return total

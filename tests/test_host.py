@@ -320,3 +320,66 @@ def test_fig31_grid_plans_and_small_paths_match_oracle():
                         got = pathexec.execute(net, path, bitstrings=bits).reshape(-1)
                         assert np.max(np.abs(got - psi[[0, -1]])) < 1e-12
     assert worst < 1.0
+
+
+@pytest.mark.parametrize("case", ["grid3x4_cap10", "grid3x4_cap8", "brickwork12_dense", "hea10"])
+def test_sliced_paths_sum_to_the_oracle(case):
+    """Index slicing: a sum over a bond index equals the sum of the
+    contractions with that index fixed to each value (eq. (2.2)).  The planned
+    sliced path, executed slice by slice in FP64 on the CPU (fixing the
+    sliced modes with np.take), must sum to the oracle's result, and every
+    intermediate of the sliced program must fit the cap."""
+    params = None
+    if case.startswith("grid"):
+        cap = int(case[-2:].lstrip("p"))
+        circ, bits = workloads.config2(rows=3, cols=4, depth=8, n_bitstrings=64)
+        net = Network.from_circuit(circ, output="amplitudes", n_bitstrings=64)
+        want = oracle.amplitudes(oracle.statevector(circ), circ.n_qubits, bits)
+    elif case == "brickwork12_dense":
+        cap, bits = 12, None
+        circ = workloads.brickwork(12, 12, np.random.default_rng(5))
+        net = Network.from_circuit(circ, fuse="dense")
+        want = oracle.statevector(circ)
+    else:
+        cap, bits = 10, None
+        circ, pb, _ = workloads.config4(n=10, layers=3, batch=1)
+        params = pb[0]
+        net = Network.from_circuit(circ)
+        want = oracle.statevector(circ, params)
+    assert net.plan().stats["max_intermediate_elems"] > 2 ** cap  # slicing is needed
+    with pytest.raises(TNError) as e:
+        net.plan(max_log2_intermediate=cap)
+    assert e.value.status == _lib.TN_ELIMIT
+    path = net.plan(max_log2_intermediate=cap, max_slice_bits=12)
+    cut = path.slices()
+    st = path.stats
+    assert cut and st["n_slice_bits"] == len(cut)  # every mode here has extent 2
+    assert st["max_intermediate_elems"] <= 2 ** cap
+    out_modes, _ = net.output()
+    assert not set(cut) & set(out_modes)
+    for s in range(st["n_steps"]):
+        assert not set(cut) & set(path.step(s)["modes"])
+    got = pathexec.execute_sliced(net, path, params=params, bitstrings=bits).reshape(-1)[: want.size]
+    assert np.max(np.abs(got - want)) < 1e-12
+
+
+def test_slicing_options_and_limits():
+    net = Network.from_circuit(workloads.config0())
+    assert net.plan().slices() == [] and net.plan().stats["n_slice_bits"] == 0
+    for bad in (-1, 17):
+        with pytest.raises(TNError) as e:
+            net.plan(max_slice_bits=bad)
+        assert e.value.status == _lib.TN_EINVAL
+    # an output intermediate cannot be sliced: a statevector never fits a cap below its own size
+    with pytest.raises(TNError) as e:
+        net.plan(max_log2_intermediate=8, max_slice_bits=16)
+    assert e.value.status == _lib.TN_ELIMIT
+    # too small a budget for the cap
+    circ, bits = workloads.config2(rows=3, cols=4, depth=8, n_bitstrings=64)
+    amp = Network.from_circuit(circ, output="amplitudes", n_bitstrings=64)
+    with pytest.raises(TNError) as e:
+        amp.plan(max_log2_intermediate=8, max_slice_bits=2)
+    assert e.value.status == _lib.TN_ELIMIT
+    # the sliced workspace holds the full inputs, the running sum and one slice's program
+    p = amp.plan(max_log2_intermediate=10, max_slice_bits=12)
+    assert p.workspace_bytes(1) < amp.plan().workspace_bytes(1)
