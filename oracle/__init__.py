@@ -33,7 +33,7 @@ import numpy as np
 from workloads import Circuit, Gate, TWO_QUBIT
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_LIB_PATH = os.environ.get("ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")  # ORACLE_LIB: sanitizer build
 
 KIND_ID = {"H": 0, "X": 1, "Y": 2, "Z": 3, "S": 4, "T": 5, "SX": 6, "SY": 7, "SW": 8,
            "RX": 9, "RY": 10, "RZ": 11, "U3": 12, "MIXER": 13,

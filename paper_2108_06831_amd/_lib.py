@@ -10,7 +10,8 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libtnq.so")
+# TNQ_LIB selects another build of the same library (the host-sanitizer build)
+LIB_PATH = os.environ.get("TNQ_LIB") or os.path.join(_HERE, "libtnq.so")
 
 TN_OK, TN_EINVAL, TN_ENOMEM, TN_ELIMIT, TN_EDEVICE, TN_EUNSUPPORTED = range(6)
 STATUS_NAMES = {0: "TN_OK", 1: "TN_EINVAL", 2: "TN_ENOMEM", 3: "TN_ELIMIT", 4: "TN_EDEVICE", 5: "TN_EUNSUPPORTED"}
