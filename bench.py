@@ -411,6 +411,77 @@ class Gradients(Workload):
                 "sample": f"exact parameter-shift derivatives of the first {k} angles of vector 0 ({dt:.1f} s)"}
 
 
+def paper_workload(args):
+    """Sec. 4's sweep over the Fig. 3.1 test circuit (n qubits, k rounds): for
+    every (n, k) of Fig. 4.1b, the greedy planner's host time beside the
+    seconds the figure reports for its third-party library (other hardware,
+    other tool: context, not a target), and the GPU time of the contraction to
+    the full statevector and to the closed amplitude <0...0|U|0...0> along
+    the greedy order.  Prints one JSON line with a row per (n, k)."""
+    import torch
+    import workloads
+    import paper_2108_06831_amd as tnq
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    fig = []
+    with open(os.path.join(ROOT, "workloads", "fig41b_greedy_seconds.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                n, k, sec = line.split()
+                fig.append((int(n), int(k), float(sec)))
+    if args.paper_max_qubits:
+        fig = [r for r in fig if r[0] <= args.paper_max_qubits]
+
+    def gpu_ms(fn, reps):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    rows = []
+    zero = torch.zeros(1, dtype=torch.int64, device="cuda")
+    for n, k, fig_s in fig:
+        circ = workloads.paper_test_circuit(n, k)
+        sv = tnq.Network.from_circuit(circ)
+        amp = tnq.Network.from_circuit(circ, output="amplitudes", n_bitstrings=1)
+        plan_s = []
+        for _ in range(3):  # the best of three plans, as host timings are noisy
+            p_sv = sv.plan("greedy", max_log2_intermediate=30, max_slice_bits=16)
+            plan_s.append(p_sv.stats["plan_seconds"])
+        p_amp = amp.plan("greedy", max_log2_intermediate=30, max_slice_bits=16)
+        out = torch.empty(1, 1 << n, dtype=torch.complex64, device="cuda")
+        ws = torch.empty(p_sv.workspace_bytes(1), dtype=torch.uint8, device="cuda")
+        ws_a = torch.empty(p_amp.workspace_bytes(1), dtype=torch.uint8, device="cuda")
+        a_out = torch.empty(1, dtype=torch.complex64, device="cuda")
+        reps = 20 if n >= 24 else 100
+        sv_ms = gpu_ms(lambda: tnq.contract_path(sv, p_sv, out=out, workspace=ws), reps)
+        amp_ms = gpu_ms(lambda: tnq.amplitudes(amp, p_amp, zero, out=a_out, workspace=ws_a), reps)
+        # the closed network's value is the statevector's first amplitude (two different networks and orders)
+        a0, s0 = complex(a_out.cpu()[0]), complex(out[0, 0].cpu())
+        agree = abs(a0 - s0) / max(abs(s0), 1e-30)
+        rows.append({"n": n, "k": k, "plan_seconds": min(plan_s), "fig41b_seconds": fig_s,
+                     "statevector_ms": round(sv_ms, 4), "amplitude_ms": round(amp_ms, 4),
+                     "statevector_max_log2": int(np.log2(p_sv.stats["max_intermediate_elems"])),
+                     "amplitude_max_log2": int(np.log2(p_amp.stats["max_intermediate_elems"])),
+                     "amplitude_slice_bits": p_amp.stats["n_slice_bits"], "amp0_vs_state0": agree})
+        print(f"  n={n:2d} k={k:2d}: plan {min(plan_s) * 1e3:8.2f} ms (Fig. 4.1b {fig_s:9.3f} s); "
+              f"statevector {sv_ms:8.3f} ms, <0|U|0> {amp_ms:7.3f} ms; |a0-psi0|/|psi0| {agree:.1e}",
+              file=sys.stderr, flush=True)
+        del out, ws, ws_a
+    print(json.dumps({"metric": "Fig. 3.1 circuits: greedy planning seconds and GPU contraction ms",
+                      "unit": "seconds / ms", "n_gpus": 1, "data": "synthetic", "rows": rows,
+                      "max_plan_seconds": max(r["plan_seconds"] for r in rows),
+                      "max_fig41b_seconds": max(r["fig41b_seconds"] for r in rows)}))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -440,7 +511,17 @@ def main():
     ap.add_argument("--retune", action="store_true", help="ignore stored tuning records")
     ap.add_argument("--no-graph", action="store_true",
                     help="config 3: eager calls instead of one HIP graph per step (e.g. for counter collection)")
+    ap.add_argument("--paper-workload", action="store_true",
+                    help="the Fig. 3.1 sweep instead of a config: planner seconds per (n, k) beside Fig. 4.1b's, "
+                         "and GPU contraction times")
+    ap.add_argument("--paper-max-qubits", type=int, default=0, help="--paper-workload: only n up to this")
     args = ap.parse_args()
+    if args.paper_workload:
+        if args.gpus != 1:
+            print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
+                  file=sys.stderr)
+            sys.exit(2)
+        return paper_workload(args)
     short = args.config in (0, 1, 2)
     if args.path is None:
         args.path = "greedy" if args.config == 0 else "search"
