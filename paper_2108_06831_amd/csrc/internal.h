@@ -131,20 +131,23 @@ struct SweepGateDesc {
   int32_t gidx[16];      // element of G for (m, k) (dense, m*2^n + k) or b (diagonal)
   // diagonal gates, resolved for the gate's segment: bit j of the index is register bit kreg[j]
   // (>= 0), else the thread's local bit csrc[j] (0..l-1) or the chunk base's address bit csrc[j] - 64
-  int8_t kreg[2], csrc[2];
-  int32_t pad;
+  int32_t kreg[2], csrc[2];
 };
 // Inside a pass, gates run in segments: a segment names four local bits
 // (`rbits`, indices into lpos) that each thread holds in registers (16
 // elements per thread); its dense gates act only on those bits, its diagonal
 // gates on any bits.  Between segments the chunk goes through LDS once.
+// (Every field of the descriptors the pass kernels read per gate and segment
+// is 32 bits wide: the kernels then fetch them with scalar loads, whereas
+// narrower fields are read with vector memory loads whose latency every gate
+// would wait for.)
 struct SweepSegment {
-  int8_t rbits[4];
+  int32_t rbits[4];
   int32_t first_gate, n_gates;
   // thread index bit t -> local bit tpos[t] (the local bits outside the registers, ascending);
   // physoff[r]: LDS slot offset (padded) of the register combination r
-  int8_t tpos[8];
-  uint16_t physoff[16];
+  int32_t tpos[8];
+  int32_t physoff[16];
 };
 struct SweepPass {
   int32_t l;
@@ -169,7 +172,7 @@ struct AdjGateDesc {
   int32_t form;     // ADJ_*: shape of the generator (dense gates) / of U (diagonal gates)
   float gen[8];     // generator G: dense 2x2 row-major, or diagonal entries (complex, re/im interleaved)
   int32_t uform;    // dense one-qubit gates: GateForm of U (kFormReal, kFormRxLike or kFormGeneric)
-  int8_t kreg[2], csrc[2];  // diagonal gates, resolved for the gate's segment as in SweepGateDesc
+  int32_t kreg[2], csrc[2];  // diagonal gates, resolved for the gate's segment as in SweepGateDesc
 };
 // dense one-qubit generators c X or Y, real diagonal generators, diagonal
 // gates whose entries are all +1 or -1 (applied as sign flips; bit b of

@@ -624,6 +624,67 @@ struct SweepPassArgs {
 __device__ inline int64_t ins0(int64_t x, int p) { return ((x >> p) << (p + 1)) | (x & (((int64_t)1 << p) - 1)); }
 __device__ inline int lds_phys(int i) { return i + (i >> 5); }
 
+// Moving a chunk of 2^l = 16 nt elements between HBM and LDS: thread tid
+// takes elements tid + k nt, k = 0..15 (consecutive threads on consecutive
+// addresses).  The loads are issued eight at a time before their LDS writes,
+// so a thread waits for HBM twice per chunk instead of once per element,
+// without holding all sixteen in registers (which would lower the occupancy
+// of the pass kernels); the empty asm keeps the compiler from merging the two
+// halves.
+__device__ __forceinline__ void chunk_to_lds(float2* buf, const float2* src, int64_t base, const int64_t* dep_hi,
+                                             int tid, int nt) {
+#pragma unroll 1
+  for (int h = 0; h < 2; ++h) {
+    float2 v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int i = tid + (8 * h + k) * nt;
+      v[k] = src[base | (i & 31) | dep_hi[i >> 5]];
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) buf[lds_phys(tid + (8 * h + k) * nt)] = v[k];
+    asm volatile("" ::: "memory");
+  }
+}
+// The same for two tensors at once (eight elements of each in flight).
+__device__ __forceinline__ void chunk2_to_lds(float2* buf0, float2* buf1, const float2* src0, const float2* src1,
+                                              int64_t base, const int64_t* dep_hi, int tid, int nt) {
+#pragma unroll 1
+  for (int h = 0; h < 2; ++h) {
+    float2 v[8], w[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int i = tid + (8 * h + k) * nt;
+      const int64_t x = base | (i & 31) | dep_hi[i >> 5];
+      v[k] = src0[x];
+      w[k] = src1[x];
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      buf0[lds_phys(tid + (8 * h + k) * nt)] = v[k];
+      buf1[lds_phys(tid + (8 * h + k) * nt)] = w[k];
+    }
+    asm volatile("" ::: "memory");
+  }
+}
+__device__ __forceinline__ void chunk_from_lds(float2* dst, const float2* buf, int64_t base, const int64_t* dep_hi,
+                                               int tid, int nt) {
+  // the addresses are computed again here rather than kept in registers since the load
+  asm volatile("" ::: "memory");
+#pragma unroll 1
+  for (int h = 0; h < 2; ++h) {
+    float2 v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = buf[lds_phys(tid + (8 * h + k) * nt)];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int i = tid + (8 * h + k) * nt;
+      dst[base | (i & 31) | dep_hi[i >> 5]] = v[k];
+    }
+    asm volatile("" ::: "memory");
+  }
+}
+
 // Shapes of a one-qubit matrix that take half the multiplies (known from the
 // gate kinds, see GateForm): every entry real (RY, H, X, ...), or a real
 // diagonal and an imaginary off-diagonal (RX, Y, the QAOA mixer exp(-i b X)).
@@ -889,7 +950,12 @@ __device__ __forceinline__ void apply_signs(float2 (&x)[16], int n, int k0, int 
 
 
 template <int PREC>
-__global__ __launch_bounds__(kThreads) void k_sweep_pass(SweepPassArgs a) {
+// The descriptor and value tables come as separate __restrict__ arguments: the
+// compiler may then read them with scalar loads (nothing the kernel writes can
+// alias them) instead of vector memory loads on every gate.
+__global__ __launch_bounds__(kThreads) void k_sweep_pass(SweepPassArgs a, const SweepGateDesc* __restrict__ gates,
+                                                          const SweepSegment* __restrict__ segs,
+                                                          const float2* __restrict__ vals) {
   __shared__ float2 buf[(1 << kSweepMaxLocal) + (1 << (kSweepMaxLocal - 5))];
   __shared__ int64_t dep_hi[1 << (kSweepMaxLocal - 5)];
   const int z = blockIdx.y;
@@ -908,11 +974,11 @@ __global__ __launch_bounds__(kThreads) void k_sweep_pass(SweepPassArgs a) {
   __syncthreads();
   const float2* in = a.in + (int64_t)z * a.in_bs;
   float2* out = a.out + (int64_t)z * a.out_bs;
-  const float2* V0 = a.vals + (int64_t)z * a.vals_bs;
-  for (int i = tid; i < L; i += nt) buf[lds_phys(i)] = in[base | (i & 31) | dep_hi[i >> 5]];
+  const float2* V0 = vals + (int64_t)z * a.vals_bs;
+  chunk_to_lds(buf, in, base, dep_hi, tid, nt);
   __syncthreads();
   for (int sg = 0; sg < a.n_segs; ++sg) {
-    const SweepSegment& seg = a.segs[sg];
+    const SweepSegment& seg = segs[sg];
     // the thread's local bits outside the registers, and its slots (see SweepSegment)
     int ob = 0;
 #pragma unroll
@@ -926,7 +992,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep_pass(SweepPassArgs a) {
     // segment: they are multiplied into one per-thread factor, applied once
     float2 ph = f2(1.f, 0.f);
     for (int gi = seg.first_gate; gi < seg.first_gate + seg.n_gates; ++gi) {
-      const SweepGateDesc& gd = a.gates[gi];
+      const SweepGateDesc& gd = gates[gi];
       const float2* V = V0 + gd.voff;
       if (gd.diag) {
         const bool two = gd.n == 2;
@@ -982,7 +1048,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep_pass(SweepPassArgs a) {
     for (int r = 0; r < 16; ++r) buf[pob + seg.physoff[r]] = cmul<TN_PREC_C64>(ph, x[r]);
     __syncthreads();
   }
-  for (int i = tid; i < L; i += nt) out[base | (i & 31) | dep_hi[i >> 5]] = buf[lds_phys(i)];
+  chunk_from_lds(out, buf, base, dep_hi, tid, nt);
 }
 
 // The gate values of a chain's passes in one table (see SweepChain).
@@ -1031,9 +1097,11 @@ hipError_t launch_sweep_pass(hipStream_t s, const SweepPass& ps, int bits, const
   if (chunks > ((int64_t)1 << 24)) return hipErrorInvalidValue;
   const int threads = 1 << (ps.l - 4);
   if (precision == TN_PREC_BF16X3)
-    hipLaunchKernelGGL(k_sweep_pass<TN_PREC_BF16X3>, dim3((unsigned)chunks, batch), dim3(threads), 0, s, a);
+    hipLaunchKernelGGL(k_sweep_pass<TN_PREC_BF16X3>, dim3((unsigned)chunks, batch), dim3(threads), 0, s, a, a.gates,
+                       a.segs, a.vals);
   else
-    hipLaunchKernelGGL(k_sweep_pass<TN_PREC_C64>, dim3((unsigned)chunks, batch), dim3(threads), 0, s, a);
+    hipLaunchKernelGGL(k_sweep_pass<TN_PREC_C64>, dim3((unsigned)chunks, batch), dim3(threads), 0, s, a, a.gates, a.segs,
+                       a.vals);
   return hipGetLastError();
 }
 
@@ -1221,12 +1289,37 @@ struct GemmArgs {
   int64_t a_bs, b_bs, c_bs;
   int64_t batch, M, N, K;
   int64_t tiles_m, tiles_n;
+  int64_t band_n;   // tile columns per band of the tile order (divides tiles_n)
   int64_t c_elems;  // elements of C per parameter vector (split-K partial stride)
-  int32_t nbb, nbm, nbn, nbk, split, pad;
+  int32_t nbb, nbm, nbn, nbk, split, xcd;
   int8_t a_b[kGemmMaxBits], a_m[kGemmMaxBits], a_k[kGemmMaxBits];
   int8_t b_b[kGemmMaxBits], b_k[kGemmMaxBits], b_n[kGemmMaxBits];
   int8_t c_b[kGemmMaxBits], c_m[kGemmMaxBits], c_n[kGemmMaxBits];
 };
+
+// Tile order of the matrix-product kernels.  The GPU hands consecutive
+// workgroup ids to its eight XCDs in turn, and each XCD has its own L2.  With
+// xcd set (the grid is a multiple of 8), workgroup h takes logical id
+// (h mod 8) * (grid / 8) + h / 8, so each XCD runs one contiguous range of
+// logical ids, in order.  Logical ids walk the tile grid in bands of band_n
+// tile columns, n fastest inside a band: an XCD's range then covers a block of
+// rows of one band, whose B column tiles stay in its L2 while the rows pass
+// and whose A row tiles are used band_n times in a row.
+struct TileCoord {
+  int64_t tm, tn, rest;  // rest: the split, batch and parameter-vector index
+};
+
+__device__ inline TileCoord tile_coord(const GemmArgs& g) {
+  int64_t bid = blockIdx.x;
+  if (g.xcd) {
+    const int64_t per = (int64_t)gridDim.x >> 3;
+    bid = (bid & 7) * per + (bid >> 3);
+  }
+  const int64_t tmn = g.tiles_m * g.tiles_n;
+  const int64_t r = bid % tmn, band_tiles = g.tiles_m * g.band_n;
+  const int64_t band = r / band_tiles, q = r - band * band_tiles;
+  return {q / g.band_n, band * g.band_n + q % g.band_n, bid / tmn};
+}
 
 // Unrolled to the maximum map length: the positions sit in the kernel's
 // argument block at constant offsets, so they are read with scalar loads
@@ -1298,11 +1391,9 @@ __global__ __launch_bounds__(kThreads) void k_gemm(GemmArgs g) {
   __bf16 (*Bh)[kB3Row] = reinterpret_cast<__bf16 (*)[kB3Row]>(smem + 2 * BM * kB3Row * 2);
   __bf16 (*Bl)[kB3Row] = reinterpret_cast<__bf16 (*)[kB3Row]>(smem + 2 * BM * kB3Row * 2 + BN * kB3Row * 2);
 
-  int64_t bid = blockIdx.x;
-  const int64_t tn = bid % g.tiles_n;
-  bid /= g.tiles_n;
-  const int64_t tm = bid % g.tiles_m;
-  bid /= g.tiles_m;
+  const TileCoord tc = tile_coord(g);
+  const int64_t tn = tc.tn, tm = tc.tm;
+  int64_t bid = tc.rest;
   const int64_t ks = bid % g.split;
   bid /= g.split;
   const int64_t gb = bid % g.batch;
@@ -1535,11 +1626,9 @@ __global__ __launch_bounds__(kThreads, TM == 1 && !BP ? 4 : 2) void k_gemm3m(Gem
   __shared__ int64_t TAm[BM], TCm[BM], TBn[BN], TCn[BN], TAk[BK], TBk[BK];
   constexpr int kKt = 64;  // K tiles whose origin deposits are tabulated (the rest computed on the fly)
   __shared__ int64_t TAt[kKt], TBt[kKt];
-  int64_t bid = blockIdx.x;
-  const int64_t tn = bid % g.tiles_n;
-  bid /= g.tiles_n;
-  const int64_t tm = bid % g.tiles_m;
-  bid /= g.tiles_m;
+  const TileCoord tc = tile_coord(g);
+  const int64_t tn = tc.tn, tm = tc.tm;
+  int64_t bid = tc.rest;
   const int64_t ks = bid % g.split;
   bid /= g.split;
   const int64_t n_bgroups = BP == 1 ? g.batch / 4 : g.batch;
@@ -2071,7 +2160,8 @@ hipError_t launch_gemm(hipStream_t s, const GemmDesc& d, int tile, int split, co
   g.split = split > 1 ? split : 1;
   g.c_elems = d.batch * d.M * d.N;
   g.a_bs = a_bs; g.b_bs = b_bs;
-  g.nbb = d.nbb; g.nbm = d.nbm; g.nbn = d.nbn; g.nbk = d.nbk; g.pad = 0;
+  g.nbb = d.nbb; g.nbm = d.nbm; g.nbn = d.nbn; g.nbk = d.nbk; g.xcd = 0;
+  g.band_n = 1;
   for (int j = 0; j < kGemmMaxBits; ++j) {
     g.a_b[j] = d.a_b[j]; g.a_m[j] = d.a_m[j]; g.a_k[j] = d.a_k[j];
     g.b_b[j] = d.b_b[j]; g.b_k[j] = d.b_k[j]; g.b_n[j] = d.b_n[j];
@@ -2111,6 +2201,9 @@ hipError_t launch_gemm(hipStream_t s, const GemmDesc& d, int tile, int split, co
   const int64_t batch_blocks = tile == kGemmBatchPacked ? d.batch / 4 : d.batch;
   const int64_t blocks = g.tiles_m * g.tiles_n * g.split * batch_blocks * batch;
   if (blocks > ((int64_t)1 << 24)) return hipErrorInvalidValue;  // grid of < 2^32 work-items
+  // bands of a quarter of the tile columns on large grids (two XCDs per band), whole rows otherwise
+  g.band_n = g.tiles_n >= 16 && g.tiles_n % 4 == 0 && g.tiles_m >= 16 ? g.tiles_n / 4 : g.tiles_n;
+  g.xcd = blocks % 8 == 0 ? 1 : 0;
   const bool narrow = tile_narrow(d, tile);
   void* fn = precision == TN_PREC_BF16X3 ? gemm_fn_tile<1>(tile, d.a_kfast, d.b_nfast, narrow)
                                          : gemm_fn_tile<0>(tile, d.a_kfast, d.b_nfast, narrow);
@@ -2487,7 +2580,9 @@ __device__ __forceinline__ float reg_grad_y(const float2 (&p)[16], const float2 
 }
 
 template <int PREC>
-__global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a) {
+__global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a, const AdjGateDesc* __restrict__ gates,
+                                                            const SweepSegment* __restrict__ segs,
+                                                            const float2* __restrict__ Uall) {
   constexpr int kBuf = (1 << kSweepMaxLocal) + (1 << (kSweepMaxLocal - 5));
   __shared__ float2 bp[kBuf], bl[kBuf];
   __shared__ int64_t dep_hi[1 << (kSweepMaxLocal - 5)];
@@ -2505,19 +2600,15 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a) {
   __syncthreads();
   float2* P = a.psi + (int64_t)z * a.psi_bs;
   float2* Lm = a.lam + (int64_t)z * a.lam_bs;
-  const float2* Uz = a.U + (int64_t)z * a.u_bs;
+  const float2* Uz = Uall + (int64_t)z * a.u_bs;
   for (int64_t c = blockIdx.x; c < a.n_chunks; c += gridDim.x) {
     int64_t base = 0;
     for (int j = 0; j < a.n_rest; ++j)
       if ((c >> j) & 1) base |= (int64_t)1 << a.rest[j];
-    for (int i = tid; i < L; i += nt) {
-      const int64_t x = base | (i & 31) | dep_hi[i >> 5];
-      bp[lds_phys(i)] = P[x];
-      bl[lds_phys(i)] = Lm[x];
-    }
+    chunk2_to_lds(bp, bl, P, Lm, base, dep_hi, tid, nt);
     __syncthreads();
     for (int sg = 0; sg < a.n_segs; ++sg) {
-      const SweepSegment& seg = a.segs[sg];
+      const SweepSegment& seg = segs[sg];
       int ob = 0;
 #pragma unroll
       for (int t = 0; t < 8; ++t) ob |= ((tid >> t) & 1) << seg.tpos[t];
@@ -2534,7 +2625,7 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a) {
       // gradient term Im<lambda|G|psi> unchanged (|factor|^2 = 1)
       float2 ph = f2(1.f, 0.f);
       for (int gi = seg.first_gate; gi < seg.first_gate + seg.n_gates; ++gi) {
-        const AdjGateDesc& gd = a.gates[gi];
+        const AdjGateDesc& gd = gates[gi];
         const float2* U = Uz + (int64_t)gd.gate * 16;
         const float2* G = reinterpret_cast<const float2*>(gd.gen);
         if (gd.diag) {
@@ -2647,16 +2738,13 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a) {
       }
       __syncthreads();
     }
-    for (int i = tid; i < L; i += nt) {
-      const int64_t x = base | (i & 31) | dep_hi[i >> 5];
-      P[x] = bp[lds_phys(i)];
-      Lm[x] = bl[lds_phys(i)];
-    }
+    chunk_from_lds(P, bp, base, dep_hi, tid, nt);
+    chunk_from_lds(Lm, bl, base, dep_hi, tid, nt);
     __syncthreads();
   }
   // every (slot, block) entry of the pass's gates is written, zero for blocks without a chunk
   for (int gi = a.first_gate + tid; gi < a.first_gate + a.n_gates; gi += nt) {
-    const AdjGateDesc& gd = a.gates[gi];
+    const AdjGateDesc& gd = gates[gi];
     if (gd.red < 0 || gd.slot < 0) continue;
     double v = 0;
     for (int w = 0; w < nw; ++w) v += red[gd.red][w];
@@ -2695,9 +2783,11 @@ hipError_t launch_adjoint_pass(hipStream_t s, const SweepPass& ps, int bits, con
   a.n_chunks = (int64_t)1 << nr;
   const int threads = 1 << (ps.l - 4);
   if (precision == TN_PREC_BF16X3)
-    hipLaunchKernelGGL(k_adjoint_pass<TN_PREC_BF16X3>, dim3(kReduceBlocks, batch), dim3(threads), 0, s, a);
+    hipLaunchKernelGGL(k_adjoint_pass<TN_PREC_BF16X3>, dim3(kReduceBlocks, batch), dim3(threads), 0, s, a, a.gates,
+                       a.segs, a.U);
   else
-    hipLaunchKernelGGL(k_adjoint_pass<TN_PREC_C64>, dim3(kReduceBlocks, batch), dim3(threads), 0, s, a);
+    hipLaunchKernelGGL(k_adjoint_pass<TN_PREC_C64>, dim3(kReduceBlocks, batch), dim3(threads), 0, s, a, a.gates, a.segs,
+                       a.U);
   return hipGetLastError();
 }
 

@@ -334,7 +334,6 @@ void build_chains(tn_path* path, int T) {
         gd.voff = (int32_t)path->sweep_val_src.size() - ch.first_val;
         for (int j = 0; j < ne; ++j)
           path->sweep_val_src.push_back((d.g.off + d.gidx[j]) | ((int64_t)d.g.buf << 56));
-        gd.pad = 0;
         // resolve the diagonal's bits for its segment
         const PlannedSeg* segp = nullptr;
         for (const PlannedSeg& sg : pp.segs)
