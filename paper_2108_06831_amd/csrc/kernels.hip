@@ -599,6 +599,25 @@ hipError_t launch_small_steps(hipStream_t s, const SmallStep* steps, const int32
   return hipGetLastError();
 }
 
+// deposit(x, pos, nbits): bit j of x (j < nbits) placed at address position
+// pos[j]; the address maps of the permute and matrix-product kernels.
+// The positions are read four at a time as 32-bit words (each map starts at
+// a multiple of 4 bytes of the argument block): word loads of the argument
+// block are scalar loads, while a byte-wise read becomes one vector memory
+// load per bit that the loop waits for.
+static_assert(kGemmMaxBits % 4 == 0, "position maps of whole 32-bit words");
+__device__ inline int64_t deposit(int64_t x, const int8_t* pos, int nbits) {
+  const int32_t* w = reinterpret_cast<const int32_t*>(pos);
+  int64_t r = 0;
+  for (int j = 0; j < nbits; j += 4) {
+    const int32_t p4 = w[j >> 2];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (j + q < nbits) r |= ((x >> (j + q)) & 1) << ((p4 >> (8 * q)) & 63);
+  }
+  return r;
+}
+
 // ---------------------------------------------------------------------------
 // Fused streaming pass: a chunk of 2^l elements (address bits lpos, the five
 // lowest always among them so that loads and stores move 256-byte runs) is
@@ -608,6 +627,7 @@ hipError_t launch_small_steps(hipStream_t s, const SmallStep* steps, const int32
 // four register bits, applies the segment's gates in registers, and the chunk
 // goes through LDS only between segments.
 // ---------------------------------------------------------------------------
+// (lpos and rest start at multiples of 4 bytes: deposit() reads them as 32-bit words)
 struct SweepPassArgs {
   const float2* in;
   float2* out;
@@ -620,6 +640,8 @@ struct SweepPassArgs {
   int8_t lpos[kSweepMaxLocal];
   int8_t rest[64];
 };
+static_assert(offsetof(SweepPassArgs, lpos) % 4 == 0 && offsetof(SweepPassArgs, rest) % 4 == 0 &&
+                  kSweepMaxLocal % 4 == 0, "position maps aligned to 32-bit words");
 
 __device__ inline int64_t ins0(int64_t x, int p) { return ((x >> p) << (p + 1)) | (x & (((int64_t)1 << p) - 1)); }
 __device__ inline int lds_phys(int i) { return i + (i >> 5); }
@@ -962,15 +984,9 @@ __global__ __launch_bounds__(kThreads) void k_sweep_pass(SweepPassArgs a, const 
   const int64_t c = blockIdx.x;
   const int L = 1 << a.l;
   const int nt = blockDim.x, tid = threadIdx.x;
-  int64_t base = 0;
-  for (int j = 0; j < a.n_rest; ++j)
-    if ((c >> j) & 1) base |= (int64_t)1 << a.rest[j];
-  for (int h = tid; h < (L >> 5); h += nt) {
-    int64_t d = 0;
-    for (int j = 5; j < a.l; ++j)
-      if ((h >> (j - 5)) & 1) d |= (int64_t)1 << a.lpos[j];
-    dep_hi[h] = d;
-  }
+  const int64_t base = deposit(c, a.rest, a.n_rest);
+  // address bits of local index bits 5.. (the five lowest local bits are address bits 0..4)
+  for (int h = tid; h < (L >> 5); h += nt) dep_hi[h] = deposit((int64_t)h << 5, a.lpos, a.l);
   __syncthreads();
   const float2* in = a.in + (int64_t)z * a.in_bs;
   float2* out = a.out + (int64_t)z * a.out_bs;
@@ -1157,18 +1173,22 @@ hipError_t launch_accumulate(hipStream_t s, const float2* src, int64_t src_bs, f
 // ---------------------------------------------------------------------------
 constexpr int kMaxTileBits = 10;
 
+// (every map starts at a multiple of 4 bytes: deposit() reads them as 32-bit words)
 struct PermArgs {
   const float2* in;
   float2* out;
   int64_t in_bs, out_bs;
   int64_t n_blocks;
   int32_t tile_bits, rest_bits;
-  int8_t tin[kMaxTileBits];    // input position of tile-index bit j (load order)
-  int8_t tsrc[kMaxTileBits];   // store order: bit j of the store index = load-index bit tsrc[j]
-  int8_t tout[kMaxTileBits];   // output position of store-index bit j
   int8_t rest_in[64];
   int8_t rest_out[64];
+  int8_t tin[kMaxTileBits + 2];   // input position of tile-index bit j (load order)
+  int8_t tsrc[kMaxTileBits + 2];  // store order: bit j of the store index = load-index bit tsrc[j]
+  int8_t tout[kMaxTileBits + 2];  // output position of store-index bit j
 };
+static_assert(offsetof(PermArgs, rest_in) % 4 == 0 && offsetof(PermArgs, tin) % 4 == 0 &&
+                  offsetof(PermArgs, tsrc) % 4 == 0 && offsetof(PermArgs, tout) % 4 == 0,
+              "position maps aligned to 32-bit words");
 
 __global__ __launch_bounds__(kThreads) void k_permute(PermArgs a) {
   __shared__ float2 buf[(1 << kMaxTileBits) + (1 << (kMaxTileBits - 5))];
@@ -1179,28 +1199,16 @@ __global__ __launch_bounds__(kThreads) void k_permute(PermArgs a) {
   constexpr int kPer = (1 << kMaxTileBits) / kThreads;
   int64_t in_off[kPer], out_off[kPer];
   int lds_src[kPer];
+#pragma unroll
   for (int e = 0; e < kPer; ++e) {
     const int l = threadIdx.x + e * kThreads;
-    int64_t io = 0, oo = 0;
-    int src = 0;
-    for (int j = 0; j < a.tile_bits; ++j) {
-      if ((l >> j) & 1) {
-        io |= (int64_t)1 << a.tin[j];
-        oo |= (int64_t)1 << a.tout[j];
-        src |= 1 << a.tsrc[j];
-      }
-    }
-    in_off[e] = io;
-    out_off[e] = oo;
+    in_off[e] = deposit(l, a.tin, a.tile_bits);
+    out_off[e] = deposit(l, a.tout, a.tile_bits);
+    const int src = (int)deposit(l, a.tsrc, a.tile_bits);
     lds_src[e] = src + (src >> 5);
   }
   for (int64_t blk = blockIdx.x; blk < a.n_blocks; blk += gridDim.x) {
-    int64_t ib = 0, ob = 0;
-    for (int j = 0; j < a.rest_bits; ++j)
-      if ((blk >> j) & 1) {
-        ib |= (int64_t)1 << a.rest_in[j];
-        ob |= (int64_t)1 << a.rest_out[j];
-      }
+    const int64_t ib = deposit(blk, a.rest_in, a.rest_bits), ob = deposit(blk, a.rest_out, a.rest_bits);
     for (int e = 0; e < kPer; ++e) {
       const int l = threadIdx.x + e * kThreads;
       if (l < tile) buf[l + (l >> 5)] = in[ib | in_off[e]];
@@ -1319,19 +1327,6 @@ __device__ inline TileCoord tile_coord(const GemmArgs& g) {
   const int64_t r = bid % tmn, band_tiles = g.tiles_m * g.band_n;
   const int64_t band = r / band_tiles, q = r - band * band_tiles;
   return {q / g.band_n, band * g.band_n + q % g.band_n, bid / tmn};
-}
-
-// Unrolled to the maximum map length: the positions sit in the kernel's
-// argument block at constant offsets, so they are read with scalar loads
-// issued together, not one dependent vector load per bit.
-__device__ inline int64_t deposit(int64_t x, const int8_t* pos, int nbits) {
-  int64_t r = 0;
-#pragma unroll
-  for (int j = 0; j < kGemmMaxBits; ++j) {
-    if (j >= nbits) break;
-    r |= ((x >> j) & 1) << pos[j];
-  }
-  return r;
 }
 
 // BF16x3 split precision: x_hi = bf16(x), x_lo = bf16(x - x_hi), both round
@@ -1935,6 +1930,12 @@ __device__ void elem_sum_lanes(const ElemMember& e, const int64_t* TO, const int
 // turned into LDS tables (four 6-bit chunks of the result index, one table of
 // summed offsets per operand), so an output costs twelve table reads before
 // its sum.
+static_assert(offsetof(ElemMember, bo) == offsetof(ElemMember, ao) + kElemGroupOutBits &&
+                  offsetof(ElemMember, co) == offsetof(ElemMember, bo) + kElemGroupOutBits &&
+                  offsetof(ElemMember, ak) == offsetof(ElemMember, co) + kElemGroupOutBits &&
+                  offsetof(ElemMember, bk) == offsetof(ElemMember, ak) + kElemKBits,
+              "the position maps of a member are consecutive bytes");
+
 template <int PREC>
 __global__ __launch_bounds__(kThreads) void k_elem_group(ElemGroupArgs g) {
   __shared__ int64_t TO[3 * kElemChunks * 64];  // [operand A, B, C][chunk][chunk value]
@@ -1946,9 +1947,18 @@ __global__ __launch_bounds__(kThreads) void k_elem_group(ElemGroupArgs g) {
   const ElemMember& e = g.m[mi];
   const int nblk = (mi + 1 < g.n ? g.m[mi + 1].block0 : g.total_blocks) - e.block0;
   const int ob = e.out_bits, kb = e.k_bits;
+  // the member's position maps (ao, bo, co, ak, bk: consecutive bytes) staged in LDS with one
+  // load per thread: read from the argument block at a run-time member index, each byte
+  // would be a vector memory load that the table loops below wait for
+  constexpr int kPosBytes = 3 * kElemGroupOutBits + 2 * kElemKBits;
+  __shared__ int8_t PM[kPosBytes];
+  for (int t = threadIdx.x; t < kPosBytes; t += kThreads) PM[t] = e.ao[t];
+  __syncthreads();
+  const int8_t* pak = PM + 3 * kElemGroupOutBits;
+  const int8_t* pbk = pak + kElemKBits;
   for (int t = threadIdx.x; t < 3 * kElemChunks * 64; t += kThreads) {
     const int map = t / (kElemChunks * 64), ch = (t >> 6) % kElemChunks, x = t & 63;
-    const int8_t* pos = map == 0 ? e.ao : map == 1 ? e.bo : e.co;
+    const int8_t* pos = PM + map * kElemGroupOutBits;
     int64_t r = 0;
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
@@ -1966,8 +1976,8 @@ __global__ __launch_bounds__(kThreads) void k_elem_group(ElemGroupArgs g) {
 #pragma unroll
     for (int j = 0; j < kElemKBits; ++j)
       if (j < kb && ((k >> j) & 1)) {
-        ra |= (int64_t)1 << e.ak[j];
-        rb |= (int64_t)1 << e.bk[j];
+        ra |= (int64_t)1 << pak[j];
+        rb |= (int64_t)1 << pbk[j];
       }
     TKa[k] = ra;
     TKb[k] = rb;
@@ -2465,6 +2475,8 @@ struct AdjPassArgs {
   int8_t lpos[kSweepMaxLocal];
   int8_t rest[64];
 };
+static_assert(offsetof(AdjPassArgs, lpos) % 4 == 0 && offsetof(AdjPassArgs, rest) % 4 == 0,
+              "position maps aligned to 32-bit words");
 
 __device__ inline float im_conj_mul(float2 l, float2 q) { return l.x * q.y - l.y * q.x; }
 __device__ inline float2 cmulf(float2 a, float2 b) { return f2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
@@ -2591,20 +2603,13 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a, const 
   const int L = 1 << a.l;
   const int nt = blockDim.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
   for (int i = tid; i < a.n_red * nw; i += nt) red[i / nw][i % nw] = 0.0;
-  for (int h = tid; h < (L >> 5); h += nt) {
-    int64_t d = 0;
-    for (int j = 5; j < a.l; ++j)
-      if ((h >> (j - 5)) & 1) d |= (int64_t)1 << a.lpos[j];
-    dep_hi[h] = d;
-  }
+  for (int h = tid; h < (L >> 5); h += nt) dep_hi[h] = deposit((int64_t)h << 5, a.lpos, a.l);
   __syncthreads();
   float2* P = a.psi + (int64_t)z * a.psi_bs;
   float2* Lm = a.lam + (int64_t)z * a.lam_bs;
   const float2* Uz = Uall + (int64_t)z * a.u_bs;
   for (int64_t c = blockIdx.x; c < a.n_chunks; c += gridDim.x) {
-    int64_t base = 0;
-    for (int j = 0; j < a.n_rest; ++j)
-      if ((c >> j) & 1) base |= (int64_t)1 << a.rest[j];
+    const int64_t base = deposit(c, a.rest, a.n_rest);
     chunk2_to_lds(bp, bl, P, Lm, base, dep_hi, tid, nt);
     __syncthreads();
     for (int sg = 0; sg < a.n_segs; ++sg) {
