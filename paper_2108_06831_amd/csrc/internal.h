@@ -109,7 +109,17 @@ struct SkinnyDesc {
 // one-qubit matrix that is real (H, X, RY, ...) or has a real diagonal and an
 // imaginary off-diagonal (RX, Y, the QAOA mixer); a diagonal whose entries are
 // all +1 or -1 (Z, CZ), or all of modulus one (RZ, S, T, CPHASE, ZZPHASE).
-enum GateForm { kFormGeneric = 0, kFormReal = 1, kFormRxLike = 2, kFormUnit = 3, kFormSigns = 4 };
+enum GateForm { kFormGeneric = 0, kFormReal = 1, kFormRxLike = 2, kFormUnit = 3, kFormSigns = 4,
+                // a group of ZZ phase gates with one angle (in a pass: a header, then its members):
+                // the product of their diagonals is w^cut(x), w the phase of one differing edge and
+                // cut(x) the number of member edges whose two bits differ
+                kFormCount = 5, kFormCountMember = 6 };
+constexpr int kCountMaxEdges = 64;   // members of one group
+constexpr int kCountTabMax = 512;    // entries of a pass's power tables (w^0 .. w^E per group), staged in LDS
+// a gathered gate value (SweepChain::vals): offset | buffer << 56, or with kValPow the
+// value at offset raised to the power in bits 48..55
+constexpr int64_t kValPow = (int64_t)1 << 62;
+constexpr int kValExpShift = 48;
 
 // Fused streaming of a chain of gate-sized steps on one large tensor: the
 // chain is split into passes; a pass keeps a chunk of 2^l elements (the bits
@@ -155,6 +165,7 @@ struct SweepPass {
   int32_t first_gate, n_gates;
   int32_t first_seg, n_segs;
   int32_t n_red;  // adjoint passes: gradient accumulators of the pass
+  int32_t ctab_off = 0, ctab_n = 0;  // the pass's power tables in the chain's value table
 };
 
 // Reverse sweep of the adjoint gradient in fused passes: psi and lambda
@@ -297,6 +308,10 @@ struct StepProgram {
   // steps grp_from..this one are pairwise independent and touch disjoint
   // workspace ranges where one of them writes (they may run in one launch)
   int32_t grp_from = -1;
+  // a gate-sized step whose gate is one ZZ phase exp(-i t (1 - Z Z) / 2): the angle's
+  // parameter index (-1: fixed angle zz_angle); -2 otherwise
+  int32_t zz_param = -2;
+  double zz_angle = 0;
   double flops = 0, bytes = 0;
   int64_t gemm_bmnk[4] = {0, 0, 0, 0};
 };

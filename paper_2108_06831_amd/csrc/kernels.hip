@@ -637,6 +637,7 @@ struct SweepPassArgs {
   const SweepGateDesc* gates;
   const SweepSegment* segs;
   int32_t n_segs, l, n_rest, pad;
+  int32_t ctab_off, ctab_n;  // the pass's power tables in vals
   int8_t lpos[kSweepMaxLocal];
   int8_t rest[64];
 };
@@ -971,15 +972,68 @@ __device__ __forceinline__ void apply_signs(float2 (&x)[16], int n, int k0, int 
 }
 
 
+// A count group: x[r] *= w^cut(r), cut(r) the number of the group's E member
+// edges whose two bits differ at the thread's element r.  An edge between
+// two bits outside the registers adds a per-thread constant; an edge from
+// register bit j to a constant bit b adds 1 where bit j of r differs from b;
+// an edge between register bits j and k (the same for every thread) adds 1
+// where they differ.  The powers come from the pass's LDS table tab.
+__device__ __forceinline__ int count_pair(int j, int k) {  // 0..5 for the unordered pairs of 0..3
+  const int lo = j < k ? j : k, hi = j < k ? k : j;
+  return lo == 0 ? hi - 1 : lo == 1 ? hi + 1 : 5;
+}
 template <int PREC>
+__device__ __forceinline__ void apply_count_group(float2 (&x)[16], const SweepGateDesc* __restrict__ m, int E, int ob,
+                                                  int64_t base, const float2* tab) {
+  int K = 0;                  // constant edges that differ
+  uint32_t to0 = 0, to1 = 0;  // per register bit j (8-bit fields): edges to a constant 0 / 1
+  uint64_t pr = 0;            // per register-bit pair (8-bit fields): edges between two register bits
+  for (int e = 0; e < E; ++e) {
+    const int k0 = m[e].kreg[0], k1 = m[e].kreg[1];
+    auto cbit = [&](int j) {
+      const int cs = m[e].csrc[j];
+      return cs >= 64 ? (int)((base >> (cs - 64)) & 1) : ((ob >> cs) & 1);
+    };
+    if (k0 < 0 && k1 < 0) {
+      K += cbit(0) ^ cbit(1);
+    } else if (k0 >= 0 && k1 >= 0) {
+      pr += (uint64_t)1 << (8 * count_pair(k0, k1));
+    } else {
+      const int j = k0 >= 0 ? k0 : k1;
+      if (cbit(k0 >= 0 ? 1 : 0)) to1 += 1u << (8 * j);
+      else to0 += 1u << (8 * j);
+    }
+  }
+  // partial sums over register bits {0, 1} and {2, 3}: where bit j is set the edges to a
+  // constant 0 differ, where it is clear those to a constant 1
+  int s01[4], s23[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    s01[b] = K + (int)(((b & 1 ? to0 : to1) >> 0) & 255) + (int)(((b & 2 ? to0 : to1) >> 8) & 255);
+    s23[b] = (int)(((b & 1 ? to0 : to1) >> 16) & 255) + (int)(((b & 2 ? to0 : to1) >> 24) & 255);
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    int pc = 0;  // register-register edges that differ at r (the same for every thread)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int k = j + 1; k < 4; ++k)
+        if (((r >> j) ^ (r >> k)) & 1) pc += (int)((pr >> (8 * count_pair(j, k))) & 255);
+    x[r] = cmul<PREC>(tab[s01[r & 3] + s23[r >> 2] + pc], x[r]);
+  }
+}
+
 // The descriptor and value tables come as separate __restrict__ arguments: the
 // compiler may then read them with scalar loads (nothing the kernel writes can
 // alias them) instead of vector memory loads on every gate.
+template <int PREC>
 __global__ __launch_bounds__(kThreads) void k_sweep_pass(SweepPassArgs a, const SweepGateDesc* __restrict__ gates,
                                                           const SweepSegment* __restrict__ segs,
                                                           const float2* __restrict__ vals) {
   __shared__ float2 buf[(1 << kSweepMaxLocal) + (1 << (kSweepMaxLocal - 5))];
   __shared__ int64_t dep_hi[1 << (kSweepMaxLocal - 5)];
+  __shared__ float2 ctab[kCountTabMax];  // powers w^c of the pass's count groups
   const int z = blockIdx.y;
   const int64_t c = blockIdx.x;
   const int L = 1 << a.l;
@@ -991,6 +1045,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep_pass(SweepPassArgs a, const 
   const float2* in = a.in + (int64_t)z * a.in_bs;
   float2* out = a.out + (int64_t)z * a.out_bs;
   const float2* V0 = vals + (int64_t)z * a.vals_bs;
+  for (int t = tid; t < a.ctab_n; t += nt) ctab[t] = V0[a.ctab_off + t];
   chunk_to_lds(buf, in, base, dep_hi, tid, nt);
   __syncthreads();
   for (int sg = 0; sg < a.n_segs; ++sg) {
@@ -1010,6 +1065,11 @@ __global__ __launch_bounds__(kThreads) void k_sweep_pass(SweepPassArgs a, const 
     for (int gi = seg.first_gate; gi < seg.first_gate + seg.n_gates; ++gi) {
       const SweepGateDesc& gd = gates[gi];
       const float2* V = V0 + gd.voff;
+      if (gd.form == kFormCount) {
+        apply_count_group<PREC>(x, gates + gi + 1, gd.n, ob, base, ctab + gd.voff);
+        gi += gd.n;
+        continue;
+      }
       if (gd.diag) {
         const bool two = gd.n == 2;
         const float2 d0 = V[0], d1 = V[1];
@@ -1074,9 +1134,20 @@ __global__ void k_gather_vals(const int64_t* src, int n, const float2* IN, int64
   const int z = blockIdx.y;
   if (i >= n) return;
   const int64_t v = src[i];
-  const int64_t off = v & (((int64_t)1 << 56) - 1);
-  const float2* b = (v >> 56) == BUF_IN ? IN + (int64_t)z * in_bs : WS + (int64_t)z * ws_bs;
-  out[(int64_t)z * out_bs + i] = b[off];
+  const int64_t off = v & (((int64_t)1 << kValExpShift) - 1);
+  const float2* b = ((v >> 56) & 0x3f) == BUF_IN ? IN + (int64_t)z * in_bs : WS + (int64_t)z * ws_bs;
+  float2 r = b[off];
+  if (v & kValPow) {  // w^e by repeated multiplication in FP64, rounded once
+    const int e = (int)((v >> kValExpShift) & 0xff);
+    double pr = 1.0, pi = 0.0;
+    for (int k = 0; k < e; ++k) {
+      const double t = pr * r.x - pi * r.y;
+      pi = pr * r.y + pi * r.x;
+      pr = t;
+    }
+    r = f2((float)pr, (float)pi);
+  }
+  out[(int64_t)z * out_bs + i] = r;
 }
 
 hipError_t launch_gather_vals(hipStream_t s, const int64_t* src, int n, const float2* IN, int64_t in_bs,
@@ -1098,7 +1169,10 @@ hipError_t launch_sweep_pass(hipStream_t s, const SweepPass& ps, int bits, const
   a.n_segs = ps.n_segs;
   a.l = ps.l;
   a.pad = 0;
+  a.ctab_off = ps.ctab_off;
+  a.ctab_n = ps.ctab_n;
   if (ps.l < kSweepMinLocal || ps.l > kSweepMaxLocal) return hipErrorInvalidValue;
+  if (ps.ctab_n < 0 || ps.ctab_n > kCountTabMax || (ps.ctab_n > 0 && !vals)) return hipErrorInvalidValue;
   std::vector<char> local(bits, 0);
   for (int j = 0; j < ps.l; ++j) {
     a.lpos[j] = ps.lpos[j];

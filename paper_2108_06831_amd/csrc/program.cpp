@@ -311,9 +311,11 @@ void build_chains(tn_path* path, int T) {
       ps.l = pp.l;
       for (int j = 0; j < kSweepMaxLocal; ++j) ps.lpos[j] = j < ps.l ? (int8_t)pp.lpos[j] : 0;
       ps.first_gate = (int32_t)path->sweep_gates.size();
-      ps.n_gates = (int32_t)pp.gates.size();
       ps.n_red = 0;
-      for (size_t gi = 0; gi < pp.gates.size(); ++gi) {
+      std::vector<int64_t> ctab;  // the pass's power tables
+      // the descriptor of planned gate gi, its diagonal bits resolved for segment sg
+      // (values: appended to the chain's value table unless `with_vals` is false)
+      auto make_gd = [&](int gi, const PlannedSeg& sg, bool with_vals) {
         const PlannedGate& pg = pp.gates[gi];
         const SkinnyDesc& d = path->steps[s + pg.item].sk;
         SweepGateDesc gd;
@@ -332,38 +334,91 @@ void build_chains(tn_path* path, int T) {
         for (int j = 0; j < ne; ++j) gd.gidx[j] = d.gidx[j];
         // the gate's values, in the order the kernel reads them
         gd.voff = (int32_t)path->sweep_val_src.size() - ch.first_val;
-        for (int j = 0; j < ne; ++j)
-          path->sweep_val_src.push_back((d.g.off + d.gidx[j]) | ((int64_t)d.g.buf << 56));
-        // resolve the diagonal's bits for its segment
-        const PlannedSeg* segp = nullptr;
-        for (const PlannedSeg& sg : pp.segs)
-          if ((int)gi >= sg.first && (int)gi < sg.first + sg.count) segp = &sg;
+        if (with_vals)
+          for (int j = 0; j < ne; ++j)
+            path->sweep_val_src.push_back((d.g.off + d.gidx[j]) | ((int64_t)d.g.buf << 56));
         gd.kreg[0] = gd.kreg[1] = -1;
         gd.csrc[0] = gd.csrc[1] = 0;
-        if (gd.diag && segp) {
+        if (gd.diag) {
           for (int j = 0; j < gd.n; ++j) {
             const int lj = gd.lidx[j];
             if (lj < 0) {
-              gd.csrc[j] = (int8_t)(64 + (-lj - 1));
+              gd.csrc[j] = 64 + (-lj - 1);
               continue;
             }
             for (int r = 0; r < 4; ++r)
-              if (segp->rbits[r] == lj) gd.kreg[j] = (int8_t)r;
-            if (gd.kreg[j] < 0) gd.csrc[j] = (int8_t)lj;
+              if (sg.rbits[r] == lj) gd.kreg[j] = r;
+            if (gd.kreg[j] < 0) gd.csrc[j] = lj;
           }
         }
-        path->sweep_gates.push_back(gd);
-      }
+        return gd;
+      };
       ps.first_seg = (int32_t)path->segments.size();
       for (const PlannedSeg& sg : pp.segs) {
         SweepSegment seg;
         for (int j = 0; j < 4; ++j) seg.rbits[j] = sg.rbits[j];
-        seg.first_gate = ps.first_gate + sg.first;
-        seg.n_gates = sg.count;
+        seg.first_gate = (int32_t)path->sweep_gates.size();
+        const int g_end = sg.first + sg.count;
+        for (int g = sg.first; g < g_end;) {
+          if (!pp.gates[g].diag) {
+            path->sweep_gates.push_back(make_gd(g, sg, true));
+            ++g;
+            continue;
+          }
+          // a run of consecutive diagonal gates commutes: its ZZ phases that share one angle
+          // become count groups, the rest keep their order
+          int g2 = g;
+          while (g2 < g_end && pp.gates[g2].diag) ++g2;
+          std::vector<std::pair<std::pair<int32_t, double>, std::vector<int>>> groups;
+          std::vector<int> rest;
+          for (int q = g; q < g2; ++q) {
+            const StepProgram& P = path->steps[s + pp.gates[q].item];
+            if (P.zz_param == -2) {
+              rest.push_back(q);
+              continue;
+            }
+            const std::pair<int32_t, double> key(P.zz_param, P.zz_angle);
+            size_t k = 0;
+            while (k < groups.size() && (groups[k].first != key || groups[k].second.size() >= (size_t)kCountMaxEdges))
+              ++k;
+            if (k == groups.size()) groups.push_back({key, {}});
+            groups[k].second.push_back(q);
+          }
+          for (auto& gr : groups)
+            if (gr.second.size() < 2 || ctab.size() + gr.second.size() + 1 > (size_t)kCountTabMax) {
+              rest.insert(rest.end(), gr.second.begin(), gr.second.end());
+              gr.second.clear();
+            }
+          std::sort(rest.begin(), rest.end());
+          for (int q : rest) path->sweep_gates.push_back(make_gd(q, sg, true));
+          for (const auto& gr : groups) {
+            if (gr.second.empty()) continue;
+            const int E = (int)gr.second.size();
+            const SkinnyDesc& d0 = path->steps[s + pp.gates[gr.second[0]].item].sk;
+            SweepGateDesc h = make_gd(gr.second[0], sg, false);
+            h.form = kFormCount;
+            h.n = E;
+            h.voff = (int32_t)ctab.size();  // index in the pass's tables
+            const int64_t w_src = (d0.g.off + d0.gidx[1]) | ((int64_t)d0.g.buf << 56);  // entry of differing bits
+            for (int c = 0; c <= E; ++c) ctab.push_back(w_src | kValPow | ((int64_t)c << kValExpShift));
+            path->sweep_gates.push_back(h);
+            for (int q : gr.second) {
+              SweepGateDesc m = make_gd(q, sg, false);
+              m.form = kFormCountMember;
+              path->sweep_gates.push_back(m);
+            }
+          }
+          g = g2;
+        }
+        seg.n_gates = (int32_t)path->sweep_gates.size() - seg.first_gate;
         fill_segment_tables(seg, ps.l);
         path->segments.push_back(seg);
       }
       ps.n_segs = (int32_t)pp.segs.size();
+      ps.n_gates = (int32_t)path->sweep_gates.size() - ps.first_gate;
+      ps.ctab_off = (int32_t)path->sweep_val_src.size() - ch.first_val;
+      ps.ctab_n = (int32_t)ctab.size();
+      path->sweep_val_src.insert(path->sweep_val_src.end(), ctab.begin(), ctab.end());
       path->passes.push_back(ps);
     }
     ch.n_passes = (int32_t)path->passes.size() - ch.first_pass;
@@ -648,6 +703,10 @@ tn_status compile_program(const tn_network* net, tn_path* path, const std::vecto
           if (d.nk == 0 && d.nm == 0 && r.diag && whole) {
             d.g_unit = unit ? 1 : 0;
             d.g_form = signs ? kFormSigns : unit ? kFormUnit : kFormGeneric;
+            if (d.nb == 2 && r.nq == 2 && r.op_end - r.op_begin == 1 && net->ops[r.op_begin].kind == TN_GATE_ZZPHASE) {
+              P.zz_param = net->ops[r.op_begin].param[0];
+              P.zz_angle = P.zz_param >= 0 ? 0.0 : net->ops[r.op_begin].angle[0];
+            }
           } else if (d.nb == 0 && d.nk == 1 && d.nm == 1 && !r.diag && whole && r.nq == 1) {
             d.g_form = real ? kFormReal : rxl ? kFormRxLike : kFormGeneric;
           }

@@ -376,6 +376,7 @@ static tn_status run_steps_body(hipStream_t s, tn_path* path, const Bases& B, in
         double fl = 0;
         for (int g = 0; g < ps.n_gates; ++g) {
           const SweepGateDesc& gd = path->sweep_gates[ps.first_gate + g];
+          if (gd.form == kFormCount) continue;  // its member gates are counted
           fl += gd.diag ? 8.0 : 8.0 * (1 << gd.n);
         }
         prof_stop(s, ev, TN_KERNEL_SWEEP, 16.0 * std::ldexp(1.0, ch.bits) * batch,
