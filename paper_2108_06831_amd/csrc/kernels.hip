@@ -2665,6 +2665,30 @@ __device__ __forceinline__ float reg_grad_y(const float2 (&p)[16], const float2 
   return g;
 }
 
+// Sum over the 64 lanes of a wave, the result in lane 63: DPP moves within
+// quads, half rows and rows, then the row broadcasts of lane 15 and lane 31
+// (six dependent VALU operations; a shuffle network would wait on LDS at each
+// of its six steps).
+__device__ __forceinline__ float wave_sum_to_63(float v) {
+  auto dpp = [](float x, int ctrl, int row_mask) -> float {
+    switch (ctrl) {  // the control word must be a compile-time constant
+      case 0xb1: return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xb1, 0xf, 0xf, false));
+      case 0x4e: return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x4e, 0xf, 0xf, false));
+      case 0x141: return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x141, 0xf, 0xf, false));
+      case 0x140: return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x140, 0xf, 0xf, false));
+      case 0x142: return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x142, 0xa, 0xf, false));
+      default: return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x143, 0xc, 0xf, false));
+    }
+  };
+  v += dpp(v, 0xb1, 0xf);   // quad_perm [1, 0, 3, 2]
+  v += dpp(v, 0x4e, 0xf);   // quad_perm [2, 3, 0, 1]
+  v += dpp(v, 0x141, 0xf);  // row_half_mirror
+  v += dpp(v, 0x140, 0xf);  // row_mirror: every lane of a row holds the row's sum
+  v += dpp(v, 0x142, 0xa);  // row_bcast:15 into rows 1 and 3
+  v += dpp(v, 0x143, 0xc);  // row_bcast:31 into rows 2 and 3: lane 63 holds the total
+  return v;
+}
+
 template <int PREC>
 __global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a, const AdjGateDesc* __restrict__ gates,
                                                             const SweepSegment* __restrict__ segs,
@@ -2703,10 +2727,17 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a, const 
       // segment's end; they commute with the segment's gates and leave every
       // gradient term Im<lambda|G|psi> unchanged (|factor|^2 = 1)
       float2 ph = f2(1.f, 0.f);
+      // Im(conj(lambda) psi) at each element is unchanged by unit-modulus diagonal gates, so
+      // along a run of diagonal gates its sums are formed once: over the thread's elements
+      // (tT) and over those whose register bit j is 1 (tS[j]); a one-bit diagonal generator's
+      // term is then q0 (tT - s1) + q1 s1, s1 the sum where the gate's bit is 1
+      bool have_t = false;
+      float tT = 0.f, tS0 = 0.f, tS1 = 0.f, tS2 = 0.f, tS3 = 0.f;
       for (int gi = seg.first_gate; gi < seg.first_gate + seg.n_gates; ++gi) {
         const AdjGateDesc& gd = gates[gi];
         const float2* U = Uz + (int64_t)gd.gate * 16;
         const float2* G = reinterpret_cast<const float2*>(gd.gen);
+        if (!gd.diag) have_t = false;
         if (gd.diag) {
           const int k[2] = {gd.kreg[0], gd.n == 2 ? gd.kreg[1] : -1};
           int c = 0;  // the index bits that are constant over the thread's elements
@@ -2731,10 +2762,28 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a, const 
           const float2 u0 = U[0], u1 = two ? U[5] : U[3], u2 = two ? U[10] : f2(1.f, 0.f),
                        u3 = two ? U[15] : f2(1.f, 0.f);
           if (gd.red >= 0) {
-            const float q2 = two ? G[2].x : 0.f, q3 = two ? G[3].x : 0.f;
-            double v = (double)diag_grad(xp, xl, gd.n, k[0], k[1], c, G[0].x, G[1].x, q2, q3);
-            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-            if (lane == 0) red[gd.red][wv] += v;
+            float v;
+            if (!two) {
+              if (!have_t) {
+                tT = tS0 = tS1 = tS2 = tS3 = 0.f;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                  const float t = im_conj_mul(xl[r], xp[r]);
+                  tT += t;
+                  if (r & 1) tS0 += t;
+                  if (r & 2) tS1 += t;
+                  if (r & 4) tS2 += t;
+                  if (r & 8) tS3 += t;
+                }
+                have_t = true;
+              }
+              const float s1 = k[0] >= 0 ? (k[0] == 0 ? tS0 : k[0] == 1 ? tS1 : k[0] == 2 ? tS2 : tS3) : (c ? tT : 0.f);
+              v = G[0].x * (tT - s1) + G[1].x * s1;
+            } else {
+              v = diag_grad(xp, xl, gd.n, k[0], k[1], c, G[0].x, G[1].x, G[2].x, G[3].x);
+            }
+            v = wave_sum_to_63(v);
+            if (lane == 63) red[gd.red][wv] += (double)v;
           }
           const float2 d0 = f2(u0.x, -u0.y), d1 = f2(u1.x, -u1.y), d2 = f2(u2.x, -u2.y), d3 = f2(u3.x, -u3.y);
           if (uniform) {
@@ -2770,9 +2819,8 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a, const 
                 default: g = reg_grad1<3>(xp, xl, G); break;
               }
             }
-            double v = (double)g;
-            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-            if (lane == 0) red[gd.red][wv] += v;
+            g = wave_sum_to_63(g);
+            if (lane == 63) red[gd.red][wv] += (double)g;
           }
           // U^dagger[m][k] = conj(U[k][m])
           float2 ud[4];
