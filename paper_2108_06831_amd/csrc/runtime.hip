@@ -933,15 +933,55 @@ extern "C" tn_status tn_amplitudes(void* stream, int32_t precision, tn_network* 
   return finish_to(s, f, fbs, path, to, (float2*)out_dev, count, count, 1, (float2*)(w + L.aux_off));
 }
 
-extern "C" size_t tn_expectation_workspace_bytes(tn_network* const* nets, tn_path* const* paths, int32_t n_circuits,
-                                                 int32_t batch) {
+// Circuits of one tn_expectation call are independent: they run on kExpLanes
+// streams at once (the caller's and kExpLanes - 1 of the library's, forked
+// from and joined back into the caller's stream with events, so the call stays
+// ordered on it and captures into one graph), each lane with its own
+// workspace slot.  Small circuits then fill the GPU beside large ones.
+constexpr int kExpLanes = 4;
+
+static size_t expect_slot_bytes(tn_network* const* nets, tn_path* const* paths, int32_t n_circuits, int32_t batch) {
   size_t mx = 0;
   for (int i = 0; i < n_circuits; ++i) {
     if (!nets || !paths || !nets[i] || !paths[i]) return 0;
     mx = std::max(mx, paths[i]->slice_bits > 0 ? layout_sliced(nets[i], paths[i], batch, expect_aux(batch)).total
                                                : layout_ws(nets[i], paths[i], batch, expect_aux(batch)).total);
   }
-  return mx;
+  return align256(mx);
+}
+
+static int expect_lanes(int32_t n_circuits) { return std::max(1, std::min((int)n_circuits, kExpLanes)); }
+
+extern "C" size_t tn_expectation_workspace_bytes(tn_network* const* nets, tn_path* const* paths, int32_t n_circuits,
+                                                 int32_t batch) {
+  if (n_circuits < 1) return 0;
+  return expect_slot_bytes(nets, paths, n_circuits, batch) * (size_t)expect_lanes(n_circuits);
+}
+
+// the library's side streams and fork/join events, per device (created on first use; default priority)
+struct SideLanes {
+  hipStream_t stream[kExpLanes - 1] = {};
+  hipEvent_t fork = nullptr, join[kExpLanes - 1] = {};
+};
+static std::mutex g_lanes_mu;
+static SideLanes* g_lanes[64];
+
+static tn_status side_lanes(SideLanes** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return set_error(TN_EDEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_lanes_mu);
+  if (!g_lanes[dev]) {
+    SideLanes* L = new SideLanes();
+    for (int k = 0; k < kExpLanes - 1; ++k) {
+      HIP_TRY(hipStreamCreateWithFlags(&L->stream[k], hipStreamNonBlocking));
+      HIP_TRY(hipEventCreateWithFlags(&L->join[k], hipEventDisableTiming));
+    }
+    HIP_TRY(hipEventCreateWithFlags(&L->fork, hipEventDisableTiming));
+    g_lanes[dev] = L;
+  }
+  *out = g_lanes[dev];
+  return TN_OK;
 }
 
 extern "C" tn_status tn_expectation(void* stream, int32_t precision, tn_network* const* nets, tn_path* const* paths,
@@ -954,25 +994,56 @@ extern "C" tn_status tn_expectation(void* stream, int32_t precision, tn_network*
   const size_t need = tn_expectation_workspace_bytes(nets, paths, n_circuits, batch);
   if (need == 0) return set_error(TN_EINVAL, "NULL network or path");
   if (workspace_bytes < need) return set_error(TN_ENOMEM, "workspace too small: need " + std::to_string(need));
-  hipStream_t s = (hipStream_t)stream;
+  const size_t slot = expect_slot_bytes(nets, paths, n_circuits, batch);
+  // every check and host-side table before the first launch, so that an error leaves no lane forked
+  std::vector<ZTerms> all_terms(n_circuits);
+  std::vector<DevNet*> devs(n_circuits);
   for (int c = 0; c < n_circuits; ++c) {
+    const double* prm = params_dev ? params_dev[c] : nullptr;
+    tn_status st = check_common(nets[c], paths[c], prm, batch, precision);
+    if (st != TN_OK) return set_error(st, "circuit " + std::to_string(c) + ": " + g_err);
+    if (nets[c]->output_kind != TN_OUT_STATEVECTOR)
+      return set_error(TN_EINVAL, "expectation needs a statevector network");
+    if ((st = make_terms(nets[c], paths[c], &obs[c], &all_terms[c])) != TN_OK) return st;
+    if ((st = ensure_device(nets[c], &devs[c])) != TN_OK) return st;
+    DevPath* dp;
+    if ((st = ensure_path_device(paths[c], &dp)) != TN_OK) return st;
+  }
+  hipStream_t s0 = (hipStream_t)stream;
+  // kernel timing measures per stream: with it on, every circuit runs on the caller's stream
+  const int lanes = g_prof ? 1 : expect_lanes(n_circuits);
+  SideLanes* SL_ = nullptr;
+  if (lanes > 1) {
+    tn_status st = side_lanes(&SL_);
+    if (st != TN_OK) return st;
+    HIP_TRY(hipEventRecord(SL_->fork, s0));
+    for (int k = 0; k < lanes - 1; ++k) HIP_TRY(hipStreamWaitEvent(SL_->stream[k], SL_->fork, 0));
+  }
+  tn_status result = TN_OK;
+  for (int c = 0; c < n_circuits && result == TN_OK; ++c) {
     tn_network* net = nets[c];
     tn_path* path = paths[c];
     const double* prm = params_dev ? params_dev[c] : nullptr;
-    tn_status st = check_common(net, path, prm, batch, precision);
-    if (st != TN_OK) return set_error(st, "circuit " + std::to_string(c) + ": " + g_err);
-    if (net->output_kind != TN_OUT_STATEVECTOR) return set_error(TN_EINVAL, "expectation needs a statevector network");
-    ZTerms terms;
-    if ((st = make_terms(net, path, &obs[c], &terms)) != TN_OK) return st;
-    DevNet* d;
-    if ((st = ensure_device(net, &d)) != TN_OK) return st;
-    char* w = (char*)workspace_dev;
+    const int lane = c % lanes;
+    hipStream_t s = lane == 0 ? s0 : SL_->stream[lane - 1];
+    const ZTerms& terms = all_terms[c];
+    DevNet* d = devs[c];
+    char* w = (char*)workspace_dev + (size_t)lane * slot;
+    tn_status st;
     if (path->slice_bits > 0) {  // the state is the sum of the slices
       const SliceLayout SL = layout_sliced(net, path, batch, expect_aux(batch));
-      if ((st = run_slices(s, net, path, d, prm, batch, nullptr, 0, w, SL, precision)) != TN_OK) return st;
+      if ((st = run_slices(s, net, path, d, prm, batch, nullptr, 0, w, SL, precision)) != TN_OK) {
+        result = st;
+        break;
+      }
       hipEvent_t ev = prof_start(s, TN_KERNEL_REDUCE);
-      HIP_TRY(launch_expectation(s, (float2*)(w + SL.acc_off), path->final_elems, path->final_elems, terms, batch,
-                                 (double*)(w + SL.prog_off + SL.prog.aux_off), out_dev + (int64_t)c * batch, 1));
+      const hipError_t e = launch_expectation(s, (float2*)(w + SL.acc_off), path->final_elems, path->final_elems,
+                                              terms, batch, (double*)(w + SL.prog_off + SL.prog.aux_off),
+                                              out_dev + (int64_t)c * batch, 1);
+      if (e != hipSuccess) {
+        result = set_error(TN_EDEVICE, std::string("expectation: ") + hipGetErrorString(e));
+        break;
+      }
       prof_stop(s, ev, TN_KERNEL_REDUCE, 8.0 * (double)path->final_elems * batch, 0.0);
       continue;
     }
@@ -982,16 +1053,31 @@ extern "C" tn_status tn_expectation(void* stream, int32_t precision, tn_network*
     B.in_bs = net->input_elems;
     B.ws = (float2*)(w + L.arena_off);
     B.ws_bs = path->ws_elems;
-    if ((st = materialize(s, net, d, prm, batch, nullptr, 0, B.in)) != TN_OK) return st;
-    if ((st = run_steps(s, path, B, batch, precision)) != TN_OK) return st;
+    if ((st = materialize(s, net, d, prm, batch, nullptr, 0, B.in)) != TN_OK ||
+        (st = run_steps(s, path, B, batch, precision)) != TN_OK) {
+      result = st;
+      break;
+    }
     int64_t fbs;
     float2* f = resolve(B, path->final_ref, &fbs);
     hipEvent_t ev = prof_start(s, TN_KERNEL_REDUCE);
-    HIP_TRY(launch_expectation(s, f, fbs, path->final_elems, terms, batch, (double*)(w + L.aux_off),
-                               out_dev + (int64_t)c * batch, 1));
+    const hipError_t e = launch_expectation(s, f, fbs, path->final_elems, terms, batch, (double*)(w + L.aux_off),
+                                            out_dev + (int64_t)c * batch, 1);
+    if (e != hipSuccess) {
+      result = set_error(TN_EDEVICE, std::string("expectation: ") + hipGetErrorString(e));
+      break;
+    }
     prof_stop(s, ev, TN_KERNEL_REDUCE, 8.0 * (double)path->final_elems * batch, 0.0);
   }
-  return TN_OK;
+  // join the lanes back into the caller's stream (also after an error, so no lane stays forked)
+  for (int k = 0; k < lanes - 1; ++k) {
+    const hipError_t e1 = hipEventRecord(SL_->join[k], SL_->stream[k]);
+    const hipError_t e2 = hipStreamWaitEvent(s0, SL_->join[k], 0);
+    if (result == TN_OK && (e1 != hipSuccess || e2 != hipSuccess))
+      result = set_error(TN_EDEVICE, std::string("joining the expectation lanes: ") +
+                                         hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+  }
+  return result;
 }
 
 // ---------------------------------------------------------------------------
