@@ -172,7 +172,8 @@ struct SweepPass {
 // chunks of 2^l elements stay in LDS while every gate of the pass is undone
 // on both, each parametric gate first adding its chunk's share of
 // Im<lambda|G|psi> to an accumulator of its own (`red`).
-constexpr int kAdjMaxRed = 128;
+constexpr int kAdjMaxRed = 128;     // two per lane of a wave (the kernel's register accumulators)
+constexpr int kAdjPreGates = 128;   // gates of a pass whose U entries the kernel stages in LDS
 struct AdjGateDesc {
   int32_t diag, n;
   int32_t lidx[2];  // as in SweepGateDesc

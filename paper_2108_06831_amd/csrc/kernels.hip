@@ -2697,15 +2697,41 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a, const 
   __shared__ float2 bp[kBuf], bl[kBuf];
   __shared__ int64_t dep_hi[1 << (kSweepMaxLocal - 5)];
   __shared__ double red[kAdjMaxRed][kThreads / 64];
+  __shared__ float2 upre[kAdjPreGates][4];  // the entries of U the pass's first gates use (see below)
   const int z = blockIdx.y;
   const int L = 1 << a.l;
   const int nt = blockDim.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
-  for (int i = tid; i < a.n_red * nw; i += nt) red[i / nw][i % nw] = 0.0;
+  if (blockIdx.x >= a.n_chunks) {  // no chunk for this block: its partial of every gradient term is zero
+    for (int gi = a.first_gate + tid; gi < a.first_gate + a.n_gates; gi += nt) {
+      const AdjGateDesc& gd = gates[gi];
+      if (gd.red >= 0 && gd.slot >= 0)
+        a.partials[(int64_t)z * a.pstride + (int64_t)gd.slot * kReduceBlocks + blockIdx.x] = 0.0;
+    }
+    return;
+  }
+  const float2* Uz = Uall + (int64_t)z * a.u_bs;
+  // U of the first kAdjPreGates gates staged in LDS (one load per thread, all in flight together,
+  // instead of a scalar load on every gate): diagonal U[0], U[3] (one bit) or U[0], U[5], U[10],
+  // U[15] (two bits); one-qubit dense U[0..3]; two-qubit dense gates read U from memory
+  for (int i = tid; i < min(a.n_gates, kAdjPreGates) * 4; i += nt) {
+    const int g = i >> 2, e = i & 3;
+    const AdjGateDesc& gd = gates[a.first_gate + g];
+    const int idx = gd.diag ? (gd.n == 2 ? 5 * e : (e == 1 ? 3 : 0)) : e;
+    upre[g][e] = Uz[(int64_t)gd.gate * 16 + idx];
+  }
   for (int h = tid; h < (L >> 5); h += nt) dep_hi[h] = deposit((int64_t)h << 5, a.lpos, a.l);
   __syncthreads();
   float2* P = a.psi + (int64_t)z * a.psi_bs;
   float2* Lm = a.lam + (int64_t)z * a.lam_bs;
-  const float2* Uz = Uall + (int64_t)z * a.u_bs;
+  // gradient sums of this wave in registers: lane j holds slot j (accA) and slot 64 + j (accB)
+  double accA = 0.0, accB = 0.0;
+  auto add_grad = [&](int slot, float v) {
+    v = wave_sum_to_63(v);
+    const double sv = (double)__int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+    const double add = lane == (slot & 63) ? sv : 0.0;  // selects only: no run-time choice of a register
+    accA += slot < 64 ? add : 0.0;
+    accB += slot < 64 ? 0.0 : add;
+  };
   for (int64_t c = blockIdx.x; c < a.n_chunks; c += gridDim.x) {
     const int64_t base = deposit(c, a.rest, a.n_rest);
     chunk2_to_lds(bp, bl, P, Lm, base, dep_hi, tid, nt);
@@ -2737,6 +2763,8 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a, const 
         const AdjGateDesc& gd = gates[gi];
         const float2* U = Uz + (int64_t)gd.gate * 16;
         const float2* G = reinterpret_cast<const float2*>(gd.gen);
+        const int pg = gi - a.first_gate;
+        const float2* Up = pg < kAdjPreGates ? upre[pg] : nullptr;
         if (!gd.diag) have_t = false;
         if (gd.diag) {
           const int k[2] = {gd.kreg[0], gd.n == 2 ? gd.kreg[1] : -1};
@@ -2759,8 +2787,8 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a, const 
             continue;
           }
           // U^dagger diagonal: conj(U[b][b])
-          const float2 u0 = U[0], u1 = two ? U[5] : U[3], u2 = two ? U[10] : f2(1.f, 0.f),
-                       u3 = two ? U[15] : f2(1.f, 0.f);
+          const float2 u0 = Up ? Up[0] : U[0], u1 = Up ? Up[1] : two ? U[5] : U[3],
+                       u2 = two ? (Up ? Up[2] : U[10]) : f2(1.f, 0.f), u3 = two ? (Up ? Up[3] : U[15]) : f2(1.f, 0.f);
           if (gd.red >= 0) {
             float v;
             if (!two) {
@@ -2782,8 +2810,7 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a, const 
             } else {
               v = diag_grad(xp, xl, gd.n, k[0], k[1], c, G[0].x, G[1].x, G[2].x, G[3].x);
             }
-            v = wave_sum_to_63(v);
-            if (lane == 63) red[gd.red][wv] += (double)v;
+            add_grad(gd.red, v);
           }
           const float2 d0 = f2(u0.x, -u0.y), d1 = f2(u1.x, -u1.y), d2 = f2(u2.x, -u2.y), d3 = f2(u3.x, -u3.y);
           if (uniform) {
@@ -2819,15 +2846,15 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a, const 
                 default: g = reg_grad1<3>(xp, xl, G); break;
               }
             }
-            g = wave_sum_to_63(g);
-            if (lane == 63) red[gd.red][wv] += (double)g;
+            add_grad(gd.red, g);
           }
           // U^dagger[m][k] = conj(U[k][m])
+          const float2 w0 = Up ? Up[0] : U[0], w1 = Up ? Up[1] : U[1], w2 = Up ? Up[2] : U[2], w3 = Up ? Up[3] : U[3];
           float2 ud[4];
-          ud[0] = f2(U[0].x, -U[0].y);
-          ud[1] = f2(U[2].x, -U[2].y);
-          ud[2] = f2(U[1].x, -U[1].y);
-          ud[3] = f2(U[3].x, -U[3].y);
+          ud[0] = f2(w0.x, -w0.y);
+          ud[1] = f2(w2.x, -w2.y);
+          ud[2] = f2(w1.x, -w1.y);
+          ud[3] = f2(w3.x, -w3.y);
           const int form = gd.uform == kFormReal ? kDenseReal : gd.uform == kFormRxLike ? kDenseRxLike : kDenseGeneric;
           switch (gd.rb[0]) {
             case 0: reg_apply1<PREC, 0>(xp, ud, form); reg_apply1<PREC, 0>(xl, ud, form); break;
@@ -2869,7 +2896,10 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a, const 
     chunk_from_lds(Lm, bl, base, dep_hi, tid, nt);
     __syncthreads();
   }
-  // every (slot, block) entry of the pass's gates is written, zero for blocks without a chunk
+  red[lane][wv] = accA;
+  red[64 + lane][wv] = accB;
+  __syncthreads();
+  // every (slot, block) entry of the pass's gates is written
   for (int gi = a.first_gate + tid; gi < a.first_gate + a.n_gates; gi += nt) {
     const AdjGateDesc& gd = gates[gi];
     if (gd.red < 0 || gd.slot < 0) continue;
