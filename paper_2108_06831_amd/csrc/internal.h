@@ -116,6 +116,7 @@ enum GateForm { kFormGeneric = 0, kFormReal = 1, kFormRxLike = 2, kFormUnit = 3,
                 kFormCount = 5, kFormCountMember = 6 };
 constexpr int kCountMaxEdges = 64;   // members of one group
 constexpr int kCountTabMax = 512;    // entries of a pass's power tables (w^0 .. w^E per group), staged in LDS
+constexpr int kPassValMax = 640;     // a pass's gate values and power tables staged in LDS together (when they fit)
 // a gathered gate value (SweepChain::vals): offset | buffer << 56, or with kValPow the
 // value at offset raised to the power in bits 48..55
 constexpr int64_t kValPow = (int64_t)1 << 62;
@@ -166,6 +167,7 @@ struct SweepPass {
   int32_t first_seg, n_segs;
   int32_t n_red;  // adjoint passes: gradient accumulators of the pass
   int32_t ctab_off = 0, ctab_n = 0;  // the pass's power tables in the chain's value table
+  int32_t val_off = 0;               // the pass's first gate value (its values run up to ctab_off + ctab_n)
 };
 
 // Reverse sweep of the adjoint gradient in fused passes: psi and lambda

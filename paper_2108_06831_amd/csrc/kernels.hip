@@ -637,7 +637,10 @@ struct SweepPassArgs {
   const SweepGateDesc* gates;
   const SweepSegment* segs;
   int32_t n_segs, l, n_rest, pad;
-  int32_t ctab_off, ctab_n;  // the pass's power tables in vals
+  int32_t ctab_off;          // the pass's power tables in vals
+  int32_t lds_off, lds_n;    // the range of vals staged in LDS: the pass's gate values and power
+                             // tables when they fit (gates_in_lds), else the power tables only
+  int32_t gates_in_lds, pad2;
   int8_t lpos[kSweepMaxLocal];
   int8_t rest[64];
 };
@@ -1033,7 +1036,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep_pass(SweepPassArgs a, const 
                                                           const float2* __restrict__ vals) {
   __shared__ float2 buf[(1 << kSweepMaxLocal) + (1 << (kSweepMaxLocal - 5))];
   __shared__ int64_t dep_hi[1 << (kSweepMaxLocal - 5)];
-  __shared__ float2 ctab[kCountTabMax];  // powers w^c of the pass's count groups
+  __shared__ float2 vtab[kPassValMax];  // see SweepPassArgs::lds_off
   const int z = blockIdx.y;
   const int64_t c = blockIdx.x;
   const int L = 1 << a.l;
@@ -1045,7 +1048,8 @@ __global__ __launch_bounds__(kThreads) void k_sweep_pass(SweepPassArgs a, const 
   const float2* in = a.in + (int64_t)z * a.in_bs;
   float2* out = a.out + (int64_t)z * a.out_bs;
   const float2* V0 = vals + (int64_t)z * a.vals_bs;
-  for (int t = tid; t < a.ctab_n; t += nt) ctab[t] = V0[a.ctab_off + t];
+  for (int t = tid; t < a.lds_n; t += nt) vtab[t] = V0[a.lds_off + t];
+  const float2* ctab = vtab + (a.ctab_off - a.lds_off);
   chunk_to_lds(buf, in, base, dep_hi, tid, nt);
   __syncthreads();
   for (int sg = 0; sg < a.n_segs; ++sg) {
@@ -1064,7 +1068,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep_pass(SweepPassArgs a, const 
     float2 ph = f2(1.f, 0.f);
     for (int gi = seg.first_gate; gi < seg.first_gate + seg.n_gates; ++gi) {
       const SweepGateDesc& gd = gates[gi];
-      const float2* V = V0 + gd.voff;
+      const float2* V = a.gates_in_lds ? vtab + (gd.voff - a.lds_off) : V0 + gd.voff;
       if (gd.form == kFormCount) {
         apply_count_group<PREC>(x, gates + gi + 1, gd.n, ob, base, ctab + gd.voff);
         gi += gd.n;
@@ -1170,9 +1174,14 @@ hipError_t launch_sweep_pass(hipStream_t s, const SweepPass& ps, int bits, const
   a.l = ps.l;
   a.pad = 0;
   a.ctab_off = ps.ctab_off;
-  a.ctab_n = ps.ctab_n;
+  const int n_all = ps.ctab_off + ps.ctab_n - ps.val_off;  // the pass's values and tables
+  a.gates_in_lds = n_all <= kPassValMax ? 1 : 0;
+  a.lds_off = a.gates_in_lds ? ps.val_off : ps.ctab_off;
+  a.lds_n = a.gates_in_lds ? n_all : ps.ctab_n;
+  a.pad2 = 0;
   if (ps.l < kSweepMinLocal || ps.l > kSweepMaxLocal) return hipErrorInvalidValue;
-  if (ps.ctab_n < 0 || ps.ctab_n > kCountTabMax || (ps.ctab_n > 0 && !vals)) return hipErrorInvalidValue;
+  if (ps.ctab_n < 0 || ps.ctab_n > kCountTabMax || n_all < 0 || (a.lds_n > 0 && !vals)) return hipErrorInvalidValue;
+  static_assert(kCountTabMax <= kPassValMax, "the power tables alone always fit");
   std::vector<char> local(bits, 0);
   for (int j = 0; j < ps.l; ++j) {
     a.lpos[j] = ps.lpos[j];

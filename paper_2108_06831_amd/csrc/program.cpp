@@ -312,6 +312,7 @@ void build_chains(tn_path* path, int T) {
       for (int j = 0; j < kSweepMaxLocal; ++j) ps.lpos[j] = j < ps.l ? (int8_t)pp.lpos[j] : 0;
       ps.first_gate = (int32_t)path->sweep_gates.size();
       ps.n_red = 0;
+      ps.val_off = (int32_t)path->sweep_val_src.size() - ch.first_val;
       std::vector<int64_t> ctab;  // the pass's power tables
       // the descriptor of planned gate gi, its diagonal bits resolved for segment sg
       // (values: appended to the chain's value table unless `with_vals` is false)
