@@ -599,6 +599,18 @@ hipError_t launch_small_steps(hipStream_t s, const SmallStep* steps, const int32
   return hipGetLastError();
 }
 
+// Result stores of the matrix products are streaming (non-temporal) stores:
+// a large product writes far more result than it reads operands, and
+// ordinary stores would evict the operand tiles that later tiles of the same
+// XCD still read from its L2.
+typedef float float2_nt __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void store_stream(float2* p, float re, float im) {
+  float2_nt v;
+  v.x = re;
+  v.y = im;
+  __builtin_nontemporal_store(v, reinterpret_cast<float2_nt*>(p));
+}
+
 // deposit(x, pos, nbits): bit j of x (j < nbits) placed at address position
 // pos[j]; the address maps of the permute and matrix-product kernels.
 // The positions are read four at a time as 32-bit words (each map starts at
@@ -1670,7 +1682,8 @@ __global__ __launch_bounds__(kThreads) void k_gemm(GemmArgs g) {
         const int rl = wm * 32 * TM + i * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
         const int jj = lane & 31;
         const int cl = wn * 16 * TN + j * 16 + (jj >> 1);
-        if (m0 + rl < g.M && n0 + cl < g.N) Cf[(base_c | TCm[rl] | TCn[cl]) * 2 + (jj & 1)] = acc[i][j][v];
+        if (m0 + rl < g.M && n0 + cl < g.N)
+          __builtin_nontemporal_store(acc[i][j][v], &Cf[(base_c | TCm[rl] | TCn[cl]) * 2 + (jj & 1)]);
       }
 }
 
@@ -1919,7 +1932,7 @@ __global__ __launch_bounds__(kThreads, TM == 1 && !BP ? 4 : 2) void k_gemm3m(Gem
       const int cl = BP ? r32 : wn * 32 + r32;
       if (a_in(rl) && (BP == 1 ? cl < g.N : BP == 2 ? n0 + 32 * w + cl < g.N : n0 + cl < g.N)) {
         const float a = p1[i][v], b = p2[i][v];
-        C[base_c | TCm[rl] | TCn[cl]] = f2(a - b, p3[i][v] - a - b);
+        store_stream(&C[base_c | TCm[rl] | TCn[cl]], a - b, p3[i][v] - a - b);
       }
     }
 }
