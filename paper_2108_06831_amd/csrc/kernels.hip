@@ -599,18 +599,6 @@ hipError_t launch_small_steps(hipStream_t s, const SmallStep* steps, const int32
   return hipGetLastError();
 }
 
-// Result stores of the matrix products are streaming (non-temporal) stores:
-// a large product writes far more result than it reads operands, and
-// ordinary stores would evict the operand tiles that later tiles of the same
-// XCD still read from its L2.
-typedef float float2_nt __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ void store_stream(float2* p, float re, float im) {
-  float2_nt v;
-  v.x = re;
-  v.y = im;
-  __builtin_nontemporal_store(v, reinterpret_cast<float2_nt*>(p));
-}
-
 // deposit(x, pos, nbits): bit j of x (j < nbits) placed at address position
 // pos[j]; the address maps of the permute and matrix-product kernels.
 // The positions are read four at a time as 32-bit words (each map starts at
@@ -662,6 +650,23 @@ static_assert(offsetof(SweepPassArgs, lpos) % 4 == 0 && offsetof(SweepPassArgs, 
 __device__ inline int64_t ins0(int64_t x, int p) { return ((x >> p) << (p + 1)) | (x & (((int64_t)1 << p) - 1)); }
 __device__ inline int lds_phys(int i) { return i + (i >> 5); }
 
+// Streaming (non-temporal) loads and stores.  The matrix products store their
+// results this way: a large product writes far more result than it reads
+// operands, and ordinary stores would evict the operand tiles that later
+// tiles of the same XCD still read from its L2.  The fused passes move each
+// chunk through once.
+typedef float float2_nt __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void store_stream(float2* p, float re, float im) {
+  float2_nt v;
+  v.x = re;
+  v.y = im;
+  __builtin_nontemporal_store(v, reinterpret_cast<float2_nt*>(p));
+}
+__device__ __forceinline__ float2 load_stream(const float2* p) {
+  const float2_nt v = __builtin_nontemporal_load(reinterpret_cast<const float2_nt*>(p));
+  return f2(v.x, v.y);
+}
+
 // Moving a chunk of 2^l = 16 nt elements between HBM and LDS: thread tid
 // takes elements tid + k nt, k = 0..15 (consecutive threads on consecutive
 // addresses).  The loads are issued eight at a time before their LDS writes,
@@ -677,7 +682,7 @@ __device__ __forceinline__ void chunk_to_lds(float2* buf, const float2* src, int
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const int i = tid + (8 * h + k) * nt;
-      v[k] = src[base | (i & 31) | dep_hi[i >> 5]];
+      v[k] = load_stream(&src[base | (i & 31) | dep_hi[i >> 5]]);
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k) buf[lds_phys(tid + (8 * h + k) * nt)] = v[k];
@@ -694,8 +699,8 @@ __device__ __forceinline__ void chunk2_to_lds(float2* buf0, float2* buf1, const 
     for (int k = 0; k < 8; ++k) {
       const int i = tid + (8 * h + k) * nt;
       const int64_t x = base | (i & 31) | dep_hi[i >> 5];
-      v[k] = src0[x];
-      w[k] = src1[x];
+      v[k] = load_stream(&src0[x]);
+      w[k] = load_stream(&src1[x]);
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
@@ -717,7 +722,7 @@ __device__ __forceinline__ void chunk_from_lds(float2* dst, const float2* buf, i
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const int i = tid + (8 * h + k) * nt;
-      dst[base | (i & 31) | dep_hi[i >> 5]] = v[k];
+      store_stream(&dst[base | (i & 31) | dep_hi[i >> 5]], v[k].x, v[k].y);
     }
     asm volatile("" ::: "memory");
   }
