@@ -57,6 +57,24 @@ class Workload:
         return None
 
 
+def host_description():
+    """The host the CPU baseline ran on: processor model, logical CPUs, memory."""
+    model, mem_kib = None, None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal:"):
+                mem_kib = int(line.split()[1])
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "host_logical_cpus": os.cpu_count(),
+            "host_mem_gib": round(mem_kib / 2 ** 20, 1) if mem_kib else None}
+
+
 def stored_traffic(config, precision, kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summaries (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy's reading),
@@ -711,6 +729,7 @@ def main():
             wl.check()
         cb = wl.cpu_baseline()
         if cb is not None:
+            cb.update(host_description())
             result["cpu_baseline"] = cb
     print(json.dumps(result))
 
