@@ -1019,12 +1019,30 @@ extern "C" tn_status tn_expectation(void* stream, int32_t precision, tn_network*
     HIP_TRY(hipEventRecord(SL_->fork, s0));
     for (int k = 0; k < lanes - 1; ++k) HIP_TRY(hipStreamWaitEvent(SL_->stream[k], SL_->fork, 0));
   }
+  // circuits to lanes by the planner's run-time model, largest first, each to the lane with the
+  // least work so far (ties: the lower lane), so that the lanes finish close together
+  std::vector<int> lane_of(n_circuits, 0);
+  if (lanes > 1) {
+    std::vector<int> order(n_circuits);
+    std::vector<double> cost(n_circuits);
+    for (int c = 0; c < n_circuits; ++c) {
+      order[c] = c;
+      cost[c] = paths[c]->stats.modeled_seconds * std::ldexp(1.0, paths[c]->slice_bits);
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    std::vector<double> load(lanes, 0.0);
+    for (int c : order) {
+      const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      lane_of[c] = k;
+      load[k] += cost[c];
+    }
+  }
   tn_status result = TN_OK;
   for (int c = 0; c < n_circuits && result == TN_OK; ++c) {
     tn_network* net = nets[c];
     tn_path* path = paths[c];
     const double* prm = params_dev ? params_dev[c] : nullptr;
-    const int lane = c % lanes;
+    const int lane = lane_of[c];
     hipStream_t s = lane == 0 ? s0 : SL_->stream[lane - 1];
     const ZTerms& terms = all_terms[c];
     DevNet* d = devs[c];
