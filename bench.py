@@ -536,7 +536,7 @@ def main():
     args = ap.parse_args()
     if args.paper_workload:
         if args.gpus != 1:
-            print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
+            print(f"bench.py measures one GPU: the library has no multi-GPU path (asked for --gpus {args.gpus}).",
                   file=sys.stderr)
             sys.exit(2)
         return paper_workload(args)
@@ -551,7 +551,7 @@ def main():
         args.warmup = 200 if short else 5
 
     if args.gpus != 1:
-        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
+        print(f"bench.py measures one GPU: the library has no multi-GPU path (asked for --gpus {args.gpus}).",
               file=sys.stderr)
         sys.exit(2)
 

@@ -57,7 +57,7 @@ typedef enum {
   TN_ENOMEM = 2,       /* caller's workspace smaller than required, or a host allocation failed */
   TN_ELIMIT = 3,       /* the plan's largest intermediate exceeds the requested cap */
   TN_EDEVICE = 4,      /* a HIP runtime error */
-  TN_EUNSUPPORTED = 5  /* a valid request this build does not handle (e.g. a non power-of-two extent) */
+  TN_EUNSUPPORTED = 5  /* a valid request the library does not handle (e.g. a non power-of-two extent) */
 } tn_status;
 
 /* Arithmetic of the pairwise products.  C64: complex64 operands, FP32
@@ -331,7 +331,7 @@ tn_status tn_expectation(void* stream, int32_t precision, tn_network* const* net
  *   grad_out_dev: device float64[batch] (dL/dE, NULL = ones);
  *   value_dev: device float64[batch]; grad_dev: device float64[batch][n_params].
  * Workspace: tn_backward_workspace_bytes.  TN_EUNSUPPORTED for a parametric
- * gate whose generator this build does not know (MATRIX gates are fixed).
+ * gate whose generator the library does not know (MATRIX gates are fixed).
  */
 size_t tn_backward_workspace_bytes(const tn_network* net, const tn_path* path, int32_t batch);
 tn_status tn_backward(void* stream, int32_t precision, tn_network* net, tn_path* path, const double* params_dev,
