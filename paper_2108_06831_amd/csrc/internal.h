@@ -175,7 +175,7 @@ struct SweepPass {
 // on both, each parametric gate first adding its chunk's share of
 // Im<lambda|G|psi> to an accumulator of its own (`red`).
 constexpr int kAdjMaxRed = 128;     // two per lane of a wave (the kernel's register accumulators)
-constexpr int kAdjPreGates = 128;   // gates of a pass whose U entries the kernel stages in LDS
+constexpr int kAdjPreGates = 128;   // gates of an adjoint pass at most (the kernel stages their U entries in LDS)
 struct AdjGateDesc {
   int32_t diag, n;
   int32_t lidx[2];  // as in SweepGateDesc

@@ -1046,8 +1046,11 @@ __device__ __forceinline__ void apply_count_group(float2 (&x)[16], const SweepGa
 
 // The descriptor and value tables come as separate __restrict__ arguments: the
 // compiler may then read them with scalar loads (nothing the kernel writes can
-// alias them) instead of vector memory loads on every gate.
-template <int PREC>
+// alias them) instead of vector memory loads on every gate.  VL: the gate
+// values are read from their LDS copy (a compile-time choice: a pointer that
+// may point to LDS or to global memory would be read with flat loads, whose
+// latency every gate would wait on).
+template <int PREC, bool VL>
 __global__ __launch_bounds__(kThreads) void k_sweep_pass(SweepPassArgs a, const SweepGateDesc* __restrict__ gates,
                                                           const SweepSegment* __restrict__ segs,
                                                           const float2* __restrict__ vals) {
@@ -1085,7 +1088,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep_pass(SweepPassArgs a, const 
     float2 ph = f2(1.f, 0.f);
     for (int gi = seg.first_gate; gi < seg.first_gate + seg.n_gates; ++gi) {
       const SweepGateDesc& gd = gates[gi];
-      const float2* V = a.gates_in_lds ? vtab + (gd.voff - a.lds_off) : V0 + gd.voff;
+      const float2* V = VL ? vtab + (gd.voff - a.lds_off) : V0 + gd.voff;
       if (gd.form == kFormCount) {
         apply_count_group<PREC>(x, gates + gi + 1, gd.n, ob, base, ctab + gd.voff);
         gi += gd.n;
@@ -1212,12 +1215,18 @@ hipError_t launch_sweep_pass(hipStream_t s, const SweepPass& ps, int bits, const
   const int64_t chunks = (int64_t)1 << nr;
   if (chunks > ((int64_t)1 << 24)) return hipErrorInvalidValue;
   const int threads = 1 << (ps.l - 4);
-  if (precision == TN_PREC_BF16X3)
-    hipLaunchKernelGGL(k_sweep_pass<TN_PREC_BF16X3>, dim3((unsigned)chunks, batch), dim3(threads), 0, s, a, a.gates,
-                       a.segs, a.vals);
-  else
-    hipLaunchKernelGGL(k_sweep_pass<TN_PREC_C64>, dim3((unsigned)chunks, batch), dim3(threads), 0, s, a, a.gates, a.segs,
-                       a.vals);
+  const dim3 grid((unsigned)chunks, batch);
+  if (precision == TN_PREC_BF16X3) {
+    if (a.gates_in_lds)
+      hipLaunchKernelGGL((k_sweep_pass<TN_PREC_BF16X3, true>), grid, dim3(threads), 0, s, a, a.gates, a.segs, a.vals);
+    else
+      hipLaunchKernelGGL((k_sweep_pass<TN_PREC_BF16X3, false>), grid, dim3(threads), 0, s, a, a.gates, a.segs, a.vals);
+  } else {
+    if (a.gates_in_lds)
+      hipLaunchKernelGGL((k_sweep_pass<TN_PREC_C64, true>), grid, dim3(threads), 0, s, a, a.gates, a.segs, a.vals);
+    else
+      hipLaunchKernelGGL((k_sweep_pass<TN_PREC_C64, false>), grid, dim3(threads), 0, s, a, a.gates, a.segs, a.vals);
+  }
   return hipGetLastError();
 }
 
@@ -2737,10 +2746,10 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a, const 
     return;
   }
   const float2* Uz = Uall + (int64_t)z * a.u_bs;
-  // U of the first kAdjPreGates gates staged in LDS (one load per thread, all in flight together,
-  // instead of a scalar load on every gate): diagonal U[0], U[3] (one bit) or U[0], U[5], U[10],
-  // U[15] (two bits); one-qubit dense U[0..3]; two-qubit dense gates read U from memory
-  for (int i = tid; i < min(a.n_gates, kAdjPreGates) * 4; i += nt) {
+  // U of the pass's gates (at most kAdjPreGates) staged in LDS, one load per thread, all in flight
+  // together: diagonal U[0], U[3] (one bit) or U[0], U[5], U[10], U[15] (two bits); one-qubit dense
+  // U[0..3]; two-qubit dense gates read U from memory
+  for (int i = tid; i < a.n_gates * 4; i += nt) {
     const int g = i >> 2, e = i & 3;
     const AdjGateDesc& gd = gates[a.first_gate + g];
     const int idx = gd.diag ? (gd.n == 2 ? 5 * e : (e == 1 ? 3 : 0)) : e;
@@ -2790,8 +2799,7 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a, const 
         const AdjGateDesc& gd = gates[gi];
         const float2* U = Uz + (int64_t)gd.gate * 16;
         const float2* G = reinterpret_cast<const float2*>(gd.gen);
-        const int pg = gi - a.first_gate;
-        const float2* Up = pg < kAdjPreGates ? upre[pg] : nullptr;
+        const float2* Up = upre[gi - a.first_gate];
         if (!gd.diag) have_t = false;
         if (gd.diag) {
           const int k[2] = {gd.kreg[0], gd.n == 2 ? gd.kreg[1] : -1};
@@ -2814,8 +2822,7 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a, const 
             continue;
           }
           // U^dagger diagonal: conj(U[b][b])
-          const float2 u0 = Up ? Up[0] : U[0], u1 = Up ? Up[1] : two ? U[5] : U[3],
-                       u2 = two ? (Up ? Up[2] : U[10]) : f2(1.f, 0.f), u3 = two ? (Up ? Up[3] : U[15]) : f2(1.f, 0.f);
+          const float2 u0 = Up[0], u1 = Up[1], u2 = two ? Up[2] : f2(1.f, 0.f), u3 = two ? Up[3] : f2(1.f, 0.f);
           if (gd.red >= 0) {
             float v;
             if (!two) {
@@ -2876,7 +2883,7 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a, const 
             add_grad(gd.red, g);
           }
           // U^dagger[m][k] = conj(U[k][m])
-          const float2 w0 = Up ? Up[0] : U[0], w1 = Up ? Up[1] : U[1], w2 = Up ? Up[2] : U[2], w3 = Up ? Up[3] : U[3];
+          const float2 w0 = Up[0], w1 = Up[1], w2 = Up[2], w3 = Up[3];
           float2 ud[4];
           ud[0] = f2(w0.x, -w0.y);
           ud[1] = f2(w2.x, -w2.y);
@@ -2953,7 +2960,9 @@ hipError_t launch_adjoint_pass(hipStream_t s, const SweepPass& ps, int bits, con
   a.first_gate = ps.first_gate;
   a.n_gates = ps.n_gates;
   // 64 threads at least (whole waves for the gradient reductions), 256 at most
-  if (ps.l < 10 || ps.l > kSweepMaxLocal || ps.n_red < 0 || ps.n_red > kAdjMaxRed) return hipErrorInvalidValue;
+  if (ps.l < 10 || ps.l > kSweepMaxLocal || ps.n_red < 0 || ps.n_red > kAdjMaxRed || ps.n_gates < 0 ||
+      ps.n_gates > kAdjPreGates)
+    return hipErrorInvalidValue;
   std::vector<char> local(bits, 0);
   for (int j = 0; j < ps.l; ++j) {
     a.lpos[j] = ps.lpos[j];

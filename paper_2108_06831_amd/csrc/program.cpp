@@ -297,6 +297,7 @@ void build_chains(tn_path* path, int T) {
       const SkinnyDesc& d = path->steps[i].sk;
       PassItem it;
       it.diag = d.nb > 0;
+      it.movable = path->steps[i].zz_param == -2;  // ZZ phases stay together for count groups
       if (d.nb == 0) for (int j = 0; j < d.nk; ++j) it.pos.push_back(d.k_pos[j]);
       else for (int j = 0; j < d.nb; ++j) it.pos.push_back(d.bt_pos[j]);
       items.push_back(it);
@@ -1149,6 +1150,7 @@ void build_adjoint_plan(const tn_network* net, tn_path* path, const std::vector<
     if (g.nq == 2 && !g.diag && g.gen != GEN_NONE) return;
     PassItem it;
     it.diag = g.diag != 0;
+    it.grad = slot_of_gate[gi] >= 0;
     const int p0 = pos_of(path->final_bits, net->wire_final[g.q[0]] * 64);
     const int p1 = g.nq == 2 ? pos_of(path->final_bits, net->wire_final[g.q[1]] * 64) : 0;
     if (p0 < 0 || p1 < 0) return;
@@ -1158,7 +1160,7 @@ void build_adjoint_plan(const tn_network* net, tn_path* path, const std::vector<
     items.push_back(it);
   }
   std::vector<PlannedPass> planned;
-  if (!plan_passes(R, items, planned)) return;
+  if (!plan_passes(R, items, planned, kAdjPreGates, kAdjMaxRed)) return;
   for (const PlannedPass& pp : planned) {
     SweepPass ps;
     ps.l = pp.l;
