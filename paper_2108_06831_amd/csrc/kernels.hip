@@ -733,17 +733,17 @@ __device__ __forceinline__ void chunk_from_lds(float2* dst, const float2* buf, i
 // diagonal and an imaginary off-diagonal (RX, Y, the QAOA mixer exp(-i b X)).
 enum { kDenseGeneric = 0, kDenseReal = 1, kDenseRxLike = 2 };
 
-template <int PREC, int U>
-__device__ __forceinline__ void reg_apply1(float2 (&x)[16], const float2* g, int form = kDenseGeneric) {
+template <int PREC, int U, int FORM>
+__device__ __forceinline__ void reg_apply1(float2 (&x)[16], const float2* g) {
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     if (r & (1 << U)) continue;
     const int r1 = r | (1 << U);
     const float2 a = x[r], b = x[r1];
-    if (PREC == TN_PREC_C64 && form == kDenseReal) {
+    if (PREC == TN_PREC_C64 && FORM == kDenseReal) {
       x[r] = f2(fmaf(g[0].x, a.x, g[1].x * b.x), fmaf(g[0].x, a.y, g[1].x * b.y));
       x[r1] = f2(fmaf(g[2].x, a.x, g[3].x * b.x), fmaf(g[2].x, a.y, g[3].x * b.y));
-    } else if (PREC == TN_PREC_C64 && form == kDenseRxLike) {
+    } else if (PREC == TN_PREC_C64 && FORM == kDenseRxLike) {
       // g1 = i g1.y, g2 = i g2.y: i t (u + i v) = -t v + i t u
       x[r] = f2(fmaf(g[0].x, a.x, -g[1].y * b.y), fmaf(g[0].x, a.y, g[1].y * b.x));
       x[r1] = f2(fmaf(g[3].x, b.x, -g[2].y * a.y), fmaf(g[3].x, b.y, g[2].y * a.x));
@@ -752,6 +752,33 @@ __device__ __forceinline__ void reg_apply1(float2 (&x)[16], const float2* g, int
       x[r1] = cmac<PREC>(cmul<PREC>(g[2], a), g[3], b);
     }
   }
+}
+
+// A dense one-qubit gate on register bit rb, its values in the given form, on
+// one state (NS = 1) or on x and y (NS = 2).  Bit and form are compile-time
+// constants in every case: a form tested inside the unrolled element loop
+// would be turned into per-element selects between the variants.
+template <int PREC, int NS>
+__device__ __forceinline__ void apply_dense1(float2 (&x)[16], float2 (&y)[16], const float2* g, int rb, int form) {
+#define TNQ_DENSE1(U, F)                   \
+  reg_apply1<PREC, U, F>(x, g);            \
+  if (NS == 2) reg_apply1<PREC, U, F>(y, g); \
+  break;
+  switch (rb * 3 + form) {
+    case 0: TNQ_DENSE1(0, 0)
+    case 1: TNQ_DENSE1(0, 1)
+    case 2: TNQ_DENSE1(0, 2)
+    case 3: TNQ_DENSE1(1, 0)
+    case 4: TNQ_DENSE1(1, 1)
+    case 5: TNQ_DENSE1(1, 2)
+    case 6: TNQ_DENSE1(2, 0)
+    case 7: TNQ_DENSE1(2, 1)
+    case 8: TNQ_DENSE1(2, 2)
+    case 9: TNQ_DENSE1(3, 0)
+    case 10: TNQ_DENSE1(3, 1)
+    default: TNQ_DENSE1(3, 2)
+  }
+#undef TNQ_DENSE1
 }
 
 template <int PREC, int U0, int U1>
@@ -1086,7 +1113,35 @@ __global__ __launch_bounds__(kThreads) void k_sweep_pass(SweepPassArgs a, const 
     // bit of the gate outside the register set) commute with every gate of the
     // segment: they are multiplied into one per-thread factor, applied once
     float2 ph = f2(1.f, 0.f);
-    for (int gi = seg.first_gate; gi < seg.first_gate + seg.n_gates; ++gi) {
+    const int g_end = seg.first_gate + seg.n_gates;
+    int gi = seg.first_gate;
+    // the segment's leading diagonal gates with no bit in the registers (the
+    // planner puts them first): only the per-thread factor changes, so this
+    // loop carries no register elements (the main loop below copies them back
+    // into place on every gate)
+    for (; gi < g_end; ++gi) {
+      const SweepGateDesc& gd = gates[gi];
+      if (!gd.diag || gd.form == kFormCount || gd.form == kFormCountMember || gd.kreg[0] >= 0 ||
+          (gd.n == 2 && gd.kreg[1] >= 0))
+        break;
+      const float2* V = VL ? vtab + (gd.voff - a.lds_off) : V0 + gd.voff;
+      int cb = 0;
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        if (j >= gd.n) continue;
+        const int cs = gd.csrc[j];
+        cb |= (cs >= 64 ? (int)((base >> (cs - 64)) & 1) : ((ob >> cs) & 1)) << j;
+      }
+      const bool two = gd.n == 2;
+      const float2 d0 = V[0], d1 = V[1], d2 = two ? V[2] : d0, d3 = two ? V[3] : d0;
+      const float2 f = cb == 0 ? d0 : cb == 1 ? d1 : cb == 2 ? d2 : d3;
+      if (gd.form == kFormSigns) {
+        if (f.x < 0.f) ph = f2(-ph.x, -ph.y);
+      } else {
+        ph = cmul<TN_PREC_C64>(ph, f);
+      }
+    }
+    for (; gi < g_end; ++gi) {
       const SweepGateDesc& gd = gates[gi];
       const float2* V = VL ? vtab + (gd.voff - a.lds_off) : V0 + gd.voff;
       if (gd.form == kFormCount) {
@@ -1124,12 +1179,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep_pass(SweepPassArgs a, const 
       } else if (gd.n == 1) {
         const float2 g[4] = {V[0], V[1], V[2], V[3]};
         const int form = gd.form == kFormReal ? kDenseReal : gd.form == kFormRxLike ? kDenseRxLike : kDenseGeneric;
-        switch (gd.rb[0]) {
-          case 0: reg_apply1<PREC, 0>(x, g, form); break;
-          case 1: reg_apply1<PREC, 1>(x, g, form); break;
-          case 2: reg_apply1<PREC, 2>(x, g, form); break;
-          default: reg_apply1<PREC, 3>(x, g, form); break;
-        }
+        apply_dense1<PREC, 1>(x, x, g, gd.rb[0], form);
       } else {
         float2 g[16];
 #pragma unroll
@@ -2795,7 +2845,44 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a, const 
       // term is then q0 (tT - s1) + q1 s1, s1 the sum where the gate's bit is 1
       bool have_t = false;
       float tT = 0.f, tS0 = 0.f, tS1 = 0.f, tS2 = 0.f, tS3 = 0.f;
-      for (int gi = seg.first_gate; gi < seg.first_gate + seg.n_gates; ++gi) {
+      const int g_end = seg.first_gate + seg.n_gates;
+      int gi = seg.first_gate;
+      // the segment's leading diagonal gates with no bit in the registers (the planner puts
+      // them first; they commute with the rest of the segment): their gradient terms need only
+      // tT, and they change only ph, so this loop carries no register elements
+      for (; gi < g_end; ++gi) {
+        const AdjGateDesc& gd = gates[gi];
+        if (!gd.diag || gd.kreg[0] >= 0 || (gd.n == 2 && gd.kreg[1] >= 0)) break;
+        int c = 0;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          if (j >= gd.n) continue;
+          const int cs = gd.csrc[j];
+          c |= (cs >= 64 ? (int)((base >> (cs - 64)) & 1) : ((ob >> cs) & 1)) << j;
+        }
+        if (gd.form & ADJ_DIAG_SIGNS) {
+          if (((gd.form >> 8) >> c) & 1) ph = f2(-ph.x, -ph.y);
+          continue;
+        }
+        const float2* Up = upre[gi - a.first_gate];
+        if (gd.red >= 0) {
+          if (!have_t) {
+            tT = 0.f;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) tT += im_conj_mul(xl[r], xp[r]);
+            have_t = true;
+          }
+          const float* G = gd.gen;  // diagonal generator entries, re/im interleaved
+          const float q = c == 0 ? G[0] : c == 1 ? G[2] : c == 2 ? G[4] : G[6];
+          add_grad(gd.red, q * tT);
+        }
+        const bool two = gd.n == 2;
+        const float2 u0 = Up[0], u1 = Up[1], u2 = two ? Up[2] : u0, u3 = two ? Up[3] : u0;
+        const float2 u = c == 0 ? u0 : c == 1 ? u1 : c == 2 ? u2 : u3;  // U^dagger: conj(U[b][b])
+        ph = cmul<TN_PREC_C64>(ph, f2(u.x, -u.y));
+      }
+      have_t = false;  // the main loop's sums also split tT by register bit
+      for (; gi < g_end; ++gi) {
         const AdjGateDesc& gd = gates[gi];
         const float2* U = Uz + (int64_t)gd.gate * 16;
         const float2* G = reinterpret_cast<const float2*>(gd.gen);
@@ -2890,12 +2977,7 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a, const 
           ud[2] = f2(w1.x, -w1.y);
           ud[3] = f2(w3.x, -w3.y);
           const int form = gd.uform == kFormReal ? kDenseReal : gd.uform == kFormRxLike ? kDenseRxLike : kDenseGeneric;
-          switch (gd.rb[0]) {
-            case 0: reg_apply1<PREC, 0>(xp, ud, form); reg_apply1<PREC, 0>(xl, ud, form); break;
-            case 1: reg_apply1<PREC, 1>(xp, ud, form); reg_apply1<PREC, 1>(xl, ud, form); break;
-            case 2: reg_apply1<PREC, 2>(xp, ud, form); reg_apply1<PREC, 2>(xl, ud, form); break;
-            default: reg_apply1<PREC, 3>(xp, ud, form); reg_apply1<PREC, 3>(xl, ud, form); break;
-          }
+          apply_dense1<PREC, 2>(xp, xl, ud, gd.rb[0], form);
         } else {
           // dense two-qubit gates carry no gradient term (the planner checks)
           float2 ud[16];

@@ -413,6 +413,14 @@ void build_chains(tn_path* path, int T) {
           g = g2;
         }
         seg.n_gates = (int32_t)path->sweep_gates.size() - seg.first_gate;
+        // the segment's diagonal gates on bits outside its registers first: they commute with
+        // every other gate of the segment and change only a per-thread factor, so the kernel
+        // runs them in a loop of their own that leaves the register elements alone
+        std::stable_partition(path->sweep_gates.begin() + seg.first_gate, path->sweep_gates.end(),
+                              [](const SweepGateDesc& gd) {
+                                return gd.diag && gd.form != kFormCount && gd.form != kFormCountMember &&
+                                       gd.kreg[0] < 0 && (gd.n == 1 || gd.kreg[1] < 0);
+                              });
         fill_segment_tables(seg, ps.l);
         path->segments.push_back(seg);
       }
@@ -1242,6 +1250,12 @@ void build_adjoint_plan(const tn_network* net, tn_path* path, const std::vector<
       for (int j = 0; j < 4; ++j) seg.rbits[j] = sg.rbits[j];
       seg.first_gate = ps.first_gate + sg.first;
       seg.n_gates = sg.count;
+      // diagonal gates on bits outside the registers first (as in the forward passes; their
+      // gradient terms do not depend on where in the segment they are taken)
+      std::stable_partition(path->adj_gates.begin() + seg.first_gate,
+                            path->adj_gates.begin() + seg.first_gate + seg.n_gates, [](const AdjGateDesc& gd) {
+                              return gd.diag && gd.kreg[0] < 0 && (gd.n == 1 || gd.kreg[1] < 0);
+                            });
       fill_segment_tables(seg, ps.l);
       path->adj_segments.push_back(seg);
     }
