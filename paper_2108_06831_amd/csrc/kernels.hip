@@ -733,6 +733,16 @@ __device__ __forceinline__ void chunk_from_lds(float2* dst, const float2* buf, i
 // diagonal and an imaginary off-diagonal (RX, Y, the QAOA mixer exp(-i b X)).
 enum { kDenseGeneric = 0, kDenseReal = 1, kDenseRxLike = 2 };
 
+// The register-position variants of a helper below are the same code apart
+// from which elements they touch, and in reduced precision they are long
+// enough that the compiler merges their common tails, selecting the elements
+// through pointers, which puts all of them in scratch memory.  A distinct
+// (empty) marker at the end of each variant keeps the tails apart.
+template <int PREC, int ID>
+__device__ __forceinline__ void variant_end() {
+  if constexpr (PREC != TN_PREC_C64) asm volatile("; variant %0" ::"n"(ID));
+}
+
 template <int PREC, int U, int FORM>
 __device__ __forceinline__ void reg_apply1(float2 (&x)[16], const float2* g) {
 #pragma unroll
@@ -752,6 +762,7 @@ __device__ __forceinline__ void reg_apply1(float2 (&x)[16], const float2* g) {
       x[r1] = cmac<PREC>(cmul<PREC>(g[2], a), g[3], b);
     }
   }
+  variant_end<PREC, U * 3 + FORM>();
 }
 
 // A dense one-qubit gate on register bit rb, its values in the given form, on
@@ -764,7 +775,9 @@ __device__ __forceinline__ void apply_dense1(float2 (&x)[16], float2 (&y)[16], c
   reg_apply1<PREC, U, F>(x, g);            \
   if (NS == 2) reg_apply1<PREC, U, F>(y, g); \
   break;
-  switch (rb * 3 + form) {
+  // (the reduced-precision products take one form for all: identical cases would be merged
+  // into code that indexes the elements through pointers, which keeps them out of registers)
+  switch (rb * 3 + (PREC == TN_PREC_C64 ? form : kDenseGeneric)) {
     case 0: TNQ_DENSE1(0, 0)
     case 1: TNQ_DENSE1(0, 1)
     case 2: TNQ_DENSE1(0, 2)
@@ -798,6 +811,7 @@ __device__ __forceinline__ void reg_apply2(float2 (&x)[16], const float2* g) {
       x[id[m]] = acc;
     }
   }
+  variant_end<PREC, 16 + U0 * 4 + U1>();
 }
 
 // Diagonal factor on the 16 register elements, with the bits of the factor's
@@ -806,6 +820,7 @@ template <int PREC, int U>
 __device__ __forceinline__ void diag_reg1(float2 (&x)[16], float2 e0, float2 e1) {
 #pragma unroll
   for (int r = 0; r < 16; ++r) x[r] = cmul<PREC>((r >> U) & 1 ? e1 : e0, x[r]);
+  variant_end<PREC, 32 + U>();
 }
 // ... or d_{bit U0 of r + 2 bit U1 of r}
 template <int PREC, int U0, int U1>
@@ -815,6 +830,7 @@ __device__ __forceinline__ void diag_reg2(float2 (&x)[16], float2 d0, float2 d1,
     const int b = ((r >> U0) & 1) | (((r >> U1) & 1) << 1);
     x[r] = cmul<PREC>(b == 0 ? d0 : b == 1 ? d1 : b == 2 ? d2 : d3, x[r]);
   }
+  variant_end<PREC, 48 + U0 * 4 + U1>();
 }
 
 // x[r] *= d_b, b = bit0 + 2 bit1 of the diagonal's index.  Bit j is register
@@ -886,6 +902,7 @@ __device__ __forceinline__ void diag_reg2_rel(float2 (&x)[16], float2 (&y)[16], 
     x[r] = cmul<PREC>(q, x[r]);
     if (NS == 2) y[r] = cmul<PREC>(q, y[r]);
   }
+  variant_end<PREC, 64 + NS * 16 + U0 * 4 + U1>();
 }
 template <int PREC, int NS, int U>
 __device__ __forceinline__ void diag_reg1_rel(float2 (&x)[16], float2 (&y)[16], float2 q1) {
@@ -895,6 +912,7 @@ __device__ __forceinline__ void diag_reg1_rel(float2 (&x)[16], float2 (&y)[16], 
       x[r] = cmul<PREC>(q1, x[r]);
       if (NS == 2) y[r] = cmul<PREC>(q1, y[r]);
     }
+  variant_end<PREC, 112 + NS * 4 + U>();
 }
 __device__ inline bool is_one(float2 v) { return v.x == 1.f && v.y == 0.f; }
 
@@ -1113,6 +1131,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep_pass(SweepPassArgs a, const 
     // bit of the gate outside the register set) commute with every gate of the
     // segment: they are multiplied into one per-thread factor, applied once
     float2 ph = f2(1.f, 0.f);
+    bool ph_used = false;  // the same for the whole block: set where a gate's descriptor sends it to ph
     const int g_end = seg.first_gate + seg.n_gates;
     int gi = seg.first_gate;
     // the segment's leading diagonal gates with no bit in the registers (the
@@ -1135,6 +1154,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep_pass(SweepPassArgs a, const 
       const bool two = gd.n == 2;
       const float2 d0 = V[0], d1 = V[1], d2 = two ? V[2] : d0, d3 = two ? V[3] : d0;
       const float2 f = cb == 0 ? d0 : cb == 1 ? d1 : cb == 2 ? d2 : d3;
+      ph_used = true;
       if (gd.form == kFormSigns) {
         if (f.x < 0.f) ph = f2(-ph.x, -ph.y);
       } else {
@@ -1164,6 +1184,7 @@ __global__ __launch_bounds__(kThreads) void k_sweep_pass(SweepPassArgs a, const 
         if (gd.form == kFormSigns) {  // entries +-1: sign flips, no multiplies
           const int sm = (d0.x < 0.f) | ((d1.x < 0.f) << 1) | ((d2.x < 0.f) << 2) | ((d3.x < 0.f) << 3);
           if (k0 < 0 && k1 < 0) {
+            ph_used = true;
             if ((sm >> cb) & 1) ph = f2(-ph.x, -ph.y);
           } else {
             apply_signs(x, gd.n, k0, k1, cb, sm);
@@ -1171,8 +1192,10 @@ __global__ __launch_bounds__(kThreads) void k_sweep_pass(SweepPassArgs a, const 
         } else if (k0 < 0 && k1 < 0) {
           const float2 f = cb == 0 ? d0 : cb == 1 ? d1 : cb == 2 ? d2 : d3;
           ph = cmul<TN_PREC_C64>(ph, f);
+          ph_used = true;
         } else if (gd.form == kFormUnit) {
           apply_diag_unit<PREC, 1>(x, x, ph, gd.n, k0, k1, cb, d0, d1, d2, d3);
+          ph_used = true;
         } else {
           apply_diag<PREC>(x, gd.n, k0, k1, cb, d0, d1, d2, d3);
         }
@@ -1194,8 +1217,13 @@ __global__ __launch_bounds__(kThreads) void k_sweep_pass(SweepPassArgs a, const 
         }
       }
     }
+    if (ph_used) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) buf[pob + seg.physoff[r]] = cmul<TN_PREC_C64>(ph, x[r]);
+      for (int r = 0; r < 16; ++r) buf[pob + seg.physoff[r]] = cmul<TN_PREC_C64>(ph, x[r]);
+    } else {  // no gate of the segment touched the factor (it is 1)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) buf[pob + seg.physoff[r]] = x[r];
+    }
     __syncthreads();
   }
   chunk_from_lds(out, buf, base, dep_hi, tid, nt);
@@ -2839,6 +2867,7 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a, const 
       // segment's end; they commute with the segment's gates and leave every
       // gradient term Im<lambda|G|psi> unchanged (|factor|^2 = 1)
       float2 ph = f2(1.f, 0.f);
+      bool ph_used = false;  // the same for the whole block (set by gates' descriptors)
       // Im(conj(lambda) psi) at each element is unchanged by unit-modulus diagonal gates, so
       // along a run of diagonal gates its sums are formed once: over the thread's elements
       // (tT) and over those whose register bit j is 1 (tS[j]); a one-bit diagonal generator's
@@ -2860,6 +2889,7 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a, const 
           const int cs = gd.csrc[j];
           c |= (cs >= 64 ? (int)((base >> (cs - 64)) & 1) : ((ob >> cs) & 1)) << j;
         }
+        ph_used = true;
         if (gd.form & ADJ_DIAG_SIGNS) {
           if (((gd.form >> 8) >> c) & 1) ph = f2(-ph.x, -ph.y);
           continue;
@@ -2901,6 +2931,7 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a, const 
           const bool uniform = k[0] < 0 && k[1] < 0;  // the same entry for every element of the thread
           if (gd.form & ADJ_DIAG_SIGNS) {  // Z, CZ: U^dagger = U, entries +-1
             if (uniform) {
+              ph_used = true;
               if (((gd.form >> 8) >> c) & 1) ph = f2(-ph.x, -ph.y);
               continue;
             }
@@ -2934,6 +2965,7 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a, const 
             add_grad(gd.red, v);
           }
           const float2 d0 = f2(u0.x, -u0.y), d1 = f2(u1.x, -u1.y), d2 = f2(u2.x, -u2.y), d3 = f2(u3.x, -u3.y);
+          ph_used = true;
           if (uniform) {
             const float2 f = c == 0 ? d0 : c == 1 ? d1 : c == 2 ? d2 : d3;
             ph = cmul<TN_PREC_C64>(ph, f);
@@ -3001,10 +3033,18 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a, const 
           }
         }
       }
+      if (ph_used) {
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        bp[pob + seg.physoff[r]] = cmul<TN_PREC_C64>(ph, xp[r]);
-        bl[pob + seg.physoff[r]] = cmul<TN_PREC_C64>(ph, xl[r]);
+        for (int r = 0; r < 16; ++r) {
+          bp[pob + seg.physoff[r]] = cmul<TN_PREC_C64>(ph, xp[r]);
+          bl[pob + seg.physoff[r]] = cmul<TN_PREC_C64>(ph, xl[r]);
+        }
+      } else {  // no gate of the segment touched the factor (it is 1)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          bp[pob + seg.physoff[r]] = xp[r];
+          bl[pob + seg.physoff[r]] = xl[r];
+        }
       }
       __syncthreads();
     }
