@@ -300,9 +300,23 @@ static_assert(sizeof(SmallStep) % 16 == 0, "SmallStep is copied in 16-byte words
 
 enum StepKind { SK_SKINNY = 0, SK_GEMM = 1, SK_SMALL = 2 };
 
+// A run of outer products of a tensor with one-qubit vectors: skinny steps with
+// no summed, batch or shared bits and one output bit, each on the previous
+// step's result.  Each step puts its vector's bit above the bits it was given,
+// so the run's result is C[m_k .. m_1 | o] = T[o] g_1[m_1] .. g_k[m_k]: one
+// launch writes it, where the steps would write every intermediate.
+constexpr int kOuterMax = 24;
+struct OuterChain {
+  BufRef t, c;
+  int32_t t_bits, k;              // T has 2^t_bits elements; k vectors
+  int64_t vsrc[kOuterMax][2];     // g_i[m]: element offset | buffer << 56
+  double flops = 0, bytes = 0;    // per batch item, for kernel timing
+};
+
 struct StepProgram {
   int32_t kind;
   int32_t chain = -1;  // >= 0: first step of fused chain `chain`; -2: inside a chain (skipped)
+  int32_t outer = -1;  // >= 0: first step of outer-product run `outer` (run in one launch); -2: inside one
   SmallStep sm;
   std::vector<PermuteDesc> pre;  // operand permutes before the product
   SkinnyDesc sk;
@@ -374,6 +388,8 @@ struct tn_path {
   std::vector<int32_t> small_levels;         // level i owns steps small_levels[i] .. small_levels[i+1]-1
   std::vector<uint32_t> small_items;         // work items of every round (see SmallStep::item0)
   int64_t small_region = 0;                  // workspace elements reserved for their results
+  // runs of outer products written in one launch
+  std::vector<tnq::OuterChain> outers;
   // fused streaming chains
   std::vector<tnq::SweepChain> chains;
   std::vector<tnq::SweepPass> passes;

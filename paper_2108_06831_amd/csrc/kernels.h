@@ -35,6 +35,12 @@ hipError_t launch_q328_finish(hipStream_t s, const void* f, int64_t f_bs, float2
 hipError_t launch_skinny(hipStream_t s, const SkinnyDesc& d, const float2* g, int64_t g_bs, const float2* t,
                          int64_t t_bs, float2* c, int64_t c_bs, int batch, int precision);
 
+// A run of outer products with one-qubit vectors in one launch (see OuterChain);
+// the vectors' values are read from `in` or `ws` by their sources.
+hipError_t launch_outer_chain(hipStream_t s, const OuterChain& oc, const float2* t, int64_t t_bs, float2* c,
+                              int64_t c_bs, const float2* in, int64_t in_bs, const float2* ws, int64_t ws_bs,
+                              int batch);
+
 // Bit permutation of a 2^bits array: input bit p -> output bit dst[p].
 hipError_t launch_permute(hipStream_t s, const PermuteDesc& d, const float2* in, int64_t in_bs, float2* out,
                           int64_t out_bs, int batch);

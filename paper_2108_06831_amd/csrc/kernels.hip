@@ -404,6 +404,57 @@ __global__ __launch_bounds__(kThreads) void k_skinny(SkinnyArgs a) {
   }
 }
 
+// A run of outer products (see OuterChain): block (h, z) writes the 2^t_bits
+// elements of C whose vector bits are h, T times the block's factor
+// g_1[h_1] .. g_k[h_k].  The factor is formed in FP32 whatever the precision
+// of the products (each step has a single term: there is nothing to sum).
+struct OuterArgs {
+  const float2* t;
+  float2* c;
+  const float2* in;
+  const float2* ws;
+  int64_t t_bs, c_bs, in_bs, ws_bs;
+  int32_t t_bits, k;
+  int64_t vsrc[kOuterMax][2];
+};
+
+__global__ __launch_bounds__(kThreads) void k_outer_chain(OuterArgs a) {
+  const int z = blockIdx.y;
+  const int64_t h = blockIdx.x;
+  float2 f = f2(1.f, 0.f);
+  for (int i = 0; i < a.k; ++i) {
+    const int64_t v = a.vsrc[i][(h >> i) & 1];
+    const float2* b = ((v >> 56) & 0x3f) == BUF_IN ? a.in + (int64_t)z * a.in_bs : a.ws + (int64_t)z * a.ws_bs;
+    f = cmul<TN_PREC_C64>(f, b[v & (((int64_t)1 << 56) - 1)]);
+  }
+  // two elements per access (t_bits >= 8)
+  const float4* T = reinterpret_cast<const float4*>(a.t + (int64_t)z * a.t_bs);
+  float4* C = reinterpret_cast<float4*>(a.c + (int64_t)z * a.c_bs + (h << a.t_bits));
+  const int64_t n = (int64_t)1 << (a.t_bits - 1);
+  for (int64_t o = threadIdx.x; o < n; o += blockDim.x) {
+    const float4 x = T[o];
+    const float2 y0 = cmul<TN_PREC_C64>(f, f2(x.x, x.y)), y1 = cmul<TN_PREC_C64>(f, f2(x.z, x.w));
+    C[o] = make_float4(y0.x, y0.y, y1.x, y1.y);
+  }
+}
+
+hipError_t launch_outer_chain(hipStream_t s, const OuterChain& oc, const float2* t, int64_t t_bs, float2* c,
+                              int64_t c_bs, const float2* in, int64_t in_bs, const float2* ws, int64_t ws_bs,
+                              int batch) {
+  if (oc.k < 1 || oc.k > kOuterMax || oc.k > 24 || oc.t_bits < 8 || oc.t_bits > 40) return hipErrorInvalidValue;
+  if ((reinterpret_cast<uintptr_t>(t) | reinterpret_cast<uintptr_t>(c)) & 15) return hipErrorInvalidValue;
+  if (((t_bs | c_bs) & 1) != 0) return hipErrorInvalidValue;  // float4 accesses in every batch item
+  OuterArgs a;
+  a.t = t; a.c = c; a.in = in; a.ws = ws;
+  a.t_bs = t_bs; a.c_bs = c_bs; a.in_bs = in_bs; a.ws_bs = ws_bs;
+  a.t_bits = oc.t_bits;
+  a.k = oc.k;
+  for (int i = 0; i < kOuterMax; ++i)
+    for (int m = 0; m < 2; ++m) a.vsrc[i][m] = i < oc.k ? oc.vsrc[i][m] : 0;
+  hipLaunchKernelGGL(k_outer_chain, dim3(1u << oc.k, batch), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
 template <int NK, int NM>
 static void* skinny_fn(int prec) {
   return prec == TN_PREC_BF16X3 ? (void*)k_skinny<NK, NM, TN_PREC_BF16X3> : (void*)k_skinny<NK, NM, TN_PREC_C64>;

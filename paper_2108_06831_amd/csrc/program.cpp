@@ -452,6 +452,59 @@ std::vector<int32_t> output_layout(const tn_network* net) {
   return to;
 }
 
+// Runs of outer products with one-qubit vectors (see OuterChain), e.g. a
+// product state growing one qubit at a time before the gates act on it.
+void build_outer_chains(tn_path* path, int T) {
+  path->outers.clear();
+  const int S = (int)path->steps.size();
+  auto outer_step = [&](int s) {
+    const StepProgram& P = path->steps[s];
+    const SkinnyDesc& d = P.sk;
+    return P.kind == SK_SKINNY && P.chain == -1 && P.pre.empty() && d.nk == 0 && d.nm == 1 && d.nb == 0 &&
+           d.c_mode == 1 && d.mofs[0] == 0 && d.mofs[1] == ((int64_t)1 << d.t_bits);
+  };
+  for (int s = path->n_small; s < S;) {
+    if (!outer_step(s)) {
+      ++s;
+      continue;
+    }
+    int e = s + 1;
+    while (e < S && e - s < kOuterMax && outer_step(e)) {
+      // the next step must act on this step's result
+      const int ia = path->pairs[2 * e], ib = path->pairs[2 * e + 1];
+      if (ia != T + e - 1 && ib != T + e - 1) break;
+      const SkinnyDesc& q = path->steps[e].sk;
+      const SkinnyDesc& p = path->steps[e - 1].sk;
+      if (q.t.buf != p.c.buf || q.t.off != p.c.off || q.t_bits != p.t_bits + 1) break;
+      ++e;
+    }
+    const SkinnyDesc& first = path->steps[s].sk;
+    const SkinnyDesc& last = path->steps[e - 1].sk;
+    // the launch reads T while it writes C: they may not overlap; a block per value of the
+    // vector bits writes T's 2^t_bits elements, so T should not be tiny
+    const int64_t tn = (int64_t)1 << first.t_bits, cn = (int64_t)1 << (last.t_bits + 1);
+    const bool overlap = first.t.buf == last.c.buf && first.t.off < last.c.off + cn && last.c.off < first.t.off + tn;
+    if (e - s < 2 || overlap || first.t_bits < 8) {
+      s = e;
+      continue;
+    }
+    OuterChain oc;
+    oc.t = first.t;
+    oc.c = last.c;
+    oc.t_bits = first.t_bits;
+    oc.k = e - s;
+    oc.bytes = 8.0 * (double)(tn + cn);
+    for (int i = 0; i < oc.k; ++i) {
+      StepProgram& P = path->steps[s + i];
+      for (int m = 0; m < 2; ++m) oc.vsrc[i][m] = (P.sk.g.off + P.sk.gidx[m]) | ((int64_t)P.sk.g.buf << 56);
+      oc.flops += P.flops;
+      P.outer = i == 0 ? (int32_t)path->outers.size() : -2;
+    }
+    path->outers.push_back(oc);
+    s = e;
+  }
+}
+
 tn_status compile_program(const tn_network* net, tn_path* path, const std::vector<int32_t>* final_layout) {
   const int T = (int)net->tensors.size();
   const int S = (int)path->pairs.size() / 2;
@@ -1090,6 +1143,7 @@ tn_status compile_program(const tn_network* net, tn_path* path, const std::vecto
     }
   }
   build_chains(path, T);
+  build_outer_chains(path, T);
   st.n_product_launches = 0;
   for (int s = path->n_small, run0 = -1, run_len = 0; s < S; ++s) {
     const StepProgram& P = path->steps[s];

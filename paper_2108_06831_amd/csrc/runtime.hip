@@ -384,6 +384,29 @@ static tn_status run_steps_body(hipStream_t s, tn_path* path, const Bases& B, in
       }
       continue;
     }
+    if (P.outer >= 0 && !B.pair_a) {
+      // a run of outer products in one launch (its steps run one by one when T or C is not
+      // 16-byte aligned in every batch item)
+      const OuterChain& oc = path->outers[P.outer];
+      int64_t tbs, cbs, IN_bs, WS_bs;
+      const float2* t = resolve(B, oc.t, &tbs);
+      float2* c = resolve(B, oc.c, &cbs);
+      BufRef ri, rw;
+      ri.buf = BUF_IN;
+      rw.buf = BUF_WS;
+      const float2* INp = resolve(B, ri, &IN_bs);
+      const float2* WSp = resolve(B, rw, &WS_bs);
+      const bool aligned = t && c && ((reinterpret_cast<uintptr_t>(t) | reinterpret_cast<uintptr_t>(c)) & 15) == 0 &&
+                           (batch == 1 || ((tbs | cbs) & 1) == 0);
+      if (aligned) {
+        hipEvent_t ev = prof_start(s, TN_KERNEL_SKINNY);
+        HIP_TRY(launch_outer_chain(s, oc, t, batch == 1 ? 0 : tbs, c, batch == 1 ? 0 : cbs, INp, IN_bs, WSp, WS_bs,
+                                   batch));
+        prof_stop(s, ev, TN_KERNEL_SKINNY, oc.bytes * batch, oc.flops * batch);
+        si += oc.k - 1;
+        continue;
+      }
+    }
     for (const PermuteDesc& pd : P.pre) {
       int64_t ibs, obs;
       float2* ip = resolve(B, pd.in, &ibs);
