@@ -398,6 +398,10 @@ struct tn_path {
   std::vector<int64_t> sweep_val_src;        // gate values of the chains: element offset | (buffer << 56)
   // adjoint gradient passes over the final tensor (built on first use; adj_state 1: built, -1: not possible)
   int32_t adj_state = 0;
+  // the layout (labels, C order) the passes run in: the final tensor's, or the qubit order when
+  // that needs fewer passes (adj_perm = 1: the state is permuted into it first)
+  std::vector<int32_t> adj_bits;
+  int32_t adj_perm = 0;
   std::vector<tnq::SweepPass> adj_passes;
   std::vector<tnq::SweepSegment> adj_segments;
   std::vector<tnq::AdjGateDesc> adj_gates;

@@ -1206,23 +1206,45 @@ void build_adjoint_plan(const tn_network* net, tn_path* path, const std::vector<
   if (R < 18 || path->final_elems != ((int64_t)1 << R) || path->final_ref.buf != BUF_WS) return;
   const int G = (int)net->sweep.size();
   if ((int)slot_of_gate.size() != G) return;
+  // the passes' operations in a layout (-1: a gate the passes cannot take)
+  auto make_items = [&](const std::vector<int32_t>& bits, std::vector<PassItem>& items) {
+    items.clear();
+    for (int gi = G - 1; gi >= 0; --gi) {  // the reverse sweep undoes the gates last to first
+      const SweepGate& g = net->sweep[gi];
+      if (g.nq == 2 && !g.diag && g.gen != GEN_NONE) return false;
+      PassItem it;
+      it.diag = g.diag != 0;
+      it.grad = slot_of_gate[gi] >= 0;
+      const int p0 = pos_of(bits, net->wire_final[g.q[0]] * 64);
+      const int p1 = g.nq == 2 ? pos_of(bits, net->wire_final[g.q[1]] * 64) : 0;
+      if (p0 < 0 || p1 < 0) return false;
+      // bit 0 of the gate's own index is its second qubit (the first is the more significant)
+      if (g.nq == 2) it.pos = {p1, p0};
+      else it.pos = {p0};
+      items.push_back(it);
+    }
+    return true;
+  };
   std::vector<PassItem> items;
-  for (int gi = G - 1; gi >= 0; --gi) {  // the reverse sweep undoes the gates last to first
-    const SweepGate& g = net->sweep[gi];
-    if (g.nq == 2 && !g.diag && g.gen != GEN_NONE) return;
-    PassItem it;
-    it.diag = g.diag != 0;
-    it.grad = slot_of_gate[gi] >= 0;
-    const int p0 = pos_of(path->final_bits, net->wire_final[g.q[0]] * 64);
-    const int p1 = g.nq == 2 ? pos_of(path->final_bits, net->wire_final[g.q[1]] * 64) : 0;
-    if (p0 < 0 || p1 < 0) return;
-    // bit 0 of the gate's own index is its second qubit (the first is the more significant)
-    if (g.nq == 2) it.pos = {p1, p0};
-    else it.pos = {p0};
-    items.push_back(it);
-  }
   std::vector<PlannedPass> planned;
-  if (!plan_passes(R, items, planned, kAdjPreGates, kAdjMaxRed)) return;
+  if (!make_items(path->final_bits, items) || !plan_passes(R, items, planned, kAdjPreGates, kAdjMaxRed)) return;
+  path->adj_bits = path->final_bits;
+  path->adj_perm = 0;
+  // the qubit order (qubit 0 most significant) keeps neighbouring qubits on neighbouring bits, the
+  // layout a contraction leaves need not; take it when its light cones need fewer passes (one
+  // permute of the state costs about a pass's traffic on one state)
+  if (R == net->n_qubits) {
+    std::vector<int32_t> nat(R);
+    for (int q = 0; q < R; ++q) nat[q] = net->wire_final[q] * 64;
+    std::vector<PassItem> items2;
+    std::vector<PlannedPass> planned2;
+    if (nat != path->final_bits && make_items(nat, items2) &&
+        plan_passes(R, items2, planned2, kAdjPreGates, kAdjMaxRed) && planned2.size() < planned.size()) {
+      planned.swap(planned2);
+      path->adj_bits = nat;
+      path->adj_perm = 1;
+    }
+  }
   for (const PlannedPass& pp : planned) {
     SweepPass ps;
     ps.l = pp.l;

@@ -536,7 +536,9 @@ static tn_status finish_to(hipStream_t s, const float2* f, int64_t fbs, const tn
 static bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
 
 // map qubit masks to address-bit masks of the final tensor
-static tn_status make_terms(const tn_network* net, const tn_path* path, const tn_observable* obs, ZTerms* t) {
+// The observable's Z strings as address masks of a state in layout `bits` (labels, C order).
+static tn_status make_terms(const tn_network* net, const std::vector<int32_t>& bits, const tn_observable* obs,
+                            ZTerms* t) {
   if (!obs || obs->n_terms < 0 || (obs->n_terms > 0 && (!obs->z_mask || !obs->coeff)))
     return set_error(TN_EINVAL, "bad observable");
   if (obs->n_terms > kMaxTerms)
@@ -549,7 +551,7 @@ static tn_status make_terms(const tn_network* net, const tn_path* path, const tn
     if (n < 64 && (qm >> n) != 0) return set_error(TN_EINVAL, "observable mask names a qubit >= n_qubits");
     for (int q = 0; q < n; ++q)
       if ((qm >> (n - 1 - q)) & 1) {
-        const int p = pos_in(path->final_bits, lab(net->wire_final[q], 0));
+        const int p = pos_in(bits, lab(net->wire_final[q], 0));
         if (p < 0) return set_error(TN_EINVAL, "qubit leg missing from the final tensor");
         m |= (uint64_t)1 << p;
       }
@@ -1027,7 +1029,7 @@ extern "C" tn_status tn_expectation(void* stream, int32_t precision, tn_network*
     if (st != TN_OK) return set_error(st, "circuit " + std::to_string(c) + ": " + g_err);
     if (nets[c]->output_kind != TN_OUT_STATEVECTOR)
       return set_error(TN_EINVAL, "expectation needs a statevector network");
-    if ((st = make_terms(nets[c], paths[c], &obs[c], &all_terms[c])) != TN_OK) return st;
+    if ((st = make_terms(nets[c], paths[c]->final_bits, &obs[c], &all_terms[c])) != TN_OK) return st;
     if ((st = ensure_device(nets[c], &devs[c])) != TN_OK) return st;
     DevPath* dp;
     if ((st = ensure_path_device(paths[c], &dp)) != TN_OK) return st;
@@ -1162,8 +1164,15 @@ extern "C" tn_status tn_backward(void* stream, int32_t precision, tn_network* ne
   if (!workspace_dev || !value_dev || (net->n_params > 0 && !grad_dev)) return set_error(TN_EINVAL, "NULL buffer");
   const size_t need = tn_backward_workspace_bytes(net, path, batch);
   if (workspace_bytes < need) return set_error(TN_ENOMEM, "workspace too small: need " + std::to_string(need));
+  if (path->adj_state == 0) {
+    DevNet* d0;
+    if ((st = ensure_device(net, &d0)) != TN_OK) return st;
+    build_adjoint_plan(net, path, d0->slot_of_gate);
+  }
+  // the passes' layout: the final tensor's, or the qubit order (the state is permuted first)
+  const bool perm = path->adj_state == 1 && path->adj_perm;
   ZTerms terms;
-  if ((st = make_terms(net, path, obs, &terms)) != TN_OK) return st;
+  if ((st = make_terms(net, perm ? path->adj_bits : path->final_bits, obs, &terms)) != TN_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   DevNet* d;
   if ((st = ensure_device(net, &d)) != TN_OK) return st;
@@ -1182,15 +1191,31 @@ extern "C" tn_status tn_backward(void* stream, int32_t precision, tn_network* ne
   if (path->final_ref.buf != BUF_WS) return set_error(TN_EUNSUPPORTED, "backward of a network without contraction steps");
   const int64_t n = path->final_elems;
   double* partial = (double*)(w + L.base.aux_off);
-  HIP_TRY(launch_expectation(s, psi, pbs, n, terms, batch, partial, value_dev, 1));
   float2* lam = (float2*)(w + L.lam_off);
-  HIP_TRY(launch_apply_diag_obs(s, psi, pbs, lam, n, n, terms, batch));
+  int64_t lbs = n;
+  if (perm) {
+    // psi into the qubit order, in lambda's buffer; lambda then takes psi's
+    PermuteDesc pd;
+    pd.bits = (int32_t)path->final_bits.size();
+    for (int p = 0; p < pd.bits; ++p) {
+      const int32_t label = path->final_bits[pd.bits - 1 - p];
+      const int q = pos_in(path->adj_bits, label);
+      if (q < 0) return set_error(TN_EINVAL, "internal: adjoint layout misses a leg of the final tensor");
+      pd.dst[p] = q;
+    }
+    hipEvent_t ev = prof_start(s, TN_KERNEL_PERMUTE);
+    HIP_TRY(launch_permute(s, pd, psi, pbs, lam, n, batch));
+    prof_stop(s, ev, TN_KERNEL_PERMUTE, 16.0 * (double)n * batch, 0.0);
+    std::swap(psi, lam);
+    std::swap(pbs, lbs);
+  }
+  HIP_TRY(launch_expectation(s, psi, pbs, n, terms, batch, partial, value_dev, 1));
+  HIP_TRY(launch_apply_diag_obs(s, psi, pbs, lam, lbs, n, terms, batch));
   float2* umats = (float2*)(w + L.mats_off);
   HIP_TRY(launch_sweep_matrices(s, d->sweep_recipes, (int)net->sweep.size(), d->sweep_ops, d->mats, params_dev,
                                 net->n_params, batch, umats));
   double* parts = (double*)(w + L.part_off);
   const int64_t pstride = (int64_t)std::max(d->n_slots, 1) * kReduceBlocks;
-  if (path->adj_state == 0) build_adjoint_plan(net, path, d->slot_of_gate);
   if (path->adj_state == 1) {
     // fused passes: both states stream through LDS once per pass
     DevPath* dp;
@@ -1211,7 +1236,7 @@ extern "C" tn_status tn_backward(void* stream, int32_t precision, tn_network* ne
       }
       hipEvent_t ev = prof_start(s, TN_KERNEL_ADJOINT);
       HIP_TRY(launch_adjoint_pass(s, ps, bits, dp->adj_gates, dp->adj_segments, umats,
-                                  (int64_t)net->sweep.size() * 16, psi, pbs, lam, n, batch, parts, pstride,
+                                  (int64_t)net->sweep.size() * 16, psi, pbs, lam, lbs, batch, parts, pstride,
                                   precision));
       prof_stop(s, ev, TN_KERNEL_ADJOINT, 32.0 * (double)n * batch, fl * batch);
     }
@@ -1227,7 +1252,7 @@ extern "C" tn_status tn_backward(void* stream, int32_t precision, tn_network* ne
     if (a.pos[0] < 0 || a.pos[1] < 0 || (1ll << a.pos[0]) >= n || (1ll << a.pos[1]) >= n)
       return set_error(TN_EINVAL, "internal: qubit leg missing from the final tensor");
     hipEvent_t ev = prof_start(s, TN_KERNEL_ADJOINT);
-    HIP_TRY(launch_adjoint_step(s, a, umats + (int64_t)gi * 16, (int64_t)net->sweep.size() * 16, psi, pbs, lam, n,
+    HIP_TRY(launch_adjoint_step(s, a, umats + (int64_t)gi * 16, (int64_t)net->sweep.size() * 16, psi, pbs, lam, lbs,
                                 n, batch, parts, pstride, precision));
     const double per = 8.0 * (double)(1 << g.nq);  // dense U^dagger on both states, as in the fused passes
     prof_stop(s, ev, TN_KERNEL_ADJOINT, 32.0 * (double)n * batch,
