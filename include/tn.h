@@ -301,11 +301,11 @@ tn_status tn_amplitudes(void* stream, int32_t precision, tn_network* net, tn_pat
  * Sec. 2.2.1), and a diagonal D only weights |psi_x|^2 per basis state.
  *   nets/paths/obs: host arrays of n_circuits;
  *   params_dev: host array of n_circuits device pointers, each [batch][n_params_c] float64 (or NULL);
- *   workspace_dev: device, >= tn_expectation_workspace_bytes(...) (up to four circuits run at
- *     once, each in its own slot of the workspace);
+ *   workspace_dev: device, >= tn_expectation_workspace_bytes(...) (up to twelve circuits run
+ *     at once, each in its own slot of the workspace);
  *   out_dev: device float64[n_circuits][batch].
  * The circuits are independent: the library spreads them over the caller's
- * stream and up to three streams of its own, which wait for the caller's
+ * stream and up to eleven streams of its own, which wait for the caller's
  * stream at the start and which the caller's stream waits for at the end, so
  * the work is ordered on `stream` as one call (and a capture of `stream`
  * records all of it).  With kernel timing on (tn_profile_enable) every circuit
