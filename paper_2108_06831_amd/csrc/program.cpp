@@ -868,7 +868,21 @@ tn_status compile_program(const tn_network* net, tn_path* path, const std::vecto
         if (tile != kGemmVector && C.elems * kGemmMaxSplit <= ((int64_t)1 << 22) && g.K >= 64)
           g.max_split = kGemmMaxSplit;
       }
+      // a matrix-core tile stores each row of its result as 32 consecutive columns per wave:
+      // for a short sum the stores are the product's time, so take the orientation whose
+      // columns are the result's lowest address bits (the tuner may still choose otherwise)
       P.orient[0] = P.orient[1] = 0;
+      {
+        auto low_n = [](const GemmDesc& g) {
+          int c = 0;
+          while (c < g.nbn && c < 5 && g.c_n[c] == c) ++c;
+          return c;
+        };
+        for (int prec = 0; prec < 2; ++prec)
+          if (P.gm[0].K <= 32 && P.gm[0].tile[prec] != kGemmVector && P.gm[1].tile[prec] != kGemmVector &&
+              low_n(P.gm[1]) > low_n(P.gm[0]))
+            P.orient[prec] = 1;
+      }
       const int max_split = std::max(P.gm[0].max_split, P.gm[1].max_split);
       if (max_split > 1) {
         BufRef tmp;
