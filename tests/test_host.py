@@ -175,6 +175,21 @@ def test_config_plan_sizes():
     assert p4.stats["max_intermediate_elems"] >= 2 ** 20
 
 
+def test_gate_passes_are_planned_on_the_pass_workloads():
+    """The fused gate passes (paper Sec. 3's streaming of gates over a large
+    state) take the whole gate chains of the ansatz and of a 26-qubit QAOA
+    circuit: the pass planner checks its own reordering of diagonal gates
+    and would leave a chain to the per-step kernels if that check failed."""
+    circ, params, _ = workloads.config4()
+    p4 = Network.from_circuit(circ).plan("sequential")
+    assert p4.stats["n_sweep_passes"] == 8
+    assert p4.stats["n_sweep_steps"] >= 590
+    inst = [it for it in workloads.config3() if it.circuit.n_qubits == 26][0]
+    p3 = Network.from_circuit(inst.circuit).plan("sequential")
+    assert 9 <= p3.stats["n_sweep_passes"] <= 11
+    assert p3.stats["n_sweep_steps"] >= 280
+
+
 def test_invalid_inputs_are_rejected():
     c = workloads.Circuit(3, [workloads.Gate("CZ", (0, 1))])
     c.gates[0].qubits = (0, 0)
