@@ -420,3 +420,19 @@ def test_grouped_launches_random_grids(seed):
     got = amplitudes(net, path, bits).cpu().numpy()
     torch.cuda.synchronize()
     assert relerr(got, want) < C64_TOL
+
+
+@pytest.mark.parametrize("n,p,batch", [(18, 1, 1), (20, 2, 3)])
+def test_product_state_outer_runs(n, p, batch):
+    """|+> on every qubit, then QAOA layers (Sec. 3's circuits act on a
+    product state): along the sequential order the state first grows one
+    qubit at a time by outer products, which run as one launch; every
+    amplitude of every parameter vector against the oracle."""
+    rng = np.random.default_rng(500 + n)
+    edges = workloads.random_regular_graph(n, 3, rng)
+    circ = workloads.qaoa_circuit(n, edges, p)
+    params = rng.uniform(0.0, np.pi, size=(batch, 2 * p))
+    print(f"product-state circuit n={n} p={p} batch={batch}", flush=True)
+    got = statevector_gpu(circ, "sequential", params=params, batch=batch)
+    for b in range(batch):
+        assert relerr(got[b], oracle.statevector(circ, params[b])) < C64_TOL
