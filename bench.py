@@ -75,10 +75,11 @@ def host_description():
             "host_mem_gib": round(mem_kib / 2 ** 20, 1) if mem_kib else None}
 
 
-def stored_traffic(config, precision, kernel):
+def stored_traffic(config, precision, kernel, alg_bytes_per_launch):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summaries (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy's reading),
-    if they were taken on the current kernel source; else None."""
+    if they were taken on the current kernel source and on launches of the
+    same plan (the same algorithmic bytes per launch); else None."""
     import glob
     import hashlib
     src = hashlib.sha256(open(os.path.join(ROOT, "paper_2108_06831_amd", "csrc", "kernels.hip"), "rb").read())
@@ -89,7 +90,9 @@ def stored_traffic(config, precision, kernel):
                 continue
             kv = dict(x.split("=", 1) for x in line.split()[1:])
             if all(kv.get(k) == v for k, v in want.items()):
-                return float(kv["bytes_per_launch"])
+                alg = float(kv.get("alg_bytes_per_launch", "nan"))
+                if abs(alg - alg_bytes_per_launch) <= 1e-6 * alg_bytes_per_launch:
+                    return float(kv["bytes_per_launch"])
     return None
 
 
@@ -654,7 +657,7 @@ def main():
     value = wl.units_per_step / (ms * 1e-3)
 
     kind, rec = dominant, prof[dominant]
-    traffic = stored_traffic(args.config, args.precision, kind)
+    traffic = stored_traffic(args.config, args.precision, kind, rec["bytes"] / rec["launches"])
     if kind == "gemm":
         # BF16x3 needs three bf16 products per product term: its ceiling is a third of the bf16 peak
         peak = PEAK_FP32_MFMA_TFLOPS if args.precision == "c64" else PEAK_BF16_MFMA_TFLOPS / 3

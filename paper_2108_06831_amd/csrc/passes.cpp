@@ -19,7 +19,9 @@ bool plan_passes(int R, const std::vector<PassItem>& items, std::vector<PlannedP
                  int max_grads) {
   out.clear();
   if (R < 16 || max_items < 1 || max_grads < 1) return false;
-  const int lmax = std::min(kSweepMaxLocal, R - 8);  // >= 8, enough for the low bits plus two more
+  // Every pass takes the widest local set: passes on states of 2^16..2^19 elements are
+  // launch-bound, so fewer of them beat more blocks per pass.
+  const int lmax = std::min(kSweepMaxLocal, R - 4);
   const int low = 5;
   std::vector<char> done(items.size(), 0);
   size_t remaining = items.size();

@@ -188,6 +188,10 @@ def test_gate_passes_are_planned_on_the_pass_workloads():
     p3 = Network.from_circuit(inst.circuit).plan("sequential")
     assert 9 <= p3.stats["n_sweep_passes"] <= 11
     assert p3.stats["n_sweep_steps"] >= 280
+    # small states take the full 2^12-element chunk too: few, launch-bound passes
+    inst16 = [it for it in workloads.config3() if it.circuit.n_qubits == 16][0]
+    p16 = Network.from_circuit(inst16.circuit).plan("sequential")
+    assert p16.stats["n_sweep_passes"] <= 5
 
 
 def test_invalid_inputs_are_rejected():
