@@ -845,6 +845,31 @@ __device__ __forceinline__ void apply_dense1(float2 (&x)[16], float2 (&y)[16], c
 #undef TNQ_DENSE1
 }
 
+// Four dense one-qubit gates of one form on register bits 0, 1, 2 and 3, in
+// that order (gate r's values at g[4 r]), on x (NS = 1) or on x and y (NS =
+// 2): one straight-line run, where gate-by-gate dispatch would end every gate
+// with a copy of the elements back into the registers the loop carries them in.
+template <int PREC, int NS>
+__device__ __forceinline__ void apply_dense1_run4(float2 (&x)[16], float2 (&y)[16], const float2* g, int form) {
+#define TNQ_RUN4(F)                                         \
+  reg_apply1<PREC, 0, F>(x, g);                             \
+  if (NS == 2) reg_apply1<PREC, 0, F>(y, g);                \
+  reg_apply1<PREC, 1, F>(x, g + 4);                         \
+  if (NS == 2) reg_apply1<PREC, 1, F>(y, g + 4);            \
+  reg_apply1<PREC, 2, F>(x, g + 8);                         \
+  if (NS == 2) reg_apply1<PREC, 2, F>(y, g + 8);            \
+  reg_apply1<PREC, 3, F>(x, g + 12);                        \
+  if (NS == 2) reg_apply1<PREC, 3, F>(y, g + 12);           \
+  variant_end<PREC, 200 + NS * 4 + F>();                    \
+  break;
+  switch (PREC == TN_PREC_C64 ? form : kDenseGeneric) {
+    case kDenseReal: TNQ_RUN4(kDenseReal)
+    case kDenseRxLike: TNQ_RUN4(kDenseRxLike)
+    default: TNQ_RUN4(kDenseGeneric)
+  }
+#undef TNQ_RUN4
+}
+
 template <int PREC, int U0, int U1>
 __device__ __forceinline__ void reg_apply2(float2 (&x)[16], const float2* g) {
 #pragma unroll
@@ -1251,8 +1276,21 @@ __global__ __launch_bounds__(kThreads) void k_sweep_pass(SweepPassArgs a, const 
           apply_diag<PREC>(x, gd.n, k0, k1, cb, d0, d1, d2, d3);
         }
       } else if (gd.n == 1) {
-        const float2 g[4] = {V[0], V[1], V[2], V[3]};
         const int form = gd.form == kFormReal ? kDenseReal : gd.form == kFormRxLike ? kDenseRxLike : kDenseGeneric;
+        if (gd.run4) {  // this gate and the next three: register bits 0..3, one form
+          float2 g[16];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int vo = gates[gi + j].voff;
+            const float2* Vj = VL ? vtab + (vo - a.lds_off) : V0 + vo;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) g[4 * j + e] = Vj[e];
+          }
+          apply_dense1_run4<PREC, 1>(x, x, g, form);
+          gi += 3;
+          continue;
+        }
+        const float2 g[4] = {V[0], V[1], V[2], V[3]};
         apply_dense1<PREC, 1>(x, x, g, gd.rb[0], form);
       } else {
         float2 g[16];
@@ -2854,6 +2892,35 @@ __device__ __forceinline__ float wave_sum_to_63(float v) {
   return v;
 }
 
+// One gate of a run of four dense one-qubit gates in the reverse sweep (see
+// apply_dense1_run4): its gradient term from the states as they stand, then
+// U^dagger on register bit R of both states, R and U's form F fixed.
+template <int PREC, int R, int F, class AddGrad>
+__device__ __forceinline__ void adj_run_slot(float2 (&xp)[16], float2 (&xl)[16], const AdjGateDesc& gd,
+                                             const float2* Up, AddGrad& add_grad) {
+  if (gd.red >= 0) {
+    const float2* G = reinterpret_cast<const float2*>(gd.gen);
+    const float g = gd.form == ADJ_GEN_X ? reg_grad_x<R>(xp, xl, G[2].x)
+                    : gd.form == ADJ_GEN_Y ? reg_grad_y<R>(xp, xl)
+                                           : reg_grad1<R>(xp, xl, G);
+    add_grad(gd.red, g);
+  }
+  // U^dagger[m][k] = conj(U[k][m])
+  const float2 ud[4] = {f2(Up[0].x, -Up[0].y), f2(Up[2].x, -Up[2].y), f2(Up[1].x, -Up[1].y), f2(Up[3].x, -Up[3].y)};
+  reg_apply1<PREC, R, F>(xp, ud);
+  reg_apply1<PREC, R, F>(xl, ud);
+}
+
+template <int PREC, int F, class AddGrad>
+__device__ __forceinline__ void adj_run4(float2 (&xp)[16], float2 (&xl)[16], const AdjGateDesc* gd,
+                                         const float2 (*Up)[4], AddGrad& add_grad) {
+  adj_run_slot<PREC, 0, F>(xp, xl, gd[0], Up[0], add_grad);
+  adj_run_slot<PREC, 1, F>(xp, xl, gd[1], Up[1], add_grad);
+  adj_run_slot<PREC, 2, F>(xp, xl, gd[2], Up[2], add_grad);
+  adj_run_slot<PREC, 3, F>(xp, xl, gd[3], Up[3], add_grad);
+  variant_end<PREC, 220 + F>();
+}
+
 template <int PREC>
 __global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a, const AdjGateDesc* __restrict__ gates,
                                                             const SweepSegment* __restrict__ segs,
@@ -3025,6 +3092,17 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a, const 
           // unitary gates: the entries have unit modulus, so the first one joins the deferred phase
           apply_diag_unit<PREC, 2>(xp, xl, ph, gd.n, k[0], k[1], c, d0, d1, d2, d3);
         } else if (gd.n == 1) {
+          if (gd.run4) {  // this gate and the next three: register bits 0..3, one form of U
+            const int f = gd.uform == kFormReal ? kDenseReal : gd.uform == kFormRxLike ? kDenseRxLike : kDenseGeneric;
+            const float2(*Ur)[4] = upre + (gi - a.first_gate);
+            switch (PREC == TN_PREC_C64 ? f : kDenseGeneric) {
+              case kDenseReal: adj_run4<PREC, kDenseReal>(xp, xl, gates + gi, Ur, add_grad); break;
+              case kDenseRxLike: adj_run4<PREC, kDenseRxLike>(xp, xl, gates + gi, Ur, add_grad); break;
+              default: adj_run4<PREC, kDenseGeneric>(xp, xl, gates + gi, Ur, add_grad); break;
+            }
+            gi += 3;
+            continue;
+          }
           if (gd.red >= 0) {
             float g;
             if (gd.form == ADJ_GEN_X) {

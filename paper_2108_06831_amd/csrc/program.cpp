@@ -18,8 +18,6 @@
 #include <chrono>
 #include <cstdlib>
 #include <thread>
-#include <cstdio>
-#include <cstdlib>
 #include <cmath>
 #include <map>
 #include <set>
@@ -256,6 +254,66 @@ void fill_segment_tables(SweepSegment& seg, int l) {
 // streaming passes (light-cone rule: a gate joins the current pass if its bits
 // fit in the pass's local set and no earlier gate left out of the pass touches
 // them; gates on disjoint bits commute).
+
+// Runs of dense one-qubit gates for the pass kernels.  A dense one-qubit gate
+// on register bit r commutes with every gate that leaves bit r alone, so for
+// each such gate the first later gates of the same form on the other three
+// register bits, each reached without crossing a gate on its bit, move up
+// beside it; the four are put in register-bit order and the first is marked,
+// and the kernels apply them as one straight-line run.
+inline int run_form(const SweepGateDesc& d) { return d.form; }
+inline int run_form(const AdjGateDesc& d) { return d.uform; }  // the gradient's generator may differ
+inline bool group_header(const SweepGateDesc& d) { return d.diag && d.form == kFormCount; }
+inline bool group_header(const AdjGateDesc&) { return false; }
+
+template <class Desc>
+void mark_runs4(Desc* g, int n) {
+  // whether d acts on register bit r (a count group's header carries no bits: its members do)
+  auto touches = [](const Desc& d, int r) {
+    if (!d.diag) return d.rb[0] == r || (d.n == 2 && d.rb[1] == r);
+    if (group_header(d)) return false;
+    return d.kreg[0] == r || (d.n == 2 && d.kreg[1] == r);
+  };
+  const std::vector<Desc> v(g, g + n);
+  std::vector<char> used(n, 0);
+  int o = 0;
+  for (int i = 0; i < n; ++i) {
+    if (used[i]) continue;
+    const Desc& d = v[i];
+    if (!d.diag && d.n == 1 && d.rb[0] >= 0 && d.rb[0] < 4) {
+      int pick[4] = {-1, -1, -1, -1};
+      pick[d.rb[0]] = i;
+      bool ok = true;
+      for (int r = 0; r < 4 && ok; ++r) {
+        if (r == d.rb[0]) continue;
+        for (int j = i + 1; j < n; ++j) {
+          if (used[j]) continue;
+          const Desc& e = v[j];
+          if (!e.diag && e.n == 1 && e.rb[0] == r && run_form(e) == run_form(d)) {
+            pick[r] = j;
+            break;
+          }
+          if (touches(e, r)) break;
+        }
+        ok = pick[r] >= 0;
+      }
+      if (ok) {
+        for (int r = 0; r < 4; ++r) {
+          g[o] = v[pick[r]];
+          g[o].run4 = r == 0;
+          used[pick[r]] = 1;
+          ++o;
+        }
+        continue;
+      }
+    }
+    g[o] = v[i];
+    g[o].run4 = 0;
+    used[i] = 1;
+    ++o;
+  }
+}
+
 void build_chains(tn_path* path, int T) {
   path->chains.clear();
   path->passes.clear();
@@ -421,6 +479,7 @@ void build_chains(tn_path* path, int T) {
                                 return gd.diag && gd.form != kFormCount && gd.form != kFormCountMember &&
                                        gd.kreg[0] < 0 && (gd.n == 1 || gd.kreg[1] < 0);
                               });
+        mark_runs4(path->sweep_gates.data() + seg.first_gate, seg.n_gates);
         fill_segment_tables(seg, ps.l);
         path->segments.push_back(seg);
       }
@@ -1346,6 +1405,7 @@ void build_adjoint_plan(const tn_network* net, tn_path* path, const std::vector<
                             path->adj_gates.begin() + seg.first_gate + seg.n_gates, [](const AdjGateDesc& gd) {
                               return gd.diag && gd.kreg[0] < 0 && (gd.n == 1 || gd.kreg[1] < 0);
                             });
+      mark_runs4(path->adj_gates.data() + seg.first_gate, seg.n_gates);
       fill_segment_tables(seg, ps.l);
       path->adj_segments.push_back(seg);
     }
