@@ -50,7 +50,7 @@ class tn_path_stats(ctypes.Structure):
                 ("n_skinny_steps", ctypes.c_int32), ("n_small_steps", ctypes.c_int32),
                 ("n_small_lists", ctypes.c_int32), ("n_sweep_steps", ctypes.c_int32),
                 ("n_sweep_passes", ctypes.c_int32), ("n_product_launches", ctypes.c_int32),
-                ("n_slice_bits", ctypes.c_int32)]
+                ("n_slice_bits", ctypes.c_int32), ("n_sweep_gate_runs", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

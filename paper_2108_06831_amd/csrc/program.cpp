@@ -1237,6 +1237,8 @@ tn_status compile_program(const tn_network* net, tn_path* path, const std::vecto
     st.n_sweep_steps += ch.n_steps;
     st.n_sweep_passes += ch.n_passes;
   }
+  st.n_sweep_gate_runs = 0;
+  for (const SweepGateDesc& gd : path->sweep_gates) st.n_sweep_gate_runs += gd.run4;
   st.n_small_steps = path->n_small;
   st.n_small_lists = path->small_lists.empty() ? 0 : (int32_t)path->small_lists.size() - 1;
   const int last = S > 0 ? T + S - 1 : 0;

@@ -184,10 +184,13 @@ def test_gate_passes_are_planned_on_the_pass_workloads():
     p4 = Network.from_circuit(circ).plan("sequential")
     assert p4.stats["n_sweep_passes"] == 8
     assert p4.stats["n_sweep_steps"] >= 590
+    # most dense one-qubit gates (RY on every qubit of every layer) run four at a time
+    assert p4.stats["n_sweep_gate_runs"] >= 25
     inst = [it for it in workloads.config3() if it.circuit.n_qubits == 26][0]
     p3 = Network.from_circuit(inst.circuit).plan("sequential")
     assert 9 <= p3.stats["n_sweep_passes"] <= 11
     assert p3.stats["n_sweep_steps"] >= 280
+    assert p3.stats["n_sweep_gate_runs"] >= 18   # the mixers' RX gates
     # small states take the full 2^12-element chunk too: few, launch-bound passes
     inst16 = [it for it in workloads.config3() if it.circuit.n_qubits == 16][0]
     p16 = Network.from_circuit(inst16.circuit).plan("sequential")
