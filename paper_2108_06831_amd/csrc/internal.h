@@ -143,9 +143,10 @@ struct SweepGateDesc {
   // diagonal gates, resolved for the gate's segment: bit j of the index is register bit kreg[j]
   // (>= 0), else the thread's local bit csrc[j] (0..l-1) or the chunk base's address bit csrc[j] - 64
   int32_t kreg[2], csrc[2];
-  // dense one-qubit gates: 1 on the first of four consecutive gates of one form on register bits
-  // 0, 1, 2 and 3 in that order, which the kernel applies as one straight-line run
-  int32_t run4 = 0;
+  // dense one-qubit gates: on the first of two to four consecutive gates of one form on distinct
+  // register bits, in increasing bit order, the mask of those bits (0: no run); the kernels apply
+  // the run as straight-line code
+  int32_t run_mask = 0;
 };
 // Inside a pass, gates run in segments: a segment names four local bits
 // (`rbits`, indices into lpos) that each thread holds in registers (16
@@ -190,7 +191,7 @@ struct AdjGateDesc {
   float gen[8];     // generator G: dense 2x2 row-major, or diagonal entries (complex, re/im interleaved)
   int32_t uform;    // dense one-qubit gates: GateForm of U (kFormReal, kFormRxLike or kFormGeneric)
   int32_t kreg[2], csrc[2];  // diagonal gates, resolved for the gate's segment as in SweepGateDesc
-  int32_t run4 = 0;          // as in SweepGateDesc (the four share uform)
+  int32_t run_mask = 0;      // as in SweepGateDesc (the run's gates share uform)
 };
 // dense one-qubit generators c X or Y, real diagonal generators, diagonal
 // gates whose entries are all +1 or -1 (applied as sign flips; bit b of

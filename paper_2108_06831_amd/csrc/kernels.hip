@@ -845,29 +845,51 @@ __device__ __forceinline__ void apply_dense1(float2 (&x)[16], float2 (&y)[16], c
 #undef TNQ_DENSE1
 }
 
-// Four dense one-qubit gates of one form on register bits 0, 1, 2 and 3, in
-// that order (gate r's values at g[4 r]), on x (NS = 1) or on x and y (NS =
-// 2): one straight-line run, where gate-by-gate dispatch would end every gate
-// with a copy of the elements back into the registers the loop carries them in.
-template <int PREC, int NS>
-__device__ __forceinline__ void apply_dense1_run4(float2 (&x)[16], float2 (&y)[16], const float2* g, int form) {
-#define TNQ_RUN4(F)                                         \
-  reg_apply1<PREC, 0, F>(x, g);                             \
-  if (NS == 2) reg_apply1<PREC, 0, F>(y, g);                \
-  reg_apply1<PREC, 1, F>(x, g + 4);                         \
-  if (NS == 2) reg_apply1<PREC, 1, F>(y, g + 4);            \
-  reg_apply1<PREC, 2, F>(x, g + 8);                         \
-  if (NS == 2) reg_apply1<PREC, 2, F>(y, g + 8);            \
-  reg_apply1<PREC, 3, F>(x, g + 12);                        \
-  if (NS == 2) reg_apply1<PREC, 3, F>(y, g + 12);           \
-  variant_end<PREC, 200 + NS * 4 + F>();                    \
-  break;
-  switch (PREC == TN_PREC_C64 ? form : kDenseGeneric) {
-    case kDenseReal: TNQ_RUN4(kDenseReal)
-    case kDenseRxLike: TNQ_RUN4(kDenseRxLike)
-    default: TNQ_RUN4(kDenseGeneric)
+// A run of two to four dense one-qubit gates of one form on the register bits
+// of mask M, in increasing bit order (the k-th gate's values at gp[k]), on x
+// (NS = 1) or on x and y (NS = 2): straight-line code, where gate-by-gate
+// dispatch would end every gate with a copy of the elements back into the
+// registers the loop carries them in.
+template <int PREC, int NS, int M, int F>
+__device__ __forceinline__ void run_apply(float2 (&x)[16], float2 (&y)[16], const float2* const (&gp)[4]) {
+  int k = 0;
+  if constexpr ((M & 1) != 0) {
+    reg_apply1<PREC, 0, F>(x, gp[k]);
+    if (NS == 2) reg_apply1<PREC, 0, F>(y, gp[k]);
+    ++k;
   }
-#undef TNQ_RUN4
+  if constexpr ((M & 2) != 0) {
+    reg_apply1<PREC, 1, F>(x, gp[k]);
+    if (NS == 2) reg_apply1<PREC, 1, F>(y, gp[k]);
+    ++k;
+  }
+  if constexpr ((M & 4) != 0) {
+    reg_apply1<PREC, 2, F>(x, gp[k]);
+    if (NS == 2) reg_apply1<PREC, 2, F>(y, gp[k]);
+    ++k;
+  }
+  if constexpr ((M & 8) != 0) {
+    reg_apply1<PREC, 3, F>(x, gp[k]);
+    if (NS == 2) reg_apply1<PREC, 3, F>(y, gp[k]);
+  }
+  variant_end<PREC, 200 + M * 8 + NS * 4 + F>();
+}
+
+template <int PREC, int NS>
+__device__ __forceinline__ void apply_dense1_run(float2 (&x)[16], float2 (&y)[16], const float2* const (&g)[4],
+                                                 int mask, int form) {
+#define TNQ_RUN(M)                                                   \
+  case M * 3 + kDenseGeneric: run_apply<PREC, NS, M, kDenseGeneric>(x, y, g); break; \
+  case M * 3 + kDenseReal: run_apply<PREC, NS, M, kDenseReal>(x, y, g); break;       \
+  case M * 3 + kDenseRxLike: run_apply<PREC, NS, M, kDenseRxLike>(x, y, g); break;
+  switch (mask * 3 + (PREC == TN_PREC_C64 ? form : kDenseGeneric)) {
+    TNQ_RUN(3) TNQ_RUN(5) TNQ_RUN(6) TNQ_RUN(7) TNQ_RUN(9) TNQ_RUN(10) TNQ_RUN(11) TNQ_RUN(12) TNQ_RUN(13)
+    TNQ_RUN(14)
+    default: run_apply<PREC, NS, 15, kDenseGeneric>(x, y, g); break;  // mask 15, generic form
+    case 15 * 3 + kDenseReal: run_apply<PREC, NS, 15, kDenseReal>(x, y, g); break;
+    case 15 * 3 + kDenseRxLike: run_apply<PREC, NS, 15, kDenseRxLike>(x, y, g); break;
+  }
+#undef TNQ_RUN
 }
 
 template <int PREC, int U0, int U1>
@@ -1277,17 +1299,16 @@ __global__ __launch_bounds__(kThreads) void k_sweep_pass(SweepPassArgs a, const 
         }
       } else if (gd.n == 1) {
         const int form = gd.form == kFormReal ? kDenseReal : gd.form == kFormRxLike ? kDenseRxLike : kDenseGeneric;
-        if (gd.run4) {  // this gate and the next three: register bits 0..3, one form
-          float2 g[16];
+        if (gd.run_mask) {  // this gate and the next ones: one per bit of the mask, one form
+          const int cnt = __builtin_popcount(gd.run_mask);
+          const float2* gp[4];
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
-            const int vo = gates[gi + j].voff;
-            const float2* Vj = VL ? vtab + (vo - a.lds_off) : V0 + vo;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) g[4 * j + e] = Vj[e];
+            const int vo = j < cnt ? gates[gi + j].voff : gd.voff;
+            gp[j] = VL ? vtab + (vo - a.lds_off) : V0 + vo;
           }
-          apply_dense1_run4<PREC, 1>(x, x, g, form);
-          gi += 3;
+          apply_dense1_run<PREC, 1>(x, x, gp, gd.run_mask, form);
+          gi += cnt - 1;
           continue;
         }
         const float2 g[4] = {V[0], V[1], V[2], V[3]};
@@ -2892,8 +2913,8 @@ __device__ __forceinline__ float wave_sum_to_63(float v) {
   return v;
 }
 
-// One gate of a run of four dense one-qubit gates in the reverse sweep (see
-// apply_dense1_run4): its gradient term from the states as they stand, then
+// One gate of a run of dense one-qubit gates in the reverse sweep (see
+// run_apply): its gradient term from the states as they stand, then
 // U^dagger on register bit R of both states, R and U's form F fixed.
 template <int PREC, int R, int F, class AddGrad>
 __device__ __forceinline__ void adj_run_slot(float2 (&xp)[16], float2 (&xl)[16], const AdjGateDesc& gd,
@@ -2911,14 +2932,33 @@ __device__ __forceinline__ void adj_run_slot(float2 (&xp)[16], float2 (&xl)[16],
   reg_apply1<PREC, R, F>(xl, ud);
 }
 
-template <int PREC, int F, class AddGrad>
-__device__ __forceinline__ void adj_run4(float2 (&xp)[16], float2 (&xl)[16], const AdjGateDesc* gd,
-                                         const float2 (*Up)[4], AddGrad& add_grad) {
-  adj_run_slot<PREC, 0, F>(xp, xl, gd[0], Up[0], add_grad);
-  adj_run_slot<PREC, 1, F>(xp, xl, gd[1], Up[1], add_grad);
-  adj_run_slot<PREC, 2, F>(xp, xl, gd[2], Up[2], add_grad);
-  adj_run_slot<PREC, 3, F>(xp, xl, gd[3], Up[3], add_grad);
-  variant_end<PREC, 220 + F>();
+// The run of mask M: its k-th gate (descriptor gd[k], U entries Up[k]) on the k-th bit of M.
+template <int PREC, int M, int F, class AddGrad>
+__device__ __forceinline__ void adj_run(float2 (&xp)[16], float2 (&xl)[16], const AdjGateDesc* gd,
+                                        const float2 (*Up)[4], AddGrad& add_grad) {
+  int k = 0;
+  if constexpr ((M & 1) != 0) { adj_run_slot<PREC, 0, F>(xp, xl, gd[k], Up[k], add_grad); ++k; }
+  if constexpr ((M & 2) != 0) { adj_run_slot<PREC, 1, F>(xp, xl, gd[k], Up[k], add_grad); ++k; }
+  if constexpr ((M & 4) != 0) { adj_run_slot<PREC, 2, F>(xp, xl, gd[k], Up[k], add_grad); ++k; }
+  if constexpr ((M & 8) != 0) adj_run_slot<PREC, 3, F>(xp, xl, gd[k], Up[k], add_grad);
+  variant_end<PREC, 400 + M * 4 + F>();
+}
+
+template <int PREC, class AddGrad>
+__device__ __forceinline__ void adj_apply_run(float2 (&xp)[16], float2 (&xl)[16], const AdjGateDesc* gd,
+                                              const float2 (*Up)[4], AddGrad& add_grad, int mask, int form) {
+#define TNQ_ADJ_RUN(M)                                                                              \
+  case M * 3 + kDenseGeneric: adj_run<PREC, M, kDenseGeneric>(xp, xl, gd, Up, add_grad); break; \
+  case M * 3 + kDenseReal: adj_run<PREC, M, kDenseReal>(xp, xl, gd, Up, add_grad); break;       \
+  case M * 3 + kDenseRxLike: adj_run<PREC, M, kDenseRxLike>(xp, xl, gd, Up, add_grad); break;
+  switch (mask * 3 + (PREC == TN_PREC_C64 ? form : kDenseGeneric)) {
+    TNQ_ADJ_RUN(3) TNQ_ADJ_RUN(5) TNQ_ADJ_RUN(6) TNQ_ADJ_RUN(7) TNQ_ADJ_RUN(9) TNQ_ADJ_RUN(10) TNQ_ADJ_RUN(11)
+    TNQ_ADJ_RUN(12) TNQ_ADJ_RUN(13) TNQ_ADJ_RUN(14)
+    default: adj_run<PREC, 15, kDenseGeneric>(xp, xl, gd, Up, add_grad); break;  // mask 15, generic form
+    case 15 * 3 + kDenseReal: adj_run<PREC, 15, kDenseReal>(xp, xl, gd, Up, add_grad); break;
+    case 15 * 3 + kDenseRxLike: adj_run<PREC, 15, kDenseRxLike>(xp, xl, gd, Up, add_grad); break;
+  }
+#undef TNQ_ADJ_RUN
 }
 
 template <int PREC>
@@ -3092,15 +3132,10 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a, const 
           // unitary gates: the entries have unit modulus, so the first one joins the deferred phase
           apply_diag_unit<PREC, 2>(xp, xl, ph, gd.n, k[0], k[1], c, d0, d1, d2, d3);
         } else if (gd.n == 1) {
-          if (gd.run4) {  // this gate and the next three: register bits 0..3, one form of U
+          if (gd.run_mask) {  // this gate and the next ones: one per bit of the mask, one form of U
             const int f = gd.uform == kFormReal ? kDenseReal : gd.uform == kFormRxLike ? kDenseRxLike : kDenseGeneric;
-            const float2(*Ur)[4] = upre + (gi - a.first_gate);
-            switch (PREC == TN_PREC_C64 ? f : kDenseGeneric) {
-              case kDenseReal: adj_run4<PREC, kDenseReal>(xp, xl, gates + gi, Ur, add_grad); break;
-              case kDenseRxLike: adj_run4<PREC, kDenseRxLike>(xp, xl, gates + gi, Ur, add_grad); break;
-              default: adj_run4<PREC, kDenseGeneric>(xp, xl, gates + gi, Ur, add_grad); break;
-            }
-            gi += 3;
+            adj_apply_run<PREC>(xp, xl, gates + gi, upre + (gi - a.first_gate), add_grad, gd.run_mask, f);
+            gi += __builtin_popcount(gd.run_mask) - 1;
             continue;
           }
           if (gd.red >= 0) {

@@ -259,15 +259,16 @@ void fill_segment_tables(SweepSegment& seg, int l) {
 // on register bit r commutes with every gate that leaves bit r alone, so for
 // each such gate the first later gates of the same form on the other three
 // register bits, each reached without crossing a gate on its bit, move up
-// beside it; the four are put in register-bit order and the first is marked,
-// and the kernels apply them as one straight-line run.
+// beside it; when there are two to four of them they are put in register-bit
+// order, the first carries the mask of their bits, and the kernels apply them
+// as one straight-line run.
 inline int run_form(const SweepGateDesc& d) { return d.form; }
 inline int run_form(const AdjGateDesc& d) { return d.uform; }  // the gradient's generator may differ
 inline bool group_header(const SweepGateDesc& d) { return d.diag && d.form == kFormCount; }
 inline bool group_header(const AdjGateDesc&) { return false; }
 
 template <class Desc>
-void mark_runs4(Desc* g, int n) {
+void mark_runs(Desc* g, int n) {
   // whether d acts on register bit r (a count group's header carries no bits: its members do)
   auto touches = [](const Desc& d, int r) {
     if (!d.diag) return d.rb[0] == r || (d.n == 2 && d.rb[1] == r);
@@ -283,24 +284,27 @@ void mark_runs4(Desc* g, int n) {
     if (!d.diag && d.n == 1 && d.rb[0] >= 0 && d.rb[0] < 4) {
       int pick[4] = {-1, -1, -1, -1};
       pick[d.rb[0]] = i;
-      bool ok = true;
-      for (int r = 0; r < 4 && ok; ++r) {
+      int mask = 1 << d.rb[0];
+      for (int r = 0; r < 4; ++r) {
         if (r == d.rb[0]) continue;
         for (int j = i + 1; j < n; ++j) {
           if (used[j]) continue;
           const Desc& e = v[j];
           if (!e.diag && e.n == 1 && e.rb[0] == r && run_form(e) == run_form(d)) {
             pick[r] = j;
+            mask |= 1 << r;
             break;
           }
           if (touches(e, r)) break;
         }
-        ok = pick[r] >= 0;
       }
-      if (ok) {
+      if (mask != (1 << d.rb[0])) {
+        bool first = true;
         for (int r = 0; r < 4; ++r) {
+          if (pick[r] < 0) continue;
           g[o] = v[pick[r]];
-          g[o].run4 = r == 0;
+          g[o].run_mask = first ? mask : 0;
+          first = false;
           used[pick[r]] = 1;
           ++o;
         }
@@ -308,7 +312,7 @@ void mark_runs4(Desc* g, int n) {
       }
     }
     g[o] = v[i];
-    g[o].run4 = 0;
+    g[o].run_mask = 0;
     used[i] = 1;
     ++o;
   }
@@ -479,7 +483,7 @@ void build_chains(tn_path* path, int T) {
                                 return gd.diag && gd.form != kFormCount && gd.form != kFormCountMember &&
                                        gd.kreg[0] < 0 && (gd.n == 1 || gd.kreg[1] < 0);
                               });
-        mark_runs4(path->sweep_gates.data() + seg.first_gate, seg.n_gates);
+        mark_runs(path->sweep_gates.data() + seg.first_gate, seg.n_gates);
         fill_segment_tables(seg, ps.l);
         path->segments.push_back(seg);
       }
@@ -1238,7 +1242,7 @@ tn_status compile_program(const tn_network* net, tn_path* path, const std::vecto
     st.n_sweep_passes += ch.n_passes;
   }
   st.n_sweep_gate_runs = 0;
-  for (const SweepGateDesc& gd : path->sweep_gates) st.n_sweep_gate_runs += gd.run4;
+  for (const SweepGateDesc& gd : path->sweep_gates) st.n_sweep_gate_runs += gd.run_mask != 0;
   st.n_small_steps = path->n_small;
   st.n_small_lists = path->small_lists.empty() ? 0 : (int32_t)path->small_lists.size() - 1;
   const int last = S > 0 ? T + S - 1 : 0;
@@ -1407,7 +1411,7 @@ void build_adjoint_plan(const tn_network* net, tn_path* path, const std::vector<
                             path->adj_gates.begin() + seg.first_gate + seg.n_gates, [](const AdjGateDesc& gd) {
                               return gd.diag && gd.kreg[0] < 0 && (gd.n == 1 || gd.kreg[1] < 0);
                             });
-      mark_runs4(path->adj_gates.data() + seg.first_gate, seg.n_gates);
+      mark_runs(path->adj_gates.data() + seg.first_gate, seg.n_gates);
       fill_segment_tables(seg, ps.l);
       path->adj_segments.push_back(seg);
     }
