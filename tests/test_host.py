@@ -184,7 +184,7 @@ def test_gate_passes_are_planned_on_the_pass_workloads():
     p4 = Network.from_circuit(circ).plan("sequential")
     assert p4.stats["n_sweep_passes"] == 8
     assert p4.stats["n_sweep_steps"] >= 590
-    # most dense one-qubit gates (RY on every qubit of every layer) run four at a time
+    # most dense one-qubit gates (RY on every qubit of every layer) run in straight-line runs
     assert p4.stats["n_sweep_gate_runs"] >= 25
     inst = [it for it in workloads.config3() if it.circuit.n_qubits == 26][0]
     p3 = Network.from_circuit(inst.circuit).plan("sequential")
