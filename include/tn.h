@@ -156,9 +156,9 @@ typedef struct {
                                     that follow each other share a launch */
   int32_t n_slice_bits;          /* address bits of the sliced bond indices: 2^n_slice_bits slices (0: none);
                                     flops, bytes and max_intermediate_elems are per slice */
-  int32_t n_sweep_gate_runs;     /* runs of two to four dense one-qubit gates on distinct register bits of a
-                                    segment that the fused passes apply as straight-line code (each run's
-                                    gates are among the n_sweep_steps) */
+  int32_t n_sweep_gate_runs;     /* runs of two to four gates on distinct register bits of a segment (dense
+                                    one-qubit gates of one form, or one-bit unit diagonals) that the fused
+                                    passes apply as straight-line code (their gates are among n_sweep_steps) */
 } tn_path_stats;
 
 typedef struct tn_network tn_network;

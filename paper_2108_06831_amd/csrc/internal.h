@@ -143,9 +143,10 @@ struct SweepGateDesc {
   // diagonal gates, resolved for the gate's segment: bit j of the index is register bit kreg[j]
   // (>= 0), else the thread's local bit csrc[j] (0..l-1) or the chunk base's address bit csrc[j] - 64
   int32_t kreg[2], csrc[2];
-  // dense one-qubit gates: on the first of two to four consecutive gates of one form on distinct
-  // register bits, in increasing bit order, the mask of those bits (0: no run); the kernels apply
-  // the run as straight-line code
+  // on the first of two to four consecutive gates on distinct register bits, in increasing bit
+  // order, the mask of those bits (0: no run); the kernels apply the run as straight-line code.
+  // The gates of a run are all dense one-qubit gates of one form, or all one-bit diagonal gates
+  // with unit-modulus entries
   int32_t run_mask = 0;
 };
 // Inside a pass, gates run in segments: a segment names four local bits

@@ -1068,6 +1068,37 @@ __device__ __forceinline__ void apply_diag_unit(float2 (&x)[16], float2 (&y)[16]
   }
 }
 
+// A run of one-bit unit diagonal gates on the register bits of mask M, in
+// increasing bit order, each already split as in apply_diag_unit (its first
+// entry joined the deferred phase; q[k]: the k-th gate's second entry relative
+// to its first): straight-line code, without the gate loop's copy per gate.
+template <int PREC, int NS, int M>
+__device__ __forceinline__ void diag_run_m(float2 (&x)[16], float2 (&y)[16], const float2 (&q)[4]) {
+  int k = 0;
+  if constexpr ((M & 1) != 0) diag_reg1_rel<PREC, NS, 0>(x, y, q[k++]);
+  if constexpr ((M & 2) != 0) diag_reg1_rel<PREC, NS, 1>(x, y, q[k++]);
+  if constexpr ((M & 4) != 0) diag_reg1_rel<PREC, NS, 2>(x, y, q[k++]);
+  if constexpr ((M & 8) != 0) diag_reg1_rel<PREC, NS, 3>(x, y, q[k]);
+  variant_end<PREC, 500 + NS * 16 + M>();
+}
+
+template <int PREC, int NS>
+__device__ __forceinline__ void diag_run(float2 (&x)[16], float2 (&y)[16], const float2 (&q)[4], int mask) {
+  switch (mask) {
+    case 3: diag_run_m<PREC, NS, 3>(x, y, q); break;
+    case 5: diag_run_m<PREC, NS, 5>(x, y, q); break;
+    case 6: diag_run_m<PREC, NS, 6>(x, y, q); break;
+    case 7: diag_run_m<PREC, NS, 7>(x, y, q); break;
+    case 9: diag_run_m<PREC, NS, 9>(x, y, q); break;
+    case 10: diag_run_m<PREC, NS, 10>(x, y, q); break;
+    case 11: diag_run_m<PREC, NS, 11>(x, y, q); break;
+    case 12: diag_run_m<PREC, NS, 12>(x, y, q); break;
+    case 13: diag_run_m<PREC, NS, 13>(x, y, q); break;
+    case 14: diag_run_m<PREC, NS, 14>(x, y, q); break;
+    default: diag_run_m<PREC, NS, 15>(x, y, q); break;
+  }
+}
+
 // Sign mask of a diagonal whose used entries are all +1 or -1 (CZ, Z), or -1.
 __device__ __forceinline__ int sign_mask(int n, float2 d0, float2 d1, float2 d2, float2 d3) {
   auto pm1 = [](float2 d) { return d.y == 0.f && fabsf(d.x) == 1.f; };
@@ -1265,6 +1296,22 @@ __global__ __launch_bounds__(kThreads) void k_sweep_pass(SweepPassArgs a, const 
       if (gd.form == kFormCount) {
         apply_count_group<PREC>(x, gates + gi + 1, gd.n, ob, base, ctab + gd.voff);
         gi += gd.n;
+        continue;
+      }
+      if (gd.diag && gd.run_mask) {  // one-bit unit diagonals on the mask's register bits, in bit order
+        const int cnt = __builtin_popcount(gd.run_mask);
+        float2 q[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int vo = j < cnt ? gates[gi + j].voff : gd.voff;
+          const float2* Vj = VL ? vtab + (vo - a.lds_off) : V0 + vo;
+          const float2 e0 = Vj[0], e1 = Vj[1];
+          if (j < cnt) ph = cmul<TN_PREC_C64>(ph, e0);
+          q[j] = cmul<TN_PREC_C64>(e1, f2(e0.x, -e0.y));
+        }
+        ph_used = true;
+        diag_run<PREC, 1>(x, x, q, gd.run_mask);
+        gi += cnt - 1;
         continue;
       }
       if (gd.diag) {
@@ -3076,6 +3123,49 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a, const 
         const float2* G = reinterpret_cast<const float2*>(gd.gen);
         const float2* Up = upre[gi - a.first_gate];
         if (!gd.diag) have_t = false;
+        if (gd.diag && gd.run_mask) {  // one-bit unit diagonals on the mask's register bits, in bit order
+          const int cnt = __builtin_popcount(gd.run_mask);
+          // their gradient terms: a unit diagonal applied to both states leaves Im(conj(l) p)
+          // unchanged, so the whole run shares one set of sums
+          bool any_red = false;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) any_red |= j < cnt && gates[gi + j].red >= 0;
+          if (any_red && !have_t) {
+            tT = tS0 = tS1 = tS2 = tS3 = 0.f;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              const float t = im_conj_mul(xl[r], xp[r]);
+              tT += t;
+              if (r & 1) tS0 += t;
+              if (r & 2) tS1 += t;
+              if (r & 4) tS2 += t;
+              if (r & 8) tS3 += t;
+            }
+            have_t = true;
+          }
+          float2 q[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            q[j] = f2(1.f, 0.f);
+            if (j >= cnt) continue;
+            const AdjGateDesc& gj = gates[gi + j];  // the run's gates are in register-bit order
+            if (gj.red >= 0) {
+              const float2* Gj = reinterpret_cast<const float2*>(gj.gen);
+              const int b = gj.kreg[0];
+              const float s1 = b == 0 ? tS0 : b == 1 ? tS1 : b == 2 ? tS2 : tS3;
+              add_grad(gj.red, Gj[0].x * (tT - s1) + Gj[1].x * s1);
+            }
+            // U^dagger: conj of the entries; the first joins the deferred phase
+            const float2* Uj = upre[gi + j - a.first_gate];
+            const float2 e0 = f2(Uj[0].x, -Uj[0].y), e1 = f2(Uj[1].x, -Uj[1].y);
+            ph = cmul<TN_PREC_C64>(ph, e0);
+            q[j] = cmul<TN_PREC_C64>(e1, f2(e0.x, -e0.y));
+          }
+          ph_used = true;
+          diag_run<PREC, 2>(xp, xl, q, gd.run_mask);
+          gi += cnt - 1;
+          continue;
+        }
         if (gd.diag) {
           const int k[2] = {gd.kreg[0], gd.n == 2 ? gd.kreg[1] : -1};
           int c = 0;  // the index bits that are constant over the thread's elements

@@ -267,6 +267,60 @@ inline int run_form(const AdjGateDesc& d) { return d.uform; }  // the gradient's
 inline bool group_header(const SweepGateDesc& d) { return d.diag && d.form == kFormCount; }
 inline bool group_header(const AdjGateDesc&) { return false; }
 
+inline bool unit_diag1(const SweepGateDesc& d) { return d.diag && d.n == 1 && d.kreg[0] >= 0 && d.form == kFormUnit; }
+inline bool unit_diag1(const AdjGateDesc& d) {
+  return d.diag && d.n == 1 && d.kreg[0] >= 0 && !(d.form & ADJ_DIAG_SIGNS);
+}
+
+// Runs of one-bit unit diagonal gates on register bits (RZ and its like), found
+// as the dense runs are: a diagonal gate on register bit r commutes with every
+// gate but a dense one on bit r, so it moves up past the others beside the
+// first such gate; two to four on distinct bits make a run.
+template <class Desc>
+void mark_diag_runs(Desc* g, int n) {
+  const std::vector<Desc> v(g, g + n);
+  std::vector<char> used(n, 0);
+  int o = 0;
+  for (int i = 0; i < n; ++i) {
+    if (used[i]) continue;
+    const Desc& d = v[i];
+    if (unit_diag1(d) && d.run_mask == 0) {
+      int pick[4] = {-1, -1, -1, -1};
+      const int b0 = d.kreg[0];
+      pick[b0] = i;
+      int mask = 1 << b0;
+      for (int r = 0; r < 4; ++r) {
+        if (r == b0) continue;
+        for (int j = i + 1; j < n; ++j) {
+          if (used[j]) continue;
+          const Desc& e = v[j];
+          if (unit_diag1(e) && e.kreg[0] == r) {
+            pick[r] = j;
+            mask |= 1 << r;
+            break;
+          }
+          if (!e.diag && (e.rb[0] == r || (e.n == 2 && e.rb[1] == r))) break;
+        }
+      }
+      if (mask != (1 << b0)) {
+        bool first = true;
+        for (int r = 0; r < 4; ++r) {
+          if (pick[r] < 0) continue;
+          g[o] = v[pick[r]];
+          g[o].run_mask = first ? mask : 0;
+          first = false;
+          used[pick[r]] = 1;
+          ++o;
+        }
+        continue;
+      }
+    }
+    g[o] = v[i];
+    used[i] = 1;
+    ++o;
+  }
+}
+
 template <class Desc>
 void mark_runs(Desc* g, int n) {
   // whether d acts on register bit r (a count group's header carries no bits: its members do)
@@ -484,6 +538,7 @@ void build_chains(tn_path* path, int T) {
                                        gd.kreg[0] < 0 && (gd.n == 1 || gd.kreg[1] < 0);
                               });
         mark_runs(path->sweep_gates.data() + seg.first_gate, seg.n_gates);
+        mark_diag_runs(path->sweep_gates.data() + seg.first_gate, seg.n_gates);
         fill_segment_tables(seg, ps.l);
         path->segments.push_back(seg);
       }
@@ -1412,6 +1467,7 @@ void build_adjoint_plan(const tn_network* net, tn_path* path, const std::vector<
                               return gd.diag && gd.kreg[0] < 0 && (gd.n == 1 || gd.kreg[1] < 0);
                             });
       mark_runs(path->adj_gates.data() + seg.first_gate, seg.n_gates);
+      mark_diag_runs(path->adj_gates.data() + seg.first_gate, seg.n_gates);
       fill_segment_tables(seg, ps.l);
       path->adj_segments.push_back(seg);
     }
