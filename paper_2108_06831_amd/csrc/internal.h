@@ -146,7 +146,8 @@ struct SweepGateDesc {
   // on the first of two to four consecutive gates on distinct register bits, in increasing bit
   // order, the mask of those bits (0: no run); the kernels apply the run as straight-line code.
   // The gates of a run are all dense one-qubit gates of one form, or all one-bit diagonal gates
-  // with unit-modulus entries
+  // with unit-modulus entries.  On the first of a run of diagonal gates with entries +-1 (CZ, Z)
+  // and a bit in the registers, it holds instead the number of the run's gates (2 to 16)
   int32_t run_mask = 0;
 };
 // Inside a pass, gates run in segments: a segment names four local bits

@@ -1099,6 +1099,31 @@ __device__ __forceinline__ void diag_run(float2 (&x)[16], float2 (&y)[16], const
   }
 }
 
+// The thread's elements that a diagonal with entries +-1 negates, as a 16-bit
+// mask over the register combinations r: entry b (bit 0 from register bit k0
+// or constant bit 0 of c, bit 1 likewise from k1 or c) is -1 where bit b of
+// `signs` is set, as in apply_signs.
+__device__ __forceinline__ int sign_pattern(int n, int k0, int k1, int c, int signs) {
+  auto ones = [](int k) { return k == 0 ? 0xAAAA : k == 1 ? 0xCCCC : k == 2 ? 0xF0F0 : 0xFF00; };
+  const int A = k0 >= 0 ? ones(k0) : ((c & 1) ? 0xFFFF : 0);
+  const int B = n == 2 ? (k1 >= 0 ? ones(k1) : ((c & 2) ? 0xFFFF : 0)) : 0;
+  int m = 0;
+  if (signs & 1) m |= ~A & ~B;
+  if (signs & 2) m |= A & ~B;
+  if (signs & 4) m |= ~A & B;
+  if (signs & 8) m |= A & B;
+  return m & 0xFFFF;
+}
+
+// x[r] = -x[r] where bit r of m is set (sign-bit flips, no multiplies)
+__device__ __forceinline__ void flip_signs(float2 (&x)[16], int m) {
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const unsigned s = (unsigned)((m >> r) & 1) << 31;
+    x[r] = f2(__uint_as_float(__float_as_uint(x[r].x) ^ s), __uint_as_float(__float_as_uint(x[r].y) ^ s));
+  }
+}
+
 // Sign mask of a diagonal whose used entries are all +1 or -1 (CZ, Z), or -1.
 __device__ __forceinline__ int sign_mask(int n, float2 d0, float2 d1, float2 d2, float2 d3) {
   auto pm1 = [](float2 d) { return d.y == 0.f && fabsf(d.x) == 1.f; };
@@ -1296,6 +1321,26 @@ __global__ __launch_bounds__(kThreads) void k_sweep_pass(SweepPassArgs a, const 
       if (gd.form == kFormCount) {
         apply_count_group<PREC>(x, gates + gi + 1, gd.n, ob, base, ctab + gd.voff);
         gi += gd.n;
+        continue;
+      }
+      if (gd.diag && gd.run_mask && gd.form == kFormSigns) {  // run_mask gates with entries +-1
+        int m = 0;
+        for (int j = 0; j < gd.run_mask; ++j) {
+          const SweepGateDesc& gj = gates[gi + j];
+          const float2* Vj = VL ? vtab + (gj.voff - a.lds_off) : V0 + gj.voff;
+          const bool two = gj.n == 2;
+          const int sm = (Vj[0].x < 0.f) | ((Vj[1].x < 0.f) << 1) | (two ? ((Vj[2].x < 0.f) << 2) | ((Vj[3].x < 0.f) << 3) : 0);
+          int cb = 0;
+#pragma unroll
+          for (int t = 0; t < 2; ++t) {
+            if (t >= gj.n || gj.kreg[t] >= 0) continue;
+            const int cs = gj.csrc[t];
+            cb |= (cs >= 64 ? (int)((base >> (cs - 64)) & 1) : ((ob >> cs) & 1)) << t;
+          }
+          m ^= sign_pattern(gj.n, gj.kreg[0], two ? gj.kreg[1] : -1, cb, sm);
+        }
+        flip_signs(x, m);
+        gi += gd.run_mask - 1;
         continue;
       }
       if (gd.diag && gd.run_mask) {  // one-bit unit diagonals on the mask's register bits, in bit order
@@ -3123,6 +3168,26 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_pass(AdjPassArgs a, const 
         const float2* G = reinterpret_cast<const float2*>(gd.gen);
         const float2* Up = upre[gi - a.first_gate];
         if (!gd.diag) have_t = false;
+        if (gd.diag && gd.run_mask && (gd.form & ADJ_DIAG_SIGNS)) {  // run_mask gates with entries +-1
+          // (U^dagger = U; no gradient terms; sign flips of both states leave Im(conj(l) p) as it was)
+          int m = 0;
+          for (int j = 0; j < gd.run_mask; ++j) {
+            const AdjGateDesc& gj = gates[gi + j];
+            const bool two = gj.n == 2;
+            int cj = 0;
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+              if (t >= gj.n || gj.kreg[t] >= 0) continue;
+              const int cs = gj.csrc[t];
+              cj |= (cs >= 64 ? (int)((base >> (cs - 64)) & 1) : ((ob >> cs) & 1)) << t;
+            }
+            m ^= sign_pattern(gj.n, gj.kreg[0], two ? gj.kreg[1] : -1, cj, gj.form >> 8);
+          }
+          flip_signs(xp, m);
+          flip_signs(xl, m);
+          gi += gd.run_mask - 1;
+          continue;
+        }
         if (gd.diag && gd.run_mask) {  // one-bit unit diagonals on the mask's register bits, in bit order
           const int cnt = __builtin_popcount(gd.run_mask);
           // their gradient terms: a unit diagonal applied to both states leaves Im(conj(l) p)

@@ -321,6 +321,58 @@ void mark_diag_runs(Desc* g, int n) {
   }
 }
 
+inline int reg_bits(const SweepGateDesc& d) {
+  return (d.kreg[0] >= 0 ? 1 << d.kreg[0] : 0) | (d.n == 2 && d.kreg[1] >= 0 ? 1 << d.kreg[1] : 0);
+}
+inline int reg_bits(const AdjGateDesc& d) {
+  return (d.kreg[0] >= 0 ? 1 << d.kreg[0] : 0) | (d.n == 2 && d.kreg[1] >= 0 ? 1 << d.kreg[1] : 0);
+}
+inline bool sign_diag(const SweepGateDesc& d) { return d.diag && d.form == kFormSigns && reg_bits(d) != 0; }
+inline bool sign_diag(const AdjGateDesc& d) {
+  return d.diag && (d.form & ADJ_DIAG_SIGNS) && d.red < 0 && reg_bits(d) != 0;
+}
+
+// Runs of diagonal gates with entries +-1 and a bit in the registers (CZ, Z):
+// such a gate commutes with every gate but a dense one on its register bits,
+// so later ones move up beside the first while no dense gate on their bits
+// lies in between; two to sixteen make a run, whose sign flips the kernels
+// combine into one mask over the thread's elements.
+template <class Desc>
+void mark_sign_runs(Desc* g, int n) {
+  const std::vector<Desc> v(g, g + n);
+  std::vector<char> used(n, 0);
+  int o = 0;
+  for (int i = 0; i < n; ++i) {
+    if (used[i]) continue;
+    if (sign_diag(v[i]) && v[i].run_mask == 0) {
+      std::vector<int> pick{i};
+      int blocked = 0;  // register bits of the dense gates passed
+      for (int j = i + 1; j < n && pick.size() < 16; ++j) {
+        if (used[j]) continue;
+        const Desc& e = v[j];
+        if (!e.diag) {
+          blocked |= 1 << e.rb[0];
+          if (e.n == 2) blocked |= 1 << e.rb[1];
+          continue;
+        }
+        if (sign_diag(e) && e.run_mask == 0 && !(reg_bits(e) & blocked)) pick.push_back(j);
+      }
+      if (pick.size() >= 2) {
+        for (size_t k = 0; k < pick.size(); ++k) {
+          g[o] = v[pick[k]];
+          g[o].run_mask = k == 0 ? (int32_t)pick.size() : 0;
+          used[pick[k]] = 1;
+          ++o;
+        }
+        continue;
+      }
+    }
+    g[o] = v[i];
+    used[i] = 1;
+    ++o;
+  }
+}
+
 template <class Desc>
 void mark_runs(Desc* g, int n) {
   // whether d acts on register bit r (a count group's header carries no bits: its members do)
@@ -539,6 +591,7 @@ void build_chains(tn_path* path, int T) {
                               });
         mark_runs(path->sweep_gates.data() + seg.first_gate, seg.n_gates);
         mark_diag_runs(path->sweep_gates.data() + seg.first_gate, seg.n_gates);
+        mark_sign_runs(path->sweep_gates.data() + seg.first_gate, seg.n_gates);
         fill_segment_tables(seg, ps.l);
         path->segments.push_back(seg);
       }
@@ -1468,6 +1521,7 @@ void build_adjoint_plan(const tn_network* net, tn_path* path, const std::vector<
                             });
       mark_runs(path->adj_gates.data() + seg.first_gate, seg.n_gates);
       mark_diag_runs(path->adj_gates.data() + seg.first_gate, seg.n_gates);
+      mark_sign_runs(path->adj_gates.data() + seg.first_gate, seg.n_gates);
       fill_segment_tables(seg, ps.l);
       path->adj_segments.push_back(seg);
     }
